@@ -1,0 +1,639 @@
+"""Pins for the FP64 oracle: checks against what the paper and the
+mathematics fix, independent of the oracle's own code paths.
+
+Each test names the passage it pins.  None of them re-types an oracle
+formula and compares it with itself: the expected values come from hand
+worked tables (golden files), closed forms, polynomial reproduction,
+finite differences, invariants, exact adjoints or convergence orders.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import load_golden
+
+# Test-side cube-map table, typed from the published selection table (the
+# golden file cubemap_faces.txt pins it): d/|ma| = M + sc S + tc T.
+TM = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+TS = np.array([[0, 0, -1], [0, 0, 1], [1, 0, 0], [1, 0, 0], [1, 0, 0], [-1, 0, 0]], float)
+TT = np.array([[0, -1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1], [0, -1, 0], [0, -1, 0]], float)
+
+
+def chart_dir(face, u, v):
+    """Unit direction of chart point (u, v) of a face (extended plane)."""
+    u = np.asarray(u, float)
+    v = np.asarray(v, float)
+    w = TM[face] + (2 * u - 1)[..., None] * TS[face] + (2 * v - 1)[..., None] * TT[face]
+    return w / np.linalg.norm(w, axis=-1, keepdims=True)
+
+
+def face_uv(d):
+    """(face, u, v) of directions by the published table (test-side)."""
+    d = np.asarray(d, float)
+    ax, ay, az = np.abs(d).T
+    face = np.where((ax >= ay) & (ax >= az), np.where(d[:, 0] >= 0, 0, 1),
+                    np.where(ay >= az, np.where(d[:, 1] >= 0, 2, 3), np.where(d[:, 2] >= 0, 4, 5)))
+    ma = np.einsum("ij,ij->i", d, TM[face])
+    sc = np.einsum("ij,ij->i", d, TS[face])
+    tc = np.einsum("ij,ij->i", d, TT[face])
+    return face, 0.5 * (sc / ma + 1), 0.5 * (tc / ma + 1)
+
+
+def rng(k=0):
+    return np.random.default_rng(1234 + k)
+
+
+# ---------------------------------------------------------------------------
+# Hermite basis, Sec. 3.3 Eq. (3)
+# ---------------------------------------------------------------------------
+def test_hermite_cardinal_conditions():
+    b0 = oracle.hermite_basis(0.0)
+    b1 = oracle.hermite_basis(1.0)
+    # values H0, H1, H0d, H1d at s=0 and s=1
+    assert list(b0[:4]) == [1.0, 0.0, 0.0, 0.0]
+    assert list(b1[:4]) == [0.0, 1.0, 0.0, 0.0]
+    # derivatives H0', H1', H0d', H1d'
+    assert list(b0[4:]) == [0.0, 0.0, 1.0, 0.0]
+    assert list(b1[4:]) == [0.0, 0.0, 0.0, 1.0]
+
+
+def test_hermite_partition_and_derivative_consistency():
+    for s in rng().uniform(-0.5, 1.5, 50):
+        b = oracle.hermite_basis(s)
+        assert abs(b[0] + b[1] - 1.0) < 1e-14
+        h = 1e-6
+        fd = (oracle.hermite_basis(s + h)[:4] - oracle.hermite_basis(s - h)[:4]) / (2 * h)
+        np.testing.assert_allclose(b[4:], fd, atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Cube-map mapping, Sec. 3.2
+# ---------------------------------------------------------------------------
+def test_cubemap_golden_table():
+    rows = load_golden("cubemap_faces.txt")
+    N = 16
+    for x, y, z, face, u, v in rows:
+        f, i0, j0, s, t = oracle.locate(np.array([[x, y, z]], np.float32), N)
+        assert f[0] == int(face), (x, y, z)
+        assert abs((i0[0] + s[0] - 0.5) / N - u) < 1e-12, (x, y, z)
+        assert abs((j0[0] + t[0] - 0.5) / N - v) < 1e-12, (x, y, z)
+
+
+def test_test_table_matches_golden():
+    rows = np.array(load_golden("cubemap_faces.txt"))
+    f, u, v = face_uv(rows[:, :3])
+    np.testing.assert_array_equal(f, rows[:, 3].astype(int))
+    np.testing.assert_allclose(u, rows[:, 4], atol=1e-15)
+    np.testing.assert_allclose(v, rows[:, 5], atol=1e-15)
+
+
+def test_locate_fp32_decision_and_local_coords():
+    d = workloads.uniform_dirs(20000, rng(1))
+    for N in (10, 32, 257):
+        f, i0, j0, s, t = oracle.locate(d, N)
+        # the FP32 decision, every step correctly rounded (numpy float32 ops)
+        ff, uu, vv = face_uv(d.astype(np.float64))
+        np.testing.assert_array_equal(f, ff)
+        dd = d.astype(np.float32)
+        ma = np.abs(np.einsum("ij,ij->i", dd, TM[ff].astype(np.float32))).astype(np.float32)
+        sc = np.einsum("ij,ij->i", dd, TS[ff].astype(np.float32)).astype(np.float32)
+        a = (sc / ma).astype(np.float32)
+        fu = (((a + np.float32(1)) * np.float32(0.5)) * np.float32(N)).astype(np.float32) + np.float32(0.5)
+        np.testing.assert_array_equal(i0, np.minimum(np.floor(fu), N).astype(np.int32))
+        # the FP64 local coordinate agrees with the test-side u
+        np.testing.assert_allclose(i0 + s, uu * N + 0.5, atol=1e-9)
+        np.testing.assert_allclose(j0 + t, vv * N + 0.5, atol=1e-9)
+        assert s.min() > -1e-5 and s.max() < 1 + 1e-5
+        assert i0.min() >= 0 and i0.max() <= N
+
+
+def test_invalid_directions_give_nan():
+    lut = workloads.random_lut(8, rng(2))
+    d = np.array([[0, 0, 0], [np.nan, 1, 0], [np.inf, 0, 0], [1, 0, 0]], np.float32)
+    out = oracle.query(lut, d)
+    assert np.all(np.isnan(out[:3]))
+    assert np.all(np.isfinite(out[3]))
+
+
+# ---------------------------------------------------------------------------
+# Reconstruction, Sec. 3.3 Eqs. (4)-(5)
+# ---------------------------------------------------------------------------
+def poly_lut(N, C):
+    """LUT holding (P, P_u h, P_v h, P_uv h^2) of per-face bicubics
+    P_f(u,v) = sum_ab C[f,a,b] u^a v^b at the texel centres u_p=(p-1/2)/N."""
+    p = (np.arange(N + 2) - 0.5) / N
+    U, V = np.meshgrid(p, p, indexing="xy")  # [q, p]
+    lut = np.zeros((6, N + 2, N + 2, 4))
+    for f in range(6):
+        P, Pu, Pv, Puv = poly_eval(C[f], U, V)
+        lut[f, ..., 0] = P
+        lut[f, ..., 1] = Pu / N
+        lut[f, ..., 2] = Pv / N
+        lut[f, ..., 3] = Puv / N ** 2
+    return lut
+
+
+def poly_eval(c, u, v):
+    P = Pu = Pv = Puv = 0.0
+    for a in range(4):
+        for b in range(4):
+            P = P + c[a, b] * u ** a * v ** b
+            if a:
+                Pu = Pu + c[a, b] * a * u ** (a - 1) * v ** b
+            if b:
+                Pv = Pv + c[a, b] * b * u ** a * v ** (b - 1)
+            if a and b:
+                Puv = Puv + c[a, b] * a * b * u ** (a - 1) * v ** (b - 1)
+    return P, Pu, Pv, Puv
+
+
+@pytest.mark.parametrize("N", [4, 10, 33])
+def test_reproduces_bicubic_polynomials(N):
+    r = rng(N)
+    C = r.standard_normal((6, 4, 4))
+    lut = poly_lut(N, C)
+    d = workloads.uniform_dirs(6000, r)
+    ch = oracle.query_chart(lut, d)
+    f, u, v = face_uv(d.astype(np.float64))
+    for face in range(6):
+        m = f == face
+        P, Pu, Pv, _ = poly_eval(C[face], u[m], v[m])
+        scale = np.abs(C[face]).sum() * 10
+        np.testing.assert_allclose(ch[m, 0], P, atol=1e-12 * scale)
+        np.testing.assert_allclose(ch[m, 1], Pu, atol=1e-11 * scale)
+        np.testing.assert_allclose(ch[m, 2], Pv, atol=1e-11 * scale)
+
+
+def test_stored_values_at_texel_centres():
+    N = 9
+    lut = workloads.random_lut(N, rng(3)).astype(np.float64)
+    for face in range(6):
+        for i0 in range(N + 1):
+            for j0 in (0, 3, N):
+                for (i, j) in ((0, 0), (1, 0), (0, 1), (1, 1)):
+                    r, ru, rv = oracle.reconstruct(lut, face, i0, j0, float(i), float(j))
+                    tex = lut[face, j0 + j, i0 + i]
+                    assert r == tex[0]
+                    assert abs(ru - N * tex[1]) <= 1e-14 * N
+                    assert abs(rv - N * tex[2]) <= 1e-14 * N
+
+
+def test_c1_across_cell_edges():
+    N = 12
+    lut = workloads.random_lut(N, rng(4)).astype(np.float64)
+    r = rng(5)
+    for _ in range(200):
+        face = int(r.integers(6))
+        i0 = int(r.integers(N))
+        j0 = int(r.integers(N + 1))
+        t = float(r.uniform())
+        a = oracle.reconstruct(lut, face, i0, j0, 1.0, t)
+        b = oracle.reconstruct(lut, face, i0 + 1, j0, 0.0, t)
+        np.testing.assert_allclose(a, b, atol=1e-13 * N)
+        j0 = int(r.integers(N))
+        i0 = int(r.integers(N + 1))
+        s = float(r.uniform())
+        a = oracle.reconstruct(lut, face, i0, j0, s, 1.0)
+        b = oracle.reconstruct(lut, face, i0, j0 + 1, s, 0.0)
+        np.testing.assert_allclose(a, b, atol=1e-13 * N)
+
+
+# ---------------------------------------------------------------------------
+# Gradient transport, Sec. 3.4 Eqs. (6)-(9), and the normal, Eq. (10)
+# ---------------------------------------------------------------------------
+def test_transport_identities():
+    N = 16
+    lut = workloads.random_lut(N, rng(6))
+    d = workloads.uniform_dirs(5000, rng(7))
+    out = oracle.query(lut, d)
+    closed = oracle.query(lut, d, closed_form=True)
+    scale = np.linalg.norm(out[:, 1:], axis=1).max()
+    np.testing.assert_allclose(out, closed, atol=1e-12 * scale)
+    ch = oracle.query_chart(lut, d)
+    a, b = ch[:, 5], ch[:, 6]
+    rho2 = 1 + a * a + b * b
+    np.testing.assert_allclose(ch[:, 3], 16.0 / rho2 ** 3, rtol=1e-12)  # det G = 16 / rho^6
+    assert ch[:, 3].min() >= 16.0 / 27.0 - 1e-12  # clamp is inert on a face
+    assert np.all(ch[:, 4] == 0)
+    w = ch[:, 7:10]
+    g = out[:, 1:]
+    assert np.abs(np.einsum("ij,ij->i", g, w)).max() < 1e-12 * scale
+    # grad . e1 = r_u, grad . e2 = r_v with e1, e2 from finite differences of
+    # the test-side chart map
+    f, u, v = face_uv(d.astype(np.float64))
+    h = 1e-6
+    e1 = np.stack([(chart_dir(ff, uu + h, vv) - chart_dir(ff, uu - h, vv)) / (2 * h) for ff, uu, vv in zip(f, u, v)])
+    e2 = np.stack([(chart_dir(ff, uu, vv + h) - chart_dir(ff, uu, vv - h)) / (2 * h) for ff, uu, vv in zip(f, u, v)])
+    np.testing.assert_allclose(np.einsum("ij,ij->i", g, e1), ch[:, 1], atol=1e-7 * scale)
+    np.testing.assert_allclose(np.einsum("ij,ij->i", g, e2), ch[:, 2], atol=1e-7 * scale)
+
+
+def test_gradient_matches_fd_of_reconstruction():
+    """The spherical gradient equals central differences of the reconstructed
+    value along tangent directions (catches a wrong sign, index or
+    transposed operand anywhere in Eqs. (5)-(9))."""
+    N = 8
+    c = workloads.sh_glyph_coeffs(6, 1, rng(8))[0]
+    lut = oracle.bake_sh(c, N)
+    d = workloads.uniform_dirs(3000, rng(9)).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    f, i0, j0, s, t = oracle.locate(d.astype(np.float32), N)
+    keep = (s > 0.05) & (s < 0.95) & (t > 0.05) & (t < 0.95)
+    d = d[keep]
+    base = oracle.query_f64(lut, d)
+    r = rng(10)
+    tau = r.standard_normal(d.shape)
+    tau -= np.einsum("ij,ij->i", tau, d)[:, None] * d
+    tau /= np.linalg.norm(tau, axis=1, keepdims=True)
+    delta = 1e-5 / N
+    # geodesic steps w(+-delta) = cos(delta) w +- sin(delta) tau
+    dp = math.cos(delta) * d + math.sin(delta) * tau
+    dm = math.cos(delta) * d - math.sin(delta) * tau
+    fd = (oracle.query_f64(lut, dp)[:, 0] - oracle.query_f64(lut, dm)[:, 0]) / (2 * delta)
+    an = np.einsum("ij,ij->i", base[:, 1:], tau)
+    scale = np.linalg.norm(base[:, 1:], axis=1).max()
+    assert np.abs(fd - an).max() < 1e-6 * scale
+
+
+def test_constant_lut_gives_sphere():
+    N = 7
+    lut = np.zeros((6, N + 2, N + 2, 4))
+    lut[..., 0] = 1.25
+    d = workloads.uniform_dirs(2000, rng(11))
+    out, n = oracle.query(lut, d, normals=True)
+    # partition of unity holds up to rounding of the 16-term sum
+    assert np.abs(out[:, 0] - 1.25).max() < 1e-15
+    assert np.abs(out[:, 1:]).max() < 1e-13
+    w = d.astype(np.float64) / np.linalg.norm(d.astype(np.float64), axis=1, keepdims=True)
+    np.testing.assert_allclose(n, w, atol=1e-13)
+
+
+def test_normal_is_gradient_of_implicit_function():
+    """n of Eq. (10) is parallel to grad F for F(x) = |x| - R(x/|x|): check
+    against central differences of F built from FP64 reconstructions."""
+    N = 12
+    c = workloads.sh_glyph_coeffs(4, 1, rng(12))[0]
+    lut = oracle.bake_sh(c, N)
+    d = workloads.uniform_dirs(400, rng(13)).astype(np.float64)
+    out, n = oracle.query(lut, d.astype(np.float32), normals=True)
+    w = d / np.linalg.norm(d, axis=1, keepdims=True)
+    x = w * out[:, :1]  # surface point (centre at origin)
+    h = 1e-6
+    gF = np.zeros_like(x)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        Fp = np.linalg.norm(x + e, axis=1) - oracle.query_f64(lut, x + e)[:, 0]
+        Fm = np.linalg.norm(x - e, axis=1) - oracle.query_f64(lut, x - e)[:, 0]
+        gF[:, k] = (Fp - Fm) / (2 * h)
+    gF /= np.linalg.norm(gF, axis=1, keepdims=True)
+    # compare where the query direction's cell is the same for x +- h
+    err = np.linalg.norm(gF - n, axis=1)
+    assert np.median(err) < 1e-7
+    assert np.mean(err < 1e-6) > 0.97
+
+
+# ---------------------------------------------------------------------------
+# Real spherical harmonics (bake input function)
+# ---------------------------------------------------------------------------
+def test_sh_closed_forms_low_order():
+    d = workloads.uniform_dirs(500, rng(14)).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    x, y, z = d.T
+    Y = oracle.sh_basis(2, d)
+    pi = math.pi
+    exp = np.stack([
+        np.full_like(x, 0.5 / math.sqrt(pi)),
+        math.sqrt(3 / (4 * pi)) * y, math.sqrt(3 / (4 * pi)) * z, math.sqrt(3 / (4 * pi)) * x,
+        0.5 * math.sqrt(15 / pi) * x * y, 0.5 * math.sqrt(15 / pi) * y * z,
+        0.25 * math.sqrt(5 / pi) * (3 * z * z - 1), 0.5 * math.sqrt(15 / pi) * x * z,
+        0.25 * math.sqrt(15 / pi) * (x * x - y * y)], axis=1)
+    np.testing.assert_allclose(Y, exp, atol=1e-14)
+
+
+def test_sh_addition_theorem():
+    d = workloads.uniform_dirs(300, rng(15)).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = oracle.sh_basis(16, d)
+    for l in range(17):
+        s = (Y[:, l * l:(l + 1) * (l + 1)] ** 2).sum(axis=1)
+        np.testing.assert_allclose(s, (2 * l + 1) / (4 * math.pi), rtol=1e-11)
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_sh_orthonormality_by_quadrature(L):
+    nz = L + 1
+    zs, wz = np.polynomial.legendre.leggauss(nz)
+    nphi = 2 * L + 2
+    phi = 2 * math.pi * np.arange(nphi) / nphi
+    Z, PHI = np.meshgrid(zs, phi, indexing="ij")
+    W = np.repeat(wz, nphi) * (2 * math.pi / nphi)
+    sx = np.sqrt(1 - Z ** 2)
+    d = np.stack([sx * np.cos(PHI), sx * np.sin(PHI), Z], axis=-1).reshape(-1, 3)
+    Y = oracle.sh_basis(L, d)
+    G = (Y * W[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye((L + 1) ** 2), atol=1e-12 if L <= 8 else 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Bake, Sec. 3.3 Alg. 1 (analytic SH mode)
+# ---------------------------------------------------------------------------
+def test_bake_channels_vs_finite_differences():
+    N = 16
+    c = workloads.sh_glyph_coeffs(8, 1, rng(16))[0]
+    r = rng(17)
+    h = 1e-4
+    for _ in range(40):
+        face = int(r.integers(6))
+        u, v = r.uniform(-0.05, 1.05, 2)
+        ch = oracle.bake_sh_point(c, N, face, u, v)
+
+        def G(uu, vv):
+            return oracle.sh_truth(c, chart_dir(face, np.array([uu]), np.array([vv])))[0, 0]
+
+        g0 = G(u, v)
+        gu = (G(u + h, v) - G(u - h, v)) / (2 * h)
+        gv = (G(u, v + h) - G(u, v - h)) / (2 * h)
+        guv = (G(u + h, v + h) - G(u + h, v - h) - G(u - h, v + h) + G(u - h, v - h)) / (4 * h * h)
+        assert abs(ch[0] - g0) < 1e-14
+        assert abs(ch[1] - gu / N) < 1e-8
+        assert abs(ch[2] - gv / N) < 1e-8
+        assert abs(ch[3] - guv / N ** 2) < 1e-7
+
+
+def test_bake_linear_function_closed_form():
+    """R(w) = a . w (degree 1): G(A,B) = (alpha + beta A + gamma B)/sqrt(1+A^2+B^2)
+    with A = 2u-1, B = 2v-1, alpha = a.M, beta = a.S, gamma = a.T."""
+    avec = np.array([0.3, -0.7, 0.45])
+    k = math.sqrt(4 * math.pi / 3)
+    c = np.zeros(4)
+    c[1], c[2], c[3] = avec[1] * k, avec[2] * k, avec[0] * k  # Y_{1,-1} ~ y, Y_10 ~ z, Y_11 ~ x
+    N = 6
+    lut = oracle.bake_sh(c, N)
+    for face in range(6):
+        al, be, ga = avec @ TM[face], avec @ TS[face], avec @ TT[face]
+        for q in range(N + 2):
+            for p in range(N + 2):
+                A = 2 * (p - 0.5) / N - 1
+                B = 2 * (q - 0.5) / N - 1
+                n = 1 + A * A + B * B
+                num = al + be * A + ga * B
+                G = num * n ** -0.5
+                GA = be * n ** -0.5 - num * A * n ** -1.5
+                GB = ga * n ** -0.5 - num * B * n ** -1.5
+                GAB = -be * B * n ** -1.5 - ga * A * n ** -1.5 + 3 * num * A * B * n ** -2.5
+                exp = [G, 2 * GA / N, 2 * GB / N, 4 * GAB / N ** 2]
+                np.testing.assert_allclose(lut[face, q, p], exp, atol=1e-14)
+
+
+def test_gutter_is_function_at_texel_centre_direction():
+    """Sec. 3.2: gutter texels hold the function at their own texel-centre
+    direction (on the extended face plane), not a copy of a neighbour."""
+    N = 10
+    c = workloads.sh_glyph_coeffs(6, 1, rng(18))[0]
+    lut = oracle.bake_sh(c, N)
+    for face in range(6):
+        for (p, q) in ((0, 0), (0, 5), (N + 1, 3), (4, N + 1), (N + 1, N + 1)):
+            w = chart_dir(face, np.array([(p - 0.5) / N]), np.array([(q - 0.5) / N]))
+            assert abs(lut[face, q, p, 0] - oracle.sh_truth(c, w)[0, 0]) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Method vs truth (convergence trend, paper Sec. 4.2 Table psnr_value)
+# ---------------------------------------------------------------------------
+def test_convergence_orders_and_psnr_trend():
+    c = workloads.sh_glyph_coeffs(8, 1, rng(19))[0]
+    d = workloads.uniform_dirs(20000, rng(20))
+    truth = oracle.sh_truth(c, d.astype(np.float64))
+    ev, eg, psnr = [], [], []
+    Ns = (8, 16, 32, 64)
+    peak = truth[:, 0].max() - truth[:, 0].min()
+    for N in Ns:
+        out = oracle.query(oracle.bake_sh(c, N), d)
+        dv = out[:, 0] - truth[:, 0]
+        ev.append(np.sqrt(np.mean(dv ** 2)))
+        eg.append(np.sqrt(np.mean(np.sum((out[:, 1:] - truth[:, 1:]) ** 2, axis=1))))
+        psnr.append(20 * math.log10(peak / ev[-1]))
+    sv = [math.log2(ev[i] / ev[i + 1]) for i in range(3)]
+    sg = [math.log2(eg[i] / eg[i + 1]) for i in range(3)]
+    # bicubic Hermite with exact derivatives: value O(h^4), gradient O(h^3)
+    assert 3.3 < sv[-1] < 5.5, sv
+    assert 2.3 < sg[-1] < 4.5, sg
+    # Table psnr_value: Hermite gains ~30 dB per doubling from N=8 to 32
+    paper = {int(r[0]): r[3] for r in load_golden("psnr_value_table.txt")}
+    assert psnr[1] - psnr[0] > 20 and psnr[2] - psnr[1] > 20
+    assert (paper[16] - paper[8]) > 20 and (paper[32] - paper[16]) > 20
+
+
+def test_face_seam_jump_converges():
+    """Across a face seam the two faces' patches agree to interpolation
+    order (value O(h^4), gradient O(h^3)); no exact equality is claimed."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(21))[0]
+    r = rng(22)
+    # points on the +X / +Y seam: x = y > |z|
+    zz = r.uniform(-0.9, 0.9, 400)
+    d = np.stack([np.ones_like(zz), np.ones_like(zz), zz], axis=1)
+    jv, jg = [], []
+    for N in (16, 32, 64):
+        lut = oracle.bake_sh(c, N)
+        a = oracle.query_f64(lut, d, face=0)
+        b = oracle.query_f64(lut, d, face=2)
+        jv.append(np.abs(a[:, 0] - b[:, 0]).max())
+        jg.append(np.linalg.norm(a[:, 1:] - b[:, 1:], axis=1).max())
+    ov = math.log2(jv[1] / jv[2])
+    og = math.log2(jg[1] / jg[2])
+    assert ov > 3.5, (jv, ov)
+    assert og > 2.5, (jg, og)
+
+
+# ---------------------------------------------------------------------------
+# General-mode (finite difference) bake, Sec. 3.3 Alg. 1
+# ---------------------------------------------------------------------------
+def test_fd_bake_second_order():
+    c = workloads.sh_glyph_coeffs(6, 1, rng(23))[0]
+    errs = []
+    for N in (16, 32, 64):
+        dirs = oracle.margin_dirs(N)
+        samples = oracle.sh_truth(c, dirs.reshape(-1, 3))[:, 0].reshape(6, N + 4, N + 4)
+        fd = oracle.bake_fd(samples, N)
+        an = oracle.bake_sh(c, N)
+        np.testing.assert_allclose(fd[..., 0], an[..., 0], atol=1e-14)
+        # scaled channels r_u h: FD error O(h^2) relative to r_u, i.e. O(h^3) on r_u h
+        errs.append(np.abs(fd[..., 1:3] - an[..., 1:3]).max() * N)
+    o = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert 1.6 < o[-1] < 2.5, (errs, o)
+
+
+# ---------------------------------------------------------------------------
+# Bounding radius and ray casting, Sec. 3.1
+# ---------------------------------------------------------------------------
+def test_rmax_bound_is_upper_bound():
+    N = 12
+    c = workloads.sh_glyph_coeffs(8, 1, rng(24))[0]
+    lut = oracle.bake_sh(c, N)
+    bound = oracle.rmax_bound(lut)
+    d = workloads.uniform_dirs(200000, rng(25))
+    m = oracle.query(lut, d)[:, 0].max()
+    assert bound >= m
+    assert bound < m * 1.05
+    lut0 = np.zeros((6, N + 2, N + 2, 4))
+    lut0[..., 0] = 0.8
+    assert oracle.rmax_bound(lut0) == 0.8
+
+
+def test_bezier_net_reproduces_patch():
+    """The control net behind the bound is the patch in Bernstein form:
+    sum_ab B_a(s) B_b(t) Bz[a,b] equals the Hermite reconstruction."""
+    N = 7
+    lut = workloads.random_lut(N, rng(40)).astype(np.float64)
+    r = rng(41)
+
+    def bern(x):
+        return np.array([(1 - x) ** 3, 3 * x * (1 - x) ** 2, 3 * x * x * (1 - x), x ** 3])
+
+    for _ in range(100):
+        face, i0, j0 = int(r.integers(6)), int(r.integers(N + 1)), int(r.integers(N + 1))
+        s, t = r.uniform(0, 1, 2)
+        Bz = oracle.cell_bezier(lut, face, i0, j0)
+        val = bern(s) @ Bz @ bern(t)
+        assert abs(val - oracle.reconstruct(lut, face, i0, j0, s, t)[0]) < 1e-13
+
+
+def test_trace_constant_sphere_closed_form():
+    N = 6
+    R0 = 0.9
+    lut = np.zeros((6, N + 2, N + 2, 4))
+    lut[..., 0] = R0
+    r = rng(26)
+    P = 500
+    o = np.tile(np.array([[0.2, -0.1, 3.0]]), (P, 1))
+    tgt = r.uniform(-0.6, 0.6, (P, 3)) * np.array([1, 1, 0])
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o32, d32 = o.astype(np.float32), d.astype(np.float32)
+    t, out, n = oracle.trace(lut, np.zeros(3), R0 * 1.05, o32, d32)
+    oo = o32.astype(np.float64)
+    dd = d32.astype(np.float64)
+    dd /= np.linalg.norm(dd, axis=1, keepdims=True)
+    b = np.einsum("ij,ij->i", oo, dd)
+    cc = np.einsum("ij,ij->i", oo, oo) - R0 * R0
+    t_exact = -b - np.sqrt(b * b - cc)
+    hit = np.isfinite(t)
+    assert hit.all()
+    np.testing.assert_allclose(t, t_exact, rtol=1e-12)
+    x = oo + t[:, None] * dd
+    np.testing.assert_allclose(n, x / np.linalg.norm(x, axis=1, keepdims=True), atol=1e-10)
+
+
+def test_trace_hits_are_first_roots():
+    N = 16
+    c = workloads.sh_glyph_coeffs(8, 1, rng(27))[0]
+    lut = oracle.bake_sh(c, N)
+    rmax = oracle.rmax_bound(lut)
+    o, d = workloads.camera_rays(48, 36, eye=(0.3, 0.2, 3.5))
+    t, out, n = oracle.trace(lut, np.zeros(3), rmax, o, d)
+    hit = np.isfinite(t)
+    assert 0.2 < hit.mean() < 0.9
+    bad_first = 0
+    for k in np.flatnonzero(hit)[::7]:
+        F = oracle.trace_F(lut, np.zeros(3), o[k].astype(float), d[k].astype(float), np.array([t[k]]))
+        assert abs(F[0]) < 1e-10 * rmax
+        # dense scan from the entry of the bounding sphere up to t
+        oo = o[k].astype(float)
+        dd = d[k].astype(float) / np.linalg.norm(d[k].astype(float))
+        bq = oo @ dd
+        t0 = max(-bq - math.sqrt(bq * bq - (oo @ oo - rmax * rmax)), 0.0)
+        ts = np.linspace(t0, t[k], 4096)[:-2]
+        Fs = oracle.trace_F(lut, np.zeros(3), oo, dd, ts)
+        bad_first += int((Fs < 0).any())
+    assert bad_first <= 1
+    # misses: F stays positive along a dense scan of the bounding interval
+    for k in np.flatnonzero(~hit)[::50]:
+        oo = o[k].astype(float)
+        dd = d[k].astype(float) / np.linalg.norm(d[k].astype(float))
+        bq = oo @ dd
+        disc = bq * bq - (oo @ oo - rmax * rmax)
+        if disc < 0:
+            continue
+        ts = np.linspace(-bq - math.sqrt(disc), -bq + math.sqrt(disc), 2048)
+        assert (oracle.trace_F(lut, np.zeros(3), oo, dd, ts) > -1e-3).all()
+
+
+# ---------------------------------------------------------------------------
+# Backward (differentiation form)
+# ---------------------------------------------------------------------------
+def test_backward_adjoint_identity():
+    N = 10
+    r = rng(28)
+    lut = workloads.random_lut(N, r).astype(np.float64)
+    d = workloads.uniform_dirs(3000, r)
+    g = r.standard_normal((3000, 4))
+    dl = r.standard_normal(lut.shape)
+    gl, _ = oracle.backward(lut, d, g, want_dirs=False)
+    lhs = np.sum(oracle.query(dl, d) * g)  # forward is linear in the LUT
+    rhs = np.sum(dl * gl)
+    assert abs(lhs - rhs) < 1e-11 * max(abs(lhs), 1.0) * 10
+
+
+def test_backward_lut_fd_on_texels():
+    N = 8
+    r = rng(29)
+    lut = workloads.random_lut(N, r).astype(np.float64)
+    d = workloads.uniform_dirs(4000, r)
+    g = r.standard_normal((4000, 4))
+    gl, _ = oracle.backward(lut, d, g, want_dirs=False)
+    eps = 1e-3
+    for _ in range(64):
+        idx = tuple(int(r.integers(s)) for s in lut.shape)
+        lp = lut.copy()
+        lp[idx] += eps
+        lm = lut.copy()
+        lm[idx] -= eps
+        fd = (np.sum(oracle.query(lp, d) * g) - np.sum(oracle.query(lm, d) * g)) / (2 * eps)
+        assert abs(fd - gl[idx]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_backward_dirs_fd_and_homogeneity():
+    N = 12
+    r = rng(30)
+    c = workloads.sh_glyph_coeffs(6, 1, r)[0]
+    lut = oracle.bake_sh(c, N)
+    d = workloads.uniform_dirs(1500, r)
+    f, i0, j0, s, t = oracle.locate(d, N)
+    keep = (s > 0.02) & (s < 0.98) & (t > 0.02) & (t < 0.98)
+    d = d[keep]
+    g = r.standard_normal((d.shape[0], 4))
+    _, gd = oracle.backward(lut, d, g, want_lut=False)
+    dd = d.astype(np.float64)
+    # 0-homogeneous outputs: grad_d . d = 0
+    scale = np.abs(gd).max()
+    assert np.abs(np.einsum("ij,ij->i", gd, dd)).max() < 1e-11 * scale
+    h = 1e-7
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        Lp = np.sum(oracle.query_f64(lut, dd + e) * g, axis=1)
+        Lm = np.sum(oracle.query_f64(lut, dd - e) * g, axis=1)
+        fd = (Lp - Lm) / (2 * h)
+        assert np.abs(fd - gd[:, k]).max() < 1e-5 * scale
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+def test_batched_equals_per_object():
+    r = rng(31)
+    Ns = [4, 9, 16]
+    luts = [workloads.random_lut(N, r).astype(np.float64) for N in Ns]
+    counts = [100, 1, 250]
+    dirs = workloads.uniform_dirs(sum(counts), r)
+    off = np.cumsum([0] + [l.size // 4 for l in luts])[:-1]
+    qb = np.cumsum([0] + counts)[:-1]
+    flat = np.concatenate([l.reshape(-1) for l in luts])
+    out = oracle.query_objects(flat, off, Ns, qb, counts, dirs)
+    for k in range(3):
+        ref = oracle.query(luts[k], dirs[qb[k]:qb[k] + counts[k]])
+        assert np.array_equal(out[qb[k]:qb[k] + counts[k]], ref)

@@ -1,0 +1,215 @@
+"""Seeded synthetic inputs for the Spherical Hermite Maps workloads.
+
+This module holds no arithmetic of the method itself (no cubemap mapping, no
+bake, no Hermite reconstruction, no gradient transport): it draws random
+numbers and evaluates the *target* functions that a user would hand to the
+method (SH coefficient vectors, Gaussian bumps, value-noise heightfields),
+plus camera rays.  Both the FP64 oracle and the GPU library consume what it
+produces; neither imports the other.
+
+Every generator takes a ``numpy.random.Generator`` (PCG64).  The canonical
+workloads use seed 20063 + k for workload k (k = 1..5).
+
+Workloads (all synthetic; the paper's own glyph seed, dMRI data, asteroid
+mesh and planet generator are not available, these stand in for them):
+  1  one SH glyph, L=4, face N=10, 65,536 uniform directions
+  2  32,768 SH glyphs, L=8, N=32, 256 uniform directions per glyph
+  3  one radial impostor, 64 Gaussian bumps on radius 1, N=256,
+     1920x1080 primary rays
+  4  fBm heightfield target 1 + 0.2 fBm(w), 2^22 directions, N=512
+  5  4,096 uneven objects, N in {8..256}, L in {2..16}, lognormal counts
+"""
+import math
+
+import numpy as np
+
+SEED_BASE = 20063
+
+
+def rng_for(workload):
+    return np.random.default_rng(SEED_BASE + int(workload))
+
+
+# --------------------------------------------------------------------------
+# directions
+# --------------------------------------------------------------------------
+def uniform_dirs(n, rng):
+    """Uniform on the sphere: normalised N(0, I3), drawn in FP64 and rounded
+    once to FP32 (the rounded vectors are the inputs; they are not
+    renormalised)."""
+    g = rng.standard_normal((n, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    return g.astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# SH glyph coefficients
+# --------------------------------------------------------------------------
+def sh_degree_of_index(L):
+    return np.concatenate([np.full(2 * l + 1, l) for l in range(L + 1)])
+
+
+def sh_glyph_coeffs(L, n_obj, rng):
+    """Coefficients c_lm = z / (1 + l)^2, z ~ N(0, 1), then the affine map
+    R = 1 + 0.3 SH / B folded in, with B the coefficient bound
+    B = sum_l |c_l| sqrt((2l+1) / 4pi) >= max |SH| (Cauchy-Schwarz plus the
+    addition theorem), so that R lies in [0.7, 1.3] without evaluating SH.
+    Y_00 = 1 / (2 sqrt(pi)), so the constant 1 is c_00 += 2 sqrt(pi).
+    Returns FP64 [n_obj, (L+1)^2]; index k = l^2 + l + m."""
+    K = (L + 1) ** 2
+    lk = sh_degree_of_index(L)
+    c = rng.standard_normal((n_obj, K)) / (1.0 + lk) ** 2
+    B = np.zeros(n_obj)
+    for l in range(L + 1):
+        sl = slice(l * l, (l + 1) * (l + 1))
+        B += np.linalg.norm(c[:, sl], axis=1) * math.sqrt((2 * l + 1) / (4 * math.pi))
+    c = 0.3 * c / B[:, None]
+    c[:, 0] += 2.0 * math.sqrt(math.pi)
+    return c
+
+
+# --------------------------------------------------------------------------
+# Gaussian bumps (workload 3)
+# --------------------------------------------------------------------------
+def bump_params(rng, K=64):
+    """Centres uniform on the sphere, amplitudes U[0.02, 0.15], widths
+    U[0.05, 0.4] rad; the bump is a exp((w . mu - 1) / width^2) (von
+    Mises-Fisher form, ~ exp(-theta^2 / (2 width^2)) near its centre)."""
+    mu = rng.standard_normal((K, 3))
+    mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+    amp = rng.uniform(0.02, 0.15, K)
+    width = rng.uniform(0.05, 0.4, K)
+    return mu, amp, width
+
+
+def bumps_value(mu, amp, width, base, dirs):
+    """R(w) = base + sum_k amp_k exp((w . mu_k - 1) / width_k^2), w = d/|d|."""
+    d = np.asarray(dirs, np.float64).reshape(-1, 3)
+    w = d / np.linalg.norm(d, axis=1, keepdims=True)
+    out = np.full(w.shape[0], float(base))
+    for k in range(len(amp)):
+        out += amp[k] * np.exp((w @ mu[k] - 1.0) / (width[k] ** 2))
+    return out
+
+
+def camera_rays(width=1920, height=1080, eye=(0.0, 0.0, 3.5), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=40.0):
+    """Pinhole camera, one ray per pixel centre (row-major, top row first).
+    Returns origins [P, 3] and unit directions [P, 3], FP32."""
+    eye = np.asarray(eye, np.float64)
+    fwd = np.asarray(target, np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, np.asarray(up, np.float64))
+    right /= np.linalg.norm(right)
+    upv = np.cross(right, fwd)
+    th = math.tan(math.radians(vfov_deg) / 2.0)
+    aspect = width / height
+    px = (np.arange(width) + 0.5) / width * 2.0 - 1.0
+    py = 1.0 - (np.arange(height) + 0.5) / height * 2.0
+    X, Y = np.meshgrid(px * th * aspect, py * th)
+    d = fwd[None, None, :] + X[..., None] * right[None, None, :] + Y[..., None] * upv[None, None, :]
+    d = d.reshape(-1, 3)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(eye, d.shape)
+    return np.ascontiguousarray(o, np.float32), np.ascontiguousarray(d, np.float32)
+
+
+# --------------------------------------------------------------------------
+# fBm value-noise heightfield (workload 4)
+# --------------------------------------------------------------------------
+def _hash3(ix, iy, iz, seed):
+    """32-bit integer hash of a lattice point -> U[-1, 1] (murmur3 finaliser)."""
+    h = (ix.astype(np.uint32) * np.uint32(0x8DA6B343)) ^ (iy.astype(np.uint32) * np.uint32(0xD8163841)) \
+        ^ (iz.astype(np.uint32) * np.uint32(0xCB1AB31F)) ^ np.uint32(seed)
+    h ^= h >> np.uint32(16)
+    h *= np.uint32(0x85EBCA6B)
+    h ^= h >> np.uint32(13)
+    h *= np.uint32(0xC2B2AE35)
+    h ^= h >> np.uint32(16)
+    return h.astype(np.float64) / 4294967295.0 * 2.0 - 1.0
+
+
+def _fade(x):
+    return x * x * x * (x * (x * 6.0 - 15.0) + 10.0)
+
+
+def _dfade(x):
+    return 30.0 * x * x * (x * (x - 2.0) + 1.0)
+
+
+def value_noise(p, seed):
+    """Trilinear value noise with quintic fade; returns value [n] and the
+    ambient gradient [n, 3]."""
+    with np.errstate(over="ignore"):
+        fl = np.floor(p)
+        i = fl.astype(np.int64)
+        f = p - fl
+        w = _fade(f)
+        dw = _dfade(f)
+        val = np.zeros(p.shape[0])
+        grad = np.zeros_like(p)
+        for cx in (0, 1):
+            for cy in (0, 1):
+                for cz in (0, 1):
+                    h = _hash3(i[:, 0] + cx, i[:, 1] + cy, i[:, 2] + cz, seed)
+                    wx = w[:, 0] if cx else 1.0 - w[:, 0]
+                    wy = w[:, 1] if cy else 1.0 - w[:, 1]
+                    wz = w[:, 2] if cz else 1.0 - w[:, 2]
+                    sx = 1.0 if cx else -1.0
+                    sy = 1.0 if cy else -1.0
+                    sz = 1.0 if cz else -1.0
+                    val += h * wx * wy * wz
+                    grad[:, 0] += h * sx * dw[:, 0] * wy * wz
+                    grad[:, 1] += h * wx * sy * dw[:, 1] * wz
+                    grad[:, 2] += h * wx * wy * sz * dw[:, 2]
+    return val, grad
+
+
+def fbm_target(dirs, seed, octaves=6, lacunarity=2.0, gain=0.5, f0=2.0, amp=0.2):
+    """R*(w) = 1 + amp * fBm(w), fBm = sum_o gain^o noise(lacunarity^o f0 w)
+    / sum_o gain^o.  Returns R* [n] and its spherical gradient [n, 3] (the
+    tangential part of the ambient gradient at the unit direction)."""
+    d = np.asarray(dirs, np.float64).reshape(-1, 3)
+    w = d / np.linalg.norm(d, axis=1, keepdims=True)
+    val = np.zeros(w.shape[0])
+    grad = np.zeros_like(w)
+    norm = sum(gain ** o for o in range(octaves))
+    for o in range(octaves):
+        freq = f0 * lacunarity ** o
+        v, g = value_noise(w * freq, seed + 101 * o)
+        val += gain ** o * v
+        grad += gain ** o * freq * g
+    val = 1.0 + amp * val / norm
+    grad = amp * grad / norm
+    grad -= np.sum(grad * w, axis=1, keepdims=True) * w
+    return val, grad
+
+
+# --------------------------------------------------------------------------
+# uneven batch (workload 5)
+# --------------------------------------------------------------------------
+BATCH_NS = (8, 16, 32, 64, 128, 256)
+BATCH_NP = (0.3, 0.25, 0.2, 0.15, 0.07, 0.03)
+
+
+def uneven_batch(rng, n_obj=4096, mu=9.0, sigma=1.5, qmin=64, qmax=1 << 20, Lmin=2, Lmax=16):
+    """Per object: face size N, SH order L, query count Q (lognormal,
+    clipped).  Returns dict of int arrays."""
+    Ns = rng.choice(np.array(BATCH_NS), size=n_obj, p=np.array(BATCH_NP))
+    Ls = rng.integers(Lmin, Lmax + 1, size=n_obj)
+    Q = np.clip(np.rint(rng.lognormal(mu, sigma, size=n_obj)), qmin, qmax).astype(np.int64)
+    return {"N": Ns.astype(np.int32), "L": Ls.astype(np.int32), "Q": Q}
+
+
+# --------------------------------------------------------------------------
+# arbitrary LUT contents (the query is defined for any LUT)
+# --------------------------------------------------------------------------
+def random_lut(N, rng, n_obj=None, base=1.0, spread=0.2):
+    """Random texel data in LUT layout [..., 6, N+2, N+2, 4]: values in
+    base +- spread, scaled derivative channels of a comparable scale."""
+    shape = (6, N + 2, N + 2, 4) if n_obj is None else (n_obj, 6, N + 2, N + 2, 4)
+    x = rng.uniform(-1.0, 1.0, shape)
+    x[..., 0] = base + spread * x[..., 0]
+    x[..., 1] *= 0.5 * spread
+    x[..., 2] *= 0.5 * spread
+    x[..., 3] *= 0.25 * spread
+    return x.astype(np.float32)
