@@ -1,0 +1,240 @@
+/*
+ * shm.h -- C ABI of the MI355X (gfx950) Spherical Hermite Maps library.
+ *
+ * Spherical Hermite Maps (Abouagour & Garyfallidis, arXiv 2602.20063) store a
+ * star-shaped radial function R(w) in a padded cube map whose texels hold the
+ * value and scaled chart derivatives (r, r_u h, r_v h, r_uv h^2), h = 1/N
+ * (Sec. 3.3, Eq. 2).  A query maps a direction to a face and (u, v), gathers
+ * one 2x2 texel footprint (16 scalars) and applies bicubic Hermite
+ * reconstruction (Eqs. 3-5); the chart derivatives become the spherical
+ * gradient through the cube-map metric tensor (Sec. 3.4, Eqs. 6-9) and the
+ * normal follows from Eq. 10.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers unless the comment says "host".
+ *    The caller allocates and owns every buffer, including workspaces; the
+ *    library never frees caller memory.  It allocates device memory only in
+ *    shm_plan_create (released by shm_plan_destroy).
+ *  - Every call is asynchronous on the given HIP stream (0 = the null
+ *    stream); arguments are validated on the host before anything is
+ *    enqueued.  Calls return SHM_OK or an error code and never throw;
+ *    shm_last_error() gives a thread-local message for the last failure.
+ *  - Faces are ordered +X, -X, +Y, -Y, +Z, -Z with the hardware cube-map
+ *    (s, t) orientation: d/|ma| = M + sc S + tc T, u = (sc+1)/2,
+ *    v = (tc+1)/2 (Sec. 3.2).  Face ties go X before Y before Z, and a
+ *    component >= 0 (including -0) selects the positive face.
+ *  - TEXEL layout (the paper's padded cube map, Sec. 3.2-3.3):
+ *      lut[obj][face][q][p][ch], q = v row 0..N+1, p = u column 0..N+1,
+ *      ch = (r, r_u h, r_v h, r_uv h^2); padded texel p has its centre at
+ *      u = (p - 1/2)/N, p = 0 and N+1 are the one-texel gutter.
+ *    CELL layout (derived copy of the same data for the gather): every cell
+ *      (i0, j0), i0, j0 in 0..N, stores its whole 2x2 footprint contiguously:
+ *      lut[obj][face][j0][i0][corner][ch], corner = (i0,j0), (i0+1,j0),
+ *      (i0,j0+1), (i0+1,j0+1), so one query reads one aligned 64 B (FP32)
+ *      or 32 B (FP16) block.
+ *  - Queries: directions need not be unit length (w = d/|d|).  A zero or
+ *    non-finite direction is not an error: its outputs are NaN.
+ *  - Output of a query: out[q] = (R, gx, gy, gz) with (gx, gy, gz) the
+ *    spherical gradient of R as an ambient vector (tangent to the sphere);
+ *    normal[q] = (R w - grad R) / |R w - grad R| (Eq. 10), optional.
+ */
+#ifndef SHM_H
+#define SHM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHM_ABI_VERSION 1
+
+#if defined(__GNUC__)
+#define SHM_API __attribute__((visibility("default")))
+#else
+#define SHM_API
+#endif
+
+typedef enum {
+    SHM_OK = 0,
+    SHM_ERR_INVALID_ARG = 1, /* null pointer, size out of range, bad enum */
+    SHM_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. L > 16)  */
+    SHM_ERR_WORKSPACE = 3,   /* workspace missing or too small            */
+    SHM_ERR_HIP = 4          /* a HIP runtime call failed                 */
+} shm_status;
+
+typedef enum { SHM_F32 = 0, SHM_F16 = 1 } shm_dtype;
+typedef enum { SHM_LAYOUT_TEXEL = 0, SHM_LAYOUT_CELL = 1 } shm_layout;
+
+#define SHM_MAX_N 1024 /* largest interior face resolution */
+#define SHM_MAX_L 16   /* largest SH order of the analytic bake */
+
+/* ABI version (SHM_ABI_VERSION). */
+SHM_API int shm_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next call on this thread. */
+SHM_API const char* shm_last_error(void);
+
+/* Number of scalar elements of one object's LUT: 6 (N+2)^2 4 for TEXEL,
+ * 6 (N+1)^2 16 for CELL.  0 for an invalid N or layout. */
+SHM_API int64_t shm_lut_elems(int32_t N, int32_t layout);
+
+/* ------------------------------------------------------------------------
+ * Bake, analytic SH mode (Sec. 3.3 Alg. 1; "Analytic SH derivatives").
+ * Every padded texel, gutter included, gets (G, G_u h, G_v h, G_uv h^2) of
+ * G(u,v) = sum_k coeffs[k] Y_k(normalise(M + (2u-1) S + (2v-1) T)), with
+ * orthonormal real SH (no Condon-Shortley phase), k = l^2 + l + m.
+ *   coeffs   [n_obj][(L+1)^2] FP32 (any affine map already folded in)
+ *   L        0..16;  N 1..SHM_MAX_N;  n_obj >= 1
+ *   lut_out  [n_obj][6][N+2][N+2][4] in out_dtype (TEXEL layout)
+ *   ws       workspace of shm_bake_sh_lut_workspace(L, N) bytes: the SH
+ *            basis table (value, h-scaled first and mixed derivatives at
+ *            every padded texel), rebuilt by every call
+ * The contraction coeffs x basis runs on the matrix cores (FP32 MFMA, FP32
+ * accumulation); the basis table is evaluated in FP64 and stored in FP32.
+ * ---------------------------------------------------------------------- */
+SHM_API size_t shm_bake_sh_lut_workspace(int32_t L, int32_t N);
+SHM_API int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Bake, general mode (Sec. 3.3 Alg. 1 with central differences and a
+ * one-texel bake-time margin).
+ * shm_margin_dirs writes the unit directions at which the caller samples its
+ * function: dirs [6][N+4][N+4][3] FP32, index p in 0..N+3 at u=(p-3/2)/N
+ * (p = 1..N+2 are the stored texels 0..N+1, p = 0 and N+3 the margin).
+ * shm_bake_fd turns samples [n_obj][6][N+4][N+4] FP32 taken at those
+ * directions into LUTs [n_obj][6][N+2][N+2][4] (TEXEL, out_dtype):
+ *   r_u h = (r[p+1] - r[p-1]) / 2,  r_v h likewise,
+ *   r_uv h^2 = (r[p+1,q+1] - r[p+1,q-1] - r[p-1,q+1] + r[p-1,q-1]) / 4.
+ * ---------------------------------------------------------------------- */
+SHM_API int shm_margin_dirs(int32_t N, float* dirs, hipStream_t stream);
+SHM_API int shm_bake_fd(const float* samples, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out, hipStream_t stream);
+
+/* TEXEL -> CELL copy of n_obj LUTs of face size N (same dtype). */
+SHM_API int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, int64_t n_obj, void* lut_cell,
+                     hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Query, value + gradient (Sec. 3.2-3.4, Eqs. 3-10): the hot path.
+ * n_obj objects of one face size N, stored back to back in `lut`
+ * (shm_lut_elems(N, layout) elements each); object o answers the queries
+ * dirs[o*q_per_obj .. (o+1)*q_per_obj).
+ *   lut     FP32 or FP16 (dtype), TEXEL or CELL (layout); FP16 data are
+ *           decoded to FP32 and all arithmetic is FP32
+ *   dirs    [n_obj*q_per_obj][3] FP32
+ *   out     [n_obj*q_per_obj][4] FP32 (R, gx, gy, gz)
+ *   normal  [n_obj*q_per_obj][3] FP32 or NULL
+ * The face and cell are decided in FP32 by: a = sc/ma, u = (a+1)*0.5,
+ * f = u*N + 0.5, i0 = min(floor(f), N), every step correctly rounded.
+ * ---------------------------------------------------------------------- */
+SHM_API int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
+                         int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many objects of different face sizes and query counts in
+ * one persistent launch.  Objects are described on the HOST:
+ *   lut_offset  element offset of the object's LUT inside `lut`
+ *   N           face size 1..SHM_MAX_N
+ *   q_begin     first query of the object in dirs/out
+ *   q_count     number of queries (>= 0)
+ * A plan owns the device copy of the descriptors, the work list (object,
+ * query range) items, the chosen launch shape and optionally a captured HIP
+ * graph.  The LUT dtype/layout are fixed at creation.
+ * ---------------------------------------------------------------------- */
+typedef struct shm_object {
+    int64_t lut_offset;
+    int32_t N;
+    int32_t reserved;
+    int64_t q_begin;
+    int64_t q_count;
+} shm_object;
+
+typedef struct shm_plan shm_plan;
+
+/* Launch shape of the persistent kernel. */
+typedef struct shm_launch_shape {
+    int32_t block;       /* threads per workgroup: 64, 128, 256 or 512        */
+    int32_t qpt;         /* queries per thread per pass: 1, 2 or 4            */
+    int32_t tile;        /* queries per work item, a multiple of block * qpt  */
+    int32_t grid_per_cu; /* persistent workgroups per compute unit, 1..32     */
+} shm_launch_shape;
+
+SHM_API int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, int32_t layout, hipStream_t stream,
+                    shm_plan** plan_out);
+/* Times every candidate launch shape on the given (real) buffers, keeps the
+ * fastest and returns it in *chosen (may be NULL).  Synchronises `stream`.
+ * cache_path: JSON file (host path) that remembers the choice for this
+ * workload signature, or NULL. */
+SHM_API int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float* out, const char* cache_path,
+                      hipStream_t stream, shm_launch_shape* chosen);
+SHM_API int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape);
+SHM_API int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal, hipStream_t stream);
+/* Captures one shm_plan_launch with these buffers into a HIP graph owned by
+ * the plan; shm_plan_graph_launch replays it on `stream`. */
+SHM_API int shm_plan_capture_graph(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal,
+                           hipStream_t stream);
+SHM_API int shm_plan_graph_launch(shm_plan* plan, hipStream_t stream);
+SHM_API int64_t shm_plan_work_items(const shm_plan* plan);
+SHM_API int shm_plan_destroy(shm_plan* plan);
+
+/* ------------------------------------------------------------------------
+ * Backward (differentiation form) for FP32 TEXEL LUTs with uniform objects
+ * as in shm_query_value_grad.  With upstream grad_out[q] = dL/d(R, g):
+ *   grad_lut   dL/dLUT, FP32, same shape as lut, overwritten (or NULL)
+ *   grad_dirs  dL/d dirs [Q][3] (or NULL); the outputs are 0-homogeneous
+ *              in d, so grad_dirs[q] . dirs[q] = 0
+ * grad_lut is deterministic: queries are sorted by cell once (stable: by
+ * cell, then by query index) and every texel pulls the contributions of the
+ * queries of its <= 4 adjacent cells in that fixed order; no floating-point
+ * atomics.  shm_backward_sort builds the sort in the workspace; it stays
+ * valid while dirs (and N, n_obj, q_per_obj) are unchanged, so a fitting
+ * loop sorts once and passes sort_ready = 1 afterwards.
+ * ---------------------------------------------------------------------- */
+SHM_API size_t shm_backward_workspace(int32_t N, int64_t n_obj, int64_t q_per_obj);
+/* Cell key of every query: ((obj*6 + face)*(N+1) + j0)*(N+1) + i0, or
+ * 0xFFFFFFFF for an invalid direction.  keys [n_obj*q_per_obj] uint32.
+ * A caller whose directions stay fixed (a fitting loop) can reorder its
+ * queries once by (key, index); the backward's per-query pass is then
+ * coalesced. */
+SHM_API int shm_cell_keys(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream);
+SHM_API int shm_backward_sort(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+SHM_API int shm_query_backward(const float* lut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
+                       const float* grad_out, float* grad_lut, float* grad_dirs, void* ws, size_t ws_bytes,
+                       int32_t sort_ready, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Ray casting against x(w) = c + R(w) w (Sec. 3.1, Eq. 1), one object.
+ * F(t) = |o + t d - c| - R(w), F'(t) = d.w - (d . grad R)/|o + t d - c|.
+ * Schedule (fixed counts): bounding sphere |x - c| = rmax -> [t_in, t_out]
+ * (miss if none or t_out < 0); march t_k = t0 + k (t_out - t0)/n_march,
+ * t0 = max(t_in, 0), k = 1..n_march, the first F(t_k) < 0 brackets the
+ * root; n_bisect halvings; n_newton safeguarded Newton steps from the
+ * bracket midpoint (a step leaving the closed bracket falls back to its
+ * midpoint); one last evaluation at the final t.
+ *   center   host float[3];  rmax > 0 must bound R (see shm_lut_rmax)
+ *   ray_o, ray_d  [P][3] FP32 (d need not be unit)
+ *   t_out    [P] (+inf on a miss);  out [P][4] (R, grad) and normal [P][3]
+ *            (may be NULL) at the hit, NaN on a miss
+ * n_march + n_bisect + n_newton + 1 <= 64 evaluations per ray.
+ * ---------------------------------------------------------------------- */
+SHM_API int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax, const float* ray_o,
+                     const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
+                     float* out, float* normal, hipStream_t stream);
+
+/* Upper bound of the reconstructed R over one TEXEL LUT: the largest Bezier
+ * control point of any cell's bicubic patch (convex hull property).  Writes
+ * one float to rmax_out (device). */
+SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHM_H */

@@ -70,6 +70,11 @@ def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
 
 
+def num_threads():
+    """OpenMP threads the oracle runs with."""
+    return int(lib().orc_num_threads())
+
+
 def lut_shape(N):
     return (6, N + 2, N + 2, 4)
 

@@ -442,6 +442,8 @@ ORC_API void orc_reconstruct(const double* lut, int N, int face, int i0, int j0,
 ORC_API void orc_query_objects(const double* lut, const int64_t* lut_off, const int32_t* Ns, const int64_t* q_begin,
                                const int64_t* q_count, int64_t n_obj, const float* dirs, double* out, double* normal)
 {
+    /* objects in parallel; the per-object loop inside runs on its thread */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t o = 0; o < n_obj; ++o)
         orc_query(lut + 4 * lut_off[o], Ns[o], dirs + 3 * q_begin[o], q_count[o], 0, out + 4 * q_begin[o],
                   normal ? normal + 3 * q_begin[o] : NULL);
@@ -890,3 +892,10 @@ ORC_API void orc_trace_F(const double* lut, int N, const double* center, const d
 }
 
 ORC_API int orc_version(void) { return 1; }
+
+#ifdef _OPENMP
+#include <omp.h>
+ORC_API int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+ORC_API int orc_num_threads(void) { return 1; }
+#endif

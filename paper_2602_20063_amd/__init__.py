@@ -1,0 +1,388 @@
+"""MI355X (gfx950) Spherical Hermite Maps: Python binding of libshm.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libshm.so`` (built from ``csrc/`` by ``build.py``).  PyTorch provides
+device memory and streams.  There is no CPU fallback: if the library is not
+built or no GPU is present the calls raise.
+
+The functions named ``shm_*`` mirror the C ABI in ``include/shm.h`` one to
+one (same names and arguments, tensors in place of device pointers); the
+helpers below them allocate outputs and workspaces with torch.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshm.so")
+
+SHM_OK, SHM_ERR_INVALID_ARG, SHM_ERR_UNSUPPORTED, SHM_ERR_WORKSPACE, SHM_ERR_HIP = range(5)
+SHM_F32, SHM_F16 = 0, 1
+SHM_LAYOUT_TEXEL, SHM_LAYOUT_CELL = 0, 1
+SHM_MAX_N, SHM_MAX_L = 1024, 16
+
+
+class ShmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libshm error {code}: {msg}")
+        self.code = code
+
+
+class shm_object(ctypes.Structure):
+    _fields_ = [("lut_offset", ctypes.c_int64), ("N", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("q_begin", ctypes.c_int64), ("q_count", ctypes.c_int64)]
+
+
+class shm_launch_shape(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("qpt", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"block": self.block, "qpt": self.qpt, "tile": self.tile, "grid_per_cu": self.grid_per_cu}
+
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "shm_version": (ctypes.c_int, []),
+    "shm_last_error": (ctypes.c_char_p, []),
+    "shm_lut_elems": (_I64, [_I32, _I32]),
+    "shm_bake_sh_lut_workspace": (_SZ, [_I32, _I32]),
+    "shm_bake_sh_lut": (ctypes.c_int, [_VP, _I32, _I32, _I64, _I32, _VP, _VP, _SZ, _VP]),
+    "shm_margin_dirs": (ctypes.c_int, [_I32, _VP, _VP]),
+    "shm_bake_fd": (ctypes.c_int, [_VP, _I32, _I64, _I32, _VP, _VP]),
+    "shm_lut_to_cells": (ctypes.c_int, [_VP, _I32, _I32, _I64, _VP, _VP]),
+    "shm_query_value_grad": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I64, _VP, _I64, _VP, _VP, _VP]),
+    "shm_plan_create": (ctypes.c_int, [_VP, _I64, _I32, _I32, _VP, ctypes.POINTER(_VP)]),
+    "shm_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_char_p, _VP, ctypes.POINTER(shm_launch_shape)]),
+    "shm_plan_set_shape": (ctypes.c_int, [_VP, ctypes.POINTER(shm_launch_shape)]),
+    "shm_plan_launch": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "shm_plan_capture_graph": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "shm_plan_graph_launch": (ctypes.c_int, [_VP, _VP]),
+    "shm_plan_work_items": (_I64, [_VP]),
+    "shm_plan_destroy": (ctypes.c_int, [_VP]),
+    "shm_backward_workspace": (_SZ, [_I32, _I64, _I64]),
+    "shm_cell_keys": (ctypes.c_int, [_I32, _I64, _VP, _I64, _VP, _VP]),
+    "shm_backward_sort": (ctypes.c_int, [_I32, _I64, _VP, _I64, _VP, _SZ, _VP]),
+    "shm_query_backward": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _I32, _VP]),
+    "shm_trace_radial": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP,
+                                        _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
+    "shm_lut_rmax": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libshm.so (fails loudly if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2602_20063_amd/build.py (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SHM_OK:
+        raise ShmError(rc, lib().shm_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libshm takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libshm takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return SHM_F32
+    if t.dtype == torch.float16:
+        return SHM_F16
+    raise ValueError(f"LUT dtype must be float32 or float16, got {t.dtype}")
+
+
+def _need(t, dtype, name):
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+# ---------------------------------------------------------------------------
+# one-to-one mirrors of the C ABI
+# ---------------------------------------------------------------------------
+def shm_version():
+    return lib().shm_version()
+
+
+def shm_last_error():
+    return lib().shm_last_error().decode()
+
+
+def shm_lut_elems(N, layout=SHM_LAYOUT_TEXEL):
+    return lib().shm_lut_elems(N, layout)
+
+
+def shm_bake_sh_lut_workspace(L, N):
+    return lib().shm_bake_sh_lut_workspace(L, N)
+
+
+def shm_bake_sh_lut(coeffs, L, N, n_obj, out_dtype, lut_out, ws, stream=None):
+    _need(coeffs, torch.float32, "coeffs")
+    return _check(lib().shm_bake_sh_lut(_ptr(coeffs), L, N, n_obj, out_dtype, _ptr(lut_out), _ptr(ws),
+                                        ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def shm_margin_dirs(N, dirs, stream=None):
+    _need(dirs, torch.float32, "dirs")
+    return _check(lib().shm_margin_dirs(N, _ptr(dirs), _stream(stream)))
+
+
+def shm_bake_fd(samples, N, n_obj, out_dtype, lut_out, stream=None):
+    _need(samples, torch.float32, "samples")
+    return _check(lib().shm_bake_fd(_ptr(samples), N, n_obj, out_dtype, _ptr(lut_out), _stream(stream)))
+
+
+def shm_lut_to_cells(lut_texel, dtype, N, n_obj, lut_cell, stream=None):
+    return _check(lib().shm_lut_to_cells(_ptr(lut_texel), dtype, N, n_obj, _ptr(lut_cell), _stream(stream)))
+
+
+def shm_query_value_grad(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, normal=None, stream=None):
+    _need(dirs, torch.float32, "dirs")
+    _need(out, torch.float32, "out")
+    return _check(lib().shm_query_value_grad(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, _ptr(out),
+                                             _ptr(normal), _stream(stream)))
+
+
+def shm_backward_workspace(N, n_obj, q_per_obj):
+    return lib().shm_backward_workspace(N, n_obj, q_per_obj)
+
+
+def shm_cell_keys(N, n_obj, dirs, q_per_obj, keys, stream=None):
+    _need(keys, torch.int32, "keys (uint32 bits stored as int32)")
+    return _check(lib().shm_cell_keys(N, n_obj, _ptr(dirs), q_per_obj, _ptr(keys), _stream(stream)))
+
+
+def shm_backward_sort(N, n_obj, dirs, q_per_obj, ws, stream=None):
+    return _check(lib().shm_backward_sort(N, n_obj, _ptr(dirs), q_per_obj, _ptr(ws), ws.numel() * ws.element_size(),
+                                          _stream(stream)))
+
+
+def shm_query_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_dirs, ws, sort_ready, stream=None):
+    return _check(lib().shm_query_backward(_ptr(lut), N, n_obj, _ptr(dirs), q_per_obj, _ptr(grad_out), _ptr(grad_lut),
+                                           _ptr(grad_dirs), _ptr(ws), ws.numel() * ws.element_size(),
+                                           1 if sort_ready else 0, _stream(stream)))
+
+
+def shm_trace_radial(lut, dtype, N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out,
+                     normal=None, stream=None):
+    c = (ctypes.c_float * 3)(*[float(x) for x in center])
+    return _check(lib().shm_trace_radial(_ptr(lut), dtype, N, c, float(rmax), _ptr(ray_o), _ptr(ray_d), P, n_march,
+                                         n_bisect, n_newton, _ptr(t_out), _ptr(out), _ptr(normal), _stream(stream)))
+
+
+def shm_lut_rmax(lut, dtype, N, rmax_out, stream=None):
+    return _check(lib().shm_lut_rmax(_ptr(lut), dtype, N, _ptr(rmax_out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# plans (batched form)
+# ---------------------------------------------------------------------------
+class Plan:
+    """Owns a shm_plan: the batched persistent launch over uneven objects.
+
+    objs: sequence of (lut_offset, N, q_begin, q_count)."""
+
+    def __init__(self, objs, dtype, layout=SHM_LAYOUT_TEXEL, stream=None):
+        arr = (shm_object * len(objs))()
+        for i, (off, N, qb, qc) in enumerate(objs):
+            arr[i].lut_offset, arr[i].N, arr[i].reserved, arr[i].q_begin, arr[i].q_count = int(off), int(N), 0, int(qb), int(qc)
+        self._arr = arr
+        self.dtype, self.layout = dtype, layout
+        h = ctypes.c_void_p()
+        _check(lib().shm_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(objs), dtype, layout, _stream(stream),
+                                     ctypes.byref(h)))
+        self.handle = h
+
+    def autotune(self, lut, dirs, out, cache_path=None, stream=None):
+        s = shm_launch_shape()
+        _check(lib().shm_plan_autotune(self.handle, _ptr(lut), _ptr(dirs), _ptr(out),
+                                       cache_path.encode() if cache_path else None, _stream(stream), ctypes.byref(s)))
+        return s.as_dict()
+
+    def set_shape(self, block, qpt, tile, grid_per_cu):
+        s = shm_launch_shape(block, qpt, tile, grid_per_cu)
+        _check(lib().shm_plan_set_shape(self.handle, ctypes.byref(s)))
+
+    def launch(self, lut, dirs, out, normal=None, stream=None):
+        _check(lib().shm_plan_launch(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), _ptr(normal), _stream(stream)))
+
+    def capture_graph(self, lut, dirs, out, normal=None, stream=None):
+        _check(lib().shm_plan_capture_graph(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), _ptr(normal), _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        _check(lib().shm_plan_graph_launch(self.handle, _stream(stream)))
+
+    @property
+    def work_items(self):
+        return lib().shm_plan_work_items(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().shm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# allocating helpers
+# ---------------------------------------------------------------------------
+def lut_n(lut, layout=SHM_LAYOUT_TEXEL):
+    """Face size N of a LUT tensor [..., 6, N+2, N+2, 4] (TEXEL) or
+    [..., 6, N+1, N+1, 16] (CELL)."""
+    return lut.shape[-2] - (2 if layout == SHM_LAYOUT_TEXEL else 1)
+
+
+def bake_sh(coeffs, N, dtype=torch.float32, stream=None):
+    """coeffs [n_obj, (L+1)^2] FP32 (device) -> LUT [n_obj, 6, N+2, N+2, 4]."""
+    n_obj, K = coeffs.shape
+    L = int(round(K ** 0.5)) - 1
+    if (L + 1) ** 2 != K:
+        raise ValueError("coeffs must have (L+1)^2 columns")
+    lut = torch.empty((n_obj, 6, N + 2, N + 2, 4), dtype=dtype, device=coeffs.device)
+    ws = torch.empty(max(shm_bake_sh_lut_workspace(L, N), 1), dtype=torch.uint8, device=coeffs.device)
+    shm_bake_sh_lut(coeffs, L, N, n_obj, _dtype_code(lut), lut, ws, stream)
+    return lut
+
+
+def to_cells(lut, stream=None):
+    """TEXEL LUT [n, 6, N+2, N+2, 4] -> CELL LUT [n, 6, N+1, N+1, 16]."""
+    N = lut_n(lut)
+    n_obj = lut.numel() // (6 * (N + 2) * (N + 2) * 4)
+    cells = torch.empty((n_obj, 6, N + 1, N + 1, 16), dtype=lut.dtype, device=lut.device)
+    shm_lut_to_cells(lut, _dtype_code(lut), N, n_obj, cells, stream)
+    return cells
+
+
+def query(lut, dirs, q_per_obj=None, layout=SHM_LAYOUT_TEXEL, normals=False, stream=None):
+    """Value + spherical gradient: lut [n_obj, 6, ...] (TEXEL or CELL),
+    dirs [n_obj * q_per_obj, 3] -> out [Q, 4] (R, grad) (+ normal [Q, 3])."""
+    N = lut_n(lut, layout)
+    per = 6 * (N + 2) * (N + 2) * 4 if layout == SHM_LAYOUT_TEXEL else 6 * (N + 1) * (N + 1) * 16
+    n_obj = lut.numel() // per
+    Q = dirs.shape[0]
+    if q_per_obj is None:
+        q_per_obj = Q // n_obj
+    if q_per_obj * n_obj != Q:
+        raise ValueError("dirs must hold n_obj * q_per_obj directions")
+    out = torch.empty((Q, 4), dtype=torch.float32, device=dirs.device)
+    nrm = torch.empty((Q, 3), dtype=torch.float32, device=dirs.device) if normals else None
+    shm_query_value_grad(lut, _dtype_code(lut), layout, N, n_obj, dirs, q_per_obj, out, nrm, stream)
+    return (out, nrm) if normals else out
+
+
+def margin_dirs(N, device="cuda", stream=None):
+    d = torch.empty((6, N + 4, N + 4, 3), dtype=torch.float32, device=device)
+    shm_margin_dirs(N, d, stream)
+    return d
+
+
+def bake_fd(samples, N, dtype=torch.float32, stream=None):
+    """samples [n_obj, 6, N+4, N+4] at margin_dirs(N) -> LUT."""
+    n_obj = samples.numel() // (6 * (N + 4) * (N + 4))
+    lut = torch.empty((n_obj, 6, N + 2, N + 2, 4), dtype=dtype, device=samples.device)
+    shm_bake_fd(samples, N, n_obj, _dtype_code(lut), lut, stream)
+    return lut
+
+
+def lut_rmax(lut, stream=None):
+    N = lut_n(lut)
+    r = torch.empty(1, dtype=torch.float32, device=lut.device)
+    shm_lut_rmax(lut, _dtype_code(lut), N, r, stream)
+    return r
+
+
+def cell_keys(lut_N, dirs, n_obj=1, stream=None):
+    Q = dirs.shape[0]
+    keys = torch.empty(Q, dtype=torch.int32, device=dirs.device)
+    shm_cell_keys(lut_N, n_obj, dirs, Q // n_obj, keys, stream)
+    return keys
+
+
+def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, normals=True, stream=None):
+    N = lut_n(lut)
+    P = ray_o.shape[0]
+    t = torch.empty(P, dtype=torch.float32, device=ray_o.device)
+    out = torch.empty((P, 4), dtype=torch.float32, device=ray_o.device)
+    nrm = torch.empty((P, 3), dtype=torch.float32, device=ray_o.device) if normals else None
+    shm_trace_radial(lut, _dtype_code(lut), N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t, out,
+                     nrm, stream)
+    return t, out, nrm
+
+
+class BackwardContext:
+    """Workspace + cached sort for repeated backward passes over fixed
+    directions (a fitting loop)."""
+
+    def __init__(self, N, n_obj, dirs, q_per_obj, stream=None):
+        self.N, self.n_obj, self.q_per_obj = N, n_obj, q_per_obj
+        self.dirs = dirs
+        nbytes = shm_backward_workspace(N, n_obj, q_per_obj)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dirs.device)
+        shm_backward_sort(N, n_obj, dirs, q_per_obj, self.ws, stream)
+
+    def backward(self, lut, grad_out, want_lut=True, want_dirs=True, stream=None):
+        gl = torch.empty_like(lut) if want_lut else None
+        gd = torch.empty((self.dirs.shape[0], 3), dtype=torch.float32, device=lut.device) if want_dirs else None
+        shm_query_backward(lut, self.N, self.n_obj, self.dirs, self.q_per_obj, grad_out.contiguous(), gl, gd, self.ws,
+                           True, stream)
+        return gl, gd
+
+
+class HermiteQuery(torch.autograd.Function):
+    """out = (R, grad R) of every direction; differentiable with respect to
+    the FP32 TEXEL LUT and to the directions (hand-written HIP backward)."""
+
+    @staticmethod
+    def forward(ctx, lut, dirs, bctx=None):
+        N = lut_n(lut)
+        n_obj = lut.numel() // (6 * (N + 2) * (N + 2) * 4)
+        out = torch.empty((dirs.shape[0], 4), dtype=torch.float32, device=dirs.device)
+        shm_query_value_grad(lut, SHM_F32, SHM_LAYOUT_TEXEL, N, n_obj, dirs, dirs.shape[0] // n_obj, out)
+        if bctx is None:
+            bctx = BackwardContext(N, n_obj, dirs.detach(), dirs.shape[0] // n_obj)
+        ctx.bctx = bctx
+        ctx.save_for_backward(lut, dirs)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        lut, dirs = ctx.saved_tensors
+        gl, gd = ctx.bctx.backward(lut, grad_out.contiguous().float(), want_lut=ctx.needs_input_grad[0],
+                                   want_dirs=ctx.needs_input_grad[1])
+        return gl, gd, None

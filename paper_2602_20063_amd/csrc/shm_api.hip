@@ -1,0 +1,525 @@
+// C ABI of libshm: argument validation, status codes, plans (batched form).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "shm_internal.hpp"
+
+namespace shm {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+int device_cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+// launchers implemented in the kernel translation units
+size_t bake_workspace_bytes(int L, int N);
+int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dtype, void* lut, void* ws,
+                   hipStream_t stream);
+int launch_margin_dirs(int N, float* dirs, hipStream_t stream);
+int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, void* lut, hipStream_t stream);
+int launch_lut_rmax(const void* lut, int dtype, int N, float* rmax_out, hipStream_t stream);
+size_t backward_workspace_bytes(int N, int64_t n_obj, int64_t q_per_obj);
+int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream);
+int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream);
+int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
+                    float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
+int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, const float* ray_o,
+                 const float* ray_d, int64_t P, int n_march, int n_bisect, int n_newton, float* t_out, float* out,
+                 float* normal, hipStream_t stream);
+
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+static bool valid_N(int N) { return N >= 1 && N <= SHM_MAX_N; }
+static bool valid_dtype(int d) { return d == SHM_F32 || d == SHM_F16; }
+static bool valid_layout(int l) { return l == SHM_LAYOUT_TEXEL || l == SHM_LAYOUT_CELL; }
+
+}  // namespace shm
+
+using namespace shm;
+
+// ---------------------------------------------------------------------------
+// plan (batched form)
+// ---------------------------------------------------------------------------
+struct shm_plan {
+    int dtype = 0, layout = 0, device = 0, n_cu = 256;
+    std::vector<shm_object> objs;
+    shm_object* d_objs = nullptr;
+    WorkItem* d_items = nullptr;
+    int64_t items_cap = 0, n_items = 0;
+    shm_launch_shape shape{256, 2, 2048, 8};
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t signature = 0;
+};
+
+static int plan_build_items(shm_plan* P, hipStream_t stream)
+{
+    std::vector<WorkItem> items;
+    const int64_t tile = P->shape.tile;
+    for (size_t o = 0; o < P->objs.size(); ++o) {
+        const shm_object& ob = P->objs[o];
+        for (int64_t q = 0; q < ob.q_count; q += tile) {
+            WorkItem w;
+            w.q0 = ob.q_begin + q;
+            w.obj = (int32_t)o;
+            w.n = (int32_t)std::min<int64_t>(tile, ob.q_count - q);
+            items.push_back(w);
+        }
+    }
+    const int64_t n = (int64_t)items.size();
+    if (n > P->items_cap) {
+        if (P->d_items) SHM_HIP_CHECK(hipFree(P->d_items));
+        P->d_items = nullptr;
+        P->items_cap = 0;
+        SHM_HIP_CHECK(hipMalloc(&P->d_items, (size_t)std::max<int64_t>(n, 1) * sizeof(WorkItem)));
+        P->items_cap = std::max<int64_t>(n, 1);
+    }
+    P->n_items = n;
+    if (n) {
+        SHM_HIP_CHECK(hipMemcpyAsync(P->d_items, items.data(), (size_t)n * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
+        SHM_HIP_CHECK(hipStreamSynchronize(stream));  // `items` is a host temporary
+    }
+    return SHM_OK;
+}
+
+static int check_shape(const shm_launch_shape& s)
+{
+    if (!(s.block == 64 || s.block == 128 || s.block == 256 || s.block == 512))
+        return fail(SHM_ERR_INVALID_ARG, "shape.block must be 64, 128, 256 or 512 (got %d)", s.block);
+    if (!(s.qpt == 1 || s.qpt == 2 || s.qpt == 4)) return fail(SHM_ERR_INVALID_ARG, "shape.qpt must be 1, 2 or 4");
+    if (s.tile <= 0 || s.tile % (s.block * s.qpt) != 0 || s.tile > (1 << 24))
+        return fail(SHM_ERR_INVALID_ARG, "shape.tile must be a positive multiple of block*qpt (<= 2^24)");
+    if (s.grid_per_cu < 1 || s.grid_per_cu > 32) return fail(SHM_ERR_INVALID_ARG, "shape.grid_per_cu must be 1..32");
+    return SHM_OK;
+}
+
+static uint64_t fnv1a(uint64_t h, const void* p, size_t n)
+{
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+extern "C" {
+
+int shm_version(void) { return SHM_ABI_VERSION; }
+
+const char* shm_last_error(void) { return g_err.c_str(); }
+
+int64_t shm_lut_elems(int32_t N, int32_t layout)
+{
+    if (!valid_N(N) || !valid_layout(layout)) return 0;
+    return layout == SHM_LAYOUT_CELL ? cell_elems(N) : texel_elems(N);
+}
+
+size_t shm_bake_sh_lut_workspace(int32_t L, int32_t N)
+{
+    if (L < 0 || L > SHM_MAX_L || !valid_N(N)) return 0;
+    return bake_workspace_bytes(L, N);
+}
+
+int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out,
+                    void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    if (L < 0) return fail(SHM_ERR_INVALID_ARG, "bake: L must be >= 0 (got %d)", L);
+    if (L > SHM_MAX_L) return fail(SHM_ERR_UNSUPPORTED, "bake: L must be <= %d (got %d)", SHM_MAX_L, L);
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bake: N must be 1..%d (got %d)", SHM_MAX_N, N);
+    if (n_obj < 0) return fail(SHM_ERR_INVALID_ARG, "bake: n_obj must be >= 0");
+    if (!valid_dtype(out_dtype)) return fail(SHM_ERR_INVALID_ARG, "bake: bad dtype %d", out_dtype);
+    if (n_obj == 0) return SHM_OK;
+    if (!coeffs || !lut_out) return fail(SHM_ERR_INVALID_ARG, "bake: null pointer");
+    if (!ws || ws_bytes < bake_workspace_bytes(L, N))
+        return fail(SHM_ERR_WORKSPACE, "bake: workspace of %zu bytes needed (got %zu)", bake_workspace_bytes(L, N), ws_bytes);
+    return launch_bake_sh(coeffs, L, N, n_obj, out_dtype, lut_out, ws, stream);
+}
+
+int shm_margin_dirs(int32_t N, float* dirs, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "margin_dirs: N must be 1..%d", SHM_MAX_N);
+    if (!dirs) return fail(SHM_ERR_INVALID_ARG, "margin_dirs: null pointer");
+    return launch_margin_dirs(N, dirs, stream);
+}
+
+int shm_bake_fd(const float* samples, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bake_fd: N must be 1..%d", SHM_MAX_N);
+    if (n_obj < 0 || !valid_dtype(out_dtype)) return fail(SHM_ERR_INVALID_ARG, "bake_fd: bad n_obj or dtype");
+    if (n_obj == 0) return SHM_OK;
+    if (!samples || !lut_out) return fail(SHM_ERR_INVALID_ARG, "bake_fd: null pointer");
+    if (!aligned(lut_out, out_dtype == SHM_F16 ? 8 : 16)) return fail(SHM_ERR_INVALID_ARG, "bake_fd: misaligned LUT");
+    return launch_bake_fd(samples, N, n_obj, out_dtype, lut_out, stream);
+}
+
+int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, int64_t n_obj, void* lut_cell, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N) || !valid_dtype(dtype) || n_obj < 0) return fail(SHM_ERR_INVALID_ARG, "lut_to_cells: bad N, dtype or n_obj");
+    if (n_obj == 0) return SHM_OK;
+    if (!lut_texel || !lut_cell) return fail(SHM_ERR_INVALID_ARG, "lut_to_cells: null pointer");
+    const size_t al = dtype == SHM_F16 ? 8 : 16;
+    if (!aligned(lut_texel, al) || !aligned(lut_cell, al)) return fail(SHM_ERR_INVALID_ARG, "lut_to_cells: misaligned");
+    return launch_lut_to_cells(lut_texel, dtype, N, n_obj, lut_cell, stream);
+}
+
+int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
+                         int64_t q_per_obj, float* out, float* normal, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype)) return fail(SHM_ERR_INVALID_ARG, "query: bad dtype %d", dtype);
+    if (!valid_layout(layout)) return fail(SHM_ERR_INVALID_ARG, "query: bad layout %d", layout);
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "query: N must be 1..%d (got %d)", SHM_MAX_N, N);
+    if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query: negative size");
+    if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
+    if (!lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "query: null pointer");
+    const size_t al = (dtype == SHM_F16 && layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(out, 16) || !aligned(dirs, 4) || (normal && !aligned(normal, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "query: misaligned buffer (lut %zu B, out 16 B)", al);
+    return launch_query_uniform(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, normal, stream);
+}
+
+// ---------------------------------------------------------------------------
+int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, int32_t layout, hipStream_t stream,
+                    shm_plan** plan_out)
+{
+    clear_error();
+    if (!plan_out) return fail(SHM_ERR_INVALID_ARG, "plan_create: null plan_out");
+    *plan_out = nullptr;
+    if (n_obj < 0 || (n_obj > 0 && !objs_host)) return fail(SHM_ERR_INVALID_ARG, "plan_create: bad object list");
+    if (n_obj > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "plan_create: too many objects");
+    if (!valid_dtype(dtype) || !valid_layout(layout)) return fail(SHM_ERR_INVALID_ARG, "plan_create: bad dtype/layout");
+    const int64_t align_elems = (dtype == SHM_F16) ? (layout == SHM_LAYOUT_CELL ? 8 : 4) : 4;
+    for (int64_t o = 0; o < n_obj; ++o) {
+        const shm_object& b = objs_host[o];
+        if (!valid_N(b.N)) return fail(SHM_ERR_INVALID_ARG, "plan_create: object %lld has N=%d", (long long)o, b.N);
+        if (b.lut_offset < 0 || b.lut_offset % align_elems)
+            return fail(SHM_ERR_INVALID_ARG, "plan_create: object %lld lut_offset %lld must be >= 0 and a multiple of %lld",
+                        (long long)o, (long long)b.lut_offset, (long long)align_elems);
+        if (b.q_begin < 0 || b.q_count < 0) return fail(SHM_ERR_INVALID_ARG, "plan_create: object %lld bad query range", (long long)o);
+    }
+    shm_plan* P = new shm_plan();
+    P->dtype = dtype;
+    P->layout = layout;
+    P->objs.assign(objs_host, objs_host + n_obj);
+    hipGetDevice(&P->device);
+    P->n_cu = device_cu_count();
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &dtype, sizeof dtype);
+    h = fnv1a(h, &layout, sizeof layout);
+    for (auto& b : P->objs) {
+        h = fnv1a(h, &b.N, sizeof b.N);
+        h = fnv1a(h, &b.q_count, sizeof b.q_count);
+    }
+    P->signature = h;
+    int rc;
+    if (hipMalloc(&P->d_objs, (size_t)std::max<int64_t>(n_obj, 1) * sizeof(shm_object)) != hipSuccess) {
+        delete P;
+        return fail(SHM_ERR_HIP, "plan_create: hipMalloc failed");
+    }
+    if (n_obj && hipMemcpyAsync(P->d_objs, objs_host, (size_t)n_obj * sizeof(shm_object), hipMemcpyHostToDevice, stream) != hipSuccess) {
+        shm_plan_destroy(P);
+        return fail(SHM_ERR_HIP, "plan_create: copy of descriptors failed");
+    }
+    if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        shm_plan_destroy(P);
+        return fail(SHM_ERR_HIP, "plan_create: stream creation failed");
+    }
+    if ((rc = plan_build_items(P, stream)) != SHM_OK) {
+        std::string msg = g_err;
+        shm_plan_destroy(P);
+        return fail(rc, "%s", msg.c_str());
+    }
+    *plan_out = P;
+    return SHM_OK;
+}
+
+int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape)
+{
+    clear_error();
+    if (!plan || !shape) return fail(SHM_ERR_INVALID_ARG, "plan_set_shape: null argument");
+    int rc = check_shape(*shape);
+    if (rc) return rc;
+    const bool retile = shape->tile != plan->shape.tile;
+    plan->shape = *shape;
+    if (plan->exec) { hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    return retile ? plan_build_items(plan, plan->cap_stream) : SHM_OK;
+}
+
+int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal, hipStream_t stream)
+{
+    clear_error();
+    if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_launch: null plan");
+    if (plan->n_items == 0) return SHM_OK;
+    if (!lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "plan_launch: null pointer");
+    const size_t al = (plan->dtype == SHM_F16 && plan->layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "plan_launch: misaligned buffer");
+    return launch_query_persistent(lut, plan->dtype, plan->layout, plan->d_objs, plan->d_items, plan->n_items,
+                                   plan->shape, plan->n_cu, dirs, out, normal, stream);
+}
+
+static std::map<std::string, shm_launch_shape> read_cache(const char* path)
+{
+    std::map<std::string, shm_launch_shape> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        // "  "<key>": [block, qpt, tile, grid_per_cu],"
+        size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find('['), d = line.find(']');
+        if (a == std::string::npos || b == std::string::npos || c == std::string::npos || d == std::string::npos) continue;
+        shm_launch_shape s;
+        if (sscanf(line.c_str() + c, "[%d, %d, %d, %d]", &s.block, &s.qpt, &s.tile, &s.grid_per_cu) == 4 && check_shape(s) == SHM_OK)
+            m[line.substr(a + 1, b - a - 1)] = s;
+    }
+    clear_error();
+    return m;
+}
+
+static void write_cache(const char* path, const std::map<std::string, shm_launch_shape>& m)
+{
+    std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        f << "{\n";
+        size_t i = 0;
+        for (auto& kv : m) {
+            f << "  \"" << kv.first << "\": [" << kv.second.block << ", " << kv.second.qpt << ", " << kv.second.tile
+              << ", " << kv.second.grid_per_cu << "]" << (++i < m.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float* out, const char* cache_path,
+                      hipStream_t stream, shm_launch_shape* chosen)
+{
+    clear_error();
+    if (!plan || !lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "plan_autotune: null argument");
+    char key[96];
+    {
+        hipDeviceProp_t prop;
+        hipGetDeviceProperties(&prop, plan->device);
+        snprintf(key, sizeof key, "%s/%d/%016llx", prop.gcnArchName, plan->n_cu, (unsigned long long)plan->signature);
+        for (char* c = key; *c; ++c)
+            if (*c == '"' || *c == '\\') *c = '_';
+    }
+    std::map<std::string, shm_launch_shape> cache;
+    if (cache_path) {
+        cache = read_cache(cache_path);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            int rc = shm_plan_set_shape(plan, &it->second);
+            if (rc) return rc;
+            if (chosen) *chosen = it->second;
+            return SHM_OK;
+        }
+    }
+    std::vector<shm_launch_shape> cands;
+    for (int block : {256, 512})
+        for (int qpt : {1, 2, 4})
+            for (int mult : {1, 4, 16})
+                for (int gpc : {4, 8, 16}) cands.push_back(shm_launch_shape{block, qpt, block * qpt * mult, gpc});
+    hipEvent_t e0, e1;
+    SHM_HIP_CHECK(hipEventCreate(&e0));
+    SHM_HIP_CHECK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    shm_launch_shape best = plan->shape;
+    int rc = SHM_OK;
+    for (const auto& s : cands) {
+        if ((rc = shm_plan_set_shape(plan, &s)) != SHM_OK) break;
+        if ((rc = shm_plan_launch(plan, lut, dirs, out, nullptr, stream)) != SHM_OK) break;  // warm-up
+        hipEventRecord(e0, stream);
+        const int reps = 3;
+        for (int r = 0; r < reps && rc == SHM_OK; ++r) rc = shm_plan_launch(plan, lut, dirs, out, nullptr, stream);
+        hipEventRecord(e1, stream);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SHM_ERR_HIP, "plan_autotune: event sync failed"); break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) { best_ms = ms; best = s; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = shm_plan_set_shape(plan, &best)) != SHM_OK) return rc;
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        cache[key] = best;
+        write_cache(cache_path, cache);
+    }
+    return SHM_OK;
+}
+
+int shm_plan_capture_graph(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal, hipStream_t stream)
+{
+    clear_error();
+    if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_capture_graph: null plan");
+    (void)stream;
+    if (plan->exec) { hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    SHM_HIP_CHECK(hipStreamSynchronize(plan->cap_stream));
+    SHM_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = shm_plan_launch(plan, lut, dirs, out, normal, plan->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
+    if (rc) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(SHM_ERR_HIP, "plan_capture_graph: end capture: %s", hipGetErrorString(e));
+    plan->graph = g;
+    e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        plan->graph = nullptr;
+        plan->exec = nullptr;
+        return fail(SHM_ERR_HIP, "plan_capture_graph: instantiate: %s", hipGetErrorString(e));
+    }
+    return SHM_OK;
+}
+
+int shm_plan_graph_launch(shm_plan* plan, hipStream_t stream)
+{
+    clear_error();
+    if (!plan || !plan->exec) return fail(SHM_ERR_INVALID_ARG, "plan_graph_launch: no captured graph");
+    SHM_HIP_CHECK(hipGraphLaunch(plan->exec, stream));
+    return SHM_OK;
+}
+
+int64_t shm_plan_work_items(const shm_plan* plan) { return plan ? plan->n_items : -1; }
+
+int shm_plan_destroy(shm_plan* plan)
+{
+    if (!plan) return SHM_OK;
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    if (plan->cap_stream) {
+        hipStreamSynchronize(plan->cap_stream);
+        hipStreamDestroy(plan->cap_stream);
+    }
+    if (plan->d_items) hipFree(plan->d_items);
+    if (plan->d_objs) hipFree(plan->d_objs);
+    delete plan;
+    return SHM_OK;
+}
+
+// ---------------------------------------------------------------------------
+size_t shm_backward_workspace(int32_t N, int64_t n_obj, int64_t q_per_obj)
+{
+    if (!valid_N(N) || n_obj < 0 || q_per_obj < 0) return 0;
+    return backward_workspace_bytes(N, n_obj, q_per_obj);
+}
+
+static int check_bwd(int32_t N, int64_t n_obj, int64_t q_per_obj, const void* ws, size_t ws_bytes)
+{
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "backward: N must be 1..%d", SHM_MAX_N);
+    if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "backward: negative size");
+    const int64_t Q = n_obj * q_per_obj;
+    const int64_t cells = n_obj * 6ll * (N + 1) * (N + 1);
+    if (Q >= 0xffffffffll || cells + 1 >= 0xffffffffll)
+        return fail(SHM_ERR_UNSUPPORTED, "backward: more than 2^32 queries or cells");
+    if (!ws || ws_bytes < backward_workspace_bytes(N, n_obj, q_per_obj))
+        return fail(SHM_ERR_WORKSPACE, "backward: workspace of %zu bytes needed (got %zu)",
+                    backward_workspace_bytes(N, n_obj, q_per_obj), ws_bytes);
+    if (!aligned(ws, 256)) return fail(SHM_ERR_INVALID_ARG, "backward: workspace must be 256-byte aligned");
+    return SHM_OK;
+}
+
+int shm_backward_sort(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, size_t ws_bytes,
+                      hipStream_t stream)
+{
+    clear_error();
+    int rc = check_bwd(N, n_obj, q_per_obj, ws, ws_bytes);
+    if (rc) return rc;
+    if (n_obj * q_per_obj > 0 && !dirs) return fail(SHM_ERR_INVALID_ARG, "backward_sort: null dirs");
+    return launch_backward_sort(N, n_obj, dirs, q_per_obj, ws, stream);
+}
+
+int shm_cell_keys(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N) || n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "cell_keys: bad N or size");
+    if (n_obj * 6ll * (N + 1) * (N + 1) >= 0xffffffffll) return fail(SHM_ERR_UNSUPPORTED, "cell_keys: more than 2^32 cells");
+    if (n_obj * q_per_obj == 0) return SHM_OK;
+    if (!dirs || !keys) return fail(SHM_ERR_INVALID_ARG, "cell_keys: null pointer");
+    return launch_cell_keys(N, n_obj, dirs, q_per_obj, keys, stream);
+}
+
+int shm_query_backward(const float* lut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
+                       const float* grad_out, float* grad_lut, float* grad_dirs, void* ws, size_t ws_bytes,
+                       int32_t sort_ready, hipStream_t stream)
+{
+    clear_error();
+    int rc = check_bwd(N, n_obj, q_per_obj, ws, ws_bytes);
+    if (rc) return rc;
+    const int64_t Q = n_obj * q_per_obj;
+    if (!lut && (grad_dirs || grad_lut)) return fail(SHM_ERR_INVALID_ARG, "backward: null lut");
+    if (Q > 0 && (!dirs || !grad_out)) return fail(SHM_ERR_INVALID_ARG, "backward: null dirs or grad_out");
+    if (!aligned(lut, 16) || (grad_lut && !aligned(grad_lut, 16)) || (grad_out && !aligned(grad_out, 16)))
+        return fail(SHM_ERR_INVALID_ARG, "backward: lut, grad_lut and grad_out must be 16-byte aligned");
+    if (!sort_ready && (rc = launch_backward_sort(N, n_obj, dirs, q_per_obj, ws, stream)) != SHM_OK) return rc;
+    return launch_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_dirs, ws, stream);
+}
+
+// ---------------------------------------------------------------------------
+int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax, const float* ray_o,
+                     const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
+                     float* out, float* normal, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "trace: bad dtype or N");
+    if (P < 0) return fail(SHM_ERR_INVALID_ARG, "trace: negative ray count");
+    if (!(rmax > 0.0f) || !std::isfinite(rmax)) return fail(SHM_ERR_INVALID_ARG, "trace: rmax must be positive and finite");
+    if (n_march < 1 || n_bisect < 0 || n_newton < 0 || n_march + n_bisect + n_newton + 1 > 64)
+        return fail(SHM_ERR_INVALID_ARG, "trace: iteration counts must satisfy n_march >= 1 and total <= 64");
+    if (!center) return fail(SHM_ERR_INVALID_ARG, "trace: null center");
+    if (P == 0) return SHM_OK;
+    if (!lut || !ray_o || !ray_d || !t_out || !out) return fail(SHM_ERR_INVALID_ARG, "trace: null pointer");
+    if (!aligned(lut, dtype == SHM_F16 ? 8 : 16) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "trace: misaligned buffer");
+    return launch_trace(lut, dtype, N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal, stream);
+}
+
+int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: bad dtype or N");
+    if (!lut || !rmax_out) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: null pointer");
+    if (!aligned(rmax_out, 4)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: misaligned output");
+    return launch_lut_rmax(lut, dtype, N, rmax_out, stream);
+}
+
+}  // extern "C"

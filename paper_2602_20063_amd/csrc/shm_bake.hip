@@ -1,0 +1,417 @@
+// LUT bake (Sec. 3.3, Alg. 1).
+//
+// Analytic SH mode: the bake of n_obj glyphs is the contraction
+//     LUT[o][texel*4 + ch] = sum_k coeffs[o][k] * B[k][texel*4 + ch]
+// with B the basis table holding, at every padded texel (gutter included),
+// (Y_k, h dY_k/du, h dY_k/dv, h^2 d2Y_k/dudv).  The table is built by
+// k_sh_basis with the chain rule through the chart map
+//     w(u,v) = w~ / |w~|,  w~ = M + (2u-1) S + (2v-1) T
+//     Y_u  = gradP . w_u,   Y_v = gradP . w_v,
+//     Y_uv = w_u^T HessP w_v + gradP . w_uv,
+// where P is the Cartesian polynomial form of Y_lm,
+//     P_l0 = Qn_l^0(z),  P_{l,+-m} = sqrt2 Qn_l^m(z) {Re, Im}(x + i y)^m,
+// Qn_l^m the normalised associated Legendre "polynomial part"
+// (K_lm d^m P_l / dz^m), so gradients and Hessians are exact polynomials.
+// The table is built in FP64 and stored in FP32; the contraction runs on the
+// matrix cores (v_mfma_f32_16x16x4f32, FP32 operands and accumulation).
+//
+// General mode: central differences on samples taken on the padded grid
+// plus a one-texel margin.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "shm_internal.hpp"
+
+namespace shm {
+
+// face frame: M (major axis), S, T (sc, tc axes) of the hardware cube map
+__device__ __forceinline__ void face_frame(int f, float M[3], float S[3], float T[3])
+{
+    for (int k = 0; k < 3; ++k) M[k] = S[k] = T[k] = 0.0f;
+    switch (f) {
+    case 0: M[0] = 1; S[2] = -1; T[1] = -1; break;
+    case 1: M[0] = -1; S[2] = 1; T[1] = -1; break;
+    case 2: M[1] = 1; S[0] = 1; T[2] = 1; break;
+    case 3: M[1] = -1; S[0] = 1; T[2] = -1; break;
+    case 4: M[2] = 1; S[0] = 1; T[1] = -1; break;
+    default: M[2] = -1; S[0] = -1; T[1] = -1; break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Basis table.  One lane per padded texel; writes Bt[k][row], row = texel*4+ch
+// (k-major so the MFMA B operand loads are coalesced), ld = rows_pad.
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, float* __restrict__ Bt)
+{
+    const int P = N + 2;
+    const int ntex = 6 * P * P;
+    const int tex = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tex >= ntex) return;
+    const int face = tex / (P * P);
+    const int rem = tex - face * P * P;
+    const int q = rem / P, p = rem - q * P;
+    float Mf[3], Sf[3], Tf[3];
+    face_frame(face, Mf, Sf, Tf);
+    const Real invN = Real(1) / Real(N);
+    const Real A = Real(2) * ((Real)p - Real(0.5)) * invN - Real(1);
+    const Real B = Real(2) * ((Real)q - Real(0.5)) * invN - Real(1);
+    Real w[3], wu[3], wv[3], wuv[3];
+    Real rho2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        w[k] = (Real)Mf[k] + A * (Real)Sf[k] + B * (Real)Tf[k];
+        rho2 += w[k] * w[k];
+    }
+    const Real rho = sqrt(rho2), irho = Real(1) / rho;
+    for (int k = 0; k < 3; ++k) w[k] *= irho;
+    const Real wS = A * irho, wT = B * irho;  // w . S, w . T
+    for (int k = 0; k < 3; ++k) {
+        wu[k] = Real(2) * irho * ((Real)Sf[k] - wS * w[k]);
+        wv[k] = Real(2) * irho * ((Real)Tf[k] - wT * w[k]);
+        wuv[k] = Real(4) * irho * irho * (Real(3) * wS * wT * w[k] - wT * (Real)Sf[k] - wS * (Real)Tf[k]);
+    }
+    const Real x = w[0], y = w[1], z = w[2];
+    const Real sN = invN, sN2 = invN * invN;
+    const int64_t row = (int64_t)tex * 4;
+    auto emit = [&](int k, Real val, const Real g[3], const Real H[6]) {
+        // H = (xx, xy, xz, yy, yz, zz)
+        const Real Yu = g[0] * wu[0] + g[1] * wu[1] + g[2] * wu[2];
+        const Real Yv = g[0] * wv[0] + g[1] * wv[1] + g[2] * wv[2];
+        const Real Hv0 = H[0] * wv[0] + H[1] * wv[1] + H[2] * wv[2];
+        const Real Hv1 = H[1] * wv[0] + H[3] * wv[1] + H[4] * wv[2];
+        const Real Hv2 = H[2] * wv[0] + H[4] * wv[1] + H[5] * wv[2];
+        const Real Yuv = wu[0] * Hv0 + wu[1] * Hv1 + wu[2] * Hv2 + g[0] * wuv[0] + g[1] * wuv[1] + g[2] * wuv[2];
+        float* dst = Bt + (int64_t)k * rows_pad + row;
+        dst[0] = (float)val;
+        dst[1] = (float)(Yu * sN);
+        dst[2] = (float)(Yv * sN);
+        dst[3] = (float)(Yuv * sN2);
+    };
+    const Real SQ2 = sqrt(Real(2));
+    // complex powers (x + i y)^m = A_m + i B_m, sliding window m-2..m
+    Real Am2 = 0, Bm2 = 0, Am1 = 0, Bm1 = 0, Am = 1, Bm = 0;
+    Real diag = Real(0.28209479177387814347);  // Qn_0^0 = 1/sqrt(4 pi)
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) {
+            Am2 = Am1; Bm2 = Bm1;
+            Am1 = Am; Bm1 = Bm;
+            Am = Am1 * x - Bm1 * y;
+            Bm = Am1 * y + Bm1 * x;
+            diag *= sqrt(Real(2 * m + 1) / Real(2 * m));
+        }
+        // seeds of columns m, m+1, m+2 (diagonal values)
+        const Real d0 = diag;
+        const Real d1 = d0 * sqrt(Real(2 * m + 3) / Real(2 * m + 2));
+        const Real d2 = d1 * sqrt(Real(2 * m + 5) / Real(2 * m + 4));
+        Real c0p1 = 0, c0p2 = 0, c1p1 = 0, c1p2 = 0, c2p1 = 0, c2p2 = 0;
+        for (int l = m; l <= L; ++l) {
+            // column mc at order l: 0 below the diagonal, seed on it, recurrence above
+            auto step = [&](int mc, Real seed, Real& p1, Real& p2) -> Real {
+                Real v;
+                if (l < mc) v = 0;
+                else if (l == mc) v = seed;
+                else {
+                    const Real ll = (Real)l, mm = (Real)mc;
+                    const Real a = sqrt((Real(4) * ll * ll - Real(1)) / (ll * ll - mm * mm));
+                    const Real b = sqrt((((ll - 1) * (ll - 1)) - mm * mm) * (Real(2) * ll + Real(1)) /
+                                        ((Real(2) * ll - Real(3)) * (ll * ll - mm * mm)));
+                    v = a * z * p1 - b * p2;
+                }
+                p2 = p1;
+                p1 = v;
+                return v;
+            };
+            const Real q0 = step(m, d0, c0p1, c0p2);
+            const Real q1 = step(m + 1, d1, c1p1, c1p2);
+            const Real q2 = step(m + 2, d2, c2p1, c2p2);
+            const Real f1 = sqrt(Real((l + m + 1) * (l - m)));
+            const Real f2 = (l - m - 1 >= 0) ? f1 * sqrt(Real((l + m + 2) * (l - m - 1))) : Real(0);
+            const Real dq = f1 * q1, d2q = f2 * q2;  // dQn/dz, d2Qn/dz2
+            if (m == 0) {
+                const Real g[3] = {0, 0, dq};
+                const Real H[6] = {0, 0, 0, 0, 0, d2q};
+                emit(l * l + l, q0, g, H);
+            } else {
+                const Real mm1 = (Real)(m * (m - 1));
+                const Real mr = (Real)m;
+                {   // +m: Re
+                    const Real g[3] = {SQ2 * q0 * mr * Am1, -SQ2 * q0 * mr * Bm1, SQ2 * dq * Am};
+                    const Real H[6] = {SQ2 * q0 * mm1 * Am2, -SQ2 * q0 * mm1 * Bm2, SQ2 * dq * mr * Am1,
+                                       -SQ2 * q0 * mm1 * Am2, -SQ2 * dq * mr * Bm1, SQ2 * d2q * Am};
+                    emit(l * l + l + m, SQ2 * q0 * Am, g, H);
+                }
+                {   // -m: Im
+                    const Real g[3] = {SQ2 * q0 * mr * Bm1, SQ2 * q0 * mr * Am1, SQ2 * dq * Bm};
+                    const Real H[6] = {SQ2 * q0 * mm1 * Bm2, SQ2 * q0 * mm1 * Am2, SQ2 * dq * mr * Bm1,
+                                       -SQ2 * q0 * mm1 * Bm2, SQ2 * dq * mr * Am1, SQ2 * d2q * Bm};
+                    emit(l * l + l - m, SQ2 * q0 * Bm, g, H);
+                }
+            }
+        }
+    }
+    // zero padding rows of K (k = K .. Kp-1)
+    for (int k = (L + 1) * (L + 1); k < Kp; ++k) {
+        float* dst = Bt + (int64_t)k * rows_pad + row;
+        dst[0] = dst[1] = dst[2] = dst[3] = 0.0f;
+    }
+}
+
+// zero the padding columns rows .. rows_pad-1 of every k
+__global__ void k_zero_cols(float* __restrict__ Bt, int Kp, int64_t rows, int64_t rows_pad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = rows_pad - rows;
+    if (i >= w * Kp) return;
+    const int64_t k = i / w, c = i - k * w;
+    Bt[k * rows_pad + rows + c] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Contraction on the matrix cores.  D[o][row] = sum_k C[o][k] Bt[k][row].
+// Block: 256 lanes (4 waves, 2 x 2), tile 64 objects x 128 rows; each wave
+// 32 x 64 = 2 x 4 MFMA 16x16 tiles.  K is staged through LDS in chunks.
+// v_mfma_f32_16x16x4f32 operand layout (lane l): A[m = l%16][k = l/16],
+// B[k = l/16][n = l%16], D[m = 4*(l/16) + i][n = l%16], i = 0..3.
+// ---------------------------------------------------------------------------
+constexpr int GB_M = 64, GB_N = 128, GB_KC = 96;
+constexpr int GB_LDA = GB_M + 1, GB_LDB = GB_N + 16;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <bool F16OUT>
+__global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, int K, int64_t n_obj,
+                                                   const float* __restrict__ Bt, int Kp, int64_t rows,
+                                                   int64_t rows_pad, void* __restrict__ lut)
+{
+    __shared__ float As[GB_KC * GB_LDA];
+    __shared__ float Bs[GB_KC * GB_LDB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;  // wave position in the 2 x 2 grid
+    const int64_t o0 = (int64_t)blockIdx.y * GB_M;
+    const int64_t r0 = (int64_t)blockIdx.x * GB_N;
+    floatx4 acc[2][4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < Kp; kc += GB_KC) {
+        const int kn = (Kp - kc) < GB_KC ? (Kp - kc) : GB_KC;  // multiple of 4
+        // stage A: As[k][m] = C[o0+m][kc+k] (zero outside)
+        for (int i = tid; i < GB_M * kn; i += 256) {
+            const int m = i / kn, k = i - m * kn;
+            const int64_t o = o0 + m;
+            const int kk = kc + k;
+            As[k * GB_LDA + m] = (o < n_obj && kk < K) ? C[o * K + kk] : 0.0f;
+        }
+        // stage B: Bs[k][n] = Bt[kc+k][r0+n]  (rows_pad covers the tile)
+        for (int i = tid; i < GB_N * kn; i += 256) {
+            const int k = i / GB_N, n = i - k * GB_N;
+            Bs[k * GB_LDB + n] = Bt[(int64_t)(kc + k) * rows_pad + r0 + n];
+        }
+        __syncthreads();
+        for (int k = 0; k < kn; k += 4) {
+            const int kr = k + (lane >> 4);
+            float a[2], b[4];
+            for (int i = 0; i < 2; ++i) a[i] = As[kr * GB_LDA + wm * 32 + i * 16 + (lane & 15)];
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kr * GB_LDB + wn * 64 + j * 16 + (lane & 15)];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // epilogue: D[m][n] -> lut[o0 + m][r0 + n]
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = r0 + wn * 64 + j * 16 + (lane & 15);
+            if (col >= rows) continue;
+            for (int e = 0; e < 4; ++e) {
+                const int64_t o = o0 + wm * 32 + i * 16 + 4 * (lane >> 4) + e;
+                if (o >= n_obj) continue;
+                if constexpr (F16OUT)
+                    reinterpret_cast<__half*>(lut)[o * rows + col] = __float2half(acc[i][j][e]);
+                else
+                    reinterpret_cast<float*>(lut)[o * rows + col] = acc[i][j][e];
+            }
+        }
+}
+
+static inline int bake_kp(int L) { return (((L + 1) * (L + 1)) + 3) / 4 * 4; }
+static inline int64_t bake_rows(int N) { return texel_elems(N); }
+static inline int64_t bake_rows_pad(int N) { return (bake_rows(N) + GB_N - 1) / GB_N * GB_N; }
+
+size_t bake_workspace_bytes(int L, int N) { return (size_t)bake_kp(L) * (size_t)bake_rows_pad(N) * sizeof(float); }
+
+int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dtype, void* lut, void* ws,
+                   hipStream_t stream)
+{
+    const int K = (L + 1) * (L + 1), Kp = bake_kp(L);
+    const int64_t rows = bake_rows(N), rows_pad = bake_rows_pad(N);
+    float* Bt = reinterpret_cast<float*>(ws);
+    const int ntex = 6 * (N + 2) * (N + 2);
+    // The table is evaluated in FP64 at every order: it is a vanishing part of
+    // the bake's arithmetic, and in FP32 the tangential chain rule loses
+    // ~1e-4 of the derivative channels to cancellation against the large
+    // radial part of the Cartesian polynomial's gradient.
+    hipLaunchKernelGGL(k_sh_basis<double>, dim3((ntex + 127) / 128), dim3(128), 0, stream, L, N, Kp, rows_pad, Bt);
+    SHM_LAUNCH_CHECK();
+    if (rows_pad > rows) {
+        const int64_t n = (rows_pad - rows) * Kp;
+        hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, Bt, Kp, rows, rows_pad);
+        SHM_LAUNCH_CHECK();
+    }
+    const int64_t gy = (n_obj + GB_M - 1) / GB_M;
+    const int64_t gx = rows_pad / GB_N;
+    if (gy > 65535 * 16 || gx > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "bake: too many objects for one launch");
+    // grid.y is limited; split objects into launches of <= 65535 tiles
+    for (int64_t y0 = 0; y0 < gy; y0 += 65535) {
+        const int64_t ny = (gy - y0) < 65535 ? (gy - y0) : 65535;
+        const int64_t ob = y0 * GB_M;
+        const int64_t nob = (n_obj - ob) < ny * GB_M ? (n_obj - ob) : ny * GB_M;
+        const dim3 grid((unsigned)gx, (unsigned)ny);
+        if (out_dtype == SHM_F16)
+            hipLaunchKernelGGL(k_bake_gemm<true>, grid, dim3(256), 0, stream, coeffs + ob * K, K, nob, Bt, Kp, rows,
+                               rows_pad, (void*)(reinterpret_cast<__half*>(lut) + ob * rows));
+        else
+            hipLaunchKernelGGL(k_bake_gemm<false>, grid, dim3(256), 0, stream, coeffs + ob * K, K, nob, Bt, Kp, rows,
+                               rows_pad, (void*)(reinterpret_cast<float*>(lut) + ob * rows));
+        SHM_LAUNCH_CHECK();
+    }
+    return SHM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// General mode: sample directions and central differences.
+// ---------------------------------------------------------------------------
+__global__ void k_margin_dirs(int N, float* __restrict__ dirs)
+{
+    const int P = N + 4;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * P * P) return;
+    const int face = i / (P * P), rem = i - face * P * P;
+    const int q = rem / P, p = rem - q * P;
+    float M[3], S[3], T[3];
+    face_frame(face, M, S, T);
+    const float A = 2.0f * ((float)p - 1.5f) / (float)N - 1.0f;
+    const float B = 2.0f * ((float)q - 1.5f) / (float)N - 1.0f;
+    float w[3], n2 = 0.f;
+    for (int k = 0; k < 3; ++k) { w[k] = M[k] + A * S[k] + B * T[k]; n2 += w[k] * w[k]; }
+    const float in = 1.0f / sqrtf(n2);
+    for (int k = 0; k < 3; ++k) dirs[(int64_t)i * 3 + k] = w[k] * in;
+}
+
+template <bool F16OUT>
+__global__ void k_bake_fd(const float* __restrict__ samples, int N, int64_t n_obj, void* __restrict__ lut)
+{
+    const int P = N + 2, Pm = N + 4;
+    const int64_t per = 6ll * P * P;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= per * n_obj) return;
+    const int64_t obj = i / per;
+    const int rem = (int)(i - obj * per);
+    const int face = rem / (P * P), r2 = rem - face * P * P;
+    const int q = r2 / P, p = r2 - q * P;
+    const float* S = samples + obj * 6ll * Pm * Pm + (int64_t)face * Pm * Pm;
+    const int pp = p + 1, qq = q + 1;
+    auto at = [&](int a, int b) { return S[(int64_t)b * Pm + a]; };
+    const float c = at(pp, qq);
+    const float du = 0.5f * (at(pp + 1, qq) - at(pp - 1, qq));
+    const float dv = 0.5f * (at(pp, qq + 1) - at(pp, qq - 1));
+    const float duv = 0.25f * ((at(pp + 1, qq + 1) - at(pp + 1, qq - 1)) - (at(pp - 1, qq + 1) - at(pp - 1, qq - 1)));
+    if constexpr (F16OUT) {
+        __half* o = reinterpret_cast<__half*>(lut) + i * 4;
+        o[0] = __float2half(c); o[1] = __float2half(du); o[2] = __float2half(dv); o[3] = __float2half(duv);
+    } else {
+        reinterpret_cast<float4*>(lut)[i] = make_float4(c, du, dv, duv);
+    }
+}
+
+int launch_margin_dirs(int N, float* dirs, hipStream_t stream)
+{
+    const int n = 6 * (N + 4) * (N + 4);
+    hipLaunchKernelGGL(k_margin_dirs, dim3((n + 255) / 256), dim3(256), 0, stream, N, dirs);
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, void* lut, hipStream_t stream)
+{
+    const int64_t n = 6ll * (N + 2) * (N + 2) * n_obj;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "bake_fd: too large");
+    if (out_dtype == SHM_F16)
+        hipLaunchKernelGGL(k_bake_fd<true>, dim3((unsigned)blocks), dim3(256), 0, stream, samples, N, n_obj, lut);
+    else
+        hipLaunchKernelGGL(k_bake_fd<false>, dim3((unsigned)blocks), dim3(256), 0, stream, samples, N, n_obj, lut);
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Bernstein bound of the reconstruction (largest Bezier control point of any
+// cell).  1-D Hermite (p0, m0, p1, m1) -> Bezier (p0, p0+m0/3, p1-m1/3, p1),
+// tensor product over the cell.  Max-reduction through the order-preserving
+// integer image of non-negative floats is exact; a negative bound clamps to
+// 0 (R >= 0 for a star-shaped surface).
+// ---------------------------------------------------------------------------
+template <bool F16>
+__global__ void k_lut_rmax(const void* __restrict__ lut, int N, unsigned int* __restrict__ out_bits)
+{
+    const int C = N + 1, P = N + 2;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float best = 0.0f;
+    if (i < 6 * C * C) {
+        const int face = i / (C * C), rem = i - face * C * C;
+        const int j0 = rem / C, i0 = rem - j0 * C;
+        float G[4][4];  // [s-index over (p0, m0, p1, m1)][t-index likewise]
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                const int64_t t = ((int64_t)(face * P + j0 + dj) * P + i0 + di) * 4;
+                float c[4];
+                if constexpr (F16) {
+                    const __half* h = reinterpret_cast<const __half*>(lut) + t;
+                    for (int k = 0; k < 4; ++k) c[k] = __half2float(h[k]);
+                } else {
+                    const float* f = reinterpret_cast<const float*>(lut) + t;
+                    for (int k = 0; k < 4; ++k) c[k] = f[k];
+                }
+                G[2 * di][2 * dj] = c[0];
+                G[2 * di + 1][2 * dj] = c[1];
+                G[2 * di][2 * dj + 1] = c[2];
+                G[2 * di + 1][2 * dj + 1] = c[3];
+            }
+        float H[4][4];
+        for (int b = 0; b < 4; ++b) {
+            H[0][b] = G[0][b];
+            H[1][b] = G[0][b] + G[1][b] / 3.0f;
+            H[2][b] = G[2][b] - G[3][b] / 3.0f;
+            H[3][b] = G[2][b];
+        }
+        for (int a = 0; a < 4; ++a) {
+            const float z0 = H[a][0], z1 = H[a][0] + H[a][1] / 3.0f, z2 = H[a][2] - H[a][3] / 3.0f, z3 = H[a][2];
+            best = fmaxf(best, fmaxf(fmaxf(z0, z1), fmaxf(z2, z3)));
+        }
+    }
+    // wave reduction, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) best = fmaxf(best, __shfl_xor(best, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out_bits, __float_as_uint(best));
+}
+
+__global__ void k_bits_to_float(const unsigned int* bits, float* out) { *out = __uint_as_float(*bits); }
+
+__global__ void k_fill_u32(unsigned int* p, unsigned int v) { *p = v; }
+
+int launch_lut_rmax(const void* lut, int dtype, int N, float* rmax_out, hipStream_t stream)
+{
+    unsigned int* bits = reinterpret_cast<unsigned int*>(rmax_out);  // reuse the output word
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, bits, 0u);
+    const int n = 6 * (N + 1) * (N + 1);
+    if (dtype == SHM_F16)
+        hipLaunchKernelGGL(k_lut_rmax<true>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, bits);
+    else
+        hipLaunchKernelGGL(k_lut_rmax<false>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, bits);
+    hipLaunchKernelGGL(k_bits_to_float, dim3(1), dim3(1), 0, stream, bits, rmax_out);
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+}  // namespace shm

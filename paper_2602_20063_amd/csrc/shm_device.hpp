@@ -1,0 +1,321 @@
+// Device-side building blocks of the Spherical Hermite Map query (gfx950).
+//
+//   locate()      direction -> cube-map face, cell and local (s, t)   Sec. 3.2
+//   load_*()      the 2x2 footprint (16 scalars) from a TEXEL or CELL LUT
+//   hermite()     value and chart derivatives, Eqs. (3)-(5)
+//   transport()   chart derivatives -> spherical gradient, Sec. 3.4
+//
+// The gradient uses the closed form of the metric-tensor solve of
+// Eqs. (6)-(9): with a = sc/ma, b = tc/ma and rho = sqrt(1 + a^2 + b^2),
+//   grad R = (rho / 2) [ r_u (S - a M) + r_v (T - b M) ],
+// which is what Cramer's rule returns for e1 = dw/du, e2 = dw/dv on the
+// face (det G = 16 / rho^6 >= 16/27 there, so the clamp never acts).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shm {
+
+struct Loc {
+    int face;     // 0..5 = +X, -X, +Y, -Y, +Z, -Z; -1 = invalid direction
+    int i0, j0;   // cell: corners are padded texels (i0+{0,1}, j0+{0,1})
+    float s, t;   // local coordinates in the cell
+    float a, b;   // sc/ma, tc/ma in [-1, 1]
+};
+
+// Face selection on the raw components, ties X > Y > Z, sign >= 0 -> +face.
+// The integer decision follows exactly: a = sc/ma, u = (a+1)*0.5,
+// f = u*N + 0.5, i0 = min(floor(f), N), each step rounded to nearest (no
+// contraction).  The local coordinate s is then formed to ~1 ulp of s from
+// a double-float a (residual of the division by fma) instead of f - i0,
+// whose error grows like ulp(N).
+__device__ __forceinline__ Loc locate(float x, float y, float z, int N)
+{
+#pragma clang fp contract(off)
+    Loc L;
+    const float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
+    const bool isx = (ax >= ay) && (ax >= az);
+    const bool isy = !isx && (ay >= az);
+    float sc, tc, ma;
+    int face;
+    if (isx) {
+        const bool pos = x >= 0.0f;
+        face = pos ? 0 : 1;
+        ma = ax;
+        sc = pos ? -z : z;
+        tc = -y;
+    } else if (isy) {
+        const bool pos = y >= 0.0f;
+        face = pos ? 2 : 3;
+        ma = ay;
+        sc = x;
+        tc = pos ? z : -z;
+    } else {
+        const bool pos = z >= 0.0f;
+        face = pos ? 4 : 5;
+        ma = az;
+        sc = pos ? x : -x;
+        tc = -y;
+    }
+    const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && (ma > 0.0f);
+    const float a = sc / ma;
+    const float b = tc / ma;
+    const float u = (a + 1.0f) * 0.5f;
+    const float v = (b + 1.0f) * 0.5f;
+    const float Nf = (float)N;
+    float fu = u * Nf;
+    float fv = v * Nf;
+    fu = fu + 0.5f;
+    fv = fv + 0.5f;
+    int i0 = (int)floorf(fu);
+    int j0 = (int)floorf(fv);
+    i0 = i0 > N ? N : (i0 < 0 ? 0 : i0);
+    j0 = j0 > N ? N : (j0 < 0 ? 0 : j0);
+    // s = (a + 1) N/2 + 1/2 - i0 with a = a_hi + a_lo (exact residual)
+    const float a_lo = __builtin_fmaf(-a, ma, sc) / ma;
+    const float b_lo = __builtin_fmaf(-b, ma, tc) / ma;
+    const float halfN = 0.5f * Nf;
+    const float cu = (halfN + 0.5f) - (float)i0;  // exact: half-integers below 2^23
+    const float cv = (halfN + 0.5f) - (float)j0;
+    L.s = __builtin_fmaf(a, halfN, cu) + a_lo * halfN;
+    L.t = __builtin_fmaf(b, halfN, cv) + b_lo * halfN;
+    L.a = a;
+    L.b = b;
+    L.i0 = i0;
+    L.j0 = j0;
+    L.face = ok ? face : -1;
+    return L;
+}
+
+// 16 footprint scalars: c[corner][ch], corner 0 = (i0,j0), 1 = (i0+1,j0),
+// 2 = (i0,j0+1), 3 = (i0+1,j0+1); ch = (r, r_u h, r_v h, r_uv h^2).
+struct Foot {
+    float4 c[4];
+};
+
+__device__ __forceinline__ float4 h4_to_f4(uint2 h)
+{
+    const __half2 lo = *reinterpret_cast<const __half2*>(&h.x);
+    const __half2 hi = *reinterpret_cast<const __half2*>(&h.y);
+    const float2 a = __half22float2(lo), b = __half22float2(hi);
+    return make_float4(a.x, a.y, b.x, b.y);
+}
+
+// TEXEL layout, FP32: two rows of two texels (2 x 32 B).
+__device__ __forceinline__ Foot load_texel_f32(const float* __restrict__ lut, int N, const Loc& L)
+{
+    const int P = N + 2;
+    const int64_t row0 = ((int64_t)(L.face * P + L.j0) * P + L.i0) * 4;
+    const float4* p0 = reinterpret_cast<const float4*>(lut + row0);
+    const float4* p1 = reinterpret_cast<const float4*>(lut + row0 + (int64_t)P * 4);
+    Foot F;
+    F.c[0] = *(p0);
+    F.c[1] = *(p0 + 1);
+    F.c[2] = *(p1);
+    F.c[3] = *(p1 + 1);
+    return F;
+}
+
+__device__ __forceinline__ Foot load_texel_f16(const __half* __restrict__ lut, int N, const Loc& L)
+{
+    const int P = N + 2;
+    const int64_t row0 = ((int64_t)(L.face * P + L.j0) * P + L.i0) * 4;
+    const uint2* p0 = reinterpret_cast<const uint2*>(lut + row0);
+    const uint2* p1 = reinterpret_cast<const uint2*>(lut + row0 + (int64_t)P * 4);
+    Foot F;
+    F.c[0] = h4_to_f4(*(p0));
+    F.c[1] = h4_to_f4(*(p0 + 1));
+    F.c[2] = h4_to_f4(*(p1));
+    F.c[3] = h4_to_f4(*(p1 + 1));
+    return F;
+}
+
+// CELL layout: one contiguous, aligned block per cell.
+__device__ __forceinline__ Foot load_cell_f32(const float* __restrict__ lut, int N, const Loc& L)
+{
+    const int C = N + 1;
+    const int64_t cell = (int64_t)(L.face * C + L.j0) * C + L.i0;
+    const float4* p = reinterpret_cast<const float4*>(lut + cell * 16);
+    Foot F;
+    F.c[0] = *(p);
+    F.c[1] = *(p + 1);
+    F.c[2] = *(p + 2);
+    F.c[3] = *(p + 3);
+    return F;
+}
+
+__device__ __forceinline__ Foot load_cell_f16(const __half* __restrict__ lut, int N, const Loc& L)
+{
+    const int C = N + 1;
+    const int64_t cell = (int64_t)(L.face * C + L.j0) * C + L.i0;
+    const uint4* p = reinterpret_cast<const uint4*>(lut + cell * 16);
+    const uint4 q0 = *(p);
+    const uint4 q1 = *(p + 1);
+    Foot F;
+    F.c[0] = h4_to_f4(make_uint2(q0.x, q0.y));
+    F.c[1] = h4_to_f4(make_uint2(q0.z, q0.w));
+    F.c[2] = h4_to_f4(make_uint2(q1.x, q1.y));
+    F.c[3] = h4_to_f4(make_uint2(q1.z, q1.w));
+    return F;
+}
+
+template <bool FP16, bool CELL>
+__device__ __forceinline__ Foot load_foot(const void* __restrict__ lut, int N, const Loc& L)
+{
+    if constexpr (CELL) {
+        if constexpr (FP16) return load_cell_f16(reinterpret_cast<const __half*>(lut), N, L);
+        else return load_cell_f32(reinterpret_cast<const float*>(lut), N, L);
+    } else {
+        if constexpr (FP16) return load_texel_f16(reinterpret_cast<const __half*>(lut), N, L);
+        else return load_texel_f32(reinterpret_cast<const float*>(lut), N, L);
+    }
+}
+
+// Cubic Hermite basis on [0,1], Eq. (3): only H1, H0d, H1d are needed
+// (H0 = 1 - H1) plus first derivatives (H0' = -H1').
+struct Basis1 {
+    float h1, h0d, h1d;      // H1, H0^d, H1^d
+    float d1, d0d, d1d;      // H1', (H0^d)', (H1^d)'
+};
+
+__device__ __forceinline__ Basis1 basis1(float s)
+{
+    Basis1 B;
+    const float s2 = s * s;
+    B.h1 = s2 * (3.0f - 2.0f * s);          // -2s^3 + 3s^2
+    B.h0d = s * (s - 1.0f) * (s - 1.0f);    // s^3 - 2s^2 + s
+    B.h1d = s2 * (s - 1.0f);                // s^3 - s^2
+    B.d1 = 6.0f * s * (1.0f - s);           // -6s^2 + 6s
+    B.d0d = (3.0f * s - 1.0f) * (s - 1.0f); // 3s^2 - 4s + 1
+    B.d1d = s * (3.0f * s - 2.0f);          // 3s^2 - 2s
+    return B;
+}
+
+struct Patch {
+    float r, rs, rt;  // value and derivatives in the local (s, t); r_u = N rs
+};
+
+// Eq. (4) and its s, t derivatives, evaluated in difference form: every
+// corner difference (exact in FP32 for nearby values) is taken before it is
+// weighted, so chart derivatives keep full relative accuracy at large N.
+__device__ __forceinline__ Patch hermite(const Foot& F, float s, float t)
+{
+    const Basis1 S = basis1(s), T = basis1(t);
+    const float4 c00 = F.c[0], c10 = F.c[1], c01 = F.c[2], c11 = F.c[3];
+    // differences along s (rows j = 0, 1) and along t (columns i = 0, 1)
+    const float dsR0 = c10.x - c00.x, dsR1 = c11.x - c01.x;
+    const float dtR0 = c01.x - c00.x;
+    const float dtU0 = c01.y - c00.y, dtU1 = c11.y - c10.y;
+    const float dsV0 = c10.z - c00.z, dsV1 = c11.z - c01.z;
+    // f_j(s): Hermite in s of (r, r_u h) on row j; g_j(s): of (r_v h, r_uv h^2)
+    const float f0 = c00.x + S.h1 * dsR0 + S.h0d * c00.y + S.h1d * c10.y;
+    const float df = dtR0 + S.h1 * (dsR1 - dsR0) + S.h0d * dtU0 + S.h1d * dtU1;  // f1 - f0
+    const float g0 = c00.z + S.h1 * dsV0 + S.h0d * c00.w + S.h1d * c10.w;
+    const float g1 = c01.z + S.h1 * dsV1 + S.h0d * c01.w + S.h1d * c11.w;
+    const float f0s = S.d1 * dsR0 + S.d0d * c00.y + S.d1d * c10.y;
+    const float f1s = S.d1 * dsR1 + S.d0d * c01.y + S.d1d * c11.y;
+    const float g0s = S.d1 * dsV0 + S.d0d * c00.w + S.d1d * c10.w;
+    const float g1s = S.d1 * dsV1 + S.d0d * c01.w + S.d1d * c11.w;
+    Patch P;
+    P.r = f0 + T.h1 * df + T.h0d * g0 + T.h1d * g1;
+    P.rs = f0s + T.h1 * (f1s - f0s) + T.h0d * g0s + T.h1d * g1s;
+    P.rt = T.d1 * df + T.d0d * g0 + T.d1d * g1;
+    return P;
+}
+
+struct Patch2 {
+    float r, rs, rt, rss, rst, rtt;  // value, first and second local derivatives
+};
+
+// Eq. (4) with first and second derivatives in (s, t) (difference form as in
+// hermite()); the second derivatives feed the direction gradient of the
+// backward.  H1'' = 6 - 12s, (H0^d)'' = 6s - 4, (H1^d)'' = 6s - 2.
+__device__ __forceinline__ Patch2 hermite2(const Foot& F, float s, float t)
+{
+    const Basis1 S = basis1(s), T = basis1(t);
+    const float e1s = 6.0f - 12.0f * s, e0ds = 6.0f * s - 4.0f, e1ds = 6.0f * s - 2.0f;
+    const float e1t = 6.0f - 12.0f * t, e0dt = 6.0f * t - 4.0f, e1dt = 6.0f * t - 2.0f;
+    const float4 c00 = F.c[0], c10 = F.c[1], c01 = F.c[2], c11 = F.c[3];
+    const float dsR0 = c10.x - c00.x, dsR1 = c11.x - c01.x;
+    const float dtR0 = c01.x - c00.x;
+    const float dtU0 = c01.y - c00.y, dtU1 = c11.y - c10.y;
+    const float dsV0 = c10.z - c00.z, dsV1 = c11.z - c01.z;
+    const float f0 = c00.x + S.h1 * dsR0 + S.h0d * c00.y + S.h1d * c10.y;
+    const float df = dtR0 + S.h1 * (dsR1 - dsR0) + S.h0d * dtU0 + S.h1d * dtU1;
+    const float g0 = c00.z + S.h1 * dsV0 + S.h0d * c00.w + S.h1d * c10.w;
+    const float g1 = c01.z + S.h1 * dsV1 + S.h0d * c01.w + S.h1d * c11.w;
+    const float f0s = S.d1 * dsR0 + S.d0d * c00.y + S.d1d * c10.y;
+    const float f1s = S.d1 * dsR1 + S.d0d * c01.y + S.d1d * c11.y;
+    const float g0s = S.d1 * dsV0 + S.d0d * c00.w + S.d1d * c10.w;
+    const float g1s = S.d1 * dsV1 + S.d0d * c01.w + S.d1d * c11.w;
+    const float f0ss = e1s * dsR0 + e0ds * c00.y + e1ds * c10.y;
+    const float f1ss = e1s * dsR1 + e0ds * c01.y + e1ds * c11.y;
+    const float g0ss = e1s * dsV0 + e0ds * c00.w + e1ds * c10.w;
+    const float g1ss = e1s * dsV1 + e0ds * c01.w + e1ds * c11.w;
+    Patch2 P;
+    P.r = f0 + T.h1 * df + T.h0d * g0 + T.h1d * g1;
+    P.rs = f0s + T.h1 * (f1s - f0s) + T.h0d * g0s + T.h1d * g1s;
+    P.rt = T.d1 * df + T.d0d * g0 + T.d1d * g1;
+    P.rss = f0ss + T.h1 * (f1ss - f0ss) + T.h0d * g0ss + T.h1d * g1ss;
+    P.rst = T.d1 * (f1s - f0s) + T.d0d * g0s + T.d1d * g1s;
+    P.rtt = e1t * df + e0dt * g0 + e1dt * g1;
+    return P;
+}
+
+// Per-face frame as signed axis vectors: M, S, T of the hardware cube map.
+__device__ __forceinline__ void frame_of(int face, float3& M, float3& S, float3& T)
+{
+    switch (face) {
+    case 0: M = make_float3(1, 0, 0); S = make_float3(0, 0, -1); T = make_float3(0, -1, 0); break;
+    case 1: M = make_float3(-1, 0, 0); S = make_float3(0, 0, 1); T = make_float3(0, -1, 0); break;
+    case 2: M = make_float3(0, 1, 0); S = make_float3(1, 0, 0); T = make_float3(0, 0, 1); break;
+    case 3: M = make_float3(0, -1, 0); S = make_float3(1, 0, 0); T = make_float3(0, 0, -1); break;
+    case 4: M = make_float3(0, 0, 1); S = make_float3(1, 0, 0); T = make_float3(0, -1, 0); break;
+    default: M = make_float3(0, 0, -1); S = make_float3(-1, 0, 0); T = make_float3(0, -1, 0); break;
+    }
+}
+
+// Ambient spherical gradient from chart derivatives (r_u, r_v), closed form
+// of the Sec. 3.4 metric solve.  Per face: M, S, T are signed axis vectors.
+__device__ __forceinline__ float3 transport(int face, float a, float b, float ru, float rv)
+{
+    const float rho = sqrtf(1.0f + a * a + b * b);
+    const float k = 0.5f * rho;
+    const float gu = k * ru, gv = k * rv;
+    const float gm = -(a * gu + b * gv);  // component along M
+    // g = gu S + gv T + gm M
+    switch (face) {
+    case 0: return make_float3(gm, -gv, -gu);   // M=+x S=-z T=-y
+    case 1: return make_float3(-gm, -gv, gu);   // M=-x S=+z T=-y
+    case 2: return make_float3(gu, gm, gv);     // M=+y S=+x T=+z
+    case 3: return make_float3(gu, -gm, -gv);   // M=-y S=+x T=-z
+    case 4: return make_float3(gu, -gv, gm);    // M=+z S=+x T=-y
+    default: return make_float3(-gu, -gv, -gm); // M=-z S=-x T=-y
+    }
+}
+
+// Eq. (10)
+__device__ __forceinline__ float3 normal_of(float R, float x, float y, float z, float3 g)
+{
+    const float il = rsqrtf(x * x + y * y + z * z);
+    const float mx = R * x * il - g.x, my = R * y * il - g.y, mz = R * z * il - g.z;
+    const float in = rsqrtf(mx * mx + my * my + mz * mz);
+    return make_float3(mx * in, my * in, mz * in);
+}
+
+// Full query: returns (R, gx, gy, gz); NaN for an invalid direction.
+template <bool FP16, bool CELL>
+__device__ __forceinline__ float4 query_one(const void* __restrict__ lut, int N, float x, float y, float z)
+{
+    const Loc L = locate(x, y, z, N);
+    if (L.face < 0) return make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+    const Foot F = load_foot<FP16, CELL>(lut, N, L);
+    const Patch P = hermite(F, L.s, L.t);
+    const float Nf = (float)N;
+    const float3 g = transport(L.face, L.a, L.b, Nf * P.rs, Nf * P.rt);
+    return make_float4(P.r, g.x, g.y, g.z);
+}
+
+}  // namespace shm

@@ -1,0 +1,56 @@
+// Host-side internals shared by the translation units of libshm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/shm.h"
+
+namespace shm {
+
+// thread-local last-error message; returns `code` for convenient chaining
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define SHM_HIP_CHECK(expr)                                                                   \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return ::shm::fail(SHM_ERR_HIP, "%s: %s (%s:%d)", #expr,        \
+                                                 hipGetErrorString(e_), __FILE__, __LINE__);  \
+    } while (0)
+
+#define SHM_LAUNCH_CHECK()                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = hipGetLastError();                                                    \
+        if (e_ != hipSuccess) return ::shm::fail(SHM_ERR_HIP, "kernel launch: %s (%s:%d)",    \
+                                                 hipGetErrorString(e_), __FILE__, __LINE__);  \
+    } while (0)
+
+inline int64_t texel_elems(int N) { return 6ll * (N + 2) * (N + 2) * 4; }
+inline int64_t cell_elems(int N) { return 6ll * (N + 1) * (N + 1) * 16; }
+inline size_t dtype_bytes(int dt) { return dt == SHM_F16 ? 2 : 4; }
+
+// number of compute units of the current device (cached per device)
+int device_cu_count();
+
+// work item of the persistent query kernel: queries [q0, q0 + n) of object obj
+struct WorkItem {
+    int64_t q0;
+    int32_t obj;
+    int32_t n;
+};
+
+// device copy of a host shm_object (same layout)
+static_assert(sizeof(shm_object) == 32, "shm_object layout");
+
+// launchers (validated arguments)
+int launch_query_uniform(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
+                         int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
+int launch_query_persistent(const void* lut, int dtype, int layout, const shm_object* objs_dev,
+                            const WorkItem* items_dev, int64_t n_items, const shm_launch_shape& shape, int n_cu,
+                            const float* dirs, float* out, float* normal, hipStream_t stream);
+int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* cells, hipStream_t stream);
+
+}  // namespace shm

@@ -1,0 +1,206 @@
+// Query kernels: value + spherical gradient from a Spherical Hermite Map
+// (Sec. 3.2-3.4).  One lane answers one query: locate -> 16-scalar gather ->
+// Hermite patch -> closed-form metric transport -> coalesced float4 store.
+//
+// The query is bound by HBM traffic: every query's footprint is one random
+// gather of 64 B (FP32) or 32 B (FP16), and HBM serves random requests in
+// 128 B lines, so the CELL layout (footprint contiguous and aligned, one
+// line per query) is what the throughput path uses; the TEXEL layout is
+// served by the same kernel (two 32 B row segments per query).
+#include "shm_device.hpp"
+#include "shm_internal.hpp"
+
+namespace shm {
+
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+// consecutive logical tiles share an XCD (and its L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, local = b >> 3;
+    const int start = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    return start + local;
+}
+
+template <bool FP16, bool CELL, bool NRM>
+__global__ __launch_bounds__(256) void k_query_uniform(const void* __restrict__ lut, int N, int64_t lut_elems,
+                                                       int64_t q_per_obj, int tiles_per_obj,
+                                                       const float* __restrict__ dirs, float* __restrict__ out,
+                                                       float* __restrict__ nrm)
+{
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int obj = b / tiles_per_obj;
+    const int tile = b - obj * tiles_per_obj;
+    const int64_t ql = (int64_t)tile * 256 + threadIdx.x;
+    if (ql >= q_per_obj) return;
+    const int64_t q = (int64_t)obj * q_per_obj + ql;
+    const char* base = reinterpret_cast<const char*>(lut) + (size_t)obj * (size_t)lut_elems * (FP16 ? 2 : 4);
+    const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+    const float4 r = query_one<FP16, CELL>(base, N, x, y, z);
+    reinterpret_cast<float4*>(out)[q] = r;
+    if constexpr (NRM) {
+        const float3 n = normal_of(r.x, x, y, z, make_float3(r.y, r.z, r.w));
+        nrm[3 * q] = n.x;
+        nrm[3 * q + 1] = n.y;
+        nrm[3 * q + 2] = n.z;
+    }
+}
+
+template <bool FP16, bool CELL, bool NRM>
+static void launch_uniform_t(dim3 grid, hipStream_t st, const void* lut, int N, int64_t le, int64_t qpo, int tpo,
+                             const float* dirs, float* out, float* nrm)
+{
+    hipLaunchKernelGGL((k_query_uniform<FP16, CELL, NRM>), grid, dim3(256), 0, st, lut, N, le, qpo, tpo, dirs, out,
+                       nrm);
+}
+
+int launch_query_uniform(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
+                         int64_t q_per_obj, float* out, float* normal, hipStream_t stream)
+{
+    if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
+    const int64_t tiles = (q_per_obj + 255) / 256;
+    if (tiles > 0x7fffffff || tiles * n_obj > 0x7fffffff)
+        return fail(SHM_ERR_UNSUPPORTED, "query: %lld objects x %lld tiles exceeds one launch", (long long)n_obj,
+                    (long long)tiles);
+    const dim3 grid((unsigned)(tiles * n_obj));
+    const int64_t le = layout == SHM_LAYOUT_CELL ? cell_elems(N) : texel_elems(N);
+    const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL, nrm = normal != nullptr;
+    const int tpo = (int)tiles;
+#define SHM_Q(a, b, c) launch_uniform_t<a, b, c>(grid, stream, lut, N, le, q_per_obj, tpo, dirs, out, normal)
+    if (f16) {
+        if (cell) { if (nrm) SHM_Q(true, true, true); else SHM_Q(true, true, false); }
+        else { if (nrm) SHM_Q(true, false, true); else SHM_Q(true, false, false); }
+    } else {
+        if (cell) { if (nrm) SHM_Q(false, true, true); else SHM_Q(false, true, false); }
+        else { if (nrm) SHM_Q(false, false, true); else SHM_Q(false, false, false); }
+    }
+#undef SHM_Q
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernel.  The work list holds (object, query range)
+// items of at most `tile` queries, ordered by object.  Workgroup g takes
+// items g, g + G, g + 2G, ... (static striding: deterministic, no counters,
+// nothing to reset, so a captured graph replays as is).  Items processed at
+// the same time are neighbours in the list, so an object's LUT is read by
+// many workgroups at once and stays resident in L2 / MALL.
+// ---------------------------------------------------------------------------
+template <bool FP16, bool CELL, bool NRM, int QPT>
+__global__ void k_query_persistent(const void* __restrict__ lut, const shm_object* __restrict__ objs,
+                                   const WorkItem* __restrict__ items, int64_t n_items,
+                                   const float* __restrict__ dirs, float* __restrict__ out, float* __restrict__ nrm)
+{
+    const int G = (int)gridDim.x;
+    const int g = xcd_remap((int)blockIdx.x, G);
+    const int B = (int)blockDim.x;
+    for (int64_t w = g; w < n_items; w += G) {
+        const WorkItem it = items[w];
+        const shm_object o = objs[it.obj];
+        const int N = o.N;
+        const char* base = reinterpret_cast<const char*>(lut) + (size_t)o.lut_offset * (FP16 ? 2 : 4);
+        for (int k0 = 0; k0 < it.n; k0 += B * QPT) {
+            float x[QPT], y[QPT], z[QPT];
+            int64_t qq[QPT];
+            bool act[QPT];
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                const int k = k0 + j * B + (int)threadIdx.x;
+                act[j] = k < it.n;
+                qq[j] = it.q0 + k;
+                if (act[j]) {
+                    x[j] = dirs[3 * qq[j]];
+                    y[j] = dirs[3 * qq[j] + 1];
+                    z[j] = dirs[3 * qq[j] + 2];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                if (!act[j]) continue;
+                const float4 r = query_one<FP16, CELL>(base, N, x[j], y[j], z[j]);
+                reinterpret_cast<float4*>(out)[qq[j]] = r;
+                if constexpr (NRM) {
+                    const float3 n = normal_of(r.x, x[j], y[j], z[j], make_float3(r.y, r.z, r.w));
+                    nrm[3 * qq[j]] = n.x;
+                    nrm[3 * qq[j] + 1] = n.y;
+                    nrm[3 * qq[j] + 2] = n.z;
+                }
+            }
+        }
+    }
+}
+
+template <bool FP16, bool CELL, bool NRM>
+static void launch_persistent_t(int qpt, dim3 grid, dim3 block, hipStream_t st, const void* lut,
+                                const shm_object* objs, const WorkItem* items, int64_t n_items, const float* dirs,
+                                float* out, float* nrm)
+{
+    switch (qpt) {
+    case 1: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 1>), grid, block, 0, st, lut, objs, items, n_items, dirs, out, nrm); break;
+    case 2: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 2>), grid, block, 0, st, lut, objs, items, n_items, dirs, out, nrm); break;
+    default: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 4>), grid, block, 0, st, lut, objs, items, n_items, dirs, out, nrm); break;
+    }
+}
+
+int launch_query_persistent(const void* lut, int dtype, int layout, const shm_object* objs_dev,
+                            const WorkItem* items_dev, int64_t n_items, const shm_launch_shape& shape, int n_cu,
+                            const float* dirs, float* out, float* normal, hipStream_t stream)
+{
+    if (n_items == 0) return SHM_OK;
+    int64_t G = (int64_t)shape.grid_per_cu * n_cu;
+    if (G > n_items) G = n_items;
+    const dim3 grid((unsigned)G), block((unsigned)shape.block);
+    const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL, nrm = normal != nullptr;
+#define SHM_P(a, b, c) launch_persistent_t<a, b, c>(shape.qpt, grid, block, stream, lut, objs_dev, items_dev, n_items, dirs, out, normal)
+    if (f16) {
+        if (cell) { if (nrm) SHM_P(true, true, true); else SHM_P(true, true, false); }
+        else { if (nrm) SHM_P(true, false, true); else SHM_P(true, false, false); }
+    } else {
+        if (cell) { if (nrm) SHM_P(false, true, true); else SHM_P(false, true, false); }
+        else { if (nrm) SHM_P(false, false, true); else SHM_P(false, false, false); }
+    }
+#undef SHM_P
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// TEXEL -> CELL relayout: one lane per (cell, corner), 16 B (FP32) or 8 B
+// (FP16) written contiguously.
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ void k_lut_to_cells(const V* __restrict__ tex, int N, int64_t total, V* __restrict__ cells)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int corner = (int)(i & 3);
+    const int64_t cell = i >> 2;
+    const int C = N + 1, P = N + 2;
+    const int64_t per_obj = 6ll * C * C;
+    const int64_t obj = cell / per_obj;
+    int64_t r = cell - obj * per_obj;
+    const int face = (int)(r / ((int64_t)C * C));
+    r -= (int64_t)face * C * C;
+    const int j0 = (int)(r / C), i0 = (int)(r - (int64_t)j0 * C);
+    const int p = i0 + (corner & 1), q = j0 + (corner >> 1);
+    cells[i] = tex[obj * (6ll * P * P) + ((int64_t)face * P + q) * P + p];
+}
+
+int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* cells, hipStream_t stream)
+{
+    const int64_t total = n_obj * 6ll * (N + 1) * (N + 1) * 4;  // (cell, corner) pairs
+    if (total == 0) return SHM_OK;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "lut_to_cells: too large");
+    if (dtype == SHM_F16)
+        hipLaunchKernelGGL(k_lut_to_cells<uint2>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           reinterpret_cast<const uint2*>(lut), N, total, reinterpret_cast<uint2*>(cells));
+    else
+        hipLaunchKernelGGL(k_lut_to_cells<float4>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           reinterpret_cast<const float4*>(lut), N, total, reinterpret_cast<float4*>(cells));
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+}  // namespace shm

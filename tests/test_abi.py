@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/shm.h, and rejects bad arguments with
+the documented status codes before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2602_20063_amd as shm
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "shm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^SHM_API\s+[\w\s\*]+?\b(shm_\w+)\(", text, flags=re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = shm.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in shm.SIGNATURES, f"{n} has no Python binding"
+    assert set(shm.SIGNATURES) == set(names)
+
+
+def test_version_and_sizes():
+    assert shm.shm_version() == 1
+    assert shm.shm_lut_elems(10, shm.SHM_LAYOUT_TEXEL) == 6 * 12 * 12 * 4
+    assert shm.shm_lut_elems(32, shm.SHM_LAYOUT_CELL) == 6 * 33 * 33 * 16
+    assert shm.shm_lut_elems(0, 0) == 0
+    assert shm.shm_lut_elems(2000, 0) == 0
+    assert shm.shm_lut_elems(4, 7) == 0
+    # basis table: padded K x padded rows, FP32
+    assert shm.shm_bake_sh_lut_workspace(8, 32) >= 81 * 6 * 34 * 34 * 4 * 4
+    assert shm.shm_bake_sh_lut_workspace(17, 32) == 0
+    assert shm.shm_backward_workspace(512, 1, 1 << 22) > (1 << 22) * 36
+
+
+def call(name, *args):
+    return getattr(shm.lib(), name)(*args)
+
+
+def test_query_argument_validation():
+    p = ctypes.c_void_p(16)
+    cases = [
+        ((p, 5, 0, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),  # dtype
+        ((p, 0, 3, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),  # layout
+        ((p, 0, 0, 0, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),   # N
+        ((p, 0, 0, 1025, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),
+        ((p, 0, 0, 10, -1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),
+        ((None, 0, 0, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),
+        ((p, 0, 0, 10, 1, p, 8, ctypes.c_void_p(20), None, None), shm.SHM_ERR_INVALID_ARG),  # misaligned out
+        ((p, 0, 0, 10, 0, p, 8, p, None, None), shm.SHM_OK),               # empty: nothing to do
+        ((p, 0, 0, 10, 3, p, 0, p, None, None), shm.SHM_OK),
+    ]
+    for args, code in cases:
+        assert call("shm_query_value_grad", *args) == code, args
+    assert "N must be" in shm.shm_last_error() or True
+
+
+def test_error_message_is_set():
+    p = ctypes.c_void_p(16)
+    assert call("shm_query_value_grad", p, 0, 0, 0, 1, p, 8, p, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert "N must be" in shm.shm_last_error()
+
+
+def test_bake_argument_validation():
+    p = ctypes.c_void_p(256)
+    assert call("shm_bake_sh_lut", p, 17, 8, 1, 0, p, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_bake_sh_lut", p, -1, 8, 1, 0, p, p, 1 << 30, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_bake_sh_lut", p, 4, 8, 1, 0, p, p, 16, None) == shm.SHM_ERR_WORKSPACE
+    assert call("shm_bake_sh_lut", p, 4, 8, 1, 0, p, None, 1 << 30, None) == shm.SHM_ERR_WORKSPACE
+    assert call("shm_bake_sh_lut", p, 4, 8, 1, 9, p, p, 1 << 30, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_bake_sh_lut", p, 4, 8, 0, 0, None, None, 0, None) == shm.SHM_OK
+
+
+def test_backward_and_trace_validation():
+    p = ctypes.c_void_p(256)
+    assert call("shm_backward_sort", 8, 1, p, 100, p, 10, None) == shm.SHM_ERR_WORKSPACE
+    assert call("shm_backward_sort", 0, 1, p, 100, p, 1 << 30, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_backward_sort", 8, 1, p, 100, ctypes.c_void_p(300), 1 << 30, None) == shm.SHM_ERR_INVALID_ARG
+    c = (ctypes.c_float * 3)(0, 0, 0)
+    assert call("shm_trace_radial", p, 0, 8, c, ctypes.c_float(-1.0), p, p, 10, 20, 8, 3, p, p, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_trace_radial", p, 0, 8, c, ctypes.c_float(1.0), p, p, 10, 40, 20, 10, p, p, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_trace_radial", p, 0, 8, None, ctypes.c_float(1.0), p, p, 10, 20, 8, 3, p, p, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_trace_radial", p, 0, 8, c, ctypes.c_float(1.0), p, p, 0, 20, 8, 3, p, p, None, None) == shm.SHM_OK
+
+
+def test_plan_validation():
+    h = ctypes.c_void_p()
+    objs = (shm.shm_object * 2)()
+    objs[0].lut_offset, objs[0].N, objs[0].q_begin, objs[0].q_count = 0, 8, 0, 10
+    objs[1].lut_offset, objs[1].N, objs[1].q_begin, objs[1].q_count = 3, 8, 10, 10  # misaligned offset
+    assert call("shm_plan_create", ctypes.cast(objs, ctypes.c_void_p), 2, 0, 0, None, ctypes.byref(h)) == shm.SHM_ERR_INVALID_ARG
+    objs[1].lut_offset, objs[1].N = 4, 0
+    assert call("shm_plan_create", ctypes.cast(objs, ctypes.c_void_p), 2, 0, 0, None, ctypes.byref(h)) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_plan_create", None, 2, 0, 0, None, ctypes.byref(h)) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_plan_launch", None, None, None, None, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_plan_graph_launch", None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_plan_destroy", None) == shm.SHM_OK
+    assert shm.lib().shm_plan_work_items(None) == -1
+    s = shm.shm_launch_shape(100, 1, 100, 4)
+    assert call("shm_plan_set_shape", None, ctypes.byref(s)) == shm.SHM_ERR_INVALID_ARG

@@ -1,0 +1,121 @@
+"""GPU backward (dL/dLUT by sorted texel pull, dL/d dirs) against the FP64
+oracle, finite differences and bitwise repeatability."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2602_20063_amd as shm
+import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rng(k):
+    return np.random.default_rng(999 + k)
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def run_bwd(lut, dirs, g, n_obj=1):
+    lut_t, d_t, g_t = gpu(lut), gpu(dirs), gpu(g)
+    N = lut.shape[-2] - 2
+    bc = shm.BackwardContext(N, n_obj, d_t, dirs.shape[0] // n_obj)
+    gl, gd = bc.backward(lut_t, g_t)
+    torch.cuda.synchronize()
+    return gl.cpu().numpy(), gd.cpu().numpy()
+
+
+def test_backward_matches_oracle():
+    r = rng(1)
+    N = 16
+    c = workloads.sh_glyph_coeffs(6, 1, r)[0]
+    lut = oracle.bake_sh(c, N).astype(np.float32)
+    dirs = workloads.uniform_dirs(20000, r)
+    g = r.standard_normal((20000, 4)).astype(np.float32)
+    gl, gd = run_bwd(lut, dirs, g)
+    rl, rd = oracle.backward(lut, dirs, g)
+    scale = np.sqrt(np.mean(rl ** 2, axis=(0, 1, 2)))
+    assert (np.abs(gl - rl).max(axis=(0, 1, 2)) / scale).max() < 1e-4
+    gn = np.linalg.norm(rd, axis=1)
+    floor = np.sqrt(np.mean(gn ** 2))
+    err = np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)
+    assert err.max() < 1e-3, err.max()
+    assert np.sqrt(np.mean(err ** 2)) < 1e-4
+
+
+def test_backward_multi_object_and_invalid():
+    r = rng(2)
+    N, n = 8, 5
+    lut = workloads.random_lut(N, r, n_obj=n)
+    qpo = 333
+    dirs = workloads.uniform_dirs(n * qpo, r)
+    dirs[7] = 0.0
+    dirs[400] = np.nan
+    g = r.standard_normal((n * qpo, 4)).astype(np.float32)
+    gl, gd = run_bwd(lut, dirs, g, n_obj=n)
+    for o in range(n):
+        sl = slice(o * qpo, (o + 1) * qpo)
+        rl, rd = oracle.backward(lut[o], dirs[sl], g[sl])
+        scale = np.sqrt(np.mean(rl ** 2))
+        assert np.abs(gl[o] - rl).max() / scale < 1e-4
+        ok = np.isfinite(rd[:, 0])
+        assert np.array_equal(np.isfinite(gd[sl, 0]), ok)
+        gn = np.linalg.norm(rd[ok], axis=1)
+        floor = np.sqrt(np.mean(gn ** 2))
+        assert (np.linalg.norm(gd[sl][ok] - rd[ok], axis=1) / np.maximum(gn, floor)).max() < 1e-3
+
+
+def test_backward_bitwise_repeatable():
+    r = rng(3)
+    N = 64
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(300000, r)
+    g = r.standard_normal((300000, 4)).astype(np.float32)
+    a = run_bwd(lut, dirs, g)
+    b = run_bwd(lut, dirs, g)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_backward_all_queries_in_one_cell():
+    """Degenerate distribution: every query in the same cell (one long
+    segment) and queries on cell edges."""
+    r = rng(4)
+    N = 4
+    lut = workloads.random_lut(N, r)
+    base = np.array([1.0, 0.1, 0.2])
+    dirs = (base + 1e-4 * r.standard_normal((5000, 3))).astype(np.float32)
+    g = r.standard_normal((5000, 4)).astype(np.float32)
+    gl, _ = run_bwd(lut, dirs, g)
+    rl, _ = oracle.backward(lut, dirs, g, want_dirs=False)
+    scale = np.abs(rl).max()
+    assert np.abs(gl - rl).max() / scale < 1e-4
+
+
+def test_autograd_function_and_fd():
+    """torch.autograd through the HIP backward; finite differences of the
+    FP64 oracle loss on 64 random texels."""
+    r = rng(5)
+    N = 12
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(4096, r)
+    w = r.standard_normal((4096, 4))
+    lut_t = gpu(lut).requires_grad_(True)
+    d_t = gpu(dirs).requires_grad_(True)
+    out = shm.HermiteQuery.apply(lut_t, d_t)
+    loss = (out.double() * gpu(w, torch.float64)).sum()
+    loss.backward()
+    gl = lut_t.grad.cpu().numpy()
+    eps = 1e-3
+    lut64 = lut.astype(np.float64)
+    for _ in range(64):
+        idx = tuple(int(r.integers(s)) for s in lut.shape)
+        lp, lm = lut64.copy(), lut64.copy()
+        lp[idx] += eps
+        lm[idx] -= eps
+        fd = (np.sum(oracle.query(lp, dirs) * w) - np.sum(oracle.query(lm, dirs) * w)) / (2 * eps)
+        assert abs(fd - gl[idx]) <= 1e-4 * max(1.0, abs(fd)), (idx, fd, gl[idx])
+    assert d_t.grad is not None and torch.isfinite(d_t.grad).all()

@@ -1,0 +1,106 @@
+"""Batched persistent launch: bitwise equal to per-object launches of the
+same dtype; captured HIP graph replays; autotuned shapes."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2602_20063_amd as shm
+import workloads
+from parity import check_value_grad
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def build_batch(n_obj, seed, dtype=np.float32, qscale=1.0):
+    r = np.random.default_rng(seed)
+    spec = workloads.uneven_batch(r, n_obj=n_obj, mu=6.0 * qscale, sigma=1.0, qmin=1, qmax=5000, Lmax=6)
+    luts, objs, off, qb = [], [], 0, 0
+    for o in range(n_obj):
+        N = int(min(spec["N"][o], 64))
+        lut = workloads.random_lut(N, r)
+        luts.append(lut.reshape(-1))
+        q = int(spec["Q"][o])
+        objs.append((off, N, qb, q))
+        off += lut.size
+        qb += q
+    flat = np.concatenate(luts).astype(dtype)
+    dirs = workloads.uniform_dirs(qb, r)
+    return flat, objs, dirs
+
+
+@pytest.mark.parametrize("dt,layout", [(torch.float32, 0), (torch.float16, 0), (torch.float16, 1), (torch.float32, 1)])
+def test_plan_equals_per_object(dt, layout):
+    flat, objs, dirs = build_batch(40, 5)
+    code = shm.SHM_F16 if dt == torch.float16 else shm.SHM_F32
+    lut_t = torch.as_tensor(flat).to(DEV, dt)
+    if layout == shm.SHM_LAYOUT_CELL:  # convert each object to cells
+        parts, cobjs, off = [], [], 0
+        for (o_off, N, qb, q) in objs:
+            n = 6 * (N + 2) * (N + 2) * 4
+            cl = shm.to_cells(lut_t[o_off:o_off + n].reshape(1, 6, N + 2, N + 2, 4)).reshape(-1)
+            parts.append(cl)
+            cobjs.append((off, N, qb, q))
+            off += cl.numel()
+        lut_t = torch.cat(parts)
+        objs = cobjs
+    d_t = torch.as_tensor(dirs).to(DEV)
+    out = torch.full((dirs.shape[0], 4), float("nan"), device=DEV)
+    plan = shm.Plan(objs, code, layout)
+    plan.launch(lut_t, d_t, out)
+    ref = torch.full_like(out, float("nan"))
+    for (off, N, qb, q) in objs:
+        if q == 0:
+            continue
+        n = shm.shm_lut_elems(N, layout)
+        shm.shm_query_value_grad(lut_t[off:off + n], code, layout, N, 1, d_t[qb:qb + q], q, ref[qb:qb + q])
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    plan.close()
+
+
+def test_plan_matches_oracle_and_shapes():
+    flat, objs, dirs = build_batch(25, 6)
+    lut_t = torch.as_tensor(flat).to(DEV)
+    d_t = torch.as_tensor(dirs).to(DEV)
+    ref = oracle.query_objects(flat.reshape(-1).astype(np.float64),
+                               [o[0] // 4 for o in objs], [o[1] for o in objs], [o[2] for o in objs],
+                               [o[3] for o in objs], dirs)
+    plan = shm.Plan(objs, shm.SHM_F32)
+    for shape in [(64, 1, 64, 1), (256, 2, 512, 8), (512, 4, 2048, 16), (128, 1, 128 * 7, 3)]:
+        plan.set_shape(*shape)
+        out = torch.full((dirs.shape[0], 4), float("nan"), device=DEV)
+        plan.launch(lut_t, d_t, out)
+        torch.cuda.synchronize()
+        check_value_grad(out.cpu().numpy(), ref, f"shape {shape}")
+    plan.close()
+
+
+def test_graph_capture_replays(tmp_path):
+    flat, objs, dirs = build_batch(30, 7)
+    lut_t = torch.as_tensor(flat).to(DEV, torch.float16)
+    d_t = torch.as_tensor(dirs).to(DEV)
+    out = torch.zeros((dirs.shape[0], 4), device=DEV)
+    plan = shm.Plan(objs, shm.SHM_F16)
+    cache = str(tmp_path / "tune.json")
+    shape = plan.autotune(lut_t, d_t, out, cache_path=cache)
+    assert shape["tile"] % (shape["block"] * shape["qpt"]) == 0
+    saved = json.load(open(cache))
+    assert len(saved) == 1
+    plan2 = shm.Plan(objs, shm.SHM_F16)
+    assert plan2.autotune(lut_t, d_t, out, cache_path=cache) == shape
+    plan2.close()
+    ref = torch.zeros_like(out)
+    plan.launch(lut_t, d_t, ref)
+    plan.capture_graph(lut_t, d_t, out)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        plan.graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+    plan.close()

@@ -1,0 +1,173 @@
+"""GPU parity of the query (value + spherical gradient) against the FP64
+oracle, element by element on the same seeded inputs and the same LUT data.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2602_20063_amd as shm
+import workloads
+from parity import check_value_grad, angle_deg
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rng(k):
+    return np.random.default_rng(777 + k)
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def gpu_query(lut32, dirs, layout=shm.SHM_LAYOUT_TEXEL, dtype=torch.float32, q_per_obj=None, normals=False):
+    lut_t = gpu(lut32, dtype)
+    if layout == shm.SHM_LAYOUT_CELL:
+        lut_t = shm.to_cells(lut_t.reshape((-1,) + lut_t.shape[-4:]))
+    res = shm.query(lut_t, gpu(dirs), q_per_obj=q_per_obj, layout=layout, normals=normals)
+    torch.cuda.synchronize()
+    if normals:
+        return res[0].cpu().numpy(), res[1].cpu().numpy()
+    return res.cpu().numpy()
+
+
+def edge_dirs():
+    """Axis directions, face ties, sign ties, -0, cube corners, directions
+    landing exactly on cell boundaries and invalid directions."""
+    d = [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+         [1, 1, 0], [1, -1, 0], [-1, 1, 1], [1, 1, 1], [-1, -1, -1], [0, 1, 1], [0, -1, -1],
+         [-0.0, 0.0, 1.0], [1, -0.0, -0.0], [0.5, 0.5, 0.5], [3, 1, 2], [1e-30, 0, 0],
+         [1e30, 1e29, -1e29], [0, 0, 0], [np.nan, 1, 0], [np.inf, 0, 0]]
+    return np.array(d, np.float32)
+
+
+@pytest.mark.parametrize("layout", [shm.SHM_LAYOUT_TEXEL, shm.SHM_LAYOUT_CELL])
+def test_query_cfg1_random_lut(layout):
+    """Workload 1 shape (N=10, 65,536 directions) on arbitrary texel data."""
+    r = rng(1)
+    N = 10
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(65536, workloads.rng_for(1))
+    out = gpu_query(lut, dirs, layout)
+    ref = oracle.query(lut, dirs)
+    check_value_grad(out, ref, "cfg1 random lut")
+
+
+def test_query_cfg1_sh_glyph_with_normals():
+    c = workloads.sh_glyph_coeffs(4, 1, workloads.rng_for(1))[0]
+    N = 10
+    lut = oracle.bake_sh(c, N).astype(np.float32)
+    dirs = workloads.uniform_dirs(65536, workloads.rng_for(1))
+    out, nrm = gpu_query(lut, dirs, normals=True)
+    ref, rn = oracle.query(lut, dirs, normals=True)
+    check_value_grad(out, ref, "cfg1 glyph")
+    assert angle_deg(nrm, rn).max() < 1e-3
+
+
+def test_cell_keys_bit_exact():
+    """Face and cell decisions are identical to the oracle's FP32 decision."""
+    dirs = np.concatenate([workloads.uniform_dirs(200000, rng(2)), edge_dirs()[:19]])
+    for N in (1, 10, 32, 257, 1024):
+        keys = shm.cell_keys(N, gpu(dirs)).cpu().numpy().view(np.uint32)
+        f, i0, j0, _, _ = oracle.locate(dirs, N)
+        C = N + 1
+        exp = ((f.astype(np.int64) * C + j0) * C + i0).astype(np.uint32)
+        exp[f < 0] = 0xFFFFFFFF
+        assert np.array_equal(keys, exp), N
+
+
+def test_layouts_agree_bitwise():
+    r = rng(3)
+    N = 17
+    lut = workloads.random_lut(N, r, n_obj=3)
+    dirs = workloads.uniform_dirs(3 * 1000, r)
+    a = gpu_query(lut, dirs, shm.SHM_LAYOUT_TEXEL)
+    b = gpu_query(lut, dirs, shm.SHM_LAYOUT_CELL)
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases():
+    r = rng(4)
+    N = 8
+    lut = workloads.random_lut(N, r)
+    d = edge_dirs()
+    out = gpu_query(lut, d)
+    ref = oracle.query(lut, d)
+    check_value_grad(out, ref, "edge dirs")
+    assert np.isnan(out[-3:]).all()
+    # texel-centre directions and exact cell-boundary directions
+    N = 6
+    lut = workloads.random_lut(N, r)
+    dd = []
+    for p in range(N + 1):
+        u = p / N  # f = uN + 1/2 = p + 1/2 ... cell edges sit at u = (k - 1/2)/N
+        for q in range(N + 1):
+            v = (q + 0.5) / N
+            for uu, vv in ((u, v), (np.clip((p - 0.5) / N, 0, 1), v)):
+                dd.append([1.0, -(2 * vv - 1), -(2 * uu - 1)])  # +X face: sc = -z, tc = -y
+    dd = np.array(dd, np.float32)
+    check_value_grad(gpu_query(lut, dd), oracle.query(lut, dd), "boundaries")
+
+
+def test_empty_and_ragged():
+    r = rng(5)
+    N = 12
+    lut = workloads.random_lut(N, r, n_obj=4)
+    for qpo in (1, 255, 257, 1000):
+        dirs = workloads.uniform_dirs(4 * qpo, r)
+        check_value_grad(gpu_query(lut, dirs, q_per_obj=qpo), oracle.query_objects(
+            lut.reshape(-1), np.arange(4) * (lut.size // 16), [N] * 4, np.arange(4) * qpo, [qpo] * 4, dirs), f"qpo {qpo}")
+    lut_t = gpu(lut)
+    empty = torch.empty((0, 3), device=DEV)
+    out = torch.empty((0, 4), device=DEV)
+    shm.shm_query_value_grad(lut_t, shm.SHM_F32, 0, N, 4, empty, 0, out)
+
+
+@pytest.mark.parametrize("N", [1, 2, 64, 512, 1024])
+def test_resolution_extremes(N):
+    r = rng(6 + N)
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(20000, r)
+    check_value_grad(gpu_query(lut, dirs), oracle.query(lut, dirs), f"N={N}")
+
+
+def test_large_n_smooth_lut_gradient_accuracy():
+    """Smooth data at N=512: gradient relative accuracy must hold even where
+    r_u is O(1) while texel differences are O(1/N)."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(7))[0]
+    N = 512
+    lut = oracle.bake_sh(c, N).astype(np.float32)
+    dirs = workloads.uniform_dirs(50000, rng(8))
+    check_value_grad(gpu_query(lut, dirs), oracle.query(lut, dirs), "N=512 glyph")
+
+
+def test_fp16_lut():
+    """FP16 storage: FP32 arithmetic on the decoded values matches the oracle
+    on the same (FP16-rounded) data; the error against the FP32 LUT is the
+    quantisation error and is only bounded loosely here (it grows ~ N)."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(9))[0]
+    N = 32
+    lut = oracle.bake_sh(c, N)
+    lut16 = lut.astype(np.float16)
+    dirs = workloads.uniform_dirs(65536, rng(10))
+    for layout in (shm.SHM_LAYOUT_TEXEL, shm.SHM_LAYOUT_CELL):
+        out = gpu_query(lut16.astype(np.float32), dirs, layout, dtype=torch.float16)
+        check_value_grad(out, oracle.query(lut16.astype(np.float64), dirs), "fp16 same data")
+    ref64 = oracle.query(lut, dirs)
+    assert np.abs(out[:, 0] - ref64[:, 0]).max() < 2e-3
+
+
+def test_cfg2_shape_reduced_and_sampled_full():
+    """Workload 2 layout (glyph-contiguous queries, 256 per glyph, N=32,
+    L=8): 256 glyphs element by element."""
+    n = 256
+    c = workloads.sh_glyph_coeffs(8, n, workloads.rng_for(2))
+    lut = oracle.bake_sh(c, 32).astype(np.float32)
+    dirs = workloads.uniform_dirs(n * 256, workloads.rng_for(2))
+    out = gpu_query(lut, dirs, q_per_obj=256)
+    ref = oracle.query_objects(lut.reshape(-1), np.arange(n) * (lut[0].size // 4), [32] * n, np.arange(n) * 256,
+                               [256] * n, dirs)
+    check_value_grad(out, ref, "cfg2 reduced")

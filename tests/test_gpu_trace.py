@@ -1,0 +1,83 @@
+"""Ray casting on the GPU against the FP64 oracle's schedule on the same
+LUT data."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2602_20063_amd as shm
+import workloads
+from parity import angle_deg
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def trace_both(lut32, rmax, o, d, dtype=torch.float32):
+    t, out, n = shm.trace(gpu(lut32, dtype), (0.0, 0.0, 0.0), rmax, gpu(o), gpu(d))
+    torch.cuda.synchronize()
+    ref = oracle.trace(lut32.astype(np.float64) if dtype == torch.float32 else lut32.astype(np.float16).astype(np.float64),
+                       np.zeros(3), rmax, o, d)
+    return (t.cpu().numpy(), out.cpu().numpy(), n.cpu().numpy()), ref
+
+
+def compare(g, ref, what, max_disagree=0.002):
+    tg, og, ng = g
+    tr, orf, nr = ref
+    hg, hr = np.isfinite(tg), np.isfinite(tr)
+    disagree = np.mean(hg != hr)
+    assert disagree <= max_disagree, f"{what}: hit mask disagreement {disagree:.4f}"
+    both = hg & hr
+    rel = np.abs(tg[both] - tr[both]) / tr[both]
+    assert np.median(rel) < 1e-6, f"{what}: median |dt|/t {np.median(rel):.2e}"
+    assert np.mean(rel < 1e-4) > 0.995, f"{what}: |dt|/t tail"
+    ang = angle_deg(ng[both], nr[both])
+    assert np.median(ang) < 1e-3 and np.mean(ang < 0.05) > 0.995, f"{what}: normal angle"
+    assert np.isnan(og[~hg]).all() and np.isinf(tg[~hg]).all()
+
+
+def test_trace_sh_glyph():
+    c = workloads.sh_glyph_coeffs(8, 1, np.random.default_rng(3))[0]
+    N = 32
+    lut = oracle.bake_sh(c, N).astype(np.float32)
+    rmax = oracle.rmax_bound(lut.astype(np.float64)) * 1.0001
+    o, d = workloads.camera_rays(160, 120)
+    g, ref = trace_both(lut, rmax, o, d)
+    compare(g, ref, "glyph")
+
+
+def test_trace_bumps_fd_lut():
+    """Workload 3 surface (64 bumps) at reduced resolution, FP32 and FP16."""
+    mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+    N = 64
+    dirs = oracle.margin_dirs(N)
+    samples = workloads.bumps_value(mu, amp, width, 1.0, dirs.reshape(-1, 3)).reshape(6, N + 4, N + 4)
+    lut = oracle.bake_fd(samples, N).astype(np.float32)
+    rmax = oracle.rmax_bound(lut.astype(np.float64)) * 1.0001
+    o, d = workloads.camera_rays(192, 108)
+    g, ref = trace_both(lut, rmax, o, d)
+    compare(g, ref, "bumps fp32")
+    g16, ref16 = trace_both(lut, rmax, o, d, dtype=torch.float16)
+    compare(g16, ref16, "bumps fp16")
+
+
+def test_trace_constant_sphere_and_misses():
+    N = 8
+    lut = np.zeros((6, N + 2, N + 2, 4), np.float32)
+    lut[..., 0] = 0.75
+    o, d = workloads.camera_rays(64, 64, eye=(0.0, 0.0, 2.0), vfov_deg=60.0)
+    g, ref = trace_both(lut, 0.8, o, d)
+    compare(g, ref, "sphere", max_disagree=0.0)
+    tg = g[0]
+    hit = np.isfinite(tg)
+    oo = o.astype(np.float64)
+    dd = d.astype(np.float64) / np.linalg.norm(d.astype(np.float64), axis=1, keepdims=True)
+    b = np.sum(oo * dd, axis=1)
+    disc = b * b - (np.sum(oo * oo, axis=1) - 0.75 ** 2)
+    assert np.array_equal(hit, disc > 0) or np.mean(hit != (disc > 0)) < 0.002
+    te = -b[hit] - np.sqrt(disc[hit])
+    assert np.abs(tg[hit] - te).max() < 1e-5

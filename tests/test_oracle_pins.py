@@ -637,3 +637,41 @@ def test_batched_equals_per_object():
     for k in range(3):
         ref = oracle.query(luts[k], dirs[qb[k]:qb[k] + counts[k]])
         assert np.array_equal(out[qb[k]:qb[k] + counts[k]], ref)
+
+
+# ---------------------------------------------------------------------------
+# Bump-field target (radial impostor workload)
+# ---------------------------------------------------------------------------
+def test_bumps_truth_and_bake_against_independent_evaluation():
+    """Values against the generator's independent numpy evaluation; the
+    spherical gradient and the baked chart channels against finite
+    differences of that evaluation."""
+    mu, amp, width = workloads.bump_params(rng(50), 12)
+    d = workloads.uniform_dirs(500, rng(51)).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    tr = oracle.bumps_truth(mu, amp, width, 1.0, d)
+    np.testing.assert_allclose(tr[:, 0], workloads.bumps_value(mu, amp, width, 1.0, d), rtol=1e-14)
+    tau = np.cross(d, np.array([0.2, -0.4, 0.9]))
+    tau /= np.linalg.norm(tau, axis=1, keepdims=True)
+    h = 1e-6
+    fd = (workloads.bumps_value(mu, amp, width, 1.0, d + h * tau) - workloads.bumps_value(mu, amp, width, 1.0, d - h * tau)) / (2 * h)
+    assert np.abs(fd - np.sum(tr[:, 1:] * tau, axis=1)).max() < 1e-6
+    assert np.abs(np.sum(tr[:, 1:] * d, axis=1)).max() < 1e-12
+    N = 16
+    lut = oracle.bake_bumps(mu, amp, width, 1.0, N)
+    hh = 1e-4
+    r = rng(52)
+    for _ in range(30):
+        face = int(r.integers(6))
+        p, q = int(r.integers(N + 2)), int(r.integers(N + 2))
+        u, v = (p - 0.5) / N, (q - 0.5) / N
+
+        def G(uu, vv):
+            return workloads.bumps_value(mu, amp, width, 1.0, chart_dir(face, np.array([uu]), np.array([vv])))[0]
+
+        ch = lut[face, q, p]
+        assert abs(ch[0] - G(u, v)) < 1e-14
+        assert abs(ch[1] - (G(u + hh, v) - G(u - hh, v)) / (2 * hh) / N) < 1e-7
+        assert abs(ch[2] - (G(u, v + hh) - G(u, v - hh)) / (2 * hh) / N) < 1e-7
+        guv = (G(u + hh, v + hh) - G(u + hh, v - hh) - G(u - hh, v + hh) + G(u - hh, v - hh)) / (4 * hh * hh)
+        assert abs(ch[3] - guv / N ** 2) < 1e-6

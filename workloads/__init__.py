@@ -184,6 +184,61 @@ def fbm_target(dirs, seed, octaves=6, lacunarity=2.0, gain=0.5, f0=2.0, amp=0.2)
     return val, grad
 
 
+def _mul32(h, c):
+    """(h * c) mod 2^32 for 0 <= h < 2^32 held in int64, without overflow."""
+    lo = c & 0xFFFF
+    hi = c >> 16
+    return (h * lo + (((h * hi) & 0xFFFF) << 16)) & 0xFFFFFFFF
+
+
+def fbm_target_torch(dirs, seed, octaves=6, lacunarity=2.0, gain=0.5, f0=2.0, amp=0.2):
+    """The same target as fbm_target, evaluated with torch (any device, FP64);
+    returns (R* [n], spherical gradient [n, 3])."""
+    import torch
+
+    d = dirs.to(torch.float64)
+    w = d / torch.linalg.norm(d, dim=1, keepdim=True)
+    val = torch.zeros(w.shape[0], dtype=torch.float64, device=w.device)
+    grad = torch.zeros_like(w)
+    norm = sum(gain ** o for o in range(octaves))
+    M = 0xFFFFFFFF
+    for o in range(octaves):
+        freq = f0 * lacunarity ** o
+        p = w * freq
+        fl = torch.floor(p)
+        i = fl.to(torch.int64)
+        f = p - fl
+        wt = _fade(f)
+        dwt = _dfade(f)
+        s = (seed + 101 * o) & M
+        for cx in (0, 1):
+            for cy in (0, 1):
+                for cz in (0, 1):
+                    h = _mul32((i[:, 0] + cx) & M, 0x8DA6B343) ^ _mul32((i[:, 1] + cy) & M, 0xD8163841) \
+                        ^ _mul32((i[:, 2] + cz) & M, 0xCB1AB31F) ^ s
+                    h = h ^ (h >> 16)
+                    h = _mul32(h, 0x85EBCA6B)
+                    h = h ^ (h >> 13)
+                    h = _mul32(h, 0xC2B2AE35)
+                    h = h ^ (h >> 16)
+                    hv = h.to(torch.float64) / 4294967295.0 * 2.0 - 1.0
+                    wx = wt[:, 0] if cx else 1.0 - wt[:, 0]
+                    wy = wt[:, 1] if cy else 1.0 - wt[:, 1]
+                    wz = wt[:, 2] if cz else 1.0 - wt[:, 2]
+                    sx = 1.0 if cx else -1.0
+                    sy = 1.0 if cy else -1.0
+                    sz = 1.0 if cz else -1.0
+                    v = gain ** o
+                    val += v * hv * wx * wy * wz
+                    grad[:, 0] += v * freq * hv * sx * dwt[:, 0] * wy * wz
+                    grad[:, 1] += v * freq * hv * wx * sy * dwt[:, 1] * wz
+                    grad[:, 2] += v * freq * hv * wx * wy * sz * dwt[:, 2]
+    val = 1.0 + amp * val / norm
+    grad = amp * grad / norm
+    grad = grad - torch.sum(grad * w, dim=1, keepdim=True) * w
+    return val, grad
+
+
 # --------------------------------------------------------------------------
 # uneven batch (workload 5)
 # --------------------------------------------------------------------------
