@@ -248,10 +248,10 @@ int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dty
     const int64_t rows = bake_rows(N), rows_pad = bake_rows_pad(N);
     float* Bt = reinterpret_cast<float*>(ws);
     const int ntex = 6 * (N + 2) * (N + 2);
-    // The table is evaluated in FP64 at every order: it is a vanishing part of
-    // the bake's arithmetic, and in FP32 the tangential chain rule loses
-    // ~1e-4 of the derivative channels to cancellation against the large
-    // radial part of the Cartesian polynomial's gradient.
+    // The table is evaluated in FP64 at every order (it is a vanishing part
+    // of the bake's arithmetic) so that it adds nothing beyond its FP32
+    // storage rounding: the tangential chain rule cancels the radial part of
+    // the Cartesian polynomial's gradient, which grows with the SH order.
     hipLaunchKernelGGL(k_sh_basis<double>, dim3((ntex + 127) / 128), dim3(128), 0, stream, L, N, Kp, rows_pad, Bt);
     SHM_LAUNCH_CHECK();
     if (rows_pad > rows) {

@@ -68,7 +68,19 @@ def test_bake_then_query_end_to_end():
     ref_lut = oracle.bake_sh(c32.astype(np.float64), N)
     off = np.arange(n) * (ref_lut[0].size // 4)
     ref = oracle.query_objects(ref_lut.reshape(-1), off, [N] * n, np.arange(n) * 256, [256] * n, dirs)
-    check_value_grad(out, ref, "bake+query", val_rtol=2e-5, grad_rtol=2e-4)
+    # Error against FP64 end to end: the FP32 LUT holds R ~ 1 to a few ulps
+    # (storage rounding plus FP32 accumulation in the contraction), and the
+    # chart gradient differences R across h = 1/N with weights up to 1.5, so
+    # the gradient carries an absolute error of order N * eps32 * |R|.
+    eps32 = np.finfo(np.float32).eps
+    ok = np.isfinite(ref[:, 0])
+    dv = np.abs(out[ok, 0] - ref[ok, 0]) / np.abs(ref[ok, 0])
+    assert dv.max() < 2e-6
+    gn = np.linalg.norm(ref[ok, 1:], axis=1)
+    floor = np.sqrt(np.mean(gn ** 2))
+    err = np.linalg.norm(out[ok, 1:] - ref[ok, 1:], axis=1)
+    bound = 1e-4 * np.maximum(gn, floor) + 12 * N * eps32 * np.abs(ref[ok, 0]).max()
+    assert np.all(err <= bound), (err / bound).max()
 
 
 def test_margin_dirs_and_fd_bake():
