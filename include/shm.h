@@ -233,6 +233,29 @@ SHM_API int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const fl
  * one float to rmax_out (device). */
 SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Comparison paths of the paper's experiments (Sec. 4.2, 4.4, 4.5; Tables
+ * psnr_value, cost_extended, runtime), on the same GPU as the Hermite query.
+ * shm_query_baseline reconstructs from a value-only LUT
+ *   vlut [n_obj][6][N+4][N+4] FP32, texel p at u = (p - 3/2)/N (a two-texel
+ *   gutter; exactly the samples at shm_margin_dirs(N)):
+ *   SHM_RECON_NEAREST      nearest texel, zero gradient (1 fetch)
+ *   SHM_RECON_BILINEAR_FD  bilinear value, chart derivatives by central
+ *                          differences of 4 more bilinear lookups at u +- h,
+ *                          v +- h (5 x 4 = 20 fetches)
+ *   SHM_RECON_BICUBIC      16-tap Catmull-Rom value and analytic gradient
+ * then transports (r_u, r_v) to the spherical gradient as the Hermite query
+ * does.  shm_sh_eval evaluates sum_k coeffs[k] Y_k and its spherical
+ * gradient directly, without a LUT (coeffs [n_obj][(L+1)^2], L <= 16).
+ * Both write out [n_obj*q_per_obj][4] = (R, gx, gy, gz); NaN for invalid
+ * directions.
+ * ---------------------------------------------------------------------- */
+typedef enum { SHM_RECON_NEAREST = 0, SHM_RECON_BILINEAR_FD = 1, SHM_RECON_BICUBIC = 2 } shm_recon;
+SHM_API int shm_query_baseline(const float* vlut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
+                               int32_t method, float* out, hipStream_t stream);
+SHM_API int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs, int64_t q_per_obj,
+                        float* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

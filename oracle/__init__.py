@@ -295,3 +295,18 @@ def trace_F(lut, center, o, d, ts):
     lib().orc_trace_F(_p(lut), ctypes.c_int(N), _p(_f64(center)), _p(_f64(o)), _p(_f64(d)), _p(ts),
                       ctypes.c_int64(ts.size), _p(F))
     return F
+
+
+BASELINE_NEAREST, BASELINE_BILINEAR_FD, BASELINE_BICUBIC = 0, 1, 2
+
+
+def baseline_query(vlut, dirs, method):
+    """Comparison reconstructions on a value-only LUT [6, N+4, N+4] (texel p
+    at u = (p - 3/2)/N): 0 nearest, 1 bilinear + finite-difference
+    gradient, 2 Catmull-Rom bicubic + analytic gradient.  (R, grad) [Q, 4]."""
+    v = _f64(vlut)
+    N = v.shape[-1] - 4
+    d = _f32(dirs).reshape(-1, 3)
+    out = np.empty((d.shape[0], 4))
+    lib().orc_baseline_query(_p(v), ctypes.c_int(N), _p(d), ctypes.c_int64(d.shape[0]), ctypes.c_int(method), _p(out))
+    return out

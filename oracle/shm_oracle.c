@@ -891,6 +891,91 @@ ORC_API void orc_trace_F(const double* lut, int N, const double* center, const d
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Comparison reconstructions of the paper's experiments (Sec. 4.1, 4.4,     */
+/* Tables psnr_value, cost_extended, runtime) on a value-only LUT.           */
+/* ------------------------------------------------------------------------ */
+/* Value-only LUT: vlut[face][q][p], p, q in 0..N+3, texel p centred at
+ * u = (p - 3/2)/N (a two-texel gutter: the 4x4 bicubic footprint of any
+ * cell the faces' queries reach stays inside the table).  Continuous
+ * coordinate f = u N + 3/2.
+ *   method 0  nearest texel (value only, zero gradient)
+ *   method 1  bilinear value; chart derivatives by central differences of the
+ *             bilinear reconstruction at u +- h, v +- h (four extra lookups)
+ *   method 2  16-tap Catmull-Rom bicubic value and its analytic derivatives
+ * The chart derivatives become the spherical gradient as in Sec. 3.4. */
+static double vl_at(const double* vl, int N, int f, int p, int q)
+{
+    int P = N + 4;
+    if (p < 0) p = 0;
+    if (q < 0) q = 0;
+    if (p > N + 3) p = N + 3;
+    if (q > N + 3) q = N + 3;
+    return vl[((size_t)f * P + q) * P + p];
+}
+
+static double bilinear_at(const double* vl, int N, int face, double a, double b)
+{
+    double fu = (a + 1.0) * 0.5 * N + 1.5, fv = (b + 1.0) * 0.5 * N + 1.5;
+    int i0 = (int)floor(fu), j0 = (int)floor(fv);
+    double s = fu - i0, t = fv - j0;
+    return (1 - s) * (1 - t) * vl_at(vl, N, face, i0, j0) + s * (1 - t) * vl_at(vl, N, face, i0 + 1, j0) +
+           (1 - s) * t * vl_at(vl, N, face, i0, j0 + 1) + s * t * vl_at(vl, N, face, i0 + 1, j0 + 1);
+}
+
+/* Catmull-Rom weights of taps -1, 0, 1, 2 at t, and their derivatives */
+static void catmull_rom(double t, double w[4], double dw[4])
+{
+    double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2 * t2 - t);
+    w[1] = 0.5 * (3 * t3 - 5 * t2 + 2);
+    w[2] = 0.5 * (-3 * t3 + 4 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+    dw[0] = 0.5 * (-3 * t2 + 4 * t - 1);
+    dw[1] = 0.5 * (9 * t2 - 10 * t);
+    dw[2] = 0.5 * (-9 * t2 + 8 * t + 1);
+    dw[3] = 0.5 * (3 * t2 - 2 * t);
+}
+
+ORC_API void orc_baseline_query(const double* vlut, int N, const float* dirs, int64_t Q, int method, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        double d[3] = {dirs[3 * q], dirs[3 * q + 1], dirs[3 * q + 2]};
+        int f = face_select(d[0], d[1], d[2]);
+        if (f < 0) { for (int k = 0; k < 4; ++k) out[4 * q + k] = NAN; continue; }
+        double a = dot3(d, FS[f]) / dot3(d, FM[f]), b = dot3(d, FT[f]) / dot3(d, FM[f]);
+        double fu = (a + 1.0) * 0.5 * N + 1.5, fv = (b + 1.0) * 0.5 * N + 1.5;
+        double R = 0, ru = 0, rv = 0;
+        if (method == 0) {
+            R = vl_at(vlut, N, f, (int)floor(fu + 0.5), (int)floor(fv + 0.5));
+        } else if (method == 1) {
+            double h = 1.0 / N, da = 2.0 * h; /* a = 2u - 1: a step of h in u is 2h in a */
+            R = bilinear_at(vlut, N, f, a, b);
+            ru = (bilinear_at(vlut, N, f, a + da, b) - bilinear_at(vlut, N, f, a - da, b)) / (2 * h);
+            rv = (bilinear_at(vlut, N, f, a, b + da) - bilinear_at(vlut, N, f, a, b - da)) / (2 * h);
+        } else {
+            int i0 = (int)floor(fu), j0 = (int)floor(fv);
+            double s = fu - i0, t = fv - j0, ws[4], dws[4], wt[4], dwt[4];
+            catmull_rom(s, ws, dws);
+            catmull_rom(t, wt, dwt);
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i) {
+                    double v = vl_at(vlut, N, f, i0 - 1 + i, j0 - 1 + j);
+                    R += ws[i] * wt[j] * v;
+                    ru += dws[i] * wt[j] * v;
+                    rv += ws[i] * dwt[j] * v;
+                }
+            ru *= N;
+            rv *= N;
+        }
+        double g[3];
+        transport_closed(f, a, b, ru, rv, g);
+        out[4 * q] = R;
+        for (int k = 0; k < 3; ++k) out[4 * q + 1 + k] = g[k];
+    }
+}
+
 ORC_API int orc_version(void) { return 1; }
 
 #ifdef _OPENMP

@@ -21,6 +21,7 @@ SHM_OK, SHM_ERR_INVALID_ARG, SHM_ERR_UNSUPPORTED, SHM_ERR_WORKSPACE, SHM_ERR_HIP
 SHM_F32, SHM_F16 = 0, 1
 SHM_LAYOUT_TEXEL, SHM_LAYOUT_CELL = 0, 1
 SHM_MAX_N, SHM_MAX_L = 1024, 16
+SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC = 0, 1, 2
 
 
 class ShmError(RuntimeError):
@@ -73,6 +74,8 @@ SIGNATURES = {
     "shm_trace_radial": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP,
                                         _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
     "shm_lut_rmax": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+    "shm_query_baseline": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _I32, _VP, _VP]),
+    "shm_sh_eval": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP]),
 }
 
 _lib = None
@@ -205,6 +208,17 @@ def shm_lut_rmax(lut, dtype, N, rmax_out, stream=None):
     return _check(lib().shm_lut_rmax(_ptr(lut), dtype, N, _ptr(rmax_out), _stream(stream)))
 
 
+def shm_query_baseline(vlut, N, n_obj, dirs, q_per_obj, method, out, stream=None):
+    _need(vlut, torch.float32, "vlut")
+    return _check(lib().shm_query_baseline(_ptr(vlut), N, n_obj, _ptr(dirs), q_per_obj, method, _ptr(out),
+                                           _stream(stream)))
+
+
+def shm_sh_eval(coeffs, L, n_obj, dirs, q_per_obj, out, stream=None):
+    _need(coeffs, torch.float32, "coeffs")
+    return _check(lib().shm_sh_eval(_ptr(coeffs), L, n_obj, _ptr(dirs), q_per_obj, _ptr(out), _stream(stream)))
+
+
 # ---------------------------------------------------------------------------
 # plans (batched form)
 # ---------------------------------------------------------------------------
@@ -304,6 +318,28 @@ def query(lut, dirs, q_per_obj=None, layout=SHM_LAYOUT_TEXEL, normals=False, str
     nrm = torch.empty((Q, 3), dtype=torch.float32, device=dirs.device) if normals else None
     shm_query_value_grad(lut, _dtype_code(lut), layout, N, n_obj, dirs, q_per_obj, out, nrm, stream)
     return (out, nrm) if normals else out
+
+
+def query_baseline(vlut, dirs, method, q_per_obj=None, stream=None):
+    """Comparison reconstruction from a value-only LUT [n_obj, 6, N+4, N+4]."""
+    N = vlut.shape[-1] - 4
+    n_obj = vlut.numel() // (6 * (N + 4) * (N + 4))
+    Q = dirs.shape[0]
+    q_per_obj = Q // n_obj if q_per_obj is None else q_per_obj
+    out = torch.empty((Q, 4), dtype=torch.float32, device=dirs.device)
+    shm_query_baseline(vlut, N, n_obj, dirs, q_per_obj, method, out, stream)
+    return out
+
+
+def sh_eval(coeffs, dirs, q_per_obj=None, stream=None):
+    """Direct SH evaluation (no LUT): coeffs [n_obj, (L+1)^2] -> (R, grad)."""
+    n_obj, K = coeffs.shape
+    L = int(round(K ** 0.5)) - 1
+    Q = dirs.shape[0]
+    q_per_obj = Q // n_obj if q_per_obj is None else q_per_obj
+    out = torch.empty((Q, 4), dtype=torch.float32, device=dirs.device)
+    shm_sh_eval(coeffs, L, n_obj, dirs, q_per_obj, out, stream)
+    return out
 
 
 def margin_dirs(N, device="cuda", stream=None):

@@ -522,4 +522,31 @@ int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hip
     return launch_lut_rmax(lut, dtype, N, rmax_out, stream);
 }
 
+// ---------------------------------------------------------------------------
+int shm_query_baseline(const float* vlut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
+                       int32_t method, float* out, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "query_baseline: N must be 1..%d", SHM_MAX_N);
+    if (method < SHM_RECON_NEAREST || method > SHM_RECON_BICUBIC) return fail(SHM_ERR_INVALID_ARG, "query_baseline: bad method %d", method);
+    if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query_baseline: negative size");
+    if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
+    if (!vlut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "query_baseline: null pointer");
+    if (!aligned(out, 16) || !aligned(vlut, 4) || !aligned(dirs, 4)) return fail(SHM_ERR_INVALID_ARG, "query_baseline: misaligned buffer");
+    return launch_query_baseline(vlut, N, n_obj, dirs, q_per_obj, method, out, stream);
+}
+
+int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs, int64_t q_per_obj, float* out,
+                hipStream_t stream)
+{
+    clear_error();
+    if (L < 0) return fail(SHM_ERR_INVALID_ARG, "sh_eval: L must be >= 0");
+    if (L > SHM_MAX_L) return fail(SHM_ERR_UNSUPPORTED, "sh_eval: L must be <= %d", SHM_MAX_L);
+    if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "sh_eval: negative size");
+    if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
+    if (!coeffs || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "sh_eval: null pointer");
+    if (!aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "sh_eval: misaligned output");
+    return launch_sh_eval(coeffs, L, n_obj, dirs, q_per_obj, out, stream);
+}
+
 }  // extern "C"

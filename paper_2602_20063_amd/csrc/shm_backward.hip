@@ -8,8 +8,10 @@
 //   2. query:  per query (original order) the direction gradient (second
 //              chart derivatives + derivative of the chart map) and a compact
 //              record (s, t, gR, N lambda_u, N lambda_v) stored at its rank
-//   3. pull:   per texel, the contributions of the queries of its <= 4
-//              adjacent cells, cells and queries in a fixed order
+//   3. cells:  per cell, the sum over its sorted query segment of the 16
+//              weights (4 corners x 4 channels), in segment order
+//   4. texels: per texel, the corner sums of its <= 4 adjacent cells in a
+//              fixed order
 // The sort depends only on the directions and is reused while they stay
 // fixed.  Integer atomics appear only in the per-block digit histograms.
 #include "shm_device.hpp"
@@ -21,11 +23,12 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;                       // elements per thread per tile
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // 4096 elements per block
 constexpr uint32_t KEY_INVALID = 0xffffffffu;
+constexpr int SC_THREADS = 256, SC_ITEMS = 16, SC_TILE = SC_THREADS * SC_ITEMS;  // scan tiles
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BwdLayout {
-    size_t keys0, vals0, keys1, vals1, rank, cstart, hist, rec4, rec1, total;
+    size_t keys0, vals0, keys1, vals1, rank, cstart, hist, tsum, rec4, rec1, csum, total;
     int64_t Q, n_cells, nb;
     int passes;
 };
@@ -48,8 +51,10 @@ static BwdLayout bwd_layout(int N, int64_t n_obj, int64_t q_per_obj)
     W.rank = take(W.Q * 4);
     W.cstart = take((W.n_cells + 1) * 4);
     W.hist = take((size_t)256 * W.nb * 4);
+    W.tsum = take(((size_t)256 * W.nb + SC_TILE - 1) / SC_TILE * 4);
     W.rec4 = take(W.Q * 16);
     W.rec1 = take(W.Q * 4);
+    W.csum = take(W.n_cells * 64);
     W.total = o;
     return W;
 }
@@ -92,29 +97,71 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __res
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of n uint32 in one workgroup of 1024 lanes (chunked)
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ a, int64_t n)
+// exclusive scan of n uint32: per-block scans of 4096 elements (256 lanes x
+// 16), a one-workgroup scan of the block totals, then the block offsets
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total)
 {
-    __shared__ uint32_t part[1024];
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t b = (int64_t)threadIdx.x * per;
-    const int64_t e = (b + per) < n ? (b + per) : n;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += a[i];
-    part[threadIdx.x] = s;
+    // Hillis-Steele over the 256 lanes of the workgroup
+    const int t = threadIdx.x;
+    sh[t] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
-        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    for (int off = 1; off < SC_THREADS; off <<= 1) {
+        const uint32_t a = t >= off ? sh[t - off] : 0u;
         __syncthreads();
-        part[threadIdx.x] += v;
+        sh[t] += a;
         __syncthreads();
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    const uint32_t incl = sh[t];
+    *total = sh[SC_THREADS - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_tiles(uint32_t* __restrict__ a, int64_t n,
+                                                           uint32_t* __restrict__ tile_sums)
+{
+    __shared__ uint32_t sh[SC_THREADS];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    uint32_t v[SC_ITEMS], sum = 0;
+#pragma unroll
+    for (int i = 0; i < SC_ITEMS; ++i) {
+        v[i] = (base + i < n) ? a[base + i] : 0u;
+        sum += v[i];
     }
+    uint32_t total;
+    uint32_t run = block_excl_scan(sum, sh, &total);
+#pragma unroll
+    for (int i = 0; i < SC_ITEMS; ++i) {
+        if (base + i < n) a[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// one workgroup: exclusive scan of the tile sums (any count, chunks of 256)
+__global__ __launch_bounds__(SC_THREADS) void k_scan_sums(uint32_t* __restrict__ s, int64_t n)
+{
+    __shared__ uint32_t sh[SC_THREADS];
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += SC_THREADS) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint32_t v = i < n ? s[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan(v, sh, &total);
+        if (i < n) s[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_add(uint32_t* __restrict__ a, int64_t n,
+                                                         const uint32_t* __restrict__ tile_sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    const uint32_t add = tile_sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SC_ITEMS; ++i)
+        if (base + i < n) a[base + i] += add;
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t* __restrict__ kin,
@@ -194,13 +241,18 @@ int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_
     uint32_t* k1 = reinterpret_cast<uint32_t*>(base + W.keys1);
     uint32_t* v1 = reinterpret_cast<uint32_t*>(base + W.vals1);
     uint32_t* hist = reinterpret_cast<uint32_t*>(base + W.hist);
+    uint32_t* tsum = reinterpret_cast<uint32_t*>(base + W.tsum);
+    const int64_t n_hist = (int64_t)256 * W.nb;
+    const int64_t n_tiles = (n_hist + SC_TILE - 1) / SC_TILE;
     const unsigned gq = (unsigned)((W.Q + 255) / 256);
     hipLaunchKernelGGL(k_cell_keys, dim3(gq), dim3(256), 0, stream, N, W.Q, q_per_obj, dirs, (uint32_t)W.n_cells, k0, v0);
     SHM_LAUNCH_CHECK();
     for (int p = 0; p < W.passes; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, W.Q, shift, W.nb, hist);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, hist, (int64_t)256 * W.nb);
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SC_THREADS), 0, stream, tsum, n_tiles);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, v0, W.Q, shift, W.nb,
                            hist, k1, v1);
         SHM_LAUNCH_CHECK();
@@ -285,11 +337,45 @@ __global__ void k_bwd_query(const float* __restrict__ lut, int N, int64_t lut_el
 }
 
 // ---------------------------------------------------------------------------
-// texel pull: grad_lut[texel] = sum over adjacent cells (fixed order) of the
-// contributions of their queries (sorted order)
+// cell pass: csum[c][corner] (float4 over channels) = sum over the queries of
+// cell c, in sorted order, of that corner's 4 channel weights
 // ---------------------------------------------------------------------------
-__global__ void k_bwd_pull(int N, int64_t n_tex, const uint32_t* __restrict__ cs, const float4* __restrict__ rec4,
-                           const float* __restrict__ rec1, float4* __restrict__ grad_lut)
+__global__ void k_bwd_cells(int64_t n_cells, const uint32_t* __restrict__ cs, const float4* __restrict__ rec4,
+                            const float* __restrict__ rec1, float4* __restrict__ csum)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const uint32_t kb = cs[c], ke = cs[c + 1];
+    float4 a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t kk = kb; kk < ke; ++kk) {
+        const float4 r = rec4[kk];
+        const float nlv = rec1[kk];
+        const Basis1 S = basis1(r.x), T = basis1(r.y);
+        const float gR = r.z, nlu = r.w;
+#pragma unroll
+        for (int corner = 0; corner < 4; ++corner) {
+            const bool ci = corner & 1, cj = corner >> 1;
+            const float Hi = ci ? S.h1 : 1.0f - S.h1, Hdi = ci ? S.h1d : S.h0d;
+            const float dHi = ci ? S.d1 : -S.d1, dHdi = ci ? S.d1d : S.d0d;
+            const float Hj = cj ? T.h1 : 1.0f - T.h1, Hdj = cj ? T.h1d : T.h0d;
+            const float dHj = cj ? T.d1 : -T.d1, dHdj = cj ? T.d1d : T.d0d;
+            a[corner].x += gR * Hi * Hj + nlu * dHi * Hj + nlv * Hi * dHj;
+            a[corner].y += gR * Hdi * Hj + nlu * dHdi * Hj + nlv * Hdi * dHj;
+            a[corner].z += gR * Hi * Hdj + nlu * dHi * Hdj + nlv * Hi * dHdj;
+            a[corner].w += gR * Hdi * Hdj + nlu * dHdi * Hdj + nlv * Hdi * dHdj;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) csum[c * 4 + k] = a[k];
+}
+
+// ---------------------------------------------------------------------------
+// texel pass: grad_lut[texel] = sum over its adjacent cells (fixed order) of
+// the cell sum of the corner this texel is
+// ---------------------------------------------------------------------------
+__global__ void k_bwd_texels(int N, int64_t n_tex, const float4* __restrict__ csum, float4* __restrict__ grad_lut)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_tex) return;
@@ -307,23 +393,11 @@ __global__ void k_bwd_pull(int N, int64_t n_tex, const uint32_t* __restrict__ cs
         for (int di = 1; di >= 0; --di) {
             const int i0 = p - di;
             if (i0 < 0 || i0 > N) continue;
-            const int64_t c = cell_base + (int64_t)j0 * C + i0;
-            const uint32_t kb = cs[c], ke = cs[c + 1];
-            const bool ci = di == 1, cj = dj == 1;  // this texel is corner (di, dj) of cell (i0, j0)
-            for (uint32_t kk = kb; kk < ke; ++kk) {
-                const float4 r = rec4[kk];
-                const float nlv = rec1[kk];
-                const Basis1 S = basis1(r.x), T = basis1(r.y);
-                const float Hi = ci ? S.h1 : 1.0f - S.h1, Hdi = ci ? S.h1d : S.h0d;
-                const float dHi = ci ? S.d1 : -S.d1, dHdi = ci ? S.d1d : S.d0d;
-                const float Hj = cj ? T.h1 : 1.0f - T.h1, Hdj = cj ? T.h1d : T.h0d;
-                const float dHj = cj ? T.d1 : -T.d1, dHdj = cj ? T.d1d : T.d0d;
-                const float gR = r.z, nlu = r.w;
-                acc.x += gR * Hi * Hj + nlu * dHi * Hj + nlv * Hi * dHj;
-                acc.y += gR * Hdi * Hj + nlu * dHdi * Hj + nlv * Hdi * dHj;
-                acc.z += gR * Hi * Hdj + nlu * dHi * Hdj + nlv * Hi * dHdj;
-                acc.w += gR * Hdi * Hdj + nlu * dHdi * Hdj + nlv * Hdi * dHdj;
-            }
+            const float4 v = csum[(cell_base + (int64_t)j0 * C + i0) * 4 + (dj * 2 + di)];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
         }
     }
     grad_lut[i] = acc;
@@ -344,9 +418,12 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
         SHM_LAUNCH_CHECK();
     }
     if (grad_lut) {
+        float4* csum = reinterpret_cast<float4*>(base + W.csum);
+        hipLaunchKernelGGL(k_bwd_cells, dim3((unsigned)((W.n_cells + 255) / 256)), dim3(256), 0, stream, W.n_cells, cs,
+                           rec4, rec1, csum);
         const int64_t n_tex = n_obj * 6ll * (N + 2) * (N + 2);
-        hipLaunchKernelGGL(k_bwd_pull, dim3((unsigned)((n_tex + 255) / 256)), dim3(256), 0, stream, N, n_tex, cs,
-                           rec4, rec1, reinterpret_cast<float4*>(grad_lut));
+        hipLaunchKernelGGL(k_bwd_texels, dim3((unsigned)((n_tex + 255) / 256)), dim3(256), 0, stream, N, n_tex, csum,
+                           reinterpret_cast<float4*>(grad_lut));
         SHM_LAUNCH_CHECK();
     }
     return SHM_OK;

@@ -38,12 +38,25 @@ __device__ __forceinline__ void face_frame(int f, float M[3], float S[3], float 
     }
 }
 
+__device__ __forceinline__ int64_t basis_index(int k, int64_t col, int Kp, int64_t rows_pad, int frag)
+{
+    if (!frag) return (int64_t)k * rows_pad + col;
+    const int64_t t = col >> 5;
+    const int c = (int)(col & 31);
+    const int lane = (k & 3) * 16 + (c & 15);
+    return ((t * (Kp >> 2) + (k >> 2)) * 2 + (c >> 4)) * 64 + lane;
+}
+
 // ---------------------------------------------------------------------------
 // Basis table.  One lane per padded texel; writes Bt[k][row], row = texel*4+ch
 // (k-major so the MFMA B operand loads are coalesced), ld = rows_pad.
 // ---------------------------------------------------------------------------
+// Layouts of the table: k-major Bt[k][col] (ld = rows_pad), or, for the
+// register-resident contraction, MFMA fragment order
+// Bf[t][s][j][lane] with col = 32 t + 16 j + lane % 16 and k = 4 s + lane / 16,
+// so one column tile's B fragments are contiguous.
 template <typename Real>
-__global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, float* __restrict__ Bt)
+__global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, int frag, float* __restrict__ Bt)
 {
     const int P = N + 2;
     const int ntex = 6 * P * P;
@@ -82,11 +95,8 @@ __global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, float* __rest
         const Real Hv1 = H[1] * wv[0] + H[3] * wv[1] + H[4] * wv[2];
         const Real Hv2 = H[2] * wv[0] + H[4] * wv[1] + H[5] * wv[2];
         const Real Yuv = wu[0] * Hv0 + wu[1] * Hv1 + wu[2] * Hv2 + g[0] * wuv[0] + g[1] * wuv[1] + g[2] * wuv[2];
-        float* dst = Bt + (int64_t)k * rows_pad + row;
-        dst[0] = (float)val;
-        dst[1] = (float)(Yu * sN);
-        dst[2] = (float)(Yv * sN);
-        dst[3] = (float)(Yuv * sN2);
+        const float v4[4] = {(float)val, (float)(Yu * sN), (float)(Yv * sN), (float)(Yuv * sN2)};
+        for (int ch = 0; ch < 4; ++ch) Bt[basis_index(k, row + ch, Kp, rows_pad, frag)] = v4[ch];
     };
     const Real SQ2 = sqrt(Real(2));
     // complex powers (x + i y)^m = A_m + i B_m, sliding window m-2..m
@@ -151,20 +161,18 @@ __global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, float* __rest
         }
     }
     // zero padding rows of K (k = K .. Kp-1)
-    for (int k = (L + 1) * (L + 1); k < Kp; ++k) {
-        float* dst = Bt + (int64_t)k * rows_pad + row;
-        dst[0] = dst[1] = dst[2] = dst[3] = 0.0f;
-    }
+    for (int k = (L + 1) * (L + 1); k < Kp; ++k)
+        for (int ch = 0; ch < 4; ++ch) Bt[basis_index(k, row + ch, Kp, rows_pad, frag)] = 0.0f;
 }
 
 // zero the padding columns rows .. rows_pad-1 of every k
-__global__ void k_zero_cols(float* __restrict__ Bt, int Kp, int64_t rows, int64_t rows_pad)
+__global__ void k_zero_cols(float* __restrict__ Bt, int Kp, int64_t rows, int64_t rows_pad, int frag)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w = rows_pad - rows;
     if (i >= w * Kp) return;
     const int64_t k = i / w, c = i - k * w;
-    Bt[k * rows_pad + rows + c] = 0.0f;
+    Bt[basis_index((int)k, rows + c, Kp, rows_pad, frag)] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -235,6 +243,118 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
         }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident contraction for K <= 4 * G2_KS (SH order <= 8).
+// Work split: workgroup b runs on XCD b % 8 (round-robin dispatch), and XCD x
+// owns column chunk x of the basis table, so that chunk (~1/8 of the table)
+// stays in the XCD's L2.  Each wave owns 32 objects at a time: their
+// coefficients sit in registers as MFMA A fragments for the whole K; it then
+// walks the column tiles (32 columns) of its chunk, loading the B fragments
+// of the next tile while the 4 x KS MFMAs of the current one run, and
+// stores a 32 x 32 output tile per step.  No LDS, no barriers.
+// ---------------------------------------------------------------------------
+constexpr int G2_KS = 21;  // K steps of 4 held in registers (K <= 84)
+
+template <bool F16OUT>
+__device__ __forceinline__ void g2_tile(const float (&a)[2][G2_KS], const float (&b)[2][G2_KS], int ks, int64_t o0,
+                                        int64_t n_obj, int64_t col0, int64_t rows, int lm, int lk,
+                                        void* __restrict__ lut)
+{
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < G2_KS; ++s) {
+        if (s < ks) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int64_t col = col0 + 16 * j + lm;
+        if (col >= rows) continue;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t o = o0 + 16 * i + 4 * lk + e;
+                if (o >= n_obj) continue;
+                if constexpr (F16OUT)
+                    reinterpret_cast<__half*>(lut)[o * rows + col] = __float2half(acc[i][j][e]);
+                else
+                    reinterpret_cast<float*>(lut)[o * rows + col] = acc[i][j][e];
+            }
+    }
+}
+
+// B fragments of column tile t from the fragment-ordered table: b[j][s] at
+// Bf[t][s][j][lane], all offsets immediate from one base.
+__device__ __forceinline__ void g2_load_b(const float* __restrict__ Bf, int ks, int64_t t, int lane,
+                                          float (&b)[2][G2_KS])
+{
+    const float* base = Bf + t * (int64_t)ks * 128 + lane;
+#pragma unroll
+    for (int s = 0; s < G2_KS; ++s)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j][s] = (s < ks) ? base[s * 128 + j * 64] : 0.0f;
+}
+
+template <bool F16OUT>
+__global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__ C, int K, int64_t n_obj,
+                                                       const float* __restrict__ Bt, int ks, int64_t rows,
+                                                       int64_t rows_pad, void* __restrict__ lut, int waves_per_xcd,
+                                                       int n_sub)
+{
+    // XCD x owns column chunk x; the chunk is cut into n_sub sub-chunks and
+    // the work units (object group, sub-chunk) are dealt to the XCD's waves
+    const int lane = threadIdx.x & 63;
+    const int xcd = blockIdx.x & 7;
+    const int wave_in_xcd = (int)(blockIdx.x >> 3) * 4 + (int)(threadIdx.x >> 6);
+    const int64_t ntiles = rows_pad / 32;  // column tiles of 32
+    const int64_t per_chunk = (ntiles + 7) / 8;
+    const int64_t c_begin = xcd * per_chunk;
+    const int64_t c_end = (c_begin + per_chunk) < ntiles ? (c_begin + per_chunk) : ntiles;
+    const int64_t per_sub = (per_chunk + n_sub - 1) / n_sub;
+    const int64_t n_og = (n_obj + 31) / 32;
+    const int lm = lane & 15, lk = lane >> 4;
+    for (int64_t u = wave_in_xcd; u < n_og * n_sub; u += waves_per_xcd) {
+        const int64_t og = u / n_sub, sub = u - og * n_sub;
+        const int64_t t_begin = c_begin + sub * per_sub;
+        const int64_t t_end = (t_begin + per_sub) < c_end ? (t_begin + per_sub) : c_end;
+        if (t_begin >= t_end) continue;
+        const int64_t o0 = og * 32;
+        float a[2][G2_KS];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t o = o0 + 16 * i + lm;
+#pragma unroll
+            for (int s = 0; s < G2_KS; ++s) {
+                const int k = 4 * s + lk;
+                a[i][s] = (s < ks && o < n_obj && k < K) ? C[o * K + k] : 0.0f;
+            }
+        }
+        // ping-pong over two B buffers: the next tile loads while this one computes
+        float b0[2][G2_KS], b1[2][G2_KS];
+        int64_t t = t_begin;
+        g2_load_b(Bt, ks, t, lane, b0);
+        while (t < t_end) {
+            if (t + 1 < t_end) g2_load_b(Bt, ks, t + 1, lane, b1);
+            g2_tile<F16OUT>(a, b0, ks, o0, n_obj, t * 32, rows, lm, lk, lut);
+            ++t;
+            if (t >= t_end) break;
+            if (t + 1 < t_end) g2_load_b(Bt, ks, t + 1, lane, b0);
+            g2_tile<F16OUT>(a, b1, ks, o0, n_obj, t * 32, rows, lm, lk, lut);
+            ++t;
+        }
+    }
+}
+
 static inline int bake_kp(int L) { return (((L + 1) * (L + 1)) + 3) / 4 * 4; }
 static inline int64_t bake_rows(int N) { return texel_elems(N); }
 static inline int64_t bake_rows_pad(int N) { return (bake_rows(N) + GB_N - 1) / GB_N * GB_N; }
@@ -248,16 +368,41 @@ int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dty
     const int64_t rows = bake_rows(N), rows_pad = bake_rows_pad(N);
     float* Bt = reinterpret_cast<float*>(ws);
     const int ntex = 6 * (N + 2) * (N + 2);
+    const bool regs = Kp <= 4 * G2_KS;  // register-resident contraction (fragment-ordered table)
     // The table is evaluated in FP64 at every order (it is a vanishing part
     // of the bake's arithmetic) so that it adds nothing beyond its FP32
     // storage rounding: the tangential chain rule cancels the radial part of
     // the Cartesian polynomial's gradient, which grows with the SH order.
-    hipLaunchKernelGGL(k_sh_basis<double>, dim3((ntex + 127) / 128), dim3(128), 0, stream, L, N, Kp, rows_pad, Bt);
+    hipLaunchKernelGGL(k_sh_basis<double>, dim3((ntex + 127) / 128), dim3(128), 0, stream, L, N, Kp, rows_pad,
+                       regs ? 1 : 0, Bt);
     SHM_LAUNCH_CHECK();
     if (rows_pad > rows) {
         const int64_t n = (rows_pad - rows) * Kp;
-        hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, Bt, Kp, rows, rows_pad);
+        hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, Bt, Kp, rows, rows_pad,
+                           regs ? 1 : 0);
         SHM_LAUNCH_CHECK();
+    }
+    if (regs) {
+        // 8 XCDs x blocks_per_xcd workgroups of 4 waves, two workgroups per CU
+        const int n_cu = device_cu_count();
+        const int64_t n_og = (n_obj + 31) / 32;
+        int64_t per_xcd = (int64_t)(n_cu / 8) * 2;
+        if (per_xcd < 1) per_xcd = 1;
+        const int waves_per_xcd = (int)per_xcd * 4;
+        // enough (object group, column sub-chunk) units for every wave
+        const int64_t ntiles = rows_pad / 32, per_chunk = (ntiles + 7) / 8;
+        int64_t n_sub = (waves_per_xcd + n_og - 1) / n_og;
+        if (n_sub > per_chunk) n_sub = per_chunk;
+        if (n_sub < 1) n_sub = 1;
+        const dim3 grid((unsigned)(per_xcd * 8));
+        if (out_dtype == SHM_F16)
+            hipLaunchKernelGGL(k_bake_gemm2<true>, grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, Kp / 4, rows,
+                               rows_pad, lut, waves_per_xcd, (int)n_sub);
+        else
+            hipLaunchKernelGGL(k_bake_gemm2<false>, grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, Kp / 4, rows,
+                               rows_pad, lut, waves_per_xcd, (int)n_sub);
+        SHM_LAUNCH_CHECK();
+        return SHM_OK;
     }
     const int64_t gy = (n_obj + GB_M - 1) / GB_M;
     const int64_t gx = rows_pad / GB_N;

@@ -16,7 +16,36 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Cache policy of the footprint loads: each cell is touched by one query,
+// so the loads can bypass the caches' retention (non-temporal).
+#ifndef SHM_LUT_NT
+#define SHM_LUT_NT 0
+#endif
+
 namespace shm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 ld_f4(const float4* p)
+{
+#if SHM_LUT_NT
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+#else
+    return *p;
+#endif
+}
+
+__device__ __forceinline__ uint4 ld_u4(const uint4* p)
+{
+#if SHM_LUT_NT
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+#else
+    return *p;
+#endif
+}
 
 struct Loc {
     int face;     // 0..5 = +X, -X, +Y, -Y, +Z, -Z; -1 = invalid direction
@@ -139,10 +168,10 @@ __device__ __forceinline__ Foot load_cell_f32(const float* __restrict__ lut, int
     const int64_t cell = (int64_t)(L.face * C + L.j0) * C + L.i0;
     const float4* p = reinterpret_cast<const float4*>(lut + cell * 16);
     Foot F;
-    F.c[0] = *(p);
-    F.c[1] = *(p + 1);
-    F.c[2] = *(p + 2);
-    F.c[3] = *(p + 3);
+    F.c[0] = ld_f4(p);
+    F.c[1] = ld_f4(p + 1);
+    F.c[2] = ld_f4(p + 2);
+    F.c[3] = ld_f4(p + 3);
     return F;
 }
 
@@ -151,8 +180,8 @@ __device__ __forceinline__ Foot load_cell_f16(const __half* __restrict__ lut, in
     const int C = N + 1;
     const int64_t cell = (int64_t)(L.face * C + L.j0) * C + L.i0;
     const uint4* p = reinterpret_cast<const uint4*>(lut + cell * 16);
-    const uint4 q0 = *(p);
-    const uint4 q1 = *(p + 1);
+    const uint4 q0 = ld_u4(p);
+    const uint4 q1 = ld_u4(p + 1);
     Foot F;
     F.c[0] = h4_to_f4(make_uint2(q0.x, q0.y));
     F.c[1] = h4_to_f4(make_uint2(q0.z, q0.w));

@@ -52,5 +52,9 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
                             const WorkItem* items_dev, int64_t n_items, const shm_launch_shape& shape, int n_cu,
                             const float* dirs, float* out, float* normal, hipStream_t stream);
 int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* cells, hipStream_t stream);
+int launch_query_baseline(const float* vlut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, int method,
+                          float* out, hipStream_t stream);
+int launch_sh_eval(const float* coeffs, int L, int64_t n_obj, const float* dirs, int64_t q_per_obj, float* out,
+                   hipStream_t stream);
 
 }  // namespace shm

@@ -119,3 +119,21 @@ def test_autograd_function_and_fd():
         fd = (np.sum(oracle.query(lp, dirs) * w) - np.sum(oracle.query(lm, dirs) * w)) / (2 * eps)
         assert abs(fd - gl[idx]) <= 1e-4 * max(1.0, abs(fd)), (idx, fd, gl[idx])
     assert d_t.grad is not None and torch.isfinite(d_t.grad).all()
+
+
+@pytest.mark.parametrize("N", [100, 512])
+def test_backward_three_radix_passes(N):
+    """Cell keys above 2^16 take three 8-bit radix passes (N >= 105 for one
+    object); N = 100 takes two."""
+    r = rng(10 + N)
+    lut = workloads.random_lut(N, r)
+    Q = 30000
+    dirs = workloads.uniform_dirs(Q, r)
+    g = r.standard_normal((Q, 4)).astype(np.float32)
+    gl, gd = run_bwd(lut, dirs, g)
+    rl, rd = oracle.backward(lut, dirs, g)
+    scale = np.abs(rl).max()
+    assert np.abs(gl - rl).max() / scale < 1e-4
+    gn = np.linalg.norm(rd, axis=1)
+    floor = np.sqrt(np.mean(gn ** 2))
+    assert (np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3

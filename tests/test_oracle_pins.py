@@ -675,3 +675,97 @@ def test_bumps_truth_and_bake_against_independent_evaluation():
         assert abs(ch[2] - (G(u, v + hh) - G(u, v - hh)) / (2 * hh) / N) < 1e-7
         guv = (G(u + hh, v + hh) - G(u + hh, v - hh) - G(u - hh, v + hh) + G(u - hh, v - hh)) / (4 * hh * hh)
         assert abs(ch[3] - guv / N ** 2) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Comparison reconstructions (Sec. 4.2 Table psnr_value, Sec. 4.4 Table
+# cost_extended): nearest, bilinear + finite-difference normals, Catmull-Rom
+# ---------------------------------------------------------------------------
+def value_lut(N, fn):
+    """Value-only LUT [6, N+4, N+4] of fn(face, u, v), texel p at u=(p-3/2)/N."""
+    p = (np.arange(N + 4) - 1.5) / N
+    U, V = np.meshgrid(p, p, indexing="xy")
+    return np.stack([fn(f, U, V) for f in range(6)])
+
+
+def check_chart_grad(out, d, f, pu, pv, tol):
+    """out's gradient against chart derivatives (pu, pv): grad . e1 = pu and
+    grad . e2 = pv, with e1, e2 from finite differences of the chart map."""
+    ff, u, v = face_uv(d.astype(np.float64))
+    h = 1e-6
+    for k in range(len(d)):
+        e1 = (chart_dir(ff[k], u[k] + h, v[k]) - chart_dir(ff[k], u[k] - h, v[k])) / (2 * h)
+        e2 = (chart_dir(ff[k], u[k], v[k] + h) - chart_dir(ff[k], u[k], v[k] - h)) / (2 * h)
+        assert abs(out[k, 1:] @ e1 - pu[k]) < tol and abs(out[k, 1:] @ e2 - pv[k]) < tol
+
+
+def test_bilinear_fd_reproduces_bilinear_functions():
+    N = 9
+    r = rng(60)
+    C = r.standard_normal((6, 4))
+    vl = value_lut(N, lambda f, U, V: C[f, 0] + C[f, 1] * U + C[f, 2] * V + C[f, 3] * U * V)
+    d = workloads.uniform_dirs(400, r)
+    out = oracle.baseline_query(vl, d, oracle.BASELINE_BILINEAR_FD)
+    f, u, v = face_uv(d.astype(np.float64))
+    np.testing.assert_allclose(out[:, 0], C[f, 0] + C[f, 1] * u + C[f, 2] * v + C[f, 3] * u * v, atol=1e-12)
+    check_chart_grad(out, d, f, C[f, 1] + C[f, 3] * v, C[f, 2] + C[f, 3] * u, 1e-6)
+
+
+def test_catmull_rom_reproduces_biquadratics():
+    N = 7
+    r = rng(61)
+    C = r.standard_normal((6, 3, 3))
+    def P(f, U, V, du=0, dv=0):
+        out = 0.0
+        for a in range(3):
+            for b in range(3):
+                ca = (a if du else 1) * (U ** (a - du) if a >= du else 0)
+                cb = (b if dv else 1) * (V ** (b - dv) if b >= dv else 0)
+                out = out + C[f, a, b] * ca * cb
+        return out
+    vl = value_lut(N, lambda f, U, V: P(f, U, V))
+    d = workloads.uniform_dirs(400, r)
+    out = oracle.baseline_query(vl, d, oracle.BASELINE_BICUBIC)
+    f, u, v = face_uv(d.astype(np.float64))
+    np.testing.assert_allclose(out[:, 0], [P(ff, uu, vv) for ff, uu, vv in zip(f, u, v)], atol=1e-12)
+    check_chart_grad(out, d, f, [P(ff, uu, vv, du=1) for ff, uu, vv in zip(f, u, v)],
+                     [P(ff, uu, vv, dv=1) for ff, uu, vv in zip(f, u, v)], 1e-6)
+
+
+def test_nearest_returns_texel_values():
+    N = 6
+    r = rng(62)
+    vl = r.standard_normal((6, N + 4, N + 4))
+    d = workloads.uniform_dirs(300, r)
+    out = oracle.baseline_query(vl, d, oracle.BASELINE_NEAREST)
+    f, u, v = face_uv(d.astype(np.float64))
+    p = np.floor(u * N + 1.5 + 0.5).astype(int)
+    q = np.floor(v * N + 1.5 + 0.5).astype(int)
+    np.testing.assert_array_equal(out[:, 0], vl[f, q, p])
+    assert np.all(out[:, 1:] == 0)
+
+
+def test_value_psnr_ordering_matches_table_psnr_value():
+    """Table psnr_value: Hermite > Catmull-Rom bicubic > bilinear at every N,
+    with gains per doubling of roughly +12 dB (bilinear), +22 dB (bicubic),
+    +30 dB (Hermite) between N = 8, 16, 32."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(63))[0]
+    d = workloads.uniform_dirs(30000, rng(64))
+    truth = oracle.sh_truth(c, d.astype(np.float64))[:, 0]
+    peak = truth.max() - truth.min()
+    psnr = {}
+    for N in (8, 16, 32):
+        vl = oracle.sh_truth(c, oracle.margin_dirs(N).reshape(-1, 3))[:, 0].reshape(6, N + 4, N + 4)
+        for name, m in (("bilinear", oracle.BASELINE_BILINEAR_FD), ("bicubic", oracle.BASELINE_BICUBIC)):
+            e = oracle.baseline_query(vl, d, m)[:, 0] - truth
+            psnr[(name, N)] = 20 * math.log10(peak / np.sqrt(np.mean(e ** 2)))
+        e = oracle.query(oracle.bake_sh(c, N), d)[:, 0] - truth
+        psnr[("hermite", N)] = 20 * math.log10(peak / np.sqrt(np.mean(e ** 2)))
+    paper = {int(row[0]): row[1:] for row in load_golden("psnr_value_table.txt")}
+    for N in (8, 16, 32):
+        assert psnr[("hermite", N)] > psnr[("bicubic", N)] > psnr[("bilinear", N)], (N, psnr)
+        assert paper[N][2] > paper[N][1] > paper[N][0]
+    gains = {m: psnr[(m, 32)] - psnr[(m, 16)] for m in ("bilinear", "bicubic", "hermite")}
+    assert 9 < gains["bilinear"] < 15, gains      # second order: ~12 dB
+    assert 15 < gains["bicubic"] < 27, gains      # paper: 21.5 dB
+    assert gains["hermite"] > gains["bicubic"]
