@@ -140,7 +140,7 @@ def main():
 
     if args.counters:
         # three launches of the query, then a plain copy of known size for
-        # the counter calibration
+        # the counter calibration, then one bake and one backward pass
         for _ in range(3):
             step()
         src = torch.empty(1 << 28, dtype=torch.float32, device=DEV).fill_(1.0)  # 1 GiB
@@ -149,7 +149,16 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"counters_run": True, "query_launches": 3, "copy_bytes": src.numel() * 4}))
+        del src, dst
+        shm.bake_sh(c_t, N)
+        Nb, Qb = 512, 1 << 22
+        d4 = to_dev(workloads.uniform_dirs(Qb, workloads.rng_for(4)))
+        d4 = d4[torch.argsort(shm.cell_keys(Nb, d4).to(torch.int64) & 0xFFFFFFFF, stable=True)].contiguous()
+        lut4 = torch.zeros((1, 6, Nb + 2, Nb + 2, 4), device=DEV)
+        bctx = shm.BackwardContext(Nb, 1, d4, Qb)
+        bctx.backward(lut4, torch.ones((Qb, 4), device=DEV))
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "query_launches": 3, "copy_bytes": 1 << 30}))
         return
 
     # ---------------- headline timing
@@ -227,6 +236,8 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
 
     forms["comparison"] = run_comparison(c_t, dirs_t, ms_cell, forms["query_f32_texel"]["ms"])
     log("comparison", forms["comparison"])
+    forms["mip_lod"] = run_mip_lod()
+    log("mip", forms["mip_lod"])
     forms["backward_fit"] = run_backward_fit()
     log("backward", forms["backward_fit"])
     forms["batched"], sample["batched"] = run_batched()
@@ -238,8 +249,8 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
 
 def run_comparison(c_t, dirs_t, ms_hermite_cell, ms_hermite_texel):
     """The paper's comparison paths on the glyph-field shape (Table runtime):
-    nearest, bilinear + FD normals, 16-tap Catmull-Rom bicubic from value-only
-    LUTs [glyphs, 6, N+4, N+4] FP32, and direct SH evaluation without a LUT.
+    nearest, bilinear + FD normals, 16-tap Catmull-Rom bicubic, fast bicubic
+    (cubic B-spline as 4 bilinear lookups) + FD normals from value-only LUTs [glyphs, 6, N+4, N+4] FP32, and direct SH evaluation without a LUT.
     The value-only LUT contents are random (the access pattern, not the
     values, sets the cost); accuracy is checked by the tests."""
     N, n_glyph, q_per = W2["N"], W2["n_glyph"], W2["q_per"]
@@ -249,7 +260,8 @@ def run_comparison(c_t, dirs_t, ms_hermite_cell, ms_hermite_texel):
     out = torch.empty((Q, 4), device=DEV)
     res = {"hermite_cell_ms": ms_hermite_cell, "hermite_texel_ms": ms_hermite_texel}
     for name, m in (("nearest", shm.SHM_RECON_NEAREST), ("bilinear_fd", shm.SHM_RECON_BILINEAR_FD),
-                    ("bicubic_catmull_rom", shm.SHM_RECON_BICUBIC)):
+                    ("bicubic_catmull_rom", shm.SHM_RECON_BICUBIC),
+                    ("fast_bicubic_fd", shm.SHM_RECON_FAST_BICUBIC_FD)):
         shm.shm_query_baseline(vlut, N, n_glyph, dirs_t, q_per, m, out)
         res[name + "_ms"] = t_gpu(lambda: shm.shm_query_baseline(vlut, N, n_glyph, dirs_t, q_per, m, out), 10)
     shm.shm_sh_eval(c_t, W2["L"], n_glyph, dirs_t, q_per, out)
@@ -257,6 +269,38 @@ def run_comparison(c_t, dirs_t, ms_hermite_cell, ms_hermite_texel):
     res["hermite_cell_speedup_vs_bicubic"] = res["bicubic_catmull_rom_ms"] / ms_hermite_cell
     res["hermite_texel_speedup_vs_bicubic"] = res["bicubic_catmull_rom_ms"] / ms_hermite_texel
     res["queries"] = Q
+    return res
+
+
+def run_mip_lod():
+    """Table lod on the GPU: one SH glyph (L = 8) baked at N = 32, three mip
+    levels built derivative-consistently and naively, mean / 95th percentile
+    normal error (degrees) against the direct SH normals at 100,000 uniform
+    directions."""
+    r = workloads.rng_for(2)
+    c = to_dev(workloads.sh_glyph_coeffs(8, 1, r).astype(np.float32))
+    d = to_dev(workloads.uniform_dirs(100000, r))
+    w = d / d.norm(dim=1, keepdim=True)
+
+    def normals(o):
+        n = o[:, :1] * w - o[:, 1:]
+        return n / n.norm(dim=1, keepdim=True)
+
+    tn = normals(shm.sh_eval(c, d))
+
+    def err(lut):
+        a = torch.rad2deg(torch.acos(torch.clamp((normals(shm.query(lut, d)) * tn).sum(dim=1), -1, 1)))
+        return a.mean().item(), torch.quantile(a, 0.95).item()
+
+    cons = naive = shm.bake_sh(c, 32)[0]
+    res = {"level0_N32": dict(zip(("mean_deg", "p95_deg"), err(cons)))}
+    for lev in (1, 2, 3):
+        cons, naive = shm.mip_level(cons), shm.mip_level(naive, naive=True)
+        ec, en = err(cons), err(naive)
+        res[f"level{lev}_N{32 >> lev}"] = {"consistent_mean_deg": ec[0], "consistent_p95_deg": ec[1],
+                                           "naive_mean_deg": en[0], "naive_p95_deg": en[1], "ratio": en[0] / ec[0]}
+    lut = shm.bake_sh(c, 32)[0]
+    res["mip_level_32_to_16_us"] = t_gpu(lambda: shm.mip_level(lut), 10) * 1e3
     return res
 
 

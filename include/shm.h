@@ -188,11 +188,12 @@ SHM_API int shm_plan_destroy(shm_plan* plan);
  * as in shm_query_value_grad.  With upstream grad_out[q] = dL/d(R, g):
  *   grad_lut   dL/dLUT, FP32, same shape as lut, overwritten (or NULL)
  *   grad_dirs  dL/d dirs [Q][3] (or NULL); the outputs are 0-homogeneous
- *              in d, so grad_dirs[q] . dirs[q] = 0
+ *              in d, so grad_dirs[q] . dirs[q] = 0; NaN for an invalid
+ *              direction (zero, NaN or Inf component)
  * grad_lut is deterministic: queries are sorted by cell once (stable: by
- * cell, then by query index) and every texel pulls the contributions of the
- * queries of its <= 4 adjacent cells in that fixed order; no floating-point
- * atomics.  shm_backward_sort builds the sort in the workspace; it stays
+ * cell, then by query index); each cell sums its queries' contributions in
+ * that order and every texel adds the sums of its <= 4 adjacent cells in a
+ * fixed order; no floating-point atomics.  shm_backward_sort builds the sort in the workspace; it stays
  * valid while dirs (and N, n_obj, q_per_obj) are unchanged, so a fitting
  * loop sorts once and passes sort_ready = 1 afterwards.
  * ---------------------------------------------------------------------- */
@@ -200,8 +201,8 @@ SHM_API size_t shm_backward_workspace(int32_t N, int64_t n_obj, int64_t q_per_ob
 /* Cell key of every query: ((obj*6 + face)*(N+1) + j0)*(N+1) + i0, or
  * 0xFFFFFFFF for an invalid direction.  keys [n_obj*q_per_obj] uint32.
  * A caller whose directions stay fixed (a fitting loop) can reorder its
- * queries once by (key, index); the backward's per-query pass is then
- * coalesced. */
+ * queries once by (key, index); the backward's reads of dirs and
+ * grad_out are then coalesced. */
 SHM_API int shm_cell_keys(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream);
 SHM_API int shm_backward_sort(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, size_t ws_bytes,
                       hipStream_t stream);
@@ -234,6 +235,25 @@ SHM_API int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const fl
 SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Mip chain (Sec. 4.7, Table lod): the next level (face size N/2, N even) of
+ * one FP32 TEXEL LUT.
+ *   mode 0 (consistent): the value field is box-filtered -- every coarse
+ *     sample is the mean of the level-N map at the four fine texel-centre
+ *     directions the coarse texel covers, evaluated as queries (points
+ *     beyond the face read the neighbouring face) -- on the coarse padded
+ *     grid plus a margin ring, and the derivative channels are recomputed
+ *     from the filtered values by central differences (as shm_bake_fd);
+ *   mode 1 (naive): as mode 0, but every interior coarse texel holds the
+ *     plain average of the four fine texels' stored channels, as a
+ *     box-filtering mip generator would.
+ *   lut [6][N+2][N+2][4] -> out [6][N/2+2][N/2+2][4]; ws of
+ *   shm_mip_level_workspace(N) bytes (the filtered samples).
+ * ---------------------------------------------------------------------- */
+SHM_API size_t shm_mip_level_workspace(int32_t N);
+SHM_API int shm_mip_level(const float* lut, int32_t N, int32_t mode, void* ws, size_t ws_bytes, float* out,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Comparison paths of the paper's experiments (Sec. 4.2, 4.4, 4.5; Tables
  * psnr_value, cost_extended, runtime), on the same GPU as the Hermite query.
  * shm_query_baseline reconstructs from a value-only LUT
@@ -244,13 +264,22 @@ SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_
  *                          differences of 4 more bilinear lookups at u +- h,
  *                          v +- h (5 x 4 = 20 fetches)
  *   SHM_RECON_BICUBIC      16-tap Catmull-Rom value and analytic gradient
+ *   SHM_RECON_FAST_BICUBIC_FD  "fast bicubic" (Table cost_extended): the
+ *                          cubic B-spline of the samples evaluated as 4
+ *                          bilinear lookups (FP32 weights), gradient as in
+ *                          SHM_RECON_BILINEAR_FD (4 + 4 lookups)
  * then transports (r_u, r_v) to the spherical gradient as the Hermite query
  * does.  shm_sh_eval evaluates sum_k coeffs[k] Y_k and its spherical
  * gradient directly, without a LUT (coeffs [n_obj][(L+1)^2], L <= 16).
  * Both write out [n_obj*q_per_obj][4] = (R, gx, gy, gz); NaN for invalid
  * directions.
  * ---------------------------------------------------------------------- */
-typedef enum { SHM_RECON_NEAREST = 0, SHM_RECON_BILINEAR_FD = 1, SHM_RECON_BICUBIC = 2 } shm_recon;
+typedef enum {
+    SHM_RECON_NEAREST = 0,
+    SHM_RECON_BILINEAR_FD = 1,
+    SHM_RECON_BICUBIC = 2,
+    SHM_RECON_FAST_BICUBIC_FD = 3
+} shm_recon;
 SHM_API int shm_query_baseline(const float* vlut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
                                int32_t method, float* out, hipStream_t stream);
 SHM_API int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs, int64_t q_per_obj,

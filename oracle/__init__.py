@@ -254,12 +254,13 @@ def backward(lut, dirs, grad_out, want_lut=True, want_dirs=True):
     return gl, gd
 
 
-def rmax_bound(lut):
-    """Bernstein (convex hull) upper bound of the reconstruction over all cells."""
+def rmax_bound(lut, absval=False):
+    """Bernstein (convex hull) upper bound of the reconstruction over all
+    cells (of its absolute value with absval, for signed functions)."""
     lut = _f64(lut)
     N = lut.shape[1] - 2
     lib().orc_rmax_bound.restype = ctypes.c_double
-    return float(lib().orc_rmax_bound(_p(lut), ctypes.c_int(N)))
+    return float(lib().orc_rmax_bound(_p(lut), ctypes.c_int(N), ctypes.c_int(1 if absval else 0)))
 
 
 def cell_bezier(lut, face, i0, j0):
@@ -287,6 +288,54 @@ def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3):
     return t, out, nrm
 
 
+def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px=0.0, eps_px=0.125, n_march=20,
+             n_bisect=16, n_newton=3):
+    """Ray casting of the rendered radius R = scale r (scale |r| if signed)
+    with the adaptive bisection budget (px = focal length in pixels; 0 for
+    the fixed count n_bisect).  rmax bounds R; centre and rmax are taken as
+    FP32.  Returns t, (R, grad) [P, 4], normal [P, 3], sign of r [P] int8,
+    F evaluations [P] int32."""
+    lut = _f64(lut)
+    N = lut.shape[1] - 2
+    o = _f32(ray_o).reshape(-1, 3)
+    d = _f32(ray_d).reshape(-1, 3)
+    P = o.shape[0]
+    c = _f32(center).reshape(3)
+    t = np.empty(P)
+    out = np.empty((P, 4))
+    nrm = np.empty((P, 3))
+    sgn = np.empty(P, dtype=np.int8)
+    ev = np.empty(P, dtype=np.int32)
+    lib().orc_trace_ex(_p(lut), ctypes.c_int(N), _p(c), ctypes.c_float(rmax), ctypes.c_double(scale),
+                       ctypes.c_int(1 if signed else 0), ctypes.c_float(px), ctypes.c_float(eps_px), _p(o), _p(d),
+                       ctypes.c_int64(P), ctypes.c_int(n_march), ctypes.c_int(n_bisect), ctypes.c_int(n_newton), _p(t),
+                       _p(out), _p(nrm), _p(sgn), _p(ev))
+    return t, out, nrm, sgn, ev
+
+
+def bisect_budget(o, center, rmax, px, eps_px, n_march, n_bisect):
+    """The trace's per-ray bisection count (FP32 decision)."""
+    o = _f32(o).reshape(3)
+    c = _f32(center).reshape(3)
+    return int(lib().orc_bisect_budget(_p(o), _p(c), ctypes.c_float(rmax), ctypes.c_float(px), ctypes.c_float(eps_px),
+                                       ctypes.c_int(n_march), ctypes.c_int(n_bisect)))
+
+
+def query_scaled(lut, dirs, scale=1.0, signed=False):
+    """Rendered radius R = scale r (scale |r| if signed, gradient
+    scale sign(r) grad r): (R, grad) [Q, 4], normal [Q, 3], sign [Q] int8."""
+    lut = _f64(lut)
+    N = lut.shape[1] - 2
+    d = _f32(dirs).reshape(-1, 3)
+    Q = d.shape[0]
+    out = np.empty((Q, 4))
+    nrm = np.empty((Q, 3))
+    sgn = np.empty(Q, dtype=np.int8)
+    lib().orc_query_scaled(_p(lut), ctypes.c_int(N), _p(d), ctypes.c_int64(Q), ctypes.c_double(scale),
+                           ctypes.c_int(1 if signed else 0), _p(out), _p(nrm), _p(sgn))
+    return out, nrm, sgn
+
+
 def trace_F(lut, center, o, d, ts):
     lut = _f64(lut)
     N = lut.shape[1] - 2
@@ -297,16 +346,29 @@ def trace_F(lut, center, o, d, ts):
     return F
 
 
-BASELINE_NEAREST, BASELINE_BILINEAR_FD, BASELINE_BICUBIC = 0, 1, 2
+BASELINE_NEAREST, BASELINE_BILINEAR_FD, BASELINE_BICUBIC, BASELINE_FAST_BICUBIC_FD = 0, 1, 2, 3
 
 
 def baseline_query(vlut, dirs, method):
     """Comparison reconstructions on a value-only LUT [6, N+4, N+4] (texel p
     at u = (p - 3/2)/N): 0 nearest, 1 bilinear + finite-difference
-    gradient, 2 Catmull-Rom bicubic + analytic gradient.  (R, grad) [Q, 4]."""
+    gradient, 2 Catmull-Rom bicubic + analytic gradient, 3 cubic B-spline
+    ("fast bicubic") + the finite-difference gradient of 1.  (R, grad) [Q, 4]."""
     v = _f64(vlut)
     N = v.shape[-1] - 4
     d = _f32(dirs).reshape(-1, 3)
     out = np.empty((d.shape[0], 4))
     lib().orc_baseline_query(_p(v), ctypes.c_int(N), _p(d), ctypes.c_int64(d.shape[0]), ctypes.c_int(method), _p(out))
+    return out
+
+
+def mip_level(lut, naive=False):
+    """Next mip level (N -> N/2) of a TEXEL LUT: derivative-consistent
+    (filtered values, derivatives by central differences) or naive (box
+    filter of all four stored channels of interior texels)."""
+    lut = _f64(lut)
+    N = lut.shape[1] - 2
+    assert N % 2 == 0
+    out = np.empty(lut_shape(N // 2))
+    lib().orc_mip_level(_p(lut), ctypes.c_int(N), ctypes.c_int(1 if naive else 0), _p(out))
     return out

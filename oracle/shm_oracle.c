@@ -396,6 +396,45 @@ ORC_API void orc_query(const double* lut, int N, const float* dirs, int64_t Q, i
     }
 }
 
+/* Rendered radius of Sec. 3.1 for a user scale s > 0: R = s r for a
+ * nonnegative function; for a signed one R = s |r|, whose gradient is
+ * s sign(r) grad r by the chain rule of the absolute value (Sec. 3.4, after
+ * Eq. 10), with sign(0) = 0.  The normal is Eq. 10 with these R, grad R. */
+static double rendered(double r, const double gr[3], double s, int signed_, double g[3], int* sgn)
+{
+    int sg = r > 0.0 ? 1 : (r < 0.0 ? -1 : 0);
+    double k = signed_ ? s * sg : s;
+    for (int i = 0; i < 3; ++i) g[i] = k * gr[i];
+    if (sgn) *sgn = sg;
+    return signed_ ? s * fabs(r) : s * r;
+}
+
+/* Query of the rendered radius: out (R, grad R), normal (Eq. 10), and the
+ * sign of r (+1, -1, 0; 0 also for an invalid direction). */
+ORC_API void orc_query_scaled(const double* lut, int N, const float* dirs, int64_t Q, double scale, int signed_,
+                              double* out, double* normal, int8_t* sign)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        double d[3] = {dirs[3 * q], dirs[3 * q + 1], dirs[3 * q + 2]};
+        query_t QR;
+        if (!query_hd(lut, N, d, NULL, 1, &QR)) {
+            for (int k = 0; k < 4; ++k) out[4 * q + k] = NAN;
+            if (normal) for (int k = 0; k < 3; ++k) normal[3 * q + k] = NAN;
+            if (sign) sign[q] = 0;
+            continue;
+        }
+        double gr[3], g[3], w[3];
+        int sg;
+        for (int k = 0; k < 3; ++k) { gr[k] = QR.T.grad[k].v; w[k] = QR.T.w[k].v; }
+        double R = rendered(QR.R.v, gr, scale, signed_, g, &sg);
+        out[4 * q] = R;
+        for (int k = 0; k < 3; ++k) out[4 * q + 1 + k] = g[k];
+        if (normal) normal_of(R, w, g, normal + 3 * q);
+        if (sign) sign[q] = (int8_t)sg;
+    }
+}
+
 /* FP64 directions, FP64 cell decision (finite-difference pins, truth-level
  * comparisons).  face_forced < 0: own face; else evaluate on that face. */
 ORC_API void orc_query_f64(const double* lut, int N, const double* dirs, int64_t Q, int face_forced, double* out)
@@ -776,7 +815,9 @@ ORC_API void orc_cell_bezier(const double* lut, int N, int face, int i0, int j0,
         for (int b = 0; b < 4; ++b) out16[4 * a + b] = Bz[a][b];
 }
 
-ORC_API double orc_rmax_bound(const double* lut, int N)
+/* Largest Bezier control point of any cell (absval: largest |control
+ * point|, which bounds |r|, the radius of a signed function). */
+ORC_API double orc_rmax_bound(const double* lut, int N, int absval)
 {
     double best = -INFINITY;
     for (int face = 0; face < 6; ++face)
@@ -785,8 +826,10 @@ ORC_API double orc_rmax_bound(const double* lut, int N)
                 double Bz[4][4];
                 cell_bezier(lut, N, face, i0, j0, Bz);
                 for (int a = 0; a < 4; ++a)
-                    for (int b = 0; b < 4; ++b)
-                        if (Bz[a][b] > best) best = Bz[a][b];
+                    for (int b = 0; b < 4; ++b) {
+                        double v = absval ? fabs(Bz[a][b]) : Bz[a][b];
+                        if (v > best) best = v;
+                    }
             }
     return best;
 }
@@ -805,30 +848,65 @@ ORC_API double orc_rmax_bound(const double* lut, int N)
  *      takes t - F/F' if it lies in the closed bracket, else the bracket
  *      midpoint
  *   5. one last evaluation at the final t gives R, grad R and the normal
- * Outputs: t (+inf for a miss), out4 = (R, grad) and normal3 (NaN on a miss). */
-typedef struct { double F, dF, R, g[3], w[3]; int ok; } feval_t;
+ * Outputs: t (+inf for a miss), out4 = (R, grad) and normal3 (NaN on a miss).
+ * R is the rendered radius (scale s, optionally signed: R = s |r|). */
+typedef struct { double F, dF, R, g[3], w[3]; int ok, sgn; } feval_t;
 
-static feval_t trace_eval(const double* lut, int N, const double o[3], const double c[3], const double dn[3], double t)
+static feval_t trace_eval(const double* lut, int N, const double o[3], const double c[3], const double dn[3], double t,
+                          double scale, int signed_)
 {
     feval_t E;
     double p[3];
     for (int k = 0; k < 3; ++k) p[k] = o[k] + t * dn[k] - c[k];
     query_t QR;
     E.ok = query_hd(lut, N, p, NULL, 0, &QR);
-    if (!E.ok) { E.F = NAN; E.dF = NAN; return E; }
-    double len = sqrt(dot3(p, p));
-    E.R = QR.R.v;
-    for (int k = 0; k < 3; ++k) { E.g[k] = QR.T.grad[k].v; E.w[k] = p[k] / len; }
+    if (!E.ok) { E.F = NAN; E.dF = NAN; E.sgn = 0; return E; }
+    double len = sqrt(dot3(p, p)), gr[3];
+    for (int k = 0; k < 3; ++k) { gr[k] = QR.T.grad[k].v; E.w[k] = p[k] / len; }
+    E.R = rendered(QR.R.v, gr, scale, signed_, E.g, &E.sgn);
     E.F = len - E.R;
     E.dF = dot3(dn, E.w) - dot3(dn, E.g) / len;
     return E;
 }
 
-ORC_API void orc_trace(const double* lut, int N, const double* center, double rmax, const float* ray_o, const float* ray_d,
-                       int64_t P, int n_march, int n_bisect, int n_newton, double* t_out, double* out4, double* normal3)
+/* Bisection budget of a ray (Sec. 3.1: more refinement for glyphs that
+ * project larger, the projected size estimated from the bounding radius and
+ * the depth).  The march bracket is at most 2 rmax / n_march long; at the
+ * distance |o - c| it spans e = 2 rmax px / (|o - c| n_march) pixels, px
+ * being the focal length in pixels.  Bisect until e <= eps_px, at most
+ * n_bisect times.  The decision is taken in FP32 in this fixed order
+ * (halving is exact), so any implementation of it picks the same count;
+ * px <= 0 means the fixed count n_bisect. */
+static int bisect_budget(const float o[3], const float c[3], float rmax, float px, float eps_px, int n_march, int n_bisect)
 {
+    if (!(px > 0.0f)) return n_bisect;
+    float ox = o[0] - c[0], oy = o[1] - c[1], oz = o[2] - c[2];
+    float dd = ox * ox + oy * oy + oz * oz;
+    float depth = sqrtf(dd);
+    float e = (2.0f * rmax * px) / (depth * (float)n_march);
+    int k = 0;
+    while (k < n_bisect && e > eps_px) { e *= 0.5f; ++k; }
+    return k;
+}
+
+ORC_API int orc_bisect_budget(const float* o, const float* c, float rmax, float px, float eps_px, int n_march, int n_bisect)
+{
+    return bisect_budget(o, c, rmax, px, eps_px, n_march, n_bisect);
+}
+
+/* Full form: scale, signed, adaptive budget (px > 0; the FP32 centre and
+ * rmax decide the budget), per-ray sign of r at the hit (0 on a miss) and
+ * number of F evaluations.  orc_trace is the plain form. */
+ORC_API void orc_trace_ex(const double* lut, int N, const float* center_f, float rmax_f, double scale, int signed_,
+                          float px, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int n_march,
+                          int n_bisect, int n_newton, double* t_out, double* out4, double* normal3, int8_t* sign,
+                          int32_t* evals)
+{
+    const double center[3] = {center_f[0], center_f[1], center_f[2]}, rmax = rmax_f;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < P; ++r) {
+        const int nb = bisect_budget(ray_o + 3 * r, center_f, rmax_f, px, eps_px, n_march, n_bisect);
+        int ne = 0;
         double o[3] = {ray_o[3 * r], ray_o[3 * r + 1], ray_o[3 * r + 2]};
         double d[3] = {ray_d[3 * r], ray_d[3 * r + 1], ray_d[3 * r + 2]};
         double dl = sqrt(dot3(d, d));
@@ -846,18 +924,21 @@ ORC_API void orc_trace(const double* lut, int N, const double* center, double rm
                 double lo = t0, hi = t0;
                 for (int k = 1; k <= n_march; ++k) {
                     double tk = t0 + (double)k * (t1 - t0) / (double)n_march;
-                    feval_t E = trace_eval(lut, N, o, center, dn, tk);
+                    feval_t E = trace_eval(lut, N, o, center, dn, tk, scale, signed_);
+                    ++ne;
                     if (E.ok && E.F < 0.0) { hit = 1; lo = t0 + (double)(k - 1) * (t1 - t0) / (double)n_march; hi = tk; break; }
                 }
                 if (hit) {
-                    for (int it = 0; it < n_bisect; ++it) {
+                    for (int it = 0; it < nb; ++it) {
                         double mid = 0.5 * (lo + hi);
-                        feval_t E = trace_eval(lut, N, o, center, dn, mid);
+                        feval_t E = trace_eval(lut, N, o, center, dn, mid, scale, signed_);
+                        ++ne;
                         if (E.F < 0.0) hi = mid; else lo = mid;
                     }
                     t = 0.5 * (lo + hi);
                     for (int it = 0; it < n_newton; ++it) {
-                        feval_t E = trace_eval(lut, N, o, center, dn, t);
+                        feval_t E = trace_eval(lut, N, o, center, dn, t, scale, signed_);
+                        ++ne;
                         if (E.F < 0.0) hi = t; else lo = t;
                         double tn = t - E.F / E.dF;
                         if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
@@ -868,15 +949,27 @@ ORC_API void orc_trace(const double* lut, int N, const double* center, double rm
         }
         t_out[r] = hit ? t : INFINITY;
         if (hit) {
-            feval_t E = trace_eval(lut, N, o, center, dn, t);
+            feval_t E = trace_eval(lut, N, o, center, dn, t, scale, signed_);
+            ++ne;
             out4[4 * r] = E.R;
             for (int k = 0; k < 3; ++k) out4[4 * r + 1 + k] = E.g[k];
             if (normal3) normal_of(E.R, E.w, E.g, normal3 + 3 * r);
+            if (sign) sign[r] = (int8_t)E.sgn;
         } else {
             for (int k = 0; k < 4; ++k) out4[4 * r + k] = NAN;
             if (normal3) for (int k = 0; k < 3; ++k) normal3[3 * r + k] = NAN;
+            if (sign) sign[r] = 0;
         }
+        if (evals) evals[r] = ne;
     }
+}
+
+ORC_API void orc_trace(const double* lut, int N, const double* center, double rmax, const float* ray_o, const float* ray_d,
+                       int64_t P, int n_march, int n_bisect, int n_newton, double* t_out, double* out4, double* normal3)
+{
+    const float c[3] = {(float)center[0], (float)center[1], (float)center[2]};
+    orc_trace_ex(lut, N, c, (float)rmax, 1.0, 0, 0.0f, 0.0f, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out4,
+                 normal3, NULL, NULL);
 }
 
 /* F(t) of one ray at explicit t values (pin tests and hit validation). */
@@ -886,7 +979,7 @@ ORC_API void orc_trace_F(const double* lut, int N, const double* center, const d
     double dl = sqrt(dot3(d, d));
     double dn[3] = {d[0] / dl, d[1] / dl, d[2] / dl};
     for (int64_t i = 0; i < n; ++i) {
-        feval_t E = trace_eval(lut, N, o, center, dn, ts[i]);
+        feval_t E = trace_eval(lut, N, o, center, dn, ts[i], 1.0, 0);
         F[i] = E.F;
     }
 }
@@ -903,6 +996,10 @@ ORC_API void orc_trace_F(const double* lut, int N, const double* center, const d
  *   method 1  bilinear value; chart derivatives by central differences of the
  *             bilinear reconstruction at u +- h, v +- h (four extra lookups)
  *   method 2  16-tap Catmull-Rom bicubic value and its analytic derivatives
+ *   method 3  "fast bicubic" (Table cost_extended): the uniform cubic B-spline
+ *             of the samples (the filter a 4-bilinear-fetch evaluation
+ *             computes); chart derivatives by the central differences of
+ *             method 1, the finite-difference fallback the table lists
  * The chart derivatives become the spherical gradient as in Sec. 3.4. */
 static double vl_at(const double* vl, int N, int f, int p, int q)
 {
@@ -937,6 +1034,16 @@ static void catmull_rom(double t, double w[4], double dw[4])
     dw[3] = 0.5 * (3 * t2 - 2 * t);
 }
 
+/* uniform cubic B-spline weights of taps -1, 0, 1, 2 at t */
+static void bspline3(double t, double w[4])
+{
+    double t2 = t * t, t3 = t2 * t, m = 1.0 - t;
+    w[0] = m * m * m / 6.0;
+    w[1] = (3 * t3 - 6 * t2 + 4) / 6.0;
+    w[2] = (-3 * t3 + 3 * t2 + 3 * t + 1) / 6.0;
+    w[3] = t3 / 6.0;
+}
+
 ORC_API void orc_baseline_query(const double* vlut, int N, const float* dirs, int64_t Q, int method, double* out)
 {
 #pragma omp parallel for schedule(static)
@@ -949,9 +1056,18 @@ ORC_API void orc_baseline_query(const double* vlut, int N, const float* dirs, in
         double R = 0, ru = 0, rv = 0;
         if (method == 0) {
             R = vl_at(vlut, N, f, (int)floor(fu + 0.5), (int)floor(fv + 0.5));
-        } else if (method == 1) {
+        } else if (method == 1 || method == 3) {
             double h = 1.0 / N, da = 2.0 * h; /* a = 2u - 1: a step of h in u is 2h in a */
-            R = bilinear_at(vlut, N, f, a, b);
+            if (method == 1) {
+                R = bilinear_at(vlut, N, f, a, b);
+            } else {
+                int i0 = (int)floor(fu), j0 = (int)floor(fv);
+                double ws[4], wt[4];
+                bspline3(fu - i0, ws);
+                bspline3(fv - j0, wt);
+                for (int j = 0; j < 4; ++j)
+                    for (int i = 0; i < 4; ++i) R += ws[i] * wt[j] * vl_at(vlut, N, f, i0 - 1 + i, j0 - 1 + j);
+            }
             ru = (bilinear_at(vlut, N, f, a + da, b) - bilinear_at(vlut, N, f, a - da, b)) / (2 * h);
             rv = (bilinear_at(vlut, N, f, a, b + da) - bilinear_at(vlut, N, f, a, b - da)) / (2 * h);
         } else {
@@ -973,6 +1089,57 @@ ORC_API void orc_baseline_query(const double* vlut, int N, const float* dirs, in
         transport_closed(f, a, b, ru, rv, g);
         out[4 * q] = R;
         for (int k = 0; k < 3; ++k) out[4 * q + 1 + k] = g[k];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mip chain (Sec. 4.7, Table lod)                                           */
+/* ------------------------------------------------------------------------ */
+/* Next level of a TEXEL LUT of face size N (even) -> N/2.
+ * Consistent (mode 0): the value field is box-filtered -- the coarse value at
+ *   a texel centre is the mean of the fine map at the four fine texel-centre
+ *   directions the coarse texel covers (evaluated as queries, so points
+ *   outside the face read the neighbouring face) -- on the coarse padded grid
+ *   plus a margin ring, and the derivative channels are recomputed from the
+ *   filtered values by central differences (the general-mode bake).
+ * Naive (mode 1): as consistent, but every interior coarse texel holds the
+ *   plain average of the four fine texels' stored channels
+ *   (r, r_u h, r_v h, r_uv h^2), as a box-filtering mip generator would. */
+ORC_API void orc_mip_level(const double* lut, int N, int mode, double* out)
+{
+    int Nc = N / 2, Pm = Nc + 4, P = N + 2;
+    double* samples = (double*)malloc(sizeof(double) * 6 * Pm * Pm);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int face = 0; face < 6; ++face)
+        for (int q = 0; q < Pm; ++q)
+            for (int p = 0; p < Pm; ++p) {
+                /* coarse texel (p, q) of the margin grid: u = (p - 3/2)/Nc; its
+                 * fine sub-texel centres sit at u -+ 1/(2N) */
+                double uc = ((double)p - 1.5) / Nc, vc = ((double)q - 1.5) / Nc, acc = 0.0;
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        double u = uc + (a ? 0.5 : -0.5) / N, v = vc + (b ? 0.5 : -0.5) / N;
+                        double d[3];
+                        for (int k = 0; k < 3; ++k) d[k] = FM[face][k] + (2 * u - 1) * FS[face][k] + (2 * v - 1) * FT[face][k];
+                        query_t QR;
+                        query_hd(lut, N, d, NULL, 0, &QR);
+                        acc += QR.R.v;
+                    }
+                samples[((size_t)face * Pm + q) * Pm + p] = 0.25 * acc;
+            }
+    orc_bake_fd(samples, Nc, out);
+    free(samples);
+    if (mode == 1) {
+        for (int face = 0; face < 6; ++face)
+            for (int q = 1; q <= Nc; ++q)
+                for (int p = 1; p <= Nc; ++p)
+                    for (int ch = 0; ch < 4; ++ch) {
+                        double acc = 0.0;
+                        for (int b = 0; b < 2; ++b)
+                            for (int a = 0; a < 2; ++a)
+                                acc += lut[(((size_t)face * P + (2 * q - 1 + b)) * P + (2 * p - 1 + a)) * 4 + ch];
+                        out[texel_index(Nc, face, p, q) + ch] = 0.25 * acc;
+                    }
     }
 }
 

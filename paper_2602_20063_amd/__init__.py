@@ -21,7 +21,7 @@ SHM_OK, SHM_ERR_INVALID_ARG, SHM_ERR_UNSUPPORTED, SHM_ERR_WORKSPACE, SHM_ERR_HIP
 SHM_F32, SHM_F16 = 0, 1
 SHM_LAYOUT_TEXEL, SHM_LAYOUT_CELL = 0, 1
 SHM_MAX_N, SHM_MAX_L = 1024, 16
-SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC = 0, 1, 2
+SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC, SHM_RECON_FAST_BICUBIC_FD = 0, 1, 2, 3
 
 
 class ShmError(RuntimeError):
@@ -74,6 +74,8 @@ SIGNATURES = {
     "shm_trace_radial": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP,
                                         _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
     "shm_lut_rmax": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+    "shm_mip_level_workspace": (_SZ, [_I32]),
+    "shm_mip_level": (ctypes.c_int, [_VP, _I32, _I32, _VP, _SZ, _VP, _VP]),
     "shm_query_baseline": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _I32, _VP, _VP]),
     "shm_sh_eval": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP]),
 }
@@ -208,6 +210,16 @@ def shm_lut_rmax(lut, dtype, N, rmax_out, stream=None):
     return _check(lib().shm_lut_rmax(_ptr(lut), dtype, N, _ptr(rmax_out), _stream(stream)))
 
 
+def shm_mip_level_workspace(N):
+    return lib().shm_mip_level_workspace(N)
+
+
+def shm_mip_level(lut, N, mode, ws, out, stream=None):
+    _need(lut, torch.float32, "lut")
+    return _check(lib().shm_mip_level(_ptr(lut), N, mode, _ptr(ws), ws.numel() * ws.element_size(), _ptr(out),
+                                      _stream(stream)))
+
+
 def shm_query_baseline(vlut, N, n_obj, dirs, q_per_obj, method, out, stream=None):
     _need(vlut, torch.float32, "vlut")
     return _check(lib().shm_query_baseline(_ptr(vlut), N, n_obj, _ptr(dirs), q_per_obj, method, _ptr(out),
@@ -318,6 +330,16 @@ def query(lut, dirs, q_per_obj=None, layout=SHM_LAYOUT_TEXEL, normals=False, str
     nrm = torch.empty((Q, 3), dtype=torch.float32, device=dirs.device) if normals else None
     shm_query_value_grad(lut, _dtype_code(lut), layout, N, n_obj, dirs, q_per_obj, out, nrm, stream)
     return (out, nrm) if normals else out
+
+
+def mip_level(lut, naive=False, stream=None):
+    """Next mip level (N -> N/2) of one FP32 TEXEL LUT [6, N+2, N+2, 4]
+    (or [1, 6, ...]): derivative-consistent, or naive box filtering."""
+    N = lut_n(lut)
+    out = torch.empty((6, N // 2 + 2, N // 2 + 2, 4), dtype=torch.float32, device=lut.device)
+    ws = torch.empty(shm_mip_level_workspace(N), dtype=torch.uint8, device=lut.device)
+    shm_mip_level(lut, N, 1 if naive else 0, ws, out, stream)
+    return out.reshape(lut.shape[:-4] + out.shape)
 
 
 def query_baseline(vlut, dirs, method, q_per_obj=None, stream=None):

@@ -59,6 +59,8 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
 int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, const float* ray_o,
                  const float* ray_d, int64_t P, int n_march, int n_bisect, int n_newton, float* t_out, float* out,
                  float* normal, hipStream_t stream);
+size_t mip_workspace_bytes(int N);
+int launch_mip_level(const float* lut, int N, int mode, float* ws, float* out, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 static bool valid_N(int N) { return N >= 1 && N <= SHM_MAX_N; }
@@ -523,12 +525,31 @@ int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hip
 }
 
 // ---------------------------------------------------------------------------
+size_t shm_mip_level_workspace(int32_t N)
+{
+    if (!valid_N(N) || N < 2 || (N & 1)) return 0;
+    return mip_workspace_bytes(N);
+}
+
+int shm_mip_level(const float* lut, int32_t N, int32_t mode, void* ws, size_t ws_bytes, float* out, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N) || N < 2 || (N & 1)) return fail(SHM_ERR_INVALID_ARG, "mip_level: N must be even, 2..%d", SHM_MAX_N);
+    if (mode != 0 && mode != 1) return fail(SHM_ERR_INVALID_ARG, "mip_level: mode must be 0 or 1");
+    if (!lut || !out) return fail(SHM_ERR_INVALID_ARG, "mip_level: null pointer");
+    if (!aligned(lut, 16) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "mip_level: misaligned LUT");
+    if (!ws || ws_bytes < mip_workspace_bytes(N))
+        return fail(SHM_ERR_WORKSPACE, "mip_level: workspace of %zu bytes needed (got %zu)", mip_workspace_bytes(N), ws_bytes);
+    return launch_mip_level(lut, N, mode, reinterpret_cast<float*>(ws), out, stream);
+}
+
+// ---------------------------------------------------------------------------
 int shm_query_baseline(const float* vlut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
                        int32_t method, float* out, hipStream_t stream)
 {
     clear_error();
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "query_baseline: N must be 1..%d", SHM_MAX_N);
-    if (method < SHM_RECON_NEAREST || method > SHM_RECON_BICUBIC) return fail(SHM_ERR_INVALID_ARG, "query_baseline: bad method %d", method);
+    if (method < SHM_RECON_NEAREST || method > SHM_RECON_FAST_BICUBIC_FD) return fail(SHM_ERR_INVALID_ARG, "query_baseline: bad method %d", method);
     if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query_baseline: negative size");
     if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
     if (!vlut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "query_baseline: null pointer");

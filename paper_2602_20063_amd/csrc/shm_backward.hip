@@ -4,14 +4,13 @@
 // dL/dLUT is a scatter of per-query weights onto 4 texels.  To make it
 // deterministic without floating-point atomics:
 //   1. sort:   cell key per query, stable LSD radix sort (8-bit digits) of
-//              (key, query index) -> permutation, cell segment starts, rank
-//   2. query:  per query (original order) the direction gradient (second
-//              chart derivatives + derivative of the chart map) and a compact
-//              record (s, t, gR, N lambda_u, N lambda_v) stored at its rank
-//   3. cells:  per cell, the sum over its sorted query segment of the 16
-//              weights (4 corners x 4 channels), in segment order
-//   4. texels: per texel, the corner sums of its <= 4 adjacent cells in a
-//              fixed order
+//              (key, query index) -> permutation, cell segment starts
+//   2. tiles:  one workgroup per 15 x 15 texel tile of a face; one lane per
+//              cell of the tile (halo included) sums the 16 weights (4 corners
+//              x 4 channels) of its sorted query segment in order and, for the
+//              cells the tile owns, writes the direction gradient (second
+//              chart derivatives + derivative of the chart map); each texel
+//              then adds its <= 4 cells' corner sums in a fixed order
 // The sort depends only on the directions and is reused while they stay
 // fixed.  Integer atomics appear only in the per-block digit histograms.
 #include "shm_device.hpp"
@@ -28,7 +27,7 @@ constexpr int SC_THREADS = 256, SC_ITEMS = 16, SC_TILE = SC_THREADS * SC_ITEMS; 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BwdLayout {
-    size_t keys0, vals0, keys1, vals1, rank, cstart, hist, tsum, rec4, rec1, csum, total;
+    size_t keys0, vals0, keys1, vals1, cstart, hist, tsum, total;
     int64_t Q, n_cells, nb;
     int passes;
 };
@@ -48,13 +47,9 @@ static BwdLayout bwd_layout(int N, int64_t n_obj, int64_t q_per_obj)
     W.vals0 = take(W.Q * 4);
     W.keys1 = take(W.Q * 4);
     W.vals1 = take(W.Q * 4);
-    W.rank = take(W.Q * 4);
     W.cstart = take((W.n_cells + 1) * 4);
     W.hist = take((size_t)256 * W.nb * 4);
     W.tsum = take(((size_t)256 * W.nb + SC_TILE - 1) / SC_TILE * 4);
-    W.rec4 = take(W.Q * 16);
-    W.rec1 = take(W.Q * 4);
-    W.csum = take(W.n_cells * 64);
     W.total = o;
     return W;
 }
@@ -225,12 +220,6 @@ __global__ void k_cell_start(const uint32_t* __restrict__ sk, int64_t Q, int64_t
     cs[c] = (uint32_t)lo;
 }
 
-__global__ void k_inverse_perm(const uint32_t* __restrict__ perm, int64_t Q, uint32_t* __restrict__ rank)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < Q) rank[perm[k]] = (uint32_t)k;
-}
-
 int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream)
 {
     const BwdLayout W = bwd_layout(N, n_obj, q_per_obj);
@@ -261,10 +250,8 @@ int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_
     }
     // sorted keys in k0, permutation in v0 (buffer 0 or 1 depending on parity)
     uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
-    uint32_t* rank = reinterpret_cast<uint32_t*>(base + W.rank);
     hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.n_cells + 1 + 255) / 256)), dim3(256), 0, stream, k0, W.Q,
                        W.n_cells, cs);
-    hipLaunchKernelGGL(k_inverse_perm, dim3(gq), dim3(256), 0, stream, v0, W.Q, rank);
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }
@@ -280,127 +267,199 @@ int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
 }
 
 // ---------------------------------------------------------------------------
-// per-query pass: direction gradient and the record at the query's rank
+// Fused gradient pass.  One workgroup per tile of BT x BT texels of one face;
+// its texels touch the BC x BC cells i0 in [p0-1, p0+BT-1], j0 in
+// [q0-1, q0+BT-1].  In the sorted order each row of those cells is one
+// contiguous range of queries, so the tile's queries are BC ranges, read as
+// one concatenated list in rounds of BWD_THREADS:
+//   * every lane takes the next query of the list (balanced, coalesced when
+//     the directions are sorted), computes its 16 weights (4 corners x 4
+//     channels) into an LDS slot and, if the tile owns the query's cell
+//     (i0 >= p0, j0 >= q0: every cell has one owner), its direction
+//     gradient;
+//   * every cell lane (one per cell) adds the slots of its segment, in
+//     sorted order.
+// Then each texel adds the corner sums of its <= 4 cells in a fixed order.
+// Every sum has a fixed order: the result is deterministic, with no atomics.
 // ---------------------------------------------------------------------------
-__global__ void k_bwd_query(const float* __restrict__ lut, int N, int64_t lut_elems, int64_t Q, int64_t q_per_obj,
-                            const float* __restrict__ dirs, const float* __restrict__ gout,
-                            const uint32_t* __restrict__ rank, float4* __restrict__ rec4, float* __restrict__ rec1,
-                            float* __restrict__ grad_dirs)
+constexpr int BT = 15;                 // texels per tile side: BC * BC = 256 cells, one per lane
+constexpr int BC = BT + 1;             // cells per tile side
+constexpr int BWD_THREADS = 256;
+static_assert(BC * BC == BWD_THREADS, "one lane per cell of a tile");
+
+// dL/d(16 footprint scalars) of one query, as 4 corners x (r, r_u h, r_v h, r_uv h^2)
+__device__ __forceinline__ void query_weights(float gR, float nlu, float nlv, const Basis1& Sb, const Basis1& Tt,
+                                              float4 w[4])
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= Q) return;
-    const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
-    const Loc L = locate(x, y, z, N);
-    const uint32_t pos = rank[q];
-    if (L.face < 0) {
-        rec4[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
-        rec1[pos] = 0.f;
-        if (grad_dirs) {
-            const float nan = __builtin_nanf("");
-            grad_dirs[3 * q] = nan;
-            grad_dirs[3 * q + 1] = nan;
-            grad_dirs[3 * q + 2] = nan;
-        }
-        return;
+#pragma unroll
+    for (int corner = 0; corner < 4; ++corner) {
+        const bool cI = corner & 1, cJ = corner >> 1;
+        const float Hi = cI ? Sb.h1 : 1.0f - Sb.h1, Hdi = cI ? Sb.h1d : Sb.h0d;
+        const float dHi = cI ? Sb.d1 : -Sb.d1, dHdi = cI ? Sb.d1d : Sb.d0d;
+        const float Hj = cJ ? Tt.h1 : 1.0f - Tt.h1, Hdj = cJ ? Tt.h1d : Tt.h0d;
+        const float dHj = cJ ? Tt.d1 : -Tt.d1, dHdj = cJ ? Tt.d1d : Tt.d0d;
+        w[corner].x = gR * Hi * Hj + nlu * dHi * Hj + nlv * Hi * dHj;
+        w[corner].y = gR * Hdi * Hj + nlu * dHdi * Hj + nlv * Hdi * dHj;
+        w[corner].z = gR * Hi * Hdj + nlu * dHi * Hdj + nlv * Hi * dHdj;
+        w[corner].w = gR * Hdi * Hdj + nlu * dHdi * Hdj + nlv * Hdi * dHdj;
     }
-    const float4 g = reinterpret_cast<const float4*>(gout)[q];
-    const float gR = g.x;
-    float3 M, S, T;
-    frame_of(L.face, M, S, T);
-    const float a = L.a, b = L.b;
-    const float3 Sa = make_float3(S.x - a * M.x, S.y - a * M.y, S.z - a * M.z);
-    const float3 Tb = make_float3(T.x - b * M.x, T.y - b * M.y, T.z - b * M.z);
-    const float gS = g.y * Sa.x + g.z * Sa.y + g.w * Sa.z;
-    const float gT = g.y * Tb.x + g.z * Tb.y + g.w * Tb.z;
-    const float rho = sqrtf(1.0f + a * a + b * b);
-    const float k = 0.5f * rho;
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
+                                                           int64_t Q, const float* __restrict__ dirs,
+                                                           const float* __restrict__ gout,
+                                                           const uint32_t* __restrict__ perm,
+                                                           const uint32_t* __restrict__ cs, int tiles_per_face,
+                                                           float* __restrict__ grad_lut, float* __restrict__ grad_dirs)
+{
+    __shared__ float4 slot[BWD_THREADS][4];  // one query's weights per lane; later the cell sums
+    __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
+    __shared__ int64_t row_off[BC + 1];      // offsets of the rows in the concatenated list
+    const int C = N + 1, P = N + 2;
+    const int tpf = tiles_per_face;
+    int b = blockIdx.x;
+    const int per_face = tpf * tpf;
+    const int64_t fo = b / per_face;  // object * 6 + face
+    b -= (int)(fo * per_face);
+    const int p0 = (b % tpf) * BT, q0 = (b / tpf) * BT;
+    const int64_t obj = fo / 6;
+    const int face = (int)(fo - obj * 6);
+    const int64_t cbase = fo * (int64_t)C * C;
+    const int i_lo = max(p0 - 1, 0), i_hi = min(p0 + BT - 1, N);  // the tile's cell columns (p0 <= N + 1)
+    const int tid = threadIdx.x;
+    if (tid < BC) {
+        const int j0 = q0 - 1 + tid;
+        int64_t a = 0, e = 0;
+        if (j0 >= 0 && j0 <= N) {
+            const int64_t c0 = cbase + (int64_t)j0 * C;
+            a = min((int64_t)cs[c0 + i_lo], Q);
+            e = min(max((int64_t)cs[c0 + i_hi + 1], a), Q);
+        }
+        row_start[tid] = a;
+        row_off[tid + 1] = e - a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        row_off[0] = 0;
+        for (int k = 1; k <= BC; ++k) row_off[k] += row_off[k - 1];
+    }
+    __syncthreads();
+    // this lane's cell and its segment in the concatenated list
+    const int ci = tid % BC, cj = tid / BC;
+    const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
+    int64_t seg_lo = 0, seg_hi = 0;
+    if (grad_lut && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N) {
+        const int64_t c = cbase + (int64_t)j0c * C + i0c;
+        const int64_t rs = row_start[cj], len = row_off[cj + 1] - row_off[cj];
+        const int64_t a = min(max((int64_t)cs[c] - rs, (int64_t)0), len);
+        const int64_t e = min(max((int64_t)cs[c + 1] - rs, a), len);
+        seg_lo = row_off[cj] + a;
+        seg_hi = row_off[cj] + e;
+    }
+    const int64_t total = row_off[BC];
     const float Nf = (float)N;
-    const float lu = k * gS, lv = k * gT;  // dL/dr_u, dL/dr_v
-    rec4[pos] = make_float4(L.s, L.t, gR, Nf * lu);
-    rec1[pos] = Nf * lv;
-    if (grad_dirs) {
-        const int64_t obj = q / q_per_obj;
-        const Foot F = load_texel_f32(lut + obj * lut_elems, N, L);
-        const Patch2 P = hermite2(F, L.s, L.t);
-        const float gM = g.y * M.x + g.z * M.y + g.w * M.z;
-        const float ru = Nf * P.rs, rv = Nf * P.rt;
-        const float hN2 = 0.5f * Nf * Nf;
-        const float common = (ru * gS + rv * gT) / (2.0f * rho);
-        const float dLda = 0.5f * Nf * gR * P.rs + a * common + k * (hN2 * P.rss * gS - ru * gM + hN2 * P.rst * gT);
-        const float dLdb = 0.5f * Nf * gR * P.rt + b * common + k * (hN2 * P.rst * gS + hN2 * P.rtt * gT - rv * gM);
-        const float ma = x * M.x + y * M.y + z * M.z;
-        const float im = 1.0f / ma;
-        grad_dirs[3 * q] = (dLda * Sa.x + dLdb * Tb.x) * im;
-        grad_dirs[3 * q + 1] = (dLda * Sa.y + dLdb * Tb.y) * im;
-        grad_dirs[3 * q + 2] = (dLda * Sa.z + dLdb * Tb.z) * im;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// cell pass: csum[c][corner] (float4 over channels) = sum over the queries of
-// cell c, in sorted order, of that corner's 4 channel weights
-// ---------------------------------------------------------------------------
-__global__ void k_bwd_cells(int64_t n_cells, const uint32_t* __restrict__ cs, const float4* __restrict__ rec4,
-                            const float* __restrict__ rec1, float4* __restrict__ csum)
-{
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    const uint32_t kb = cs[c], ke = cs[c + 1];
-    float4 a[4];
+    float3 M, S, T;
+    frame_of(face, M, S, T);
+    float4 acc[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (uint32_t kk = kb; kk < ke; ++kk) {
-        const float4 r = rec4[kk];
-        const float nlv = rec1[kk];
-        const Basis1 S = basis1(r.x), T = basis1(r.y);
-        const float gR = r.z, nlu = r.w;
+    for (int k = 0; k < 4; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t base = 0; base < total; base += BWD_THREADS) {
+        const int64_t g = base + tid;
+        if (g < total) {
+            int r = 0;
+            while (g >= row_off[r + 1]) ++r;
+            const int64_t q = perm[row_start[r] + (g - row_off[r])];
+            float4 w[4];
 #pragma unroll
-        for (int corner = 0; corner < 4; ++corner) {
-            const bool ci = corner & 1, cj = corner >> 1;
-            const float Hi = ci ? S.h1 : 1.0f - S.h1, Hdi = ci ? S.h1d : S.h0d;
-            const float dHi = ci ? S.d1 : -S.d1, dHdi = ci ? S.d1d : S.d0d;
-            const float Hj = cj ? T.h1 : 1.0f - T.h1, Hdj = cj ? T.h1d : T.h0d;
-            const float dHj = cj ? T.d1 : -T.d1, dHdj = cj ? T.d1d : T.d0d;
-            a[corner].x += gR * Hi * Hj + nlu * dHi * Hj + nlv * Hi * dHj;
-            a[corner].y += gR * Hdi * Hj + nlu * dHdi * Hj + nlv * Hdi * dHj;
-            a[corner].z += gR * Hi * Hdj + nlu * dHi * Hdj + nlv * Hi * dHdj;
-            a[corner].w += gR * Hdi * Hdj + nlu * dHdi * Hdj + nlv * Hdi * dHdj;
+            for (int k = 0; k < 4; ++k) w[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (q < Q) {
+                const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+                const Loc L = locate(x, y, z, N);  // the cell of row r (keys come from the same decision)
+                const float4 gq = reinterpret_cast<const float4*>(gout)[q];
+                const float A = L.a, B = L.b;
+                const float3 Sa = make_float3(S.x - A * M.x, S.y - A * M.y, S.z - A * M.z);
+                const float3 Tb = make_float3(T.x - B * M.x, T.y - B * M.y, T.z - B * M.z);
+                const float gS = gq.y * Sa.x + gq.z * Sa.y + gq.w * Sa.z;
+                const float gT = gq.y * Tb.x + gq.z * Tb.y + gq.w * Tb.z;
+                const float rho = sqrtf(1.0f + A * A + B * B);
+                const float kk2 = 0.5f * rho;
+                const float nlu = Nf * kk2 * gS, nlv = Nf * kk2 * gT, gR = gq.x;
+                if (grad_lut) query_weights(gR, nlu, nlv, basis1(L.s), basis1(L.t), w);
+                if (grad_dirs && L.i0 >= p0 && r >= 1) {  // the tile owns the cell
+                    const Foot F = load_texel_f32(lut + obj * lut_elems, N, L);
+                    const Patch2 Pp = hermite2(F, L.s, L.t);
+                    const float gM = gq.y * M.x + gq.z * M.y + gq.w * M.z;
+                    const float ru = Nf * Pp.rs, rv = Nf * Pp.rt;
+                    const float hN2 = 0.5f * Nf * Nf;
+                    const float common = (ru * gS + rv * gT) / (2.0f * rho);
+                    const float dLda = 0.5f * Nf * gR * Pp.rs + A * common + kk2 * (hN2 * Pp.rss * gS - ru * gM + hN2 * Pp.rst * gT);
+                    const float dLdb = 0.5f * Nf * gR * Pp.rt + B * common + kk2 * (hN2 * Pp.rst * gS + hN2 * Pp.rtt * gT - rv * gM);
+                    const float im = 1.0f / (x * M.x + y * M.y + z * M.z);
+                    grad_dirs[3 * q] = (dLda * Sa.x + dLdb * Tb.x) * im;
+                    grad_dirs[3 * q + 1] = (dLda * Sa.y + dLdb * Tb.y) * im;
+                    grad_dirs[3 * q + 2] = (dLda * Sa.z + dLdb * Tb.z) * im;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
         }
-    }
+        __syncthreads();
+        const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
+        for (int k2 = lo; k2 < hi; ++k2) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) csum[c * 4 + k] = a[k];
+            for (int k = 0; k < 4; ++k) {
+                const float4 v = slot[k2][k];
+                acc[k].x += v.x;
+                acc[k].y += v.y;
+                acc[k].z += v.z;
+                acc[k].w += v.w;
+            }
+        }
+        __syncthreads();
+    }
+    if (!grad_lut) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) slot[tid][k] = acc[k];
+    __syncthreads();
+    // texel (p0 + tx, q0 + ty) is corner (1,1) of cell (tx, ty), (0,1) of
+    // (tx+1, ty), (1,0) of (tx, ty+1) and (0,0) of (tx+1, ty+1) in tile cells
+    for (int t = tid; t < BT * BT; t += BWD_THREADS) {
+        const int tx = t % BT, ty = t / BT;
+        const int p = p0 + tx, q = q0 + ty;
+        if (p > N + 1 || q > N + 1) continue;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int dj = 1; dj >= 0; --dj)
+#pragma unroll
+            for (int di = 1; di >= 0; --di) {
+                const float4 v = slot[(ty + 1 - dj) * BC + (tx + 1 - di)][dj * 2 + di];
+                a.x += v.x;
+                a.y += v.y;
+                a.z += v.z;
+                a.w += v.w;
+            }
+        reinterpret_cast<float4*>(grad_lut)[(fo * P + q) * (int64_t)P + p] = a;
+    }
 }
 
-// ---------------------------------------------------------------------------
-// texel pass: grad_lut[texel] = sum over its adjacent cells (fixed order) of
-// the cell sum of the corner this texel is
-// ---------------------------------------------------------------------------
-__global__ void k_bwd_texels(int N, int64_t n_tex, const float4* __restrict__ csum, float4* __restrict__ grad_lut)
+__global__ void k_zero_f4(float4* __restrict__ a, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_tex) return;
-    const int P = N + 2, C = N + 1;
-    const int64_t per = 6ll * P * P;
-    const int64_t obj = i / per;
-    const int rem = (int)(i - obj * per);
-    const int face = rem / (P * P), r2 = rem - face * P * P;
-    const int q = r2 / P, p = r2 - q * P;
-    const int64_t cell_base = (obj * 6 + face) * (int64_t)C * C;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int dj = 1; dj >= 0; --dj) {
-        const int j0 = q - dj;
-        if (j0 < 0 || j0 > N) continue;
-        for (int di = 1; di >= 0; --di) {
-            const int i0 = p - di;
-            if (i0 < 0 || i0 > N) continue;
-            const float4 v = csum[(cell_base + (int64_t)j0 * C + i0) * 4 + (dj * 2 + di)];
-            acc.x += v.x;
-            acc.y += v.y;
-            acc.z += v.z;
-            acc.w += v.w;
-        }
-    }
-    grad_lut[i] = acc;
+    if (i < n) a[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// invalid directions sort after every cell: NaN direction gradient
+__global__ void k_bwd_invalid(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ cs, int64_t n_cells,
+                              int64_t Q, float* __restrict__ grad_dirs)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Q || k < (int64_t)cs[n_cells]) return;
+    const int64_t q = perm[k];
+    if (q >= Q) return;
+    const float nan = __builtin_nanf("");
+    grad_dirs[3 * q] = nan;
+    grad_dirs[3 * q + 1] = nan;
+    grad_dirs[3 * q + 2] = nan;
 }
 
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
@@ -409,21 +468,27 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     const BwdLayout W = bwd_layout(N, n_obj, q_per_obj);
     char* base = reinterpret_cast<char*>(ws);
     const uint32_t* cs = reinterpret_cast<const uint32_t*>(base + W.cstart);
-    const uint32_t* rank = reinterpret_cast<const uint32_t*>(base + W.rank);
-    float4* rec4 = reinterpret_cast<float4*>(base + W.rec4);
-    float* rec1 = reinterpret_cast<float*>(base + W.rec1);
-    if (W.Q > 0) {
-        hipLaunchKernelGGL(k_bwd_query, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, lut, N,
-                           texel_elems(N), W.Q, q_per_obj, dirs, gout, rank, rec4, rec1, grad_dirs);
-        SHM_LAUNCH_CHECK();
+    // after an odd number of passes the sorted pairs sit in the second buffers
+    const uint32_t* perm = reinterpret_cast<const uint32_t*>(base + ((W.passes & 1) ? W.vals1 : W.vals0));
+    if (!grad_lut && !grad_dirs) return SHM_OK;
+    if (W.Q == 0) {  // no queries: the sort wrote nothing, the gradient is zero
+        if (grad_lut) {
+            const int64_t n = n_obj * 6ll * (N + 2) * (N + 2);
+            if (n > 0) hipLaunchKernelGGL(k_zero_f4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                                          reinterpret_cast<float4*>(grad_lut), n);
+            SHM_LAUNCH_CHECK();
+        }
+        return SHM_OK;
     }
-    if (grad_lut) {
-        float4* csum = reinterpret_cast<float4*>(base + W.csum);
-        hipLaunchKernelGGL(k_bwd_cells, dim3((unsigned)((W.n_cells + 255) / 256)), dim3(256), 0, stream, W.n_cells, cs,
-                           rec4, rec1, csum);
-        const int64_t n_tex = n_obj * 6ll * (N + 2) * (N + 2);
-        hipLaunchKernelGGL(k_bwd_texels, dim3((unsigned)((n_tex + 255) / 256)), dim3(256), 0, stream, N, n_tex, csum,
-                           reinterpret_cast<float4*>(grad_lut));
+    const int tpf = (N + 2 + BT - 1) / BT;
+    const int64_t tiles = n_obj * 6ll * tpf * tpf;
+    if (tiles > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "backward: too many tiles for one launch");
+    hipLaunchKernelGGL(k_bwd_fused, dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N, texel_elems(N),
+                       W.Q, dirs, gout, perm, cs, tpf, grad_lut, grad_dirs);
+    SHM_LAUNCH_CHECK();
+    if (grad_dirs) {
+        hipLaunchKernelGGL(k_bwd_invalid, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, perm, cs, W.n_cells,
+                           W.Q, grad_dirs);
         SHM_LAUNCH_CHECK();
     }
     return SHM_OK;

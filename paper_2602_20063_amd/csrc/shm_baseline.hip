@@ -3,7 +3,8 @@
 //   * value-only LUT reconstructions (Table cost_extended, Table runtime):
 //     nearest texel, bilinear with finite-difference normals (4 extra
 //     bilinear lookups at u +- h, v +- h), 16-tap Catmull-Rom bicubic with its
-//     analytic gradient;
+//     analytic gradient, and "fast bicubic": the cubic B-spline evaluated as
+//     four bilinear lookups, with the same finite-difference gradient;
 //   * direct SH evaluation without any LUT (the paper's per-fragment SH
 //     baseline, Sec. 4.5).
 // The value-only LUT is vlut[obj][face][q][p], p, q in 0..N+3, texel p at
@@ -32,6 +33,38 @@ __device__ __forceinline__ float bilinear_at(const float* __restrict__ vl, int N
     return r0 + t * (r1 - r0);
 }
 
+// bilinear lookup between texels (i, j) and (i+1, j+1) at fractions (fx, fy)
+__device__ __forceinline__ float bilinear_ij(const float* __restrict__ vl, int P, int face, int i, int j, float fx,
+                                             float fy)
+{
+    const float v00 = vl_at(vl, P, face, i, j), v10 = vl_at(vl, P, face, i + 1, j);
+    const float v01 = vl_at(vl, P, face, i, j + 1), v11 = vl_at(vl, P, face, i + 1, j + 1);
+    const float r0 = v00 + fx * (v10 - v00), r1 = v01 + fx * (v11 - v01);
+    return r0 + fy * (r1 - r0);
+}
+
+// Cubic B-spline weights w0..w3 (taps -1..2) at t, folded into two bilinear
+// lookups per axis: w0 v[-1] + w1 v[0] = g0 lerp(v[-1], v[0], w1/g0) with
+// g0 = w0 + w1, and w2 v[1] + w3 v[2] = g1 lerp(v[1], v[2], w3/g1) with
+// g1 = w2 + w3.  Both g are >= 1/6 on [0, 1).
+struct Fold {
+    float g0, g1, f0, f1;
+};
+__device__ __forceinline__ Fold bspline_fold(float t)
+{
+    const float t2 = t * t, t3 = t2 * t, m = 1.0f - t;
+    const float w0 = m * m * m * (1.0f / 6.0f);
+    const float w1 = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+    const float w2 = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+    const float w3 = t3 * (1.0f / 6.0f);
+    Fold F;
+    F.g0 = w0 + w1;
+    F.g1 = w2 + w3;
+    F.f0 = w1 / F.g0;
+    F.f1 = w3 / F.g1;
+    return F;
+}
+
 template <int METHOD>
 __global__ __launch_bounds__(256) void k_query_baseline(const float* __restrict__ vlut, int N, int64_t q_per_obj,
                                                         int tiles_per_obj, const float* __restrict__ dirs,
@@ -56,9 +89,20 @@ __global__ __launch_bounds__(256) void k_query_baseline(const float* __restrict_
     if constexpr (METHOD == SHM_RECON_NEAREST) {
         const float fu = (a + 1.0f) * 0.5f * Nf + 1.5f, fv = (bb + 1.0f) * 0.5f * Nf + 1.5f;
         R = vl_at(vl, P, L.face, (int)floorf(fu + 0.5f), (int)floorf(fv + 0.5f));
-    } else if constexpr (METHOD == SHM_RECON_BILINEAR_FD) {
+    } else if constexpr (METHOD == SHM_RECON_BILINEAR_FD || METHOD == SHM_RECON_FAST_BICUBIC_FD) {
         const float da = 2.0f / Nf;  // a = 2u - 1: one texel in u
-        R = bilinear_at(vl, N, L.face, a, bb);
+        if constexpr (METHOD == SHM_RECON_BILINEAR_FD) {
+            R = bilinear_at(vl, N, L.face, a, bb);
+        } else {
+            const float fu = (a + 1.0f) * 0.5f * Nf + 1.5f, fv = (bb + 1.0f) * 0.5f * Nf + 1.5f;
+            const int i0 = (int)floorf(fu), j0 = (int)floorf(fv);
+            const Fold X = bspline_fold(fu - (float)i0), Y = bspline_fold(fv - (float)j0);
+            const float r0 = X.g0 * bilinear_ij(vl, P, L.face, i0 - 1, j0 - 1, X.f0, Y.f0) +
+                             X.g1 * bilinear_ij(vl, P, L.face, i0 + 1, j0 - 1, X.f1, Y.f0);
+            const float r1 = X.g0 * bilinear_ij(vl, P, L.face, i0 - 1, j0 + 1, X.f0, Y.f1) +
+                             X.g1 * bilinear_ij(vl, P, L.face, i0 + 1, j0 + 1, X.f1, Y.f1);
+            R = Y.g0 * r0 + Y.g1 * r1;
+        }
         ru = (bilinear_at(vl, N, L.face, a + da, bb) - bilinear_at(vl, N, L.face, a - da, bb)) * (0.5f * Nf);
         rv = (bilinear_at(vl, N, L.face, a, bb + da) - bilinear_at(vl, N, L.face, a, bb - da)) * (0.5f * Nf);
     } else {
@@ -118,6 +162,8 @@ int launch_query_baseline(const float* vlut, int N, int64_t n_obj, const float* 
         hipLaunchKernelGGL(k_query_baseline<SHM_RECON_NEAREST>, grid, block, 0, stream, vlut, N, q_per_obj, (int)tiles, dirs, out);
     else if (method == SHM_RECON_BILINEAR_FD)
         hipLaunchKernelGGL(k_query_baseline<SHM_RECON_BILINEAR_FD>, grid, block, 0, stream, vlut, N, q_per_obj, (int)tiles, dirs, out);
+    else if (method == SHM_RECON_FAST_BICUBIC_FD)
+        hipLaunchKernelGGL(k_query_baseline<SHM_RECON_FAST_BICUBIC_FD>, grid, block, 0, stream, vlut, N, q_per_obj, (int)tiles, dirs, out);
     else
         hipLaunchKernelGGL(k_query_baseline<SHM_RECON_BICUBIC>, grid, block, 0, stream, vlut, N, q_per_obj, (int)tiles, dirs, out);
     SHM_LAUNCH_CHECK();

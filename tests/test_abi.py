@@ -38,7 +38,9 @@ def test_version_and_sizes():
     # basis table: padded K x padded rows, FP32
     assert shm.shm_bake_sh_lut_workspace(8, 32) >= 81 * 6 * 34 * 34 * 4 * 4
     assert shm.shm_bake_sh_lut_workspace(17, 32) == 0
-    assert shm.shm_backward_workspace(512, 1, 1 << 22) > (1 << 22) * 36
+    # two (key, index) buffers of 8 B per query, cell starts, digit histograms
+    ws = shm.shm_backward_workspace(512, 1, 1 << 22)
+    assert (1 << 22) * 16 + 6 * 513 * 513 * 4 <= ws < (1 << 22) * 20
 
 
 def call(name, *args):

@@ -137,3 +137,25 @@ def test_backward_three_radix_passes(N):
     gn = np.linalg.norm(rd, axis=1)
     floor = np.sqrt(np.mean(gn ** 2))
     assert (np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3
+
+
+def test_backward_empty_and_partial_requests():
+    """No queries: dL/dLUT is zero (the sort writes nothing).  Asking for
+    only one of the two gradients gives the same values as asking for both."""
+    r = rng(8)
+    N = 12
+    lut_t = gpu(workloads.random_lut(N, r))
+    d0 = torch.empty((0, 3), device=DEV)
+    bc = shm.BackwardContext(N, 1, d0, 0)
+    gl = torch.full_like(lut_t, float("nan"))
+    shm.shm_query_backward(lut_t, N, 1, d0, 0, torch.empty((0, 4), device=DEV), gl, None, bc.ws, True)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(gl).item() == 0
+    dirs = workloads.uniform_dirs(7000, r)
+    g = gpu(r.standard_normal((7000, 4)))
+    bc = shm.BackwardContext(N, 1, gpu(dirs), 7000)
+    both = bc.backward(lut_t, g)
+    lut_only = bc.backward(lut_t, g, want_dirs=False)[0]
+    dirs_only = bc.backward(lut_t, g, want_lut=False)[1]
+    torch.cuda.synchronize()
+    assert torch.equal(both[0], lut_only) and torch.equal(both[1], dirs_only)

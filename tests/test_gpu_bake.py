@@ -104,3 +104,16 @@ def test_lut_rmax_bound():
         g = shm.lut_rmax(gpu(lut)).item()
         ref = oracle.rmax_bound(lut.astype(np.float64))
         assert abs(g - ref) <= 2e-6 * ref, (N, g, ref)
+
+
+@pytest.mark.parametrize("naive", [False, True])
+def test_mip_level_matches_oracle(naive):
+    """Mip chain (Sec. 4.7): three levels of a glyph map, GPU vs oracle on the
+    same FP32 input level each time."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(30))[0]
+    lut = oracle.bake_sh(c, 32).astype(np.float32)
+    for _ in range(3):
+        g = shm.mip_level(gpu(lut), naive=naive).cpu().numpy()
+        ref = oracle.mip_level(lut.astype(np.float64), naive=naive)
+        check_lut(g, ref, f"mip naive={naive}", val_rtol=2e-6, der_rtol=2e-4)
+        lut = g

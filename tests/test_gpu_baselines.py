@@ -21,7 +21,7 @@ def sh_value_lut(c, N):
     return oracle.sh_truth(c, oracle.margin_dirs(N).reshape(-1, 3))[:, 0].reshape(6, N + 4, N + 4)
 
 
-@pytest.mark.parametrize("method", [shm.SHM_RECON_BILINEAR_FD, shm.SHM_RECON_BICUBIC])
+@pytest.mark.parametrize("method", [shm.SHM_RECON_BILINEAR_FD, shm.SHM_RECON_BICUBIC, shm.SHM_RECON_FAST_BICUBIC_FD])
 def test_baseline_matches_oracle(method):
     r = np.random.default_rng(7 + method)
     c = workloads.sh_glyph_coeffs(8, 3, r)

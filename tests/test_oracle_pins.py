@@ -528,6 +528,129 @@ def test_trace_constant_sphere_closed_form():
     np.testing.assert_allclose(n, x / np.linalg.norm(x, axis=1, keepdims=True), atol=1e-10)
 
 
+def z_lut(N):
+    """r(w) = z = sqrt(4 pi / 3) Y_1^0 baked analytically: a signed function
+    whose rendered radius s|z| is two spheres of radius s/2 centred at
+    (0, 0, +-s/2) (|x - c|^2 = s^2 z^2 - s^2 z^2 + s^2/4 on x = s|z| w)."""
+    c = np.zeros(4)
+    c[2] = math.sqrt(4 * math.pi / 3)
+    return oracle.bake_sh(c, N)
+
+
+def test_signed_radius_two_spheres_closed_form():
+    N, s = 48, 0.5
+    lut = z_lut(N)
+    d = workloads.uniform_dirs(3000, rng(80)).astype(np.float64)
+    d = d[np.abs(d[:, 2]) > 0.2]  # away from the kink at z = 0
+    out, n, sg = oracle.query_scaled(lut, d, scale=s, signed=True)
+    w = d / np.linalg.norm(d, axis=1, keepdims=True)
+    z = w[:, 2]
+    np.testing.assert_allclose(out[:, 0], s * np.abs(z), atol=1e-7)
+    assert np.array_equal(sg, np.sign(z).astype(np.int8))
+    x = out[:, :1] * w
+    cen = np.zeros_like(x)
+    cen[:, 2] = np.sign(z) * s / 2
+    nn = (x - cen) / np.linalg.norm(x - cen, axis=1, keepdims=True)
+    assert np.abs(n - nn).max() < 2e-5
+    # without the sign in the gradient the lower lobe's normals are wrong
+    plain, _, _ = oracle.query_scaled(lut, d, scale=s)
+    lower = z < 0
+    assert np.allclose(out[lower, 1:], -plain[lower, 1:], atol=0, rtol=0)
+
+
+def test_scaled_radius_properties():
+    """R = s r: the normal does not depend on s; a positive function gives
+    the same result signed or not."""
+    c = workloads.sh_glyph_coeffs(6, 1, rng(81))[0]
+    lut = oracle.bake_sh(c, 12)
+    d = workloads.uniform_dirs(500, rng(82))
+    o1, n1, s1 = oracle.query_scaled(lut, d, scale=1.0)
+    o2, n2, _ = oracle.query_scaled(lut, d, scale=2.5)
+    o3, n3, s3 = oracle.query_scaled(lut, d, scale=2.5, signed=True)
+    base = oracle.query(lut, d)
+    np.testing.assert_allclose(o1, base, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(o2, 2.5 * o1, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(n2, n1, atol=1e-14)
+    assert (o1[:, 0] > 0).all() and (s1 == 1).all() and (s3 == 1).all()
+    np.testing.assert_array_equal(o3, o2)
+    np.testing.assert_array_equal(n3, n2)
+
+
+def test_bisect_budget_definition():
+    """The budget is the fewest halvings that bring the march bracket's
+    projected width e = 2 rmax px / (depth n_march) to <= eps pixels, capped;
+    it grows with the projected size (Sec. 3.1).  Checked against the
+    definition in FP64 (the FP32 decision may differ only where e 2^-k is
+    within rounding of eps)."""
+    r = rng(83)
+    cen = np.array([0.1, -0.2, 0.3], np.float32)
+    for _ in range(400):
+        o = (cen + r.normal(size=3) * r.uniform(0.5, 200)).astype(np.float32)
+        rmax, px, eps = float(r.uniform(0.1, 2)), float(r.uniform(50, 4000)), float(r.choice([0.0625, 0.125, 0.5]))
+        k = oracle.bisect_budget(o, cen, rmax, px, eps, 20, 16)
+        depth = np.linalg.norm(o.astype(np.float64) - cen.astype(np.float64))
+        e = 2 * rmax * px / (depth * 20)
+        assert 0 <= k <= 16
+        if k < 16:
+            assert e * 2.0 ** -k <= eps * (1 + 1e-6)
+        if k > 0:
+            assert e * 2.0 ** -(k - 1) > eps * (1 - 1e-6)
+    o = np.array([0, 0, 5], np.float32)
+    ks = [oracle.bisect_budget(o, np.zeros(3), 1.0, px, 0.125, 20, 16) for px in (10, 100, 1000, 10000, 1e6)]
+    assert ks == sorted(ks) and ks[0] < ks[-1] == 16
+    assert oracle.bisect_budget(o, np.zeros(3), 1.0, 0.0, 0.125, 20, 11) == 11
+
+
+def test_trace_signed_two_spheres_and_budget():
+    N, s = 48, 0.5
+    lut = z_lut(N)
+    rmax = s * oracle.rmax_bound(lut, absval=True)
+    assert s <= rmax < 1.01 * s  # max |z| = 1
+    r = rng(84)
+    P = 400
+    o = np.tile(np.array([[1.6, 0.3, 0.1]]), (P, 1))
+    tgt = np.stack([np.zeros(P), r.uniform(-0.3, 0.3, P), r.uniform(-0.55, 0.55, P)], axis=1) * s
+    dvec = tgt - o
+    o32, d32 = o.astype(np.float32), dvec.astype(np.float32)
+    t, out, n, sg, ev = oracle.trace_ex(lut, np.zeros(3), rmax, o32, d32, scale=s, signed=True)
+    oo, dd = o32.astype(np.float64), d32.astype(np.float64)
+    dd /= np.linalg.norm(dd, axis=1, keepdims=True)
+    # first hit of the two spheres; grazing rays and hits near the kink are skipped
+    best = np.full(P, np.inf)
+    clear = np.ones(P, bool)
+    for zc in (s / 2, -s / 2):
+        oc = oo - np.array([0, 0, zc])
+        b = np.einsum("ij,ij->i", oc, dd)
+        disc = b * b - (np.einsum("ij,ij->i", oc, oc) - (s / 2) ** 2)
+        clear &= np.abs(disc) > 0.05 * (s / 2) ** 2
+        th = np.where(disc > 0, -b - np.sqrt(np.maximum(disc, 0)), np.inf)
+        best = np.minimum(best, th)
+    xh = oo + best[:, None] * dd
+    ok = clear & np.isfinite(best) & (np.abs(xh[:, 2]) > 0.05 * s)
+    assert ok.sum() > 150
+    np.testing.assert_array_equal(np.isfinite(t[clear]), np.isfinite(best[clear]))
+    np.testing.assert_allclose(t[ok], best[ok], rtol=1e-6)
+    assert np.array_equal(sg[ok], np.sign(xh[ok, 2]).astype(np.int8))
+    xo = xh[ok]
+    cen = np.zeros_like(xo)
+    cen[:, 2] = np.sign(xo[:, 2]) * s / 2
+    nn = (xo - cen) / np.linalg.norm(xo - cen, axis=1, keepdims=True)
+    assert np.abs(n[ok] - nn).max() < 1e-4
+    # every hit spends march + budget + Newton + 1 evaluations
+    hit = np.isfinite(t)
+    assert (ev[hit] >= 16 + 3 + 2).all() and (ev[hit] <= 20 + 16 + 3 + 1).all()
+    # adaptive budget: a small projected size spends fewer bisections, each
+    # hit exactly march + k + Newton + 1 with k from the budget rule
+    px = 200.0
+    k = oracle.bisect_budget(o32[0], np.zeros(3), rmax, px, 0.125, 20, 16)
+    assert 0 < k < 16
+    ta, _, _, _, eva = oracle.trace_ex(lut, np.zeros(3), rmax, o32, d32, scale=s, signed=True, px=px)
+    tk, _, _, _, evk = oracle.trace_ex(lut, np.zeros(3), rmax, o32, d32, scale=s, signed=True, n_bisect=k)
+    np.testing.assert_array_equal(ta, tk)
+    np.testing.assert_array_equal(eva, evk)
+    assert (eva[hit] == ev[hit] - (16 - k)).all()
+
+
 def test_trace_hits_are_first_roots():
     N = 16
     c = workloads.sh_glyph_coeffs(8, 1, rng(27))[0]
@@ -732,6 +855,27 @@ def test_catmull_rom_reproduces_biquadratics():
                      [P(ff, uu, vv, dv=1) for ff, uu, vv in zip(f, u, v)], 1e-6)
 
 
+def test_fast_bicubic_is_the_cubic_bspline():
+    """The cubic B-spline of the samples reproduces linear and bilinear
+    functions exactly, and adds its second moment to a quadratic:
+    sum_k k^2 B(x - k) = x^2 + 1/3 in texel units, so U^2 (U = u) comes out
+    as U^2 + 1/(3 N^2).  The gradient is the bilinear central difference,
+    exact on bilinear functions."""
+    N = 9
+    r = rng(65)
+    C = r.standard_normal((6, 6))
+    vl = value_lut(N, lambda f, U, V: C[f, 0] + C[f, 1] * U + C[f, 2] * V + C[f, 3] * U * V)
+    d = workloads.uniform_dirs(400, r)
+    out = oracle.baseline_query(vl, d, oracle.BASELINE_FAST_BICUBIC_FD)
+    f, u, v = face_uv(d.astype(np.float64))
+    np.testing.assert_allclose(out[:, 0], C[f, 0] + C[f, 1] * u + C[f, 2] * v + C[f, 3] * u * v, atol=1e-12)
+    check_chart_grad(out, d, f, C[f, 1] + C[f, 3] * v, C[f, 2] + C[f, 3] * u, 1e-6)
+    vq = value_lut(N, lambda f, U, V: C[f, 0] + C[f, 4] * U * U + C[f, 5] * V * V)
+    out = oracle.baseline_query(vq, d, oracle.BASELINE_FAST_BICUBIC_FD)
+    want = C[f, 0] + C[f, 4] * (u * u + 1 / (3 * N * N)) + C[f, 5] * (v * v + 1 / (3 * N * N))
+    np.testing.assert_allclose(out[:, 0], want, atol=1e-12)
+
+
 def test_nearest_returns_texel_values():
     N = 6
     r = rng(62)
@@ -769,3 +913,52 @@ def test_value_psnr_ordering_matches_table_psnr_value():
     assert 9 < gains["bilinear"] < 15, gains      # second order: ~12 dB
     assert 15 < gains["bicubic"] < 27, gains      # paper: 21.5 dB
     assert gains["hermite"] > gains["bicubic"]
+
+
+# ---------------------------------------------------------------------------
+# Mip chain (Sec. 4.7, Table lod)
+# ---------------------------------------------------------------------------
+def test_mip_constant_and_box_filter():
+    N = 8
+    lut = np.zeros((6, N + 2, N + 2, 4))
+    lut[..., 0] = 0.9
+    for naive in (False, True):
+        m = oracle.mip_level(lut, naive=naive)
+        assert np.abs(m[..., 0] - 0.9).max() < 1e-13 and np.abs(m[..., 1:]).max() < 1e-13
+    lut = workloads.random_lut(N, rng(70)).astype(np.float64)
+    box = 0.25 * (lut[:, 1:N + 1:2, 1:N + 1:2] + lut[:, 1:N + 1:2, 2:N + 2:2] + lut[:, 2:N + 2:2, 1:N + 1:2] + lut[:, 2:N + 2:2, 2:N + 2:2])
+    c = oracle.mip_level(lut)
+    n = oracle.mip_level(lut, naive=True)
+    # interior coarse values are the box filter of the fine values (the map
+    # reproduces the stored value at every fine texel centre)
+    np.testing.assert_allclose(c[:, 1:-1, 1:-1, 0], box[..., 0], atol=1e-13)
+    np.testing.assert_allclose(n[:, 1:-1, 1:-1], box, atol=1e-13)
+    # gutters are shared by both constructions
+    np.testing.assert_array_equal(c[:, 0], n[:, 0])
+
+
+def test_mip_table_lod_trend():
+    """Table lod: naive box filtering of the derivative channels is several
+    times worse at the first coarse level (5.5x in the paper), the gap
+    closing at coarser levels (2.9x, 1.3x)."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(71))[0]
+    d = workloads.uniform_dirs(20000, rng(72))
+    w = d.astype(np.float64)
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+
+    def normals(out):
+        n = out[:, :1] * w - out[:, 1:]
+        return n / np.linalg.norm(n, axis=1, keepdims=True)
+
+    tn = normals(oracle.sh_truth(c, w))
+
+    def err(lut):
+        return np.degrees(np.arccos(np.clip(np.sum(normals(oracle.query(lut, d)) * tn, axis=1), -1, 1))).mean()
+
+    cons = naive = oracle.bake_sh(c, 32)
+    ratios = []
+    for _ in range(3):
+        cons, naive = oracle.mip_level(cons), oracle.mip_level(naive, naive=True)
+        ratios.append(err(naive) / err(cons))
+    assert ratios[0] > 3.0, ratios
+    assert ratios[0] > ratios[1] > ratios[2] > 1.0, ratios
