@@ -11,8 +11,9 @@ them under "forms", each with its error against FP64:
   fp32 TEXEL layout, fp16 (CELL, TEXEL), the bake (SH basis + MFMA
   contraction), the backward and a 200-step fit (fBm target, N=512, 2^22
   directions), the batched persistent/graph launch (4,096 uneven objects,
-  FP16) against per-object FP32 launches, and ray casting (1920x1080 rays,
-  N=256 bump impostor, FP32 and FP16).
+  FP16) against per-object FP32 launches, ray casting (1920x1080 rays,
+  N=256 bump impostor, FP32 and FP16, fixed and adaptive budgets), the
+  comparison reconstructions, the mip chain and the mesh impostor bake.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms] [--no-cpu]
   python bench.py --counters    (short run for rocprofv3 --pmc passes)
@@ -238,6 +239,8 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
     log("comparison", forms["comparison"])
     forms["mip_lod"] = run_mip_lod()
     log("mip", forms["mip_lod"])
+    forms["mesh_impostor"] = run_mesh()
+    log("mesh", forms["mesh_impostor"])
     forms["backward_fit"] = run_backward_fit()
     log("backward", forms["backward_fit"])
     forms["batched"], sample["batched"] = run_batched()
@@ -301,6 +304,49 @@ def run_mip_lod():
                                            "naive_mean_deg": en[0], "naive_p95_deg": en[1], "ratio": en[0] / ec[0]}
     lut = shm.bake_sh(c, 32)[0]
     res["mip_level_32_to_16_us"] = t_gpu(lambda: shm.mip_level(lut), 10) * 1e3
+    return res
+
+
+def run_mesh():
+    """Mesh impostor (Sec. 4.9, Table asteroid_normals): the synthetic
+    asteroid mesh (81,920 triangles) baked by ray casting at N = 48 (the
+    6 x 52^2 margin grid), then the same depth samples reconstructed by
+    Hermite (FD-baked LUT), bilinear + FD, Catmull-Rom with its analytic
+    gradient, and fast bicubic + FD.  Normal error in degrees against the
+    analytic normals of the smooth surface the mesh was built from, at
+    200,000 uniform directions (so mesh faceting is part of every error)."""
+    prm = workloads.asteroid_params(workloads.rng_for(6))
+    V, F = workloads.asteroid_mesh(prm, level=6)
+    Vt, Ft = to_dev(V), torch.as_tensor(F).to(DEV)
+    N = 48
+    md = shm.margin_dirs(N).reshape(-1, 3)
+    P, T = md.shape[0], F.shape[0]
+    c0 = (0.0, 0.0, 0.0)
+    depth = shm.mesh_radial_depth(Vt, Ft, c0, md)
+    ms = t_gpu(lambda: shm.mesh_radial_depth(Vt, Ft, c0, md), 5)
+    vlut = depth.reshape(1, 6, N + 4, N + 4)
+    lut = shm.bake_fd(vlut, N)
+    ms_fd = t_gpu(lambda: shm.bake_fd(vlut, N), 10)
+    res = {"triangles": T, "rays": P, "N": N, "depth_ms": ms, "ray_triangle_tests_per_s": P * T / ms * 1e3,
+           "fd_bake_ms": ms_fd}
+    d_np = workloads.uniform_dirs(200000, workloads.rng_for(6))
+    tv, tg = workloads.asteroid_radius(prm, d_np)
+    w = d_np.astype(np.float64) / np.linalg.norm(d_np.astype(np.float64), axis=1, keepdims=True)
+    tn = tv[:, None] * w - tg
+    tn = torch.as_tensor(tn / np.linalg.norm(tn, axis=1, keepdims=True), device=DEV)
+    d = to_dev(d_np)
+    wt = torch.as_tensor(w, device=DEV)
+    tvt = torch.as_tensor(tv, device=DEV)
+    for name, fn in (("hermite", lambda: shm.query(lut, d)),
+                     ("bilinear_fd", lambda: shm.query_baseline(vlut, d, shm.SHM_RECON_BILINEAR_FD)),
+                     ("bicubic_analytic", lambda: shm.query_baseline(vlut, d, shm.SHM_RECON_BICUBIC)),
+                     ("fast_bicubic_fd", lambda: shm.query_baseline(vlut, d, shm.SHM_RECON_FAST_BICUBIC_FD))):
+        o = fn().double()
+        n = o[:, :1] * wt - o[:, 1:]
+        n = n / n.norm(dim=1, keepdim=True)
+        a = torch.rad2deg(torch.acos(torch.clamp((n * tn).sum(dim=1), -1, 1)))
+        res[name] = {"mean_deg": a.mean().item(), "p95_deg": torch.quantile(a.float(), 0.95).item(),
+                     "value_rmse": (o[:, 0] - tvt).pow(2).mean().sqrt().item()}
     return res
 
 
@@ -485,6 +531,26 @@ def run_trace():
         res[name] = {"ms": ms, "rays_per_s": P / ms * 1e3, "hit_frac": hit.float().mean().item(),
                      "evals_per_s_upper": 32 * P / ms * 1e3}
         smp[name] = (t.cpu().numpy(), nrm.cpu().numpy())
+    # Sec. 3.1 adaptive budget: bisections follow the projected size (focal
+    # length of the 1080-pixel-high image, 1/8 pixel bracket), capped at 16;
+    # the same glyph seen from 3.5 and from 12 units
+    px = 540.0 / math.tan(math.radians(20.0))
+    _, _, _, _, ev = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o, d, n_bisect=8, normals=False)
+    hit = torch.isfinite(shm.trace(lut, (0.0, 0.0, 0.0), rmax, o, d)[0])
+    res["f32"]["mean_evals_hit"] = ev[hit].float().mean().item()
+    for name, eye in (("f32_adaptive", (0.0, 0.0, 3.5)), ("f32_adaptive_far", (0.0, 0.0, 12.0))):
+        o2_np, d2_np = workloads.camera_rays(1920, 1080, eye=eye)
+        o2, d2 = to_dev(o2_np), to_dev(d2_np)
+        fn = lambda: shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, px_per_unit=px, eps_px=0.125, n_bisect=16)
+        t2, _, _, _, ev2 = fn()
+        ms = t_gpu(fn, 5)
+        h2 = torch.isfinite(t2)
+        # the march does not depend on the budget: a fixed 16 spends 16 - k more
+        _, _, _, _, ev16 = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, n_bisect=16, normals=False)
+        k = 16 - (ev16[h2].float() - ev2[h2].float()).mean().item()
+        res[name] = {"ms": ms, "rays_per_s": P / ms * 1e3, "hit_frac": h2.float().mean().item(),
+                     "eye_distance": eye[2], "bisections": round(k, 3),
+                     "mean_evals_hit": ev2[h2].float().mean().item()}
     return res, smp
 
 

@@ -136,6 +136,18 @@ SHM_API int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, in
 SHM_API int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
                          int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
 
+/* Query of the rendered radius (Sec. 3.1) for a user scale s > 0:
+ * R = s r for a nonnegative function; with SHM_SIGNED, R = s |r| and
+ * grad R = s sign(r) grad r (chain rule of Sec. 3.4, after Eq. 10; sign(0)
+ * = 0), so the normal of Eq. 10 stays outward on negative lobes.
+ *   out [Q][4] (R, grad R), normal [Q][3] or NULL, sign [Q] int8 (+1, -1,
+ *   0; 0 also for an invalid direction) or NULL.
+ * Other arguments and the cell decision as in shm_query_value_grad. */
+#define SHM_SIGNED 1
+SHM_API int shm_query_scaled(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
+                             int64_t q_per_obj, float scale, int32_t flags, float* out, float* normal, int8_t* sign,
+                             hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: many objects of different face sizes and query counts in
  * one persistent launch.  Objects are described on the HOST:
@@ -229,10 +241,37 @@ SHM_API int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const fl
                      const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
                      float* out, float* normal, hipStream_t stream);
 
-/* Upper bound of the reconstructed R over one TEXEL LUT: the largest Bezier
- * control point of any cell's bicubic patch (convex hull property).  Writes
+/* The full form (Sec. 3.1): the surface is x(w) = c + R(w) w with the
+ * rendered radius R = scale r (scale |r| with SHM_SIGNED, as in
+ * shm_query_scaled), and the number of bisections can follow the glyph's
+ * projected size.  With px_per_unit > 0 (focal length in pixels), ray k
+ * bisects k_b = the fewest halvings that bring e = 2 rmax px_per_unit /
+ * (|o_k - c| n_march) pixels (the march bracket's width at the glyph's
+ * depth) down to eps_px, at most n_bisect; the decision is FP32 in this
+ * order, rounded to nearest without contraction.  px_per_unit = 0 keeps
+ * n_bisect fixed.  rmax must bound R (scale * shm_lut_rmax).
+ *   sign   [P] int8: sign of r at the hit (0 on a miss) or NULL
+ *   evals  [P] uint8: evaluations of F spent by the ray or NULL
+ * shm_trace_radial is this with scale 1, no flags, fixed counts. */
+typedef struct shm_trace_params {
+    float scale;          /* s > 0 */
+    int32_t flags;        /* 0 or SHM_SIGNED */
+    int32_t n_march;      /* >= 1 */
+    int32_t n_bisect;     /* fixed count, or the cap of the adaptive budget */
+    int32_t n_newton;     /* n_march + n_bisect + n_newton + 1 <= 64 */
+    float px_per_unit;    /* 0: fixed budget; > 0: adaptive */
+    float eps_px;         /* > 0 with an adaptive budget */
+} shm_trace_params;
+SHM_API int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax,
+                                const shm_trace_params* params, const float* ray_o, const float* ray_d, int64_t P,
+                                float* t_out, float* out, float* normal, int8_t* sign, uint8_t* evals,
+                                hipStream_t stream);
+
+/* Upper bound of the reconstructed r over one TEXEL LUT: the largest Bezier
+ * control point of any cell's bicubic patch (convex hull property); with
+ * flags = SHM_SIGNED the largest |control point|, which bounds |r|.  Writes
  * one float to rmax_out (device). */
-SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hipStream_t stream);
+SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, int32_t flags, float* rmax_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Mip chain (Sec. 4.7, Table lod): the next level (face size N/2, N even) of
@@ -254,7 +293,23 @@ SHM_API int shm_mip_level(const float* lut, int32_t N, int32_t mode, void* ws, s
                           hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Comparison paths of the paper's experiments (Sec. 4.2, 4.4, 4.5; Tables
+ * Radial depth of a triangle mesh (Sec. 4.9, mesh LOD impostors):
+ * depth[k] = max{t >= 0 : c + t w_k on the mesh surface}, w_k = dirs[k]
+ * normalised, 0 when the ray from c meets no triangle (or w_k is zero,
+ * NaN or Inf).  Every triangle is tested (a ray cast against the whole
+ * mesh, FP32; a hit needs barycentrics >= -4 ulp, so rays through shared
+ * edges are not lost).  Triangles with an index outside [0, n_verts) are
+ * skipped.  With the directions of shm_margin_dirs(N) and shm_bake_fd this
+ * bakes the mesh's impostor LUT.
+ *   verts  [n_verts][3] FP32;  tris [n_tris][3] int32;  center host float[3]
+ *   dirs   [P][3] FP32;  depth [P] FP32 (written)
+ * ---------------------------------------------------------------------- */
+SHM_API int shm_mesh_radial_depth(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                                  const float* center, const float* dirs, int64_t P, float* depth,
+                                  hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Comparison paths of the paper's experiments (Sec. 4.2, 4.5, 4.6; Tables
  * psnr_value, cost_extended, runtime), on the same GPU as the Hermite query.
  * shm_query_baseline reconstructs from a value-only LUT
  *   vlut [n_obj][6][N+4][N+4] FP32, texel p at u = (p - 3/2)/N (a two-texel
@@ -262,12 +317,14 @@ SHM_API int shm_mip_level(const float* lut, int32_t N, int32_t mode, void* ws, s
  *   SHM_RECON_NEAREST      nearest texel, zero gradient (1 fetch)
  *   SHM_RECON_BILINEAR_FD  bilinear value, chart derivatives by central
  *                          differences of 4 more bilinear lookups at u +- h,
- *                          v +- h (5 x 4 = 20 fetches)
+ *                          v +- h
  *   SHM_RECON_BICUBIC      16-tap Catmull-Rom value and analytic gradient
  *   SHM_RECON_FAST_BICUBIC_FD  "fast bicubic" (Table cost_extended): the
- *                          cubic B-spline of the samples evaluated as 4
- *                          bilinear lookups (FP32 weights), gradient as in
- *                          SHM_RECON_BILINEAR_FD (4 + 4 lookups)
+ *                          cubic B-spline of the samples (what 4 hardware
+ *                          bilinear fetches evaluate; FP32 weights here),
+ *                          gradient as in SHM_RECON_BILINEAR_FD
+ * Without texture units, all but nearest read the cell's 4 x 4 footprint
+ * once (the +-1 texel bilinear lookups fall inside it): 16 scalars.
  * then transports (r_u, r_v) to the spherical gradient as the Hermite query
  * does.  shm_sh_eval evaluates sum_k coeffs[k] Y_k and its spherical
  * gradient directly, without a LUT (coeffs [n_obj][(L+1)^2], L <= 16).

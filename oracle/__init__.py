@@ -372,3 +372,16 @@ def mip_level(lut, naive=False):
     out = np.empty(lut_shape(N // 2))
     lib().orc_mip_level(_p(lut), ctypes.c_int(N), ctypes.c_int(1 if naive else 0), _p(out))
     return out
+
+
+def mesh_radial_depth(verts, tris, center, dirs):
+    """R(w) = max{t >= 0 : c + t w on the mesh} per direction (0 if none),
+    by testing every triangle in FP64.  verts [V, 3], tris [T, 3] int."""
+    v = _f64(verts).reshape(-1, 3)
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    c = _f64(center).reshape(3)
+    d = _f32(dirs).reshape(-1, 3)
+    out = np.empty(d.shape[0])
+    lib().orc_mesh_radial_depth(_p(v), ctypes.c_int64(v.shape[0]), _p(t), ctypes.c_int64(t.shape[0]), _p(c), _p(d),
+                                ctypes.c_int64(d.shape[0]), _p(out))
+    return out

@@ -985,8 +985,8 @@ ORC_API void orc_trace_F(const double* lut, int N, const double* center, const d
 }
 
 /* ------------------------------------------------------------------------ */
-/* Comparison reconstructions of the paper's experiments (Sec. 4.1, 4.4,     */
-/* Tables psnr_value, cost_extended, runtime) on a value-only LUT.           */
+/* Comparison reconstructions of the paper's experiments (Sec. 4.2, 4.5, 4.6; */
+/* Tables psnr_value, cost_extended, runtime) on a value-only LUT.          */
 /* ------------------------------------------------------------------------ */
 /* Value-only LUT: vlut[face][q][p], p, q in 0..N+3, texel p centred at
  * u = (p - 3/2)/N (a two-texel gutter: the 4x4 bicubic footprint of any
@@ -1151,3 +1151,59 @@ ORC_API int orc_num_threads(void) { return omp_get_max_threads(); }
 #else
 ORC_API int orc_num_threads(void) { return 1; }
 #endif
+
+/* ------------------------------------------------------------------------ */
+/* Radial depth of a triangle mesh (Sec. 4.9, mesh LOD impostors)            */
+/* ------------------------------------------------------------------------ */
+/* R(w) = max{t >= 0 : c + t w lies on the mesh surface}: the farthest
+ * intersection of the ray from the centre c along the unit direction w with
+ * any triangle (closed triangles; 0 when the ray meets none).  Every
+ * triangle is tested (no acceleration structure), by solving
+ * c + t w = v0 + a (v1 - v0) + b (v2 - v0) with Cramer's rule and keeping
+ * a >= 0, b >= 0, a + b <= 1 (each with a 1e-12 tolerance, so that a ray
+ * through a shared edge or vertex meets the triangles around it).
+ * Triangles with an index outside [0, V) are skipped. */
+ORC_API void orc_mesh_radial_depth(const double* verts, int64_t V, const int32_t* tris, int64_t T, const double* c,
+                                   const float* dirs, int64_t P, double* depth)
+{
+    const double tol = 1e-12;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < P; ++r) {
+        double w[3] = {dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2]};
+        double n = sqrt(dot3(w, w));
+        double best = 0.0;
+        if (n > 0.0 && isfinite(n)) {
+            for (int k = 0; k < 3; ++k) w[k] /= n;
+            for (int64_t f = 0; f < T; ++f) {
+                int64_t i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
+                if (i0 < 0 || i0 >= V || i1 < 0 || i1 >= V || i2 < 0 || i2 >= V) continue;
+                double e1[3], e2[3], s[3];
+                for (int k = 0; k < 3; ++k) {
+                    e1[k] = verts[3 * i1 + k] - verts[3 * i0 + k];
+                    e2[k] = verts[3 * i2 + k] - verts[3 * i0 + k];
+                    s[k] = c[k] - verts[3 * i0 + k];
+                }
+                /* [-w e1 e2] (t a b)^T = s */
+                double m[3][3];
+                for (int k = 0; k < 3; ++k) { m[k][0] = -w[k]; m[k][1] = e1[k]; m[k][2] = e2[k]; }
+                double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                             m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                             m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+                if (det == 0.0) continue; /* ray parallel to the triangle's plane */
+                double x[3];
+                for (int col = 0; col < 3; ++col) {
+                    double a[3][3];
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) a[i][j] = (j == col) ? s[i] : m[i][j];
+                    double dc = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                                a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                                a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+                    x[col] = dc / det;
+                }
+                double t = x[0], a = x[1], b = x[2];
+                if (a >= -tol && b >= -tol && a + b <= 1.0 + tol && t >= 0.0 && t > best) best = t;
+            }
+        }
+        depth[r] = best;
+    }
+}

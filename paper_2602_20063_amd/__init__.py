@@ -22,6 +22,7 @@ SHM_F32, SHM_F16 = 0, 1
 SHM_LAYOUT_TEXEL, SHM_LAYOUT_CELL = 0, 1
 SHM_MAX_N, SHM_MAX_L = 1024, 16
 SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC, SHM_RECON_FAST_BICUBIC_FD = 0, 1, 2, 3
+SHM_SIGNED = 1
 
 
 class ShmError(RuntimeError):
@@ -41,6 +42,12 @@ class shm_launch_shape(ctypes.Structure):
 
     def as_dict(self):
         return {"block": self.block, "qpt": self.qpt, "tile": self.tile, "grid_per_cu": self.grid_per_cu}
+
+
+class shm_trace_params(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_float), ("flags", ctypes.c_int32), ("n_march", ctypes.c_int32),
+                ("n_bisect", ctypes.c_int32), ("n_newton", ctypes.c_int32), ("px_per_unit", ctypes.c_float),
+                ("eps_px", ctypes.c_float)]
 
 
 _VP = ctypes.c_void_p
@@ -73,9 +80,16 @@ SIGNATURES = {
     "shm_query_backward": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _I32, _VP]),
     "shm_trace_radial": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP,
                                         _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
-    "shm_lut_rmax": (ctypes.c_int, [_VP, _I32, _I32, _VP, _VP]),
+    "shm_trace_radial_ex": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float,
+                                           ctypes.POINTER(shm_trace_params), _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP,
+                                           _VP]),
+    "shm_lut_rmax": (ctypes.c_int, [_VP, _I32, _I32, _I32, _VP, _VP]),
+    "shm_query_scaled": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I64, _VP, _I64, ctypes.c_float, _I32, _VP, _VP, _VP,
+                                        _VP]),
     "shm_mip_level_workspace": (_SZ, [_I32]),
     "shm_mip_level": (ctypes.c_int, [_VP, _I32, _I32, _VP, _SZ, _VP, _VP]),
+    "shm_mesh_radial_depth": (ctypes.c_int, [_VP, _I64, _VP, _I64, ctypes.POINTER(ctypes.c_float), _VP, _I64, _VP,
+                                             _VP]),
     "shm_query_baseline": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _I32, _VP, _VP]),
     "shm_sh_eval": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP]),
 }
@@ -206,8 +220,47 @@ def shm_trace_radial(lut, dtype, N, center, rmax, ray_o, ray_d, P, n_march, n_bi
                                          n_bisect, n_newton, _ptr(t_out), _ptr(out), _ptr(normal), _stream(stream)))
 
 
-def shm_lut_rmax(lut, dtype, N, rmax_out, stream=None):
-    return _check(lib().shm_lut_rmax(_ptr(lut), dtype, N, _ptr(rmax_out), _stream(stream)))
+def shm_trace_radial_ex(lut, dtype, N, center, rmax, params, ray_o, ray_d, P, t_out, out, normal=None, sign=None,
+                        evals=None, stream=None):
+    c = (ctypes.c_float * 3)(*[float(x) for x in center])
+    return _check(lib().shm_trace_radial_ex(_ptr(lut), dtype, N, c, float(rmax), ctypes.byref(params), _ptr(ray_o),
+                                            _ptr(ray_d), P, _ptr(t_out), _ptr(out), _ptr(normal), _ptr(sign),
+                                            _ptr(evals), _stream(stream)))
+
+
+def shm_lut_rmax(lut, dtype, N, flags, rmax_out, stream=None):
+    return _check(lib().shm_lut_rmax(_ptr(lut), dtype, N, flags, _ptr(rmax_out), _stream(stream)))
+
+
+def shm_query_scaled(lut, dtype, layout, N, n_obj, dirs, q_per_obj, scale, flags, out, normal=None, sign=None,
+                     stream=None):
+    return _check(lib().shm_query_scaled(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, float(scale),
+                                         flags, _ptr(out), _ptr(normal), _ptr(sign), _stream(stream)))
+
+
+def shm_mesh_radial_depth(verts, n_verts, tris, n_tris, center, dirs, P, depth, stream=None):
+    c = (ctypes.c_float * 3)(*[float(x) for x in center])
+    return _check(lib().shm_mesh_radial_depth(_ptr(verts), n_verts, _ptr(tris), n_tris, c, _ptr(dirs), P,
+                                              _ptr(depth), _stream(stream)))
+
+
+def mesh_radial_depth(verts, tris, center, dirs, stream=None):
+    """verts [V, 3] FP32, tris [T, 3] int32 (device), center (3 floats),
+    dirs [P, 3] -> depth [P] FP32."""
+    verts = verts.contiguous()
+    tris = tris.contiguous()
+    P = dirs.shape[0]
+    depth = torch.empty(P, dtype=torch.float32, device=dirs.device)
+    shm_mesh_radial_depth(verts, verts.shape[0], tris, tris.shape[0], center, dirs, P, depth, stream)
+    return depth
+
+
+def bake_mesh(verts, tris, center, N, dtype=torch.float32, stream=None):
+    """Impostor LUT of a mesh: radial depth on the margin grid of face size
+    N, then the finite-difference bake.  LUT [1, 6, N+2, N+2, 4]."""
+    d = margin_dirs(N, device=verts.device, stream=stream).reshape(-1, 3)
+    depth = mesh_radial_depth(verts, tris, center, d, stream)
+    return bake_fd(depth.reshape(1, 6, N + 4, N + 4), N, dtype=dtype, stream=stream)
 
 
 def shm_mip_level_workspace(N):
@@ -378,10 +431,10 @@ def bake_fd(samples, N, dtype=torch.float32, stream=None):
     return lut
 
 
-def lut_rmax(lut, stream=None):
+def lut_rmax(lut, signed=False, stream=None):
     N = lut_n(lut)
     r = torch.empty(1, dtype=torch.float32, device=lut.device)
-    shm_lut_rmax(lut, _dtype_code(lut), N, r, stream)
+    shm_lut_rmax(lut, _dtype_code(lut), N, SHM_SIGNED if signed else 0, r, stream)
     return r
 
 
@@ -401,6 +454,42 @@ def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, n
     shm_trace_radial(lut, _dtype_code(lut), N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t, out,
                      nrm, stream)
     return t, out, nrm
+
+
+def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_unit=0.0, eps_px=0.125, n_march=20,
+             n_bisect=16, n_newton=3, normals=True, stream=None):
+    """Rendered-radius trace with the adaptive bisection budget: returns
+    t, (R, grad), normal, sign of r (int8), F evaluations per ray (uint8)."""
+    N = lut_n(lut)
+    P = ray_o.shape[0]
+    dev = ray_o.device
+    t = torch.empty(P, dtype=torch.float32, device=dev)
+    out = torch.empty((P, 4), dtype=torch.float32, device=dev)
+    nrm = torch.empty((P, 3), dtype=torch.float32, device=dev) if normals else None
+    sgn = torch.empty(P, dtype=torch.int8, device=dev)
+    ev = torch.empty(P, dtype=torch.uint8, device=dev)
+    prm = shm_trace_params(float(scale), SHM_SIGNED if signed else 0, n_march, n_bisect, n_newton, float(px_per_unit),
+                           float(eps_px))
+    shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, sgn, ev, stream)
+    return t, out, nrm, sgn, ev
+
+
+def query_scaled(lut, dirs, scale=1.0, signed=False, layout=None, normals=True, stream=None):
+    """Rendered-radius query of one LUT (or n_obj LUTs with equal query
+    counts): (R, grad), normal, sign of r (int8)."""
+    if layout is None:
+        layout = SHM_LAYOUT_CELL if lut.shape[-1] == 16 else SHM_LAYOUT_TEXEL
+    N = lut_n(lut, layout)
+    per = 6 * (N + 2) * (N + 2) * 4 if layout == SHM_LAYOUT_TEXEL else 6 * (N + 1) * (N + 1) * 16
+    n_obj = lut.numel() // per
+    Q = dirs.shape[0]
+    dev = dirs.device
+    out = torch.empty((Q, 4), dtype=torch.float32, device=dev)
+    nrm = torch.empty((Q, 3), dtype=torch.float32, device=dev) if normals else None
+    sgn = torch.empty(Q, dtype=torch.int8, device=dev)
+    shm_query_scaled(lut, _dtype_code(lut), layout, N, n_obj, dirs, Q // n_obj, scale, SHM_SIGNED if signed else 0, out,
+                     nrm, sgn, stream)
+    return out, nrm, sgn
 
 
 class BackwardContext:

@@ -50,15 +50,21 @@ int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dty
                    hipStream_t stream);
 int launch_margin_dirs(int N, float* dirs, hipStream_t stream);
 int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, void* lut, hipStream_t stream);
-int launch_lut_rmax(const void* lut, int dtype, int N, float* rmax_out, hipStream_t stream);
+int launch_lut_rmax(const void* lut, int dtype, int N, int flags, float* rmax_out, hipStream_t stream);
 size_t backward_workspace_bytes(int N, int64_t n_obj, int64_t q_per_obj);
 int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream);
 int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream);
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
                     float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
-int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, const float* ray_o,
-                 const float* ray_d, int64_t P, int n_march, int n_bisect, int n_newton, float* t_out, float* out,
-                 float* normal, hipStream_t stream);
+int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
+                 float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int n_march,
+                 int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign, uint8_t* evals,
+                 hipStream_t stream);
+int launch_query_scaled(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
+                        int64_t q_per_obj, float scale, int flags, float* out, float* normal, int8_t* sign,
+                        hipStream_t stream);
+int launch_mesh_depth(const float* verts, int64_t V, const int32_t* tris, int64_t T, const float* center,
+                      const float* dirs, int64_t P, float* depth, hipStream_t stream);
 size_t mip_workspace_bytes(int N);
 int launch_mip_level(const float* lut, int N, int mode, float* ws, float* out, hipStream_t stream);
 
@@ -498,30 +504,91 @@ int shm_query_backward(const float* lut, int32_t N, int64_t n_obj, const float* 
 }
 
 // ---------------------------------------------------------------------------
-int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax, const float* ray_o,
-                     const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
-                     float* out, float* normal, hipStream_t stream)
+static int check_trace_params(const shm_trace_params* tp)
+{
+    if (!tp) return fail(SHM_ERR_INVALID_ARG, "trace: null params");
+    if (!(tp->scale > 0.0f) || !std::isfinite(tp->scale)) return fail(SHM_ERR_INVALID_ARG, "trace: scale must be positive and finite");
+    if (tp->flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "trace: unknown flags 0x%x", tp->flags);
+    if (tp->n_march < 1 || tp->n_bisect < 0 || tp->n_newton < 0 || tp->n_march + tp->n_bisect + tp->n_newton + 1 > 64)
+        return fail(SHM_ERR_INVALID_ARG, "trace: iteration counts must satisfy n_march >= 1 and total <= 64");
+    if (!std::isfinite(tp->px_per_unit) || tp->px_per_unit < 0.0f)
+        return fail(SHM_ERR_INVALID_ARG, "trace: px_per_unit must be finite and >= 0");
+    if (tp->px_per_unit > 0.0f && !(tp->eps_px > 0.0f && std::isfinite(tp->eps_px)))
+        return fail(SHM_ERR_INVALID_ARG, "trace: eps_px must be positive and finite with an adaptive budget");
+    return SHM_OK;
+}
+
+int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax,
+                        const shm_trace_params* params, const float* ray_o, const float* ray_d, int64_t P, float* t_out,
+                        float* out, float* normal, int8_t* sign, uint8_t* evals, hipStream_t stream)
 {
     clear_error();
     if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "trace: bad dtype or N");
     if (P < 0) return fail(SHM_ERR_INVALID_ARG, "trace: negative ray count");
     if (!(rmax > 0.0f) || !std::isfinite(rmax)) return fail(SHM_ERR_INVALID_ARG, "trace: rmax must be positive and finite");
-    if (n_march < 1 || n_bisect < 0 || n_newton < 0 || n_march + n_bisect + n_newton + 1 > 64)
-        return fail(SHM_ERR_INVALID_ARG, "trace: iteration counts must satisfy n_march >= 1 and total <= 64");
+    int rc = check_trace_params(params);
+    if (rc) return rc;
     if (!center) return fail(SHM_ERR_INVALID_ARG, "trace: null center");
     if (P == 0) return SHM_OK;
     if (!lut || !ray_o || !ray_d || !t_out || !out) return fail(SHM_ERR_INVALID_ARG, "trace: null pointer");
     if (!aligned(lut, dtype == SHM_F16 ? 8 : 16) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "trace: misaligned buffer");
-    return launch_trace(lut, dtype, N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal, stream);
+    return launch_trace(lut, dtype, N, center, rmax, params->scale, params->flags, params->px_per_unit, params->eps_px,
+                        ray_o, ray_d, P, params->n_march, params->n_bisect, params->n_newton, t_out, out, normal, sign,
+                        evals, stream);
 }
 
-int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, float* rmax_out, hipStream_t stream)
+int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax, const float* ray_o,
+                     const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
+                     float* out, float* normal, hipStream_t stream)
+{
+    const shm_trace_params tp = {1.0f, 0, n_march, n_bisect, n_newton, 0.0f, 0.0f};
+    return shm_trace_radial_ex(lut, dtype, N, center, rmax, &tp, ray_o, ray_d, P, t_out, out, normal, nullptr, nullptr,
+                               stream);
+}
+
+int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, int32_t flags, float* rmax_out, hipStream_t stream)
 {
     clear_error();
     if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: bad dtype or N");
+    if (flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: unknown flags 0x%x", flags);
     if (!lut || !rmax_out) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: null pointer");
     if (!aligned(rmax_out, 4)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: misaligned output");
-    return launch_lut_rmax(lut, dtype, N, rmax_out, stream);
+    return launch_lut_rmax(lut, dtype, N, flags, rmax_out, stream);
+}
+
+int shm_query_scaled(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
+                     int64_t q_per_obj, float scale, int32_t flags, float* out, float* normal, int8_t* sign,
+                     hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype) || !valid_layout(layout) || !valid_N(N))
+        return fail(SHM_ERR_INVALID_ARG, "query_scaled: bad dtype, layout or N");
+    if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query_scaled: negative size");
+    if (!(scale > 0.0f) || !std::isfinite(scale)) return fail(SHM_ERR_INVALID_ARG, "query_scaled: scale must be positive and finite");
+    if (flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "query_scaled: unknown flags 0x%x", flags);
+    if (n_obj * q_per_obj == 0) return SHM_OK;
+    if (!lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "query_scaled: null pointer");
+    const size_t al = (dtype == SHM_F16 && layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(out, 16) || !aligned(dirs, 4) || (normal && !aligned(normal, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "query_scaled: misaligned buffer (lut %zu B, out 16 B)", al);
+    return launch_query_scaled(lut, dtype, layout, N, n_obj, dirs, q_per_obj, scale, flags, out, normal, sign, stream);
+}
+
+int shm_mesh_radial_depth(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                          const float* center, const float* dirs, int64_t P, float* depth, hipStream_t stream)
+{
+    clear_error();
+    if (n_verts < 0 || n_tris < 0 || P < 0) return fail(SHM_ERR_INVALID_ARG, "mesh_depth: negative size");
+    if (n_verts > 0x7fffffffll) return fail(SHM_ERR_UNSUPPORTED, "mesh_depth: more than 2^31 - 1 vertices");
+    if (!center) return fail(SHM_ERR_INVALID_ARG, "mesh_depth: null center");
+    if (!std::isfinite(center[0]) || !std::isfinite(center[1]) || !std::isfinite(center[2]))
+        return fail(SHM_ERR_INVALID_ARG, "mesh_depth: center must be finite");
+    if (P == 0) return SHM_OK;
+    if (!dirs || !depth) return fail(SHM_ERR_INVALID_ARG, "mesh_depth: null dirs or depth");
+    if (n_tris > 0 && (!tris || !verts)) return fail(SHM_ERR_INVALID_ARG, "mesh_depth: null mesh");
+    if (!aligned(depth, 4) || !aligned(dirs, 4) || (tris && !aligned(tris, 4)) || (verts && !aligned(verts, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "mesh_depth: misaligned buffer");
+    return launch_mesh_depth(verts, n_verts, tris, n_tris, center, dirs, P, depth, stream);
 }
 
 // ---------------------------------------------------------------------------

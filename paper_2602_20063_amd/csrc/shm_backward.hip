@@ -305,6 +305,36 @@ __device__ __forceinline__ void query_weights(float gR, float nlu, float nlv, co
     }
 }
 
+// dL/d dirs of one query: second chart derivatives of the patch plus the
+// derivative of the chart map (a = sc/ma, b = tc/ma) at d.  Not inlined, so
+// that every kernel variant runs the same instructions and gets the same
+// bits whichever other gradients it computes.
+__device__ __noinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int N, Loc L, float4 gq, float3 M,
+                                         float3 S, float3 T, float x, float y, float z)
+{
+    const float Nf = (float)N;
+    const float A = L.a, B = L.b;
+    const float3 Sa = make_float3(S.x - A * M.x, S.y - A * M.y, S.z - A * M.z);
+    const float3 Tb = make_float3(T.x - B * M.x, T.y - B * M.y, T.z - B * M.z);
+    const float gS = gq.y * Sa.x + gq.z * Sa.y + gq.w * Sa.z;
+    const float gT = gq.y * Tb.x + gq.z * Tb.y + gq.w * Tb.z;
+    const float rho = sqrtf(1.0f + A * A + B * B);
+    const float kk2 = 0.5f * rho;
+    const float gR = gq.x;
+    const Foot F = load_texel_f32(lut_obj, N, L);
+    const Patch2 Pp = hermite2(F, L.s, L.t);
+    const float gM = gq.y * M.x + gq.z * M.y + gq.w * M.z;
+    const float ru = Nf * Pp.rs, rv = Nf * Pp.rt;
+    const float hN2 = 0.5f * Nf * Nf;
+    const float common = (ru * gS + rv * gT) / (2.0f * rho);
+    const float dLda = 0.5f * Nf * gR * Pp.rs + A * common + kk2 * (hN2 * Pp.rss * gS - ru * gM + hN2 * Pp.rst * gT);
+    const float dLdb = 0.5f * Nf * gR * Pp.rt + B * common + kk2 * (hN2 * Pp.rst * gS + hN2 * Pp.rtt * gT - rv * gM);
+    const float im = 1.0f / (x * M.x + y * M.y + z * M.z);
+    return make_float3((dLda * Sa.x + dLdb * Tb.x) * im, (dLda * Sa.y + dLdb * Tb.y) * im,
+                       (dLda * Sa.z + dLdb * Tb.z) * im);
+}
+
+template <bool LUT, bool DIRS>
 __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
                                                            int64_t Q, const float* __restrict__ dirs,
                                                            const float* __restrict__ gout,
@@ -327,6 +357,16 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     const int64_t cbase = fo * (int64_t)C * C;
     const int i_lo = max(p0 - 1, 0), i_hi = min(p0 + BT - 1, N);  // the tile's cell columns (p0 <= N + 1)
     const int tid = threadIdx.x;
+    // this lane's cell: its segment bounds load beside the row setup
+    const int ci = tid % BC, cj = tid / BC;
+    const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
+    const bool cell_ok = LUT && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
+    int64_t cs_lo = 0, cs_hi = 0;
+    if (cell_ok) {
+        const int64_t c = cbase + (int64_t)j0c * C + i0c;
+        cs_lo = cs[c];
+        cs_hi = cs[c + 1];
+    }
     if (tid < BC) {
         const int j0 = q0 - 1 + tid;
         int64_t a = 0, e = 0;
@@ -344,15 +384,11 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         for (int k = 1; k <= BC; ++k) row_off[k] += row_off[k - 1];
     }
     __syncthreads();
-    // this lane's cell and its segment in the concatenated list
-    const int ci = tid % BC, cj = tid / BC;
-    const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
     int64_t seg_lo = 0, seg_hi = 0;
-    if (grad_lut && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N) {
-        const int64_t c = cbase + (int64_t)j0c * C + i0c;
+    if (cell_ok) {
         const int64_t rs = row_start[cj], len = row_off[cj + 1] - row_off[cj];
-        const int64_t a = min(max((int64_t)cs[c] - rs, (int64_t)0), len);
-        const int64_t e = min(max((int64_t)cs[c + 1] - rs, a), len);
+        const int64_t a = min(max(cs_lo - rs, (int64_t)0), len);
+        const int64_t e = min(max(cs_hi - rs, a), len);
         seg_lo = row_off[cj] + a;
         seg_hi = row_off[cj] + e;
     }
@@ -363,61 +399,78 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     float4 acc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the query at list position g and its cell row (Q past the end)
+    auto query_at = [&](int64_t g, int& r) -> int64_t {
+        r = 0;
+        if (g >= total) return Q;
+        while (g >= row_off[r + 1]) ++r;
+        return perm[row_start[r] + (g - row_off[r])];
+    };
+    // software pipeline: round k + 1's index, direction and upstream
+    // gradient loads are in flight while round k computes and reduces
+    int r_cur;
+    int64_t q_cur = query_at(tid, r_cur);
+    float x = 0.f, y = 0.f, z = 0.f;
+    float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (q_cur < Q) {
+        x = dirs[3 * q_cur];
+        y = dirs[3 * q_cur + 1];
+        z = dirs[3 * q_cur + 2];
+        gq = reinterpret_cast<const float4*>(gout)[q_cur];
+    }
     for (int64_t base = 0; base < total; base += BWD_THREADS) {
-        const int64_t g = base + tid;
-        if (g < total) {
-            int r = 0;
-            while (g >= row_off[r + 1]) ++r;
-            const int64_t q = perm[row_start[r] + (g - row_off[r])];
-            float4 w[4];
+        int r_next;
+        const int64_t q_next = query_at(base + BWD_THREADS + tid, r_next);
+        float4 w[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (q < Q) {
-                const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
-                const Loc L = locate(x, y, z, N);  // the cell of row r (keys come from the same decision)
-                const float4 gq = reinterpret_cast<const float4*>(gout)[q];
+        for (int k = 0; k < 4; ++k) w[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q_cur < Q) {
+            const Loc L = locate(x, y, z, N);  // the cell of row r_cur (keys come from the same decision)
+            if constexpr (LUT) {
                 const float A = L.a, B = L.b;
-                const float3 Sa = make_float3(S.x - A * M.x, S.y - A * M.y, S.z - A * M.z);
-                const float3 Tb = make_float3(T.x - B * M.x, T.y - B * M.y, T.z - B * M.z);
-                const float gS = gq.y * Sa.x + gq.z * Sa.y + gq.w * Sa.z;
-                const float gT = gq.y * Tb.x + gq.z * Tb.y + gq.w * Tb.z;
-                const float rho = sqrtf(1.0f + A * A + B * B);
-                const float kk2 = 0.5f * rho;
-                const float nlu = Nf * kk2 * gS, nlv = Nf * kk2 * gT, gR = gq.x;
-                if (grad_lut) query_weights(gR, nlu, nlv, basis1(L.s), basis1(L.t), w);
-                if (grad_dirs && L.i0 >= p0 && r >= 1) {  // the tile owns the cell
-                    const Foot F = load_texel_f32(lut + obj * lut_elems, N, L);
-                    const Patch2 Pp = hermite2(F, L.s, L.t);
-                    const float gM = gq.y * M.x + gq.z * M.y + gq.w * M.z;
-                    const float ru = Nf * Pp.rs, rv = Nf * Pp.rt;
-                    const float hN2 = 0.5f * Nf * Nf;
-                    const float common = (ru * gS + rv * gT) / (2.0f * rho);
-                    const float dLda = 0.5f * Nf * gR * Pp.rs + A * common + kk2 * (hN2 * Pp.rss * gS - ru * gM + hN2 * Pp.rst * gT);
-                    const float dLdb = 0.5f * Nf * gR * Pp.rt + B * common + kk2 * (hN2 * Pp.rst * gS + hN2 * Pp.rtt * gT - rv * gM);
-                    const float im = 1.0f / (x * M.x + y * M.y + z * M.z);
-                    grad_dirs[3 * q] = (dLda * Sa.x + dLdb * Tb.x) * im;
-                    grad_dirs[3 * q + 1] = (dLda * Sa.y + dLdb * Tb.y) * im;
-                    grad_dirs[3 * q + 2] = (dLda * Sa.z + dLdb * Tb.z) * im;
+                const float gS = gq.y * (S.x - A * M.x) + gq.z * (S.y - A * M.y) + gq.w * (S.z - A * M.z);
+                const float gT = gq.y * (T.x - B * M.x) + gq.z * (T.y - B * M.y) + gq.w * (T.z - B * M.z);
+                const float kk2 = 0.5f * sqrtf(1.0f + A * A + B * B);
+                query_weights(gq.x, Nf * kk2 * gS, Nf * kk2 * gT, basis1(L.s), basis1(L.t), w);
+            }
+            if (DIRS && L.i0 >= p0 && r_cur >= 1) {  // the tile owns the cell
+                const float3 gd = dirs_grad(lut + obj * lut_elems, N, L, gq, M, S, T, x, y, z);
+                grad_dirs[3 * q_cur] = gd.x;
+                grad_dirs[3 * q_cur + 1] = gd.y;
+                grad_dirs[3 * q_cur + 2] = gd.z;
+            }
+        }
+        if constexpr (LUT) {
+            if (base + tid < total) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
+            }
+        }
+        if (q_next < Q) {
+            x = dirs[3 * q_next];
+            y = dirs[3 * q_next + 1];
+            z = dirs[3 * q_next + 2];
+            gq = reinterpret_cast<const float4*>(gout)[q_next];
+        }
+        q_cur = q_next;
+        r_cur = r_next;
+        if constexpr (LUT) {
+            __syncthreads();
+            const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
+            for (int k2 = lo; k2 < hi; ++k2) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = slot[k2][k];
+                    acc[k].x += v.x;
+                    acc[k].y += v.y;
+                    acc[k].z += v.z;
+                    acc[k].w += v.w;
                 }
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
+            __syncthreads();
         }
-        __syncthreads();
-        const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
-        for (int k2 = lo; k2 < hi; ++k2) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float4 v = slot[k2][k];
-                acc[k].x += v.x;
-                acc[k].y += v.y;
-                acc[k].z += v.z;
-                acc[k].w += v.w;
-            }
-        }
-        __syncthreads();
     }
-    if (!grad_lut) return;
+    if constexpr (!LUT) return;
 #pragma unroll
     for (int k = 0; k < 4; ++k) slot[tid][k] = acc[k];
     __syncthreads();
@@ -483,8 +536,13 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     const int tpf = (N + 2 + BT - 1) / BT;
     const int64_t tiles = n_obj * 6ll * tpf * tpf;
     if (tiles > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "backward: too many tiles for one launch");
-    hipLaunchKernelGGL(k_bwd_fused, dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N, texel_elems(N),
-                       W.Q, dirs, gout, perm, cs, tpf, grad_lut, grad_dirs);
+#define SHM_B(A, B)                                                                                                  \
+    hipLaunchKernelGGL((k_bwd_fused<A, B>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,             \
+                       texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, grad_lut, grad_dirs)
+    if (grad_lut && grad_dirs) SHM_B(true, true);
+    else if (grad_lut) SHM_B(true, false);
+    else SHM_B(false, true);
+#undef SHM_B
     SHM_LAUNCH_CHECK();
     if (grad_dirs) {
         hipLaunchKernelGGL(k_bwd_invalid, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, perm, cs, W.n_cells,

@@ -493,13 +493,14 @@ int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, vo
 
 // ---------------------------------------------------------------------------
 // Bernstein bound of the reconstruction (largest Bezier control point of any
-// cell).  1-D Hermite (p0, m0, p1, m1) -> Bezier (p0, p0+m0/3, p1-m1/3, p1),
-// tensor product over the cell.  Max-reduction through the order-preserving
-// integer image of non-negative floats is exact; a negative bound clamps to
-// 0 (R >= 0 for a star-shaped surface).
+// cell; with SHM_SIGNED the largest |control point|, which bounds |r|).
+// 1-D Hermite (p0, m0, p1, m1) -> Bezier (p0, p0+m0/3, p1-m1/3, p1), tensor
+// product over the cell.  Max-reduction through the order-preserving integer
+// image of non-negative floats is exact; a negative bound clamps to 0
+// (R >= 0 for a star-shaped surface).
 // ---------------------------------------------------------------------------
 template <bool F16>
-__global__ void k_lut_rmax(const void* __restrict__ lut, int N, unsigned int* __restrict__ out_bits)
+__global__ void k_lut_rmax(const void* __restrict__ lut, int N, int absval, unsigned int* __restrict__ out_bits)
 {
     const int C = N + 1, P = N + 2;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -532,7 +533,13 @@ __global__ void k_lut_rmax(const void* __restrict__ lut, int N, unsigned int* __
             H[3][b] = G[2][b];
         }
         for (int a = 0; a < 4; ++a) {
-            const float z0 = H[a][0], z1 = H[a][0] + H[a][1] / 3.0f, z2 = H[a][2] - H[a][3] / 3.0f, z3 = H[a][2];
+            float z0 = H[a][0], z1 = H[a][0] + H[a][1] / 3.0f, z2 = H[a][2] - H[a][3] / 3.0f, z3 = H[a][2];
+            if (absval) {
+                z0 = fabsf(z0);
+                z1 = fabsf(z1);
+                z2 = fabsf(z2);
+                z3 = fabsf(z3);
+            }
             best = fmaxf(best, fmaxf(fmaxf(z0, z1), fmaxf(z2, z3)));
         }
     }
@@ -545,15 +552,16 @@ __global__ void k_bits_to_float(const unsigned int* bits, float* out) { *out = _
 
 __global__ void k_fill_u32(unsigned int* p, unsigned int v) { *p = v; }
 
-int launch_lut_rmax(const void* lut, int dtype, int N, float* rmax_out, hipStream_t stream)
+int launch_lut_rmax(const void* lut, int dtype, int N, int flags, float* rmax_out, hipStream_t stream)
 {
     unsigned int* bits = reinterpret_cast<unsigned int*>(rmax_out);  // reuse the output word
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, bits, 0u);
     const int n = 6 * (N + 1) * (N + 1);
+    const int absval = (flags & SHM_SIGNED) ? 1 : 0;
     if (dtype == SHM_F16)
-        hipLaunchKernelGGL(k_lut_rmax<true>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, bits);
+        hipLaunchKernelGGL(k_lut_rmax<true>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, absval, bits);
     else
-        hipLaunchKernelGGL(k_lut_rmax<false>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, bits);
+        hipLaunchKernelGGL(k_lut_rmax<false>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, absval, bits);
     hipLaunchKernelGGL(k_bits_to_float, dim3(1), dim3(1), 0, stream, bits, rmax_out);
     SHM_LAUNCH_CHECK();
     return SHM_OK;

@@ -1,12 +1,15 @@
-// Comparison paths of the paper's experiments (Sec. 4.1-4.5), run on the
+// Comparison paths of the paper's experiments (Sec. 4.2, 4.5, 4.6), run on the
 // same GPU as the Hermite query:
 //   * value-only LUT reconstructions (Table cost_extended, Table runtime):
 //     nearest texel, bilinear with finite-difference normals (4 extra
 //     bilinear lookups at u +- h, v +- h), 16-tap Catmull-Rom bicubic with its
-//     analytic gradient, and "fast bicubic": the cubic B-spline evaluated as
-//     four bilinear lookups, with the same finite-difference gradient;
+//     analytic gradient, and "fast bicubic": the cubic B-spline (what four
+//     hardware-bilinear fetches evaluate), with the same finite-difference
+//     gradient.  Without texture units every method but nearest reads the
+//     4 x 4 texel footprint of its cell once into registers (the bilinear
+//     lookups at +-1 texel fall inside it) and filters from there;
 //   * direct SH evaluation without any LUT (the paper's per-fragment SH
-//     baseline, Sec. 4.5).
+//     baseline, Sec. 4.6).
 // The value-only LUT is vlut[obj][face][q][p], p, q in 0..N+3, texel p at
 // u = (p - 3/2)/N (two-texel gutter, the sample grid of shm_margin_dirs).
 #include "shm_device.hpp"
@@ -19,50 +22,6 @@ __device__ __forceinline__ float vl_at(const float* __restrict__ vl, int P, int 
     p = p < 0 ? 0 : (p > P - 1 ? P - 1 : p);
     q = q < 0 ? 0 : (q > P - 1 ? P - 1 : q);
     return vl[((int64_t)face * P + q) * P + p];
-}
-
-__device__ __forceinline__ float bilinear_at(const float* __restrict__ vl, int N, int face, float a, float b)
-{
-    const int P = N + 4;
-    const float fu = (a + 1.0f) * 0.5f * (float)N + 1.5f, fv = (b + 1.0f) * 0.5f * (float)N + 1.5f;
-    const int i0 = (int)floorf(fu), j0 = (int)floorf(fv);
-    const float s = fu - (float)i0, t = fv - (float)j0;
-    const float v00 = vl_at(vl, P, face, i0, j0), v10 = vl_at(vl, P, face, i0 + 1, j0);
-    const float v01 = vl_at(vl, P, face, i0, j0 + 1), v11 = vl_at(vl, P, face, i0 + 1, j0 + 1);
-    const float r0 = v00 + s * (v10 - v00), r1 = v01 + s * (v11 - v01);
-    return r0 + t * (r1 - r0);
-}
-
-// bilinear lookup between texels (i, j) and (i+1, j+1) at fractions (fx, fy)
-__device__ __forceinline__ float bilinear_ij(const float* __restrict__ vl, int P, int face, int i, int j, float fx,
-                                             float fy)
-{
-    const float v00 = vl_at(vl, P, face, i, j), v10 = vl_at(vl, P, face, i + 1, j);
-    const float v01 = vl_at(vl, P, face, i, j + 1), v11 = vl_at(vl, P, face, i + 1, j + 1);
-    const float r0 = v00 + fx * (v10 - v00), r1 = v01 + fx * (v11 - v01);
-    return r0 + fy * (r1 - r0);
-}
-
-// Cubic B-spline weights w0..w3 (taps -1..2) at t, folded into two bilinear
-// lookups per axis: w0 v[-1] + w1 v[0] = g0 lerp(v[-1], v[0], w1/g0) with
-// g0 = w0 + w1, and w2 v[1] + w3 v[2] = g1 lerp(v[1], v[2], w3/g1) with
-// g1 = w2 + w3.  Both g are >= 1/6 on [0, 1).
-struct Fold {
-    float g0, g1, f0, f1;
-};
-__device__ __forceinline__ Fold bspline_fold(float t)
-{
-    const float t2 = t * t, t3 = t2 * t, m = 1.0f - t;
-    const float w0 = m * m * m * (1.0f / 6.0f);
-    const float w1 = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
-    const float w2 = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
-    const float w3 = t3 * (1.0f / 6.0f);
-    Fold F;
-    F.g0 = w0 + w1;
-    F.g1 = w2 + w3;
-    F.f0 = w1 / F.g0;
-    F.f1 = w3 / F.g1;
-    return F;
 }
 
 template <int METHOD>
@@ -89,63 +48,90 @@ __global__ __launch_bounds__(256) void k_query_baseline(const float* __restrict_
     if constexpr (METHOD == SHM_RECON_NEAREST) {
         const float fu = (a + 1.0f) * 0.5f * Nf + 1.5f, fv = (bb + 1.0f) * 0.5f * Nf + 1.5f;
         R = vl_at(vl, P, L.face, (int)floorf(fu + 0.5f), (int)floorf(fv + 0.5f));
-    } else if constexpr (METHOD == SHM_RECON_BILINEAR_FD || METHOD == SHM_RECON_FAST_BICUBIC_FD) {
-        const float da = 2.0f / Nf;  // a = 2u - 1: one texel in u
-        if constexpr (METHOD == SHM_RECON_BILINEAR_FD) {
-            R = bilinear_at(vl, N, L.face, a, bb);
-        } else {
-            const float fu = (a + 1.0f) * 0.5f * Nf + 1.5f, fv = (bb + 1.0f) * 0.5f * Nf + 1.5f;
-            const int i0 = (int)floorf(fu), j0 = (int)floorf(fv);
-            const Fold X = bspline_fold(fu - (float)i0), Y = bspline_fold(fv - (float)j0);
-            const float r0 = X.g0 * bilinear_ij(vl, P, L.face, i0 - 1, j0 - 1, X.f0, Y.f0) +
-                             X.g1 * bilinear_ij(vl, P, L.face, i0 + 1, j0 - 1, X.f1, Y.f0);
-            const float r1 = X.g0 * bilinear_ij(vl, P, L.face, i0 - 1, j0 + 1, X.f0, Y.f1) +
-                             X.g1 * bilinear_ij(vl, P, L.face, i0 + 1, j0 + 1, X.f1, Y.f1);
-            R = Y.g0 * r0 + Y.g1 * r1;
-        }
-        ru = (bilinear_at(vl, N, L.face, a + da, bb) - bilinear_at(vl, N, L.face, a - da, bb)) * (0.5f * Nf);
-        rv = (bilinear_at(vl, N, L.face, a, bb + da) - bilinear_at(vl, N, L.face, a, bb - da)) * (0.5f * Nf);
     } else {
         const float fu = (a + 1.0f) * 0.5f * Nf + 1.5f, fv = (bb + 1.0f) * 0.5f * Nf + 1.5f;
         const int i0 = (int)floorf(fu), j0 = (int)floorf(fv);
         const float s = fu - (float)i0, t = fv - (float)j0;
-        float ws[4], dws[4], wt[4], dwt[4];
-        {
-            const float s2 = s * s, s3 = s2 * s, t2 = t * t, t3 = t2 * t;
-            ws[0] = 0.5f * (-s3 + 2.0f * s2 - s);
-            ws[1] = 0.5f * (3.0f * s3 - 5.0f * s2 + 2.0f);
-            ws[2] = 0.5f * (-3.0f * s3 + 4.0f * s2 + s);
-            ws[3] = 0.5f * (s3 - s2);
-            dws[0] = 0.5f * (-3.0f * s2 + 4.0f * s - 1.0f);
-            dws[1] = 0.5f * (9.0f * s2 - 10.0f * s);
-            dws[2] = 0.5f * (-9.0f * s2 + 8.0f * s + 1.0f);
-            dws[3] = 0.5f * (3.0f * s2 - 2.0f * s);
-            wt[0] = 0.5f * (-t3 + 2.0f * t2 - t);
-            wt[1] = 0.5f * (3.0f * t3 - 5.0f * t2 + 2.0f);
-            wt[2] = 0.5f * (-3.0f * t3 + 4.0f * t2 + t);
-            wt[3] = 0.5f * (t3 - t2);
-            dwt[0] = 0.5f * (-3.0f * t2 + 4.0f * t - 1.0f);
-            dwt[1] = 0.5f * (9.0f * t2 - 10.0f * t);
-            dwt[2] = 0.5f * (-9.0f * t2 + 8.0f * t + 1.0f);
-            dwt[3] = 0.5f * (3.0f * t2 - 2.0f * t);
-        }
-        R = 0.0f;
-        float rs = 0.0f, rt = 0.0f;
+        float v[4][4];  // v[j][i]: texel (i0 - 1 + i, j0 - 1 + j)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float row = 0.0f, drow = 0.0f;
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = vl_at(vl, P, L.face, i0 - 1 + i, j0 - 1 + j);
-                row += ws[i] * v;
-                drow += dws[i] * v;
+            for (int i = 0; i < 4; ++i) v[j][i] = vl_at(vl, P, L.face, i0 - 1 + i, j0 - 1 + j);
+        if constexpr (METHOD == SHM_RECON_BICUBIC) {
+            float ws[4], dws[4], wt[4], dwt[4];
+            {
+                const float s2 = s * s, s3 = s2 * s, t2 = t * t, t3 = t2 * t;
+                ws[0] = 0.5f * (-s3 + 2.0f * s2 - s);
+                ws[1] = 0.5f * (3.0f * s3 - 5.0f * s2 + 2.0f);
+                ws[2] = 0.5f * (-3.0f * s3 + 4.0f * s2 + s);
+                ws[3] = 0.5f * (s3 - s2);
+                dws[0] = 0.5f * (-3.0f * s2 + 4.0f * s - 1.0f);
+                dws[1] = 0.5f * (9.0f * s2 - 10.0f * s);
+                dws[2] = 0.5f * (-9.0f * s2 + 8.0f * s + 1.0f);
+                dws[3] = 0.5f * (3.0f * s2 - 2.0f * s);
+                wt[0] = 0.5f * (-t3 + 2.0f * t2 - t);
+                wt[1] = 0.5f * (3.0f * t3 - 5.0f * t2 + 2.0f);
+                wt[2] = 0.5f * (-3.0f * t3 + 4.0f * t2 + t);
+                wt[3] = 0.5f * (t3 - t2);
+                dwt[0] = 0.5f * (-3.0f * t2 + 4.0f * t - 1.0f);
+                dwt[1] = 0.5f * (9.0f * t2 - 10.0f * t);
+                dwt[2] = 0.5f * (-9.0f * t2 + 8.0f * t + 1.0f);
+                dwt[3] = 0.5f * (3.0f * t2 - 2.0f * t);
             }
-            R += wt[j] * row;
-            rs += wt[j] * drow;
-            rt += dwt[j] * row;
+            R = 0.0f;
+            float rs = 0.0f, rt = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float row = 0.0f, drow = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    row += ws[i] * v[j][i];
+                    drow += dws[i] * v[j][i];
+                }
+                R += wt[j] * row;
+                rs += wt[j] * drow;
+                rt += dwt[j] * row;
+            }
+            ru = Nf * rs;
+            rv = Nf * rt;
+        } else {
+            // bilinear lookups at the cell and one texel to either side
+            auto bil = [&](int j, int i, float fx, float fy) {
+                const float r0 = v[j][i] + fx * (v[j][i + 1] - v[j][i]);
+                const float r1 = v[j + 1][i] + fx * (v[j + 1][i + 1] - v[j + 1][i]);
+                return r0 + fy * (r1 - r0);
+            };
+            const float hN = 0.5f * Nf;  // 1 / (2h): central difference over +-1 texel
+            ru = (bil(1, 2, s, t) - bil(1, 0, s, t)) * hN;
+            rv = (bil(2, 1, s, t) - bil(0, 1, s, t)) * hN;
+            if constexpr (METHOD == SHM_RECON_BILINEAR_FD) {
+                R = bil(1, 1, s, t);
+            } else {
+                // uniform cubic B-spline weights of taps -1..2
+                float ws[4], wt[4];
+                {
+                    const float s2 = s * s, s3 = s2 * s, ms = 1.0f - s;
+                    const float t2 = t * t, t3 = t2 * t, mt = 1.0f - t;
+                    const float k = 1.0f / 6.0f;
+                    ws[0] = ms * ms * ms * k;
+                    ws[1] = (3.0f * s3 - 6.0f * s2 + 4.0f) * k;
+                    ws[2] = (-3.0f * s3 + 3.0f * s2 + 3.0f * s + 1.0f) * k;
+                    ws[3] = s3 * k;
+                    wt[0] = mt * mt * mt * k;
+                    wt[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * k;
+                    wt[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * k;
+                    wt[3] = t3 * k;
+                }
+                R = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float row = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) row += ws[i] * v[j][i];
+                    R += wt[j] * row;
+                }
+            }
         }
-        ru = Nf * rs;
-        rv = Nf * rt;
     }
     const float3 g = transport(L.face, a, bb, ru, rv);
     reinterpret_cast<float4*>(out)[q] = make_float4(R, g.x, g.y, g.z);

@@ -347,4 +347,18 @@ __device__ __forceinline__ float4 query_one(const void* __restrict__ lut, int N,
     return make_float4(P.r, g.x, g.y, g.z);
 }
 
+// Rendered radius (Sec. 3.1) from (r, grad r): R = s r, or for a signed
+// function R = s |r| with gradient s sign(r) grad r (Sec. 3.4, after Eq. 10;
+// sign(0) = 0).  *sgn gets sign(r); NaN input stays NaN.
+__device__ __forceinline__ float4 rendered(float4 q, float scale, bool is_signed, int* sgn)
+{
+    const float r = q.x;
+    const int sg = r > 0.0f ? 1 : (r < 0.0f ? -1 : 0);
+    *sgn = sg;
+    const float k = is_signed ? scale * (float)sg : scale;
+    const float R = is_signed ? scale * fabsf(r) : scale * r;
+    if (r != r) return q;
+    return make_float4(R, k * q.y, k * q.z, k * q.w);
+}
+
 }  // namespace shm

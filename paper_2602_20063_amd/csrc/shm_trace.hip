@@ -3,10 +3,12 @@
 // One lane per ray.  Every evaluation of F(t) = |p - c| - R(w) is a full
 // Hermite query (locate, 16-scalar gather, patch, closed-form gradient), so
 // F'(t) = d.w - (d . grad R)/|p - c| comes from the same four texels.
-// Schedule, identical to the reference implementation in the test-suite:
-// bounding sphere -> uniform march to the first F < 0 -> bisection ->
-// safeguarded Newton -> final evaluation.  Fixed iteration counts keep the
-// FP32 path on the same steps as an FP64 evaluation of the same schedule.
+// Schedule, the same as the oracle's: bounding sphere -> uniform march to
+// the first F < 0 -> bisection -> safeguarded Newton -> final evaluation.
+// Fixed iteration counts keep the FP32 path on the same steps as an FP64
+// evaluation of the same schedule.  R is the rendered radius: s r, or s |r|
+// for a signed function.  Optionally the number of bisections adapts to the
+// glyph's projected size (Sec. 3.1), decided per ray in FP32.
 #include "shm_device.hpp"
 #include "shm_internal.hpp"
 
@@ -15,15 +17,16 @@ namespace shm {
 struct FEval {
     float F, dF, R;
     float3 g, w;
+    int sgn;
 };
 
 template <bool FP16>
 __device__ __forceinline__ FEval trace_eval(const void* __restrict__ lut, int N, float ox, float oy, float oz,
-                                            float dx, float dy, float dz, float t)
+                                            float dx, float dy, float dz, float t, float scale, bool is_signed)
 {
     FEval E;
     const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
-    const float4 r = query_one<FP16, false>(lut, N, px, py, pz);
+    const float4 r = rendered(query_one<FP16, false>(lut, N, px, py, pz), scale, is_signed, &E.sgn);
     const float len = sqrtf(px * px + py * py + pz * pz);
     const float il = 1.0f / len;
     E.R = r.x;
@@ -34,25 +37,54 @@ __device__ __forceinline__ FEval trace_eval(const void* __restrict__ lut, int N,
     return E;
 }
 
+// Bisection budget: the march bracket (at most 2 rmax / n_march long) spans
+// e = 2 rmax px / (|o - c| n_march) pixels at the glyph's depth, px being
+// the focal length in pixels; halve until e <= eps_px, at most n_bisect
+// times.  Every step is rounded to nearest without contraction (halving is
+// exact), the order fixed, so the count is reproducible bit for bit.
+__device__ __noinline__ int bisect_budget(float ox, float oy, float oz, float rmax, float px, float eps_px, int n_march,
+                                          int n_bisect)
+{
+#pragma clang fp contract(off)
+    const float dd = ox * ox + oy * oy + oz * oz;
+    const float depth = sqrtf(dd);
+    float e = (2.0f * rmax * px) / (depth * (float)n_march);
+    int k = 0;
+    while (k < n_bisect && e > eps_px) {
+        e *= 0.5f;
+        ++k;
+    }
+    return k;
+}
+
 template <bool FP16, bool NRM>
 __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int N, float cx, float cy, float cz,
-                                               float rmax, const float* __restrict__ ray_o,
-                                               const float* __restrict__ ray_d, int64_t P, int n_march, int n_bisect,
-                                               int n_newton, float* __restrict__ t_out, float* __restrict__ out,
-                                               float* __restrict__ nrm)
+                                               float rmax, float scale, int is_signed_i, float px_focal, float eps_px,
+                                               const float* __restrict__ ray_o, const float* __restrict__ ray_d,
+                                               int64_t P, int n_march, int n_bisect_max, int n_newton,
+                                               float* __restrict__ t_out, float* __restrict__ out,
+                                               float* __restrict__ nrm, int8_t* __restrict__ sign_out,
+                                               uint8_t* __restrict__ evals_out)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= P) return;
+    const bool is_signed = is_signed_i != 0;
     // origin relative to the centre; unit direction
     const float ox = ray_o[3 * r] - cx, oy = ray_o[3 * r + 1] - cy, oz = ray_o[3 * r + 2] - cz;
+    const int n_bisect =
+        px_focal > 0.0f ? bisect_budget(ox, oy, oz, rmax, px_focal, eps_px, n_march, n_bisect_max) : n_bisect_max;
+    int evals = 0;
     float dx = ray_d[3 * r], dy = ray_d[3 * r + 1], dz = ray_d[3 * r + 2];
     const float dl = sqrtf(dx * dx + dy * dy + dz * dz);
     dx /= dl;
     dy /= dl;
     dz /= dl;
+    // disc = rmax^2 - (squared distance of the centre from the ray line),
+    // formed from the perpendicular vector: b^2 - (|o - c|^2 - rmax^2)
+    // cancels catastrophically in FP32 once |o - c| >> rmax
     const float b = ox * dx + oy * dy + oz * dz;
-    const float cc = (ox * ox + oy * oy + oz * oz) - rmax * rmax;
-    const float disc = b * b - cc;
+    const float hx = ox - b * dx, hy = oy - b * dy, hz = oz - b * dz;
+    const float disc = rmax * rmax - (hx * hx + hy * hy + hz * hz);
     bool hit = false;
     float t = __builtin_inff();
     if (disc >= 0.0f && dl > 0.0f) {
@@ -64,7 +96,8 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
             float lo = t0, hi = t0;
             for (int k = 1; k <= n_march; ++k) {
                 const float tk = t0 + (float)k * step;
-                const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, tk);
+                const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, tk, scale, is_signed);
+                ++evals;
                 if (E.F < 0.0f) {
                     hit = true;
                     lo = t0 + (float)(k - 1) * step;
@@ -75,13 +108,15 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
             if (hit) {
                 for (int it = 0; it < n_bisect; ++it) {
                     const float mid = 0.5f * (lo + hi);
-                    const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, mid);
+                    const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, mid, scale, is_signed);
+                    ++evals;
                     if (E.F < 0.0f) hi = mid;
                     else lo = mid;
                 }
                 t = 0.5f * (lo + hi);
                 for (int it = 0; it < n_newton; ++it) {
-                    const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, t);
+                    const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
+                    ++evals;
                     if (E.F < 0.0f) hi = t;
                     else lo = t;
                     float tn = t - E.F / E.dF;
@@ -92,7 +127,9 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
         }
     }
     if (hit) {
-        const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, t);
+        const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
+        ++evals;
+        if (sign_out) sign_out[r] = (int8_t)E.sgn;
         t_out[r] = t;
         reinterpret_cast<float4*>(out)[r] = make_float4(E.R, E.g.x, E.g.y, E.g.z);
         if constexpr (NRM) {
@@ -104,6 +141,7 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
         }
     } else {
         const float nan = __builtin_nanf("");
+        if (sign_out) sign_out[r] = 0;
         t_out[r] = __builtin_inff();
         reinterpret_cast<float4*>(out)[r] = make_float4(nan, nan, nan, nan);
         if constexpr (NRM) {
@@ -112,24 +150,31 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
             nrm[3 * r + 2] = nan;
         }
     }
+    if (evals_out) evals_out[r] = (uint8_t)evals;
 }
 
-int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, const float* ray_o,
-                 const float* ray_d, int64_t P, int n_march, int n_bisect, int n_newton, float* t_out, float* out,
-                 float* normal, hipStream_t stream)
+int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
+                 float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int n_march,
+                 int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign, uint8_t* evals,
+                 hipStream_t stream)
 {
     if (P == 0) return SHM_OK;
     const int64_t blocks = (P + 255) / 256;
     if (blocks > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "trace: too many rays");
     const dim3 g((unsigned)blocks), bl(256);
     const float cx = center[0], cy = center[1], cz = center[2];
+    const int sgn = (flags & SHM_SIGNED) ? 1 : 0;
+#define SHM_T(F, NR)                                                                                                  \
+    hipLaunchKernelGGL((k_trace<F, NR>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, scale, sgn, px_focal, eps_px,      \
+                       ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal, sign, evals)
     if (dtype == SHM_F16) {
-        if (normal) hipLaunchKernelGGL((k_trace<true, true>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal);
-        else hipLaunchKernelGGL((k_trace<true, false>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal);
+        if (normal) SHM_T(true, true);
+        else SHM_T(true, false);
     } else {
-        if (normal) hipLaunchKernelGGL((k_trace<false, true>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal);
-        else hipLaunchKernelGGL((k_trace<false, false>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal);
+        if (normal) SHM_T(false, true);
+        else SHM_T(false, false);
     }
+#undef SHM_T
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }

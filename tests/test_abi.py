@@ -108,3 +108,48 @@ def test_plan_validation():
     assert shm.lib().shm_plan_work_items(None) == -1
     s = shm.shm_launch_shape(100, 1, 100, 4)
     assert call("shm_plan_set_shape", None, ctypes.byref(s)) == shm.SHM_ERR_INVALID_ARG
+
+
+def test_render_validation():
+    """Rendered-radius query and trace: scale, flags and budget parameters
+    are checked on the host before anything is enqueued."""
+    p = ctypes.c_void_p(256)
+    c = (ctypes.c_float * 3)(0, 0, 0)
+
+    def prm(**kw):
+        d = dict(scale=1.0, flags=0, n_march=20, n_bisect=8, n_newton=3, px_per_unit=0.0, eps_px=0.0)
+        d.update(kw)
+        return shm.shm_trace_params(**d)
+
+    def tr(pp, P=10):
+        return call("shm_trace_radial_ex", p, 0, 8, c, 1.0, ctypes.byref(pp), p, p, P, p, p, None, None, None, None)
+
+    assert tr(prm(), P=0) == shm.SHM_OK
+    assert tr(prm(flags=shm.SHM_SIGNED, px_per_unit=900.0, eps_px=0.1), P=0) == shm.SHM_OK
+    for bad in (prm(scale=0.0), prm(scale=float("inf")), prm(flags=2), prm(n_march=0), prm(n_bisect=60),
+                prm(px_per_unit=-1.0), prm(px_per_unit=float("nan")), prm(px_per_unit=100.0, eps_px=0.0)):
+        assert tr(bad) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_trace_radial_ex", p, 0, 8, c, 1.0, None, p, p, 10, p, p, None, None, None, None) == shm.SHM_ERR_INVALID_ARG
+    q = lambda scale, flags, Q=10: call("shm_query_scaled", p, 0, 0, 8, 1, p, Q, scale, flags, p, None, None, None)
+    assert q(0.0, 0) == shm.SHM_ERR_INVALID_ARG
+    assert q(float("nan"), 0) == shm.SHM_ERR_INVALID_ARG
+    assert q(1.0, 4) == shm.SHM_ERR_INVALID_ARG
+    assert q(1.0, shm.SHM_SIGNED, Q=0) == shm.SHM_OK
+    assert call("shm_query_scaled", p, 0, 0, 8, 1, None, 10, 1.0, 0, p, None, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_lut_rmax", p, 0, 8, 2, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_lut_rmax", p, 0, 8, 0, None, None) == shm.SHM_ERR_INVALID_ARG
+
+
+def test_mesh_depth_validation():
+    p = ctypes.c_void_p(256)
+    c = (ctypes.c_float * 3)(0, 0, 0)
+    cbad = (ctypes.c_float * 3)(0, float("nan"), 0)
+    f = lambda *a: call("shm_mesh_radial_depth", *a)
+    assert f(p, 8, p, 12, c, p, 0, p, None) == shm.SHM_OK          # no rays: nothing to do
+    assert f(p, -1, p, 12, c, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert f(p, 8, p, 12, None, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert f(p, 8, p, 12, cbad, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert f(p, 8, None, 12, c, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert f(p, 8, p, 12, c, None, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert f(p, 1 << 32, p, 12, c, p, 10, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert f(p, 8, p, 12, c, p, 10, ctypes.c_void_p(258), None) == shm.SHM_ERR_INVALID_ARG

@@ -801,7 +801,7 @@ def test_bumps_truth_and_bake_against_independent_evaluation():
 
 
 # ---------------------------------------------------------------------------
-# Comparison reconstructions (Sec. 4.2 Table psnr_value, Sec. 4.4 Table
+# Comparison reconstructions (Sec. 4.2 Table psnr_value, Sec. 4.5 Table
 # cost_extended): nearest, bilinear + finite-difference normals, Catmull-Rom
 # ---------------------------------------------------------------------------
 def value_lut(N, fn):
@@ -962,3 +962,102 @@ def test_mip_table_lod_trend():
         ratios.append(err(naive) / err(cons))
     assert ratios[0] > 3.0, ratios
     assert ratios[0] > ratios[1] > ratios[2] > 1.0, ratios
+
+
+# ---------------------------------------------------------------------------
+# Radial depth of a mesh (Sec. 4.9): R(w) = max{t >= 0 : c + t w on the mesh}
+# ---------------------------------------------------------------------------
+def box_mesh(lo, hi):
+    """Axis-aligned box as 12 triangles."""
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    V = np.array([[hi[0] if i & 1 else lo[0], hi[1] if i & 2 else lo[1], hi[2] if i & 4 else lo[2]] for i in range(8)])
+    quads = [(0, 1, 3, 2), (4, 6, 7, 5), (0, 4, 5, 1), (2, 3, 7, 6), (0, 2, 6, 4), (1, 5, 7, 3)]
+    F = [(a, b, c) for a, b, c, d in quads] + [(a, c, d) for a, b, c, d in quads]
+    return V, np.array(F, np.int32)
+
+
+def test_mesh_depth_cube_and_octahedron_closed_forms():
+    a, c = 0.7, np.array([0.3, -1.2, 2.0])
+    V, F = box_mesh(c - a, c + a)
+    d = np.concatenate([workloads.uniform_dirs(3000, rng(90)), oracle.margin_dirs(8).reshape(-1, 3)]).astype(np.float32)
+    w = d.astype(np.float64) / np.linalg.norm(d.astype(np.float64), axis=1, keepdims=True)
+    R = oracle.mesh_radial_depth(V, F, c, d)
+    np.testing.assert_allclose(R, a / np.abs(w).max(axis=1), rtol=1e-12)
+    Vo = np.array([[a, 0, 0], [-a, 0, 0], [0, a, 0], [0, -a, 0], [0, 0, a], [0, 0, -a]])
+    Fo = np.array([(i, j, k) for i in (0, 1) for j in (2, 3) for k in (4, 5)], np.int32)
+    R = oracle.mesh_radial_depth(Vo, Fo, np.zeros(3), d)
+    np.testing.assert_allclose(R, a / np.abs(w).sum(axis=1), rtol=1e-12)
+
+
+def test_mesh_depth_takes_the_farthest_hit():
+    """Two nested shells: every ray crosses both, the depth is the outer one;
+    a box that does not contain the centre gives the exit distance of the
+    slab test where the ray meets it and 0 elsewhere; triangles with an
+    index out of range are ignored."""
+    Vi, Fi = box_mesh([-0.5] * 3, [0.5] * 3)
+    Vo, Fo = box_mesh([-1.0] * 3, [1.0] * 3)
+    V = np.concatenate([Vi, Vo])
+    F = np.concatenate([Fi, Fo + 8]).astype(np.int32)
+    d = workloads.uniform_dirs(2000, rng(91))
+    w = d.astype(np.float64) / np.linalg.norm(d.astype(np.float64), axis=1, keepdims=True)
+    np.testing.assert_allclose(oracle.mesh_radial_depth(V, F, np.zeros(3), d), 1.0 / np.abs(w).max(axis=1), rtol=1e-12)
+    lo, hi = np.array([1.0, -0.6, -0.4]), np.array([2.5, 0.7, 0.5])
+    Vb, Fb = box_mesh(lo, hi)
+    R = oracle.mesh_radial_depth(Vb, Fb, np.zeros(3), d)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1, t2 = lo[None] / w, hi[None] / w
+    tn = np.nanmax(np.minimum(t1, t2), axis=1)
+    tf = np.nanmin(np.maximum(t1, t2), axis=1)
+    hit = (tn <= tf) & (tf >= 0)
+    assert 0.05 < hit.mean() < 0.5
+    np.testing.assert_allclose(R[hit], tf[hit], rtol=1e-12)
+    assert (R[~hit] == 0).all()
+    Fbad = np.concatenate([Fb, [[0, 1, 99], [-1, 2, 3]]]).astype(np.int32)
+    np.testing.assert_array_equal(oracle.mesh_radial_depth(Vb, Fbad, np.zeros(3), d), R)
+
+
+def test_asteroid_mesh_depth_tracks_the_radius():
+    """The synthetic asteroid mesh is star-shaped about the origin: along a
+    vertex direction the depth is that vertex's radius, and elsewhere it
+    stays within the surface's radius range (flat facets cut inside)."""
+    prm = workloads.asteroid_params(rng(92))
+    V, F = workloads.asteroid_mesh(prm, level=3)
+    R = oracle.mesh_radial_depth(V, F, np.zeros(3), V[::7])
+    np.testing.assert_allclose(R, np.linalg.norm(V[::7].astype(np.float64), axis=1), rtol=1e-6)
+    d = workloads.uniform_dirs(500, rng(93))
+    R = oracle.mesh_radial_depth(V, F, np.zeros(3), d)
+    r, _ = workloads.asteroid_radius(prm, d)
+    assert (R > 0.7).all() and np.abs(R - r).max() < 0.1
+
+
+def test_fd_baked_hermite_is_catmull_rom():
+    """Cubic Hermite interpolation whose tangents are the central
+    differences (p[i+1] - p[i-1]) / 2 is the Catmull-Rom spline, and the
+    tensor product carries the mixed channel along; so a map baked in the
+    general (finite-difference) mode reproduces the 16-tap Catmull-Rom
+    reconstruction of the same samples, value and gradient, everywhere on
+    the sphere (gutters included)."""
+    N = 12
+    r = rng(94)
+    samples = 1.0 + 0.2 * r.standard_normal((6, N + 4, N + 4))
+    lut = oracle.bake_fd(samples, N)
+    d = workloads.uniform_dirs(5000, r)
+    h = oracle.query(lut, d)
+    cr = oracle.baseline_query(samples, d, oracle.BASELINE_BICUBIC)
+    np.testing.assert_allclose(h[:, 0], cr[:, 0], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(h[:, 1:], cr[:, 1:], rtol=0, atol=1e-11)
+
+
+def test_abs_bound_of_a_signed_function():
+    """r = z - 0.3 spans about [-1.3, 0.7]: the bound of |r| covers the
+    negative lobe, the plain bound only the positive one; both hold over a
+    dense set of queries and are tight to the Bezier hull."""
+    c = np.zeros(4)
+    c[0] = -0.3 * math.sqrt(4 * math.pi)
+    c[2] = math.sqrt(4 * math.pi / 3)
+    lut = oracle.bake_sh(c, 16)
+    r = oracle.query(lut, workloads.uniform_dirs(20000, rng(95)))[:, 0]
+    plain, absb = oracle.rmax_bound(lut), oracle.rmax_bound(lut, absval=True)
+    assert plain >= r.max() and absb >= np.abs(r).max()
+    assert 0.69 < plain < 0.72 and 1.29 < absb < 1.32
+    assert oracle.rmax_bound(-lut, absval=True) == absb

@@ -246,6 +246,103 @@ BATCH_NS = (8, 16, 32, 64, 128, 256)
 BATCH_NP = (0.3, 0.25, 0.2, 0.15, 0.07, 0.03)
 
 
+def _rand_unit(rng, n):
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def asteroid_params(rng):
+    """Feature parameters of the synthetic asteroid that stands in for the
+    paper's mesh impostor model: 69 craters (6 large, 18 medium, 45 small:
+    angular radius, depth), 8 ridges along great circles (plane normal,
+    height, half-width), 30 boulders (centre, height, width) and a seed for
+    5-octave fBm."""
+    craters = [], [], []
+    for n, (r0, r1), (d0, d1) in zip((6, 18, 45), ((0.35, 0.55), (0.15, 0.3), (0.05, 0.12)),
+                                     ((0.06, 0.10), (0.03, 0.06), (0.01, 0.03))):
+        craters[0].append(_rand_unit(rng, n))
+        craters[1].append(rng.uniform(r0, r1, n))
+        craters[2].append(rng.uniform(d0, d1, n))
+    return {"craters": tuple(np.concatenate(c) for c in craters),
+            "ridges": (_rand_unit(rng, 8), rng.uniform(0.02, 0.05, 8), rng.uniform(0.04, 0.1, 8)),
+            "boulders": (_rand_unit(rng, 30), rng.uniform(0.01, 0.03, 30), rng.uniform(0.02, 0.05, 30)),
+            "noise_seed": int(rng.integers(1 << 30))}
+
+
+def asteroid_radius(prm, dirs):
+    """Radius R(w) of the asteroid and its spherical gradient [n, 3]:
+    1 + craters (bowl -D e^{-2x} with a rim 0.3 D e^{-(x-1)^2/0.18},
+    x = (1 - w.mu)/rho^2) + ridges (h e^{-(w.n/b)^2}) + boulders
+    (h e^{(w.c - 1)/s^2}) + 0.05 fBm (5 octaves); R stays in about
+    [0.8, 1.15]."""
+    d = np.asarray(dirs, np.float64).reshape(-1, 3)
+    w = d / np.linalg.norm(d, axis=1, keepdims=True)
+    val = np.ones(w.shape[0])
+    grad = np.zeros_like(w)
+    mu, rho, depth = prm["craters"]
+    for k in range(mu.shape[0]):
+        x = (1.0 - w @ mu[k]) / rho[k] ** 2
+        bowl = np.exp(-2.0 * x)
+        rim = np.exp(-(x - 1.0) ** 2 / 0.18)
+        val += -depth[k] * bowl + 0.3 * depth[k] * rim
+        dfx = 2.0 * depth[k] * bowl - 0.3 * depth[k] * rim * 2.0 * (x - 1.0) / 0.18
+        grad += dfx[:, None] * (-mu[k] / rho[k] ** 2)[None, :]
+    nrm, hgt, hw = prm["ridges"]
+    for k in range(nrm.shape[0]):
+        y = w @ nrm[k]
+        e = np.exp(-(y / hw[k]) ** 2)
+        val += hgt[k] * e
+        grad += (hgt[k] * e * (-2.0 * y / hw[k] ** 2))[:, None] * nrm[k][None, :]
+    c, h, wd = prm["boulders"]
+    for k in range(c.shape[0]):
+        e = np.exp((w @ c[k] - 1.0) / wd[k] ** 2)
+        val += h[k] * e
+        grad += (h[k] * e / wd[k] ** 2)[:, None] * c[k][None, :]
+    grad -= np.sum(grad * w, axis=1, keepdims=True) * w
+    fv, fg = fbm_target(w, prm["noise_seed"], octaves=5, amp=0.05)
+    return val + fv - 1.0, grad + fg
+
+
+def icosphere(level):
+    """Unit icosphere: the icosahedron with every triangle split into four
+    `level` times, new vertices pushed to the sphere.  Vertices [V, 3]
+    (FP64), outward-oriented triangles [T, 3] (int64); T = 20 * 4^level."""
+    p = (1 + 5 ** 0.5) / 2
+    v0 = [(-1, p, 0), (1, p, 0), (-1, -p, 0), (1, -p, 0), (0, -1, p), (0, 1, p), (0, -1, -p), (0, 1, -p),
+          (p, 0, -1), (p, 0, 1), (-p, 0, -1), (-p, 0, 1)]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+             (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    V = [np.array(x, float) / np.linalg.norm(x) for x in v0]
+    F = faces
+    for _ in range(level):
+        mids = {}
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in mids:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                mids[key] = len(V) - 1
+            return mids[key]
+
+        nf = []
+        for a, b, c in F:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = nf
+    return np.array(V), np.array(F, np.int64)
+
+
+def asteroid_mesh(prm, level=6):
+    """Star-shaped triangle mesh of the asteroid: icosphere vertices moved to
+    radius R(w).  Vertices [V, 3] FP32, triangles [T, 3] int32 (81,920 at
+    level 6), centred on the origin."""
+    V, F = icosphere(level)
+    r, _ = asteroid_radius(prm, V)
+    return np.ascontiguousarray(V * r[:, None], np.float32), np.ascontiguousarray(F, np.int32)
+
+
 def uneven_batch(rng, n_obj=4096, mu=9.0, sigma=1.5, qmin=64, qmax=1 << 20, Lmin=2, Lmax=16):
     """Per object: face size N, SH order L, query count Q (lognormal,
     clipped).  Returns dict of int arrays."""
