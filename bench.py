@@ -158,6 +158,13 @@ def main():
         lut4 = torch.zeros((1, 6, Nb + 2, Nb + 2, 4), device=DEV)
         bctx = shm.BackwardContext(Nb, 1, d4, Qb)
         bctx.backward(lut4, torch.ones((Qb, 4), device=DEV))
+        # one trace of the bump impostor (N = 256, 1920 x 1080, FP32)
+        mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+        md = shm.margin_dirs(256).cpu().numpy().reshape(-1, 3)
+        lut3 = shm.bake_fd(to_dev(workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)), 256)
+        rmax = float(shm.lut_rmax(lut3).item()) * 1.0001
+        o3, d3 = workloads.camera_rays(1920, 1080)
+        shm.trace(lut3, (0.0, 0.0, 0.0), rmax, to_dev(o3), to_dev(d3))
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "query_launches": 3, "copy_bytes": 1 << 30}))
         return
@@ -428,17 +435,19 @@ def run_backward_fit():
     return res
 
 
-def run_batched():
-    """Workload 5: 4,096 uneven objects, FP16 LUTs (CELL), one persistent
-    autotuned graph-captured launch vs per-object FP32 launches."""
+def build_uneven_batch():
+    """Workload 5 data: 4,096 objects (N, L, query counts from the uneven
+    recipe), SH coefficients, one direction set; LUTs baked on the GPU grouped
+    by (N, L) into FP32 texel LUTs (texel_off, in elements) and relaid into
+    the cell layout (cell_off); objs = (cell offset, N, first query, count)."""
     r = workloads.rng_for(5)
     spec = workloads.uneven_batch(r)
     n_obj = len(spec["N"])
     Qs = spec["Q"]
     Qtot = int(Qs.sum())
-    dirs = to_dev(workloads.uniform_dirs(Qtot, r))
+    dirs_np = workloads.uniform_dirs(Qtot, r)
+    dirs = to_dev(dirs_np)
     coeffs = [workloads.sh_glyph_coeffs(int(spec["L"][o]), 1, r)[0].astype(np.float32) for o in range(n_obj)]
-    # bake grouped by (N, L) into per-object FP32 texel LUTs, then relayout
     texel_off, off = [], 0
     for o in range(n_obj):
         texel_off.append(off)
@@ -447,10 +456,10 @@ def run_batched():
     groups = {}
     for o in range(n_obj):
         groups.setdefault((int(spec["N"][o]), int(spec["L"][o])), []).append(o)
-    for (Nn, L), objs in groups.items():
-        c = to_dev(np.stack([coeffs[o] for o in objs]))
+    for (Nn, L), members in groups.items():
+        c = to_dev(np.stack([coeffs[o] for o in members]))
         lut = shm.bake_sh(c, Nn)
-        for k, o in enumerate(objs):
+        for k, o in enumerate(members):
             n = lut[k].numel()
             lut_tex[texel_off[o]:texel_off[o] + n] = lut[k].reshape(-1)
     cell_off, off = [], 0
@@ -463,9 +472,20 @@ def run_batched():
         n = 6 * (Nn + 2) ** 2 * 4
         m = 6 * (Nn + 1) ** 2 * 16
         shm.shm_lut_to_cells(lut_tex[texel_off[o]:texel_off[o] + n], shm.SHM_F32, Nn, 1, lut32[cell_off[o]:cell_off[o] + m])
-    lut16 = lut32.half()
     qb = np.concatenate([[0], np.cumsum(Qs)[:-1]])
     objs = [(cell_off[o], int(spec["N"][o]), int(qb[o]), int(Qs[o])) for o in range(n_obj)]
+    return {"spec": spec, "n_obj": n_obj, "Qtot": Qtot, "dirs": dirs, "dirs_np": dirs_np, "lut_tex": lut_tex,
+            "texel_off": texel_off, "lut32": lut32, "cell_off": cell_off, "objs": objs, "coeffs": coeffs, "qb": qb}
+
+
+def run_batched():
+    """Workload 5: 4,096 uneven objects, FP16 LUTs (CELL), one persistent
+    autotuned graph-captured launch vs per-object FP32 launches."""
+    B = build_uneven_batch()
+    spec, n_obj, Qtot, dirs, objs = B["spec"], B["n_obj"], B["Qtot"], B["dirs"], B["objs"]
+    lut32, coeffs, qb = B["lut32"], B["coeffs"], B["qb"]
+    Qs = spec["Q"]
+    lut16 = lut32.half()
     out16 = torch.empty((Qtot, 4), device=DEV)
     out32 = torch.empty((Qtot, 4), device=DEV)
     plan = shm.Plan(objs, shm.SHM_F16, shm.SHM_LAYOUT_CELL)

@@ -44,7 +44,9 @@ __device__ __forceinline__ int64_t basis_index(int k, int64_t col, int Kp, int64
     const int64_t t = col >> 5;
     const int c = (int)(col & 31);
     const int lane = (k & 3) * 16 + (c & 15);
-    return ((t * (Kp >> 2) + (k >> 2)) * 2 + (c >> 4)) * 64 + lane;
+    const int v = 2 * (k >> 2) + (c >> 4);  // fragment value b[j][s], v = 2 s + j
+    const int G = ((Kp >> 2) + 1) >> 1;      // float4 groups per lane and tile
+    return ((t * G + (v >> 2)) * 64 + lane) * 4 + (v & 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -52,9 +54,11 @@ __device__ __forceinline__ int64_t basis_index(int k, int64_t col, int Kp, int64
 // (k-major so the MFMA B operand loads are coalesced), ld = rows_pad.
 // ---------------------------------------------------------------------------
 // Layouts of the table: k-major Bt[k][col] (ld = rows_pad), or, for the
-// register-resident contraction, MFMA fragment order
-// Bf[t][s][j][lane] with col = 32 t + 16 j + lane % 16 and k = 4 s + lane / 16,
-// so one column tile's B fragments are contiguous.
+// register-resident contraction, MFMA fragment order: the B fragment value
+// b[j][s] of lane l for column tile t (col = 32 t + 16 j + l % 16,
+// k = 4 s + l / 16) is value v = 2 s + j of the lane, and the lane's values
+// sit in float4 groups Bf[t][v / 4][l][v % 4]: one tile is ceil(KS / 2)
+// float4 loads per lane (KS = K / 4 steps).
 template <typename Real>
 __global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, int frag, float* __restrict__ Bt)
 {
@@ -251,71 +255,111 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
 // coefficients sit in registers as MFMA A fragments for the whole K; it then
 // walks the column tiles (32 columns) of its chunk, loading the B fragments
 // of the next tile while the 4 x KS MFMAs of the current one run, and
-// stores a 32 x 32 output tile per step.  No LDS, no barriers.
+// stores a 32 x 32 output tile per step, staged through the wave's own LDS
+// buffer so that it leaves as whole 128 B rows.  No workgroup barriers.
 // ---------------------------------------------------------------------------
 constexpr int G2_KS = 21;  // K steps of 4 held in registers (K <= 84)
 
-template <bool F16OUT>
-__device__ __forceinline__ void g2_tile(const float (&a)[2][G2_KS], const float (&b)[2][G2_KS], int ks, int64_t o0,
-                                        int64_t n_obj, int64_t col0, int64_t rows, int lm, int lk,
+// One wave's output tile goes through LDS so that it leaves as whole rows:
+// the MFMA D layout gives each lane 16 values in 4 rows of 16-column
+// segments; stored directly that is 64 B pieces of four rows per
+// instruction, which HBM absorbs at ~60% of the rate of full rows.  Rows are
+// padded to 36 floats (16-byte aligned, banks shifted by 4 per row).
+constexpr int G2_LDS_STRIDE = 36;
+constexpr int G2_LDS_WAVE = 32 * G2_LDS_STRIDE;  // floats per wave
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool F16OUT, int KS>
+__device__ __forceinline__ void g2_tile(const float (&a)[2][KS], const float (&b)[2][KS], int64_t o0,
+                                        int64_t n_obj, int64_t col0, int64_t rows, int lane, float* __restrict__ stage,
                                         void* __restrict__ lut)
 {
+    const int lm = lane & 15, lk = lane >> 4;
     floatx4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < G2_KS; ++s) {
-        if (s < ks) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int64_t col = col0 + 16 * j + lm;
-        if (col >= rows) continue;
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t o = o0 + 16 * i + 4 * lk + e;
-                if (o >= n_obj) continue;
-                if constexpr (F16OUT)
-                    reinterpret_cast<__half*>(lut)[o * rows + col] = __float2half(acc[i][j][e]);
-                else
-                    reinterpret_cast<float*>(lut)[o * rows + col] = acc[i][j][e];
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+    // D[m][n] with m = 16 i + 4 lk + e (object), n = 16 j + lm (column)
+    wave_lds_sync();  // the previous tile's rows have been read
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) stage[(16 * i + 4 * lk + e) * G2_LDS_STRIDE + 16 * j + lm] = acc[i][j][e];
+    wave_lds_sync();
+    // row r = lane / 8 + 8 q, columns 4 (lane % 8) .. + 3; rows is a multiple
+    // of 4, so a group of four columns is wholly inside or outside the table
+    const int cg = 4 * (lane & 7);
+    const int64_t col = col0 + cg;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = (lane >> 3) + 8 * q;
+        const int64_t o = o0 + r;
+        const float4 v = *reinterpret_cast<const float4*>(stage + r * G2_LDS_STRIDE + cg);
+        if (o < n_obj && col < rows) {
+            if constexpr (F16OUT) {
+                __half2* dst = reinterpret_cast<__half2*>(reinterpret_cast<__half*>(lut) + o * rows + col);
+                dst[0] = __floats2half2_rn(v.x, v.y);
+                dst[1] = __floats2half2_rn(v.z, v.w);
+            } else {
+                *reinterpret_cast<float4*>(reinterpret_cast<float*>(lut) + o * rows + col) = v;
             }
+        }
     }
 }
 
-// B fragments of column tile t from the fragment-ordered table: b[j][s] at
-// Bf[t][s][j][lane], all offsets immediate from one base.
-__device__ __forceinline__ void g2_load_b(const float* __restrict__ Bf, int ks, int64_t t, int lane,
-                                          float (&b)[2][G2_KS])
+// B fragments of column tile t from the fragment-ordered table: ceil(KS/2)
+// float4 loads per lane (few enough that two tiles in flight stay within the
+// hardware's count of outstanding loads), all offsets immediate from one base.
+template <int KS>
+__device__ __forceinline__ void g2_load_b(const float* __restrict__ Bf, int64_t t, int lane, float (&b)[2][KS])
 {
-    const float* base = Bf + t * (int64_t)ks * 128 + lane;
+    constexpr int G = (KS + 1) / 2;
+    const float4* base = reinterpret_cast<const float4*>(Bf) + t * (int64_t)G * 64 + lane;
+    float4 q[G];
 #pragma unroll
-    for (int s = 0; s < G2_KS; ++s)
+    for (int g = 0; g < G; ++g) q[g] = base[g * 64];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j][s] = (s < ks) ? base[s * 128 + j * 64] : 0.0f;
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int v = 2 * s + j;
+            const float4 w = q[v >> 2];
+            b[j][s] = (v & 3) == 0 ? w.x : (v & 3) == 1 ? w.y : (v & 3) == 2 ? w.z : w.w;
+        }
 }
 
-template <bool F16OUT>
+template <bool F16OUT, int KS>
 __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__ C, int K, int64_t n_obj,
-                                                       const float* __restrict__ Bt, int ks, int64_t rows,
+                                                       const float* __restrict__ Bt, int64_t rows,
                                                        int64_t rows_pad, void* __restrict__ lut, int waves_per_xcd,
                                                        int n_sub)
 {
+    __shared__ __attribute__((aligned(16))) float stage_all[4 * G2_LDS_WAVE];
+    float* stage = stage_all + (threadIdx.x >> 6) * G2_LDS_WAVE;
     // XCD x owns column chunk x; the chunk is cut into n_sub sub-chunks and
     // the work units (object group, sub-chunk) are dealt to the XCD's waves
     const int lane = threadIdx.x & 63;
     const int xcd = blockIdx.x & 7;
-    const int wave_in_xcd = (int)(blockIdx.x >> 3) * 4 + (int)(threadIdx.x >> 6);
+    // wave-uniform (read from lane 0) so that the loops below are scalar: a
+    // loop the compiler takes as divergent gets exec-mask branches and waits
+    // for all outstanding memory operations at every join
+    const int wave_in_xcd = __builtin_amdgcn_readfirstlane((int)(blockIdx.x >> 3) * 4 + (int)(threadIdx.x >> 6));
     const int64_t ntiles = rows_pad / 32;  // column tiles of 32
     const int64_t per_chunk = (ntiles + 7) / 8;
     const int64_t c_begin = xcd * per_chunk;
@@ -329,28 +373,33 @@ __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__
         const int64_t t_end = (t_begin + per_sub) < c_end ? (t_begin + per_sub) : c_end;
         if (t_begin >= t_end) continue;
         const int64_t o0 = og * 32;
-        float a[2][G2_KS];
+        // loads are unconditional (clamped addresses, then a select), so the
+        // compiler's wait counts stay exact and the prefetch below overlaps
+        float a[2][KS];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int64_t o = o0 + 16 * i + lm;
+            const int64_t oc = o < n_obj ? o : n_obj - 1;
 #pragma unroll
-            for (int s = 0; s < G2_KS; ++s) {
+            for (int s = 0; s < KS; ++s) {
                 const int k = 4 * s + lk;
-                a[i][s] = (s < ks && o < n_obj && k < K) ? C[o * K + k] : 0.0f;
+                const float v = C[oc * K + (k < K ? k : K - 1)];
+                // zero outside the table by a bit mask: a select would let the
+                // compiler sink the load into a branch of its own
+                const unsigned int keep = (o < n_obj && k < K) ? 0xffffffffu : 0u;
+                a[i][s] = __uint_as_float(__float_as_uint(v) & keep);
             }
         }
-        // ping-pong over two B buffers: the next tile loads while this one computes
-        float b0[2][G2_KS], b1[2][G2_KS];
-        int64_t t = t_begin;
-        g2_load_b(Bt, ks, t, lane, b0);
-        while (t < t_end) {
-            if (t + 1 < t_end) g2_load_b(Bt, ks, t + 1, lane, b1);
-            g2_tile<F16OUT>(a, b0, ks, o0, n_obj, t * 32, rows, lm, lk, lut);
-            ++t;
-            if (t >= t_end) break;
-            if (t + 1 < t_end) g2_load_b(Bt, ks, t + 1, lane, b0);
-            g2_tile<F16OUT>(a, b1, ks, o0, n_obj, t * 32, rows, lm, lk, lut);
-            ++t;
+        // ping-pong over two B buffers: the next tile loads while this one
+        // computes (past the last tile the last one is loaded again, unused)
+        float b0[2][KS], b1[2][KS];
+        g2_load_b<KS>(Bt, t_begin, lane, b0);
+        for (int64_t t = t_begin; t < t_end; t += 2) {
+            g2_load_b<KS>(Bt, (t + 1 < t_end) ? t + 1 : t_end - 1, lane, b1);
+            g2_tile<F16OUT, KS>(a, b0, o0, n_obj, t * 32, rows, lane, stage, lut);
+            if (t + 1 >= t_end) break;
+            g2_load_b<KS>(Bt, (t + 2 < t_end) ? t + 2 : t_end - 1, lane, b0);
+            g2_tile<F16OUT, KS>(a, b1, o0, n_obj, (t + 1) * 32, rows, lane, stage, lut);
         }
     }
 }
@@ -359,7 +408,9 @@ static inline int bake_kp(int L) { return (((L + 1) * (L + 1)) + 3) / 4 * 4; }
 static inline int64_t bake_rows(int N) { return texel_elems(N); }
 static inline int64_t bake_rows_pad(int N) { return (bake_rows(N) + GB_N - 1) / GB_N * GB_N; }
 
-size_t bake_workspace_bytes(int L, int N) { return (size_t)bake_kp(L) * (size_t)bake_rows_pad(N) * sizeof(float); }
+// K-major: Kp x rows_pad; fragment order: rows_pad x 8 ceil(Kp / 8) (4 more
+// K rows when Kp / 4 is odd)
+size_t bake_workspace_bytes(int L, int N) { return (size_t)(bake_kp(L) + 4) * (size_t)bake_rows_pad(N) * sizeof(float); }
 
 int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dtype, void* lut, void* ws,
                    hipStream_t stream)
@@ -395,12 +446,30 @@ int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dty
         if (n_sub > per_chunk) n_sub = per_chunk;
         if (n_sub < 1) n_sub = 1;
         const dim3 grid((unsigned)(per_xcd * 8));
-        if (out_dtype == SHM_F16)
-            hipLaunchKernelGGL(k_bake_gemm2<true>, grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, Kp / 4, rows,
-                               rows_pad, lut, waves_per_xcd, (int)n_sub);
-        else
-            hipLaunchKernelGGL(k_bake_gemm2<false>, grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, Kp / 4, rows,
-                               rows_pad, lut, waves_per_xcd, (int)n_sub);
+        const bool f16 = out_dtype == SHM_F16;
+        // the K steps are a compile-time count: loads and MFMAs are straight-line code
+#define SHM_G2(KSV)                                                                                                  \
+    case KSV:                                                                                                        \
+        if (f16)                                                                                                     \
+            hipLaunchKernelGGL((k_bake_gemm2<true, KSV>), grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, rows,     \
+                               rows_pad, lut, waves_per_xcd, (int)n_sub);                                            \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_bake_gemm2<false, KSV>), grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, rows,    \
+                               rows_pad, lut, waves_per_xcd, (int)n_sub);                                            \
+        break;
+        switch (Kp / 4) {  // L = 0..8: (L + 1)^2 rounded up to a multiple of 4, in steps of 4
+            SHM_G2(1)
+            SHM_G2(3)
+            SHM_G2(4)
+            SHM_G2(7)
+            SHM_G2(9)
+            SHM_G2(13)
+            SHM_G2(16)
+            SHM_G2(21)
+            default:
+                return fail(SHM_ERR_UNSUPPORTED, "bake: no contraction kernel for %d K steps", Kp / 4);
+        }
+#undef SHM_G2
         SHM_LAUNCH_CHECK();
         return SHM_OK;
     }

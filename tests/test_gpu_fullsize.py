@@ -1,0 +1,135 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py times,
+on sampled outputs the oracle computes one by one (or through properties
+that hold at any size):
+  * SH glyph field: 32,768 glyphs, L = 8, N = 32, 8,388,608 queries, cell
+    layout, FP32;
+  * bump impostor trace: N = 256, 1920 x 1080 rays;
+  * backward: N = 512, 2^22 queries (three radix passes);
+  * uneven batch: 4,096 objects, ~10^8 queries, FP16 cell LUTs, one
+    autotuned graph-captured persistent launch.
+Every oracle evaluation uses the LUT values the GPU produced (so the query,
+trace and backward are compared on the same data) and the bake is checked
+separately on the sampled objects."""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import oracle
+import paper_2602_20063_amd as shm
+import workloads
+from parity import check_value_grad
+from test_gpu_bake import check_lut
+from test_gpu_trace import compare
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def spread(n, k, rng):
+    """k sample indices over range(n), both ends included."""
+    idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, k - 2, replace=False)]))
+    return np.sort(idx)
+
+
+def test_glyph_field_full_size_sampled():
+    W = bench.W2
+    n, L, N, qp = W["n_glyph"], W["L"], W["N"], W["q_per"]
+    c, dirs = bench.setup_w2()
+    c_t, d_t = torch.as_tensor(c).to(DEV), torch.as_tensor(dirs).to(DEV)
+    lut = shm.bake_sh(c_t, N)
+    cells = shm.to_cells(lut)
+    out = torch.empty((n * qp, 4), device=DEV)
+    shm.shm_query_value_grad(cells, shm.SHM_F32, shm.SHM_LAYOUT_CELL, N, n, d_t, qp, out)
+    torch.cuda.synchronize()
+    g = spread(n, 48, np.random.default_rng(1))
+    lut_s = lut[torch.as_tensor(g, device=DEV)].cpu().numpy()
+    check_lut(lut_s, oracle.bake_sh(c[g].astype(np.float64), N), "glyph-field bake, sampled glyphs")
+    rows = (g[:, None] * qp + np.arange(qp)[None, :]).reshape(-1)
+    per = lut_s[0].size // 4
+    ref = oracle.query_objects(lut_s.reshape(-1).astype(np.float64), np.arange(len(g)) * per, [N] * len(g),
+                               np.arange(len(g)) * qp, [qp] * len(g), dirs[rows])
+    got = out[torch.as_tensor(rows, device=DEV)].cpu().numpy()
+    check_value_grad(got, ref, "glyph field, sampled glyphs")
+
+
+def test_trace_full_size_sampled():
+    N = 256
+    mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+    md = shm.margin_dirs(N).cpu().numpy().reshape(-1, 3)
+    samples = workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)
+    lut = shm.bake_fd(torch.as_tensor(samples).to(DEV), N)
+    rmax = float(shm.lut_rmax(lut).item()) * 1.0001
+    o, d = workloads.camera_rays(1920, 1080)
+    t, out, nrm = shm.trace(lut, (0.0, 0.0, 0.0), rmax, torch.as_tensor(o).to(DEV), torch.as_tensor(d).to(DEV))
+    torch.cuda.synchronize()
+    k = spread(o.shape[0], 4000, np.random.default_rng(2))
+    ref = oracle.trace(lut[0].cpu().numpy().astype(np.float64), np.zeros(3), rmax, o[k], d[k])
+    compare((t.cpu().numpy()[k], out.cpu().numpy()[k], nrm.cpu().numpy()[k]), ref, "trace 1920x1080")
+    assert 0.2 < np.isfinite(ref[0]).mean() < 0.8
+
+
+def test_backward_full_size():
+    """2^22 queries at N = 512.  dL/dLUT through the adjoint identity (the
+    outputs are linear in the LUT): sum(grad_lut * D) = sum(g * query(D)) for
+    a random LUT-shaped D, with the forward itself checked elsewhere; dL/d
+    dirs against the oracle on sampled queries."""
+    N, Q = 512, 1 << 22
+    r = workloads.rng_for(4)
+    dirs = workloads.uniform_dirs(Q, r)
+    lut_np = workloads.random_lut(N, r)
+    d_t, lut = torch.as_tensor(dirs).to(DEV), torch.as_tensor(lut_np).to(DEV)
+    gen = torch.Generator(device=DEV).manual_seed(4)
+    g = torch.randn((Q, 4), device=DEV, generator=gen)
+    D = torch.randn(lut.shape, device=DEV, generator=gen)
+    bc = shm.BackwardContext(N, 1, d_t, Q)
+    gl, gd = bc.backward(lut, g)
+    fD = shm.query(D[None], d_t)
+    torch.cuda.synchronize()
+    lhs = (gl.double() * D.double()).sum().item()
+    rhs = (g.double() * fD.double()).sum().item()
+    scale = (gl.double() * D.double()).abs().sum().item()
+    assert abs(lhs - rhs) <= 1e-5 * scale, (lhs, rhs, scale)
+    k = spread(Q, 3000, np.random.default_rng(3))
+    _, rd = oracle.backward(lut_np, dirs[k], g.cpu().numpy()[k])
+    gk = gd.cpu().numpy()[k]
+    gn = np.linalg.norm(rd, axis=1)
+    floor = np.sqrt(np.mean(gn ** 2))
+    assert (np.linalg.norm(gk - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3
+
+
+def test_uneven_batch_full_size_sampled(tmp_path):
+    B = bench.build_uneven_batch()
+    objs, n_obj, Qtot = B["objs"], B["n_obj"], B["Qtot"]
+    lut16 = B["lut32"].half()
+    out = torch.full((Qtot, 4), float("nan"), device=DEV)
+    plan = shm.Plan(objs, shm.SHM_F16, shm.SHM_LAYOUT_CELL)
+    plan.autotune(lut16, B["dirs"], out, cache_path=str(tmp_path / "tune.json"))
+    out.fill_(float("nan"))
+    plan.capture_graph(lut16, B["dirs"], out)
+    plan.graph_launch()
+    torch.cuda.synchronize()
+    plan.close()
+    spec, texel_off = B["spec"], B["texel_off"]
+    rng = np.random.default_rng(5)
+    big = np.flatnonzero(spec["N"] == spec["N"].max())
+    sel = np.unique(np.concatenate([spread(n_obj, 30, rng), big[:4], [int(np.argmax(spec["Q"]))]]))
+    flats, offs, Ns, qb, qc, rows = [], [], [], [], [], []
+    base = nq = 0
+    for o in sel:
+        Nn = int(spec["N"][o])
+        n = 6 * (Nn + 2) ** 2 * 4
+        flats.append(B["lut_tex"][texel_off[o]:texel_off[o] + n].half().double().cpu().numpy())
+        offs.append(base // 4)
+        base += n
+        q0, q = objs[o][2], objs[o][3]
+        pick = np.unique(np.concatenate([[0, q - 1], rng.choice(q, min(q, 600), replace=False)]))
+        Ns.append(Nn)
+        qb.append(nq)
+        qc.append(len(pick))
+        nq += len(pick)
+        rows.append(q0 + pick)
+    rows_all = np.concatenate(rows)
+    ref = oracle.query_objects(np.concatenate(flats), offs, Ns, qb, qc, B["dirs_np"][rows_all])
+    got = out[torch.as_tensor(rows_all, device=DEV)].cpu().numpy()
+    check_value_grad(got, ref, "uneven batch, sampled objects")
