@@ -60,7 +60,13 @@ struct Loc {
 // contraction).  The local coordinate s is then formed to ~1 ulp of s from
 // a double-float a (residual of the division by fma) instead of f - i0,
 // whose error grows like ulp(N).
-__device__ __forceinline__ Loc locate(float x, float y, float z, int N)
+// FAST: the four divisions by ma use the hardware reciprocal (~1 ulp)
+// instead of correctly rounded division.  s and t stay accurate to ~1 ulp
+// (the residual sc - a ma is still exact), but a direction within an ulp of
+// a cell boundary may be given to the neighbouring cell, whose patch agrees
+// there by C1 continuity; only the ray-casting iterations use it.
+template <bool FAST>
+__device__ __forceinline__ Loc locate_t(float x, float y, float z, int N)
 {
 #pragma clang fp contract(off)
     Loc L;
@@ -89,8 +95,9 @@ __device__ __forceinline__ Loc locate(float x, float y, float z, int N)
         tc = -y;
     }
     const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && (ma > 0.0f);
-    const float a = sc / ma;
-    const float b = tc / ma;
+    const float rma = FAST ? __builtin_amdgcn_rcpf(ma) : 0.0f;
+    const float a = FAST ? sc * rma : sc / ma;
+    const float b = FAST ? tc * rma : tc / ma;
     const float u = (a + 1.0f) * 0.5f;
     const float v = (b + 1.0f) * 0.5f;
     const float Nf = (float)N;
@@ -103,8 +110,8 @@ __device__ __forceinline__ Loc locate(float x, float y, float z, int N)
     i0 = i0 > N ? N : (i0 < 0 ? 0 : i0);
     j0 = j0 > N ? N : (j0 < 0 ? 0 : j0);
     // s = (a + 1) N/2 + 1/2 - i0 with a = a_hi + a_lo (exact residual)
-    const float a_lo = __builtin_fmaf(-a, ma, sc) / ma;
-    const float b_lo = __builtin_fmaf(-b, ma, tc) / ma;
+    const float a_lo = FAST ? __builtin_fmaf(-a, ma, sc) * rma : __builtin_fmaf(-a, ma, sc) / ma;
+    const float b_lo = FAST ? __builtin_fmaf(-b, ma, tc) * rma : __builtin_fmaf(-b, ma, tc) / ma;
     const float halfN = 0.5f * Nf;
     const float cu = (halfN + 0.5f) - (float)i0;  // exact: half-integers below 2^23
     const float cv = (halfN + 0.5f) - (float)j0;
@@ -117,6 +124,8 @@ __device__ __forceinline__ Loc locate(float x, float y, float z, int N)
     L.face = ok ? face : -1;
     return L;
 }
+
+__device__ __forceinline__ Loc locate(float x, float y, float z, int N) { return locate_t<false>(x, y, z, N); }
 
 // 16 footprint scalars: c[corner][ch], corner 0 = (i0,j0), 1 = (i0+1,j0),
 // 2 = (i0,j0+1), 3 = (i0+1,j0+1); ch = (r, r_u h, r_v h, r_uv h^2).
@@ -308,9 +317,11 @@ __device__ __forceinline__ void frame_of(int face, float3& M, float3& S, float3&
 
 // Ambient spherical gradient from chart derivatives (r_u, r_v), closed form
 // of the Sec. 3.4 metric solve.  Per face: M, S, T are signed axis vectors.
-__device__ __forceinline__ float3 transport(int face, float a, float b, float ru, float rv)
+template <bool FAST>
+__device__ __forceinline__ float3 transport_t(int face, float a, float b, float ru, float rv)
 {
-    const float rho = sqrtf(1.0f + a * a + b * b);
+    const float rho2 = 1.0f + a * a + b * b;
+    const float rho = FAST ? __builtin_amdgcn_sqrtf(rho2) : sqrtf(rho2);
     const float k = 0.5f * rho;
     const float gu = k * ru, gv = k * rv;
     const float gm = -(a * gu + b * gv);  // component along M
@@ -325,6 +336,11 @@ __device__ __forceinline__ float3 transport(int face, float a, float b, float ru
     }
 }
 
+__device__ __forceinline__ float3 transport(int face, float a, float b, float ru, float rv)
+{
+    return transport_t<false>(face, a, b, ru, rv);
+}
+
 // Eq. (10)
 __device__ __forceinline__ float3 normal_of(float R, float x, float y, float z, float3 g)
 {
@@ -335,15 +351,15 @@ __device__ __forceinline__ float3 normal_of(float R, float x, float y, float z, 
 }
 
 // Full query: returns (R, gx, gy, gz); NaN for an invalid direction.
-template <bool FP16, bool CELL>
+template <bool FP16, bool CELL, bool FAST = false>
 __device__ __forceinline__ float4 query_one(const void* __restrict__ lut, int N, float x, float y, float z)
 {
-    const Loc L = locate(x, y, z, N);
+    const Loc L = locate_t<FAST>(x, y, z, N);
     if (L.face < 0) return make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
     const Foot F = load_foot<FP16, CELL>(lut, N, L);
     const Patch P = hermite(F, L.s, L.t);
     const float Nf = (float)N;
-    const float3 g = transport(L.face, L.a, L.b, Nf * P.rs, Nf * P.rt);
+    const float3 g = transport_t<FAST>(L.face, L.a, L.b, Nf * P.rs, Nf * P.rt);
     return make_float4(P.r, g.x, g.y, g.z);
 }
 

@@ -20,15 +20,20 @@ struct FEval {
     int sgn;
 };
 
-template <bool FP16>
+// FAST evaluations (the iterations) use the hardware reciprocal, square
+// root and reciprocal square root (~1 ulp each) instead of the correctly
+// rounded sequences; the final evaluation, whose R, gradient and normal are
+// returned, is the exact query.
+template <bool FP16, bool FAST = true>
 __device__ __forceinline__ FEval trace_eval(const void* __restrict__ lut, int N, float ox, float oy, float oz,
                                             float dx, float dy, float dz, float t, float scale, bool is_signed)
 {
     FEval E;
     const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
-    const float4 r = rendered(query_one<FP16, false>(lut, N, px, py, pz), scale, is_signed, &E.sgn);
-    const float len = sqrtf(px * px + py * py + pz * pz);
-    const float il = 1.0f / len;
+    const float4 r = rendered(query_one<FP16, false, FAST>(lut, N, px, py, pz), scale, is_signed, &E.sgn);
+    const float p2 = px * px + py * py + pz * pz;
+    const float il = FAST ? __builtin_amdgcn_rsqf(p2) : 1.0f / sqrtf(p2);
+    const float len = FAST ? p2 * il : sqrtf(p2);
     E.R = r.x;
     E.g = make_float3(r.y, r.z, r.w);
     E.w = make_float3(px * il, py * il, pz * il);
@@ -119,7 +124,7 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
                     ++evals;
                     if (E.F < 0.0f) hi = t;
                     else lo = t;
-                    float tn = t - E.F / E.dF;
+                    float tn = t - E.F * __builtin_amdgcn_rcpf(E.dF);
                     if (!(tn >= lo && tn <= hi)) tn = 0.5f * (lo + hi);
                     t = tn;
                 }
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
         }
     }
     if (hit) {
-        const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
+        const FEval E = trace_eval<FP16, false>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
         ++evals;
         if (sign_out) sign_out[r] = (int8_t)E.sgn;
         t_out[r] = t;
