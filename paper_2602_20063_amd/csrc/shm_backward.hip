@@ -344,6 +344,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
 {
     __shared__ float4 slot[BWD_THREADS][4];  // one query's weights per lane; later the cell sums
     __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
+    __shared__ int64_t row_len[BC];          // queries in each cell row's range
     __shared__ int64_t row_off[BC + 1];      // offsets of the rows in the concatenated list
     const int C = N + 1, P = N + 2;
     const int tpf = tiles_per_face;
@@ -376,12 +377,13 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
             e = min(max((int64_t)cs[c0 + i_hi + 1], a), Q);
         }
         row_start[tid] = a;
-        row_off[tid + 1] = e - a;
+        row_len[tid] = e - a;
     }
     __syncthreads();
-    if (tid == 0) {
-        row_off[0] = 0;
-        for (int k = 1; k <= BC; ++k) row_off[k] += row_off[k - 1];
+    if (tid <= BC) {  // exclusive prefix: independent reads, no serial chain
+        int64_t o = 0;
+        for (int k = 0; k < tid; ++k) o += row_len[k];
+        row_off[tid] = o;
     }
     __syncthreads();
     int64_t seg_lo = 0, seg_hi = 0;
@@ -400,10 +402,14 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     // the query at list position g and its cell row (Q past the end)
+    // (binary search for the last row starting at or before g: empty rows
+    // share their successor's offset, so it lands on the row holding g)
     auto query_at = [&](int64_t g, int& r) -> int64_t {
         r = 0;
         if (g >= total) return Q;
-        while (g >= row_off[r + 1]) ++r;
+#pragma unroll
+        for (int step = BC / 2; step >= 1; step >>= 1)
+            if (row_off[r + step] <= g) r += step;
         return perm[row_start[r] + (g - row_off[r])];
     };
     // software pipeline: round k + 1's index, direction and upstream
