@@ -177,6 +177,11 @@ typedef struct shm_launch_shape {
     int32_t grid_per_cu; /* persistent workgroups per compute unit, 1..32     */
 } shm_launch_shape;
 
+/* Validates the descriptors (N in range, lut_offset >= 0 and aligned for
+ * the dtype/layout, q_begin, q_count >= 0), copies them to the device on
+ * `stream` and waits for the copy (objs_host may be released on return),
+ * builds the work list with the default shape {256, 2, 2048, 8}.  The
+ * plan must not outlive the device it was created on. */
 SHM_API int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, int32_t layout, hipStream_t stream,
                     shm_plan** plan_out);
 /* Times every candidate launch shape on the given (real) buffers, keeps the
@@ -185,6 +190,9 @@ SHM_API int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t 
  * workload signature, or NULL. */
 SHM_API int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float* out, const char* cache_path,
                       hipStream_t stream, shm_launch_shape* chosen);
+/* Sets the launch shape and drops any captured graph.  A new tile size
+ * rebuilds the work list, which first waits for all work on the device
+ * (a launch issued earlier may still read the old list). */
 SHM_API int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape);
 SHM_API int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal, hipStream_t stream);
 /* Captures one shm_plan_launch with these buffers into a HIP graph owned by

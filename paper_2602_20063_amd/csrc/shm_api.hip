@@ -108,6 +108,8 @@ static int plan_build_items(shm_plan* P, hipStream_t stream)
         }
     }
     const int64_t n = (int64_t)items.size();
+    // a launch issued earlier (on any stream) may still read the old list
+    if (P->d_items) SHM_HIP_CHECK(hipDeviceSynchronize());
     if (n > P->items_cap) {
         if (P->d_items) SHM_HIP_CHECK(hipFree(P->d_items));
         P->d_items = nullptr;
@@ -259,7 +261,9 @@ int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, i
         delete P;
         return fail(SHM_ERR_HIP, "plan_create: hipMalloc failed");
     }
-    if (n_obj && hipMemcpyAsync(P->d_objs, objs_host, (size_t)n_obj * sizeof(shm_object), hipMemcpyHostToDevice, stream) != hipSuccess) {
+    if (n_obj && (hipMemcpyAsync(P->d_objs, objs_host, (size_t)n_obj * sizeof(shm_object), hipMemcpyHostToDevice,
+                                 stream) != hipSuccess ||
+                  hipStreamSynchronize(stream) != hipSuccess)) {  // objs_host may be released on return
         shm_plan_destroy(P);
         return fail(SHM_ERR_HIP, "plan_create: copy of descriptors failed");
     }
