@@ -158,6 +158,8 @@ def main():
         lut4 = torch.zeros((1, 6, Nb + 2, Nb + 2, 4), device=DEV)
         bctx = shm.BackwardContext(Nb, 1, d4, Qb)
         bctx.backward(lut4, torch.ones((Qb, 4), device=DEV))
+        # one forward of the fit (texel layout, sorted directions, N = 512)
+        shm.shm_query_value_grad(lut4, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, Nb, 1, d4, Qb, torch.empty((Qb, 4), device=DEV))
         # one trace of the bump impostor (N = 256, 1920 x 1080, FP32)
         mu, amp, width = workloads.bump_params(workloads.rng_for(3))
         md = shm.margin_dirs(256).cpu().numpy().reshape(-1, 3)
@@ -190,6 +192,17 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_query_uniform<f32, cell>", "alg_bytes_per_launch": B},
     }
+    # the stream rate this machine delivers, measured in the same run: a 4 GiB
+    # device copy (read + write), reported beside the spec peak
+    src = torch.empty(1 << 29, dtype=torch.float64, device=DEV).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms_copy = t_gpu(lambda: dst.copy_(src), 5)
+    copy_gbs = 2 * src.numel() * 8 / ms_copy / 1e6
+    del src, dst
+    result["roofline"]["measured_copy_gbs"] = copy_gbs
+    result["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
+    log(f"device copy {copy_gbs:.0f} GB/s (read + write); headline = {achieved / copy_gbs:.3f} of it")
     forms = {}
     sample_out = {}
     if not args.no_forms:
@@ -597,9 +610,23 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
         tq += time.time() - t0
         reps += 1
     qps = reps * ns * q_per / tq
-    cpu = {"value": qps, "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # the same sample on one core (a tenth of the glyphs)
+    oracle.set_threads(1)
+    n1 = ns // 10
+    t0 = time.time()
+    oracle.query_objects(flat, off[:n1], [N] * n1, np.arange(n1) * q_per, [q_per] * n1, d[: n1 * q_per])
+    qps1 = n1 * q_per / (time.time() - t0)
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        model = next(line.split(":", 1)[1].strip() for line in open("/proc/cpuinfo") if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    cpu = {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
            "sample": f"{ns} of {W2['n_glyph']} glyphs ({ns * q_per} queries) of the SH glyph field, FP64 oracle "
-                     f"(bake of the sample {bake_s:.1f} s untimed), query repeated {reps}x ({tq:.1f} s)"}
+                     f"(bake of the sample {bake_s:.1f} s untimed), query repeated {reps}x ({tq:.1f} s)",
+           "one_core_value": qps1, "cpu_model": model}
     log("cpu baseline", cpu)
     errs = {}
 

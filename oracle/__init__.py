@@ -75,6 +75,11 @@ def num_threads():
     return int(lib().orc_num_threads())
 
 
+def set_threads(n):
+    """Number of OpenMP threads for the following oracle calls."""
+    lib().orc_set_threads(ctypes.c_int(int(n)))
+
+
 def lut_shape(N):
     return (6, N + 2, N + 2, 4)
 

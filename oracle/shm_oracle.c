@@ -1148,8 +1148,10 @@ ORC_API int orc_version(void) { return 1; }
 #ifdef _OPENMP
 #include <omp.h>
 ORC_API int orc_num_threads(void) { return omp_get_max_threads(); }
+ORC_API void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 ORC_API int orc_num_threads(void) { return 1; }
+ORC_API void orc_set_threads(int n) { (void)n; }
 #endif
 
 /* ------------------------------------------------------------------------ */
