@@ -287,21 +287,30 @@ constexpr int BC = BT + 1;             // cells per tile side
 constexpr int BWD_THREADS = 256;
 static_assert(BC * BC == BWD_THREADS, "one lane per cell of a tile");
 
-// dL/d(16 footprint scalars) of one query, as 4 corners x (r, r_u h, r_v h, r_uv h^2)
+// dL/d(16 footprint scalars) of one query, as 4 corners x (r, r_u h, r_v h, r_uv h^2).
+// Each weight is gR Fs Ft + nlu Fs' Ft + nlv Fs Ft' for one s-basis function
+// Fs (H0, H1, H0d, H1d at s) and one t-basis function Ft, so with
+// P(Fs) = gR Fs + nlu Fs' and Qv(Fs) = nlv Fs it is P(Fs) Ft + Qv(Fs) Ft'.
 __device__ __forceinline__ void query_weights(float gR, float nlu, float nlv, const Basis1& Sb, const Basis1& Tt,
                                               float4 w[4])
 {
+    // s-functions: value 0/1 (H0 = 1 - H1) and slope 0/1 (H0d, H1d), with derivatives
+    const float sv[2] = {1.0f - Sb.h1, Sb.h1}, svd[2] = {-Sb.d1, Sb.d1};
+    const float ss[2] = {Sb.h0d, Sb.h1d}, ssd[2] = {Sb.d0d, Sb.d1d};
+    const float tv[2] = {1.0f - Tt.h1, Tt.h1}, tvd[2] = {-Tt.d1, Tt.d1};
+    const float ts[2] = {Tt.h0d, Tt.h1d}, tsd[2] = {Tt.d0d, Tt.d1d};
 #pragma unroll
-    for (int corner = 0; corner < 4; ++corner) {
-        const bool cI = corner & 1, cJ = corner >> 1;
-        const float Hi = cI ? Sb.h1 : 1.0f - Sb.h1, Hdi = cI ? Sb.h1d : Sb.h0d;
-        const float dHi = cI ? Sb.d1 : -Sb.d1, dHdi = cI ? Sb.d1d : Sb.d0d;
-        const float Hj = cJ ? Tt.h1 : 1.0f - Tt.h1, Hdj = cJ ? Tt.h1d : Tt.h0d;
-        const float dHj = cJ ? Tt.d1 : -Tt.d1, dHdj = cJ ? Tt.d1d : Tt.d0d;
-        w[corner].x = gR * Hi * Hj + nlu * dHi * Hj + nlv * Hi * dHj;
-        w[corner].y = gR * Hdi * Hj + nlu * dHdi * Hj + nlv * Hdi * dHj;
-        w[corner].z = gR * Hi * Hdj + nlu * dHi * Hdj + nlv * Hi * dHdj;
-        w[corner].w = gR * Hdi * Hdj + nlu * dHdi * Hdj + nlv * Hdi * dHdj;
+    for (int cI = 0; cI < 2; ++cI) {
+        const float Pv = gR * sv[cI] + nlu * svd[cI], Qv = nlv * sv[cI];
+        const float Ps = gR * ss[cI] + nlu * ssd[cI], Qs = nlv * ss[cI];
+#pragma unroll
+        for (int cJ = 0; cJ < 2; ++cJ) {
+            float4& o = w[cJ * 2 + cI];
+            o.x = Pv * tv[cJ] + Qv * tvd[cJ];   // r
+            o.y = Ps * tv[cJ] + Qs * tvd[cJ];   // r_u h
+            o.z = Pv * ts[cJ] + Qv * tsd[cJ];   // r_v h
+            o.w = Ps * ts[cJ] + Qs * tsd[cJ];   // r_uv h^2
+        }
     }
 }
 

@@ -110,8 +110,12 @@ __device__ __forceinline__ Loc locate_t(float x, float y, float z, int N)
     i0 = i0 > N ? N : (i0 < 0 ? 0 : i0);
     j0 = j0 > N ? N : (j0 < 0 ? 0 : j0);
     // s = (a + 1) N/2 + 1/2 - i0 with a = a_hi + a_lo (exact residual)
-    const float a_lo = FAST ? __builtin_fmaf(-a, ma, sc) * rma : __builtin_fmaf(-a, ma, sc) / ma;
-    const float b_lo = FAST ? __builtin_fmaf(-b, ma, tc) * rma : __builtin_fmaf(-b, ma, tc) / ma;
+    // the residual terms only refine s, t below FP32 resolution (they are
+    // ~ulp(a)): the hardware reciprocal is exact enough for them, and the
+    // decisions above used the correctly rounded a, b
+    const float ir = FAST ? rma : __builtin_amdgcn_rcpf(ma);
+    const float a_lo = __builtin_fmaf(-a, ma, sc) * ir;
+    const float b_lo = __builtin_fmaf(-b, ma, tc) * ir;
     const float halfN = 0.5f * Nf;
     const float cu = (halfN + 0.5f) - (float)i0;  // exact: half-integers below 2^23
     const float cv = (halfN + 0.5f) - (float)j0;
