@@ -168,7 +168,7 @@ def main():
         lut3 = shm.bake_fd(to_dev(workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)), 256)
         rmax = float(shm.lut_rmax(lut3).item()) * 1.0001
         o3, d3 = workloads.camera_rays(1920, 1080)
-        shm.trace(lut3, (0.0, 0.0, 0.0), rmax, to_dev(o3), to_dev(d3))
+        shm.trace(lut3, (0.0, 0.0, 0.0), rmax, to_dev(o3), to_dev(d3), image_width=1920)
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "query_launches": 3, "copy_bytes": 1 << 30}))
         return
@@ -559,13 +559,17 @@ def run_trace():
     P = o.shape[0]
     res = {"rays": P, "N": N, "rmax": rmax}
     smp = {"mu": mu, "amp": amp, "width": width, "o": o_np, "d": d_np, "rmax": rmax}
+    W = 1920  # the rays are the row-major 1920 x 1080 image: one wavefront per 8 x 8 pixel tile
     for name, lt in (("f32", lut), ("f16", lut.half())):
-        t, out, nrm = shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d)
-        ms = t_gpu(lambda: shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d), 5)
+        t, out, nrm = shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W)
+        ms = t_gpu(lambda: shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W), 20)
         hit = torch.isfinite(t)
         res[name] = {"ms": ms, "rays_per_s": P / ms * 1e3, "hit_frac": hit.float().mean().item(),
                      "evals_per_s_upper": 32 * P / ms * 1e3}
         smp[name] = (t.cpu().numpy(), nrm.cpu().numpy())
+    # the same rays one lane per ray in image order (64-pixel row pieces per wavefront)
+    ms = t_gpu(lambda: shm.trace(lut, (0.0, 0.0, 0.0), rmax, o, d), 20)
+    res["f32_ray_order"] = {"ms": ms, "rays_per_s": P / ms * 1e3}
     # Sec. 3.1 adaptive budget: bisections follow the projected size (focal
     # length of the 1080-pixel-high image, 1/8 pixel bracket), capped at 16;
     # the same glyph seen from 3.5 and from 12 units
@@ -576,9 +580,10 @@ def run_trace():
     for name, eye in (("f32_adaptive", (0.0, 0.0, 3.5)), ("f32_adaptive_far", (0.0, 0.0, 12.0))):
         o2_np, d2_np = workloads.camera_rays(1920, 1080, eye=eye)
         o2, d2 = to_dev(o2_np), to_dev(d2_np)
-        fn = lambda: shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, px_per_unit=px, eps_px=0.125, n_bisect=16)
+        fn = lambda: shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, px_per_unit=px, eps_px=0.125, n_bisect=16,
+                                  image_width=W)
         t2, _, _, _, ev2 = fn()
-        ms = t_gpu(fn, 5)
+        ms = t_gpu(fn, 20)
         h2 = torch.isfinite(t2)
         # the march does not depend on the budget: a fixed 16 spends 16 - k more
         _, _, _, _, ev16 = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, n_bisect=16, normals=False)

@@ -260,7 +260,8 @@ SHM_API int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const fl
  * n_bisect fixed.  rmax must bound R (scale * shm_lut_rmax).
  *   sign   [P] int8: sign of r at the hit (0 on a miss) or NULL
  *   evals  [P] uint8: evaluations of F spent by the ray or NULL
- * shm_trace_radial is this with scale 1, no flags, fixed counts. */
+ * shm_trace_radial is this with scale 1, no flags, fixed counts and rays
+ * in any order. */
 typedef struct shm_trace_params {
     float scale;          /* s > 0 */
     int32_t flags;        /* 0 or SHM_SIGNED */
@@ -269,6 +270,11 @@ typedef struct shm_trace_params {
     int32_t n_newton;     /* n_march + n_bisect + n_newton + 1 <= 64 */
     float px_per_unit;    /* 0: fixed budget; > 0: adaptive */
     float eps_px;         /* > 0 with an adaptive budget */
+    int32_t image_width;  /* 0: rays in any order; W > 0: the rays are a
+                             row-major image W pixels wide (P a multiple of
+                             W) and each wavefront traces an 8 x 8 pixel tile,
+                             so that its rays take similar numbers of steps;
+                             the results are the same bits either way */
 } shm_trace_params;
 SHM_API int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax,
                                 const shm_trace_params* params, const float* ray_o, const float* ray_d, int64_t P,

@@ -47,7 +47,7 @@ class shm_launch_shape(ctypes.Structure):
 class shm_trace_params(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_float), ("flags", ctypes.c_int32), ("n_march", ctypes.c_int32),
                 ("n_bisect", ctypes.c_int32), ("n_newton", ctypes.c_int32), ("px_per_unit", ctypes.c_float),
-                ("eps_px", ctypes.c_float)]
+                ("eps_px", ctypes.c_float), ("image_width", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -445,19 +445,27 @@ def cell_keys(lut_N, dirs, n_obj=1, stream=None):
     return keys
 
 
-def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, normals=True, stream=None):
+def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, normals=True, image_width=0,
+          stream=None):
+    """Fixed-schedule trace: t, (R, grad), normal.  image_width > 0 says the
+    rays are a row-major image of that width (traced in 8 x 8 tiles)."""
     N = lut_n(lut)
     P = ray_o.shape[0]
     t = torch.empty(P, dtype=torch.float32, device=ray_o.device)
     out = torch.empty((P, 4), dtype=torch.float32, device=ray_o.device)
     nrm = torch.empty((P, 3), dtype=torch.float32, device=ray_o.device) if normals else None
-    shm_trace_radial(lut, _dtype_code(lut), N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t, out,
-                     nrm, stream)
+    if image_width:
+        prm = shm_trace_params(1.0, 0, n_march, n_bisect, n_newton, 0.0, 0.0, int(image_width))
+        shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, None, None,
+                            stream)
+    else:
+        shm_trace_radial(lut, _dtype_code(lut), N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t, out,
+                         nrm, stream)
     return t, out, nrm
 
 
 def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_unit=0.0, eps_px=0.125, n_march=20,
-             n_bisect=16, n_newton=3, normals=True, stream=None):
+             n_bisect=16, n_newton=3, normals=True, image_width=0, stream=None):
     """Rendered-radius trace with the adaptive bisection budget: returns
     t, (R, grad), normal, sign of r (int8), F evaluations per ray (uint8)."""
     N = lut_n(lut)
@@ -469,7 +477,7 @@ def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_un
     sgn = torch.empty(P, dtype=torch.int8, device=dev)
     ev = torch.empty(P, dtype=torch.uint8, device=dev)
     prm = shm_trace_params(float(scale), SHM_SIGNED if signed else 0, n_march, n_bisect, n_newton, float(px_per_unit),
-                           float(eps_px))
+                           float(eps_px), int(image_width))
     shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, sgn, ev, stream)
     return t, out, nrm, sgn, ev
 

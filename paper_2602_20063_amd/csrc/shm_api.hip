@@ -57,9 +57,9 @@ int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
                     float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
 int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
-                 float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int n_march,
-                 int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign, uint8_t* evals,
-                 hipStream_t stream);
+                 float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int image_width,
+                 int n_march, int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign,
+                 uint8_t* evals, hipStream_t stream);
 int launch_query_scaled(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
                         int64_t q_per_obj, float scale, int flags, float* out, float* normal, int8_t* sign,
                         hipStream_t stream);
@@ -519,6 +519,7 @@ static int check_trace_params(const shm_trace_params* tp)
         return fail(SHM_ERR_INVALID_ARG, "trace: px_per_unit must be finite and >= 0");
     if (tp->px_per_unit > 0.0f && !(tp->eps_px > 0.0f && std::isfinite(tp->eps_px)))
         return fail(SHM_ERR_INVALID_ARG, "trace: eps_px must be positive and finite with an adaptive budget");
+    if (tp->image_width < 0) return fail(SHM_ERR_INVALID_ARG, "trace: negative image_width");
     return SHM_OK;
 }
 
@@ -533,19 +534,22 @@ int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* 
     int rc = check_trace_params(params);
     if (rc) return rc;
     if (!center) return fail(SHM_ERR_INVALID_ARG, "trace: null center");
+    if (params->image_width > 0 && P % params->image_width != 0)
+        return fail(SHM_ERR_INVALID_ARG, "trace: %lld rays are not whole rows of width %d", (long long)P,
+                    params->image_width);
     if (P == 0) return SHM_OK;
     if (!lut || !ray_o || !ray_d || !t_out || !out) return fail(SHM_ERR_INVALID_ARG, "trace: null pointer");
     if (!aligned(lut, dtype == SHM_F16 ? 8 : 16) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "trace: misaligned buffer");
     return launch_trace(lut, dtype, N, center, rmax, params->scale, params->flags, params->px_per_unit, params->eps_px,
-                        ray_o, ray_d, P, params->n_march, params->n_bisect, params->n_newton, t_out, out, normal, sign,
-                        evals, stream);
+                        ray_o, ray_d, P, params->image_width, params->n_march, params->n_bisect, params->n_newton,
+                        t_out, out, normal, sign, evals, stream);
 }
 
 int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax, const float* ray_o,
                      const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
                      float* out, float* normal, hipStream_t stream)
 {
-    const shm_trace_params tp = {1.0f, 0, n_march, n_bisect, n_newton, 0.0f, 0.0f};
+    const shm_trace_params tp = {1.0f, 0, n_march, n_bisect, n_newton, 0.0f, 0.0f, 0};
     return shm_trace_radial_ex(lut, dtype, N, center, rmax, &tp, ray_o, ray_d, P, t_out, out, normal, nullptr, nullptr,
                                stream);
 }

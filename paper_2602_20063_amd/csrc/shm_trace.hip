@@ -66,12 +66,23 @@ template <bool FP16, bool NRM>
 __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int N, float cx, float cy, float cz,
                                                float rmax, float scale, int is_signed_i, float px_focal, float eps_px,
                                                const float* __restrict__ ray_o, const float* __restrict__ ray_d,
-                                               int64_t P, int n_march, int n_bisect_max, int n_newton,
-                                               float* __restrict__ t_out, float* __restrict__ out,
-                                               float* __restrict__ nrm, int8_t* __restrict__ sign_out,
-                                               uint8_t* __restrict__ evals_out)
+                                               int64_t P, int img_w, int64_t tiles_x, int n_march,
+                                               int n_bisect_max, int n_newton, float* __restrict__ t_out,
+                                               float* __restrict__ out, float* __restrict__ nrm,
+                                               int8_t* __restrict__ sign_out, uint8_t* __restrict__ evals_out)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (img_w > 0) {
+        // wavefront -> 8 x 8 pixel tile of the row-major image (tiles row by
+        // row), lane -> pixel in the tile; pixels past the right or bottom
+        // edge have no ray
+        const int64_t tile = r >> 6;
+        const int lane = (int)(r & 63);
+        const int64_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        const int64_t x = tx * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
+        if (x >= img_w) return;
+        r = y * img_w + x;
+    }
     if (r >= P) return;
     const bool is_signed = is_signed_i != 0;
     // origin relative to the centre; unit direction
@@ -159,19 +170,27 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
 }
 
 int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
-                 float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int n_march,
-                 int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign, uint8_t* evals,
-                 hipStream_t stream)
+                 float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int image_width,
+                 int n_march, int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign,
+                 uint8_t* evals, hipStream_t stream)
 {
     if (P == 0) return SHM_OK;
-    const int64_t blocks = (P + 255) / 256;
+    // one lane per ray, or (image rays) one wavefront per 8 x 8 tile
+    int64_t tiles_x = 0, lanes = P;
+    if (image_width > 0) {
+        const int64_t h = P / image_width;
+        tiles_x = ((int64_t)image_width + 7) / 8;
+        lanes = tiles_x * ((h + 7) / 8) * 64;
+    }
+    const int64_t blocks = (lanes + 255) / 256;
     if (blocks > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "trace: too many rays");
     const dim3 g((unsigned)blocks), bl(256);
     const float cx = center[0], cy = center[1], cz = center[2];
     const int sgn = (flags & SHM_SIGNED) ? 1 : 0;
 #define SHM_T(F, NR)                                                                                                  \
     hipLaunchKernelGGL((k_trace<F, NR>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, scale, sgn, px_focal, eps_px,      \
-                       ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out, normal, sign, evals)
+                       ray_o, ray_d, P, image_width, tiles_x, n_march, n_bisect, n_newton, t_out, out, normal, sign, \
+                       evals)
     if (dtype == SHM_F16) {
         if (normal) SHM_T(true, true);
         else SHM_T(true, false);

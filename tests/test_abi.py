@@ -117,7 +117,7 @@ def test_render_validation():
     c = (ctypes.c_float * 3)(0, 0, 0)
 
     def prm(**kw):
-        d = dict(scale=1.0, flags=0, n_march=20, n_bisect=8, n_newton=3, px_per_unit=0.0, eps_px=0.0)
+        d = dict(scale=1.0, flags=0, n_march=20, n_bisect=8, n_newton=3, px_per_unit=0.0, eps_px=0.0, image_width=0)
         d.update(kw)
         return shm.shm_trace_params(**d)
 
@@ -127,8 +127,10 @@ def test_render_validation():
     assert tr(prm(), P=0) == shm.SHM_OK
     assert tr(prm(flags=shm.SHM_SIGNED, px_per_unit=900.0, eps_px=0.1), P=0) == shm.SHM_OK
     for bad in (prm(scale=0.0), prm(scale=float("inf")), prm(flags=2), prm(n_march=0), prm(n_bisect=60),
-                prm(px_per_unit=-1.0), prm(px_per_unit=float("nan")), prm(px_per_unit=100.0, eps_px=0.0)):
-        assert tr(bad) == shm.SHM_ERR_INVALID_ARG
+                prm(px_per_unit=-1.0), prm(px_per_unit=float("nan")), prm(px_per_unit=100.0, eps_px=0.0),
+                prm(image_width=-1), prm(image_width=3), prm(image_width=20)):
+        assert tr(bad) == shm.SHM_ERR_INVALID_ARG  # 10 rays: not whole rows of 3 or 20
+    assert tr(prm(image_width=7), P=0) == shm.SHM_OK
     assert call("shm_trace_radial_ex", p, 0, 8, c, 1.0, None, p, p, 10, p, p, None, None, None, None) == shm.SHM_ERR_INVALID_ARG
     q = lambda scale, flags, Q=10: call("shm_query_scaled", p, 0, 0, 8, 1, p, Q, scale, flags, p, None, None, None)
     assert q(0.0, 0) == shm.SHM_ERR_INVALID_ARG

@@ -81,3 +81,41 @@ def test_trace_constant_sphere_and_misses():
     assert np.array_equal(hit, disc > 0) or np.mean(hit != (disc > 0)) < 0.002
     te = -b[hit] - np.sqrt(disc[hit])
     assert np.abs(tg[hit] - te).max() < 1e-5
+
+
+@pytest.mark.parametrize("W,H", [(67, 29), (8, 8), (1, 5), (200, 1)])
+def test_trace_image_tiles_same_bits(W, H):
+    """Rays of a row-major image traced one wavefront per 8 x 8 tile (ragged
+    right and bottom edges) give the same bits as one lane per ray in ray
+    order, for every output and both LUT precisions, fixed and adaptive
+    budgets; and match the oracle."""
+    mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+    N = 64
+    dirs = oracle.margin_dirs(N)
+    samples = workloads.bumps_value(mu, amp, width, 1.0, dirs.reshape(-1, 3)).reshape(6, N + 4, N + 4)
+    lut = oracle.bake_fd(samples, N).astype(np.float32)
+    rmax = oracle.rmax_bound(lut.astype(np.float64)) * 1.0001
+    o, d = workloads.camera_rays(W, H, vfov_deg=25.0)
+    og, dg = gpu(o), gpu(d)
+    for dt in (torch.float32, torch.float16):
+        lt = gpu(lut, dt)
+        lin = shm.trace(lt, (0.0, 0.0, 0.0), rmax, og, dg)
+        til = shm.trace(lt, (0.0, 0.0, 0.0), rmax, og, dg, image_width=W)
+        for a, b in zip(lin, til):
+            assert same_bits(a, b)
+        lin = shm.trace_ex(lt, (0.0, 0.0, 0.0), rmax, og, dg, px_per_unit=300.0, eps_px=0.125, n_bisect=12)
+        til = shm.trace_ex(lt, (0.0, 0.0, 0.0), rmax, og, dg, px_per_unit=300.0, eps_px=0.125, n_bisect=12,
+                           image_width=W)
+        for a, b in zip(lin, til):
+            assert same_bits(a, b)
+    g = tuple(x.cpu().numpy() for x in shm.trace(gpu(lut), (0.0, 0.0, 0.0), rmax, og, dg, image_width=W))
+    torch.cuda.synchronize()
+    ref = oracle.trace(lut.astype(np.float64), np.zeros(3), rmax, o, d)
+    assert np.isfinite(ref[0]).any()
+    compare(g, ref, f"tiled {W}x{H}", max_disagree=max(0.002, 1.5 / (W * H)))
+
+
+def same_bits(a, b):
+    if a.dtype == torch.float32:
+        return torch.equal(a.view(torch.int32), b.view(torch.int32))
+    return torch.equal(a, b)
