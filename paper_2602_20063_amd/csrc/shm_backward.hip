@@ -317,7 +317,8 @@ __device__ __forceinline__ void query_weights(float gR, float nlu, float nlv, co
 // dL/d dirs of one query: second chart derivatives of the patch plus the
 // derivative of the chart map (a = sc/ma, b = tc/ma) at d.  Not inlined, so
 // that every kernel variant runs the same instructions and gets the same
-// bits whichever other gradients it computes.
+// bits whichever other gradients it computes.  Its reciprocals and square
+// root are the hardware's (~1 ulp): no decision depends on them.
 __device__ __noinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int N, Loc L, float4 gq, float3 M,
                                          float3 S, float3 T, float x, float y, float z)
 {
@@ -327,7 +328,7 @@ __device__ __noinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int 
     const float3 Tb = make_float3(T.x - B * M.x, T.y - B * M.y, T.z - B * M.z);
     const float gS = gq.y * Sa.x + gq.z * Sa.y + gq.w * Sa.z;
     const float gT = gq.y * Tb.x + gq.z * Tb.y + gq.w * Tb.z;
-    const float rho = sqrtf(1.0f + A * A + B * B);
+    const float rho = __builtin_amdgcn_sqrtf(1.0f + A * A + B * B);
     const float kk2 = 0.5f * rho;
     const float gR = gq.x;
     const Foot F = load_texel_f32(lut_obj, N, L);
@@ -335,10 +336,10 @@ __device__ __noinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int 
     const float gM = gq.y * M.x + gq.z * M.y + gq.w * M.z;
     const float ru = Nf * Pp.rs, rv = Nf * Pp.rt;
     const float hN2 = 0.5f * Nf * Nf;
-    const float common = (ru * gS + rv * gT) / (2.0f * rho);
+    const float common = (ru * gS + rv * gT) * __builtin_amdgcn_rcpf(2.0f * rho);
     const float dLda = 0.5f * Nf * gR * Pp.rs + A * common + kk2 * (hN2 * Pp.rss * gS - ru * gM + hN2 * Pp.rst * gT);
     const float dLdb = 0.5f * Nf * gR * Pp.rt + B * common + kk2 * (hN2 * Pp.rst * gS + hN2 * Pp.rtt * gT - rv * gM);
-    const float im = 1.0f / (x * M.x + y * M.y + z * M.z);
+    const float im = __builtin_amdgcn_rcpf(x * M.x + y * M.y + z * M.z);
     return make_float3((dLda * Sa.x + dLdb * Tb.x) * im, (dLda * Sa.y + dLdb * Tb.y) * im,
                        (dLda * Sa.z + dLdb * Tb.z) * im);
 }
@@ -436,29 +437,25 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     for (int64_t base = 0; base < total; base += BWD_THREADS) {
         int r_next;
         const int64_t q_next = query_at(base + BWD_THREADS + tid, r_next);
-        float4 w[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        // list positions base + tid < total hold a query (q_cur < Q) and
+        // fill their slot; the reduction below reads no other slot
         if (q_cur < Q) {
             const Loc L = locate(x, y, z, N);  // the cell of row r_cur (keys come from the same decision)
             if constexpr (LUT) {
                 const float A = L.a, B = L.b;
                 const float gS = gq.y * (S.x - A * M.x) + gq.z * (S.y - A * M.y) + gq.w * (S.z - A * M.z);
                 const float gT = gq.y * (T.x - B * M.x) + gq.z * (T.y - B * M.y) + gq.w * (T.z - B * M.z);
-                const float kk2 = 0.5f * sqrtf(1.0f + A * A + B * B);
+                const float kk2 = 0.5f * __builtin_amdgcn_sqrtf(1.0f + A * A + B * B);
+                float4 w[4];
                 query_weights(gq.x, Nf * kk2 * gS, Nf * kk2 * gT, basis1(L.s), basis1(L.t), w);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
             }
             if (DIRS && L.i0 >= p0 && r_cur >= 1) {  // the tile owns the cell
                 const float3 gd = dirs_grad(lut + obj * lut_elems, N, L, gq, M, S, T, x, y, z);
                 grad_dirs[3 * q_cur] = gd.x;
                 grad_dirs[3 * q_cur + 1] = gd.y;
                 grad_dirs[3 * q_cur + 2] = gd.z;
-            }
-        }
-        if constexpr (LUT) {
-            if (base + tid < total) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
             }
         }
         if (q_next < Q) {
