@@ -51,7 +51,7 @@ def test_mesh_depth_box_closed_form():
 
 
 def test_mesh_depth_asteroid_full_size_sampled():
-    """The bench configuration: 81,920 triangles (20 triangle chunks combined
+    """The bench configuration: 81,920 triangles (40 triangle chunks combined
     by atomic max), the 6 x 52^2 margin grid of N = 48; the oracle checks a
     sample of the rays."""
     prm = workloads.asteroid_params(workloads.rng_for(6))
