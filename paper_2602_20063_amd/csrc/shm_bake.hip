@@ -256,7 +256,10 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
 // walks the column tiles (32 columns) of its chunk, loading the B fragments
 // of the next tile while the 4 x KS MFMAs of the current one run, and
 // stores a 32 x 32 output tile per step, staged through the wave's own LDS
-// buffer so that it leaves as whole 128 B rows.  No workgroup barriers.
+// buffer so that it leaves as whole 128 B rows.  Each tile's staging and
+// stores are threaded through the next tile's MFMAs (which run
+// asynchronously), so the matrix pipe does not wait for them.  No workgroup
+// barriers.
 // ---------------------------------------------------------------------------
 constexpr int G2_KS = 21;  // K steps of 4 held in registers (K <= 84)
 
@@ -275,52 +278,111 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool F16OUT, int KS>
-__device__ __forceinline__ void g2_tile(const float (&a)[2][KS], const float (&b)[2][KS], int64_t o0,
-                                        int64_t n_obj, int64_t col0, int64_t rows, int lane, float* __restrict__ stage,
-                                        void* __restrict__ lut)
+// MFMAs of K steps [S0, S1) of one 32 x 32 output tile: four independent
+// accumulator chains (2 object blocks x 2 column blocks of 16).
+template <int KS, int S0, int S1>
+__device__ __forceinline__ void g2_mma(const float (&a)[2][KS], const float (&b)[2][KS], floatx4 (&acc)[2][2])
 {
-    const int lm = lane & 15, lk = lane >> 4;
-    floatx4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = S0; s < S1; ++s)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-    // D[m][n] with m = 16 i + 4 lk + e (object), n = 16 j + lm (column)
-    wave_lds_sync();  // the previous tile's rows have been read
+}
+
+// Epilogue, part 1: D[m][n] with m = 16 i + 4 lk + e (object), n = 16 j + lm
+// (column) into the wave's LDS buffer, once the previous tile's rows have
+// been read out.
+__device__ __forceinline__ void g2_stage(const floatx4 (&acc)[2][2], float* __restrict__ stage, int lane)
+{
+    const int lm = lane & 15, lk = lane >> 4;
+    wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) stage[(16 * i + 4 * lk + e) * G2_LDS_STRIDE + 16 * j + lm] = acc[i][j][e];
+}
+
+// Epilogue, part 2: row r = lane / 8 + 8 q, columns 4 (lane % 8) .. + 3 read
+// back from LDS ...
+__device__ __forceinline__ void g2_unstage(const float* __restrict__ stage, int lane, float4 (&v)[4])
+{
     wave_lds_sync();
-    // row r = lane / 8 + 8 q, columns 4 (lane % 8) .. + 3; rows is a multiple
-    // of 4, so a group of four columns is wholly inside or outside the table
     const int cg = 4 * (lane & 7);
-    const int64_t col = col0 + cg;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const float4*>(stage + ((lane >> 3) + 8 * q) * G2_LDS_STRIDE + cg);
+}
+
+// ... and part 3: stored as whole 128 B rows; rows is a multiple of 4, so a
+// group of four columns is wholly inside or outside the table
+template <bool F16OUT>
+__device__ __forceinline__ void g2_store(const float4 (&v)[4], int64_t o0, int64_t n_obj, int64_t col0, int64_t rows,
+                                         int lane, void* __restrict__ lut)
+{
+    const int64_t col = col0 + 4 * (lane & 7);
+    // an empty statement that takes every value: the LDS reads stay where
+    // they were issued instead of sinking into the guarded stores below
+#pragma unroll
+    for (int q = 0; q < 4; ++q) asm volatile("" : : "v"(v[q].x), "v"(v[q].y), "v"(v[q].z), "v"(v[q].w));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int r = (lane >> 3) + 8 * q;
-        const int64_t o = o0 + r;
-        const float4 v = *reinterpret_cast<const float4*>(stage + r * G2_LDS_STRIDE + cg);
+        const int64_t o = o0 + (lane >> 3) + 8 * q;
         if (o < n_obj && col < rows) {
             if constexpr (F16OUT) {
                 __half2* dst = reinterpret_cast<__half2*>(reinterpret_cast<__half*>(lut) + o * rows + col);
-                dst[0] = __floats2half2_rn(v.x, v.y);
-                dst[1] = __floats2half2_rn(v.z, v.w);
+                dst[0] = __floats2half2_rn(v[q].x, v[q].y);
+                dst[1] = __floats2half2_rn(v[q].z, v[q].w);
             } else {
-                *reinterpret_cast<float4*>(reinterpret_cast<float*>(lut) + o * rows + col) = v;
+                *reinterpret_cast<float4*>(reinterpret_cast<float*>(lut) + o * rows + col) = v[q];
             }
         }
     }
+}
+
+// One tile's MFMAs (into acc) with the epilogue of the previous tile (prev,
+// column col_prev) threaded through them: the MFMAs run asynchronously, so
+// the LDS writes, reads and stores issued between them keep the matrix pipe
+// busy instead of following it.  The scheduling barriers keep that order.
+template <bool F16OUT, int KS>
+__device__ __forceinline__ void g2_tile_overlap(const float (&a)[2][KS], const float (&b)[2][KS], floatx4 (&acc)[2][2],
+                                                const floatx4 (&prev)[2][2], float* __restrict__ stage, int64_t o0,
+                                                int64_t n_obj, int64_t col_prev, int64_t rows, int lane,
+                                                void* __restrict__ lut)
+{
+    constexpr int S1 = KS / 4, S2 = KS / 2, S3 = (3 * KS) / 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    g2_mma<KS, 0, S1>(a, b, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    g2_stage(prev, stage, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    g2_mma<KS, S1, S2>(a, b, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    float4 v[4];
+    g2_unstage(stage, lane, v);
+    __builtin_amdgcn_sched_barrier(0);
+    g2_mma<KS, S2, S3>(a, b, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    g2_store<F16OUT>(v, o0, n_obj, col_prev, rows, lane, lut);
+    __builtin_amdgcn_sched_barrier(0);
+    g2_mma<KS, S3, KS>(a, b, acc);
+}
+
+// The last tile's epilogue on its own.
+template <bool F16OUT>
+__device__ __forceinline__ void g2_flush(const floatx4 (&acc)[2][2], float* __restrict__ stage, int64_t o0,
+                                         int64_t n_obj, int64_t col0, int64_t rows, int lane, void* __restrict__ lut)
+{
+    g2_stage(acc, stage, lane);
+    float4 v[4];
+    g2_unstage(stage, lane, v);
+    g2_store<F16OUT>(v, o0, n_obj, col0, rows, lane, lut);
 }
 
 // B fragments of column tile t from the fragment-ordered table: ceil(KS/2)
@@ -390,16 +452,35 @@ __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__
                 a[i][s] = __uint_as_float(__float_as_uint(v) & keep);
             }
         }
-        // ping-pong over two B buffers: the next tile loads while this one
-        // computes (past the last tile the last one is loaded again, unused)
+        // tile k (k = 0 .. n-1 from t_begin) uses B buffer k % 2 and
+        // accumulators k % 2; a buffer reloads (two tiles ahead) once its
+        // MFMAs have issued, and tile k's epilogue runs inside tile k+1's
+        // MFMAs (past the last tile the last one is loaded again, unused)
+        const int64_t n = t_end - t_begin;
+        auto tile_at = [&](int64_t k) { return t_begin + (k < n ? k : n - 1); };
         float b0[2][KS], b1[2][KS];
-        g2_load_b<KS>(Bt, t_begin, lane, b0);
-        for (int64_t t = t_begin; t < t_end; t += 2) {
-            g2_load_b<KS>(Bt, (t + 1 < t_end) ? t + 1 : t_end - 1, lane, b1);
-            g2_tile<F16OUT, KS>(a, b0, o0, n_obj, t * 32, rows, lane, stage, lut);
-            if (t + 1 >= t_end) break;
-            g2_load_b<KS>(Bt, (t + 2 < t_end) ? t + 2 : t_end - 1, lane, b0);
-            g2_tile<F16OUT, KS>(a, b1, o0, n_obj, (t + 1) * 32, rows, lane, stage, lut);
+        floatx4 c0[2][2], c1[2][2];
+        g2_load_b<KS>(Bt, tile_at(0), lane, b0);
+        g2_load_b<KS>(Bt, tile_at(1), lane, b1);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) c0[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        g2_mma<KS, 0, KS>(a, b0, c0);
+        g2_load_b<KS>(Bt, tile_at(2), lane, b0);
+        for (int64_t k = 1;; k += 2) {
+            if (k >= n) {
+                g2_flush<F16OUT>(c0, stage, o0, n_obj, tile_at(k - 1) * 32, rows, lane, lut);
+                break;
+            }
+            g2_tile_overlap<F16OUT, KS>(a, b1, c1, c0, stage, o0, n_obj, tile_at(k - 1) * 32, rows, lane, lut);
+            g2_load_b<KS>(Bt, tile_at(k + 2), lane, b1);
+            if (k + 1 >= n) {
+                g2_flush<F16OUT>(c1, stage, o0, n_obj, tile_at(k) * 32, rows, lane, lut);
+                break;
+            }
+            g2_tile_overlap<F16OUT, KS>(a, b0, c0, c1, stage, o0, n_obj, tile_at(k) * 32, rows, lane, lut);
+            g2_load_b<KS>(Bt, tile_at(k + 3), lane, b0);
         }
     }
 }
