@@ -317,6 +317,8 @@ __device__ __forceinline__ void g2_unstage(const float* __restrict__ stage, int 
     for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const float4*>(stage + ((lane >> 3) + 8 * q) * G2_LDS_STRIDE + cg);
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 // ... and part 3: stored as whole 128 B rows; rows is a multiple of 4, so a
 // group of four columns is wholly inside or outside the table
 template <bool F16OUT>
@@ -332,12 +334,17 @@ __device__ __forceinline__ void g2_store(const float4 (&v)[4], int64_t o0, int64
     for (int q = 0; q < 4; ++q) {
         const int64_t o = o0 + (lane >> 3) + 8 * q;
         if (o < n_obj && col < rows) {
+            // non-temporal: the output lines are written once and need not
+            // displace the basis fragments the XCD's waves share in L2
             if constexpr (F16OUT) {
-                __half2* dst = reinterpret_cast<__half2*>(reinterpret_cast<__half*>(lut) + o * rows + col);
-                dst[0] = __floats2half2_rn(v[q].x, v[q].y);
-                dst[1] = __floats2half2_rn(v[q].z, v[q].w);
+                const __half2 h0 = __floats2half2_rn(v[q].x, v[q].y), h1 = __floats2half2_rn(v[q].z, v[q].w);
+                u32x2 w;
+                w.x = *reinterpret_cast<const unsigned int*>(&h0);
+                w.y = *reinterpret_cast<const unsigned int*>(&h1);
+                __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(reinterpret_cast<__half*>(lut) + o * rows + col));
             } else {
-                *reinterpret_cast<float4*>(reinterpret_cast<float*>(lut) + o * rows + col) = v[q];
+                const floatx4 w = {v[q].x, v[q].y, v[q].z, v[q].w};
+                __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(reinterpret_cast<float*>(lut) + o * rows + col));
             }
         }
     }
