@@ -344,6 +344,16 @@ __device__ __noinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int 
                        (dLda * Sa.z + dLdb * Tb.z) * im);
 }
 
+// Workgroup barrier that orders LDS only: the threads of a tile exchange
+// data through LDS alone, so the barrier need not wait for the global loads
+// in flight (the next round's prefetch), as __syncthreads() would.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <bool LUT, bool DIRS>
 __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
                                                            int64_t Q, const float* __restrict__ dirs,
@@ -389,13 +399,13 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         row_start[tid] = a;
         row_len[tid] = e - a;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid <= BC) {  // exclusive prefix: independent reads, no serial chain
         int64_t o = 0;
         for (int k = 0; k < tid; ++k) o += row_len[k];
         row_off[tid] = o;
     }
-    __syncthreads();
+    lds_barrier();
     int64_t seg_lo = 0, seg_hi = 0;
     if (cell_ok) {
         const int64_t rs = row_start[cj], len = row_off[cj + 1] - row_off[cj];
@@ -411,35 +421,37 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     float4 acc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    // the query at list position g and its cell row (Q past the end)
-    // (binary search for the last row starting at or before g: empty rows
-    // share their successor's offset, so it lands on the row holding g)
-    auto query_at = [&](int64_t g, int& r) -> int64_t {
+    // the query at list position g and its cell row (binary search for the
+    // last row starting at or before g: empty rows share their successor's
+    // offset, so it lands on the row holding g).  The permutation is read at
+    // a position clamped into the list and the entry past the end is marked
+    // by the flag alone: no branch, so the loaded index is not waited for
+    // until its first use, a round's weights later.
+    auto query_at = [&](int64_t g, int& r, bool& valid) -> int64_t {
+        valid = g < total;
+        const int64_t gc = valid ? g : total - 1;
         r = 0;
-        if (g >= total) return Q;
 #pragma unroll
         for (int step = BC / 2; step >= 1; step >>= 1)
-            if (row_off[r + step] <= g) r += step;
-        return perm[row_start[r] + (g - row_off[r])];
+            if (row_off[r + step] <= gc) r += step;
+        int64_t pos = row_start[r] + (gc - row_off[r]);
+        pos = pos < 0 ? 0 : (pos >= Q ? Q - 1 : pos);
+        return (int64_t)perm[pos];
     };
     // software pipeline: round k + 1's index, direction and upstream
     // gradient loads are in flight while round k computes and reduces
     int r_cur;
-    int64_t q_cur = query_at(tid, r_cur);
-    float x = 0.f, y = 0.f, z = 0.f;
-    float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (q_cur < Q) {
-        x = dirs[3 * q_cur];
-        y = dirs[3 * q_cur + 1];
-        z = dirs[3 * q_cur + 2];
-        gq = reinterpret_cast<const float4*>(gout)[q_cur];
-    }
+    bool v_cur;
+    int64_t q_cur = query_at(tid, r_cur, v_cur);
+    float x = dirs[3 * q_cur], y = dirs[3 * q_cur + 1], z = dirs[3 * q_cur + 2];
+    float4 gq = reinterpret_cast<const float4*>(gout)[q_cur];
     for (int64_t base = 0; base < total; base += BWD_THREADS) {
         int r_next;
-        const int64_t q_next = query_at(base + BWD_THREADS + tid, r_next);
-        // list positions base + tid < total hold a query (q_cur < Q) and
-        // fill their slot; the reduction below reads no other slot
-        if (q_cur < Q) {
+        bool v_next;
+        const int64_t q_next = query_at(base + BWD_THREADS + tid, r_next, v_next);
+        // list positions base + tid < total hold a query and fill their
+        // slot; the reduction below reads no other slot
+        if (v_cur) {
             const Loc L = locate(x, y, z, N);  // the cell of row r_cur (keys come from the same decision)
             if constexpr (LUT) {
                 const float A = L.a, B = L.b;
@@ -458,16 +470,16 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
                 grad_dirs[3 * q_cur + 2] = gd.z;
             }
         }
-        if (q_next < Q) {
-            x = dirs[3 * q_next];
-            y = dirs[3 * q_next + 1];
-            z = dirs[3 * q_next + 2];
-            gq = reinterpret_cast<const float4*>(gout)[q_next];
-        }
+        // unconditional: q_next is a valid index even past the list's end
+        x = dirs[3 * q_next];
+        y = dirs[3 * q_next + 1];
+        z = dirs[3 * q_next + 2];
+        gq = reinterpret_cast<const float4*>(gout)[q_next];
         q_cur = q_next;
         r_cur = r_next;
+        v_cur = v_next;
         if constexpr (LUT) {
-            __syncthreads();
+            lds_barrier();
             const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
             for (int k2 = lo; k2 < hi; ++k2) {
 #pragma unroll
@@ -479,13 +491,13 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
                     acc[k].w += v.w;
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
     if constexpr (!LUT) return;
 #pragma unroll
     for (int k = 0; k < 4; ++k) slot[tid][k] = acc[k];
-    __syncthreads();
+    lds_barrier();
     // texel (p0 + tx, q0 + ty) is corner (1,1) of cell (tx, ty), (0,1) of
     // (tx+1, ty), (1,0) of (tx, ty+1) and (0,0) of (tx+1, ty+1) in tile cells
     for (int t = tid; t < BT * BT; t += BWD_THREADS) {
