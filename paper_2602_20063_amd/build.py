@@ -22,7 +22,6 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-result",
-    "-Wno-unused-value",  # best-effort HIP cleanup calls in destroy paths
 ]
 
 

@@ -242,11 +242,13 @@ int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, i
                         (long long)o, (long long)b.lut_offset, (long long)align_elems);
         if (b.q_begin < 0 || b.q_count < 0) return fail(SHM_ERR_INVALID_ARG, "plan_create: object %lld bad query range", (long long)o);
     }
+    int device = 0;
+    SHM_HIP_CHECK(hipGetDevice(&device));
     shm_plan* P = new shm_plan();
+    P->device = device;
     P->dtype = dtype;
     P->layout = layout;
     P->objs.assign(objs_host, objs_host + n_obj);
-    hipGetDevice(&P->device);
     P->n_cu = device_cu_count();
     uint64_t h = 1469598103934665603ull;
     h = fnv1a(h, &dtype, sizeof dtype);
@@ -280,6 +282,14 @@ int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, i
     return SHM_OK;
 }
 
+// Release a plan's captured graph (best effort: the handles are dropped
+// whatever the runtime answers).
+static void drop_graph(shm_plan* plan)
+{
+    if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+}
+
 int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape)
 {
     clear_error();
@@ -288,8 +298,7 @@ int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape)
     if (rc) return rc;
     const bool retile = shape->tile != plan->shape.tile;
     plan->shape = *shape;
-    if (plan->exec) { hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
-    if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    drop_graph(plan);  // captured with the previous shape
     return retile ? plan_build_items(plan, plan->cap_stream) : SHM_OK;
 }
 
@@ -346,7 +355,7 @@ int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float*
     char key[96];
     {
         hipDeviceProp_t prop;
-        hipGetDeviceProperties(&prop, plan->device);
+        SHM_HIP_CHECK(hipGetDeviceProperties(&prop, plan->device));
         snprintf(key, sizeof key, "%s/%d/%016llx", prop.gcnArchName, plan->n_cu, (unsigned long long)plan->signature);
         for (char* c = key; *c; ++c)
             if (*c == '"' || *c == '\\') *c = '_';
@@ -376,19 +385,19 @@ int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float*
     for (const auto& s : cands) {
         if ((rc = shm_plan_set_shape(plan, &s)) != SHM_OK) break;
         if ((rc = shm_plan_launch(plan, lut, dirs, out, nullptr, stream)) != SHM_OK) break;  // warm-up
-        hipEventRecord(e0, stream);
+        if (hipEventRecord(e0, stream) != hipSuccess) { rc = fail(SHM_ERR_HIP, "plan_autotune: event record failed"); break; }
         const int reps = 3;
         for (int r = 0; r < reps && rc == SHM_OK; ++r) rc = shm_plan_launch(plan, lut, dirs, out, nullptr, stream);
-        hipEventRecord(e1, stream);
         if (rc) break;
+        if (hipEventRecord(e1, stream) != hipSuccess) { rc = fail(SHM_ERR_HIP, "plan_autotune: event record failed"); break; }
         if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SHM_ERR_HIP, "plan_autotune: event sync failed"); break; }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(SHM_ERR_HIP, "plan_autotune: elapsed time failed"); break; }
         ms /= reps;
         if (ms < best_ms) { best_ms = ms; best = s; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);  // best-effort cleanup
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     if ((rc = shm_plan_set_shape(plan, &best)) != SHM_OK) return rc;
     if (chosen) *chosen = best;
@@ -404,19 +413,18 @@ int shm_plan_capture_graph(shm_plan* plan, const void* lut, const float* dirs, f
     clear_error();
     if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_capture_graph: null plan");
     (void)stream;
-    if (plan->exec) { hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
-    if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    drop_graph(plan);
     SHM_HIP_CHECK(hipStreamSynchronize(plan->cap_stream));
     SHM_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = shm_plan_launch(plan, lut, dirs, out, normal, plan->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
-    if (rc) { if (g) hipGraphDestroy(g); return rc; }
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return fail(SHM_ERR_HIP, "plan_capture_graph: end capture: %s", hipGetErrorString(e));
     plan->graph = g;
     e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         plan->graph = nullptr;
         plan->exec = nullptr;
         return fail(SHM_ERR_HIP, "plan_capture_graph: instantiate: %s", hipGetErrorString(e));
@@ -437,14 +445,14 @@ int64_t shm_plan_work_items(const shm_plan* plan) { return plan ? plan->n_items 
 int shm_plan_destroy(shm_plan* plan)
 {
     if (!plan) return SHM_OK;
-    if (plan->exec) hipGraphExecDestroy(plan->exec);
-    if (plan->graph) hipGraphDestroy(plan->graph);
+    // best-effort cleanup: every resource is released even if one call fails
+    drop_graph(plan);
     if (plan->cap_stream) {
-        hipStreamSynchronize(plan->cap_stream);
-        hipStreamDestroy(plan->cap_stream);
+        (void)hipStreamSynchronize(plan->cap_stream);
+        (void)hipStreamDestroy(plan->cap_stream);
     }
-    if (plan->d_items) hipFree(plan->d_items);
-    if (plan->d_objs) hipFree(plan->d_objs);
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_objs) (void)hipFree(plan->d_objs);
     delete plan;
     return SHM_OK;
 }
