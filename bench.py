@@ -414,36 +414,52 @@ def run_backward_fit():
     # fit: Adam with one learning rate for the value channel and one for the
     # scaled derivative channels; the value term is weighted by 1/ell^2 with
     # ell = 1/sqrt(1000) (about ten cells at N=512), so that value and normal
-    # errors enter on a comparable footing
-    val = lut[..., :1].clone().requires_grad_(True)
-    der = lut[..., 1:].clone().requires_grad_(True)
-    opt = torch.optim.Adam([{"params": [val], "lr": 1e-3}, {"params": [der], "lr": 3e-4}], betas=(0.9, 0.999), eps=1e-8)
-    w_val = 1000.0
+    # errors enter on a comparable footing.  Native: every step (forward,
+    # loss gradient, backward, Adam) in the library's kernels; then the same
+    # fit driven by PyTorch autograd and torch.optim.Adam around the library's
+    # forward and backward, for comparison.
+    w_val, lr_v, lr_d, steps = 1000.0, 1e-3, 3e-4, 200
+    lut0 = lut.clone()
+    warm = shm.LutFit(lut0.clone(), dirs, tv, tn, w_value=w_val, lr_value=lr_v, lr_deriv=lr_d)
+    warm.step()
+    fit = shm.LutFit(lut0.clone(), dirs, tv, tn, w_value=w_val, lr_value=lr_v, lr_deriv=lr_d)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(steps):
+        fit.step()
+    torch.cuda.synchronize()
+    fit_s = time.time() - t0
+    val = lut0[..., :1].clone().requires_grad_(True)
+    der = lut0[..., 1:].clone().requires_grad_(True)
+    opt = torch.optim.Adam([{"params": [val], "lr": lr_v}, {"params": [der], "lr": lr_d}], betas=(0.9, 0.999), eps=1e-8)
 
-    def loss_fn():
-        o = shm.HermiteQuery.apply(torch.cat([val, der], dim=-1).contiguous(), dirs, bctx)
+    def loss_of(o):
         R, gr = o[:, 0], o[:, 1:]
         n = R[:, None] * w - gr
         n = n / n.norm(dim=1, keepdim=True)
-        return w_val * ((R - tv) ** 2).mean() + ((n - tn) ** 2).sum(dim=1).mean(), o
+        return w_val * ((R - tv) ** 2).mean() + ((n - tn) ** 2).sum(dim=1).mean(), n
 
     torch.cuda.synchronize()
     t0 = time.time()
-    for _ in range(200):
+    for _ in range(steps):
         opt.zero_grad(set_to_none=True)
-        loss, _ = loss_fn()
+        loss, _ = loss_of(shm.HermiteQuery.apply(torch.cat([val, der], dim=-1).contiguous(), dirs, bctx))
         loss.backward()
         opt.step()
     torch.cuda.synchronize()
-    fit_s = time.time() - t0
+    fit_torch_s = time.time() - t0
     with torch.no_grad():
-        loss, o = loss_fn()
-        R, gr = o[:, 0], o[:, 1:]
-        n = R[:, None] * w - gr
-        n = n / n.norm(dim=1, keepdim=True)
+        o = torch.empty((Q, 4), device=DEV)
+        shm.shm_query_value_grad(fit.lut, shm.SHM_F32, 0, N, 1, dirs, Q, o)
+        loss, n = loss_of(o)
+        R = o[:, 0]
         ang = torch.rad2deg(torch.acos(torch.clamp((n * tn).sum(dim=1), -1, 1)))
         ang0 = torch.rad2deg(torch.acos(torch.clamp((w * tn).sum(dim=1), -1, 1)))
-        res.update({"fit_steps": 200, "fit_s": fit_s, "final_loss": loss.item(),
+        ref = torch.cat([val.detach(), der.detach()], dim=-1)
+        res.update({"fit_steps": steps, "fit_s": fit_s, "fit_ms_per_step": fit_s / steps * 1e3,
+                    "fit_torch_adam_s": fit_torch_s,
+                    "fit_native_vs_torch_max_abs": (fit.lut - ref).abs().max().item(),
+                    "final_loss": loss.item(),
                     "initial_normal_mean_deg": ang0.mean().item(),
                     "value_rmse": ((R - tv) ** 2).mean().sqrt().item(), "normal_mean_deg": ang.mean().item(),
                     "initial_value_rmse": ((1.0 - tv) ** 2).mean().sqrt().item()})

@@ -356,6 +356,35 @@ SHM_API int shm_query_baseline(const float* vlut, int32_t N, int64_t n_obj, cons
 SHM_API int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs, int64_t q_per_obj,
                         float* out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Fitting a LUT to a target (the differentiation form): the two steps of
+ * the optimisation loop around shm_query_value_grad (TEXEL, FP32) and
+ * shm_query_backward, so that a whole step runs in this library's kernels
+ * (no allocation, no host synchronisation: a fixed sequence of steps can be
+ * captured in a graph; the step number t is a launch argument).
+ *
+ * shm_fit_loss_grad writes dL/d(R, gx, gy, gz) for the objective
+ *   L = w_value mean_q (R_q - target_r[q])^2 + mean_q |n_q - target_n[q]|^2
+ * with n = (R w - grad R) / |R w - grad R| (Eq. 10), w = d/|d|:
+ *   out      [Q][4] the query's output (R, grad R), 16-byte aligned
+ *   dirs     [Q][3] the query directions
+ *   target_r [Q], target_n [Q][3] (unit normals)
+ *   grad     [Q][4] written (16-byte aligned); 0 for queries whose output
+ *            is not finite (zero or non-finite directions) or whose
+ *            R w - grad R vanishes
+ * shm_adam_step applies one Adam update in place to a FP32 TEXEL LUT
+ * param [n4][4] (n4 texels; channel 0 = r uses lr_value, channels 1..3 =
+ * the scaled derivatives use lr_deriv), with gradient grad and moment
+ * buffers m, v of the same shape (zero before step 1), step t >= 1:
+ *   m <- m + (1 - beta1)(g - m),  v <- beta2 v + (1 - beta2) g^2,
+ *   p <- p - lr / (1 - beta1^t) * m / (sqrt(v) / sqrt(1 - beta2^t) + eps).
+ * All four arrays 16-byte aligned; 0 <= beta1, beta2 < 1, eps > 0.
+ * ---------------------------------------------------------------------- */
+SHM_API int shm_fit_loss_grad(const float* out, const float* dirs, const float* target_r, const float* target_n,
+                              int64_t Q, float w_value, float* grad, hipStream_t stream);
+SHM_API int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n4, int64_t step,
+                          float lr_value, float lr_deriv, float beta1, float beta2, float eps, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,10 @@ int launch_mesh_depth(const float* verts, int64_t V, const int32_t* tris, int64_
                       const float* dirs, int64_t P, float* depth, hipStream_t stream);
 size_t mip_workspace_bytes(int N);
 int launch_mip_level(const float* lut, int N, int mode, float* ws, float* out, hipStream_t stream);
+int launch_fit_loss_grad(const float* out, const float* dirs, const float* tr, const float* tn, int64_t Q,
+                         float w_value, float* grad, hipStream_t stream);
+int launch_adam(float* p, const float* g, float* m, float* v, int64_t n4, int64_t step, float lr_value,
+                float lr_deriv, float b1, float b2, float eps, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 static bool valid_N(int N) { return N >= 1 && N <= SHM_MAX_N; }
@@ -605,6 +609,35 @@ int shm_mesh_radial_depth(const float* verts, int64_t n_verts, const int32_t* tr
     if (!aligned(depth, 4) || !aligned(dirs, 4) || (tris && !aligned(tris, 4)) || (verts && !aligned(verts, 4)))
         return fail(SHM_ERR_INVALID_ARG, "mesh_depth: misaligned buffer");
     return launch_mesh_depth(verts, n_verts, tris, n_tris, center, dirs, P, depth, stream);
+}
+
+// ---------------------------------------------------------------------------
+int shm_fit_loss_grad(const float* out, const float* dirs, const float* target_r, const float* target_n, int64_t Q,
+                      float w_value, float* grad, hipStream_t stream)
+{
+    clear_error();
+    if (Q < 0) return fail(SHM_ERR_INVALID_ARG, "fit_loss_grad: negative query count");
+    if (!std::isfinite(w_value) || w_value < 0.0f) return fail(SHM_ERR_INVALID_ARG, "fit_loss_grad: w_value must be finite and >= 0");
+    if (Q == 0) return SHM_OK;
+    if (!out || !dirs || !target_r || !target_n || !grad) return fail(SHM_ERR_INVALID_ARG, "fit_loss_grad: null pointer");
+    if (!aligned(out, 16) || !aligned(grad, 16) || !aligned(dirs, 4) || !aligned(target_r, 4) || !aligned(target_n, 4))
+        return fail(SHM_ERR_INVALID_ARG, "fit_loss_grad: misaligned buffer (out and grad need 16 bytes)");
+    return launch_fit_loss_grad(out, dirs, target_r, target_n, Q, w_value, grad, stream);
+}
+
+int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n4, int64_t step, float lr_value,
+                  float lr_deriv, float beta1, float beta2, float eps, hipStream_t stream)
+{
+    clear_error();
+    if (n4 < 0 || step < 1) return fail(SHM_ERR_INVALID_ARG, "adam: need n4 >= 0 and step >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) || !std::isfinite(eps) ||
+        !std::isfinite(lr_value) || !std::isfinite(lr_deriv))
+        return fail(SHM_ERR_INVALID_ARG, "adam: need 0 <= beta < 1, finite eps > 0 and finite learning rates");
+    if (n4 == 0) return SHM_OK;
+    if (!param || !grad || !m || !v) return fail(SHM_ERR_INVALID_ARG, "adam: null pointer");
+    if (!aligned(param, 16) || !aligned(grad, 16) || !aligned(m, 16) || !aligned(v, 16))
+        return fail(SHM_ERR_INVALID_ARG, "adam: buffers must be 16-byte aligned");
+    return launch_adam(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1, beta2, eps, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -155,3 +155,28 @@ def test_mesh_depth_validation():
     assert f(p, 8, p, 12, c, None, 10, p, None) == shm.SHM_ERR_INVALID_ARG
     assert f(p, 1 << 32, p, 12, c, p, 10, p, None) == shm.SHM_ERR_UNSUPPORTED
     assert f(p, 8, p, 12, c, p, 10, ctypes.c_void_p(258), None) == shm.SHM_ERR_INVALID_ARG
+
+
+def test_fit_validation():
+    """Loss gradient and Adam update: sizes, pointers, alignment and
+    hyper-parameters are checked on the host before anything is enqueued."""
+    p = ctypes.c_void_p(256)
+    mis = ctypes.c_void_p(260)
+    lg = lambda *a: call("shm_fit_loss_grad", *a)
+    assert lg(p, p, p, p, 0, 1.0, p, None) == shm.SHM_OK
+    assert lg(p, p, p, p, -1, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert lg(p, p, p, p, 10, float("nan"), p, None) == shm.SHM_ERR_INVALID_ARG
+    assert lg(p, p, p, p, 10, -1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert lg(None, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert lg(p, p, p, p, 10, 1.0, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert lg(mis, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    ad = lambda *a: call("shm_adam_step", *a)
+    ok = (0.9, 0.999, 1e-8)
+    assert ad(p, p, p, p, 0, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_OK
+    assert ad(p, p, p, p, 10, 0, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG       # step >= 1
+    assert ad(p, p, p, p, -1, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
+    for b1, b2, eps in ((1.0, 0.999, 1e-8), (0.9, -0.1, 1e-8), (0.9, 0.999, 0.0), (0.9, 0.999, float("inf"))):
+        assert ad(p, p, p, p, 10, 1, 1e-3, 1e-3, b1, b2, eps, None) == shm.SHM_ERR_INVALID_ARG
+    assert ad(p, p, p, p, 10, 1, float("nan"), 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
+    assert ad(p, None, p, p, 10, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
+    assert ad(p, p, mis, p, 10, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG

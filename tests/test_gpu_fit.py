@@ -1,0 +1,113 @@
+"""The fitting loop's own kernels (loss gradient, Adam update) against
+PyTorch references computed on the CPU, and a short native fit against the
+same fit driven by PyTorch autograd and torch.optim.Adam around the library's
+forward and backward."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2602_20063_amd as shm
+import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def ref_loss(out, dirs, tr, tn, w_value):
+    """The value + normal objective in FP64 on the CPU; rows whose output is
+    not finite contribute nothing but count in the means."""
+    Q = out.shape[0]
+    ok = torch.isfinite(out).all(dim=1)
+    o = out[ok]
+    w = dirs[ok] / dirs[ok].norm(dim=1, keepdim=True)
+    m = o[:, :1] * w - o[:, 1:]
+    n = m / m.norm(dim=1, keepdim=True)
+    return (w_value * ((o[:, 0] - tr[ok]) ** 2).sum() + ((n - tn[ok]) ** 2).sum()) / Q
+
+
+def test_loss_grad_matches_autograd():
+    rng = np.random.default_rng(7)
+    Q = 5003
+    dirs = workloads.uniform_dirs(Q, rng) * rng.uniform(0.5, 2.0, (Q, 1)).astype(np.float32)
+    dirs[17] = 0.0
+    out = np.concatenate([1.0 + 0.2 * rng.standard_normal((Q, 1)), 0.1 * rng.standard_normal((Q, 3))], axis=1)
+    out = out.astype(np.float32)
+    out[17] = np.nan  # the query of a zero direction
+    tr = (1.0 + 0.2 * rng.standard_normal(Q)).astype(np.float32)
+    tn = rng.standard_normal((Q, 3))
+    tn = (tn / np.linalg.norm(tn, axis=1, keepdims=True)).astype(np.float32)
+    w_value = 37.0
+    g = torch.empty((Q, 4), device=DEV)
+    shm.shm_fit_loss_grad(torch.as_tensor(out).to(DEV), torch.as_tensor(dirs).to(DEV), torch.as_tensor(tr).to(DEV),
+                          torch.as_tensor(tn).to(DEV), Q, w_value, g)
+    got = g.cpu().numpy()
+    o64 = torch.as_tensor(out, dtype=torch.float64).requires_grad_(True)
+    ref_loss(o64, torch.as_tensor(dirs, dtype=torch.float64), torch.as_tensor(tr, dtype=torch.float64),
+             torch.as_tensor(tn, dtype=torch.float64), w_value).backward()
+    ref = np.nan_to_num(o64.grad.numpy())
+    assert (got[17] == 0).all()
+    scale = np.abs(ref).max(axis=0)
+    assert (np.abs(got - ref).max(axis=0) <= 2e-5 * scale).all(), (np.abs(got - ref).max(axis=0), scale)
+
+
+def test_adam_matches_torch_adam():
+    rng = np.random.default_rng(8)
+    N = 6
+    p0 = rng.standard_normal((1, 6, N + 2, N + 2, 4)).astype(np.float32)
+    grads = [rng.standard_normal(p0.shape).astype(np.float32) * s for s in (1.0, 0.01, 3.0, 1e-4)]
+    lr_v, lr_d = 1e-2, 3e-3
+    p = torch.as_tensor(p0).to(DEV)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    val = torch.tensor(p0[..., :1], requires_grad=True)
+    der = torch.tensor(p0[..., 1:], requires_grad=True)
+    opt = torch.optim.Adam([{"params": [val], "lr": lr_v}, {"params": [der], "lr": lr_d}], betas=(0.9, 0.999),
+                           eps=1e-8, foreach=False)
+    for t, gr in enumerate(grads, start=1):
+        shm.shm_adam_step(p, torch.as_tensor(gr).to(DEV), m, v, p.numel() // 4, t, lr_v, lr_d)
+        val.grad = torch.as_tensor(gr[..., :1]).clone()
+        der.grad = torch.as_tensor(gr[..., 1:]).clone()
+        opt.step()
+        ref = torch.cat([val.detach(), der.detach()], dim=-1).numpy()
+        got = p.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-6 * (1.0 + np.abs(ref).max()), (t, np.abs(got - ref).max())
+
+
+def test_native_fit_matches_torch_loop():
+    """20 steps at N = 16 on 30,000 directions sorted by cell: the native
+    loop and the autograd + torch.optim.Adam loop end at the same LUT."""
+    N, Q = 16, 30000
+    r = workloads.rng_for(4)
+    dirs = torch.as_tensor(workloads.uniform_dirs(Q, r)).to(DEV)
+    keys = shm.cell_keys(N, dirs)
+    dirs = dirs[torch.argsort(keys.to(torch.int64) & 0xFFFFFFFF, stable=True)].contiguous()
+    tv, tg = workloads.fbm_target_torch(dirs, seed=5)
+    tv, tg = tv.float(), tg.float()
+    w = dirs / dirs.norm(dim=1, keepdim=True)
+    tn = tv[:, None] * w - tg
+    tn = (tn / tn.norm(dim=1, keepdim=True)).contiguous()
+    lut0 = torch.zeros((1, 6, N + 2, N + 2, 4), device=DEV)
+    lut0[..., 0] = 1.0
+    w_value, lr_v, lr_d, steps = 1000.0, 1e-3, 3e-4, 20
+    fit = shm.LutFit(lut0.clone(), dirs, tv, tn, w_value=w_value, lr_value=lr_v, lr_deriv=lr_d)
+    for _ in range(steps):
+        fit.step()
+    val = lut0[..., :1].clone().requires_grad_(True)
+    der = lut0[..., 1:].clone().requires_grad_(True)
+    opt = torch.optim.Adam([{"params": [val], "lr": lr_v}, {"params": [der], "lr": lr_d}], betas=(0.9, 0.999),
+                           eps=1e-8)
+    bctx = shm.BackwardContext(N, 1, dirs, Q)
+    losses = []
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        o = shm.HermiteQuery.apply(torch.cat([val, der], dim=-1).contiguous(), dirs, bctx)
+        n = o[:, :1] * w - o[:, 1:]
+        n = n / n.norm(dim=1, keepdim=True)
+        loss = w_value * ((o[:, 0] - tv) ** 2).mean() + ((n - tn) ** 2).sum(dim=1).mean()
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    torch.cuda.synchronize()
+    ref = torch.cat([val.detach(), der.detach()], dim=-1)
+    d = (fit.lut - ref).abs().max().item()
+    assert d <= 1e-4 * ref.abs().max().item(), d
+    assert losses[-1] < 0.7 * losses[0]  # and the fit makes progress
