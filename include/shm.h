@@ -382,6 +382,12 @@ SHM_API int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const flo
  * ---------------------------------------------------------------------- */
 SHM_API int shm_fit_loss_grad(const float* out, const float* dirs, const float* target_r, const float* target_n,
                               int64_t Q, float w_value, float* grad, hipStream_t stream);
+/* The forward query of one FP32 TEXEL LUT (face size N) fused with
+ * shm_fit_loss_grad: grad as above for out = the query of lut at dirs,
+ * without writing out (lut 16-byte aligned). */
+SHM_API int shm_fit_forward_loss_grad(const float* lut, int32_t N, const float* dirs, const float* target_r,
+                                      const float* target_n, int64_t Q, float w_value, float* grad,
+                                      hipStream_t stream);
 SHM_API int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n4, int64_t step,
                           float lr_value, float lr_deriv, float beta1, float beta2, float eps, hipStream_t stream);
 

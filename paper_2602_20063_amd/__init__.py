@@ -93,6 +93,7 @@ SIGNATURES = {
     "shm_query_baseline": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _I32, _VP, _VP]),
     "shm_sh_eval": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP]),
     "shm_fit_loss_grad": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, ctypes.c_float, _VP, _VP]),
+    "shm_fit_forward_loss_grad": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _VP, _VP]),
     "shm_adam_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, _VP]),
 }
@@ -252,6 +253,11 @@ def shm_fit_loss_grad(out, dirs, target_r, target_n, Q, w_value, grad, stream=No
                                           _ptr(grad), _stream(stream)))
 
 
+def shm_fit_forward_loss_grad(lut, N, dirs, target_r, target_n, Q, w_value, grad, stream=None):
+    return _check(lib().shm_fit_forward_loss_grad(_ptr(lut), N, _ptr(dirs), _ptr(target_r), _ptr(target_n), Q,
+                                                  float(w_value), _ptr(grad), _stream(stream)))
+
+
 def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     return _check(lib().shm_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), n4, step, float(lr_value),
                                       float(lr_deriv), float(beta1), float(beta2), float(eps), _stream(stream)))
@@ -260,9 +266,9 @@ def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, be
 class LutFit:
     """Fits one FP32 TEXEL LUT (face size N) to target radii and normals at
     fixed directions with Adam, every step in this library's kernels:
-    forward query, loss gradient (value + normal objective, value term
-    weighted by w_value), LUT-only backward (directions sorted once), Adam
-    update.  lut [1, 6, N+2, N+2, 4] is updated in place."""
+    forward query fused with the loss gradient (value + normal objective,
+    value term weighted by w_value), LUT-only backward (directions sorted
+    once), Adam update.  lut [1, 6, N+2, N+2, 4] is updated in place."""
 
     def __init__(self, lut, dirs, target_r, target_n, w_value=1.0, lr_value=1e-3, lr_deriv=1e-3, betas=(0.9, 0.999),
                  eps=1e-8, stream=None):
@@ -274,7 +280,6 @@ class LutFit:
         self.betas, self.eps = betas, eps
         self.bctx = BackwardContext(self.N, 1, dirs, self.Q, stream)
         dev = lut.device
-        self.out = torch.empty((self.Q, 4), device=dev)
         self.g = torch.empty((self.Q, 4), device=dev)
         self.grad = torch.empty_like(lut)
         self.m = torch.zeros_like(lut)
@@ -284,8 +289,7 @@ class LutFit:
     def step(self, stream=None):
         self.t += 1
         N, Q = self.N, self.Q
-        shm_query_value_grad(self.lut, SHM_F32, SHM_LAYOUT_TEXEL, N, 1, self.dirs, Q, self.out, stream=stream)
-        shm_fit_loss_grad(self.out, self.dirs, self.tr, self.tn, Q, self.w_value, self.g, stream)
+        shm_fit_forward_loss_grad(self.lut, N, self.dirs, self.tr, self.tn, Q, self.w_value, self.g, stream)
         shm_query_backward(self.lut, N, 1, self.dirs, Q, self.g, self.grad, None, self.bctx.ws, True, stream)
         shm_adam_step(self.lut, self.grad, self.m, self.v, self.lut.numel() // 4, self.t, self.lr_value,
                       self.lr_deriv, self.betas[0], self.betas[1], self.eps, stream)

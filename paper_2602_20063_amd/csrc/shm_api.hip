@@ -71,6 +71,8 @@ int launch_fit_loss_grad(const float* out, const float* dirs, const float* tr, c
                          float w_value, float* grad, hipStream_t stream);
 int launch_adam(float* p, const float* g, float* m, float* v, int64_t n4, int64_t step, float lr_value,
                 float lr_deriv, float b1, float b2, float eps, hipStream_t stream);
+int launch_fit_forward_loss_grad(const float* lut, int N, const float* dirs, const float* tr, const float* tn,
+                                 int64_t Q, float w_value, float* grad, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 static bool valid_N(int N) { return N >= 1 && N <= SHM_MAX_N; }
@@ -623,6 +625,21 @@ int shm_fit_loss_grad(const float* out, const float* dirs, const float* target_r
     if (!aligned(out, 16) || !aligned(grad, 16) || !aligned(dirs, 4) || !aligned(target_r, 4) || !aligned(target_n, 4))
         return fail(SHM_ERR_INVALID_ARG, "fit_loss_grad: misaligned buffer (out and grad need 16 bytes)");
     return launch_fit_loss_grad(out, dirs, target_r, target_n, Q, w_value, grad, stream);
+}
+
+int shm_fit_forward_loss_grad(const float* lut, int32_t N, const float* dirs, const float* target_r,
+                              const float* target_n, int64_t Q, float w_value, float* grad, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "fit_forward_loss_grad: bad N");
+    if (Q < 0) return fail(SHM_ERR_INVALID_ARG, "fit_forward_loss_grad: negative query count");
+    if (!std::isfinite(w_value) || w_value < 0.0f)
+        return fail(SHM_ERR_INVALID_ARG, "fit_forward_loss_grad: w_value must be finite and >= 0");
+    if (Q == 0) return SHM_OK;
+    if (!lut || !dirs || !target_r || !target_n || !grad) return fail(SHM_ERR_INVALID_ARG, "fit_forward_loss_grad: null pointer");
+    if (!aligned(lut, 16) || !aligned(grad, 16) || !aligned(dirs, 4) || !aligned(target_r, 4) || !aligned(target_n, 4))
+        return fail(SHM_ERR_INVALID_ARG, "fit_forward_loss_grad: misaligned buffer (lut and grad need 16 bytes)");
+    return launch_fit_forward_loss_grad(lut, N, dirs, target_r, target_n, Q, w_value, grad, stream);
 }
 
 int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n4, int64_t step, float lr_value,

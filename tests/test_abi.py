@@ -170,6 +170,13 @@ def test_fit_validation():
     assert lg(None, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
     assert lg(p, p, p, p, 10, 1.0, None, None) == shm.SHM_ERR_INVALID_ARG
     assert lg(mis, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    fl = lambda *a: call("shm_fit_forward_loss_grad", *a)
+    assert fl(p, 8, p, p, p, 0, 1.0, p, None) == shm.SHM_OK
+    assert fl(p, 0, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert fl(p, 8, p, p, p, -1, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert fl(None, 8, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert fl(mis, 8, p, p, p, 10, 1.0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert fl(p, 8, p, p, p, 10, float("inf"), p, None) == shm.SHM_ERR_INVALID_ARG
     ad = lambda *a: call("shm_adam_step", *a)
     ok = (0.9, 0.999, 1e-8)
     assert ad(p, p, p, p, 0, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_OK

@@ -50,6 +50,30 @@ def test_loss_grad_matches_autograd():
     assert (np.abs(got - ref).max(axis=0) <= 2e-5 * scale).all(), (np.abs(got - ref).max(axis=0), scale)
 
 
+def test_fused_forward_loss_grad_matches_two_steps():
+    """The fused kernel equals the forward query followed by the loss
+    gradient, on a random LUT with a ragged query count and a zero
+    direction."""
+    rng = np.random.default_rng(9)
+    N, Q = 24, 7777
+    lut = torch.as_tensor(workloads.random_lut(N, rng)).to(DEV)[None].contiguous()
+    dirs = workloads.uniform_dirs(Q, rng)
+    dirs[5] = 0.0
+    d = torch.as_tensor(dirs).to(DEV)
+    tr = torch.as_tensor((1.0 + 0.1 * rng.standard_normal(Q)).astype(np.float32)).to(DEV)
+    tn = rng.standard_normal((Q, 3))
+    tn = torch.as_tensor((tn / np.linalg.norm(tn, axis=1, keepdims=True)).astype(np.float32)).to(DEV)
+    out = torch.empty((Q, 4), device=DEV)
+    shm.shm_query_value_grad(lut, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, N, 1, d, Q, out)
+    g2 = torch.empty((Q, 4), device=DEV)
+    shm.shm_fit_loss_grad(out, d, tr, tn, Q, 5.0, g2)
+    g1 = torch.full((Q, 4), float("nan"), device=DEV)
+    shm.shm_fit_forward_loss_grad(lut, N, d, tr, tn, Q, 5.0, g1)
+    a, b = g1.cpu().numpy(), g2.cpu().numpy()
+    assert (a[5] == 0).all() and np.isfinite(a).all()
+    assert (np.abs(a - b).max(axis=0) <= 1e-6 * np.abs(b).max(axis=0)).all()
+
+
 def test_adam_matches_torch_adam():
     rng = np.random.default_rng(8)
     N = 6
