@@ -119,8 +119,8 @@ def main():
     ap.add_argument("--counters", action="store_true", help="short run for counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the hot path has no cross-GPU step; "
-                                   "run with --gpus 1 (multi-GPU sharding is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: the hot path has no cross-GPU step "
+                                   "(objects and queries shard across GPUs without communication); run with --gpus 1"}))
         sys.exit(2)
     torch.cuda.set_device(0)
     shm.lib()
