@@ -75,6 +75,12 @@ int launch_fit_forward_loss_grad(const float* lut, int N, const float* dirs, con
                                  int64_t Q, float w_value, float* grad, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+// n_obj * q_per_obj (both >= 0) exceeds limit, checked without overflow
+static bool product_exceeds(int64_t n_obj, int64_t q_per_obj, int64_t limit)
+{
+    return q_per_obj > 0 && n_obj > limit / q_per_obj;
+}
 static bool valid_N(int N) { return N >= 1 && N <= SHM_MAX_N; }
 static bool valid_dtype(int d) { return d == SHM_F32 || d == SHM_F16; }
 static bool valid_layout(int l) { return l == SHM_LAYOUT_TEXEL || l == SHM_LAYOUT_CELL; }
@@ -221,6 +227,8 @@ int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t
     if (!valid_layout(layout)) return fail(SHM_ERR_INVALID_ARG, "query: bad layout %d", layout);
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "query: N must be 1..%d (got %d)", SHM_MAX_N, N);
     if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query: negative size");
+    if (product_exceeds(n_obj, q_per_obj, INT64_MAX / 16))
+        return fail(SHM_ERR_UNSUPPORTED, "query: %lld x %lld queries", (long long)n_obj, (long long)q_per_obj);
     if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
     if (!lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "query: null pointer");
     const size_t al = (dtype == SHM_F16 && layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
@@ -466,7 +474,8 @@ int shm_plan_destroy(shm_plan* plan)
 // ---------------------------------------------------------------------------
 size_t shm_backward_workspace(int32_t N, int64_t n_obj, int64_t q_per_obj)
 {
-    if (!valid_N(N) || n_obj < 0 || q_per_obj < 0) return 0;
+    if (!valid_N(N) || n_obj < 0 || q_per_obj < 0 || n_obj > 0xffffffffll || product_exceeds(n_obj, q_per_obj, 0xfffffffell))
+        return 0;
     return backward_workspace_bytes(N, n_obj, q_per_obj);
 }
 
@@ -474,7 +483,9 @@ static int check_bwd(int32_t N, int64_t n_obj, int64_t q_per_obj, const void* ws
 {
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "backward: N must be 1..%d", SHM_MAX_N);
     if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "backward: negative size");
-    const int64_t Q = n_obj * q_per_obj;
+    if (n_obj > 0xffffffffll || product_exceeds(n_obj, q_per_obj, 0xfffffffell))
+        return fail(SHM_ERR_UNSUPPORTED, "backward: more than 2^32 queries or cells");
+    const int64_t Q = n_obj * q_per_obj;  // < 2^32: no overflow
     const int64_t cells = n_obj * 6ll * (N + 1) * (N + 1);
     if (Q >= 0xffffffffll || cells + 1 >= 0xffffffffll)
         return fail(SHM_ERR_UNSUPPORTED, "backward: more than 2^32 queries or cells");
@@ -499,7 +510,8 @@ int shm_cell_keys(int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj
 {
     clear_error();
     if (!valid_N(N) || n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "cell_keys: bad N or size");
-    if (n_obj * 6ll * (N + 1) * (N + 1) >= 0xffffffffll) return fail(SHM_ERR_UNSUPPORTED, "cell_keys: more than 2^32 cells");
+    if (n_obj > 0xffffffffll || n_obj * 6ll * (N + 1) * (N + 1) >= 0xffffffffll || product_exceeds(n_obj, q_per_obj, INT64_MAX / 16))
+        return fail(SHM_ERR_UNSUPPORTED, "cell_keys: more than 2^32 cells or too many queries");
     if (n_obj * q_per_obj == 0) return SHM_OK;
     if (!dirs || !keys) return fail(SHM_ERR_INVALID_ARG, "cell_keys: null pointer");
     return launch_cell_keys(N, n_obj, dirs, q_per_obj, keys, stream);

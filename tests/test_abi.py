@@ -187,3 +187,14 @@ def test_fit_validation():
     assert ad(p, p, p, p, 10, 1, float("nan"), 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
     assert ad(p, None, p, p, 10, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
     assert ad(p, p, mis, p, 10, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
+
+
+def test_size_products_do_not_overflow():
+    """Object x query counts whose product would overflow 64 bits are
+    refused on the host (no launch)."""
+    p = ctypes.c_void_p(256)
+    big = 1 << 40
+    assert shm.lib().shm_backward_workspace(8, big, big) == 0
+    assert call("shm_query_value_grad", p, 0, 0, 8, 1 << 62, p, 1 << 62, p, None, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_cell_keys", 8, big, p, big, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_backward_sort", 8, big, p, big, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
