@@ -181,6 +181,7 @@ int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, in
     if (L > SHM_MAX_L) return fail(SHM_ERR_UNSUPPORTED, "bake: L must be <= %d (got %d)", SHM_MAX_L, L);
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bake: N must be 1..%d (got %d)", SHM_MAX_N, N);
     if (n_obj < 0) return fail(SHM_ERR_INVALID_ARG, "bake: n_obj must be >= 0");
+    if (product_exceeds(n_obj, texel_elems(N), INT64_MAX / 8)) return fail(SHM_ERR_UNSUPPORTED, "bake: LUT too large");
     if (!valid_dtype(out_dtype)) return fail(SHM_ERR_INVALID_ARG, "bake: bad dtype %d", out_dtype);
     if (n_obj == 0) return SHM_OK;
     if (!coeffs || !lut_out) return fail(SHM_ERR_INVALID_ARG, "bake: null pointer");
@@ -202,6 +203,7 @@ int shm_bake_fd(const float* samples, int32_t N, int64_t n_obj, int32_t out_dtyp
     clear_error();
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bake_fd: N must be 1..%d", SHM_MAX_N);
     if (n_obj < 0 || !valid_dtype(out_dtype)) return fail(SHM_ERR_INVALID_ARG, "bake_fd: bad n_obj or dtype");
+    if (product_exceeds(n_obj, texel_elems(N), INT64_MAX / 8)) return fail(SHM_ERR_UNSUPPORTED, "bake_fd: LUT too large");
     if (n_obj == 0) return SHM_OK;
     if (!samples || !lut_out) return fail(SHM_ERR_INVALID_ARG, "bake_fd: null pointer");
     if (!aligned(lut_out, out_dtype == SHM_F16 ? 8 : 16)) return fail(SHM_ERR_INVALID_ARG, "bake_fd: misaligned LUT");
@@ -212,6 +214,7 @@ int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, int64_t n_
 {
     clear_error();
     if (!valid_N(N) || !valid_dtype(dtype) || n_obj < 0) return fail(SHM_ERR_INVALID_ARG, "lut_to_cells: bad N, dtype or n_obj");
+    if (product_exceeds(n_obj, cell_elems(N), INT64_MAX / 8)) return fail(SHM_ERR_UNSUPPORTED, "lut_to_cells: LUT too large");
     if (n_obj == 0) return SHM_OK;
     if (!lut_texel || !lut_cell) return fail(SHM_ERR_INVALID_ARG, "lut_to_cells: null pointer");
     const size_t al = dtype == SHM_F16 ? 8 : 16;
@@ -598,6 +601,7 @@ int shm_query_scaled(const void* lut, int32_t dtype, int32_t layout, int32_t N, 
     if (!valid_dtype(dtype) || !valid_layout(layout) || !valid_N(N))
         return fail(SHM_ERR_INVALID_ARG, "query_scaled: bad dtype, layout or N");
     if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query_scaled: negative size");
+    if (product_exceeds(n_obj, q_per_obj, INT64_MAX / 16)) return fail(SHM_ERR_UNSUPPORTED, "query_scaled: too many queries");
     if (!(scale > 0.0f) || !std::isfinite(scale)) return fail(SHM_ERR_INVALID_ARG, "query_scaled: scale must be positive and finite");
     if (flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "query_scaled: unknown flags 0x%x", flags);
     if (n_obj * q_per_obj == 0) return SHM_OK;
@@ -696,6 +700,7 @@ int shm_query_baseline(const float* vlut, int32_t N, int64_t n_obj, const float*
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "query_baseline: N must be 1..%d", SHM_MAX_N);
     if (method < SHM_RECON_NEAREST || method > SHM_RECON_FAST_BICUBIC_FD) return fail(SHM_ERR_INVALID_ARG, "query_baseline: bad method %d", method);
     if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query_baseline: negative size");
+    if (product_exceeds(n_obj, q_per_obj, INT64_MAX / 16)) return fail(SHM_ERR_UNSUPPORTED, "query_baseline: too many queries");
     if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
     if (!vlut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "query_baseline: null pointer");
     if (!aligned(out, 16) || !aligned(vlut, 4) || !aligned(dirs, 4)) return fail(SHM_ERR_INVALID_ARG, "query_baseline: misaligned buffer");
@@ -709,6 +714,7 @@ int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs
     if (L < 0) return fail(SHM_ERR_INVALID_ARG, "sh_eval: L must be >= 0");
     if (L > SHM_MAX_L) return fail(SHM_ERR_UNSUPPORTED, "sh_eval: L must be <= %d", SHM_MAX_L);
     if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "sh_eval: negative size");
+    if (product_exceeds(n_obj, q_per_obj, INT64_MAX / 16)) return fail(SHM_ERR_UNSUPPORTED, "sh_eval: too many queries");
     if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
     if (!coeffs || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "sh_eval: null pointer");
     if (!aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "sh_eval: misaligned output");

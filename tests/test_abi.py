@@ -198,3 +198,7 @@ def test_size_products_do_not_overflow():
     assert call("shm_query_value_grad", p, 0, 0, 8, 1 << 62, p, 1 << 62, p, None, None) == shm.SHM_ERR_UNSUPPORTED
     assert call("shm_cell_keys", 8, big, p, big, p, None) == shm.SHM_ERR_UNSUPPORTED
     assert call("shm_backward_sort", 8, big, p, big, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
+    huge = 1 << 60
+    assert call("shm_bake_fd", p, 8, huge, 0, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_lut_to_cells", p, 0, 8, huge, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_bake_sh_lut", p, 4, 8, huge, 0, p, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
