@@ -168,7 +168,7 @@ def main():
         lut3 = shm.bake_fd(to_dev(workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)), 256)
         rmax = float(shm.lut_rmax(lut3).item()) * 1.0001
         o3, d3 = workloads.camera_rays(1920, 1080)
-        shm.trace(lut3, (0.0, 0.0, 0.0), rmax, to_dev(o3), to_dev(d3), image_width=1920)
+        shm.trace(lut3, (0.0, 0.0, 0.0), rmax, to_dev(o3), to_dev(d3), image_width=1920, bound_map=shm.lut_bound_map(lut3))
         # one persistent launch of the uneven batch (FP16 cell LUTs) in the
         # launch shape the autotuner usually picks
         B = build_uneven_batch()
@@ -585,14 +585,23 @@ def run_trace():
     res = {"rays": P, "N": N, "rmax": rmax}
     smp = {"mu": mu, "amp": amp, "width": width, "o": o_np, "d": d_np, "rmax": rmax}
     W = 1920  # the rays are the row-major 1920 x 1080 image: one wavefront per 8 x 8 pixel tile
+    # block bound maps (64 x 64 blocks per face at N = 256), made once per LUT like rmax:
+    # march samples they prove outside the surface are not evaluated
+    bmap = shm.lut_bound_map(lut)
+    torch.cuda.synchronize()
+    res["bound_map_ms"] = t_gpu(lambda: shm.lut_bound_map(lut), 5)
     for name, lt in (("f32", lut), ("f16", lut.half())):
-        t, out, nrm = shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W)
-        ms = t_gpu(lambda: shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W), 20)
+        bm = bmap if lt.dtype == torch.float32 else shm.lut_bound_map(lt)
+        t, out, nrm = shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W, bound_map=bm)
+        ms = t_gpu(lambda: shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W, bound_map=bm), 20)
         hit = torch.isfinite(t)
         res[name] = {"ms": ms, "rays_per_s": P / ms * 1e3, "hit_frac": hit.float().mean().item(),
                      "evals_per_s_upper": 32 * P / ms * 1e3}
         smp[name] = (t.cpu().numpy(), nrm.cpu().numpy())
-    # the same rays one lane per ray in image order (64-pixel row pieces per wavefront)
+    # without the bound map, and then also one lane per ray in image order
+    # (64-pixel row pieces per wavefront)
+    ms = t_gpu(lambda: shm.trace(lut, (0.0, 0.0, 0.0), rmax, o, d, image_width=W), 20)
+    res["f32_no_bound_map"] = {"ms": ms, "rays_per_s": P / ms * 1e3}
     ms = t_gpu(lambda: shm.trace(lut, (0.0, 0.0, 0.0), rmax, o, d), 20)
     res["f32_ray_order"] = {"ms": ms, "rays_per_s": P / ms * 1e3}
     # Sec. 3.1 adaptive budget: bisections follow the projected size (focal
@@ -602,15 +611,21 @@ def run_trace():
     _, _, _, _, ev = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o, d, n_bisect=8, normals=False)
     hit = torch.isfinite(shm.trace(lut, (0.0, 0.0, 0.0), rmax, o, d)[0])
     res["f32"]["mean_evals_hit"] = ev[hit].float().mean().item()
+    _, _, _, _, evb = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o, d, n_bisect=8, normals=False, bound_map=bmap)
+    res["f32"]["evals_total"] = int(evb.int().sum().item())
+    res["f32_no_bound_map"]["evals_total"] = int(ev.int().sum().item())
     for name, eye in (("f32_adaptive", (0.0, 0.0, 3.5)), ("f32_adaptive_far", (0.0, 0.0, 12.0))):
         o2_np, d2_np = workloads.camera_rays(1920, 1080, eye=eye)
         o2, d2 = to_dev(o2_np), to_dev(d2_np)
         fn = lambda: shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, px_per_unit=px, eps_px=0.125, n_bisect=16,
-                                  image_width=W)
-        t2, _, _, _, ev2 = fn()
+                                  image_width=W, bound_map=bmap)
+        t2 = fn()[0]
         ms = t_gpu(fn, 20)
         h2 = torch.isfinite(t2)
-        # the march does not depend on the budget: a fixed 16 spends 16 - k more
+        # evaluation counts without the bound map: the march does not depend
+        # on the budget, so a fixed 16 spends 16 - k more
+        _, _, _, _, ev2 = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, px_per_unit=px, eps_px=0.125, n_bisect=16,
+                                       normals=False)
         _, _, _, _, ev16 = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, o2, d2, n_bisect=16, normals=False)
         k = 16 - (ev16[h2].float() - ev2[h2].float()).mean().item()
         res[name] = {"ms": ms, "rays_per_s": P / ms * 1e3, "hit_frac": h2.float().mean().item(),

@@ -72,6 +72,7 @@ typedef enum { SHM_LAYOUT_TEXEL = 0, SHM_LAYOUT_CELL = 1 } shm_layout;
 
 #define SHM_MAX_N 1024 /* largest interior face resolution */
 #define SHM_MAX_L 16   /* largest SH order of the analytic bake */
+#define SHM_MAX_BOUND_BLOCKS 64 /* largest blocks per face side of a bound map */
 
 /* ABI version (SHM_ABI_VERSION). */
 SHM_API int shm_version(void);
@@ -275,6 +276,14 @@ typedef struct shm_trace_params {
                              W) and each wavefront traces an 8 x 8 pixel tile,
                              so that its rays take similar numbers of steps;
                              the results are the same bits either way */
+    int32_t bound_blocks; /* 0: no bound map; B in 1..SHM_MAX_BOUND_BLOCKS:
+                             bound_map is shm_lut_bound_map's [6][B][B] map
+                             of this LUT (same flags), and march samples
+                             provably outside the surface (|p - c| above
+                             scale x their block's bound) are not evaluated;
+                             t, out, normal and sign are the same bits, evals
+                             counts only what was evaluated */
+    const float* bound_map;
 } shm_trace_params;
 SHM_API int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax,
                                 const shm_trace_params* params, const float* ray_o, const float* ray_d, int64_t P,
@@ -286,6 +295,16 @@ SHM_API int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const
  * flags = SHM_SIGNED the largest |control point|, which bounds |r|.  Writes
  * one float to rmax_out (device). */
 SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, int32_t flags, float* rmax_out, hipStream_t stream);
+
+/* Block bound map of one TEXEL LUT for the trace's empty-space skipping:
+ * face f is cut into blocks x blocks blocks of (u, v) (block bi covers
+ * u in [bi/blocks, (bi+1)/blocks]); map_out[f][bj][bi] (device, FP32) is
+ * the largest Bezier control point (|control point| with SHM_SIGNED), at
+ * least 0, over the cells a direction in that block can fall in, widened
+ * by one cell on every side.  It bounds r over the block as shm_lut_rmax
+ * bounds it over the sphere. */
+SHM_API int shm_lut_bound_map(const void* lut, int32_t dtype, int32_t N, int32_t flags, int32_t blocks, float* map_out,
+                              hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Mip chain (Sec. 4.7, Table lod): the next level (face size N/2, N even) of

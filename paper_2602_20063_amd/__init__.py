@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libshm.so")
 SHM_OK, SHM_ERR_INVALID_ARG, SHM_ERR_UNSUPPORTED, SHM_ERR_WORKSPACE, SHM_ERR_HIP = range(5)
 SHM_F32, SHM_F16 = 0, 1
 SHM_LAYOUT_TEXEL, SHM_LAYOUT_CELL = 0, 1
-SHM_MAX_N, SHM_MAX_L = 1024, 16
+SHM_MAX_N, SHM_MAX_L, SHM_MAX_BOUND_BLOCKS = 1024, 16, 64
 SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC, SHM_RECON_FAST_BICUBIC_FD = 0, 1, 2, 3
 SHM_SIGNED = 1
 
@@ -47,7 +47,8 @@ class shm_launch_shape(ctypes.Structure):
 class shm_trace_params(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_float), ("flags", ctypes.c_int32), ("n_march", ctypes.c_int32),
                 ("n_bisect", ctypes.c_int32), ("n_newton", ctypes.c_int32), ("px_per_unit", ctypes.c_float),
-                ("eps_px", ctypes.c_float), ("image_width", ctypes.c_int32)]
+                ("eps_px", ctypes.c_float), ("image_width", ctypes.c_int32), ("bound_blocks", ctypes.c_int32),
+                ("bound_map", ctypes.c_void_p)]
 
 
 _VP = ctypes.c_void_p
@@ -92,6 +93,7 @@ SIGNATURES = {
                                              _VP]),
     "shm_query_baseline": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _I32, _VP, _VP]),
     "shm_sh_eval": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP]),
+    "shm_lut_bound_map": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32, _VP, _VP]),
     "shm_fit_loss_grad": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, ctypes.c_float, _VP, _VP]),
     "shm_fit_forward_loss_grad": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _VP, _VP]),
     "shm_adam_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -496,17 +498,42 @@ def cell_keys(lut_N, dirs, n_obj=1, stream=None):
     return keys
 
 
+def _bound_fields(bound_map):
+    if bound_map is None:
+        return 0, None
+    if bound_map.dtype != torch.float32 or bound_map.dim() != 3 or bound_map.shape[0] != 6 or \
+            bound_map.shape[1] != bound_map.shape[2]:
+        raise ValueError("bound_map must be a [6, B, B] FP32 tensor from lut_bound_map")
+    return bound_map.shape[1], _ptr(bound_map)
+
+
+def lut_bound_map(lut, blocks=None, signed=False, stream=None):
+    """[6, blocks, blocks] FP32 block bounds of r (|r| if signed) of one
+    TEXEL LUT, for the trace's empty-space skipping.  By default a block
+    spans about 4 cells (N / 4 blocks per face side, at most 64)."""
+    N = lut_n(lut)
+    if blocks is None:
+        blocks = min(SHM_MAX_BOUND_BLOCKS, max(1, N // 4))
+    out = torch.empty((6, blocks, blocks), dtype=torch.float32, device=lut.device)
+    _check(lib().shm_lut_bound_map(_ptr(lut), _dtype_code(lut), N, SHM_SIGNED if signed else 0, blocks, _ptr(out),
+                                   _stream(stream)))
+    return out
+
+
 def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, normals=True, image_width=0,
-          stream=None):
+          bound_map=None, stream=None):
     """Fixed-schedule trace: t, (R, grad), normal.  image_width > 0 says the
-    rays are a row-major image of that width (traced in 8 x 8 tiles)."""
+    rays are a row-major image of that width (traced in 8 x 8 tiles);
+    bound_map (lut_bound_map of this LUT) skips march samples provably
+    outside the surface (the same results)."""
     N = lut_n(lut)
     P = ray_o.shape[0]
     t = torch.empty(P, dtype=torch.float32, device=ray_o.device)
     out = torch.empty((P, 4), dtype=torch.float32, device=ray_o.device)
     nrm = torch.empty((P, 3), dtype=torch.float32, device=ray_o.device) if normals else None
-    if image_width:
-        prm = shm_trace_params(1.0, 0, n_march, n_bisect, n_newton, 0.0, 0.0, int(image_width))
+    if image_width or bound_map is not None:
+        bb, bp = _bound_fields(bound_map)
+        prm = shm_trace_params(1.0, 0, n_march, n_bisect, n_newton, 0.0, 0.0, int(image_width), bb, bp)
         shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, None, None,
                             stream)
     else:
@@ -516,7 +543,7 @@ def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, n
 
 
 def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_unit=0.0, eps_px=0.125, n_march=20,
-             n_bisect=16, n_newton=3, normals=True, image_width=0, stream=None):
+             n_bisect=16, n_newton=3, normals=True, image_width=0, bound_map=None, stream=None):
     """Rendered-radius trace with the adaptive bisection budget: returns
     t, (R, grad), normal, sign of r (int8), F evaluations per ray (uint8)."""
     N = lut_n(lut)
@@ -527,8 +554,9 @@ def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_un
     nrm = torch.empty((P, 3), dtype=torch.float32, device=dev) if normals else None
     sgn = torch.empty(P, dtype=torch.int8, device=dev)
     ev = torch.empty(P, dtype=torch.uint8, device=dev)
+    bb, bp = _bound_fields(bound_map)
     prm = shm_trace_params(float(scale), SHM_SIGNED if signed else 0, n_march, n_bisect, n_newton, float(px_per_unit),
-                           float(eps_px), int(image_width))
+                           float(eps_px), int(image_width), bb, bp)
     shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, sgn, ev, stream)
     return t, out, nrm, sgn, ev
 

@@ -58,8 +58,9 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
                     float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
 int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
                  float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int image_width,
-                 int n_march, int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign,
-                 uint8_t* evals, hipStream_t stream);
+                 const float* bound_map, int bound_blocks, int n_march, int n_bisect, int n_newton, float* t_out,
+                 float* out, float* normal, int8_t* sign, uint8_t* evals, hipStream_t stream);
+int launch_bound_map(const void* lut, int dtype, int N, int flags, int blocks, float* map, hipStream_t stream);
 int launch_query_scaled(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
                         int64_t q_per_obj, float scale, int flags, float* out, float* normal, int8_t* sign,
                         hipStream_t stream);
@@ -549,6 +550,10 @@ static int check_trace_params(const shm_trace_params* tp)
     if (tp->px_per_unit > 0.0f && !(tp->eps_px > 0.0f && std::isfinite(tp->eps_px)))
         return fail(SHM_ERR_INVALID_ARG, "trace: eps_px must be positive and finite with an adaptive budget");
     if (tp->image_width < 0) return fail(SHM_ERR_INVALID_ARG, "trace: negative image_width");
+    if (tp->bound_blocks < 0 || tp->bound_blocks > SHM_MAX_BOUND_BLOCKS)
+        return fail(SHM_ERR_INVALID_ARG, "trace: bound_blocks must be 0..%d", SHM_MAX_BOUND_BLOCKS);
+    if (tp->bound_blocks > 0 && (!tp->bound_map || !aligned(tp->bound_map, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "trace: bound_blocks > 0 needs a bound map");
     return SHM_OK;
 }
 
@@ -570,17 +575,31 @@ int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* 
     if (!lut || !ray_o || !ray_d || !t_out || !out) return fail(SHM_ERR_INVALID_ARG, "trace: null pointer");
     if (!aligned(lut, dtype == SHM_F16 ? 8 : 16) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "trace: misaligned buffer");
     return launch_trace(lut, dtype, N, center, rmax, params->scale, params->flags, params->px_per_unit, params->eps_px,
-                        ray_o, ray_d, P, params->image_width, params->n_march, params->n_bisect, params->n_newton,
-                        t_out, out, normal, sign, evals, stream);
+                        ray_o, ray_d, P, params->image_width, params->bound_map, params->bound_blocks,
+                        params->n_march, params->n_bisect, params->n_newton, t_out, out, normal, sign, evals, stream);
 }
 
 int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const float* center, float rmax, const float* ray_o,
                      const float* ray_d, int64_t P, int32_t n_march, int32_t n_bisect, int32_t n_newton, float* t_out,
                      float* out, float* normal, hipStream_t stream)
 {
-    const shm_trace_params tp = {1.0f, 0, n_march, n_bisect, n_newton, 0.0f, 0.0f, 0};
+    const shm_trace_params tp = {1.0f, 0, n_march, n_bisect, n_newton, 0.0f, 0.0f, 0, 0, nullptr};
     return shm_trace_radial_ex(lut, dtype, N, center, rmax, &tp, ray_o, ray_d, P, t_out, out, normal, nullptr, nullptr,
                                stream);
+}
+
+int shm_lut_bound_map(const void* lut, int32_t dtype, int32_t N, int32_t flags, int32_t blocks, float* map_out,
+                      hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bound_map: bad dtype or N");
+    if (flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "bound_map: unknown flags 0x%x", flags);
+    if (blocks < 1 || blocks > SHM_MAX_BOUND_BLOCKS)
+        return fail(SHM_ERR_INVALID_ARG, "bound_map: blocks must be 1..%d", SHM_MAX_BOUND_BLOCKS);
+    if (!lut || !map_out) return fail(SHM_ERR_INVALID_ARG, "bound_map: null pointer");
+    if (!aligned(map_out, 4) || !aligned(lut, dtype == SHM_F16 ? 2 : 4))
+        return fail(SHM_ERR_INVALID_ARG, "bound_map: misaligned buffer");
+    return launch_bound_map(lut, dtype, N, flags, blocks, map_out, stream);
 }
 
 int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, int32_t flags, float* rmax_out, hipStream_t stream)

@@ -656,53 +656,91 @@ int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, vo
 // image of non-negative floats is exact; a negative bound clamps to 0
 // (R >= 0 for a star-shaped surface).
 // ---------------------------------------------------------------------------
+// Largest Bezier control point of cell (i0, j0) of a face (convex hull
+// bound of its bicubic patch); with absval the largest |control point|.
+template <bool F16>
+__device__ __forceinline__ float cell_bezier_max(const void* __restrict__ lut, int N, int face, int i0, int j0,
+                                                 bool absval)
+{
+    const int P = N + 2;
+    float G[4][4];  // [s-index over (p0, m0, p1, m1)][t-index likewise]
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            const int64_t t = ((int64_t)(face * P + j0 + dj) * P + i0 + di) * 4;
+            float c[4];
+            if constexpr (F16) {
+                const __half* h = reinterpret_cast<const __half*>(lut) + t;
+                for (int k = 0; k < 4; ++k) c[k] = __half2float(h[k]);
+            } else {
+                const float* f = reinterpret_cast<const float*>(lut) + t;
+                for (int k = 0; k < 4; ++k) c[k] = f[k];
+            }
+            G[2 * di][2 * dj] = c[0];
+            G[2 * di + 1][2 * dj] = c[1];
+            G[2 * di][2 * dj + 1] = c[2];
+            G[2 * di + 1][2 * dj + 1] = c[3];
+        }
+    float H[4][4];
+    for (int b = 0; b < 4; ++b) {
+        H[0][b] = G[0][b];
+        H[1][b] = G[0][b] + G[1][b] / 3.0f;
+        H[2][b] = G[2][b] - G[3][b] / 3.0f;
+        H[3][b] = G[2][b];
+    }
+    float best = -__builtin_inff();
+    for (int a = 0; a < 4; ++a) {
+        float z0 = H[a][0], z1 = H[a][0] + H[a][1] / 3.0f, z2 = H[a][2] - H[a][3] / 3.0f, z3 = H[a][2];
+        if (absval) {
+            z0 = fabsf(z0);
+            z1 = fabsf(z1);
+            z2 = fabsf(z2);
+            z3 = fabsf(z3);
+        }
+        best = fmaxf(best, fmaxf(fmaxf(z0, z1), fmaxf(z2, z3)));
+    }
+    return best;
+}
+
 template <bool F16>
 __global__ void k_lut_rmax(const void* __restrict__ lut, int N, int absval, unsigned int* __restrict__ out_bits)
 {
-    const int C = N + 1, P = N + 2;
+    const int C = N + 1;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     float best = 0.0f;
     if (i < 6 * C * C) {
         const int face = i / (C * C), rem = i - face * C * C;
         const int j0 = rem / C, i0 = rem - j0 * C;
-        float G[4][4];  // [s-index over (p0, m0, p1, m1)][t-index likewise]
-        for (int dj = 0; dj < 2; ++dj)
-            for (int di = 0; di < 2; ++di) {
-                const int64_t t = ((int64_t)(face * P + j0 + dj) * P + i0 + di) * 4;
-                float c[4];
-                if constexpr (F16) {
-                    const __half* h = reinterpret_cast<const __half*>(lut) + t;
-                    for (int k = 0; k < 4; ++k) c[k] = __half2float(h[k]);
-                } else {
-                    const float* f = reinterpret_cast<const float*>(lut) + t;
-                    for (int k = 0; k < 4; ++k) c[k] = f[k];
-                }
-                G[2 * di][2 * dj] = c[0];
-                G[2 * di + 1][2 * dj] = c[1];
-                G[2 * di][2 * dj + 1] = c[2];
-                G[2 * di + 1][2 * dj + 1] = c[3];
-            }
-        float H[4][4];
-        for (int b = 0; b < 4; ++b) {
-            H[0][b] = G[0][b];
-            H[1][b] = G[0][b] + G[1][b] / 3.0f;
-            H[2][b] = G[2][b] - G[3][b] / 3.0f;
-            H[3][b] = G[2][b];
-        }
-        for (int a = 0; a < 4; ++a) {
-            float z0 = H[a][0], z1 = H[a][0] + H[a][1] / 3.0f, z2 = H[a][2] - H[a][3] / 3.0f, z3 = H[a][2];
-            if (absval) {
-                z0 = fabsf(z0);
-                z1 = fabsf(z1);
-                z2 = fabsf(z2);
-                z3 = fabsf(z3);
-            }
-            best = fmaxf(best, fmaxf(fmaxf(z0, z1), fmaxf(z2, z3)));
-        }
+        best = fmaxf(best, cell_bezier_max<F16>(lut, N, face, i0, j0, absval != 0));
     }
     // wave reduction, then one atomic per wave
     for (int off = 32; off > 0; off >>= 1) best = fmaxf(best, __shfl_xor(best, off));
     if ((threadIdx.x & 63) == 0) atomicMax(out_bits, __float_as_uint(best));
+}
+
+// Block bound map: face f is cut into B x B blocks of (u, v) (block bi covers
+// u in [bi/B, (bi+1)/B]); map[f][bj][bi] = max(0, the largest control point
+// of the cells that block can reach, widened by one cell on every side so
+// that a direction located to within an ulp of a block edge is still
+// covered).  One 64-lane workgroup per block: lanes stride over the cells,
+// then a wave maximum.  The trace uses it to skip march samples that are
+// provably outside the surface.
+template <bool F16>
+__global__ void k_bound_map(const void* __restrict__ lut, int N, int absval, int B, float* __restrict__ map)
+{
+    const int blk = blockIdx.x;
+    const int face = blk / (B * B), rem = blk - face * B * B;
+    const int bj = rem / B, bi = rem - bj * B;
+    // cells i0 = floor(u N + 1/2) for u in the block, in integers
+    const int i_lo = max((2 * bi * N + B) / (2 * B) - 1, 0), i_hi = min((2 * (bi + 1) * N + B) / (2 * B) + 1, N);
+    const int j_lo = max((2 * bj * N + B) / (2 * B) - 1, 0), j_hi = min((2 * (bj + 1) * N + B) / (2 * B) + 1, N);
+    const int wi = i_hi - i_lo + 1, n = wi * (j_hi - j_lo + 1);
+    float best = 0.0f;
+    for (int k = threadIdx.x; k < n; k += 64) {
+        const int j0 = j_lo + k / wi, i0 = i_lo + k % wi;
+        best = fmaxf(best, cell_bezier_max<F16>(lut, N, face, i0, j0, absval != 0));
+    }
+    for (int off = 32; off > 0; off >>= 1) best = fmaxf(best, __shfl_xor(best, off));
+    if (threadIdx.x == 0) map[blk] = best;
 }
 
 __global__ void k_bits_to_float(const unsigned int* bits, float* out) { *out = __uint_as_float(*bits); }
@@ -720,6 +758,18 @@ int launch_lut_rmax(const void* lut, int dtype, int N, int flags, float* rmax_ou
     else
         hipLaunchKernelGGL(k_lut_rmax<false>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, absval, bits);
     hipLaunchKernelGGL(k_bits_to_float, dim3(1), dim3(1), 0, stream, bits, rmax_out);
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+int launch_bound_map(const void* lut, int dtype, int N, int flags, int blocks, float* map, hipStream_t stream)
+{
+    const int absval = (flags & SHM_SIGNED) ? 1 : 0;
+    const dim3 grid((unsigned)(6 * blocks * blocks)), bl(64);
+    if (dtype == SHM_F16)
+        hipLaunchKernelGGL(k_bound_map<true>, grid, bl, 0, stream, lut, N, absval, blocks, map);
+    else
+        hipLaunchKernelGGL(k_bound_map<false>, grid, bl, 0, stream, lut, N, absval, blocks, map);
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }

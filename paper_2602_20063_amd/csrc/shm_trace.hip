@@ -42,6 +42,50 @@ __device__ __forceinline__ FEval trace_eval(const void* __restrict__ lut, int N,
     return E;
 }
 
+// Empty-space test of a march sample against the block bound map (map
+// [6][B][B], bounds of r from the cells' Bezier control points): true when
+// |p - c| exceeds scale * bound (with a 2^-12 margin, far above the
+// rounding of the bound, of |p - c| and of the evaluated R), so F > 0 there
+// and the evaluation that would say so can be skipped.  The face is chosen
+// as the query chooses it; the block from a hardware-reciprocal (u, v),
+// which the map's one-cell widening covers.
+__device__ __forceinline__ bool outside_bound(const float* __restrict__ map, int B, float scale, float x, float y,
+                                              float z)
+{
+    const float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
+    const bool isx = (ax >= ay) && (ax >= az);
+    const bool isy = !isx && (ay >= az);
+    float sc, tc, ma;
+    int face;
+    if (isx) {
+        const bool pos = x >= 0.0f;
+        face = pos ? 0 : 1;
+        ma = ax;
+        sc = pos ? -z : z;
+        tc = -y;
+    } else if (isy) {
+        const bool pos = y >= 0.0f;
+        face = pos ? 2 : 3;
+        ma = ay;
+        sc = x;
+        tc = pos ? z : -z;
+    } else {
+        const bool pos = z >= 0.0f;
+        face = pos ? 4 : 5;
+        ma = az;
+        sc = pos ? x : -x;
+        tc = -y;
+    }
+    if (!(ma > 0.0f) || !(ma < __builtin_inff())) return false;
+    const float rm = __builtin_amdgcn_rcpf(ma);
+    const float Bf = (float)B;
+    int bi = (int)((sc * rm + 1.0f) * 0.5f * Bf), bj = (int)((tc * rm + 1.0f) * 0.5f * Bf);
+    bi = bi < 0 ? 0 : (bi >= B ? B - 1 : bi);
+    bj = bj < 0 ? 0 : (bj >= B ? B - 1 : bj);
+    const float rb = scale * map[(face * B + bj) * B + bi] * (1.0f + 1.0f / 4096.0f);
+    return x * x + y * y + z * z > rb * rb;
+}
+
 // Bisection budget: the march bracket (at most 2 rmax / n_march long) spans
 // e = 2 rmax px / (|o - c| n_march) pixels at the glyph's depth, px being
 // the focal length in pixels; halve until e <= eps_px, at most n_bisect
@@ -66,7 +110,8 @@ template <bool FP16, bool NRM>
 __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int N, float cx, float cy, float cz,
                                                float rmax, float scale, int is_signed_i, float px_focal, float eps_px,
                                                const float* __restrict__ ray_o, const float* __restrict__ ray_d,
-                                               int64_t P, int img_w, int64_t tiles_x, int n_march,
+                                               int64_t P, int img_w, int64_t tiles_x,
+                                               const float* __restrict__ bmap, int bmap_b, int n_march,
                                                int n_bisect_max, int n_newton, float* __restrict__ t_out,
                                                float* __restrict__ out, float* __restrict__ nrm,
                                                int8_t* __restrict__ sign_out, uint8_t* __restrict__ evals_out)
@@ -112,6 +157,8 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
             float lo = t0, hi = t0;
             for (int k = 1; k <= n_march; ++k) {
                 const float tk = t0 + (float)k * step;
+                if (bmap && outside_bound(bmap, bmap_b, scale, ox + tk * dx, oy + tk * dy, oz + tk * dz))
+                    continue;  // F > 0 there for certain: the march goes on, as it would after evaluating
                 const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, tk, scale, is_signed);
                 ++evals;
                 if (E.F < 0.0f) {
@@ -171,8 +218,8 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
 
 int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
                  float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int image_width,
-                 int n_march, int n_bisect, int n_newton, float* t_out, float* out, float* normal, int8_t* sign,
-                 uint8_t* evals, hipStream_t stream)
+                 const float* bound_map, int bound_blocks, int n_march, int n_bisect, int n_newton, float* t_out,
+                 float* out, float* normal, int8_t* sign, uint8_t* evals, hipStream_t stream)
 {
     if (P == 0) return SHM_OK;
     // one lane per ray, or (image rays) one wavefront per 8 x 8 tile
@@ -189,8 +236,8 @@ int launch_trace(const void* lut, int dtype, int N, const float* center, float r
     const int sgn = (flags & SHM_SIGNED) ? 1 : 0;
 #define SHM_T(F, NR)                                                                                                  \
     hipLaunchKernelGGL((k_trace<F, NR>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, scale, sgn, px_focal, eps_px,      \
-                       ray_o, ray_d, P, image_width, tiles_x, n_march, n_bisect, n_newton, t_out, out, normal, sign, \
-                       evals)
+                       ray_o, ray_d, P, image_width, tiles_x, bound_blocks > 0 ? bound_map : nullptr, bound_blocks,   \
+                       n_march, n_bisect, n_newton, t_out, out, normal, sign, evals)
     if (dtype == SHM_F16) {
         if (normal) SHM_T(true, true);
         else SHM_T(true, false);

@@ -117,7 +117,8 @@ def test_render_validation():
     c = (ctypes.c_float * 3)(0, 0, 0)
 
     def prm(**kw):
-        d = dict(scale=1.0, flags=0, n_march=20, n_bisect=8, n_newton=3, px_per_unit=0.0, eps_px=0.0, image_width=0)
+        d = dict(scale=1.0, flags=0, n_march=20, n_bisect=8, n_newton=3, px_per_unit=0.0, eps_px=0.0, image_width=0,
+                 bound_blocks=0, bound_map=None)
         d.update(kw)
         return shm.shm_trace_params(**d)
 
@@ -128,8 +129,9 @@ def test_render_validation():
     assert tr(prm(flags=shm.SHM_SIGNED, px_per_unit=900.0, eps_px=0.1), P=0) == shm.SHM_OK
     for bad in (prm(scale=0.0), prm(scale=float("inf")), prm(flags=2), prm(n_march=0), prm(n_bisect=60),
                 prm(px_per_unit=-1.0), prm(px_per_unit=float("nan")), prm(px_per_unit=100.0, eps_px=0.0),
-                prm(image_width=-1), prm(image_width=3), prm(image_width=20)):
-        assert tr(bad) == shm.SHM_ERR_INVALID_ARG  # 10 rays: not whole rows of 3 or 20
+                prm(image_width=-1), prm(image_width=3), prm(image_width=20),
+                prm(bound_blocks=-1), prm(bound_blocks=65, bound_map=256), prm(bound_blocks=4)):
+        assert tr(bad) == shm.SHM_ERR_INVALID_ARG  # 10 rays: not whole rows of 3 or 20; map sizes
     assert tr(prm(image_width=7), P=0) == shm.SHM_OK
     assert call("shm_trace_radial_ex", p, 0, 8, c, 1.0, None, p, p, 10, p, p, None, None, None, None) == shm.SHM_ERR_INVALID_ARG
     q = lambda scale, flags, Q=10: call("shm_query_scaled", p, 0, 0, 8, 1, p, Q, scale, flags, p, None, None, None)
@@ -140,6 +142,10 @@ def test_render_validation():
     assert call("shm_query_scaled", p, 0, 0, 8, 1, None, 10, 1.0, 0, p, None, None, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_lut_rmax", p, 0, 8, 2, p, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_lut_rmax", p, 0, 8, 0, None, None) == shm.SHM_ERR_INVALID_ARG
+    bm = lambda *a: call("shm_lut_bound_map", *a)
+    for args in ((p, 0, 8, 0, 0, p), (p, 0, 8, 0, 65, p), (p, 0, 8, 2, 8, p), (None, 0, 8, 0, 8, p), (p, 0, 8, 0, 8, None),
+                 (p, 0, 0, 0, 8, p), (p, 5, 8, 0, 8, p), (p, 0, 8, 0, 8, ctypes.c_void_p(258))):
+        assert bm(*args, None) == shm.SHM_ERR_INVALID_ARG, args
 
 
 def test_mesh_depth_validation():

@@ -133,3 +133,20 @@ def test_uneven_batch_full_size_sampled(tmp_path):
     ref = oracle.query_objects(np.concatenate(flats), offs, Ns, qb, qc, B["dirs_np"][rows_all])
     got = out[torch.as_tensor(rows_all, device=DEV)].cpu().numpy()
     check_value_grad(got, ref, "uneven batch, sampled objects")
+
+
+def test_trace_full_size_bound_map_same_bits():
+    """The benchmark's trace with the bound map and image tiles gives the
+    bits of the plain launch (1920 x 1080, N = 256)."""
+    N = 256
+    mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+    md = shm.margin_dirs(N).cpu().numpy().reshape(-1, 3)
+    samples = workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)
+    lut = shm.bake_fd(torch.as_tensor(samples).to(DEV), N)
+    rmax = float(shm.lut_rmax(lut).item()) * 1.0001
+    o, d = workloads.camera_rays(1920, 1080)
+    og, dg = torch.as_tensor(o).to(DEV), torch.as_tensor(d).to(DEV)
+    a = shm.trace(lut, (0.0, 0.0, 0.0), rmax, og, dg)
+    b = shm.trace(lut, (0.0, 0.0, 0.0), rmax, og, dg, image_width=1920, bound_map=shm.lut_bound_map(lut))
+    for x, y in zip(a, b):
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32))

@@ -119,3 +119,60 @@ def same_bits(a, b):
     if a.dtype == torch.float32:
         return torch.equal(a.view(torch.int32), b.view(torch.int32))
     return torch.equal(a, b)
+
+
+def bumps_lut(N):
+    mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+    md = oracle.margin_dirs(N)
+    samples = workloads.bumps_value(mu, amp, width, 1.0, md.reshape(-1, 3)).reshape(6, N + 4, N + 4)
+    return oracle.bake_fd(samples, N).astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [1, 5, 8, 64])
+def test_bound_map_bounds_the_reconstruction(B):
+    """Every block's bound is the oracle's largest control point over the
+    (widened) cells of the block, and no query of a direction in the block
+    exceeds it."""
+    N = 40
+    lut = bumps_lut(N)
+    bmap = shm.lut_bound_map(gpu(lut), blocks=B).cpu().numpy()
+    lut64 = lut.astype(np.float64)
+    rng = np.random.default_rng(B)
+    for f, bj, bi in [(0, 0, 0), (3, B - 1, B - 1), (5, B // 2, (B - 1) // 3)] + [tuple(x) for x in rng.integers(0, [6, B, B], (6, 3))]:
+        lo = lambda b: max((2 * b * N + B) // (2 * B) - 1, 0)
+        hi = lambda b: min((2 * (b + 1) * N + B) // (2 * B) + 1, N)
+        want = max(0.0, max(oracle.cell_bezier(lut64, f, i0, j0).max()
+                            for j0 in range(lo(bj), hi(bj) + 1) for i0 in range(lo(bi), hi(bi) + 1)))
+        assert abs(bmap[f, bj, bi] - want) <= 1e-6 * want, (f, bj, bi, bmap[f, bj, bi], want)
+    dirs = workloads.uniform_dirs(200000, rng)
+    r = shm.query(gpu(lut)[None], gpu(dirs)).cpu().numpy()[:, 0]
+    face, i0, j0, s, t = oracle.locate(dirs, N)
+    bu = np.clip(np.floor((i0 + s - 0.5) / N * B).astype(int), 0, B - 1)
+    bv = np.clip(np.floor((j0 + t - 0.5) / N * B).astype(int), 0, B - 1)
+    assert (r <= bmap[face, bv, bu] * (1 + 1e-6)).all()
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float16])
+def test_trace_bound_map_same_bits(dt):
+    """Skipping the march samples the bound map proves outside the surface
+    changes no output bit and only lowers the evaluation counts; fixed and
+    adaptive budgets, plain and signed radius, image tiles and ray order."""
+    N = 64
+    lut = gpu(bumps_lut(N), dt)
+    rmax = float(shm.lut_rmax(lut).item()) * 1.0001
+    o, d = workloads.camera_rays(67, 29, vfov_deg=30.0)
+    og, dg = gpu(o), gpu(d)
+    for signed, px in ((False, 0.0), (True, 300.0)):
+        bmap = shm.lut_bound_map(lut, blocks=16, signed=signed)
+        for w in (0, 67):
+            kw = dict(signed=signed, px_per_unit=px, eps_px=0.125, n_bisect=12, image_width=w)
+            a = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, og, dg, **kw)
+            b = shm.trace_ex(lut, (0.0, 0.0, 0.0), rmax, og, dg, bound_map=bmap, **kw)
+            for x, y in zip(a[:4], b[:4]):
+                assert same_bits(x, y)
+            ea, eb = a[4].int(), b[4].int()
+            assert (eb <= ea).all() and eb.sum() < ea.sum()
+    a = shm.trace(lut, (0.0, 0.0, 0.0), rmax, og, dg)
+    b = shm.trace(lut, (0.0, 0.0, 0.0), rmax, og, dg, bound_map=shm.lut_bound_map(lut, blocks=8))
+    for x, y in zip(a, b):
+        assert same_bits(x, y)
