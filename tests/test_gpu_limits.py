@@ -82,3 +82,10 @@ def test_trace_face_size_one():
     ref = oracle.trace(lut.astype(np.float64), np.zeros(3), rmax, o, d)
     assert np.isfinite(ref[0]).mean() > 0.2
     compare((t.cpu().numpy(), out.cpu().numpy(), n.cpu().numpy()), ref, "trace N=1", max_disagree=1.5 / o.shape[0])
+    # bound maps with more blocks than cells: the same bits
+    lg = torch.as_tensor(lut).to(DEV)
+    for B in (1, 3, 64):
+        b = shm.trace(lg, (0.0, 0.0, 0.0), rmax, torch.as_tensor(o).to(DEV), torch.as_tensor(d).to(DEV),
+                      image_width=48, bound_map=shm.lut_bound_map(lg, blocks=B))
+        for x, y in zip((t, out, n), b):
+            assert torch.equal(x.view(torch.int32), y.view(torch.int32)), B
