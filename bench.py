@@ -677,31 +677,38 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
     log("cpu baseline", cpu)
     errs = {}
 
-    def stats(o, r):
+    def stats(o, r, dirs):
         ok = np.isfinite(r[:, 0])
-        o, r = o[ok].astype(np.float64), r[ok]
+        o, r, dirs = o[ok].astype(np.float64), r[ok], dirs[ok].astype(np.float64)
         dv = np.abs(o[:, 0] - r[:, 0]) / np.abs(r[:, 0])
         gn = np.linalg.norm(r[:, 1:], axis=1)
         dg = np.linalg.norm(o[:, 1:] - r[:, 1:], axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))
+        # normals (Eq. 10) from both outputs: n = (R w - grad R) / |R w - grad R|
+        w = dirs / np.linalg.norm(dirs, axis=1, keepdims=True)
+        nrm = lambda x: (lambda m: m / np.linalg.norm(m, axis=1, keepdims=True))(x[:, :1] * w - x[:, 1:])
+        ang = np.degrees(np.arccos(np.clip(np.sum(nrm(o) * nrm(r), axis=1), -1.0, 1.0)))
         return {"value_max_rel": float(dv.max()), "value_rms_rel": float(np.sqrt(np.mean(dv ** 2))),
-                "grad_max_rel": float(dg.max()), "grad_rms_rel": float(np.sqrt(np.mean(dg ** 2)))}
+                "grad_max_rel": float(dg.max()), "grad_rms_rel": float(np.sqrt(np.mean(dg ** 2))),
+                "normal_deg_max": float(ang.max()), "normal_deg_mean": float(ang.mean())}
 
     # headline: GPU bake (FP32) + FP32 query vs FP64 bake + FP64 query
-    errs["query_f32_cell"] = stats(out_cell[: ns * q_per].cpu().numpy(), ref)
+    d_s = d[: ns * q_per]
+    errs["query_f32_cell"] = stats(out_cell[: ns * q_per].cpu().numpy(), ref, d_s)
     for name in ("query_f16_cell", "query_f16_texel"):
         if name in sample:
-            errs[name] = stats(sample[name], ref)
+            errs[name] = stats(sample[name], ref, d_s)
     if "batched" in sample:
         s = sample["batched"]
-        o_all, r_all = [], []
+        o_all, r_all, d_all = [], [], []
         q0 = 0
         for k in range(len(s["N"])):
             lut = oracle.bake_sh(s["coeffs"][k].astype(np.float64), s["N"][k])
             q = s["q"][k]
             r_all.append(oracle.query(lut, s["dirs"][q0:q0 + q]))
             o_all.append(s["out"][q0:q0 + q])
+            d_all.append(s["dirs"][q0:q0 + q])
             q0 += q
-        errs["batched"] = stats(np.concatenate(o_all), np.concatenate(r_all))
+        errs["batched"] = stats(np.concatenate(o_all), np.concatenate(r_all), np.concatenate(d_all))
     if "trace" in sample:
         s = sample["trace"]
         N3 = 256
