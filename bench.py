@@ -272,7 +272,7 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
     log("mip", forms["mip_lod"])
     forms["mesh_impostor"] = run_mesh()
     log("mesh", forms["mesh_impostor"])
-    forms["backward_fit"] = run_backward_fit()
+    forms["backward_fit"], sample["backward"] = run_backward_fit()
     log("backward", forms["backward_fit"])
     forms["batched"], sample["batched"] = run_batched()
     log("batched", {k: v for k, v in forms["batched"].items() if k != "objects"})
@@ -410,6 +410,19 @@ def run_backward_fit():
     bwd = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, gd, bctx.ws, True)
     bwd_lut = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, None, bctx.ws, True)
     fwd(); bwd()
+    # error sample: a random LUT's gradients; the LUT gradient through the
+    # adjoint identity (exact here: the outputs are linear in the LUT), the
+    # direction gradient against the FP64 oracle on sampled queries (CPU leg)
+    lut_r = to_dev(workloads.random_lut(N, workloads.rng_for(41)))[None].contiguous()
+    gl_r, gd_r = bctx.backward(lut_r, g)
+    Dr = torch.randn(lut_r.shape, device=DEV, generator=torch.Generator(device=DEV).manual_seed(41))
+    fD = shm.query(Dr, dirs)
+    lhs, rhs = (gl_r.double() * Dr.double()).sum().item(), (g.double() * fD.double()).sum().item()
+    adj = abs(lhs - rhs) / (gl_r.double() * Dr.double()).abs().sum().item()
+    ks = torch.as_tensor(np.random.default_rng(41).choice(Q, 2000, replace=False), device=DEV)
+    bwd_sample = {"lut": lut_r[0].cpu().numpy(), "dirs": dirs[ks].cpu().numpy(), "g": g[ks].cpu().numpy(),
+                  "gd": gd_r[ks].cpu().numpy(), "adjoint_rel": adj}
+    del lut_r, gl_r, gd_r, Dr, fD
     shm.shm_backward_sort(N, 1, dirs, Q, bctx.ws)  # sort again, code objects now loaded
     ms_sort = t_gpu(lambda: shm.shm_backward_sort(N, 1, dirs, Q, bctx.ws), 3)
     ms_f = t_gpu(fwd, 20)
@@ -472,7 +485,7 @@ def run_backward_fit():
                     "initial_normal_mean_deg": ang0.mean().item(),
                     "value_rmse": ((R - tv) ** 2).mean().sqrt().item(), "normal_mean_deg": ang.mean().item(),
                     "initial_value_rmse": ((1.0 - tv) ** 2).mean().sqrt().item()})
-    return res
+    return res, bwd_sample
 
 
 def build_uneven_batch():
@@ -709,6 +722,13 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
             d_all.append(s["dirs"][q0:q0 + q])
             q0 += q
         errs["batched"] = stats(np.concatenate(o_all), np.concatenate(r_all), np.concatenate(d_all))
+    if "backward" in sample:
+        s = sample["backward"]
+        _, rd = oracle.backward(s["lut"], s["dirs"], s["g"], want_lut=False)
+        gn = np.linalg.norm(rd, axis=1)
+        e = np.linalg.norm(s["gd"] - rd, axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))
+        errs["backward_fit"] = {"lut_grad_adjoint_rel": s["adjoint_rel"], "dirs_grad_max_rel": float(e.max()),
+                            "dirs_grad_rms_rel": float(np.sqrt(np.mean(e ** 2))), "dirs_sampled": int(e.size)}
     if "trace" in sample:
         s = sample["trace"]
         N3 = 256
