@@ -437,7 +437,8 @@ def run_backward_fit():
     # scaled derivative channels; the value term is weighted by 1/ell^2 with
     # ell = 1/sqrt(1000) (about ten cells at N=512), so that value and normal
     # errors enter on a comparable footing.  Native: every step (forward,
-    # loss gradient, backward, Adam) in the library's kernels; then the same
+    # loss gradient, backward, Adam) in one of the library's kernels, then in
+    # three of them; then the same
     # fit driven by PyTorch autograd and torch.optim.Adam around the library's
     # forward and backward, for comparison.
     w_val, lr_v, lr_d, steps = 1000.0, 1e-3, 3e-4, 200
@@ -451,6 +452,15 @@ def run_backward_fit():
         fit.step()
     torch.cuda.synchronize()
     fit_s = time.time() - t0
+    # the same fit with the three-kernel step (forward + loss gradient,
+    # backward, Adam) in place of the one-kernel step
+    fit3 = shm.LutFit(lut0.clone(), dirs, tv, tn, w_value=w_val, lr_value=lr_v, lr_deriv=lr_d, fused=False)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(steps):
+        fit3.step()
+    torch.cuda.synchronize()
+    fit3_s = time.time() - t0
     val = lut0[..., :1].clone().requires_grad_(True)
     der = lut0[..., 1:].clone().requires_grad_(True)
     opt = torch.optim.Adam([{"params": [val], "lr": lr_v}, {"params": [der], "lr": lr_d}], betas=(0.9, 0.999), eps=1e-8)
@@ -479,6 +489,8 @@ def run_backward_fit():
         ang0 = torch.rad2deg(torch.acos(torch.clamp((w * tn).sum(dim=1), -1, 1)))
         ref = torch.cat([val.detach(), der.detach()], dim=-1)
         res.update({"fit_steps": steps, "fit_s": fit_s, "fit_ms_per_step": fit_s / steps * 1e3,
+                    "fit_three_kernel_ms_per_step": fit3_s / steps * 1e3,
+                    "fit_one_kernel_vs_three_kernel_max_abs": (fit.lut - fit3.lut).abs().max().item(),
                     "fit_torch_adam_s": fit_torch_s,
                     "fit_native_vs_torch_max_abs": (fit.lut - ref).abs().max().item(),
                     "final_loss": loss.item(),

@@ -409,6 +409,27 @@ SHM_API int shm_fit_forward_loss_grad(const float* lut, int32_t N, const float* 
                                       hipStream_t stream);
 SHM_API int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n4, int64_t step,
                           float lr_value, float lr_deriv, float beta1, float beta2, float eps, hipStream_t stream);
+/* One whole fitting step of one FP32 TEXEL LUT (face size N) in one kernel:
+ * the forward query of lut_in at dirs, the objective's gradient as in
+ * shm_fit_loss_grad, the LUT gradient as in shm_query_backward (the same
+ * sorted, deterministic sums; no direction gradient) and the Adam update as
+ * in shm_adam_step, written to lut_out:
+ *   lut_out = adam(lut_in, dL/dLUT(lut_in), m, v, step)
+ *   lut_in, lut_out  [6][N+2][N+2][4]; lut_out is overwritten and must not
+ *            overlap lut_in (a texel's update and its neighbours' queries
+ *            run concurrently), so a loop alternates two buffers
+ *   m, v     Adam moments of the same shape, updated in place (zero before
+ *            step 1); none of the four buffers may overlap another
+ *   dirs, target_r, target_n, Q, w_value  as in shm_fit_loss_grad
+ *   step, lr_value, lr_deriv, beta1, beta2, eps  as in shm_adam_step
+ *   ws, ws_bytes  shm_backward_workspace(N, 1, Q) bytes, 256-byte aligned;
+ *            sort_ready = 0 sorts dirs into it first, 1 reuses the sort a
+ *            previous call (or shm_backward_sort(N, 1, dirs, Q)) left there
+ * Q = 0 is allowed: the gradient is zero and Adam still moves the moments. */
+SHM_API int shm_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int32_t N, const float* dirs,
+                         const float* target_r, const float* target_n, int64_t Q, float w_value, int64_t step,
+                         float lr_value, float lr_deriv, float beta1, float beta2, float eps, void* ws,
+                         size_t ws_bytes, int32_t sort_ready, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,9 @@ SIGNATURES = {
     "shm_fit_forward_loss_grad": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _VP, _VP]),
     "shm_adam_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, _VP]),
+    "shm_fit_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _I64,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    _VP, ctypes.c_size_t, _I32, _VP]),
 }
 
 _lib = None
@@ -265,36 +268,67 @@ def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, be
                                       float(lr_deriv), float(beta1), float(beta2), float(eps), _stream(stream)))
 
 
+def shm_fit_step(lut_in, lut_out, m, v, N, dirs, target_r, target_n, Q, w_value, step, lr_value, lr_deriv,
+                 beta1, beta2, eps, ws, sort_ready, stream=None):
+    for t, name in ((lut_in, "lut_in"), (lut_out, "lut_out"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, name)
+    return _check(lib().shm_fit_step(_ptr(lut_in), _ptr(lut_out), _ptr(m), _ptr(v), N, _ptr(dirs), _ptr(target_r),
+                                     _ptr(target_n), Q, float(w_value), step, float(lr_value), float(lr_deriv),
+                                     float(beta1), float(beta2), float(eps), _ptr(ws), ws.numel() * ws.element_size(),
+                                     int(bool(sort_ready)), _stream(stream)))
+
+
 class LutFit:
     """Fits one FP32 TEXEL LUT (face size N) to target radii and normals at
-    fixed directions with Adam, every step in this library's kernels:
-    forward query fused with the loss gradient (value + normal objective,
-    value term weighted by w_value), LUT-only backward (directions sorted
-    once), Adam update.  lut [1, 6, N+2, N+2, 4] is updated in place."""
+    fixed directions with Adam (value + normal objective, value term
+    weighted by w_value; directions sorted by cell once), every step in this
+    library's kernels.
+
+    fused=True: one shm_fit_step kernel per step, alternating two LUT
+    buffers; `lut` is the current one.  fused=False: the three-kernel step
+    (forward query fused with the loss gradient, LUT-only backward, Adam
+    update), updating the given LUT in place."""
 
     def __init__(self, lut, dirs, target_r, target_n, w_value=1.0, lr_value=1e-3, lr_deriv=1e-3, betas=(0.9, 0.999),
-                 eps=1e-8, stream=None):
+                 eps=1e-8, fused=True, stream=None):
         self.N = lut_n(lut)
-        self.lut, self.dirs = lut, dirs
+        self.dirs = dirs
         self.tr, self.tn = target_r.contiguous(), target_n.contiguous()
         self.Q = dirs.shape[0]
         self.w_value, self.lr_value, self.lr_deriv = w_value, lr_value, lr_deriv
         self.betas, self.eps = betas, eps
+        self.fused = fused
         self.bctx = BackwardContext(self.N, 1, dirs, self.Q, stream)
         dev = lut.device
-        self.g = torch.empty((self.Q, 4), device=dev)
-        self.grad = torch.empty_like(lut)
+        self.bufs = [lut, torch.empty_like(lut)] if fused else [lut]
+        self.cur = 0
+        if not fused:
+            self.g = torch.empty((self.Q, 4), device=dev)
+            self.grad = torch.empty_like(lut)
         self.m = torch.zeros_like(lut)
         self.v = torch.zeros_like(lut)
         self.t = 0
 
+    @property
+    def lut(self):
+        return self.bufs[self.cur]
+
     def step(self, stream=None):
         self.t += 1
         N, Q = self.N, self.Q
-        shm_fit_forward_loss_grad(self.lut, N, self.dirs, self.tr, self.tn, Q, self.w_value, self.g, stream)
-        shm_query_backward(self.lut, N, 1, self.dirs, Q, self.g, self.grad, None, self.bctx.ws, True, stream)
-        shm_adam_step(self.lut, self.grad, self.m, self.v, self.lut.numel() // 4, self.t, self.lr_value,
-                      self.lr_deriv, self.betas[0], self.betas[1], self.eps, stream)
+        b1, b2 = self.betas
+        if self.fused:
+            nxt = 1 - self.cur
+            shm_fit_step(self.bufs[self.cur], self.bufs[nxt], self.m, self.v, N, self.dirs, self.tr, self.tn, Q,
+                         self.w_value, self.t, self.lr_value, self.lr_deriv, b1, b2, self.eps, self.bctx.ws, True,
+                         stream)
+            self.cur = nxt
+            return
+        lut = self.lut
+        shm_fit_forward_loss_grad(lut, N, self.dirs, self.tr, self.tn, Q, self.w_value, self.g, stream)
+        shm_query_backward(lut, N, 1, self.dirs, Q, self.g, self.grad, None, self.bctx.ws, True, stream)
+        shm_adam_step(lut, self.grad, self.m, self.v, lut.numel() // 4, self.t, self.lr_value, self.lr_deriv, b1, b2,
+                      self.eps, stream)
 
 
 def mesh_radial_depth(verts, tris, center, dirs, stream=None):

@@ -74,6 +74,9 @@ int launch_adam(float* p, const float* g, float* m, float* v, int64_t n4, int64_
                 float lr_deriv, float b1, float b2, float eps, hipStream_t stream);
 int launch_fit_forward_loss_grad(const float* lut, int N, const float* dirs, const float* tr, const float* tn,
                                  int64_t Q, float w_value, float* grad, hipStream_t stream);
+int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
+                    const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
+                    float b2, float eps, void* ws, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
@@ -690,6 +693,42 @@ int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n
     if (!aligned(param, 16) || !aligned(grad, 16) || !aligned(m, 16) || !aligned(v, 16))
         return fail(SHM_ERR_INVALID_ARG, "adam: buffers must be 16-byte aligned");
     return launch_adam(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1, beta2, eps, stream);
+}
+
+static bool ranges_overlap(const void* a, const void* b, size_t bytes)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+int shm_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int32_t N, const float* dirs,
+                 const float* target_r, const float* target_n, int64_t Q, float w_value, int64_t step, float lr_value,
+                 float lr_deriv, float beta1, float beta2, float eps, void* ws, size_t ws_bytes, int32_t sort_ready,
+                 hipStream_t stream)
+{
+    clear_error();
+    int rc = check_bwd(N, 1, Q, ws, ws_bytes);
+    if (rc) return rc;
+    if (!std::isfinite(w_value) || w_value < 0.0f)
+        return fail(SHM_ERR_INVALID_ARG, "fit_step: w_value must be finite and >= 0");
+    if (step < 1) return fail(SHM_ERR_INVALID_ARG, "fit_step: step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) || !std::isfinite(eps) ||
+        !std::isfinite(lr_value) || !std::isfinite(lr_deriv))
+        return fail(SHM_ERR_INVALID_ARG, "fit_step: need 0 <= beta < 1, finite eps > 0 and finite learning rates");
+    if (!lut_in || !lut_out || !m || !v) return fail(SHM_ERR_INVALID_ARG, "fit_step: null LUT or moment buffer");
+    if (Q > 0 && (!dirs || !target_r || !target_n)) return fail(SHM_ERR_INVALID_ARG, "fit_step: null dirs or targets");
+    if (!aligned(lut_in, 16) || !aligned(lut_out, 16) || !aligned(m, 16) || !aligned(v, 16) ||
+        (Q > 0 && (!aligned(dirs, 4) || !aligned(target_r, 4) || !aligned(target_n, 4))))
+        return fail(SHM_ERR_INVALID_ARG, "fit_step: misaligned buffer (LUTs and moments need 16 bytes)");
+    const size_t bytes = (size_t)texel_elems(N) * sizeof(float);
+    const void* bufs[4] = {lut_in, lut_out, m, v};
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+            if (ranges_overlap(bufs[i], bufs[j], bytes))
+                return fail(SHM_ERR_INVALID_ARG, "fit_step: lut_in, lut_out, m and v must not overlap");
+    if (!sort_ready && Q > 0 && (rc = launch_backward_sort(N, 1, dirs, Q, ws, stream)) != SHM_OK) return rc;
+    return launch_fit_step(lut_in, lut_out, m, v, N, dirs, target_r, target_n, Q, w_value, step, lr_value, lr_deriv,
+                           beta1, beta2, eps, ws, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -14,6 +14,7 @@
 // The sort depends only on the directions and is reused while they stay
 // fixed.  Integer atomics appear only in the per-block digit histograms.
 #include "shm_device.hpp"
+#include "shm_fit.hpp"
 #include "shm_internal.hpp"
 
 namespace shm {
@@ -281,7 +282,24 @@ int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
 //     sorted order.
 // Then each texel adds the corner sums of its <= 4 cells in a fixed order.
 // Every sum has a fixed order: the result is deterministic, with no atomics.
+//
+// The fitting step (FIT) is the same pass with two changes: a query lane
+// computes its upstream gradient itself (the forward query of the current
+// LUT and the gradient of the value + normal objective, in place of reading
+// grad_out), and each texel applies the Adam update to its summed gradient
+// instead of writing it.  The updated texels go to a second LUT: a tile's
+// halo queries read texels that neighbouring tiles update.
 // ---------------------------------------------------------------------------
+struct FitArgs {
+    const float* tr;  // [Q] target radii
+    const float* tn;  // [Q][3] target unit normals
+    float w_value, inv_q;
+    float4* lut_out;  // the updated LUT (never the input LUT)
+    float4* m;        // Adam moments, LUT-shaped
+    float4* v;
+    AdamConsts k;
+};
+
 constexpr int BT = 15;                 // texels per tile side: BC * BC = 256 cells, one per lane
 constexpr int BC = BT + 1;             // cells per tile side
 constexpr int BWD_THREADS = 256;
@@ -354,14 +372,16 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <bool LUT, bool DIRS>
+template <bool LUT, bool DIRS, bool FIT>
 __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
                                                            int64_t Q, const float* __restrict__ dirs,
                                                            const float* __restrict__ gout,
                                                            const uint32_t* __restrict__ perm,
                                                            const uint32_t* __restrict__ cs, int tiles_per_face,
-                                                           float* __restrict__ grad_lut, float* __restrict__ grad_dirs)
+                                                           float* __restrict__ grad_lut, float* __restrict__ grad_dirs,
+                                                           FitArgs fa)
 {
+    static_assert(!FIT || (LUT && !DIRS), "the fitting step sums LUT gradients only");
     __shared__ float4 slot[BWD_THREADS][4];  // one query's weights per lane; later the cell sums
     __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
     __shared__ int64_t row_len[BC];          // queries in each cell row's range
@@ -381,7 +401,8 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     // this lane's cell: its segment bounds load beside the row setup
     const int ci = tid % BC, cj = tid / BC;
     const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
-    const bool cell_ok = LUT && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
+    // with no queries the sort wrote no segment starts: every list is empty
+    const bool cell_ok = LUT && Q > 0 && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
     int64_t cs_lo = 0, cs_hi = 0;
     if (cell_ok) {
         const int64_t c = cbase + (int64_t)j0c * C + i0c;
@@ -391,7 +412,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     if (tid < BC) {
         const int j0 = q0 - 1 + tid;
         int64_t a = 0, e = 0;
-        if (j0 >= 0 && j0 <= N) {
+        if (Q > 0 && j0 >= 0 && j0 <= N) {
             const int64_t c0 = cbase + (int64_t)j0 * C;
             a = min((int64_t)cs[c0 + i_lo], Q);
             e = min(max((int64_t)cs[c0 + i_hi + 1], a), Q);
@@ -438,13 +459,29 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         pos = pos < 0 ? 0 : (pos >= Q ? Q - 1 : pos);
         return (int64_t)perm[pos];
     };
+    // the upstream gradient of query q, or for the fitting step its targets
+    // (R*, n*), from which the lane computes the upstream gradient
+    auto upstream_in = [&](int64_t q) -> float4 {
+        if constexpr (FIT) return make_float4(fa.tr[q], fa.tn[3 * q], fa.tn[3 * q + 1], fa.tn[3 * q + 2]);
+        else return reinterpret_cast<const float4*>(gout)[q];
+    };
+    const float* lut_obj = lut + obj * lut_elems;
     // software pipeline: round k + 1's index, direction and upstream
     // gradient loads are in flight while round k computes and reduces
-    int r_cur;
-    bool v_cur;
-    int64_t q_cur = query_at(tid, r_cur, v_cur);
-    float x = dirs[3 * q_cur], y = dirs[3 * q_cur + 1], z = dirs[3 * q_cur + 2];
-    float4 gq = reinterpret_cast<const float4*>(gout)[q_cur];
+    // (an empty list, as with no queries at all, loads nothing: its clamped
+    // position would not name a query)
+    int r_cur = 0;
+    bool v_cur = false;
+    int64_t q_cur = 0;
+    float x = 0.0f, y = 0.0f, z = 0.0f;
+    float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (total > 0) {
+        q_cur = query_at(tid, r_cur, v_cur);
+        x = dirs[3 * q_cur];
+        y = dirs[3 * q_cur + 1];
+        z = dirs[3 * q_cur + 2];
+        gq = upstream_in(q_cur);
+    }
     for (int64_t base = 0; base < total; base += BWD_THREADS) {
         int r_next;
         bool v_next;
@@ -453,6 +490,11 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         // slot; the reduction below reads no other slot
         if (v_cur) {
             const Loc L = locate(x, y, z, N);  // the cell of row r_cur (keys come from the same decision)
+            if constexpr (FIT) {
+                // the forward query and the objective's gradient with respect
+                // to its output
+                gq = loss_grad_one(fit_forward(lut_obj, N, L), x, y, z, gq.x, gq.y, gq.z, gq.w, fa.w_value, fa.inv_q);
+            }
             if constexpr (LUT) {
                 const float A = L.a, B = L.b;
                 const float gS = gq.y * (S.x - A * M.x) + gq.z * (S.y - A * M.y) + gq.w * (S.z - A * M.z);
@@ -464,7 +506,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
                 for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
             }
             if (DIRS && L.i0 >= p0 && r_cur >= 1) {  // the tile owns the cell
-                const float3 gd = dirs_grad(lut + obj * lut_elems, N, L, gq, M, S, T, x, y, z);
+                const float3 gd = dirs_grad(lut_obj, N, L, gq, M, S, T, x, y, z);
                 grad_dirs[3 * q_cur] = gd.x;
                 grad_dirs[3 * q_cur + 1] = gd.y;
                 grad_dirs[3 * q_cur + 2] = gd.z;
@@ -474,7 +516,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         x = dirs[3 * q_next];
         y = dirs[3 * q_next + 1];
         z = dirs[3 * q_next + 2];
-        gq = reinterpret_cast<const float4*>(gout)[q_next];
+        gq = upstream_in(q_next);
         q_cur = q_next;
         r_cur = r_next;
         v_cur = v_next;
@@ -495,15 +537,25 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         }
     }
     if constexpr (!LUT) return;
+    // the fitting step's parameters and moments of this lane's texel load
+    // while the cell sums are exchanged
+    const int t_x = tid % BT, t_y = tid / BT, t_p = p0 + t_x, t_q = q0 + t_y;
+    const bool t_ok = tid < BT * BT && t_p <= N + 1 && t_q <= N + 1;
+    const int64_t t_i = (fo * P + t_q) * (int64_t)P + t_p;
+    float4 pp, mm, vv;
+    if (FIT && t_ok) {
+        pp = reinterpret_cast<const float4*>(lut)[t_i];
+        mm = fa.m[t_i];
+        vv = fa.v[t_i];
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) slot[tid][k] = acc[k];
     lds_barrier();
     // texel (p0 + tx, q0 + ty) is corner (1,1) of cell (tx, ty), (0,1) of
     // (tx+1, ty), (1,0) of (tx, ty+1) and (0,0) of (tx+1, ty+1) in tile cells
-    for (int t = tid; t < BT * BT; t += BWD_THREADS) {
-        const int tx = t % BT, ty = t / BT;
-        const int p = p0 + tx, q = q0 + ty;
-        if (p > N + 1 || q > N + 1) continue;
+    static_assert(BT * BT <= BWD_THREADS, "one texel per lane");
+    if (t_ok) {
+        const int tx = t_x, ty = t_y;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int dj = 1; dj >= 0; --dj)
@@ -515,7 +567,14 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
                 a.z += v.z;
                 a.w += v.w;
             }
-        reinterpret_cast<float4*>(grad_lut)[(fo * P + q) * (int64_t)P + p] = a;
+        if constexpr (FIT) {
+            adam_texel(pp, a, mm, vv, fa.k);
+            fa.lut_out[t_i] = pp;
+            fa.m[t_i] = mm;
+            fa.v[t_i] = vv;
+        } else {
+            reinterpret_cast<float4*>(grad_lut)[t_i] = a;
+        }
     }
 }
 
@@ -561,8 +620,8 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     const int64_t tiles = n_obj * 6ll * tpf * tpf;
     if (tiles > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "backward: too many tiles for one launch");
 #define SHM_B(A, B)                                                                                                  \
-    hipLaunchKernelGGL((k_bwd_fused<A, B>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,             \
-                       texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, grad_lut, grad_dirs)
+    hipLaunchKernelGGL((k_bwd_fused<A, B, false>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,      \
+                       texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, grad_lut, grad_dirs, FitArgs{})
     if (grad_lut && grad_dirs) SHM_B(true, true);
     else if (grad_lut) SHM_B(true, false);
     else SHM_B(false, true);
@@ -573,6 +632,32 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
                            W.Q, grad_dirs);
         SHM_LAUNCH_CHECK();
     }
+    return SHM_OK;
+}
+
+int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
+                    const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
+                    float b2, float eps, void* ws, hipStream_t stream)
+{
+    const BwdLayout W = bwd_layout(N, 1, Q);
+    char* base = reinterpret_cast<char*>(ws);
+    const uint32_t* cs = reinterpret_cast<const uint32_t*>(base + W.cstart);
+    const uint32_t* perm = reinterpret_cast<const uint32_t*>(base + ((W.passes & 1) ? W.vals1 : W.vals0));
+    const int tpf = (N + 2 + BT - 1) / BT;
+    const int64_t tiles = 6ll * tpf * tpf;
+    FitArgs fa;
+    fa.tr = tr;
+    fa.tn = tn;
+    fa.w_value = w_value;
+    fa.inv_q = Q > 0 ? (float)(1.0 / (double)Q) : 0.0f;
+    fa.lut_out = reinterpret_cast<float4*>(lut_out);
+    fa.m = reinterpret_cast<float4*>(m);
+    fa.v = reinterpret_cast<float4*>(v);
+    fa.k = adam_consts(step, lr_value, lr_deriv, b1, b2, eps);
+    hipLaunchKernelGGL((k_bwd_fused<true, false, true>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut_in,
+                       N, texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf, (float*)nullptr,
+                       (float*)nullptr, fa);
+    SHM_LAUNCH_CHECK();
     return SHM_OK;
 }
 

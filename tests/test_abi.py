@@ -195,6 +195,38 @@ def test_fit_validation():
     assert ad(p, p, mis, p, 10, 1, 1e-3, 1e-3, *ok, None) == shm.SHM_ERR_INVALID_ARG
 
 
+def test_fit_step_validation():
+    """The fused fitting step refuses, before any launch: overlapping LUT and
+    moment buffers (the update goes to a second LUT), a short or misaligned
+    workspace, bad hyper-parameters and null or misaligned buffers."""
+    N, Q = 8, 1000
+    lut_bytes = 6 * (N + 2) ** 2 * 16
+    a, b, m, v = (ctypes.c_void_p(k << 20) for k in (1, 2, 3, 4))
+    ws_bytes = shm.lib().shm_backward_workspace(N, 1, Q)
+    ws = ctypes.c_void_p(16 << 20)
+    d = ctypes.c_void_p(32 << 20)
+    ok = (1e-3, 1e-3, 0.9, 0.999, 1e-8)
+    fs = lambda lin, lout, mm, vv, n=N, q=Q, wv=1.0, step=1, hp=ok, w=ws, wb=ws_bytes, dd=d: call(
+        "shm_fit_step", lin, lout, mm, vv, n, dd, dd, dd, q, wv, step, *hp, w, wb, 1, None)
+    assert fs(a, a, m, v) == shm.SHM_ERR_INVALID_ARG                                   # in place
+    assert fs(a, ctypes.c_void_p((1 << 20) + lut_bytes - 16), m, v) == shm.SHM_ERR_INVALID_ARG  # overlap
+    assert fs(a, b, m, m) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, a, v) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, wb=ws_bytes - 1) == shm.SHM_ERR_WORKSPACE
+    assert fs(a, b, m, v, w=ctypes.c_void_p((16 << 20) + 16)) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, n=0) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, q=-1) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, wv=float("nan")) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, step=0) == shm.SHM_ERR_INVALID_ARG
+    for hp in ((1e-3, 1e-3, 1.0, 0.999, 1e-8), (1e-3, 1e-3, 0.9, 0.999, 0.0), (float("inf"), 1e-3, 0.9, 0.999, 1e-8)):
+        assert fs(a, b, m, v, hp=hp) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, None, m, v) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, dd=None) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, ctypes.c_void_p((3 << 20) + 4), v) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, wv=-1.0) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, m) == shm.SHM_ERR_INVALID_ARG and "overlap" in shm.shm_last_error()
+
+
 def test_size_products_do_not_overflow():
     """Object x query counts whose product would overflow 64 bits are
     refused on the host (no launch)."""

@@ -96,9 +96,11 @@ def test_adam_matches_torch_adam():
         assert np.abs(got - ref).max() <= 1e-6 * (1.0 + np.abs(ref).max()), (t, np.abs(got - ref).max())
 
 
-def test_native_fit_matches_torch_loop():
+@pytest.mark.parametrize("fused", [True, False])
+def test_native_fit_matches_torch_loop(fused):
     """20 steps at N = 16 on 30,000 directions sorted by cell: the native
-    loop and the autograd + torch.optim.Adam loop end at the same LUT."""
+    loop (one fused kernel per step, or the three-kernel step) and the
+    autograd + torch.optim.Adam loop end at the same LUT."""
     N, Q = 16, 30000
     r = workloads.rng_for(4)
     dirs = torch.as_tensor(workloads.uniform_dirs(Q, r)).to(DEV)
@@ -112,7 +114,7 @@ def test_native_fit_matches_torch_loop():
     lut0 = torch.zeros((1, 6, N + 2, N + 2, 4), device=DEV)
     lut0[..., 0] = 1.0
     w_value, lr_v, lr_d, steps = 1000.0, 1e-3, 3e-4, 20
-    fit = shm.LutFit(lut0.clone(), dirs, tv, tn, w_value=w_value, lr_value=lr_v, lr_deriv=lr_d)
+    fit = shm.LutFit(lut0.clone(), dirs, tv, tn, w_value=w_value, lr_value=lr_v, lr_deriv=lr_d, fused=fused)
     for _ in range(steps):
         fit.step()
     val = lut0[..., :1].clone().requires_grad_(True)
@@ -135,3 +137,64 @@ def test_native_fit_matches_torch_loop():
     d = (fit.lut - ref).abs().max().item()
     assert d <= 1e-4 * ref.abs().max().item(), d
     assert losses[-1] < 0.7 * losses[0]  # and the fit makes progress
+
+
+def fit_problem(N, Q, seed, zero=()):
+    """A random LUT, Q unsorted directions (some zero) and fBm targets."""
+    rng = np.random.default_rng(seed)
+    lut = torch.as_tensor(workloads.random_lut(N, rng)).to(DEV)[None].contiguous()
+    d = workloads.uniform_dirs(Q, rng)
+    d[list(zero)] = 0.0
+    dirs = torch.as_tensor(d).to(DEV)
+    at = d.copy()
+    at[list(zero)] = (0.0, 0.0, 1.0)  # targets of the zero directions: any finite values
+    at = torch.as_tensor(at).to(DEV)
+    tv, tg = workloads.fbm_target_torch(at, seed=seed)
+    w = at / at.norm(dim=1, keepdim=True)
+    tn = tv.float()[:, None] * w - tg.float()
+    tn = tn / tn.norm(dim=1, keepdim=True)
+    return lut, dirs, tv.float().contiguous(), tn.contiguous()
+
+
+@pytest.mark.parametrize("N,Q", [(16, 20011), (37, 50000)])
+def test_fused_step_matches_three_kernel_step(N, Q):
+    """The one-kernel fitting step against the three-kernel step (forward +
+    loss gradient, LUT-only backward, Adam) from the same LUT, over 4 steps:
+    unsorted directions with zero ones among them, tiles that overhang the
+    face (N + 2 not a multiple of 15).  Same sums in the same order, so the
+    moments agree to rounding and the parameters to far below an Adam step."""
+    lut, dirs, tv, tn = fit_problem(N, Q, seed=N, zero=(3, Q - 1))
+    a = shm.LutFit(lut.clone(), dirs, tv, tn, w_value=30.0, lr_value=1e-3, lr_deriv=3e-4, fused=True)
+    b = shm.LutFit(lut.clone(), dirs, tv, tn, w_value=30.0, lr_value=1e-3, lr_deriv=3e-4, fused=False)
+    for step in range(1, 5):
+        a.step()
+        b.step()
+        torch.cuda.synchronize()
+        same = torch.equal(a.lut, b.lut) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+        dm = (a.m - b.m).abs().max().item()
+        dp = (a.lut - b.lut).abs().max().item()
+        print(f"N={N} step {step}: bitwise {same}, max |dm| {dm:.3g} of {b.m.abs().max().item():.3g}, max |dp| {dp:.3g}")
+        assert dm <= 1e-5 * b.m.abs().max().item(), (step, dm)
+        assert dp <= 1e-6, (step, dp)
+        assert (b.lut != lut).float().mean().item() > 0.99  # nearly every texel moved
+    assert a.lut.data_ptr() != b.lut.data_ptr() and a.lut.data_ptr() == a.bufs[0].data_ptr()  # 4 steps: back to buffer 0
+
+
+def test_fused_step_without_queries_is_adam_with_zero_gradient():
+    """Q = 0: no query list, the gradient is zero, Adam still moves the
+    parameters by its moments."""
+    N = 20
+    rng = np.random.default_rng(2)
+    p0 = torch.as_tensor(workloads.random_lut(N, rng)).to(DEV)[None].contiguous()
+    m0 = torch.as_tensor(rng.standard_normal(p0.shape).astype(np.float32) * 1e-3).to(DEV)
+    v0 = torch.as_tensor(rng.uniform(0, 1e-6, p0.shape).astype(np.float32)).to(DEV)
+    empty = torch.empty((0, 3), device=DEV)
+    ws = torch.empty(max(shm.shm_backward_workspace(N, 1, 0), 256), dtype=torch.uint8, device=DEV)
+    out, m1, v1 = torch.full_like(p0, float("nan")), m0.clone(), v0.clone()
+    shm.shm_fit_step(p0, out, m1, v1, N, empty, empty, empty, 0, 1.0, 3, 1e-3, 3e-4, 0.9, 0.999, 1e-8, ws, False)
+    p2, m2, v2 = p0.clone(), m0.clone(), v0.clone()
+    shm.shm_adam_step(p2, torch.zeros_like(p0), m2, v2, p0.numel() // 4, 3, 1e-3, 3e-4)
+    torch.cuda.synchronize()
+    print("bitwise", torch.equal(out, p2), torch.equal(m1, m2), torch.equal(v1, v2))
+    for x, y in ((out, p2), (m1, m2), (v1, v2)):
+        assert (x - y).abs().max().item() <= 1e-7 * (1.0 + y.abs().max().item())
