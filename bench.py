@@ -162,6 +162,10 @@ def main():
         bctx.backward(lut4, torch.ones((Qb, 4), device=DEV))
         # one forward of the fit (texel layout, sorted directions, N = 512)
         shm.shm_query_value_grad(lut4, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, Nb, 1, d4, Qb, torch.empty((Qb, 4), device=DEV))
+        # one fused fitting step (same directions; unit-sphere targets)
+        lut4[..., 0] = 1.0
+        tn4 = (d4 / d4.norm(dim=1, keepdim=True)).contiguous()
+        shm.LutFit(lut4, d4, torch.full((Qb,), 1.1, device=DEV), tn4).step()
         # one trace of the bump impostor (N = 256, 1920 x 1080, FP32)
         mu, amp, width = workloads.bump_params(workloads.rng_for(3))
         md = shm.margin_dirs(256).cpu().numpy().reshape(-1, 3)

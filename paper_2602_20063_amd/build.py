@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshm.so")
 SOURCES = ["shm_api.hip", "shm_query.hip", "shm_bake.hip", "shm_backward.hip", "shm_trace.hip", "shm_baseline.hip",
            "shm_mip.hip", "shm_render.hip", "shm_mesh.hip", "shm_fit.hip"]
-HEADERS = ["shm_device.hpp", "shm_internal.hpp", os.path.join("..", "..", "include", "shm.h")]
+HEADERS = ["shm_device.hpp", "shm_fit.hpp", "shm_internal.hpp", os.path.join("..", "..", "include", "shm.h")]
 
 FLAGS = [
     "--offload-arch=gfx950",
