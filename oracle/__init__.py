@@ -28,6 +28,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "shm_oracle.c")
 _LIB = os.path.join(_HERE, "_shm_oracle.so")
+# a sanitizer-instrumented build of the same source, loaded in place of the
+# default one by the sanitizer test
+_LIB_OVERRIDE = os.environ.get("SHM_ORACLE_LIB")
 
 # -ffp-contract=off: no fused multiply-add anywhere, so the FP32 cell decision
 # in locate() is the documented sequence of correctly rounded operations.
@@ -49,9 +52,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        _lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            _lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB):
+                build()
+            _lib = ctypes.CDLL(_LIB)
     return _lib
 
 

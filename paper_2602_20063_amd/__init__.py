@@ -16,6 +16,11 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshm.so")
+# a host-only, sanitizer-instrumented build of the same sources
+# (build.build_host_sanitized) can be loaded in its place for the host-side
+# argument checks; it holds no device code
+if os.environ.get("SHM_LIBRARY"):
+    LIB_PATH = os.environ["SHM_LIBRARY"]
 
 SHM_OK, SHM_ERR_INVALID_ARG, SHM_ERR_UNSUPPORTED, SHM_ERR_WORKSPACE, SHM_ERR_HIP = range(5)
 SHM_F32, SHM_F16 = 0, 1
