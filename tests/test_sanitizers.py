@@ -72,3 +72,25 @@ def test_abi_checks_under_asan_and_ubsan(tmp_path):
                           os.path.join(ROOT, "tests", "test_abi.py")], 900)
     assert " passed" in out and "failed" not in out
     assert shm.lib()._name != lib  # this process keeps the ordinary build
+
+
+def test_planted_out_of_bounds_read_is_reported(tmp_path):
+    """Negative control: a copy of the oracle whose corner gather reads one
+    texel row and column too far is built the same way; ASan reports a
+    heap-buffer overflow in that gather on the first pin that reaches it."""
+    src = open(oracle._SRC).read()
+    good = "lut + texel_index(N, face, i0 + i, j0 + j)"
+    assert src.count(good) == 1
+    bad = tmp_path / "shm_oracle_planted.c"
+    bad.write_text(src.replace(good, "lut + texel_index(N, face, i0 + i + 1, j0 + j + 1)"))
+    lib = str(tmp_path / "planted.so")
+    flags = [f for f in oracle.CFLAGS if f != "-O2"]
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", *flags, "-o", lib, str(bad), "-lm"])
+    env = dict(os.environ, **SAN_ENV, LD_PRELOAD=runtime("gcc", "libasan.so"), SHM_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-s", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode != 0
+    assert "ERROR: AddressSanitizer: heap-buffer-overflow" in out and "gather_corners" in out, out[-3000:]
