@@ -240,3 +240,21 @@ def test_size_products_do_not_overflow():
     assert call("shm_bake_fd", p, 8, huge, 0, p, None) == shm.SHM_ERR_UNSUPPORTED
     assert call("shm_lut_to_cells", p, 0, 8, huge, p, None) == shm.SHM_ERR_UNSUPPORTED
     assert call("shm_bake_sh_lut", p, 4, 8, huge, 0, p, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
+
+
+def test_hip_error_is_reported_without_a_gpu():
+    """With no GPU visible, calls whose arguments pass the host checks reach
+    a launch (or a plan's device allocation), which the HIP runtime refuses:
+    the entry point returns SHM_ERR_HIP and shm_last_error names the failing
+    call.  Never run where a GPU is visible (the pointers are not real)."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible: this check must not launch on it")
+    p = ctypes.c_void_p(1 << 20)
+    assert call("shm_query_value_grad", p, 0, 0, 8, 1, p, 64, p, None, None) == shm.SHM_ERR_HIP
+    assert "no ROCm-capable device" in shm.shm_last_error() or "launch" in shm.shm_last_error()
+    assert call("shm_lut_rmax", p, 0, 8, 1, p, None) == shm.SHM_ERR_HIP
+    assert shm.shm_last_error()
+    # a valid call with nothing to do still succeeds: the error is not sticky
+    assert call("shm_query_value_grad", p, 0, 0, 8, 1, p, 0, p, None, None) == shm.SHM_OK
+    assert shm.shm_last_error() == ""
