@@ -137,6 +137,14 @@ SHM_API int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, in
 SHM_API int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
                          int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
 
+/* Counter of bad queries: adds to *count (one device uint64, zeroed by the
+ * caller) the number of the Q directions dirs[Q][3] that every query entry
+ * point answers with NaN: a zero vector or a NaN or Inf component.  The
+ * directions need not be unit length (any nonzero finite vector is valid).
+ * Integer atomics only (one per wavefront); no memset, so it may be
+ * captured in a graph beside the query. */
+SHM_API int shm_count_invalid(const float* dirs, int64_t Q, unsigned long long* count, hipStream_t stream);
+
 /* Query of the rendered radius (Sec. 3.1) for a user scale s > 0:
  * R = s r for a nonnegative function; with SHM_SIGNED, R = s |r| and
  * grad R = s sign(r) grad r (chain rule of Sec. 3.4, after Eq. 10; sign(0)

@@ -103,6 +103,7 @@ SIGNATURES = {
     "shm_fit_forward_loss_grad": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _VP, _VP]),
     "shm_adam_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, _VP]),
+    "shm_count_invalid": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
     "shm_fit_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _I64,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     _VP, ctypes.c_size_t, _I32, _VP]),
@@ -271,6 +272,19 @@ def shm_fit_forward_loss_grad(lut, N, dirs, target_r, target_n, Q, w_value, grad
 def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     return _check(lib().shm_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), n4, step, float(lr_value),
                                       float(lr_deriv), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def shm_count_invalid(dirs, Q, count, stream=None):
+    _need(count, torch.int64, "count")
+    return _check(lib().shm_count_invalid(_ptr(dirs), Q, _ptr(count), _stream(stream)))
+
+
+def count_invalid(dirs, stream=None):
+    """Number of directions every query answers with NaN (zero vector, NaN or
+    Inf component); synchronises."""
+    c = torch.zeros(1, dtype=torch.int64, device=dirs.device)
+    shm_count_invalid(dirs.contiguous(), dirs.shape[0], c, stream)
+    return int(c.item())
 
 
 def shm_fit_step(lut_in, lut_out, m, v, N, dirs, target_r, target_n, Q, w_value, step, lr_value, lr_deriv,

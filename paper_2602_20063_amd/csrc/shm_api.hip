@@ -74,6 +74,7 @@ int launch_adam(float* p, const float* g, float* m, float* v, int64_t n4, int64_
                 float lr_deriv, float b1, float b2, float eps, hipStream_t stream);
 int launch_fit_forward_loss_grad(const float* lut, int N, const float* dirs, const float* tr, const float* tn,
                                  int64_t Q, float w_value, float* grad, hipStream_t stream);
+int launch_count_invalid(const float* dirs, int64_t Q, unsigned long long* count, hipStream_t stream);
 int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
                     const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
                     float b2, float eps, void* ws, hipStream_t stream);
@@ -693,6 +694,16 @@ int shm_adam_step(float* param, const float* grad, float* m, float* v, int64_t n
     if (!aligned(param, 16) || !aligned(grad, 16) || !aligned(m, 16) || !aligned(v, 16))
         return fail(SHM_ERR_INVALID_ARG, "adam: buffers must be 16-byte aligned");
     return launch_adam(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1, beta2, eps, stream);
+}
+
+int shm_count_invalid(const float* dirs, int64_t Q, unsigned long long* count, hipStream_t stream)
+{
+    clear_error();
+    if (Q < 0) return fail(SHM_ERR_INVALID_ARG, "count_invalid: negative query count");
+    if (Q > INT64_MAX / 12) return fail(SHM_ERR_UNSUPPORTED, "count_invalid: too many queries");
+    if (!count || !aligned(count, 8)) return fail(SHM_ERR_INVALID_ARG, "count_invalid: count must be an 8-byte aligned device pointer");
+    if (Q > 0 && (!dirs || !aligned(dirs, 4))) return fail(SHM_ERR_INVALID_ARG, "count_invalid: null or misaligned dirs");
+    return launch_count_invalid(dirs, Q, count, stream);
 }
 
 static bool ranges_overlap(const void* a, const void* b, size_t bytes)

@@ -65,6 +65,28 @@ struct Loc {
 // (the residual sc - a ma is still exact), but a direction within an ulp of
 // a cell boundary may be given to the neighbouring cell, whose patch agrees
 // there by C1 continuity; only the ray-casting iterations use it.
+// Power-of-two prescale for a direction with largest component ma: 2^100
+// below 2^-60 and 2^-100 above 2^60, else 1, so that the scaled ma lies in
+// [2^-49, 2^40] for every finite nonzero ma (subnormal ones included) and its
+// square in the normal range.  Scaling up is exact; scaling down may round
+// components more than 2^24 times smaller than ma, below FP32 resolution of
+// the unit vector.
+__device__ __forceinline__ float dir_prescale(float ma)
+{
+    return ma < 0x1p-60f ? 0x1p100f : (ma > 0x1p60f ? 0x1p-100f : 1.0f);
+}
+
+// The unit vector d/|d| of a nonzero finite d of any magnitude.
+__device__ __forceinline__ float3 unit_dir(float x, float y, float z)
+{
+    const float k = dir_prescale(fmaxf(fabsf(x), fmaxf(fabsf(y), fabsf(z))));
+    x *= k;
+    y *= k;
+    z *= k;
+    const float il = rsqrtf(x * x + y * y + z * z);
+    return make_float3(x * il, y * il, z * il);
+}
+
 template <bool FAST>
 __device__ __forceinline__ Loc locate_t(float x, float y, float z, int N)
 {
@@ -95,6 +117,15 @@ __device__ __forceinline__ Loc locate_t(float x, float y, float z, int N)
         tc = -y;
     }
     const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && (ma > 0.0f);
+    if (!FAST) {
+        // a major axis below 2^-64 (subnormal ones included) is scaled by
+        // 2^64 first, exactly: a = sc/ma is the same correctly rounded
+        // quotient, and 1/ma in the residual below cannot overflow
+        const float k = ma < 0x1p-64f ? 0x1p64f : 1.0f;
+        sc *= k;
+        tc *= k;
+        ma *= k;
+    }
     const float rma = FAST ? __builtin_amdgcn_rcpf(ma) : 0.0f;
     const float a = FAST ? sc * rma : sc / ma;
     const float b = FAST ? tc * rma : tc / ma;
@@ -348,8 +379,8 @@ __device__ __forceinline__ float3 transport(int face, float a, float b, float ru
 // Eq. (10)
 __device__ __forceinline__ float3 normal_of(float R, float x, float y, float z, float3 g)
 {
-    const float il = rsqrtf(x * x + y * y + z * z);
-    const float mx = R * x * il - g.x, my = R * y * il - g.y, mz = R * z * il - g.z;
+    const float3 w = unit_dir(x, y, z);
+    const float mx = R * w.x - g.x, my = R * w.y - g.y, mz = R * w.z - g.z;
     const float in = rsqrtf(mx * mx + my * my + mz * mz);
     return make_float3(mx * in, my * in, mz * in);
 }

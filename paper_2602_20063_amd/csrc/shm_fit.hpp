@@ -21,8 +21,8 @@ namespace shm {
 __device__ __forceinline__ float4 loss_grad_one(float4 o, float dx, float dy, float dz, float tr, float tnx,
                                                 float tny, float tnz, float w_value, float inv_q)
 {
-    const float il = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
-    const float wx = dx * il, wy = dy * il, wz = dz * il;
+    const float3 w = unit_dir(dx, dy, dz);
+    const float wx = w.x, wy = w.y, wz = w.z;
     const float mx = o.x * wx - o.y, my = o.x * wy - o.z, mz = o.x * wz - o.w;
     const float ml2 = mx * mx + my * my + mz * mz;
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);

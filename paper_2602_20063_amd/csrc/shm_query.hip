@@ -246,4 +246,30 @@ int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* 
     return SHM_OK;
 }
 
+// Bad-query counter: the validity test of locate() (finite components, a
+// nonzero major axis) per direction, summed per wavefront by ballot and
+// added with one 64-bit integer atomic.
+__global__ void k_count_invalid(const float* __restrict__ dirs, int64_t Q, unsigned long long* __restrict__ count)
+{
+    int n = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Q; q += stride) {
+        const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+        const float ma = fmaxf(fabsf(x), fmaxf(fabsf(y), fabsf(z)));
+        n += (isfinite(x) && isfinite(y) && isfinite(z) && ma > 0.0f) ? 0 : 1;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) n += __shfl_xor(n, o, 64);
+    if ((threadIdx.x & 63) == 0 && n > 0) atomicAdd(count, (unsigned long long)n);
+}
+
+int launch_count_invalid(const float* dirs, int64_t Q, unsigned long long* count, hipStream_t stream)
+{
+    if (Q == 0) return SHM_OK;
+    const int64_t blocks = std::min<int64_t>((Q + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_count_invalid, dim3((unsigned)blocks), dim3(256), 0, stream, dirs, Q, count);
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
 }  // namespace shm

@@ -242,6 +242,17 @@ def test_size_products_do_not_overflow():
     assert call("shm_bake_sh_lut", p, 4, 8, huge, 0, p, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
 
 
+def test_count_invalid_validation():
+    p = ctypes.c_void_p(256)
+    ci = lambda *a: call("shm_count_invalid", *a)
+    assert ci(p, 0, p, None) == shm.SHM_OK             # nothing to count
+    assert ci(p, -1, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert ci(p, 10, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert ci(p, 10, ctypes.c_void_p(260), None) == shm.SHM_ERR_INVALID_ARG   # count not 8-byte aligned
+    assert ci(None, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert ci(p, 1 << 62, p, None) == shm.SHM_ERR_UNSUPPORTED
+
+
 def test_hip_error_is_reported_without_a_gpu():
     """With no GPU visible, calls whose arguments pass the host checks reach
     a launch (or a plan's device allocation), which the HIP runtime refuses:

@@ -36,11 +36,15 @@ def gpu_query(lut32, dirs, layout=shm.SHM_LAYOUT_TEXEL, dtype=torch.float32, q_p
 
 def edge_dirs():
     """Axis directions, face ties, sign ties, -0, cube corners, directions
-    landing exactly on cell boundaries and invalid directions."""
+    landing exactly on cell boundaries, subnormal to huge magnitudes and
+    invalid directions."""
     d = [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
          [1, 1, 0], [1, -1, 0], [-1, 1, 1], [1, 1, 1], [-1, -1, -1], [0, 1, 1], [0, -1, -1],
          [-0.0, 0.0, 1.0], [1, -0.0, -0.0], [0.5, 0.5, 0.5], [3, 1, 2], [1e-30, 0, 0],
-         [1e30, 1e29, -1e29], [0, 0, 0], [np.nan, 1, 0], [np.inf, 0, 0]]
+         [1e30, 1e29, -1e29],
+         # subnormal, tiny and huge magnitudes: valid, the same directions
+         [1e-42, 3e-43, -5e-43], [2e-39, -1e-39, 0], [1e-20, -1e-20, 5e-21], [3e38, -1e38, 2e38],
+         [0, 0, 0], [np.nan, 1, 0], [np.inf, 0, 0]]
     return np.array(d, np.float32)
 
 
@@ -171,3 +175,53 @@ def test_cfg2_shape_reduced_and_sampled_full():
     ref = oracle.query_objects(lut.reshape(-1), np.arange(n) * (lut[0].size // 4), [32] * n, np.arange(n) * 256,
                                [256] * n, dirs)
     check_value_grad(out, ref, "cfg2 reduced")
+
+
+def test_count_invalid_matches_the_nan_rows():
+    """The bad-query counter counts exactly the directions the query answers
+    with NaN: zero vectors (+-0), NaN or Inf components; tiny, huge and
+    subnormal nonzero vectors are valid.  Counts add up across calls."""
+    rng = np.random.default_rng(13)
+    Q = 100003
+    d = workloads.uniform_dirs(Q, rng) * rng.uniform(1e-3, 1e3, (Q, 1)).astype(np.float32)
+    k = rng.choice(Q, 600, replace=False)
+    d[k[:100]] = 0.0
+    d[k[100:150]] = -0.0
+    d[k[150:250], rng.integers(0, 3, 100)] = np.nan
+    d[k[250:350], rng.integers(0, 3, 100)] = np.inf
+    d[k[350:400], rng.integers(0, 3, 50)] = -np.inf
+    d[k[400:450]] = np.float32(1e-42)           # subnormal, valid
+    d[k[450:500]] = np.float32(3e38)            # huge, valid
+    d[k[500:600]] = d[k[500:600]] * np.float32(1e-30)
+    ref = int((~(np.isfinite(d).all(axis=1) & (np.abs(d).max(axis=1) > 0))).sum())
+    assert ref == 400  # 150 zero vectors, 100 NaN, 150 Inf
+    dirs = torch.as_tensor(d).to(DEV)
+    assert shm.count_invalid(dirs) == ref
+    c = torch.zeros(1, dtype=torch.int64, device=DEV)
+    shm.shm_count_invalid(dirs, Q, c)
+    shm.shm_count_invalid(dirs[:1000].contiguous(), 1000, c)
+    lut = torch.as_tensor(workloads.random_lut(8, rng)).to(DEV)[None].contiguous()
+    out = torch.empty((Q, 4), device=DEV)
+    nrm = torch.empty((Q, 3), device=DEV)
+    shm.shm_query_value_grad(lut, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, 8, 1, dirs, Q, out, nrm)
+    nan_rows = torch.isnan(out).all(dim=1)
+    assert int(nan_rows.sum().item()) == ref
+    assert torch.isfinite(out[~nan_rows]).all()
+    assert torch.isnan(nrm[nan_rows]).all() and torch.isfinite(nrm[~nan_rows]).all()
+    assert (nrm[~nan_rows].norm(dim=1) - 1).abs().max().item() < 1e-5
+    # a direction and its copies scaled by 2^e, -140 <= e <= 120, give the
+    # same bits: components on a 2^-9 grid stay exact down to subnormals
+    q = np.round(workloads.uniform_dirs(4096, rng) * 512.0) / 512.0
+    q = q[np.abs(q).max(axis=1) > 0].astype(np.float32)
+    base = torch.as_tensor(q).to(DEV)
+    n = base.shape[0]
+    o1 = torch.empty((n, 4), device=DEV)
+    shm.shm_query_value_grad(lut, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, 8, 1, base, n, o1)
+    assert torch.isfinite(o1).all()
+    for e in (-140, -130, -100, -64, -30, 30, 64, 100, 120):
+        sc = (q.astype(np.float64) * 2.0 ** e).astype(np.float32)
+        assert (sc.astype(np.float64) * 2.0 ** -e == q).all()  # exact
+        o2 = torch.empty((n, 4), device=DEV)
+        shm.shm_query_value_grad(lut, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, 8, 1, torch.as_tensor(sc).to(DEV), n, o2)
+        assert torch.equal(o1.view(torch.int32), o2.view(torch.int32)), e
+    assert c.item() == ref + int((~(np.isfinite(d[:1000]).all(axis=1) & (np.abs(d[:1000]).max(axis=1) > 0))).sum())
