@@ -103,6 +103,7 @@ struct shm_plan {
     shm_object* d_objs = nullptr;
     WorkItem* d_items = nullptr;
     int64_t items_cap = 0, n_items = 0;
+    XcdSplit split{};
     shm_launch_shape shape{256, 2, 2048, 8};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -125,6 +126,19 @@ static int plan_build_items(shm_plan* P, hipStream_t stream)
         }
     }
     const int64_t n = (int64_t)items.size();
+    // slice boundaries: slice s starts at the first item whose preceding
+    // queries reach s/8 of the total
+    int64_t total = 0;
+    for (const WorkItem& w : items) total += w.n;
+    XcdSplit sp{};
+    int64_t before = 0;
+    int s = 1;
+    for (int64_t i = 0; i < n && s < 8; ++i) {
+        while (s < 8 && before * 8 >= total * s) sp.b[s++] = i;
+        before += items[i].n;
+    }
+    while (s < 8) sp.b[s++] = n;
+    sp.b[8] = n;
     // a launch issued earlier (on any stream) may still read the old list
     if (P->d_items) SHM_HIP_CHECK(hipDeviceSynchronize());
     if (n > P->items_cap) {
@@ -135,6 +149,7 @@ static int plan_build_items(shm_plan* P, hipStream_t stream)
         P->items_cap = std::max<int64_t>(n, 1);
     }
     P->n_items = n;
+    P->split = sp;
     if (n) {
         SHM_HIP_CHECK(hipMemcpyAsync(P->d_items, items.data(), (size_t)n * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
         SHM_HIP_CHECK(hipStreamSynchronize(stream));  // `items` is a host temporary
@@ -333,7 +348,7 @@ int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* o
     const size_t al = (plan->dtype == SHM_F16 && plan->layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
     if (!aligned(lut, al) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "plan_launch: misaligned buffer");
     return launch_query_persistent(lut, plan->dtype, plan->layout, plan->d_objs, plan->d_items, plan->n_items,
-                                   plan->shape, plan->n_cu, dirs, out, normal, stream);
+                                   plan->split, plan->shape, plan->n_cu, dirs, out, normal, stream);
 }
 
 static std::map<std::string, shm_launch_shape> read_cache(const char* path)

@@ -42,6 +42,13 @@ struct WorkItem {
     int32_t n;
 };
 
+// The work list cut into 8 contiguous slices of (nearly) equal query counts,
+// slice s = items [b[s], b[s+1]): the blocks of one XCD (blockIdx % 8 under
+// round-robin dispatch) walk one slice, so an object's items share one L2.
+struct XcdSplit {
+    int64_t b[9];
+};
+
 // device copy of a host shm_object (same layout)
 static_assert(sizeof(shm_object) == 32, "shm_object layout");
 
@@ -49,7 +56,8 @@ static_assert(sizeof(shm_object) == 32, "shm_object layout");
 int launch_query_uniform(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
                          int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
 int launch_query_persistent(const void* lut, int dtype, int layout, const shm_object* objs_dev,
-                            const WorkItem* items_dev, int64_t n_items, const shm_launch_shape& shape, int n_cu,
+                            const WorkItem* items_dev, int64_t n_items, const XcdSplit& split,
+                            const shm_launch_shape& shape, int n_cu,
                             const float* dirs, float* out, float* normal, hipStream_t stream);
 int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* cells, hipStream_t stream);
 int launch_query_baseline(const float* vlut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, int method,

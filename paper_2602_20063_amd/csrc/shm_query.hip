@@ -132,13 +132,18 @@ int launch_query_uniform(const void* lut, int dtype, int layout, int N, int64_t 
 // ---------------------------------------------------------------------------
 template <bool FP16, bool CELL, bool NRM, int QPT>
 __global__ void k_query_persistent(const void* __restrict__ lut, const shm_object* __restrict__ objs,
-                                   const WorkItem* __restrict__ items, int64_t n_items,
+                                   const WorkItem* __restrict__ items, XcdSplit split,
                                    const float* __restrict__ dirs, float* __restrict__ out, float* __restrict__ nrm)
 {
+    // nx groups of blocks (the XCDs, or all G blocks when G < 8); group x
+    // has per blocks and walks slices x, x + nx, ... of the work list
     const int G = (int)gridDim.x;
-    const int g = xcd_remap((int)blockIdx.x, G);
+    const int nx = G < 8 ? G : 8;
+    const int x = (int)blockIdx.x % nx, local = (int)blockIdx.x / nx;
+    const int per = (G - x + nx - 1) / nx;
     const int B = (int)blockDim.x;
-    for (int64_t w = g; w < n_items; w += G) {
+    for (int s = x; s < 8; s += nx)
+    for (int64_t w = split.b[s] + local; w < split.b[s + 1]; w += per) {
         const WorkItem it = items[w];
         const shm_object o = objs[it.obj];
         const int N = o.N;
@@ -176,26 +181,27 @@ __global__ void k_query_persistent(const void* __restrict__ lut, const shm_objec
 
 template <bool FP16, bool CELL, bool NRM>
 static void launch_persistent_t(int qpt, dim3 grid, dim3 block, hipStream_t st, const void* lut,
-                                const shm_object* objs, const WorkItem* items, int64_t n_items, const float* dirs,
+                                const shm_object* objs, const WorkItem* items, const XcdSplit& split, const float* dirs,
                                 float* out, float* nrm)
 {
     switch (qpt) {
-    case 1: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 1>), grid, block, 0, st, lut, objs, items, n_items, dirs, out, nrm); break;
-    case 2: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 2>), grid, block, 0, st, lut, objs, items, n_items, dirs, out, nrm); break;
-    default: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 4>), grid, block, 0, st, lut, objs, items, n_items, dirs, out, nrm); break;
+    case 1: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 1>), grid, block, 0, st, lut, objs, items, split, dirs, out, nrm); break;
+    case 2: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 2>), grid, block, 0, st, lut, objs, items, split, dirs, out, nrm); break;
+    default: hipLaunchKernelGGL((k_query_persistent<FP16, CELL, NRM, 4>), grid, block, 0, st, lut, objs, items, split, dirs, out, nrm); break;
     }
 }
 
 int launch_query_persistent(const void* lut, int dtype, int layout, const shm_object* objs_dev,
-                            const WorkItem* items_dev, int64_t n_items, const shm_launch_shape& shape, int n_cu,
-                            const float* dirs, float* out, float* normal, hipStream_t stream)
+                            const WorkItem* items_dev, int64_t n_items, const XcdSplit& split,
+                            const shm_launch_shape& shape, int n_cu, const float* dirs, float* out, float* normal,
+                            hipStream_t stream)
 {
     if (n_items == 0) return SHM_OK;
     int64_t G = (int64_t)shape.grid_per_cu * n_cu;
     if (G > n_items) G = n_items;
     const dim3 grid((unsigned)G), block((unsigned)shape.block);
     const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL, nrm = normal != nullptr;
-#define SHM_P(a, b, c) launch_persistent_t<a, b, c>(shape.qpt, grid, block, stream, lut, objs_dev, items_dev, n_items, dirs, out, normal)
+#define SHM_P(a, b, c) launch_persistent_t<a, b, c>(shape.qpt, grid, block, stream, lut, objs_dev, items_dev, split, dirs, out, normal)
     if (f16) {
         if (cell) { if (nrm) SHM_P(true, true, true); else SHM_P(true, true, false); }
         else { if (nrm) SHM_P(true, false, true); else SHM_P(true, false, false); }
