@@ -150,3 +150,31 @@ def test_trace_full_size_bound_map_same_bits():
     b = shm.trace(lut, (0.0, 0.0, 0.0), rmax, og, dg, image_width=1920, bound_map=shm.lut_bound_map(lut))
     for x, y in zip(a, b):
         assert torch.equal(x.view(torch.int32), y.view(torch.int32))
+
+
+def test_fit_step_full_size():
+    """The fitting workload's one-kernel step (N = 512, 2^22 directions
+    sorted by cell, as bench.py runs it) against the three-kernel step, two
+    steps from a random LUT: the Adam moments within 1e-5 of their largest,
+    the parameters within 1e-6, every interior texel moved."""
+    N, Q = 512, 1 << 22
+    r = workloads.rng_for(4)
+    dirs = torch.as_tensor(workloads.uniform_dirs(Q, r)).to(DEV)
+    dirs = dirs[torch.argsort(shm.cell_keys(N, dirs).to(torch.int64) & 0xFFFFFFFF, stable=True)].contiguous()
+    lut = torch.as_tensor(workloads.random_lut(N, r)).to(DEV)[None].contiguous()
+    tv, tg = workloads.fbm_target_torch(dirs, seed=5)
+    w = dirs / dirs.norm(dim=1, keepdim=True)
+    tn = tv.float()[:, None] * w - tg.float()
+    tn = (tn / tn.norm(dim=1, keepdim=True)).contiguous()
+    tv = tv.float().contiguous()
+    a = shm.LutFit(lut.clone(), dirs, tv, tn, w_value=1000.0, lr_value=1e-3, lr_deriv=3e-4, fused=True)
+    b = shm.LutFit(lut.clone(), dirs, tv, tn, w_value=1000.0, lr_value=1e-3, lr_deriv=3e-4, fused=False)
+    for step in (1, 2):
+        a.step()
+        b.step()
+        torch.cuda.synchronize()
+        dm = (a.m - b.m).abs().max().item()
+        assert dm <= 1e-5 * b.m.abs().max().item(), (step, dm)
+        assert (a.lut - b.lut).abs().max().item() <= 1e-6, step
+    moved = (a.lut != lut)[0, :, 1:N + 1, 1:N + 1].float().mean().item()
+    assert moved > 0.999, moved
