@@ -198,3 +198,33 @@ def test_fused_step_without_queries_is_adam_with_zero_gradient():
     print("bitwise", torch.equal(out, p2), torch.equal(m1, m2), torch.equal(v1, v2))
     for x, y in ((out, p2), (m1, m2), (v1, v2)):
         assert (x - y).abs().max().item() <= 1e-7 * (1.0 + y.abs().max().item())
+
+
+def test_fused_steps_replay_from_a_graph():
+    """Two one-kernel steps (t = 1, 2) captured in a HIP graph (through
+    torch.cuda.graph) and replayed three times, with eager work and
+    synchronisations between the replays: after every replay the LUT and the
+    moments equal, bit for bit, those of the same step sequence run eagerly."""
+    N, Q = 24, 30011
+    lut, dirs, tv, tn = fit_problem(N, Q, seed=11, zero=(5,))
+    kw = dict(w_value=30.0, lr_value=1e-3, lr_deriv=3e-4, fused=True)
+    g_fit = shm.LutFit(lut.clone(), dirs, tv, tn, **kw)
+    e_fit = shm.LutFit(lut.clone(), dirs, tv, tn, **kw)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g_fit.step()
+        g_fit.step()
+    assert g_fit.cur == 0 and g_fit.t == 2
+    for rep in range(3):
+        graph.replay()
+        junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        e_fit.t = 0  # the graph holds steps 1 and 2
+        e_fit.step()
+        e_fit.step()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert torch.equal(g_fit.lut, e_fit.lut), rep
+        assert torch.equal(g_fit.m, e_fit.m) and torch.equal(g_fit.v, e_fit.v), rep
+        assert not torch.equal(g_fit.lut, lut)
