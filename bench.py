@@ -218,6 +218,18 @@ def main():
     result["roofline"]["measured_copy_gbs"] = copy_gbs
     result["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
     log(f"device copy {copy_gbs:.0f} GB/s (read + write); headline = {achieved / copy_gbs:.3f} of it")
+    # context on exactly the headline's access pattern: PyTorch gathering the
+    # same 64 B cells (index_select of the cell rows by each query's cell key;
+    # it writes the 64 B rows where the query writes 16 B results)
+    keys = shm.cell_keys(N, dirs_t, n_obj=n_glyph).to(torch.int64)
+    rows = lut_cell.view(-1, 16)
+    gathered = torch.empty((Q, 16), device=DEV)
+    torch.index_select(rows, 0, keys, out=gathered)
+    ms_gather = t_gpu(lambda: torch.index_select(rows, 0, keys, out=gathered), 10)
+    del gathered, keys
+    result["roofline"]["torch_index_select_same_cells_per_s"] = Q / (ms_gather * 1e-3)
+    log(f"torch index_select of the same 64 B cells: {Q / ms_gather / 1e6:.2f} G rows/s "
+        f"(the query: {qps / 1e9:.2f} G/s)")
     forms = {}
     sample_out = {}
     if not args.no_forms:

@@ -137,6 +137,15 @@ SHM_API int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, in
 SHM_API int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
                          int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
 
+/* Step a3 of the query alone (Sec. 3.2): the 2x2 footprint of every query,
+ * decided and loaded exactly as shm_query_value_grad does (same arguments),
+ * written as foot [n_obj*q_per_obj][4][4] FP32 (16-byte aligned): corners
+ * (i0,j0), (i0+1,j0), (i0,j0+1), (i0+1,j0+1), each (r, r_u h, r_v h,
+ * r_uv h^2), FP16 data decoded; NaN for an invalid direction.  For custom
+ * reconstructions, and as the gather-only cost of the query. */
+SHM_API int shm_gather_footprints(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj,
+                                  const float* dirs, int64_t q_per_obj, float* foot, hipStream_t stream);
+
 /* Counter of bad queries: adds to *count (one device uint64, zeroed by the
  * caller) the number of the Q directions dirs[Q][3] that every query entry
  * point answers with NaN: a zero vector or a NaN or Inf component.  The

@@ -104,6 +104,7 @@ SIGNATURES = {
     "shm_adam_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, _VP]),
     "shm_count_invalid": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    "shm_gather_footprints": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I64, _VP, _I64, _VP, _VP]),
     "shm_fit_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _I64,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     _VP, ctypes.c_size_t, _I32, _VP]),
@@ -272,6 +273,13 @@ def shm_fit_forward_loss_grad(lut, N, dirs, target_r, target_n, Q, w_value, grad
 def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     return _check(lib().shm_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), n4, step, float(lr_value),
                                       float(lr_deriv), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def shm_gather_footprints(lut, dtype, layout, N, n_obj, dirs, q_per_obj, foot, stream=None):
+    _need(dirs, torch.float32, "dirs")
+    _need(foot, torch.float32, "foot")
+    return _check(lib().shm_gather_footprints(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, _ptr(foot),
+                                              _stream(stream)))
 
 
 def shm_count_invalid(dirs, Q, count, stream=None):

@@ -75,6 +75,8 @@ int launch_adam(float* p, const float* g, float* m, float* v, int64_t n4, int64_
 int launch_fit_forward_loss_grad(const float* lut, int N, const float* dirs, const float* tr, const float* tn,
                                  int64_t Q, float w_value, float* grad, hipStream_t stream);
 int launch_count_invalid(const float* dirs, int64_t Q, unsigned long long* count, hipStream_t stream);
+int launch_gather_footprints(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
+                             int64_t q_per_obj, float* foot, hipStream_t stream);
 int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
                     const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
                     float b2, float eps, void* ws, hipStream_t stream);
@@ -258,6 +260,24 @@ int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t
     if (!aligned(lut, al) || !aligned(out, 16) || !aligned(dirs, 4) || (normal && !aligned(normal, 4)))
         return fail(SHM_ERR_INVALID_ARG, "query: misaligned buffer (lut %zu B, out 16 B)", al);
     return launch_query_uniform(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, normal, stream);
+}
+
+int shm_gather_footprints(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
+                          int64_t q_per_obj, float* foot, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype)) return fail(SHM_ERR_INVALID_ARG, "gather_footprints: bad dtype %d", dtype);
+    if (!valid_layout(layout)) return fail(SHM_ERR_INVALID_ARG, "gather_footprints: bad layout %d", layout);
+    if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "gather_footprints: N must be 1..%d (got %d)", SHM_MAX_N, N);
+    if (n_obj < 0 || q_per_obj < 0) return fail(SHM_ERR_INVALID_ARG, "gather_footprints: negative size");
+    if (product_exceeds(n_obj, q_per_obj, INT64_MAX / 64))
+        return fail(SHM_ERR_UNSUPPORTED, "gather_footprints: %lld x %lld queries", (long long)n_obj, (long long)q_per_obj);
+    if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
+    if (!lut || !dirs || !foot) return fail(SHM_ERR_INVALID_ARG, "gather_footprints: null pointer");
+    const size_t al = (dtype == SHM_F16 && layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(foot, 16) || !aligned(dirs, 4))
+        return fail(SHM_ERR_INVALID_ARG, "gather_footprints: misaligned buffer (lut %zu B, foot 16 B)", al);
+    return launch_gather_footprints(lut, dtype, layout, N, n_obj, dirs, q_per_obj, foot, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -89,6 +89,73 @@ __global__ __launch_bounds__(256) void k_query_uniform(const void* __restrict__ 
     }
 }
 
+// Step a3 alone (Sec. 3.2): the 16 footprint scalars of every query, with
+// the launch mapping, the cell decision and the loads of k_query_uniform,
+// written as 4 float4 (corners (i0,j0), (i0+1,j0), (i0,j0+1), (i0+1,j0+1),
+// each (r, r_u h, r_v h, r_uv h^2)); NaN for an invalid direction.
+template <bool FP16, bool CELL>
+__global__ __launch_bounds__(256) void k_gather_foot(const void* __restrict__ lut, int N, int64_t lut_elems,
+                                                     int64_t q_per_obj, int tiles_per_obj,
+                                                     const float* __restrict__ dirs, float4* __restrict__ foot)
+{
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int obj = b / tiles_per_obj;
+    const int tile = b - obj * tiles_per_obj;
+    const char* base = reinterpret_cast<const char*>(lut) + (size_t)obj * (size_t)lut_elems * (FP16 ? 2 : 4);
+    float x[SHM_QPT], y[SHM_QPT], z[SHM_QPT];
+    int64_t qq[SHM_QPT];
+    bool act[SHM_QPT];
+#pragma unroll
+    for (int j = 0; j < SHM_QPT; ++j) {
+        const int64_t ql = (int64_t)tile * (256 * SHM_QPT) + j * 256 + threadIdx.x;
+        act[j] = ql < q_per_obj;
+        qq[j] = (int64_t)obj * q_per_obj + ql;
+        if (act[j]) {
+            x[j] = ld_dir(dirs + 3 * qq[j]);
+            y[j] = ld_dir(dirs + 3 * qq[j] + 1);
+            z[j] = ld_dir(dirs + 3 * qq[j] + 2);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < SHM_QPT; ++j) {
+        if (!act[j]) continue;
+        const Loc L = locate(x[j], y[j], z[j], N);
+        Foot F;
+        if (L.face < 0) {
+            const float nan = __builtin_nanf("");
+#pragma unroll
+            for (int k = 0; k < 4; ++k) F.c[k] = make_float4(nan, nan, nan, nan);
+        } else {
+            F = load_foot<FP16, CELL>(base, N, L);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) foot[4 * qq[j] + k] = F.c[k];
+    }
+}
+
+int launch_gather_footprints(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
+                             int64_t q_per_obj, float* foot, hipStream_t stream)
+{
+    if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
+    const int64_t tiles = (q_per_obj + 256 * SHM_QPT - 1) / (256 * SHM_QPT);
+    if (tiles > 0x7fffffff || tiles * n_obj > 0x7fffffff)
+        return fail(SHM_ERR_UNSUPPORTED, "gather_footprints: %lld objects x %lld tiles exceeds one launch",
+                    (long long)n_obj, (long long)tiles);
+    const dim3 grid((unsigned)(tiles * n_obj));
+    const int64_t le = layout == SHM_LAYOUT_CELL ? cell_elems(N) : texel_elems(N);
+    float4* f4 = reinterpret_cast<float4*>(foot);
+    const int tpo = (int)tiles;
+    if (dtype == SHM_F16) {
+        if (layout == SHM_LAYOUT_CELL) hipLaunchKernelGGL((k_gather_foot<true, true>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+        else hipLaunchKernelGGL((k_gather_foot<true, false>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+    } else {
+        if (layout == SHM_LAYOUT_CELL) hipLaunchKernelGGL((k_gather_foot<false, true>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+        else hipLaunchKernelGGL((k_gather_foot<false, false>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+    }
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
 template <bool FP16, bool CELL, bool NRM>
 static void launch_uniform_t(dim3 grid, hipStream_t st, const void* lut, int N, int64_t le, int64_t qpo, int tpo,
                              const float* dirs, float* out, float* nrm)
@@ -124,11 +191,12 @@ int launch_query_uniform(const void* lut, int dtype, int layout, int N, int64_t 
 
 // ---------------------------------------------------------------------------
 // Persistent batched kernel.  The work list holds (object, query range)
-// items of at most `tile` queries, ordered by object.  Workgroup g takes
-// items g, g + G, g + 2G, ... (static striding: deterministic, no counters,
-// nothing to reset, so a captured graph replays as is).  Items processed at
-// the same time are neighbours in the list, so an object's LUT is read by
-// many workgroups at once and stays resident in L2 / MALL.
+// items of at most `tile` queries, ordered by object, and is cut into 8
+// contiguous slices of equal query counts; the workgroups of one XCD take
+// the items of one slice in turn (static striding: deterministic, no
+// counters, nothing to reset, so a captured graph replays as is).  Items
+// processed at the same time are neighbours in the list, so an object's LUT
+// is read by the workgroups of one XCD and stays resident in its L2.
 // ---------------------------------------------------------------------------
 template <bool FP16, bool CELL, bool NRM, int QPT>
 __global__ void k_query_persistent(const void* __restrict__ lut, const shm_object* __restrict__ objs,

@@ -242,6 +242,19 @@ def test_size_products_do_not_overflow():
     assert call("shm_bake_sh_lut", p, 4, 8, huge, 0, p, p, 1 << 30, None) == shm.SHM_ERR_UNSUPPORTED
 
 
+def test_gather_footprints_validation():
+    p = ctypes.c_void_p(256)
+    gf = lambda *a: call("shm_gather_footprints", *a)
+    assert gf(p, 0, 0, 8, 1, p, 0, p, None) == shm.SHM_OK       # nothing to gather
+    assert gf(p, 2, 0, 8, 1, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert gf(p, 0, 2, 8, 1, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert gf(p, 0, 0, 0, 1, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert gf(p, 0, 0, 8, -1, p, 10, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert gf(p, 0, 0, 8, 1, p, 10, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert gf(p, 0, 0, 8, 1, p, 10, ctypes.c_void_p(264), None) == shm.SHM_ERR_INVALID_ARG  # foot not 16 B aligned
+    assert gf(p, 0, 0, 8, 1 << 40, p, 1 << 40, p, None) == shm.SHM_ERR_UNSUPPORTED
+
+
 def test_count_invalid_validation():
     p = ctypes.c_void_p(256)
     ci = lambda *a: call("shm_count_invalid", *a)

@@ -225,3 +225,35 @@ def test_count_invalid_matches_the_nan_rows():
         shm.shm_query_value_grad(lut, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, 8, 1, torch.as_tensor(sc).to(DEV), n, o2)
         assert torch.equal(o1.view(torch.int32), o2.view(torch.int32)), e
     assert c.item() == ref + int((~(np.isfinite(d[:1000]).all(axis=1) & (np.abs(d[:1000]).max(axis=1) > 0))).sum())
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float16])
+def test_gather_footprints_bit_exact(dt):
+    """Step a3 alone: every query's 16 footprint scalars, for both layouts,
+    equal the LUT's texels at the query's cell (cell keys, themselves checked
+    bit for bit against the oracle's decision), corner by corner; FP16 data
+    decode exactly; NaN for invalid directions.  3 objects, a ragged count."""
+    rng = np.random.default_rng(21)
+    N, n_obj, qpo = 9, 3, 1001
+    lut = torch.as_tensor(workloads.random_lut(N, rng, n_obj=n_obj)).to(DEV, dt).contiguous()
+    d = workloads.uniform_dirs(n_obj * qpo, rng)
+    d[7] = 0.0
+    d[500, 1] = np.nan
+    dirs = torch.as_tensor(d).to(DEV)
+    keys = shm.cell_keys(N, dirs, n_obj=n_obj).cpu().numpy().astype(np.int64)
+    tex = lut.float().cpu().numpy()
+    ok = keys >= 0
+    assert (~ok).sum() == 2
+    i0 = keys[ok] % (N + 1)
+    j0 = (keys[ok] // (N + 1)) % (N + 1)
+    f = (keys[ok] // (N + 1) ** 2) % 6
+    o = keys[ok] // ((N + 1) ** 2 * 6)
+    ref = np.stack([tex[o, f, j0 + dj, i0 + di] for dj, di in ((0, 0), (0, 1), (1, 0), (1, 1))], axis=1)
+    layouts = [(shm.SHM_LAYOUT_TEXEL, lut), (shm.SHM_LAYOUT_CELL, shm.to_cells(lut))]
+    for layout, src in layouts:
+        foot = torch.empty((n_obj * qpo, 4, 4), device=DEV)
+        code = shm.SHM_F16 if dt == torch.float16 else shm.SHM_F32
+        shm.shm_gather_footprints(src, code, layout, N, n_obj, dirs, qpo, foot)
+        got = foot.cpu().numpy()
+        assert np.isnan(got[~ok]).all()
+        assert np.array_equal(got[ok], ref), layout
