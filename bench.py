@@ -176,7 +176,7 @@ def main():
         # one persistent launch of the uneven batch (FP16 cell LUTs) in the
         # launch shape the autotuner usually picks
         B = build_uneven_batch()
-        lut16 = B["lut32"].half()
+        lut16 = shm.cells_to_f16(B["lut32"])
         outb = torch.empty((B["Qtot"], 4), device=DEV)
         plan = shm.Plan(B["objs"], shm.SHM_F16, shm.SHM_LAYOUT_CELL)
         plan.set_shape(256, 2, 512, 4)
@@ -262,7 +262,7 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
 
     # fp16 storage
     l16t = lut_tex.half()
-    l16c = shm.to_cells(l16t)
+    l16c = shm.cells_to_f16(lut_cell)  # FP16 cell encoding, from the FP32 cells
     for name, lut, lay in (("query_f16_cell", l16c, 1), ("query_f16_texel", l16t, 0)):
         ms = t_gpu(lambda: shm.shm_query_value_grad(lut, shm.SHM_F16, lay, N, n_glyph, dirs_t, q_per, out), 20)
         forms[name] = {"queries_per_s": Q / ms * 1e3, "ms": ms, "hbm_frac": B16 / ms / 1e6 / PEAK_HBM_GBS,
@@ -566,7 +566,7 @@ def run_batched():
     spec, n_obj, Qtot, dirs, objs = B["spec"], B["n_obj"], B["Qtot"], B["dirs"], B["objs"]
     lut32, coeffs, qb = B["lut32"], B["coeffs"], B["qb"]
     Qs = spec["Q"]
-    lut16 = lut32.half()
+    lut16 = shm.cells_to_f16(lut32)
     out16 = torch.empty((Qtot, 4), device=DEV)
     out32 = torch.empty((Qtot, 4), device=DEV)
     plan = shm.Plan(objs, shm.SHM_F16, shm.SHM_LAYOUT_CELL)

@@ -32,7 +32,12 @@
  *      (i0, j0), i0, j0 in 0..N, stores its whole 2x2 footprint contiguously:
  *      lut[obj][face][j0][i0][corner][ch], corner = (i0,j0), (i0+1,j0),
  *      (i0,j0+1), (i0+1,j0+1), so one query reads one aligned 64 B (FP32)
- *      or 32 B (FP16) block.
+ *      or 32 B (FP16) block.  In FP16 cells corners 1..3 hold r as its
+ *      difference from corner 0's r (the other channels as they are): the
+ *      patch's derivatives do not see the rounding of r itself, so FP16
+ *      cells made from FP32 data (shm_cells_to_f16) keep FP16's relative
+ *      precision in the gradient.  Make FP16 cells with shm_lut_to_cells or
+ *      shm_cells_to_f16, not by an elementwise cast.
  *  - Queries: directions need not be unit length (w = d/|d|).  A zero or
  *    non-finite direction is not an error: its outputs are NaN.
  *  - Output of a query: out[q] = (R, gx, gy, gz) with (gx, gy, gz) the
@@ -117,9 +122,16 @@ SHM_API int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n
 SHM_API int shm_margin_dirs(int32_t N, float* dirs, hipStream_t stream);
 SHM_API int shm_bake_fd(const float* samples, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out, hipStream_t stream);
 
-/* TEXEL -> CELL copy of n_obj LUTs of face size N (same dtype). */
+/* TEXEL -> CELL copy of n_obj LUTs of face size N (same dtype; FP16 cells
+ * in the FP16 cell encoding above, the differences formed exactly in FP32
+ * and rounded once). */
 SHM_API int shm_lut_to_cells(const void* lut_texel, int32_t dtype, int32_t N, int64_t n_obj, void* lut_cell,
                      hipStream_t stream);
+/* FP32 CELL data -> FP16 cells in the FP16 cell encoding: n_cells whole
+ * cells (16 floats each, any face sizes back to back; cells 16-byte and
+ * cells_f16 8-byte aligned, not overlapping); each difference is formed in
+ * FP32 and rounded once, every other channel rounded once. */
+SHM_API int shm_cells_to_f16(const float* cells, int64_t n_cells, void* cells_f16, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Query, value + gradient (Sec. 3.2-3.4, Eqs. 3-10): the hot path.

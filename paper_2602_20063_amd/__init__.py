@@ -104,6 +104,7 @@ SIGNATURES = {
     "shm_adam_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, _VP]),
     "shm_count_invalid": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    "shm_cells_to_f16": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
     "shm_gather_footprints": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I64, _VP, _I64, _VP, _VP]),
     "shm_fit_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _I64,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -471,6 +472,16 @@ def bake_sh(coeffs, N, dtype=torch.float32, stream=None):
     ws = torch.empty(max(shm_bake_sh_lut_workspace(L, N), 1), dtype=torch.uint8, device=coeffs.device)
     shm_bake_sh_lut(coeffs, L, N, n_obj, _dtype_code(lut), lut, ws, stream)
     return lut
+
+
+def cells_to_f16(cells, stream=None):
+    """FP32 CELL LUT(s) (any shape made of whole 16-float cells) -> FP16 cells
+    in the FP16 cell encoding (value differences from corner 0)."""
+    _need(cells, torch.float32, "cells")
+    cells = cells.contiguous()
+    out = torch.empty(cells.shape, dtype=torch.float16, device=cells.device)
+    _check(lib().shm_cells_to_f16(_ptr(cells), cells.numel() // 16, _ptr(out), _stream(stream)))
+    return out
 
 
 def to_cells(lut, stream=None):

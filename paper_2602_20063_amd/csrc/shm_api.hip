@@ -75,6 +75,7 @@ int launch_adam(float* p, const float* g, float* m, float* v, int64_t n4, int64_
 int launch_fit_forward_loss_grad(const float* lut, int N, const float* dirs, const float* tr, const float* tn,
                                  int64_t Q, float w_value, float* grad, hipStream_t stream);
 int launch_count_invalid(const float* dirs, int64_t Q, unsigned long long* count, hipStream_t stream);
+int launch_cells_to_f16(const float* cells, int64_t n_cells, void* cells_f16, hipStream_t stream);
 int launch_gather_footprints(const void* lut, int dtype, int layout, int N, int64_t n_obj, const float* dirs,
                              int64_t q_per_obj, float* foot, hipStream_t stream);
 int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
@@ -260,6 +261,20 @@ int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t
     if (!aligned(lut, al) || !aligned(out, 16) || !aligned(dirs, 4) || (normal && !aligned(normal, 4)))
         return fail(SHM_ERR_INVALID_ARG, "query: misaligned buffer (lut %zu B, out 16 B)", al);
     return launch_query_uniform(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, normal, stream);
+}
+
+int shm_cells_to_f16(const float* cells, int64_t n_cells, void* cells_f16, hipStream_t stream)
+{
+    clear_error();
+    if (n_cells < 0) return fail(SHM_ERR_INVALID_ARG, "cells_to_f16: negative cell count");
+    if (n_cells > INT64_MAX / 64) return fail(SHM_ERR_UNSUPPORTED, "cells_to_f16: too many cells");
+    if (n_cells == 0) return SHM_OK;
+    if (!cells || !cells_f16) return fail(SHM_ERR_INVALID_ARG, "cells_to_f16: null pointer");
+    if (!aligned(cells, 16) || !aligned(cells_f16, 8)) return fail(SHM_ERR_INVALID_ARG, "cells_to_f16: misaligned buffer");
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(cells), b0 = reinterpret_cast<uintptr_t>(cells_f16);
+    if (a0 < b0 + (uintptr_t)n_cells * 32 && b0 < a0 + (uintptr_t)n_cells * 64)
+        return fail(SHM_ERR_INVALID_ARG, "cells_to_f16: input and output overlap");
+    return launch_cells_to_f16(cells, n_cells, cells_f16, stream);
 }
 
 int shm_gather_footprints(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,

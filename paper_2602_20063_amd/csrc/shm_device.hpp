@@ -219,6 +219,12 @@ __device__ __forceinline__ Foot load_cell_f32(const float* __restrict__ lut, int
     return F;
 }
 
+// FP16 cell encoding: corner 0 stores (r, r_u h, r_v h, r_uv h^2); corners
+// 1..3 store the value r as its difference from corner 0's r.  Derivatives of
+// the patch weigh the corner values by basis functions that sum to zero, so
+// the rounding of corner 0's r cancels from them exactly and only the
+// (small) differences are rounded: the gradient keeps FP16's relative
+// precision instead of losing a factor ~N to the value's rounding.
 __device__ __forceinline__ Foot load_cell_f16(const __half* __restrict__ lut, int N, const Loc& L)
 {
     const int C = N + 1;
@@ -231,6 +237,9 @@ __device__ __forceinline__ Foot load_cell_f16(const __half* __restrict__ lut, in
     F.c[1] = h4_to_f4(make_uint2(q0.z, q0.w));
     F.c[2] = h4_to_f4(make_uint2(q1.x, q1.y));
     F.c[3] = h4_to_f4(make_uint2(q1.z, q1.w));
+    F.c[1].x += F.c[0].x;
+    F.c[2].x += F.c[0].x;
+    F.c[3].x += F.c[0].x;
     return F;
 }
 

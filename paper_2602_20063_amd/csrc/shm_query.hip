@@ -284,8 +284,17 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
 
 // ---------------------------------------------------------------------------
 // TEXEL -> CELL relayout: one lane per (cell, corner), 16 B (FP32) or 8 B
-// (FP16) written contiguously.
+// (FP16) written contiguously.  FP16 cells hold the value channel of corners
+// 1..3 as differences from corner 0's value (FP16 cell encoding, see
+// load_cell_f16); from FP16 texels the difference is formed in FP32 (exact)
+// and rounded once.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint2 f4_to_h4(float4 v)
+{
+    const __half2 lo = __floats2half2_rn(v.x, v.y), hi = __floats2half2_rn(v.z, v.w);
+    return make_uint2(*reinterpret_cast<const uint32_t*>(&lo), *reinterpret_cast<const uint32_t*>(&hi));
+}
+
 template <typename V>
 __global__ void k_lut_to_cells(const V* __restrict__ tex, int N, int64_t total, V* __restrict__ cells)
 {
@@ -301,7 +310,40 @@ __global__ void k_lut_to_cells(const V* __restrict__ tex, int N, int64_t total, 
     r -= (int64_t)face * C * C;
     const int j0 = (int)(r / C), i0 = (int)(r - (int64_t)j0 * C);
     const int p = i0 + (corner & 1), q = j0 + (corner >> 1);
-    cells[i] = tex[obj * (6ll * P * P) + ((int64_t)face * P + q) * P + p];
+    const int64_t t0 = obj * (6ll * P * P) + ((int64_t)face * P + j0) * P + i0;
+    const V v = tex[obj * (6ll * P * P) + ((int64_t)face * P + q) * P + p];
+    if constexpr (sizeof(V) == 8) {  // FP16: value of corners 1..3 as a difference
+        if (corner > 0) {
+            float4 f = h4_to_f4(v);
+            f.x -= h4_to_f4(tex[t0]).x;
+            cells[i] = f4_to_h4(f);
+            return;
+        }
+    }
+    cells[i] = v;
+}
+
+// FP32 cells (any run of whole cells, mixed face sizes included) -> FP16
+// cells: the value of corners 1..3 as its difference from corner 0's value,
+// formed in FP32 and rounded once; every other channel rounded once.
+__global__ void k_cells_to_f16(const float4* __restrict__ src, int64_t n_cells, uint2* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells * 4) return;
+    float4 v = src[i];
+    if ((i & 3) != 0) v.x -= src[i & ~(int64_t)3].x;
+    dst[i] = f4_to_h4(v);
+}
+
+int launch_cells_to_f16(const float* cells, int64_t n_cells, void* cells_f16, hipStream_t stream)
+{
+    if (n_cells == 0) return SHM_OK;
+    const int64_t blocks = (n_cells * 4 + 255) / 256;
+    if (blocks > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "cells_to_f16: too large");
+    hipLaunchKernelGGL(k_cells_to_f16, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       reinterpret_cast<const float4*>(cells), n_cells, reinterpret_cast<uint2*>(cells_f16));
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
 }
 
 int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* cells, hipStream_t stream)

@@ -39,3 +39,12 @@ def angle_deg(a, b):
     b = np.asarray(b, np.float64)
     c = np.sum(a * b, axis=1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
     return np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
+
+
+def decode_f16_cells(c16):
+    """FP16 cells (the library's FP16 cell encoding: corners 1..3 hold r as a
+    difference from corner 0's r) -> the FP32 footprints a query decodes
+    (one FP32 addition per corner), same shape."""
+    c = np.asarray(c16).astype(np.float32).reshape(-1, 4, 4).copy()
+    c[:, 1:, 0] += c[:, :1, 0]
+    return c.reshape(np.asarray(c16).shape)

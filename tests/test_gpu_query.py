@@ -8,7 +8,7 @@ import torch
 import oracle
 import paper_2602_20063_amd as shm
 import workloads
-from parity import check_value_grad, angle_deg
+from parity import check_value_grad, angle_deg, decode_f16_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -257,3 +257,42 @@ def test_gather_footprints_bit_exact(dt):
         got = foot.cpu().numpy()
         assert np.isnan(got[~ok]).all()
         assert np.array_equal(got[ok], ref), layout
+
+
+def test_f16_cells_from_f32_data():
+    """FP16 cells made from FP32 cells (shm_cells_to_f16): (1) the encoding
+    bit for bit (corner 0 rounded once; corners 1..3 with r replaced by its
+    FP32 difference from corner 0's r, rounded once); (2) the FP16 cell query
+    gives the bits of the FP32 cell query on the decoded cells; (3) against
+    the oracle (FP64, on the FP32 LUT) its gradient error is far below that of
+    plain FP16 texels: the value's rounding no longer enters the derivatives."""
+    c = workloads.sh_glyph_coeffs(8, 1, rng(31))[0]
+    N = 32
+    lut = oracle.bake_sh(c, N).astype(np.float32)
+    cells32 = shm.to_cells(gpu(lut)[None])
+    c16 = shm.cells_to_f16(cells32)
+    src = cells32.cpu().numpy().reshape(-1, 4, 4)
+    enc = src.copy()
+    enc[:, 1:, 0] = enc[:, 1:, 0] - enc[:, :1, 0]
+    assert np.array_equal(c16.cpu().numpy().reshape(-1, 4, 4).view(np.uint16), enc.astype(np.float16).view(np.uint16))
+    dirs = workloads.uniform_dirs(65536, rng(32))
+    d = gpu(dirs)
+    o16 = shm.query(c16, d, layout=shm.SHM_LAYOUT_CELL)
+    dec = gpu(decode_f16_cells(c16.cpu().numpy()))
+    o32d = shm.query(dec, d, layout=shm.SHM_LAYOUT_CELL)
+    torch.cuda.synchronize()
+    assert torch.equal(o16.view(torch.int32), o32d.view(torch.int32))
+    ref = oracle.query(lut.astype(np.float64), dirs)
+    plain = gpu_query(lut.astype(np.float16).astype(np.float32), dirs, shm.SHM_LAYOUT_TEXEL, dtype=torch.float16)
+
+    def grad_err(o):
+        g, gr = o[:, 1:], ref[:, 1:]
+        gn = np.linalg.norm(gr, axis=1)
+        return np.linalg.norm(g - gr, axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))
+
+    e16, ep = grad_err(o16.cpu().numpy()), grad_err(plain)
+    print(f"FP16 gradient error, max / rms: delta cells {e16.max():.3g} / {np.sqrt(np.mean(e16**2)):.3g}, "
+          f"plain texels {ep.max():.3g} / {np.sqrt(np.mean(ep**2)):.3g}")
+    assert e16.max() < 0.05 * ep.max() and e16.max() < 5e-3
+    v16 = np.abs(o16.cpu().numpy()[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+    assert v16.max() < 1e-3  # FP16 value rounding, as before
