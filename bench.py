@@ -613,13 +613,17 @@ def run_batched():
 
 def run_trace():
     """Workload 3: radial impostor of 64 bumps, FD-baked at N=256,
-    1920x1080 primary rays, FP32 and FP16 LUT."""
+    1920x1080 primary rays; FP32 texels, FP16 texels and FP16 cells (value
+    differences, made from the FP32 data)."""
     N = 256
     mu, amp, width = workloads.bump_params(workloads.rng_for(3))
     md = shm.margin_dirs(N).cpu().numpy().reshape(-1, 3)
     samples = workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)
     lut = shm.bake_fd(to_dev(samples), N)
-    rmax = float(shm.lut_rmax(lut).item()) * 1.0001
+    c16 = shm.cells_to_f16(shm.to_cells(lut))
+    # one bounding radius for every form (and the oracle): it bounds each
+    # form's own reconstruction
+    rmax = max(float(shm.lut_rmax(x).item()) for x in (lut, lut.half(), c16)) * 1.0001
     o_np, d_np = workloads.camera_rays(1920, 1080)
     o, d = to_dev(o_np), to_dev(d_np)
     P = o.shape[0]
@@ -631,8 +635,8 @@ def run_trace():
     bmap = shm.lut_bound_map(lut)
     torch.cuda.synchronize()
     res["bound_map_ms"] = t_gpu(lambda: shm.lut_bound_map(lut), 5)
-    for name, lt in (("f32", lut), ("f16", lut.half())):
-        bm = bmap if lt.dtype == torch.float32 else shm.lut_bound_map(lt)
+    for name, lt in (("f32", lut), ("f16", lut.half()), ("f16_cell", c16)):
+        bm = bmap if name == "f32" else shm.lut_bound_map(lt)
         t, out, nrm = shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W, bound_map=bm)
         ms = t_gpu(lambda: shm.trace(lt, (0.0, 0.0, 0.0), rmax, o, d, image_width=W, bound_map=bm), 20)
         hit = torch.isfinite(t)
@@ -765,7 +769,7 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
         lut = oracle.bake_fd(smp, N3)
         sel = np.arange(0, s["o"].shape[0], 97)
         t_ref, _, n_ref = oracle.trace(lut, np.zeros(3), s["rmax"], s["o"][sel], s["d"][sel])
-        for name in ("f32", "f16"):
+        for name in ("f32", "f16", "f16_cell"):
             tg, ng = s[name][0][sel], s[name][1][sel]
             hg, hr = np.isfinite(tg), np.isfinite(t_ref)
             both = hg & hr

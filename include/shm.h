@@ -174,6 +174,10 @@ SHM_API int shm_count_invalid(const float* dirs, int64_t Q, unsigned long long* 
  *   0; 0 also for an invalid direction) or NULL.
  * Other arguments and the cell decision as in shm_query_value_grad. */
 #define SHM_SIGNED 1
+/* Flag of shm_trace_radial_ex (shm_trace_params.flags), shm_lut_rmax and
+ * shm_lut_bound_map: the LUT is in the CELL layout (16-byte aligned), read
+ * as a query reads it (FP16 cells decoded). */
+#define SHM_CELL_LUT 2
 SHM_API int shm_query_scaled(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
                              int64_t q_per_obj, float scale, int32_t flags, float* out, float* normal, int8_t* sign,
                              hipStream_t stream);
@@ -294,7 +298,7 @@ SHM_API int shm_trace_radial(const void* lut, int32_t dtype, int32_t N, const fl
  * in any order. */
 typedef struct shm_trace_params {
     float scale;          /* s > 0 */
-    int32_t flags;        /* 0 or SHM_SIGNED */
+    int32_t flags;        /* SHM_SIGNED, SHM_CELL_LUT or both, or 0 */
     int32_t n_march;      /* >= 1 */
     int32_t n_bisect;     /* fixed count, or the cap of the adaptive budget */
     int32_t n_newton;     /* n_march + n_bisect + n_newton + 1 <= 64 */
@@ -319,13 +323,15 @@ SHM_API int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const
                                 float* t_out, float* out, float* normal, int8_t* sign, uint8_t* evals,
                                 hipStream_t stream);
 
-/* Upper bound of the reconstructed r over one TEXEL LUT: the largest Bezier
- * control point of any cell's bicubic patch (convex hull property); with
- * flags = SHM_SIGNED the largest |control point|, which bounds |r|.  Writes
- * one float to rmax_out (device). */
+/* Upper bound of the reconstructed r over one LUT (TEXEL, or CELL with
+ * SHM_CELL_LUT: then from the cells as decoded): the largest Bezier control
+ * point of any cell's bicubic patch (convex hull property); with
+ * SHM_SIGNED the largest |control point|, which bounds |r|.  Writes one
+ * float to rmax_out (device). */
 SHM_API int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, int32_t flags, float* rmax_out, hipStream_t stream);
 
-/* Block bound map of one TEXEL LUT for the trace's empty-space skipping:
+/* Block bound map of one LUT (TEXEL, or CELL with SHM_CELL_LUT) for the
+ * trace's empty-space skipping:
  * face f is cut into blocks x blocks blocks of (u, v) (block bi covers
  * u in [bi/blocks, (bi+1)/blocks]); map_out[f][bj][bi] (device, FP32) is
  * the largest Bezier control point (|control point| with SHM_SIGNED), at

@@ -28,6 +28,7 @@ SHM_LAYOUT_TEXEL, SHM_LAYOUT_CELL = 0, 1
 SHM_MAX_N, SHM_MAX_L, SHM_MAX_BOUND_BLOCKS = 1024, 16, 64
 SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC, SHM_RECON_FAST_BICUBIC_FD = 0, 1, 2, 3
 SHM_SIGNED = 1
+SHM_CELL_LUT = 2
 
 
 class ShmError(RuntimeError):
@@ -556,10 +557,18 @@ def bake_fd(samples, N, dtype=torch.float32, stream=None):
     return lut
 
 
+def _layout_flags(lut, signed):
+    """(N, flags) of one TEXEL or CELL LUT tensor (CELL: last dimension 16)."""
+    cell = lut.shape[-1] == 16
+    N = lut_n(lut, SHM_LAYOUT_CELL if cell else SHM_LAYOUT_TEXEL)
+    return N, (SHM_SIGNED if signed else 0) | (SHM_CELL_LUT if cell else 0)
+
+
 def lut_rmax(lut, signed=False, stream=None):
-    N = lut_n(lut)
+    """Bezier bound of r (|r| if signed) over one TEXEL or CELL LUT."""
+    N, flags = _layout_flags(lut, signed)
     r = torch.empty(1, dtype=torch.float32, device=lut.device)
-    shm_lut_rmax(lut, _dtype_code(lut), N, SHM_SIGNED if signed else 0, r, stream)
+    shm_lut_rmax(lut, _dtype_code(lut), N, flags, r, stream)
     return r
 
 
@@ -581,14 +590,13 @@ def _bound_fields(bound_map):
 
 def lut_bound_map(lut, blocks=None, signed=False, stream=None):
     """[6, blocks, blocks] FP32 block bounds of r (|r| if signed) of one
-    TEXEL LUT, for the trace's empty-space skipping.  By default a block
-    spans about 4 cells (N / 4 blocks per face side, at most 64)."""
-    N = lut_n(lut)
+    TEXEL or CELL LUT, for the trace's empty-space skipping.  By default a
+    block spans about 4 cells (N / 4 blocks per face side, at most 64)."""
+    N, flags = _layout_flags(lut, signed)
     if blocks is None:
         blocks = min(SHM_MAX_BOUND_BLOCKS, max(1, N // 4))
     out = torch.empty((6, blocks, blocks), dtype=torch.float32, device=lut.device)
-    _check(lib().shm_lut_bound_map(_ptr(lut), _dtype_code(lut), N, SHM_SIGNED if signed else 0, blocks, _ptr(out),
-                                   _stream(stream)))
+    _check(lib().shm_lut_bound_map(_ptr(lut), _dtype_code(lut), N, flags, blocks, _ptr(out), _stream(stream)))
     return out
 
 
@@ -597,15 +605,16 @@ def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, n
     """Fixed-schedule trace: t, (R, grad), normal.  image_width > 0 says the
     rays are a row-major image of that width (traced in 8 x 8 tiles);
     bound_map (lut_bound_map of this LUT) skips march samples provably
-    outside the surface (the same results)."""
-    N = lut_n(lut)
+    outside the surface (the same results).  lut: TEXEL or CELL (last
+    dimension 16)."""
+    N, flags = _layout_flags(lut, False)
     P = ray_o.shape[0]
     t = torch.empty(P, dtype=torch.float32, device=ray_o.device)
     out = torch.empty((P, 4), dtype=torch.float32, device=ray_o.device)
     nrm = torch.empty((P, 3), dtype=torch.float32, device=ray_o.device) if normals else None
-    if image_width or bound_map is not None:
+    if image_width or bound_map is not None or flags:
         bb, bp = _bound_fields(bound_map)
-        prm = shm_trace_params(1.0, 0, n_march, n_bisect, n_newton, 0.0, 0.0, int(image_width), bb, bp)
+        prm = shm_trace_params(1.0, flags, n_march, n_bisect, n_newton, 0.0, 0.0, int(image_width), bb, bp)
         shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, None, None,
                             stream)
     else:
@@ -617,8 +626,9 @@ def trace(lut, center, rmax, ray_o, ray_d, n_march=20, n_bisect=8, n_newton=3, n
 def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_unit=0.0, eps_px=0.125, n_march=20,
              n_bisect=16, n_newton=3, normals=True, image_width=0, bound_map=None, stream=None):
     """Rendered-radius trace with the adaptive bisection budget: returns
-    t, (R, grad), normal, sign of r (int8), F evaluations per ray (uint8)."""
-    N = lut_n(lut)
+    t, (R, grad), normal, sign of r (int8), F evaluations per ray (uint8).
+    lut: TEXEL or CELL (last dimension 16)."""
+    N, flags = _layout_flags(lut, signed)
     P = ray_o.shape[0]
     dev = ray_o.device
     t = torch.empty(P, dtype=torch.float32, device=dev)
@@ -627,7 +637,7 @@ def trace_ex(lut, center, rmax, ray_o, ray_d, scale=1.0, signed=False, px_per_un
     sgn = torch.empty(P, dtype=torch.int8, device=dev)
     ev = torch.empty(P, dtype=torch.uint8, device=dev)
     bb, bp = _bound_fields(bound_map)
-    prm = shm_trace_params(float(scale), SHM_SIGNED if signed else 0, n_march, n_bisect, n_newton, float(px_per_unit),
+    prm = shm_trace_params(float(scale), flags, n_march, n_bisect, n_newton, float(px_per_unit),
                            float(eps_px), int(image_width), bb, bp)
     shm_trace_radial_ex(lut, _dtype_code(lut), N, center, rmax, prm, ray_o, ray_d, P, t, out, nrm, sgn, ev, stream)
     return t, out, nrm, sgn, ev

@@ -596,7 +596,7 @@ static int check_trace_params(const shm_trace_params* tp)
 {
     if (!tp) return fail(SHM_ERR_INVALID_ARG, "trace: null params");
     if (!(tp->scale > 0.0f) || !std::isfinite(tp->scale)) return fail(SHM_ERR_INVALID_ARG, "trace: scale must be positive and finite");
-    if (tp->flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "trace: unknown flags 0x%x", tp->flags);
+    if (tp->flags & ~(SHM_SIGNED | SHM_CELL_LUT)) return fail(SHM_ERR_INVALID_ARG, "trace: unknown flags 0x%x", tp->flags);
     if (tp->n_march < 1 || tp->n_bisect < 0 || tp->n_newton < 0 || tp->n_march + tp->n_bisect + tp->n_newton + 1 > 64)
         return fail(SHM_ERR_INVALID_ARG, "trace: iteration counts must satisfy n_march >= 1 and total <= 64");
     if (!std::isfinite(tp->px_per_unit) || tp->px_per_unit < 0.0f)
@@ -627,7 +627,8 @@ int shm_trace_radial_ex(const void* lut, int32_t dtype, int32_t N, const float* 
                     params->image_width);
     if (P == 0) return SHM_OK;
     if (!lut || !ray_o || !ray_d || !t_out || !out) return fail(SHM_ERR_INVALID_ARG, "trace: null pointer");
-    if (!aligned(lut, dtype == SHM_F16 ? 8 : 16) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "trace: misaligned buffer");
+    const size_t al = (dtype == SHM_F16 && !(params->flags & SHM_CELL_LUT)) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "trace: misaligned buffer");
     return launch_trace(lut, dtype, N, center, rmax, params->scale, params->flags, params->px_per_unit, params->eps_px,
                         ray_o, ray_d, P, params->image_width, params->bound_map, params->bound_blocks,
                         params->n_march, params->n_bisect, params->n_newton, t_out, out, normal, sign, evals, stream);
@@ -647,11 +648,11 @@ int shm_lut_bound_map(const void* lut, int32_t dtype, int32_t N, int32_t flags, 
 {
     clear_error();
     if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bound_map: bad dtype or N");
-    if (flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "bound_map: unknown flags 0x%x", flags);
+    if (flags & ~(SHM_SIGNED | SHM_CELL_LUT)) return fail(SHM_ERR_INVALID_ARG, "bound_map: unknown flags 0x%x", flags);
     if (blocks < 1 || blocks > SHM_MAX_BOUND_BLOCKS)
         return fail(SHM_ERR_INVALID_ARG, "bound_map: blocks must be 1..%d", SHM_MAX_BOUND_BLOCKS);
     if (!lut || !map_out) return fail(SHM_ERR_INVALID_ARG, "bound_map: null pointer");
-    if (!aligned(map_out, 4) || !aligned(lut, dtype == SHM_F16 ? 2 : 4))
+    if (!aligned(map_out, 4) || !aligned(lut, (flags & SHM_CELL_LUT) ? 16 : (dtype == SHM_F16 ? 2 : 4)))
         return fail(SHM_ERR_INVALID_ARG, "bound_map: misaligned buffer");
     return launch_bound_map(lut, dtype, N, flags, blocks, map_out, stream);
 }
@@ -660,9 +661,10 @@ int shm_lut_rmax(const void* lut, int32_t dtype, int32_t N, int32_t flags, float
 {
     clear_error();
     if (!valid_dtype(dtype) || !valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: bad dtype or N");
-    if (flags & ~SHM_SIGNED) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: unknown flags 0x%x", flags);
+    if (flags & ~(SHM_SIGNED | SHM_CELL_LUT)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: unknown flags 0x%x", flags);
     if (!lut || !rmax_out) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: null pointer");
-    if (!aligned(rmax_out, 4)) return fail(SHM_ERR_INVALID_ARG, "lut_rmax: misaligned output");
+    if (!aligned(rmax_out, 4) || ((flags & SHM_CELL_LUT) && !aligned(lut, 16)))
+        return fail(SHM_ERR_INVALID_ARG, "lut_rmax: misaligned buffer");
     return launch_lut_rmax(lut, dtype, N, flags, rmax_out, stream);
 }
 

@@ -20,6 +20,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include "shm_device.hpp"
 #include "shm_internal.hpp"
 
 namespace shm {
@@ -658,17 +659,31 @@ int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, vo
 // ---------------------------------------------------------------------------
 // Largest Bezier control point of cell (i0, j0) of a face (convex hull
 // bound of its bicubic patch); with absval the largest |control point|.
-template <bool F16>
+template <bool F16, bool CELL>
 __device__ __forceinline__ float cell_bezier_max(const void* __restrict__ lut, int N, int face, int i0, int j0,
                                                  bool absval)
 {
     const int P = N + 2;
     float G[4][4];  // [s-index over (p0, m0, p1, m1)][t-index likewise]
+    Foot F;
+    if constexpr (CELL) {  // the cell's footprint as a query decodes it
+        Loc L{};
+        L.face = face;
+        L.i0 = i0;
+        L.j0 = j0;
+        F = load_foot<F16, true>(lut, N, L);
+    }
     for (int dj = 0; dj < 2; ++dj)
         for (int di = 0; di < 2; ++di) {
             const int64_t t = ((int64_t)(face * P + j0 + dj) * P + i0 + di) * 4;
             float c[4];
-            if constexpr (F16) {
+            if constexpr (CELL) {
+                const float4 v = F.c[dj * 2 + di];
+                c[0] = v.x;
+                c[1] = v.y;
+                c[2] = v.z;
+                c[3] = v.w;
+            } else if constexpr (F16) {
                 const __half* h = reinterpret_cast<const __half*>(lut) + t;
                 for (int k = 0; k < 4; ++k) c[k] = __half2float(h[k]);
             } else {
@@ -701,7 +716,7 @@ __device__ __forceinline__ float cell_bezier_max(const void* __restrict__ lut, i
     return best;
 }
 
-template <bool F16>
+template <bool F16, bool CELL>
 __global__ void k_lut_rmax(const void* __restrict__ lut, int N, int absval, unsigned int* __restrict__ out_bits)
 {
     const int C = N + 1;
@@ -710,7 +725,7 @@ __global__ void k_lut_rmax(const void* __restrict__ lut, int N, int absval, unsi
     if (i < 6 * C * C) {
         const int face = i / (C * C), rem = i - face * C * C;
         const int j0 = rem / C, i0 = rem - j0 * C;
-        best = fmaxf(best, cell_bezier_max<F16>(lut, N, face, i0, j0, absval != 0));
+        best = fmaxf(best, cell_bezier_max<F16, CELL>(lut, N, face, i0, j0, absval != 0));
     }
     // wave reduction, then one atomic per wave
     for (int off = 32; off > 0; off >>= 1) best = fmaxf(best, __shfl_xor(best, off));
@@ -724,7 +739,7 @@ __global__ void k_lut_rmax(const void* __restrict__ lut, int N, int absval, unsi
 // covered).  One 64-lane workgroup per block: lanes stride over the cells,
 // then a wave maximum.  The trace uses it to skip march samples that are
 // provably outside the surface.
-template <bool F16>
+template <bool F16, bool CELL>
 __global__ void k_bound_map(const void* __restrict__ lut, int N, int absval, int B, float* __restrict__ map)
 {
     const int blk = blockIdx.x;
@@ -737,7 +752,7 @@ __global__ void k_bound_map(const void* __restrict__ lut, int N, int absval, int
     float best = 0.0f;
     for (int k = threadIdx.x; k < n; k += 64) {
         const int j0 = j_lo + k / wi, i0 = i_lo + k % wi;
-        best = fmaxf(best, cell_bezier_max<F16>(lut, N, face, i0, j0, absval != 0));
+        best = fmaxf(best, cell_bezier_max<F16, CELL>(lut, N, face, i0, j0, absval != 0));
     }
     for (int off = 32; off > 0; off >>= 1) best = fmaxf(best, __shfl_xor(best, off));
     if (threadIdx.x == 0) map[blk] = best;
@@ -753,10 +768,14 @@ int launch_lut_rmax(const void* lut, int dtype, int N, int flags, float* rmax_ou
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, bits, 0u);
     const int n = 6 * (N + 1) * (N + 1);
     const int absval = (flags & SHM_SIGNED) ? 1 : 0;
-    if (dtype == SHM_F16)
-        hipLaunchKernelGGL(k_lut_rmax<true>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, absval, bits);
-    else
-        hipLaunchKernelGGL(k_lut_rmax<false>, dim3((n + 255) / 256), dim3(256), 0, stream, lut, N, absval, bits);
+    const dim3 grid((n + 255) / 256), bl(256);
+    if (flags & SHM_CELL_LUT) {
+        if (dtype == SHM_F16) hipLaunchKernelGGL((k_lut_rmax<true, true>), grid, bl, 0, stream, lut, N, absval, bits);
+        else hipLaunchKernelGGL((k_lut_rmax<false, true>), grid, bl, 0, stream, lut, N, absval, bits);
+    } else {
+        if (dtype == SHM_F16) hipLaunchKernelGGL((k_lut_rmax<true, false>), grid, bl, 0, stream, lut, N, absval, bits);
+        else hipLaunchKernelGGL((k_lut_rmax<false, false>), grid, bl, 0, stream, lut, N, absval, bits);
+    }
     hipLaunchKernelGGL(k_bits_to_float, dim3(1), dim3(1), 0, stream, bits, rmax_out);
     SHM_LAUNCH_CHECK();
     return SHM_OK;
@@ -766,10 +785,13 @@ int launch_bound_map(const void* lut, int dtype, int N, int flags, int blocks, f
 {
     const int absval = (flags & SHM_SIGNED) ? 1 : 0;
     const dim3 grid((unsigned)(6 * blocks * blocks)), bl(64);
-    if (dtype == SHM_F16)
-        hipLaunchKernelGGL(k_bound_map<true>, grid, bl, 0, stream, lut, N, absval, blocks, map);
-    else
-        hipLaunchKernelGGL(k_bound_map<false>, grid, bl, 0, stream, lut, N, absval, blocks, map);
+    if (flags & SHM_CELL_LUT) {
+        if (dtype == SHM_F16) hipLaunchKernelGGL((k_bound_map<true, true>), grid, bl, 0, stream, lut, N, absval, blocks, map);
+        else hipLaunchKernelGGL((k_bound_map<false, true>), grid, bl, 0, stream, lut, N, absval, blocks, map);
+    } else {
+        if (dtype == SHM_F16) hipLaunchKernelGGL((k_bound_map<true, false>), grid, bl, 0, stream, lut, N, absval, blocks, map);
+        else hipLaunchKernelGGL((k_bound_map<false, false>), grid, bl, 0, stream, lut, N, absval, blocks, map);
+    }
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }

@@ -24,13 +24,13 @@ struct FEval {
 // root and reciprocal square root (~1 ulp each) instead of the correctly
 // rounded sequences; the final evaluation, whose R, gradient and normal are
 // returned, is the exact query.
-template <bool FP16, bool FAST = true>
+template <bool FP16, bool CELL, bool FAST = true>
 __device__ __forceinline__ FEval trace_eval(const void* __restrict__ lut, int N, float ox, float oy, float oz,
                                             float dx, float dy, float dz, float t, float scale, bool is_signed)
 {
     FEval E;
     const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
-    const float4 r = rendered(query_one<FP16, false, FAST>(lut, N, px, py, pz), scale, is_signed, &E.sgn);
+    const float4 r = rendered(query_one<FP16, CELL, FAST>(lut, N, px, py, pz), scale, is_signed, &E.sgn);
     const float p2 = px * px + py * py + pz * pz;
     const float il = FAST ? __builtin_amdgcn_rsqf(p2) : 1.0f / sqrtf(p2);
     const float len = FAST ? p2 * il : sqrtf(p2);
@@ -106,7 +106,7 @@ __device__ __noinline__ int bisect_budget(float ox, float oy, float oz, float rm
     return k;
 }
 
-template <bool FP16, bool NRM>
+template <bool FP16, bool CELL, bool NRM>
 __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int N, float cx, float cy, float cz,
                                                float rmax, float scale, int is_signed_i, float px_focal, float eps_px,
                                                const float* __restrict__ ray_o, const float* __restrict__ ray_d,
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
                 const float tk = t0 + (float)k * step;
                 if (bmap && outside_bound(bmap, bmap_b, scale, ox + tk * dx, oy + tk * dy, oz + tk * dz))
                     continue;  // F > 0 there for certain: the march goes on, as it would after evaluating
-                const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, tk, scale, is_signed);
+                const FEval E = trace_eval<FP16, CELL>(lut, N, ox, oy, oz, dx, dy, dz, tk, scale, is_signed);
                 ++evals;
                 if (E.F < 0.0f) {
                     hit = true;
@@ -171,14 +171,14 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
             if (hit) {
                 for (int it = 0; it < n_bisect; ++it) {
                     const float mid = 0.5f * (lo + hi);
-                    const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, mid, scale, is_signed);
+                    const FEval E = trace_eval<FP16, CELL>(lut, N, ox, oy, oz, dx, dy, dz, mid, scale, is_signed);
                     ++evals;
                     if (E.F < 0.0f) hi = mid;
                     else lo = mid;
                 }
                 t = 0.5f * (lo + hi);
                 for (int it = 0; it < n_newton; ++it) {
-                    const FEval E = trace_eval<FP16>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
+                    const FEval E = trace_eval<FP16, CELL>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
                     ++evals;
                     if (E.F < 0.0f) hi = t;
                     else lo = t;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_trace(const void* __restrict__ lut, int
         }
     }
     if (hit) {
-        const FEval E = trace_eval<FP16, false>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
+        const FEval E = trace_eval<FP16, CELL, false>(lut, N, ox, oy, oz, dx, dy, dz, t, scale, is_signed);
         ++evals;
         if (sign_out) sign_out[r] = (int8_t)E.sgn;
         t_out[r] = t;
@@ -234,16 +234,17 @@ int launch_trace(const void* lut, int dtype, int N, const float* center, float r
     const dim3 g((unsigned)blocks), bl(256);
     const float cx = center[0], cy = center[1], cz = center[2];
     const int sgn = (flags & SHM_SIGNED) ? 1 : 0;
-#define SHM_T(F, NR)                                                                                                  \
-    hipLaunchKernelGGL((k_trace<F, NR>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, scale, sgn, px_focal, eps_px,      \
+    const bool cell = (flags & SHM_CELL_LUT) != 0;
+#define SHM_T(F, C, NR)                                                                                               \
+    hipLaunchKernelGGL((k_trace<F, C, NR>), g, bl, 0, stream, lut, N, cx, cy, cz, rmax, scale, sgn, px_focal, eps_px,   \
                        ray_o, ray_d, P, image_width, tiles_x, bound_blocks > 0 ? bound_map : nullptr, bound_blocks,   \
                        n_march, n_bisect, n_newton, t_out, out, normal, sign, evals)
     if (dtype == SHM_F16) {
-        if (normal) SHM_T(true, true);
-        else SHM_T(true, false);
+        if (cell) { if (normal) SHM_T(true, true, true); else SHM_T(true, true, false); }
+        else { if (normal) SHM_T(true, false, true); else SHM_T(true, false, false); }
     } else {
-        if (normal) SHM_T(false, true);
-        else SHM_T(false, false);
+        if (cell) { if (normal) SHM_T(false, true, true); else SHM_T(false, true, false); }
+        else { if (normal) SHM_T(false, false, true); else SHM_T(false, false, false); }
     }
 #undef SHM_T
     SHM_LAUNCH_CHECK();

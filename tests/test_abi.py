@@ -127,12 +127,19 @@ def test_render_validation():
 
     assert tr(prm(), P=0) == shm.SHM_OK
     assert tr(prm(flags=shm.SHM_SIGNED, px_per_unit=900.0, eps_px=0.1), P=0) == shm.SHM_OK
-    for bad in (prm(scale=0.0), prm(scale=float("inf")), prm(flags=2), prm(n_march=0), prm(n_bisect=60),
+    for bad in (prm(scale=0.0), prm(scale=float("inf")), prm(flags=4), prm(n_march=0), prm(n_bisect=60),
                 prm(px_per_unit=-1.0), prm(px_per_unit=float("nan")), prm(px_per_unit=100.0, eps_px=0.0),
                 prm(image_width=-1), prm(image_width=3), prm(image_width=20),
                 prm(bound_blocks=-1), prm(bound_blocks=65, bound_map=256), prm(bound_blocks=4)):
         assert tr(bad) == shm.SHM_ERR_INVALID_ARG  # 10 rays: not whole rows of 3 or 20; map sizes
     assert tr(prm(image_width=7), P=0) == shm.SHM_OK
+    # cell LUTs are read with 16-byte loads, FP16 ones included
+    p8 = ctypes.c_void_p(264)
+    assert call("shm_trace_radial_ex", p8, 1, 8, c, 1.0, ctypes.byref(prm(flags=shm.SHM_CELL_LUT)), p, p, 10, p, p,
+                None, None, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_lut_rmax", p8, 1, 8, shm.SHM_CELL_LUT, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_lut_bound_map", p8, 1, 8, shm.SHM_CELL_LUT, 4, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_lut_rmax", p, 0, 8, 4, p, None) == shm.SHM_ERR_INVALID_ARG  # unknown flag
     assert call("shm_trace_radial_ex", p, 0, 8, c, 1.0, None, p, p, 10, p, p, None, None, None, None) == shm.SHM_ERR_INVALID_ARG
     q = lambda scale, flags, Q=10: call("shm_query_scaled", p, 0, 0, 8, 1, p, Q, scale, flags, p, None, None, None)
     assert q(0.0, 0) == shm.SHM_ERR_INVALID_ARG
@@ -140,10 +147,10 @@ def test_render_validation():
     assert q(1.0, 4) == shm.SHM_ERR_INVALID_ARG
     assert q(1.0, shm.SHM_SIGNED, Q=0) == shm.SHM_OK
     assert call("shm_query_scaled", p, 0, 0, 8, 1, None, 10, 1.0, 0, p, None, None, None) == shm.SHM_ERR_INVALID_ARG
-    assert call("shm_lut_rmax", p, 0, 8, 2, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_lut_rmax", p, 0, 8, 4, p, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_lut_rmax", p, 0, 8, 0, None, None) == shm.SHM_ERR_INVALID_ARG
     bm = lambda *a: call("shm_lut_bound_map", *a)
-    for args in ((p, 0, 8, 0, 0, p), (p, 0, 8, 0, 65, p), (p, 0, 8, 2, 8, p), (None, 0, 8, 0, 8, p), (p, 0, 8, 0, 8, None),
+    for args in ((p, 0, 8, 0, 0, p), (p, 0, 8, 0, 65, p), (p, 0, 8, 4, 8, p), (None, 0, 8, 0, 8, p), (p, 0, 8, 0, 8, None),
                  (p, 0, 0, 0, 8, p), (p, 5, 8, 0, 8, p), (p, 0, 8, 0, 8, ctypes.c_void_p(258))):
         assert bm(*args, None) == shm.SHM_ERR_INVALID_ARG, args
 

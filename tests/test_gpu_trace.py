@@ -176,3 +176,46 @@ def test_trace_bound_map_same_bits(dt):
     b = shm.trace(lut, (0.0, 0.0, 0.0), rmax, og, dg, bound_map=shm.lut_bound_map(lut, blocks=8))
     for x, y in zip(a, b):
         assert same_bits(x, y)
+
+
+def test_trace_cells_same_bits_and_f16_accuracy():
+    """Ray casting a CELL LUT: FP32 cells give the bits of the FP32 texel
+    LUT (the same footprints), bounds and bound maps included; FP16 cells
+    (value differences, from the FP32 data) give the bits of the FP32 cells
+    they decode to, with and without the bound map; and their normals stay
+    far closer to the FP32 trace's than plain FP16 texels'."""
+    from parity import decode_f16_cells
+    N = 64
+    lut = gpu(bumps_lut(N))[None]
+    cells = shm.to_cells(lut)
+    c16 = shm.cells_to_f16(cells)
+    dec = gpu(decode_f16_cells(c16.cpu().numpy()))
+    o, d = workloads.camera_rays(96, 64, vfov_deg=30.0)
+    og, dg = gpu(o), gpu(d)
+    rmax = float(shm.lut_rmax(lut[0]).item()) * 1.0001
+    assert same_bits(shm.lut_rmax(cells[0]), shm.lut_rmax(lut[0]))
+    assert same_bits(shm.lut_bound_map(cells[0], blocks=16), shm.lut_bound_map(lut[0], blocks=16))
+    assert same_bits(shm.lut_bound_map(c16[0], blocks=16), shm.lut_bound_map(dec[0], blocks=16))
+    assert same_bits(shm.lut_rmax(c16[0]), shm.lut_rmax(dec[0]))
+    t32 = shm.trace(lut[0], (0.0, 0.0, 0.0), rmax, og, dg)
+    for x, y in zip(t32, shm.trace(cells[0], (0.0, 0.0, 0.0), rmax, og, dg)):
+        assert same_bits(x, y)
+    rmax16 = float(shm.lut_rmax(c16[0]).item()) * 1.0001
+    kw = dict(image_width=96, bound_map=shm.lut_bound_map(c16[0]))
+    a = shm.trace(c16[0], (0.0, 0.0, 0.0), rmax16, og, dg)
+    for x, y in zip(a, shm.trace(dec[0], (0.0, 0.0, 0.0), rmax16, og, dg)):
+        assert same_bits(x, y)
+    for x, y in zip(a, shm.trace(c16[0], (0.0, 0.0, 0.0), rmax16, og, dg, **kw)):
+        assert same_bits(x, y)
+    t16 = shm.trace(lut[0].half(), (0.0, 0.0, 0.0), rmax16, og, dg)
+    hit = torch.isfinite(t32[0]) & torch.isfinite(a[0]) & torch.isfinite(t16[0])
+    assert hit.float().mean().item() > 0.2
+    ang_c = angle_deg(a[2][hit].cpu().numpy(), t32[2][hit].cpu().numpy())
+    ang_t = angle_deg(t16[2][hit].cpu().numpy(), t32[2][hit].cpu().numpy())
+    print(f"FP16 trace normal vs FP32, mean / max deg: cells {ang_c.mean():.3g} / {ang_c.max():.3g}, "
+          f"texels {ang_t.mean():.3g} / {ang_t.max():.3g}")
+    print(f"  median {np.median(ang_c):.3g} / {np.median(ang_t):.3g}, p99 {np.quantile(ang_c, 0.99):.3g} / "
+          f"{np.quantile(ang_t, 0.99):.3g}")
+    # (a few grazing rays, where a small shift of the hit swings the normal,
+    # make up the tails of both)
+    assert ang_c.mean() < 0.05 * ang_t.mean() and np.median(ang_c) < 0.05 * np.median(ang_t)
