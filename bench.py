@@ -214,10 +214,21 @@ def main():
     dst.copy_(src)
     ms_copy = t_gpu(lambda: dst.copy_(src), 5)
     copy_gbs = 2 * src.numel() * 8 / ms_copy / 1e6
-    del src, dst
+    # and a read-only stream: a sum over the same 4 GiB
+    acc = torch.empty((), dtype=torch.float64, device=DEV)
+    torch.sum(src, dim=0, out=acc)
+    ms_read = t_gpu(lambda: torch.sum(src, dim=0, out=acc), 5)
+    read_gbs = src.numel() * 8 / ms_read / 1e6
+    del src, dst, acc
     result["roofline"]["measured_copy_gbs"] = copy_gbs
     result["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
-    log(f"device copy {copy_gbs:.0f} GB/s (read + write); headline = {achieved / copy_gbs:.3f} of it")
+    result["roofline"]["measured_stream_read_gbs"] = read_gbs
+    result["roofline"]["frac_of_measured_stream_read"] = achieved / read_gbs
+    if traffic:  # real HBM bytes per launch (counters) at the measured duration
+        result["roofline"]["traffic_gbs"] = traffic / (ms * 1e-3) / 1e9
+        result["roofline"]["traffic_frac_of_measured_stream_read"] = traffic / (ms * 1e-3) / 1e9 / read_gbs
+    log(f"device copy {copy_gbs:.0f} GB/s (read + write), stream read {read_gbs:.0f} GB/s; headline = "
+        f"{achieved / copy_gbs:.3f} / {achieved / read_gbs:.3f} of them")
     # context on exactly the headline's access pattern: PyTorch gathering the
     # same 64 B cells (index_select of the cell rows by each query's cell key;
     # it writes the 64 B rows where the query writes 16 B results)
