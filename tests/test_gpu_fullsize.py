@@ -179,3 +179,51 @@ def test_fit_step_full_size():
         assert far <= 1e-5 * dp.numel() and dp.max().item() <= 2 * 1e-3, (step, far)
     moved = (a.lut != lut)[0, :, 1:N + 1, 1:N + 1].float().mean().item()
     assert moved > 0.999, moved
+
+
+def decode_cells_gpu(c16):
+    """The FP32 cells FP16 cells decode to (FP32 additions, on the GPU)."""
+    c = c16.float().reshape(-1, 4, 4)
+    c[:, 1:, 0] += c[:, :1, 0]
+    return c.reshape(c16.shape)
+
+
+def test_glyph_field_f16_cells_full_size():
+    """The benchmark's FP16 cell form (32,768 glyphs, N = 32, 8,388,608
+    queries; cells made from the FP32 cells) gives the bits of the FP32 cell
+    query on the cells it decodes to, for every query."""
+    W = bench.W2
+    n, N, qp = W["n_glyph"], W["N"], W["q_per"]
+    c, dirs = bench.setup_w2()
+    d_t = torch.as_tensor(dirs).to(DEV)
+    cells = shm.to_cells(shm.bake_sh(torch.as_tensor(c).to(DEV), N))
+    c16 = shm.cells_to_f16(cells)
+    del cells
+    dec = decode_cells_gpu(c16)
+    a = torch.empty((n * qp, 4), device=DEV)
+    b = torch.empty((n * qp, 4), device=DEV)
+    shm.shm_query_value_grad(c16, shm.SHM_F16, shm.SHM_LAYOUT_CELL, N, n, d_t, qp, a)
+    shm.shm_query_value_grad(dec, shm.SHM_F32, shm.SHM_LAYOUT_CELL, N, n, d_t, qp, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_trace_f16_cells_full_size():
+    """The benchmark's FP16-cell trace (1920 x 1080, N = 256, 8 x 8 tiles,
+    the bound map of the FP16 cells) gives the bits of the FP32-cell trace
+    of the decoded cells with that one's own bound map."""
+    N = 256
+    mu, amp, width = workloads.bump_params(workloads.rng_for(3))
+    md = shm.margin_dirs(N).cpu().numpy().reshape(-1, 3)
+    samples = workloads.bumps_value(mu, amp, width, 1.0, md).astype(np.float32)
+    c16 = shm.cells_to_f16(shm.to_cells(shm.bake_fd(torch.as_tensor(samples).to(DEV), N)))
+    dec = decode_cells_gpu(c16)
+    rmax = float(shm.lut_rmax(c16[0]).item()) * 1.0001
+    assert float(shm.lut_rmax(dec[0]).item()) * 1.0001 == rmax
+    o, d = workloads.camera_rays(1920, 1080)
+    og, dg = torch.as_tensor(o).to(DEV), torch.as_tensor(d).to(DEV)
+    a = shm.trace(c16[0], (0.0, 0.0, 0.0), rmax, og, dg, image_width=1920, bound_map=shm.lut_bound_map(c16[0]))
+    b = shm.trace(dec[0], (0.0, 0.0, 0.0), rmax, og, dg, image_width=1920, bound_map=shm.lut_bound_map(dec[0]))
+    for x, y in zip(a, b):
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32))
+    assert 0.2 < torch.isfinite(a[0]).float().mean().item() < 0.8
