@@ -342,6 +342,21 @@ class LutFit:
     def lut(self):
         return self.bufs[self.cur]
 
+    def state_dict(self):
+        """Checkpoint of the fit: current LUT, Adam moments and step count
+        (tensors cloned; save with torch.save)."""
+        return {"lut": self.lut.clone(), "m": self.m.clone(), "v": self.v.clone(), "t": int(self.t)}
+
+    def load_state_dict(self, state):
+        """Resume from state_dict(): the following steps continue the fit
+        exactly (the same bits as never having stopped)."""
+        if state["lut"].shape != self.lut.shape or state["m"].shape != self.m.shape:
+            raise ValueError("checkpoint of a LUT of another shape")
+        self.lut.copy_(state["lut"])
+        self.m.copy_(state["m"])
+        self.v.copy_(state["v"])
+        self.t = int(state["t"])
+
     def step(self, stream=None):
         self.t += 1
         N, Q = self.N, self.Q

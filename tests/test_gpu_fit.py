@@ -228,3 +228,27 @@ def test_fused_steps_replay_from_a_graph():
         assert torch.equal(g_fit.lut, e_fit.lut), rep
         assert torch.equal(g_fit.m, e_fit.m) and torch.equal(g_fit.v, e_fit.v), rep
         assert not torch.equal(g_fit.lut, lut)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_fit_checkpoint_resume(tmp_path, fused):
+    """Five steps without stopping equal three steps, a checkpoint written
+    with torch.save and read back with weights_only=True into a new fit, and
+    two more steps: the same LUT and moments, bit for bit."""
+    N, Q = 20, 25013
+    lut, dirs, tv, tn = fit_problem(N, Q, seed=12)
+    kw = dict(w_value=30.0, lr_value=1e-3, lr_deriv=3e-4, fused=fused)
+    a = shm.LutFit(lut.clone(), dirs, tv, tn, **kw)
+    for _ in range(5):
+        a.step()
+    b = shm.LutFit(lut.clone(), dirs, tv, tn, **kw)
+    for _ in range(3):
+        b.step()
+    path = tmp_path / "fit.pt"
+    torch.save(b.state_dict(), path)
+    c = shm.LutFit(torch.zeros_like(lut), dirs, tv, tn, **kw)
+    c.load_state_dict(torch.load(path, weights_only=True))
+    for _ in range(2):
+        c.step()
+    torch.cuda.synchronize()
+    assert torch.equal(a.lut, c.lut) and torch.equal(a.m, c.m) and torch.equal(a.v, c.v) and c.t == 5
