@@ -65,6 +65,17 @@ struct Loc {
 // (the residual sc - a ma is still exact), but a direction within an ulp of
 // a cell boundary may be given to the neighbouring cell, whose patch agrees
 // there by C1 continuity; only the ray-casting iterations use it.
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+// consecutive logical tiles share an XCD (and its L2): XCD x takes the
+// contiguous range of logical ids after those of XCDs 0..x-1.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, local = b >> 3;
+    const int start = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    return start + local;
+}
+
 // Power-of-two prescale for a direction with largest component ma: 2^100
 // below 2^-60 and 2^-100 above 2^60, else 1, so that the scaled ma lies in
 // [2^-49, 2^40] for every finite nonzero ma (subnormal ones included) and its

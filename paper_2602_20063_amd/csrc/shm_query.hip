@@ -41,15 +41,6 @@ __device__ __forceinline__ void st_out(float* out, int64_t q, float4 r)
 #endif
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
-// consecutive logical tiles share an XCD (and its L2).
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int xcd = b & 7, local = b >> 3;
-    const int start = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
-    return start + local;
-}
 
 template <bool FP16, bool CELL, bool NRM>
 __global__ __launch_bounds__(256) void k_query_uniform(const void* __restrict__ lut, int N, int64_t lut_elems,
