@@ -109,6 +109,105 @@ def read_counters():
 
 
 # ---------------------------------------------------------------------------
+# workload 1: one SH glyph, L = 4, N = 10, 65,536 directions (parity size)
+# ---------------------------------------------------------------------------
+W1 = dict(L=4, N=10, Q=65536)
+
+
+def setup_w1():
+    r = workloads.rng_for(1)
+    c = workloads.sh_glyph_coeffs(W1["L"], 1, r).astype(np.float32)
+    dirs = workloads.uniform_dirs(W1["Q"], r)
+    return c, dirs
+
+
+def run_cfg1():
+    """Workload 1 on the GPU: the bake of the one glyph and the query of its
+    65,536 directions (TEXEL and CELL).  At this size every launch is a few
+    microseconds: launch-latency bound, no roofline claim."""
+    c, dirs = setup_w1()
+    L, N, Q = W1["L"], W1["N"], W1["Q"]
+    c_t, d_t = to_dev(c), to_dev(dirs)
+    ws = torch.empty(max(shm.shm_bake_sh_lut_workspace(L, N), 1), dtype=torch.uint8, device=DEV)
+    lut = torch.empty((1, 6, N + 2, N + 2, 4), device=DEV)
+    bake = lambda: shm.shm_bake_sh_lut(c_t, L, N, 1, shm.SHM_F32, lut, ws)
+    bake()
+    cells = shm.to_cells(lut)
+    out = torch.empty((Q, 4), device=DEV)
+    qt = lambda: shm.shm_query_value_grad(lut, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL, N, 1, d_t, Q, out)
+    qc = lambda: shm.shm_query_value_grad(cells, shm.SHM_F32, shm.SHM_LAYOUT_CELL, N, 1, d_t, Q, out)
+    qt(); qc()
+    ms_b, ms_t, ms_c = t_gpu(bake, 200), t_gpu(qt, 200), t_gpu(qc, 200)
+    res = {"queries": Q, "sh_order": L, "face_N": N, "bake_us": ms_b * 1e3, "query_texel_us": ms_t * 1e3,
+           "query_cell_us": ms_c * 1e3, "queries_per_s_texel": Q / ms_t * 1e3, "queries_per_s_cell": Q / ms_c * 1e3,
+           "note": "launch-latency bound (1.85 MB per launch): no roofline claim"}
+    qt()
+    torch.cuda.synchronize()
+    return res, {"c": c, "dirs": dirs, "out": out.cpu().numpy(), "lut": lut[0].cpu().numpy(),
+                 "keys": shm.cell_keys(N, d_t).cpu().numpy()}
+
+
+def run_probes(lut_cell, dirs_t, out, ms_query):
+    """The memory system's rates for the headline's own access pattern
+    (probe kernels of the library, shm_probe.h), in the same run:
+      * streaming read of the whole cell LUT (13.7 GB);
+      * random 16/32/64/128 B reads, 256 per glyph region of 418 KB (the
+        query's regions and launch mapping), and 64 B reads anywhere in the
+        13.7 GB;
+      * the query's full memory pattern: one random 64 B cell per query
+        plus the streamed 12 B direction and 16 B result, no arithmetic.
+    The last is the ceiling the query's rate is set against."""
+    n, N, qp = W2["n_glyph"], W2["N"], W2["q_per"]
+    Q = n * qp
+    region = shm.shm_lut_elems(N, shm.SHM_LAYOUT_CELL) * 4
+    nbytes = lut_cell.numel() * 4
+    sink = torch.zeros(4, device=DEV)
+    res = {"region_bytes": region, "requests": Q}
+    f = lambda: shm.shm_probe_stream_read(lut_cell, nbytes, sink)
+    f()
+    ms = t_gpu(f, 5)
+    res["stream_read_gbs"] = nbytes / ms / 1e6
+    for req in (16, 32, 64, 128):
+        f = lambda: shm.shm_probe_gather(lut_cell, region, n, qp, req, 20063, None, sink)
+        f()
+        ms = t_gpu(f, 10)
+        res[f"gather_{req}B_regions_per_s"] = Q / ms * 1e3
+        res[f"gather_{req}B_regions_us"] = ms * 1e3
+    f = lambda: shm.shm_probe_gather(lut_cell, nbytes, 1, Q, 64, 20063, None, sink)
+    f()
+    ms = t_gpu(f, 10)
+    res["gather_64B_anywhere_per_s"] = Q / ms * 1e3
+    f = lambda: shm.shm_probe_gather(lut_cell, region, n, qp, 64, 20063, dirs_t, out)
+    f()
+    ms = t_gpu(f, 20)
+    res["query_pattern_us"] = ms * 1e3
+    res["query_pattern_per_s"] = Q / ms * 1e3
+    res["query_over_pattern_time"] = ms_query / ms
+    log("probes", res)
+    return res
+
+
+def run_quality():
+    """Value-only accuracy of the reconstructions the paper compares (Table
+    psnr_value: one L = 8 glyph, 100,000 uniform directions, N = 8, 16, 32),
+    computed on the GPU: Hermite (analytic SH bake, cell query), bilinear and
+    16-tap Catmull-Rom (value-only LUTs of direct SH samples).  The PSNR
+    against the FP64 truth is formed in the CPU leg."""
+    r = workloads.rng_for(2)
+    c = workloads.sh_glyph_coeffs(8, 1, r).astype(np.float32)
+    dirs = workloads.uniform_dirs(100000, r)
+    c_t, d_t = to_dev(c), to_dev(dirs)
+    outs = {}
+    for N in (8, 16, 32):
+        lut = shm.bake_sh(c_t, N)
+        outs[f"hermite_N{N}"] = shm.query(shm.to_cells(lut), d_t, layout=shm.SHM_LAYOUT_CELL)[:, 0].cpu().numpy()
+        vlut = shm.sh_eval(c_t, shm.margin_dirs(N).reshape(-1, 3))[:, 0].reshape(1, 6, N + 4, N + 4).contiguous()
+        for name, m in (("bilinear", shm.SHM_RECON_BILINEAR_FD), ("catmull_rom", shm.SHM_RECON_BICUBIC)):
+            outs[f"{name}_N{N}"] = shm.query_baseline(vlut, d_t, m)[:, 0].cpu().numpy()
+    return {"c": c[0], "dirs": dirs, "outs": outs}
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +252,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+        # the memory probes on the glyph field's cell LUT: the query's memory
+        # pattern, gathers of 64 and 128 B in glyph regions, a stream read
+        region = shm.shm_lut_elems(N, shm.SHM_LAYOUT_CELL) * 4
+        sink = torch.zeros(4, device=DEV)
+        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 64, 20063, dirs_t, out)
+        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 64, 20063, None, sink)
+        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 128, 20063, None, sink)
+        shm.shm_probe_stream_read(lut_cell, lut_cell.numel() * 4, sink)
+        torch.cuda.synchronize()
         shm.bake_sh(c_t, N)
         Nb, Qb = 512, 1 << 22
         d4 = to_dev(workloads.uniform_dirs(Qb, workloads.rng_for(4)))
@@ -241,15 +349,31 @@ def main():
     result["roofline"]["torch_index_select_same_cells_per_s"] = Q / (ms_gather * 1e-3)
     log(f"torch index_select of the same 64 B cells: {Q / ms_gather / 1e6:.2f} G rows/s "
         f"(the query: {qps / 1e9:.2f} G/s)")
+    # N13: the memory system's rates for this access pattern, same run
+    probes = run_probes(lut_cell, dirs_t, out, ms)
+    step()  # the probe wrote `out`: the headline's results again
+    ceiling = probes["query_pattern_per_s"]
+    result["roofline"]["gather_ceiling_qps"] = ceiling
+    result["roofline"]["frac_of_gather_ceiling"] = qps / ceiling
+    # line model: HBM serves a random request as a whole 128 B line, so the
+    # least traffic per query is one line for the cell + 12 B + 16 B streamed
+    line_q = PEAK_HBM_GBS * 1e9 / 156.0
+    result["roofline"]["line_model"] = {"bytes_per_query": 156, "qps_at_peak": line_q, "frac": qps / line_q}
+    result["roofline"]["probes"] = probes
+    keys2 = shm.cell_keys(N, dirs_t, n_obj=n_glyph).cpu().numpy()
+    torch.cuda.synchronize()
     forms = {}
     sample_out = {}
     if not args.no_forms:
         forms, sample_out = run_forms(c_t, dirs_t, lut_tex, lut_cell, out, ms)
     if not args.no_cpu:
-        cpu, errs = cpu_baseline_leg(c_np, dirs_np, out, sample_out)
+        cpu, errs, oracle_forms, extra = cpu_baseline_leg(c_np, dirs_np, out, sample_out, keys2)
         result["cpu_baseline"] = cpu
         for k, v in errs.items():
             forms.setdefault(k, {})["err_vs_fp64"] = v
+        for k, v in oracle_forms.items():
+            forms.setdefault(k, {})["cpu_oracle"] = v
+        result.update(extra)
     result["forms"] = forms
     print(json.dumps(result))
 
@@ -293,6 +417,9 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
     del lut_b, ws
     log("bake", forms["bake_sh"])
 
+    forms["cfg1_glyph"], sample["cfg1"] = run_cfg1()
+    log("cfg1", forms["cfg1_glyph"])
+    sample["quality"] = run_quality()
     forms["comparison"] = run_comparison(c_t, dirs_t, ms_cell, forms["query_f32_texel"]["ms"])
     log("comparison", forms["comparison"])
     forms["mip_lod"] = run_mip_lod()
@@ -448,7 +575,8 @@ def run_backward_fit():
     adj = abs(lhs - rhs) / (gl_r.double() * Dr.double()).abs().sum().item()
     ks = torch.as_tensor(np.random.default_rng(41).choice(Q, 2000, replace=False), device=DEV)
     bwd_sample = {"lut": lut_r[0].cpu().numpy(), "dirs": dirs[ks].cpu().numpy(), "g": g[ks].cpu().numpy(),
-                  "gd": gd_r[ks].cpu().numpy(), "adjoint_rel": adj}
+                  "gd": gd_r[ks].cpu().numpy(), "adjoint_rel": adj,
+                  "dirs_full": dirs.cpu().numpy(), "g_full": g.cpu().numpy()}
     del lut_r, gl_r, gd_r, Dr, fD
     shm.shm_backward_sort(N, 1, dirs, Q, bctx.ws)  # sort again, code objects now loaded
     ms_sort = t_gpu(lambda: shm.shm_backward_sort(N, 1, dirs, Q, bctx.ws), 3)
@@ -617,7 +745,11 @@ def run_batched():
            "work_items": plan.work_items}
     # sample for the error check: the first 16 objects
     smp = {"coeffs": coeffs[:16], "N": [int(x) for x in spec["N"][:16]], "q": [int(x) for x in Qs[:16]],
-           "dirs": dirs[: int(qb[16])].cpu().numpy(), "out": out16[: int(qb[16])].cpu().numpy()}
+           "dirs": dirs[: int(qb[16])].cpu().numpy(), "out": out16[: int(qb[16])].cpu().numpy(),
+           # every object's FP32 texel LUT (the data the FP16 cells encode), for the oracle's timing
+           "lut_tex": B["lut_tex"].cpu().numpy(), "texel_off": np.asarray(B["texel_off"], np.int64),
+           "N_all": np.asarray(spec["N"], np.int32), "qb_all": np.asarray(qb, np.int64),
+           "q_all": np.asarray(Qs, np.int64), "dirs_all": B["dirs_np"]}
     plan.close()
     return res, smp
 
@@ -694,11 +826,45 @@ def run_trace():
 # CPU baseline leg: the FP64 oracle on the host cores (timing and the error
 # of every GPU form against FP64)
 # ---------------------------------------------------------------------------
-def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
+def cpu_baseline_leg(c_np, dirs_np, out_cell, sample, keys2):
     import oracle
+    from oracle import ties
 
     N, q_per = W2["N"], W2["q_per"]
     ns = CPU_GLYPHS
+    cores = oracle.num_threads()
+    model = ""
+    try:
+        model = next(line.split(":", 1)[1].strip() for line in open("/proc/cpuinfo") if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+
+    def timed(fn, min_s=0.0):
+        """Seconds per call of fn() on all cores, repeated until min_s."""
+        reps, t = 0, 0.0
+        while True:
+            t0 = time.time()
+            fn()
+            t += time.time() - t0
+            reps += 1
+            if t >= min_s or reps >= 1000:
+                return t / reps, reps
+
+    def one_core(fn):
+        oracle.set_threads(1)
+        try:
+            t0 = time.time()
+            fn()
+            return time.time() - t0
+        finally:
+            oracle.set_threads(cores)
+
+    def entry(units, unit, s_all, n_all, s_one, n_one, sample_all, sample_one):
+        return {"value": n_all / s_all, "unit": unit, "cores": cores, "kind": "oracle",
+                "one_core_value": n_one / s_one, "cpu_model": model,
+                "sample": f"all cores: {sample_all}; one core: {sample_one}", "units": units}
+
+    # ---- headline: the glyph field's query, a bounded sample
     c64 = c_np[:ns].astype(np.float64)
     t0 = time.time()
     luts = oracle.bake_sh(c64, N)
@@ -706,31 +872,41 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
     d = dirs_np[: ns * q_per]
     off = np.arange(ns) * (luts[0].size // 4)
     flat = luts.reshape(-1)
-    reps, tq = 0, 0.0
-    while tq < 10.0 and reps < 2000:
-        t0 = time.time()
-        ref = oracle.query_objects(flat, off, [N] * ns, np.arange(ns) * q_per, [q_per] * ns, d)
-        tq += time.time() - t0
-        reps += 1
-    qps = reps * ns * q_per / tq
-    cores = oracle.num_threads()
-    # the same sample on one core
-    oracle.set_threads(1)
-    n1 = ns
-    t0 = time.time()
-    oracle.query_objects(flat, off[:n1], [N] * n1, np.arange(n1) * q_per, [q_per] * n1, d[: n1 * q_per])
-    qps1 = n1 * q_per / (time.time() - t0)
-    oracle.set_threads(cores)
-    model = ""
-    try:
-        model = next(line.split(":", 1)[1].strip() for line in open("/proc/cpuinfo") if line.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+    qfn = lambda k: oracle.query_objects(flat, off[:k], [N] * k, np.arange(k) * q_per, [q_per] * k, d[: k * q_per])
+    ref = qfn(ns)
+    sec, reps = timed(lambda: qfn(ns), 10.0)
+    qps = ns * q_per / sec
+    qps1 = ns * q_per / one_core(lambda: qfn(ns))
     cpu = {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
            "sample": f"{ns} of {W2['n_glyph']} glyphs ({ns * q_per} queries) of the SH glyph field, FP64 oracle "
-                     f"(bake of the sample {bake_s:.1f} s untimed), query repeated {reps}x ({tq:.1f} s)",
+                     f"(its bake of the sample, {bake_s:.1f} s, is timed separately under forms.bake_sh), "
+                     f"query repeated {reps}x ({sec * reps:.1f} s)",
            "one_core_value": qps1, "cpu_model": model}
     log("cpu baseline", cpu)
+    oracle_forms = {}
+    extra = {}
+
+    # ---- FP32/FP64 cell-decision ties (the kernels decide in FP32)
+    t2 = ties.classify(keys2, dirs_np, N, q_per_obj=q_per)
+    cell_ties = {"sh_glyph_field": {k: t2[k] for k in ("queries", "mismatches", "ties_in_band", "not_ties")}}
+    if "cfg1" in sample:
+        s1 = sample["cfg1"]
+        t1 = ties.classify(s1["keys"], s1["dirs"], W1["N"])
+        cell_ties["one_glyph_L4_N10"] = {k: t1[k] for k in ("queries", "mismatches", "ties_in_band", "not_ties")}
+    cell_ties["rule"] = ("faces must agree exactly; a cell may differ from the FP64 decision only where the FP64 "
+                         "coordinate u N + 1/2 lies within twice the FP32 decision's rounding bound of an integer")
+    extra["cell_ties"] = cell_ties
+    log("cell ties", cell_ties)
+
+    # ---- bake of the glyph field: a fixed subset of 1,024 glyphs
+    nb = 1024
+    cb = c_np[:nb].astype(np.float64)
+    sb, _ = timed(lambda: oracle.bake_sh(cb, N), 2.0)
+    s1b = one_core(lambda: oracle.bake_sh(cb[:128], N))
+    oracle_forms["bake_sh"] = entry(nb, "glyphs/s", sb, nb, s1b, 128, f"first {nb} glyphs (N=32, L=8)",
+                                    "first 128 glyphs")
+    log("oracle bake", oracle_forms["bake_sh"])
+
     errs = {}
 
     def stats(o, r, dirs):
@@ -753,6 +929,23 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
     for name in ("query_f16_cell", "query_f16_texel"):
         if name in sample:
             errs[name] = stats(sample[name], ref, d_s)
+
+    # ---- workload 1 (one glyph): the oracle's bake and query, full size
+    if "cfg1" in sample:
+        s1 = sample["cfg1"]
+        c1 = s1["c"][0].astype(np.float64)
+        lut1 = oracle.bake_sh(c1, W1["N"])
+        r1 = oracle.query(lut1, s1["dirs"])
+        errs["cfg1_glyph"] = stats(s1["out"], r1, s1["dirs"])
+        Q1 = s1["dirs"].shape[0]
+        sq, rq = timed(lambda: oracle.query(lut1, s1["dirs"]), 1.0)
+        sk, _ = timed(lambda: oracle.bake_sh(c1, W1["N"]), 0.5)
+        oracle_forms["cfg1_glyph"] = entry(Q1, "queries/s", sq, Q1, one_core(lambda: oracle.query(lut1, s1["dirs"])),
+                                           Q1, f"all {Q1} queries (x{rq})", f"all {Q1} queries")
+        oracle_forms["cfg1_glyph"]["bake_ms"] = sk * 1e3
+        oracle_forms["cfg1_glyph"]["one_core_bake_ms"] = one_core(lambda: oracle.bake_sh(c1, W1["N"])) * 1e3
+        log("oracle cfg1", oracle_forms["cfg1_glyph"])
+
     if "batched" in sample:
         s = sample["batched"]
         o_all, r_all, d_all = [], [], []
@@ -765,13 +958,47 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
             d_all.append(s["dirs"][q0:q0 + q])
             q0 += q
         errs["batched"] = stats(np.concatenate(o_all), np.concatenate(r_all), np.concatenate(d_all))
+        # the oracle's batched query over all 4,096 objects (FP64 copies of the
+        # GPU-baked FP32 texel LUTs, the data the FP16 cells encode)
+        if "lut_tex" in s:
+            lut64 = s["lut_tex"].astype(np.float64)
+            offs = s["texel_off"] // 4
+            Qb = int(s["q_all"].sum())
+            fb = lambda k: oracle.query_objects(lut64, offs[:k], s["N_all"][:k], s["qb_all"][:k], s["q_all"][:k],
+                                                s["dirs_all"][: int(s["qb_all"][k - 1] + s["q_all"][k - 1])])
+            sb_all, _ = timed(lambda: fb(len(offs)))
+            n16 = int(s["q_all"][:16].sum())
+            oracle_forms["batched"] = entry(Qb, "queries/s", sb_all, Qb, one_core(lambda: fb(16)), n16,
+                                            f"all {len(offs)} objects, {Qb} queries",
+                                            f"the first 16 objects ({n16} queries)")
+            del lut64
+            log("oracle batched", oracle_forms["batched"])
+
     if "backward" in sample:
         s = sample["backward"]
         _, rd = oracle.backward(s["lut"], s["dirs"], s["g"], want_lut=False)
         gn = np.linalg.norm(rd, axis=1)
         e = np.linalg.norm(s["gd"] - rd, axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))
         errs["backward_fit"] = {"lut_grad_adjoint_rel": s["adjoint_rel"], "dirs_grad_max_rel": float(e.max()),
-                            "dirs_grad_rms_rel": float(np.sqrt(np.mean(e ** 2))), "dirs_sampled": int(e.size)}
+                                "dirs_grad_rms_rel": float(np.sqrt(np.mean(e ** 2))), "dirs_sampled": int(e.size)}
+        # one full-size forward + backward step of the oracle (2^22 queries,
+        # N = 512; its LUT gradient sums queries sequentially in query order)
+        if "dirs_full" in s:
+            df, gf = s["dirs_full"], s["g_full"].astype(np.float64)
+            Q4 = df.shape[0]
+
+            def step4(k):
+                oracle.query(s["lut"], df[:k])
+                oracle.backward(s["lut"], df[:k], gf[:k])
+
+            s4, _ = timed(lambda: step4(Q4))
+            k1 = 1 << 16
+            oracle_forms["backward_fit"] = entry(1, "steps/s", s4, 1, one_core(lambda: step4(k1)), k1 / Q4,
+                                                 f"one step: forward + backward (LUT and directions) of all {Q4} "
+                                                 f"queries", f"the first {k1} queries of a step (scaled to steps/s)")
+            oracle_forms["backward_fit"]["step_s"] = s4
+            log("oracle fwd+bwd step", oracle_forms["backward_fit"])
+
     if "trace" in sample:
         s = sample["trace"]
         N3 = 256
@@ -790,7 +1017,40 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample):
             errs["trace_" + name] = {"rays_checked": int(sel.size), "hit_mask_agree": float(np.mean(hg == hr)),
                                      "t_rel_median": float(np.median(rel)), "t_rel_max": float(rel.max()),
                                      "normal_deg_mean": float(ang.mean()), "normal_deg_p99": float(np.percentile(ang, 99))}
-    return cpu, errs
+        P3 = s["o"].shape[0]
+        s3, _ = timed(lambda: oracle.trace(lut, np.zeros(3), s["rmax"], s["o"], s["d"]))
+        oracle_forms["trace"] = entry(P3, "rays/s", s3, P3,
+                                      one_core(lambda: oracle.trace(lut, np.zeros(3), s["rmax"], s["o"][sel],
+                                                                    s["d"][sel])), sel.size,
+                                      f"all {P3} rays of the 1920 x 1080 frame",
+                                      f"every 97th ray ({sel.size} rays)")
+        log("oracle trace", oracle_forms["trace"])
+
+    if "quality" in sample:
+        s = sample["quality"]
+        truth = oracle.sh_truth(s["c"].astype(np.float64), s["dirs"].astype(np.float64))[:, 0]
+        peak = truth.max() - truth.min()
+        ours = {}
+        for k, v in s["outs"].items():
+            rmse = np.sqrt(np.mean((v.astype(np.float64) - truth) ** 2))
+            ours[k] = float(20 * np.log10(peak / rmse))
+        extra["quality"] = {
+            "value_psnr_db_this_build": ours,
+            "value_psnr_db_paper": {"hermite": [32.2, 62.7, 93.1], "bilinear": [23.1, 35.5, 48.0],
+                                    "catmull_rom": [29.1, 51.5, 73.0], "N": [8, 16, 32],
+                                    "source": "Table psnr_value (L = 8 glyph, 100K uniform directions; the paper's "
+                                              "glyph seed and normalisation differ, so compare orderings and the "
+                                              "gain per doubling of N)"},
+            "paper_frame_rates_context": {
+                "hermite_fps": {"Intel Iris Xe (100K glyphs, N=8)": 9.0, "NVIDIA RTX 2000 Ada (1M glyphs, N=8)": 16.0},
+                "bicubic_16tap_fps": {"Intel Iris Xe (100K glyphs, N=8)": 5.1,
+                                      "NVIDIA RTX 2000 Ada (1M glyphs, N=8)": 9.0},
+                "source": "Table runtime (WebGPU fragment shaders, screen resolution not stated): context, not a "
+                          "comparable metric"},
+            "psnr_peak": "max - min of the FP64 truth over the sample",
+        }
+        log("quality", extra["quality"]["value_psnr_db_this_build"])
+    return cpu, errs, oracle_forms, extra
 
 
 if __name__ == "__main__":

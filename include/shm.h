@@ -18,8 +18,13 @@
  *    shm_plan_create (released by shm_plan_destroy).
  *  - Every call is asynchronous on the given HIP stream (0 = the null
  *    stream); arguments are validated on the host before anything is
- *    enqueued.  Calls return SHM_OK or an error code and never throw;
- *    shm_last_error() gives a thread-local message for the last failure.
+ *    enqueued.  The exceptions are the plan calls that say they wait
+ *    (shm_plan_create, shm_plan_set_shape, shm_plan_autotune,
+ *    shm_plan_capture_graph, shm_plan_destroy): each blocks the host until
+ *    its own copies, or the plan's earlier launches, have completed; none
+ *    waits for the whole device.  Calls return SHM_OK or an error code and
+ *    never throw; shm_last_error() gives a thread-local message for the last
+ *    failure (every entry point that validates arguments clears it first).
  *  - Faces are ordered +X, -X, +Y, -Y, +Z, -Z with the hardware cube-map
  *    (s, t) orientation: d/|ma| = M + sc S + tc T, u = (sc+1)/2,
  *    v = (tc+1)/2 (Sec. 3.2).  Face ties go X before Y before Z, and a
@@ -103,6 +108,9 @@ SHM_API int64_t shm_lut_elems(int32_t N, int32_t layout);
  *            every padded texel), rebuilt by every call
  * The contraction coeffs x basis runs on the matrix cores (FP32 MFMA, FP32
  * accumulation); the basis table is evaluated in FP64 and stored in FP32.
+ * The l = 0 term is not part of the contraction: Y_00 is constant, so it
+ * adds coeffs[0] Y_00 (formed in FP64, rounded once) to every value texel
+ * and nothing to the derivative channels, once, after the l >= 1 sum.
  * ---------------------------------------------------------------------- */
 SHM_API size_t shm_bake_sh_lut_workspace(int32_t L, int32_t N);
 SHM_API int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out,
@@ -144,7 +152,11 @@ SHM_API int shm_cells_to_f16(const float* cells, int64_t n_cells, void* cells_f1
  *   out     [n_obj*q_per_obj][4] FP32 (R, gx, gy, gz)
  *   normal  [n_obj*q_per_obj][3] FP32 or NULL
  * The face and cell are decided in FP32 by: a = sc/ma, u = (a+1)*0.5,
- * f = u*N + 0.5, i0 = min(floor(f), N), every step correctly rounded.
+ * f = u*N + 0.5, i0 = min(floor(f), N), every step correctly rounded.  The
+ * face is the exact one; the cell is the exact one (floor of the exact f)
+ * except where f lies within a few FP32 ulps of an integer, where it may be
+ * the neighbouring cell: the patch is C1 across cell edges, so value and
+ * gradient agree there to rounding.
  * ---------------------------------------------------------------------- */
 SHM_API int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t N, int64_t n_obj, const float* dirs,
                          int64_t q_per_obj, float* out, float* normal, hipStream_t stream);
@@ -214,23 +226,32 @@ typedef struct shm_launch_shape {
 /* Validates the descriptors (N in range, lut_offset >= 0 and aligned for
  * the dtype/layout, q_begin, q_count >= 0), copies them to the device on
  * `stream` and waits for the copy (objs_host may be released on return),
- * builds the work list with the default shape {256, 2, 2048, 8}.  The
- * plan must not outlive the device it was created on. */
+ * allocates the plan's device memory (the descriptors and a work list sized
+ * for the smallest tile a shape may have, 64 queries: sum over objects of
+ * ceil(q_count / 64) items of 16 B) and builds the work list with the
+ * default shape {256, 2, 2048, 8}.  This is the plan's only allocation.
+ * The plan must not outlive the device it was created on. */
 SHM_API int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, int32_t layout, hipStream_t stream,
                     shm_plan** plan_out);
 /* Times every candidate launch shape on the given (real) buffers, keeps the
- * fastest and returns it in *chosen (may be NULL).  Synchronises `stream`.
- * cache_path: JSON file (host path) that remembers the choice for this
- * workload signature, or NULL. */
+ * fastest and returns it in *chosen (may be NULL).  Waits for its own
+ * launches on `stream` (and, through shm_plan_set_shape, for the plan's
+ * earlier launches).  cache_path: JSON file (host path) that remembers the
+ * choice for this workload signature, or NULL. */
 SHM_API int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float* out, const char* cache_path,
                       hipStream_t stream, shm_launch_shape* chosen);
-/* Sets the launch shape and drops any captured graph.  A new tile size
- * rebuilds the work list, which first waits for all work on the device
- * (a launch issued earlier may still read the old list). */
+/* Sets the launch shape and drops any captured graph.  It first waits
+ * (host) for every launch of the plan's kernel issued so far through
+ * shm_plan_launch or shm_plan_graph_launch, on any stream: they may still
+ * read the work list or run the graph.  A new tile size then rewrites the
+ * work list in place (no allocation).  A graph that the caller captured
+ * around shm_plan_launch keeps reading the plan's list: set no new shape
+ * while the caller may still replay it. */
 SHM_API int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape);
 SHM_API int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal, hipStream_t stream);
 /* Captures one shm_plan_launch with these buffers into a HIP graph owned by
- * the plan; shm_plan_graph_launch replays it on `stream`. */
+ * the plan (replacing an earlier one once the plan's launches so far have
+ * completed); shm_plan_graph_launch replays it on `stream`. */
 SHM_API int shm_plan_capture_graph(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal,
                            hipStream_t stream);
 SHM_API int shm_plan_graph_launch(shm_plan* plan, hipStream_t stream);

@@ -32,8 +32,9 @@ _LIB = os.path.join(_HERE, "_shm_oracle.so")
 # default one by the sanitizer test
 _LIB_OVERRIDE = os.environ.get("SHM_ORACLE_LIB")
 
-# -ffp-contract=off: no fused multiply-add anywhere, so the FP32 cell decision
-# in locate() is the documented sequence of correctly rounded operations.
+# -ffp-contract=off: no fused multiply-add anywhere, so the one FP32 decision
+# (the ray caster's adaptive bisection budget) is the documented sequence of
+# correctly rounded operations.
 CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
 
 
@@ -91,8 +92,9 @@ def lut_shape(N):
 
 
 def locate(dirs, N):
-    """Face, cell (i0, j0) and local (s, t) per query (Sec. 3.2).  The face
-    and cell are decided in FP32; s, t are FP64."""
+    """Face, cell (i0, j0) and local (s, t) per query (Sec. 3.2), all from
+    the exact FP64 coordinate f = u N + 1/2 of the FP32 input: i0 =
+    min(floor(f), N), s = f - i0 (likewise j0, t)."""
     d = _f32(dirs).reshape(-1, 3)
     Q = d.shape[0]
     face = np.empty(Q, np.int32)

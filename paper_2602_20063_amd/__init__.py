@@ -110,6 +110,9 @@ SIGNATURES = {
     "shm_fit_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _I64,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     _VP, ctypes.c_size_t, _I32, _VP]),
+    # memory-system probes (include/shm_probe.h)
+    "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _VP, _VP, _VP]),
+    "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
 }
 
 _lib = None
@@ -209,6 +212,17 @@ def shm_query_value_grad(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, nor
     _need(out, torch.float32, "out")
     return _check(lib().shm_query_value_grad(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, _ptr(out),
                                              _ptr(normal), _stream(stream)))
+
+
+def shm_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, dirs, out, stream=None):
+    """Random gathers of req_bytes inside regions of base (see shm_probe.h);
+    with dirs, also the query's streamed directions and 16 B results."""
+    return _check(lib().shm_probe_gather(_ptr(base), region_bytes, n_regions, per_region, req_bytes, seed & 0xFFFFFFFF,
+                                         _ptr(dirs), _ptr(out), _stream(stream)))
+
+
+def shm_probe_stream_read(base, nbytes, sink, stream=None):
+    return _check(lib().shm_probe_stream_read(_ptr(base), nbytes, _ptr(sink), _stream(stream)))
 
 
 def shm_backward_workspace(N, n_obj, q_per_obj):
@@ -683,6 +697,8 @@ class BackwardContext:
     def __init__(self, N, n_obj, dirs, q_per_obj, stream=None):
         self.N, self.n_obj, self.q_per_obj = N, n_obj, q_per_obj
         self.dirs = dirs
+        # the sort is valid for exactly these direction values
+        self.dirs_version = dirs._version
         nbytes = shm_backward_workspace(N, n_obj, q_per_obj)
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dirs.device)
         shm_backward_sort(N, n_obj, dirs, q_per_obj, self.ws, stream)
@@ -703,10 +719,19 @@ class HermiteQuery(torch.autograd.Function):
     def forward(ctx, lut, dirs, bctx=None):
         N = lut_n(lut)
         n_obj = lut.numel() // (6 * (N + 2) * (N + 2) * 4)
-        out = torch.empty((dirs.shape[0], 4), dtype=torch.float32, device=dirs.device)
-        shm_query_value_grad(lut, SHM_F32, SHM_LAYOUT_TEXEL, N, n_obj, dirs, dirs.shape[0] // n_obj, out)
+        Q = dirs.shape[0]
+        if n_obj < 1 or Q % n_obj:
+            raise ValueError(f"{Q} directions do not split evenly over {n_obj} objects")
+        if bctx is not None:
+            if (bctx.N, bctx.n_obj, bctx.q_per_obj) != (N, n_obj, Q // n_obj):
+                raise ValueError("bctx was built for another LUT size or query split")
+            if (bctx.dirs.data_ptr() != dirs.data_ptr() or bctx.dirs.shape != dirs.shape
+                    or dirs._version != bctx.dirs_version):
+                raise ValueError("bctx was sorted for other directions (or they changed since)")
+        out = torch.empty((Q, 4), dtype=torch.float32, device=dirs.device)
+        shm_query_value_grad(lut, SHM_F32, SHM_LAYOUT_TEXEL, N, n_obj, dirs, Q // n_obj, out)
         if bctx is None:
-            bctx = BackwardContext(N, n_obj, dirs.detach(), dirs.shape[0] // n_obj)
+            bctx = BackwardContext(N, n_obj, dirs.detach(), Q // n_obj)
         ctx.bctx = bctx
         ctx.save_for_backward(lut, dirs)
         return out

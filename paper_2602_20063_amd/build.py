@@ -7,8 +7,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshm.so")
 SOURCES = ["shm_api.hip", "shm_query.hip", "shm_bake.hip", "shm_backward.hip", "shm_trace.hip", "shm_baseline.hip",
-           "shm_mip.hip", "shm_render.hip", "shm_mesh.hip", "shm_fit.hip"]
-HEADERS = ["shm_device.hpp", "shm_fit.hpp", "shm_internal.hpp", os.path.join("..", "..", "include", "shm.h")]
+           "shm_mip.hip", "shm_render.hip", "shm_mesh.hip", "shm_fit.hip", "shm_probe.hip"]
+HEADERS = ["shm_device.hpp", "shm_fit.hpp", "shm_internal.hpp", os.path.join("..", "..", "include", "shm.h"),
+           os.path.join("..", "..", "include", "shm_probe.h")]
 
 FLAGS = [
     "--offload-arch=gfx950",

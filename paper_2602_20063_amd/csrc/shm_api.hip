@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "shm_internal.hpp"
+#include "../../include/shm_probe.h"
 
 namespace shm {
 
@@ -82,6 +83,10 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
                     const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
                     float b2, float eps, void* ws, hipStream_t stream);
 
+int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int req_bytes,
+                        uint32_t seed, const float* dirs, float* out, hipStream_t stream);
+int launch_probe_stream(const void* base, int64_t bytes, float* sink, hipStream_t stream);
+
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 // n_obj * q_per_obj (both >= 0) exceeds limit, checked without overflow
@@ -112,9 +117,50 @@ struct shm_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t signature = 0;
+    // one event per stream the plan's kernel was launched on, recorded after
+    // its latest launch there: the work list may be rewritten once they have
+    // completed
+    std::vector<std::pair<hipStream_t, hipEvent_t>> launched;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // autotuner timing
 };
 
-static int plan_build_items(shm_plan* P, hipStream_t stream)
+// Smallest work-item tile a shape may have (block 64 x 1 query per thread):
+// the plan's work-list capacity is sized for it, so no shape needs more.
+static constexpr int64_t kMinTile = 64;
+
+static int64_t items_for_tile(const std::vector<shm_object>& objs, int64_t tile)
+{
+    int64_t n = 0;
+    for (const shm_object& ob : objs) n += (ob.q_count + tile - 1) / tile;
+    return n;
+}
+
+// Marks a launch of the plan's kernel on `stream` (outside graph capture:
+// a captured launch runs when its graph does, see shm_plan_set_shape).
+static int plan_mark_launch(shm_plan* P, hipStream_t stream)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    SHM_HIP_CHECK(hipStreamIsCapturing(stream, &st));
+    if (st != hipStreamCaptureStatusNone) return SHM_OK;
+    hipEvent_t ev = nullptr;
+    for (auto& se : P->launched)
+        if (se.first == stream) ev = se.second;
+    if (!ev) {
+        SHM_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        P->launched.emplace_back(stream, ev);
+    }
+    SHM_HIP_CHECK(hipEventRecord(ev, stream));
+    return SHM_OK;
+}
+
+// Host wait for every launch of the plan's kernel issued so far.
+static int plan_wait_launches(shm_plan* P)
+{
+    for (auto& se : P->launched) SHM_HIP_CHECK(hipEventSynchronize(se.second));
+    return SHM_OK;
+}
+
+static int plan_build_items(shm_plan* P)
 {
     std::vector<WorkItem> items;
     const int64_t tile = P->shape.tile;
@@ -142,20 +188,17 @@ static int plan_build_items(shm_plan* P, hipStream_t stream)
     }
     while (s < 8) sp.b[s++] = n;
     sp.b[8] = n;
-    // a launch issued earlier (on any stream) may still read the old list
-    if (P->d_items) SHM_HIP_CHECK(hipDeviceSynchronize());
-    if (n > P->items_cap) {
-        if (P->d_items) SHM_HIP_CHECK(hipFree(P->d_items));
-        P->d_items = nullptr;
-        P->items_cap = 0;
-        SHM_HIP_CHECK(hipMalloc(&P->d_items, (size_t)std::max<int64_t>(n, 1) * sizeof(WorkItem)));
-        P->items_cap = std::max<int64_t>(n, 1);
-    }
+    if (n > P->items_cap)  // cannot happen: the capacity covers the smallest tile
+        return fail(SHM_ERR_INVALID_ARG, "plan: %lld work items exceed the capacity %lld", (long long)n,
+                    (long long)P->items_cap);
+    // launches issued earlier may still read the old list
+    if (int rc = plan_wait_launches(P)) return rc;
     P->n_items = n;
     P->split = sp;
     if (n) {
-        SHM_HIP_CHECK(hipMemcpyAsync(P->d_items, items.data(), (size_t)n * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
-        SHM_HIP_CHECK(hipStreamSynchronize(stream));  // `items` is a host temporary
+        SHM_HIP_CHECK(hipMemcpyAsync(P->d_items, items.data(), (size_t)n * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                     P->cap_stream));
+        SHM_HIP_CHECK(hipStreamSynchronize(P->cap_stream));  // `items` is a host temporary
     }
     return SHM_OK;
 }
@@ -341,11 +384,19 @@ int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, i
         shm_plan_destroy(P);
         return fail(SHM_ERR_HIP, "plan_create: copy of descriptors failed");
     }
-    if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&P->t0) != hipSuccess || hipEventCreate(&P->t1) != hipSuccess) {
         shm_plan_destroy(P);
-        return fail(SHM_ERR_HIP, "plan_create: stream creation failed");
+        return fail(SHM_ERR_HIP, "plan_create: stream or event creation failed");
     }
-    if ((rc = plan_build_items(P, stream)) != SHM_OK) {
+    // the work list is sized once, for the smallest tile any shape may use
+    P->items_cap = std::max<int64_t>(items_for_tile(P->objs, kMinTile), 1);
+    if (hipMalloc(&P->d_items, (size_t)P->items_cap * sizeof(WorkItem)) != hipSuccess) {
+        P->items_cap = 0;
+        shm_plan_destroy(P);
+        return fail(SHM_ERR_HIP, "plan_create: hipMalloc of the work list (%lld items) failed", (long long)P->items_cap);
+    }
+    if ((rc = plan_build_items(P)) != SHM_OK) {
         std::string msg = g_err;
         shm_plan_destroy(P);
         return fail(rc, "%s", msg.c_str());
@@ -368,10 +419,13 @@ int shm_plan_set_shape(shm_plan* plan, const shm_launch_shape* shape)
     if (!plan || !shape) return fail(SHM_ERR_INVALID_ARG, "plan_set_shape: null argument");
     int rc = check_shape(*shape);
     if (rc) return rc;
+    // the plan's graph, and with a new tile the work list, may still be in
+    // use by launches issued earlier
+    if ((rc = plan_wait_launches(plan)) != SHM_OK) return rc;
     const bool retile = shape->tile != plan->shape.tile;
     plan->shape = *shape;
     drop_graph(plan);  // captured with the previous shape
-    return retile ? plan_build_items(plan, plan->cap_stream) : SHM_OK;
+    return retile ? plan_build_items(plan) : SHM_OK;
 }
 
 int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* out, float* normal, hipStream_t stream)
@@ -382,8 +436,9 @@ int shm_plan_launch(shm_plan* plan, const void* lut, const float* dirs, float* o
     if (!lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "plan_launch: null pointer");
     const size_t al = (plan->dtype == SHM_F16 && plan->layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
     if (!aligned(lut, al) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "plan_launch: misaligned buffer");
-    return launch_query_persistent(lut, plan->dtype, plan->layout, plan->d_objs, plan->d_items, plan->n_items,
-                                   plan->split, plan->shape, plan->n_cu, dirs, out, normal, stream);
+    int rc = launch_query_persistent(lut, plan->dtype, plan->layout, plan->d_objs, plan->d_items, plan->n_items,
+                                     plan->split, plan->shape, plan->n_cu, dirs, out, normal, stream);
+    return rc ? rc : plan_mark_launch(plan, stream);
 }
 
 static std::map<std::string, shm_launch_shape> read_cache(const char* path)
@@ -448,9 +503,7 @@ int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float*
         for (int qpt : {1, 2, 4})
             for (int mult : {1, 4, 16})
                 for (int gpc : {4, 8, 16}) cands.push_back(shm_launch_shape{block, qpt, block * qpt * mult, gpc});
-    hipEvent_t e0, e1;
-    SHM_HIP_CHECK(hipEventCreate(&e0));
-    SHM_HIP_CHECK(hipEventCreate(&e1));
+    hipEvent_t e0 = plan->t0, e1 = plan->t1;
     float best_ms = 1e30f;
     shm_launch_shape best = plan->shape;
     int rc = SHM_OK;
@@ -468,8 +521,6 @@ int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float*
         ms /= reps;
         if (ms < best_ms) { best_ms = ms; best = s; }
     }
-    (void)hipEventDestroy(e0);  // best-effort cleanup
-    (void)hipEventDestroy(e1);
     if (rc) return rc;
     if ((rc = shm_plan_set_shape(plan, &best)) != SHM_OK) return rc;
     if (chosen) *chosen = best;
@@ -485,6 +536,7 @@ int shm_plan_capture_graph(shm_plan* plan, const void* lut, const float* dirs, f
     clear_error();
     if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_capture_graph: null plan");
     (void)stream;
+    if (int rc0 = plan_wait_launches(plan)) return rc0;  // a replay of the old graph may still run
     drop_graph(plan);
     SHM_HIP_CHECK(hipStreamSynchronize(plan->cap_stream));
     SHM_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -509,7 +561,7 @@ int shm_plan_graph_launch(shm_plan* plan, hipStream_t stream)
     clear_error();
     if (!plan || !plan->exec) return fail(SHM_ERR_INVALID_ARG, "plan_graph_launch: no captured graph");
     SHM_HIP_CHECK(hipGraphLaunch(plan->exec, stream));
-    return SHM_OK;
+    return plan_mark_launch(plan, stream);
 }
 
 int64_t shm_plan_work_items(const shm_plan* plan) { return plan ? plan->n_items : -1; }
@@ -517,8 +569,14 @@ int64_t shm_plan_work_items(const shm_plan* plan) { return plan ? plan->n_items 
 int shm_plan_destroy(shm_plan* plan)
 {
     if (!plan) return SHM_OK;
-    // best-effort cleanup: every resource is released even if one call fails
+    // best-effort cleanup: every resource is released even if one call fails;
+    // launches still in flight finish first
+    (void)plan_wait_launches(plan);
+    clear_error();
     drop_graph(plan);
+    for (auto& se : plan->launched) (void)hipEventDestroy(se.second);
+    if (plan->t0) (void)hipEventDestroy(plan->t0);
+    if (plan->t1) (void)hipEventDestroy(plan->t1);
     if (plan->cap_stream) {
         (void)hipStreamSynchronize(plan->cap_stream);
         (void)hipStreamDestroy(plan->cap_stream);
@@ -840,6 +898,41 @@ int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs
     if (!coeffs || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "sh_eval: null pointer");
     if (!aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "sh_eval: misaligned output");
     return launch_sh_eval(coeffs, L, n_obj, dirs, q_per_obj, out, stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// memory-system probes
+// ---------------------------------------------------------------------------
+int shm_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int32_t req_bytes,
+                     uint32_t seed, const float* dirs, float* out, hipStream_t stream)
+{
+    clear_error();
+    if (!(req_bytes == 16 || req_bytes == 32 || req_bytes == 64 || req_bytes == 128))
+        return fail(SHM_ERR_INVALID_ARG, "probe_gather: req_bytes must be 16, 32, 64 or 128 (got %d)", req_bytes);
+    if (n_regions < 0 || per_region < 0) return fail(SHM_ERR_INVALID_ARG, "probe_gather: negative size");
+    if (region_bytes < req_bytes || region_bytes % 16)
+        return fail(SHM_ERR_INVALID_ARG, "probe_gather: region_bytes must be a multiple of 16 and >= req_bytes");
+    if (region_bytes / req_bytes > 0xffffffffll) return fail(SHM_ERR_UNSUPPORTED, "probe_gather: region too large");
+    if (product_exceeds(n_regions, region_bytes, INT64_MAX / 2) || product_exceeds(n_regions, per_region, INT64_MAX / 16))
+        return fail(SHM_ERR_UNSUPPORTED, "probe_gather: sizes overflow");
+    const int64_t tiles = (per_region + 255) / 256;
+    if (product_exceeds(n_regions, tiles, 0x7fffffff)) return fail(SHM_ERR_UNSUPPORTED, "probe_gather: grid too large");
+    if (n_regions == 0 || per_region == 0) return SHM_OK;
+    if (!base || !out) return fail(SHM_ERR_INVALID_ARG, "probe_gather: null pointer");
+    if (!aligned(base, 16) || !aligned(out, 16) || (dirs && !aligned(dirs, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "probe_gather: misaligned buffer");
+    return launch_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, dirs, out, stream);
+}
+
+int shm_probe_stream_read(const void* base, int64_t bytes, float* sink, hipStream_t stream)
+{
+    clear_error();
+    if (bytes < 0 || bytes % 16) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: bytes must be a multiple of 16");
+    if (bytes == 0) return SHM_OK;
+    if (!base || !sink) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: null pointer");
+    if (!aligned(base, 16) || !aligned(sink, 16)) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: misaligned buffer");
+    return launch_probe_stream(base, bytes, sink, stream);
 }
 
 }  // extern "C"

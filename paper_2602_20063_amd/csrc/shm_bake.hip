@@ -15,6 +15,15 @@
 // The table is built in FP64 and stored in FP32; the contraction runs on the
 // matrix cores (v_mfma_f32_16x16x4f32, FP32 operands and accumulation).
 //
+// The l = 0 term is left out of the contraction and added once, in the
+// epilogue: Y_00 is a constant with zero derivatives, so it only shifts the
+// value channel, by c_00 Y_00 (rounded once from FP64).  Its value is the
+// bulk of R (about 1 for a glyph), and summing it first would make every
+// later FP32 addition round at the scale of R rather than at the scale of
+// the varying part; the derivatives of the reconstruction difference
+// neighbouring texels' values (about 1.5 N times their rounding), so that
+// rounding is what the gradient sees.
+//
 // General mode: central differences on samples taken on the padded grid
 // plus a one-texel margin.
 #include <hip/hip_fp16.h>
@@ -188,6 +197,12 @@ __global__ void k_zero_cols(float* __restrict__ Bt, int Kp, int64_t rows, int64_
 // B[k = l/16][n = l%16], D[m = 4*(l/16) + i][n = l%16], i = 0..3.
 // ---------------------------------------------------------------------------
 constexpr int GB_M = 64, GB_N = 128, GB_KC = 96;
+
+// c_00 Y_00, Y_00 = 1 / sqrt(4 pi), formed in FP64 and rounded once
+__device__ __forceinline__ float y00_term(float c00)
+{
+    return (float)((double)c00 * 0.28209479177387814347);
+}
 constexpr int GB_LDA = GB_M + 1, GB_LDB = GB_N + 16;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -213,7 +228,7 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
             const int m = i / kn, k = i - m * kn;
             const int64_t o = o0 + m;
             const int kk = kc + k;
-            As[k * GB_LDA + m] = (o < n_obj && kk < K) ? C[o * K + kk] : 0.0f;
+            As[k * GB_LDA + m] = (o < n_obj && kk < K && kk > 0) ? C[o * K + kk] : 0.0f;
         }
         // stage B: Bs[k][n] = Bt[kc+k][r0+n]  (rows_pad covers the tile)
         for (int i = tid; i < GB_N * kn; i += 256) {
@@ -240,10 +255,12 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
             for (int e = 0; e < 4; ++e) {
                 const int64_t o = o0 + wm * 32 + i * 16 + 4 * (lane >> 4) + e;
                 if (o >= n_obj) continue;
+                // value channel (col % 4 == 0): add the l = 0 term
+                const float v = (col & 3) == 0 ? acc[i][j][e] + y00_term(C[o * K]) : acc[i][j][e];
                 if constexpr (F16OUT)
-                    reinterpret_cast<__half*>(lut)[o * rows + col] = __float2half(acc[i][j][e]);
+                    reinterpret_cast<__half*>(lut)[o * rows + col] = __float2half(v);
                 else
-                    reinterpret_cast<float*>(lut)[o * rows + col] = acc[i][j][e];
+                    reinterpret_cast<float*>(lut)[o * rows + col] = v;
             }
         }
 }
@@ -322,11 +339,15 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // ... and part 3: stored as whole 128 B rows; rows is a multiple of 4, so a
 // group of four columns is wholly inside or outside the table
+// cst[q] is the l = 0 term of object row q, added to the value channel (the
+// first of each group of four columns: a texel's channels)
 template <bool F16OUT>
-__device__ __forceinline__ void g2_store(const float4 (&v)[4], int64_t o0, int64_t n_obj, int64_t col0, int64_t rows,
-                                         int lane, void* __restrict__ lut)
+__device__ __forceinline__ void g2_store(float4 (&v)[4], const float (&cst)[4], int64_t o0, int64_t n_obj,
+                                         int64_t col0, int64_t rows, int lane, void* __restrict__ lut)
 {
     const int64_t col = col0 + 4 * (lane & 7);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q].x += cst[q];
     // an empty statement that takes every value: the LDS reads stay where
     // they were issued instead of sinking into the guarded stores below
 #pragma unroll
@@ -357,9 +378,9 @@ __device__ __forceinline__ void g2_store(const float4 (&v)[4], int64_t o0, int64
 // busy instead of following it.  The scheduling barriers keep that order.
 template <bool F16OUT, int KS>
 __device__ __forceinline__ void g2_tile_overlap(const float (&a)[2][KS], const float (&b)[2][KS], floatx4 (&acc)[2][2],
-                                                const floatx4 (&prev)[2][2], float* __restrict__ stage, int64_t o0,
-                                                int64_t n_obj, int64_t col_prev, int64_t rows, int lane,
-                                                void* __restrict__ lut)
+                                                const floatx4 (&prev)[2][2], float* __restrict__ stage,
+                                                const float (&cst)[4], int64_t o0, int64_t n_obj, int64_t col_prev,
+                                                int64_t rows, int lane, void* __restrict__ lut)
 {
     constexpr int S1 = KS / 4, S2 = KS / 2, S3 = (3 * KS) / 4;
 #pragma unroll
@@ -377,20 +398,21 @@ __device__ __forceinline__ void g2_tile_overlap(const float (&a)[2][KS], const f
     __builtin_amdgcn_sched_barrier(0);
     g2_mma<KS, S2, S3>(a, b, acc);
     __builtin_amdgcn_sched_barrier(0);
-    g2_store<F16OUT>(v, o0, n_obj, col_prev, rows, lane, lut);
+    g2_store<F16OUT>(v, cst, o0, n_obj, col_prev, rows, lane, lut);
     __builtin_amdgcn_sched_barrier(0);
     g2_mma<KS, S3, KS>(a, b, acc);
 }
 
 // The last tile's epilogue on its own.
 template <bool F16OUT>
-__device__ __forceinline__ void g2_flush(const floatx4 (&acc)[2][2], float* __restrict__ stage, int64_t o0,
-                                         int64_t n_obj, int64_t col0, int64_t rows, int lane, void* __restrict__ lut)
+__device__ __forceinline__ void g2_flush(const floatx4 (&acc)[2][2], float* __restrict__ stage, const float (&cst)[4],
+                                         int64_t o0, int64_t n_obj, int64_t col0, int64_t rows, int lane,
+                                         void* __restrict__ lut)
 {
     g2_stage(acc, stage, lane);
     float4 v[4];
     g2_unstage(stage, lane, v);
-    g2_store<F16OUT>(v, o0, n_obj, col0, rows, lane, lut);
+    g2_store<F16OUT>(v, cst, o0, n_obj, col0, rows, lane, lut);
 }
 
 // B fragments of column tile t from the fragment-ordered table: ceil(KS/2)
@@ -456,9 +478,17 @@ __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__
                 const float v = C[oc * K + (k < K ? k : K - 1)];
                 // zero outside the table by a bit mask: a select would let the
                 // compiler sink the load into a branch of its own
-                const unsigned int keep = (o < n_obj && k < K) ? 0xffffffffu : 0u;
+                // (k = 0, the l = 0 term, is added in the epilogue instead)
+                const unsigned int keep = (o < n_obj && k < K && k > 0) ? 0xffffffffu : 0u;
                 a[i][s] = __uint_as_float(__float_as_uint(v) & keep);
             }
+        }
+        // l = 0 terms of the four object rows this lane stores
+        float cst[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t o = o0 + (lane >> 3) + 8 * q;
+            cst[q] = y00_term(C[(o < n_obj ? o : n_obj - 1) * K]);
         }
         // tile k (k = 0 .. n-1 from t_begin) uses B buffer k % 2 and
         // accumulators k % 2; a buffer reloads (two tiles ahead) once its
@@ -478,16 +508,16 @@ __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__
         g2_load_b<KS>(Bt, tile_at(2), lane, b0);
         for (int64_t k = 1;; k += 2) {
             if (k >= n) {
-                g2_flush<F16OUT>(c0, stage, o0, n_obj, tile_at(k - 1) * 32, rows, lane, lut);
+                g2_flush<F16OUT>(c0, stage, cst, o0, n_obj, tile_at(k - 1) * 32, rows, lane, lut);
                 break;
             }
-            g2_tile_overlap<F16OUT, KS>(a, b1, c1, c0, stage, o0, n_obj, tile_at(k - 1) * 32, rows, lane, lut);
+            g2_tile_overlap<F16OUT, KS>(a, b1, c1, c0, stage, cst, o0, n_obj, tile_at(k - 1) * 32, rows, lane, lut);
             g2_load_b<KS>(Bt, tile_at(k + 2), lane, b1);
             if (k + 1 >= n) {
-                g2_flush<F16OUT>(c1, stage, o0, n_obj, tile_at(k) * 32, rows, lane, lut);
+                g2_flush<F16OUT>(c1, stage, cst, o0, n_obj, tile_at(k) * 32, rows, lane, lut);
                 break;
             }
-            g2_tile_overlap<F16OUT, KS>(a, b0, c0, c1, stage, o0, n_obj, tile_at(k) * 32, rows, lane, lut);
+            g2_tile_overlap<F16OUT, KS>(a, b0, c0, c1, stage, cst, o0, n_obj, tile_at(k) * 32, rows, lane, lut);
             g2_load_b<KS>(Bt, tile_at(k + 3), lane, b0);
         }
     }

@@ -2,6 +2,7 @@
 every entry point declared in include/shm.h, and rejects bad arguments with
 the documented status codes before anything is enqueued."""
 import ctypes
+import glob
 import os
 import re
 
@@ -10,11 +11,11 @@ import pytest
 import paper_2602_20063_amd as shm
 from conftest import ROOT
 
-HEADER = os.path.join(ROOT, "include", "shm.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_symbols():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^SHM_API\s+[\w\s\*]+?\b(shm_\w+)\(", text, flags=re.M)))
 
 
@@ -48,21 +49,27 @@ def call(name, *args):
 
 
 def test_query_argument_validation():
+    """Each bad argument gives its status code and a message naming it; an
+    accepted call clears the message."""
     p = ctypes.c_void_p(16)
     cases = [
-        ((p, 5, 0, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),  # dtype
-        ((p, 0, 3, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),  # layout
-        ((p, 0, 0, 0, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),   # N
-        ((p, 0, 0, 1025, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),
-        ((p, 0, 0, 10, -1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),
-        ((None, 0, 0, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG),
-        ((p, 0, 0, 10, 1, p, 8, ctypes.c_void_p(20), None, None), shm.SHM_ERR_INVALID_ARG),  # misaligned out
-        ((p, 0, 0, 10, 0, p, 8, p, None, None), shm.SHM_OK),               # empty: nothing to do
-        ((p, 0, 0, 10, 3, p, 0, p, None, None), shm.SHM_OK),
+        ((p, 5, 0, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG, "bad dtype"),
+        ((p, 0, 3, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG, "bad layout"),
+        ((p, 0, 0, 0, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG, "N must be"),
+        ((p, 0, 0, 1025, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG, "N must be"),
+        ((p, 0, 0, 10, -1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG, "negative size"),
+        ((None, 0, 0, 10, 1, p, 8, p, None, None), shm.SHM_ERR_INVALID_ARG, "null pointer"),
+        ((p, 0, 0, 10, 1, p, 8, ctypes.c_void_p(20), None, None), shm.SHM_ERR_INVALID_ARG, "misaligned"),
+        ((p, 0, 0, 10, 0, p, 8, p, None, None), shm.SHM_OK, ""),  # empty: nothing to do
+        ((p, 0, 0, 10, 3, p, 0, p, None, None), shm.SHM_OK, ""),
     ]
-    for args, code in cases:
+    for args, code, msg in cases:
         assert call("shm_query_value_grad", *args) == code, args
-    assert "N must be" in shm.shm_last_error() or True
+        err = shm.shm_last_error()
+        if code == shm.SHM_OK:
+            assert err == "", (args, err)
+        else:
+            assert msg in err, (args, err)
 
 
 def test_error_message_is_set():
@@ -289,3 +296,17 @@ def test_hip_error_is_reported_without_a_gpu():
     # a valid call with nothing to do still succeeds: the error is not sticky
     assert call("shm_query_value_grad", p, 0, 0, 8, 1, p, 0, p, None, None) == shm.SHM_OK
     assert shm.shm_last_error() == ""
+
+
+def test_probe_argument_validation():
+    p = ctypes.c_void_p(256)
+    assert call("shm_probe_gather", p, 4096, 4, 256, 48, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG  # req size
+    assert "req_bytes" in shm.shm_last_error()
+    assert call("shm_probe_gather", p, 4100, 4, 256, 64, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG  # region % 16
+    assert call("shm_probe_gather", p, 32, 4, 256, 64, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG    # region < req
+    assert call("shm_probe_gather", ctypes.c_void_p(8), 4096, 4, 256, 64, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_probe_gather", p, 4096, 4, 256, 64, 1, None, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_probe_gather", p, 4096, 1 << 40, 1 << 40, 64, 1, None, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_probe_gather", p, 4096, 0, 256, 64, 1, None, None, None) == shm.SHM_OK  # empty
+    assert call("shm_probe_stream_read", p, 100, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_probe_stream_read", p, 0, None, None) == shm.SHM_OK

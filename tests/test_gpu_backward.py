@@ -159,3 +159,25 @@ def test_backward_empty_and_partial_requests():
     dirs_only = bc.backward(lut_t, g, want_lut=False)[1]
     torch.cuda.synchronize()
     assert torch.equal(both[0], lut_only) and torch.equal(both[1], dirs_only)
+
+
+def test_hermite_query_checks_its_context():
+    """A backward context is valid only for the directions it sorted: other
+    directions, changed values, another LUT size or an uneven query split
+    are refused before anything runs."""
+    r = rng(12)
+    N = 8
+    lut_t = gpu(workloads.random_lut(N, r, n_obj=2))
+    d = gpu(workloads.uniform_dirs(1000, r))
+    bc = shm.BackwardContext(N, 2, d, 500)
+    out = shm.HermiteQuery.apply(lut_t, d, bc)  # matching context: accepted
+    assert out.shape == (1000, 4)
+    with pytest.raises(ValueError):
+        shm.HermiteQuery.apply(lut_t, d.clone(), bc)  # other storage
+    with pytest.raises(ValueError):
+        shm.HermiteQuery.apply(lut_t[:1].contiguous(), d, bc)  # one object, not two
+    with pytest.raises(ValueError):
+        shm.HermiteQuery.apply(lut_t, d[:999], None)  # 999 queries over 2 objects
+    d.mul_(2.0)  # same storage, new values: the sort is stale
+    with pytest.raises(ValueError):
+        shm.HermiteQuery.apply(lut_t, d, bc)

@@ -58,29 +58,37 @@ def test_bake_fp16_output():
 
 def test_bake_then_query_end_to_end():
     """GPU bake -> GPU query vs oracle bake -> oracle query (both from the
-    same FP32 coefficients): the end-to-end outputs agree to the query
-    tolerance."""
-    L, N, n = 8, 32, 16
+    same FP32 coefficients), 256 glyphs of the glyph field: value within
+    1e-5 and gradient within 1e-4 (relative to max(|grad|, RMS |grad|)) of
+    FP64 end to end.  The gradient of the reconstruction differences
+    neighbouring texels' values, so this holds only if the bake's value
+    channel carries little more than its FP32 storage rounding."""
+    L, N, n = 8, 32, 256
     c32 = workloads.sh_glyph_coeffs(L, n, workloads.rng_for(2)).astype(np.float32)
     dirs = workloads.uniform_dirs(n * 256, workloads.rng_for(2))
     lut = shm.bake_sh(gpu(c32), N)
-    out = shm.query(lut, gpu(dirs), q_per_obj=256).cpu().numpy()
+    out = shm.query(shm.to_cells(lut), gpu(dirs), q_per_obj=256, layout=shm.SHM_LAYOUT_CELL).cpu().numpy()
     ref_lut = oracle.bake_sh(c32.astype(np.float64), N)
     off = np.arange(n) * (ref_lut[0].size // 4)
     ref = oracle.query_objects(ref_lut.reshape(-1), off, [N] * n, np.arange(n) * 256, [256] * n, dirs)
-    # Error against FP64 end to end: the FP32 LUT holds R ~ 1 to a few ulps
-    # (storage rounding plus FP32 accumulation in the contraction), and the
-    # chart gradient differences R across h = 1/N with weights up to 1.5, so
-    # the gradient carries an absolute error of order N * eps32 * |R|.
-    eps32 = np.finfo(np.float32).eps
-    ok = np.isfinite(ref[:, 0])
-    dv = np.abs(out[ok, 0] - ref[ok, 0]) / np.abs(ref[ok, 0])
-    assert dv.max() < 2e-6
-    gn = np.linalg.norm(ref[ok, 1:], axis=1)
-    floor = np.sqrt(np.mean(gn ** 2))
-    err = np.linalg.norm(out[ok, 1:] - ref[ok, 1:], axis=1)
-    bound = 1e-4 * np.maximum(gn, floor) + 12 * N * eps32 * np.abs(ref[ok, 0]).max()
-    assert np.all(err <= bound), (err / bound).max()
+    st = check_value_grad(out, ref, "bake + query end to end")
+    print("end to end vs FP64:", st)
+
+
+@pytest.mark.parametrize("L,N", [(0, 4), (1, 6), (12, 16)])
+def test_l0_term_added_once(L, N):
+    """The l = 0 term leaves the contraction and enters the value channel
+    once: a constant function (only c_00) bakes to c_00 Y_00 rounded once,
+    with exactly zero derivative channels, through both contraction kernels
+    (register-resident for L <= 8, LDS-staged above)."""
+    n = 3
+    c = np.zeros((n, (L + 1) ** 2), np.float32)
+    c[:, 0] = np.array([3.5449077, -1.25, 7.0], np.float32)
+    lut = shm.bake_sh(gpu(c), N).cpu().numpy().reshape(n, -1, 4)
+    for o in range(n):
+        expect = np.float32(np.float64(c[o, 0]) * 0.28209479177387814347)
+        assert np.all(lut[o, :, 0] == expect)
+        assert np.all(lut[o, :, 1:] == 0.0)
 
 
 def test_margin_dirs_and_fd_bake():

@@ -104,3 +104,36 @@ def test_graph_capture_replays(tmp_path):
         torch.cuda.synchronize()
         assert torch.equal(out, ref), rep
     plan.close()
+
+
+def test_set_shape_waits_for_earlier_launches():
+    """A new tile rewrites the work list in place (the plan allocates only at
+    creation): launches already issued on two other streams, not yet waited
+    for by the caller, still read the old list to the end and give the same
+    bits; the work list never outgrows its creation-time capacity."""
+    flat, objs, dirs = build_batch(60, 8, qscale=1.3)
+    lut_t = torch.as_tensor(flat).to(DEV)
+    d_t = torch.as_tensor(dirs).to(DEV)
+    plan = shm.Plan(objs, shm.SHM_F32)
+    ref = torch.full((dirs.shape[0], 4), float("nan"), device=DEV)
+    plan.launch(lut_t, d_t, ref)
+    torch.cuda.synchronize()
+    n_default = plan.work_items
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = [torch.full_like(ref, float("nan")) for _ in range(3)]
+    for k, st in enumerate((s1, s2)):
+        st.wait_stream(torch.cuda.current_stream())
+        for _ in range(4):
+            plan.launch(lut_t, d_t, outs[k], stream=st)
+    plan.set_shape(64, 1, 64, 1)  # the smallest tile: the most work items
+    assert plan.work_items > n_default
+    plan.launch(lut_t, d_t, outs[2])
+    plan.set_shape(512, 4, 4096, 8)
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert torch.equal(outs[k], ref), k
+    out = torch.full_like(ref, float("nan"))
+    plan.launch(lut_t, d_t, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    plan.close()

@@ -98,6 +98,76 @@ def test_backward_full_size():
     assert (np.linalg.norm(gk - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3
 
 
+def test_backward_full_size_texels_elementwise_and_fd():
+    """The fitting workload's backward at full size (N = 512, 2^22 directions
+    sorted by cell, as bench.py runs it), dL/dLUT texel by texel on 64
+    sampled texels x 4 channels (gutter corners and edges included):
+      * against the oracle's backward over the queries whose cells touch a
+        sampled texel (no other query reads it, so this is the full sum);
+      * against central differences of the FP64 loss sum(g * query(LUT)) in
+        the same texel (the loss changes only through those queries)."""
+    N, Q = 512, 1 << 22
+    r = workloads.rng_for(4)
+    dirs_t = torch.as_tensor(workloads.uniform_dirs(Q, r)).to(DEV)
+    dirs_t = dirs_t[torch.argsort(shm.cell_keys(N, dirs_t).to(torch.int64) & 0xFFFFFFFF, stable=True)].contiguous()
+    dirs = dirs_t.cpu().numpy()
+    lut_np = workloads.random_lut(N, np.random.default_rng(44))
+    lut = torch.as_tensor(lut_np).to(DEV)[None].contiguous()
+    g_t = torch.randn((Q, 4), device=DEV, generator=torch.Generator(device=DEV).manual_seed(44))
+    bc = shm.BackwardContext(N, 1, dirs_t, Q)
+    gl = bc.backward(lut, g_t, want_dirs=False)[0][0].cpu().numpy()
+    g = g_t.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(45)
+    P = N + 2
+    tex = [(f, q, p) for f in (0, 3, 5) for (q, p) in ((0, 0), (0, P - 1), (P - 1, 0), (P - 1, P - 1))]
+    tex += [(int(rng.integers(6)), 0, int(rng.integers(1, P - 1))) for _ in range(6)]      # gutter rows
+    tex += [(int(rng.integers(6)), int(rng.integers(1, P - 1)), P - 1) for _ in range(6)]  # gutter columns
+    while len(tex) < 64:
+        tex.append((int(rng.integers(6)), int(rng.integers(1, P - 1)), int(rng.integers(1, P - 1))))
+    face, i0, j0, _, _ = oracle.locate(dirs, N)
+    C = N + 1
+    key = (face.astype(np.int64) * C + j0) * C + i0
+    key[face < 0] = -1
+
+    def touching(f, q, p):
+        cells = [(f * C + jj) * C + ii for jj in (q - 1, q) for ii in (p - 1, p) if 0 <= jj <= N and 0 <= ii <= N]
+        return np.flatnonzero(np.isin(key, cells))
+
+    sel = [touching(*t) for t in tex]
+    union = np.unique(np.concatenate(sel))
+    rl, _ = oracle.backward(lut_np, dirs[union], g[union], want_dirs=False)
+    lut64 = lut_np.astype(np.float64)
+    got, ref, fd = [], [], []
+    for t, idx in zip(tex, sel):
+        for ch in range(4):
+            got.append(gl[t + (ch,)])
+            ref.append(rl[t + (ch,)])
+            if idx.size == 0:
+                fd.append(0.0)
+                continue
+            eps = 1e-3
+            keep = lut64[t + (ch,)]
+            lut64[t + (ch,)] = keep + eps
+            lp = np.sum(oracle.query(lut64, dirs[idx]) * g[idx])
+            lut64[t + (ch,)] = keep - eps
+            lm = np.sum(oracle.query(lut64, dirs[idx]) * g[idx])
+            lut64[t + (ch,)] = keep
+            fd.append((lp - lm) / (2 * eps))
+    got, ref, fd = (np.array(x).reshape(-1, 4) for x in (got, ref, fd))
+    counts = np.array([x.size for x in sel])
+    print(f"sampled texels: {len(tex)}, queries per texel {counts.min()}..{counts.max()} (mean {counts.mean():.1f})")
+    # gutter corners are read only by queries within half a cell of a cube
+    # corner (mostly none); the other samples are mostly read
+    assert (counts[12:] > 0).sum() >= 48, counts
+    scale = np.sqrt(np.mean(ref ** 2, axis=0))  # per channel
+    e_ref = np.abs(got - ref) / np.maximum(np.abs(ref), scale)
+    e_fd = np.abs(fd - ref) / np.maximum(np.abs(ref), scale)
+    e_gfd = np.abs(got - fd) / np.maximum(np.abs(fd), scale)
+    print(f"grad_lut vs oracle: max rel {e_ref.max():.2e}; vs FD {e_gfd.max():.2e}; oracle vs FD {e_fd.max():.2e}")
+    assert e_ref.max() < 1e-4 and e_gfd.max() < 1e-4
+    assert e_fd.max() < 1e-7
+
+
 def test_uneven_batch_full_size_sampled(tmp_path):
     B = bench.build_uneven_batch()
     objs, n_obj, Qtot = B["objs"], B["n_obj"], B["Qtot"]

@@ -15,17 +15,51 @@ def test_seeded_and_unit():
     assert np.abs(np.linalg.norm(a.astype(np.float64), axis=1) - 1).max() < 1e-6
 
 
+def test_real_sh_convention_matches_the_oracle():
+    """The generator's real SH (scipy's complex harmonics, phase removed) is
+    the convention the oracle bakes in: orthonormal, no Condon-Shortley
+    phase, k = l^2 + l + m (Y_1,1 ~ +x, Y_1,-1 ~ +y)."""
+    import oracle
+
+    d = workloads.uniform_dirs(2000, np.random.default_rng(5)).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    for L in (2, 8, 16):
+        Y = workloads.real_sh(L, d)
+        scale = np.abs(Y).max()
+        assert np.abs(Y - oracle.sh_basis(L, d)).max() < 1e-12 * scale, L
+    k = math.sqrt(3.0 / (4.0 * math.pi))
+    Y1 = workloads.real_sh(1, d)
+    np.testing.assert_allclose(Y1[:, 1:], k * d[:, [1, 2, 0]], atol=1e-14)
+
+
+def test_fibonacci_sphere():
+    p = workloads.fibonacci_sphere(4096)
+    assert p.shape == (4096, 3)
+    assert np.abs(np.linalg.norm(p, axis=1) - 1).max() < 1e-14
+    assert np.abs(p.mean(axis=0)).max() < 1e-3  # spread evenly
+    # nearest-neighbour spacing close to the equal-area spacing sqrt(4 pi / n)
+    sub = p[::64]
+    dmin = np.sort(np.linalg.norm(sub[:, None] - p[None], axis=2), axis=1)[:, 1]
+    assert 0.6 * math.sqrt(4 * math.pi / 4096) < dmin.min() and dmin.max() < 1.6 * math.sqrt(4 * math.pi / 4096)
+
+
 def test_glyph_radius_range():
-    """R = 1 + 0.3 SH / B with B >= max |SH| keeps R inside [0.7, 1.3]."""
+    """R = 1 + 0.3 SH / max|SH| with the maximum over the 4,096-point
+    Fibonacci sphere: |R - 1| reaches exactly 0.3 there, and stays within a
+    few percent of it anywhere else on the sphere."""
     import oracle
 
     c = workloads.sh_glyph_coeffs(8, 4, workloads.rng_for(2))
     assert c.shape == (4, 81)
+    fib = workloads.fibonacci_sphere(4096)
     d = workloads.uniform_dirs(20000, np.random.default_rng(3)).astype(np.float64)
     for k in range(4):
+        Rf = oracle.sh_truth(c[k], fib)[:, 0]
+        assert abs(np.abs(Rf - 1).max() - 0.3) < 1e-12
+        assert 0.7 - 1e-12 <= Rf.min() and Rf.max() <= 1.3 + 1e-12
         R = oracle.sh_truth(c[k], d)[:, 0]
-        assert 0.7 <= R.min() and R.max() <= 1.3
-        assert R.max() - R.min() > 0.05
+        assert np.abs(R - 1).max() < 0.3 * 1.05
+        assert R.max() - R.min() > 0.2
 
 
 def test_fbm_numpy_and_torch_agree_and_gradient():

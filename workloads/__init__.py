@@ -19,6 +19,7 @@ mesh and planet generator are not available, these stand in for them):
   4  fBm heightfield target 1 + 0.2 fBm(w), 2^22 directions, N=512
   5  4,096 uneven objects, N in {8..256}, L in {2..16}, lognormal counts
 """
+import functools
 import math
 
 import numpy as np
@@ -49,21 +50,63 @@ def sh_degree_of_index(L):
     return np.concatenate([np.full(2 * l + 1, l) for l in range(L + 1)])
 
 
+def fibonacci_sphere(n=4096):
+    """n points of the golden-angle (Fibonacci) spiral on the unit sphere:
+    z_i = 1 - (2 i + 1)/n, azimuth i pi (3 - sqrt 5).  FP64 [n, 3]."""
+    i = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def real_sh(L, dirs):
+    """Orthonormal real spherical harmonics Y_k(w), k = l^2 + l + m, without
+    the Condon-Shortley phase (Y_1,1 ~ +x, Y_1,-1 ~ +y), at unit directions
+    dirs [n, 3] (FP64); from scipy's complex harmonics (which carry the
+    phase (-1)^m):  Y_l,+m = sqrt2 (-1)^m Re Y_l^m,  Y_l,-m = sqrt2 (-1)^m
+    Im Y_l^m,  Y_l,0 = Y_l^0.  Returns [n, (L+1)^2] FP64.  This is the
+    convention the target functions are written in (the generator needs it
+    for the normalisation of the glyphs, nothing else)."""
+    from scipy.special import sph_harm_y
+
+    d = np.asarray(dirs, np.float64).reshape(-1, 3)
+    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))  # polar
+    phi = np.arctan2(d[:, 1], d[:, 0])               # azimuth
+    Y = np.empty((d.shape[0], (L + 1) ** 2))
+    for l in range(L + 1):
+        Y[:, l * l + l] = sph_harm_y(l, 0, theta, phi).real
+        for m in range(1, l + 1):
+            z = sph_harm_y(l, m, theta, phi) * ((-1.0) ** m) * math.sqrt(2.0)
+            Y[:, l * l + l + m] = z.real
+            Y[:, l * l + l - m] = z.imag
+    return Y
+
+
+@functools.lru_cache(maxsize=None)
+def _fibonacci_basis(L):
+    """real_sh(L) at the 4,096-point Fibonacci sphere (read-only, cached:
+    the uneven batch draws 4,096 glyphs one at a time)."""
+    Y = real_sh(L, fibonacci_sphere(4096))
+    Y.setflags(write=False)
+    return Y
+
+
 def sh_glyph_coeffs(L, n_obj, rng):
     """Coefficients c_lm = z / (1 + l)^2, z ~ N(0, 1), then the affine map
-    R = 1 + 0.3 SH / B folded in, with B the coefficient bound
-    B = sum_l |c_l| sqrt((2l+1) / 4pi) >= max |SH| (Cauchy-Schwarz plus the
-    addition theorem), so that R lies in [0.7, 1.3] without evaluating SH.
-    Y_00 = 1 / (2 sqrt(pi)), so the constant 1 is c_00 += 2 sqrt(pi).
+    R = 1 + 0.3 SH / max|SH| folded in, max|SH| taken over the 4,096-point
+    Fibonacci sphere in FP64; R then spans [0.7, 1.3] on those points (the
+    extremes of the sphere may lie slightly beyond).  Y_00 = 1 / (2 sqrt(pi)),
+    so the constant 1 is c_00 += 2 sqrt(pi).
     Returns FP64 [n_obj, (L+1)^2]; index k = l^2 + l + m."""
     K = (L + 1) ** 2
     lk = sh_degree_of_index(L)
     c = rng.standard_normal((n_obj, K)) / (1.0 + lk) ** 2
-    B = np.zeros(n_obj)
-    for l in range(L + 1):
-        sl = slice(l * l, (l + 1) * (l + 1))
-        B += np.linalg.norm(c[:, sl], axis=1) * math.sqrt((2 * l + 1) / (4 * math.pi))
-    c = 0.3 * c / B[:, None]
+    Y = _fibonacci_basis(L)
+    M = np.empty(n_obj)
+    for o0 in range(0, n_obj, 4096):  # [4096 x K] x [K x chunk]
+        M[o0:o0 + 4096] = np.abs(Y @ c[o0:o0 + 4096].T).max(axis=0)
+    c = 0.3 * c / M[:, None]
     c[:, 0] += 2.0 * math.sqrt(math.pi)
     return c
 
