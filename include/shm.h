@@ -116,6 +116,19 @@ SHM_API size_t shm_bake_sh_lut_workspace(int32_t L, int32_t N);
 SHM_API int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out,
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The same bake for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument and no allocation; the basis table lives in a
+ * scratch array of SHM_BAKE_NOALLOC_MAX_BYTES inside the library (one per
+ * device, held until the process ends).  Bits identical to shm_bake_sh_lut.
+ * Returns SHM_ERR_UNSUPPORTED when shm_bake_sh_lut_workspace(L, N) exceeds
+ * that size (L <= 16 fits up to N = 32, L <= 8 up to N = 58).  Every call on
+ * a device shares its array: calls that overlap on one device (different
+ * streams, no ordering between them) race and must not be issued. */
+#define SHM_BAKE_NOALLOC_MAX_BYTES (32u << 20)
+SHM_API int shm_bake_sh_lut_noalloc(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype,
+                                    void* lut_out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Bake, general mode (Sec. 3.3 Alg. 1 with central differences and a
  * one-texel bake-time margin).

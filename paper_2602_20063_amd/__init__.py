@@ -29,6 +29,7 @@ SHM_MAX_N, SHM_MAX_L, SHM_MAX_BOUND_BLOCKS = 1024, 16, 64
 SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC, SHM_RECON_FAST_BICUBIC_FD = 0, 1, 2, 3
 SHM_SIGNED = 1
 SHM_CELL_LUT = 2
+SHM_BAKE_NOALLOC_MAX_BYTES = 32 << 20  # scratch of shm_bake_sh_lut_noalloc
 
 
 class ShmError(RuntimeError):
@@ -110,6 +111,7 @@ SIGNATURES = {
     "shm_fit_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _I64, ctypes.c_float, _I64,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     _VP, ctypes.c_size_t, _I32, _VP]),
+    "shm_bake_sh_lut_noalloc": (ctypes.c_int, [_VP, _I32, _I32, _I64, _I32, _VP, _VP]),
     # memory-system probes (include/shm_probe.h)
     "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _VP, _VP, _VP]),
     "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
@@ -191,6 +193,12 @@ def shm_bake_sh_lut(coeffs, L, N, n_obj, out_dtype, lut_out, ws, stream=None):
     _need(coeffs, torch.float32, "coeffs")
     return _check(lib().shm_bake_sh_lut(_ptr(coeffs), L, N, n_obj, out_dtype, _ptr(lut_out), _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def shm_bake_sh_lut_noalloc(coeffs, L, N, n_obj, out_dtype, lut_out, stream=None):
+    """The SH bake without a workspace (the library's scratch array)."""
+    _need(coeffs, torch.float32, "coeffs")
+    return _check(lib().shm_bake_sh_lut_noalloc(_ptr(coeffs), L, N, n_obj, out_dtype, _ptr(lut_out), _stream(stream)))
 
 
 def shm_margin_dirs(N, dirs, stream=None):

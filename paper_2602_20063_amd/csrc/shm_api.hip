@@ -49,6 +49,8 @@ int device_cu_count()
 size_t bake_workspace_bytes(int L, int N);
 int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dtype, void* lut, void* ws,
                    hipStream_t stream);
+int launch_bake_sh_noalloc(const float* coeffs, int L, int N, int64_t n_obj, int out_dtype, void* lut,
+                           hipStream_t stream);
 int launch_margin_dirs(int N, float* dirs, hipStream_t stream);
 int launch_bake_fd(const float* samples, int N, int64_t n_obj, int out_dtype, void* lut, hipStream_t stream);
 int launch_lut_rmax(const void* lut, int dtype, int N, int flags, float* rmax_out, hipStream_t stream);
@@ -239,21 +241,47 @@ size_t shm_bake_sh_lut_workspace(int32_t L, int32_t N)
     return bake_workspace_bytes(L, N);
 }
 
-int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out,
-                    void* ws, size_t ws_bytes, hipStream_t stream)
+// arguments of both SH bakes; SHM_OK with *nothing = true when there is no work
+static int check_bake_args(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype,
+                           const void* lut_out, bool* nothing)
 {
-    clear_error();
+    *nothing = false;
     if (L < 0) return fail(SHM_ERR_INVALID_ARG, "bake: L must be >= 0 (got %d)", L);
     if (L > SHM_MAX_L) return fail(SHM_ERR_UNSUPPORTED, "bake: L must be <= %d (got %d)", SHM_MAX_L, L);
     if (!valid_N(N)) return fail(SHM_ERR_INVALID_ARG, "bake: N must be 1..%d (got %d)", SHM_MAX_N, N);
     if (n_obj < 0) return fail(SHM_ERR_INVALID_ARG, "bake: n_obj must be >= 0");
     if (product_exceeds(n_obj, texel_elems(N), INT64_MAX / 8)) return fail(SHM_ERR_UNSUPPORTED, "bake: LUT too large");
     if (!valid_dtype(out_dtype)) return fail(SHM_ERR_INVALID_ARG, "bake: bad dtype %d", out_dtype);
-    if (n_obj == 0) return SHM_OK;
+    if (n_obj == 0) { *nothing = true; return SHM_OK; }
     if (!coeffs || !lut_out) return fail(SHM_ERR_INVALID_ARG, "bake: null pointer");
+    return SHM_OK;
+}
+
+int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype, void* lut_out,
+                    void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    bool nothing = false;
+    if (int rc = check_bake_args(coeffs, L, N, n_obj, out_dtype, lut_out, &nothing)) return rc;
+    if (nothing) return SHM_OK;
     if (!ws || ws_bytes < bake_workspace_bytes(L, N))
         return fail(SHM_ERR_WORKSPACE, "bake: workspace of %zu bytes needed (got %zu)", bake_workspace_bytes(L, N), ws_bytes);
     return launch_bake_sh(coeffs, L, N, n_obj, out_dtype, lut_out, ws, stream);
+}
+
+int shm_bake_sh_lut_noalloc(const float* coeffs, int32_t L, int32_t N, int64_t n_obj, int32_t out_dtype,
+                            void* lut_out, hipStream_t stream)
+{
+    clear_error();
+    bool nothing = false;
+    if (int rc = check_bake_args(coeffs, L, N, n_obj, out_dtype, lut_out, &nothing)) return rc;
+    const size_t need = bake_workspace_bytes(L, N);
+    if (need > (size_t)SHM_BAKE_NOALLOC_MAX_BYTES)
+        return fail(SHM_ERR_UNSUPPORTED,
+                    "bake_noalloc: the basis table for L=%d, N=%d needs %zu bytes, more than the library's %u-byte "
+                    "scratch; use shm_bake_sh_lut with a workspace", L, N, need, (unsigned)SHM_BAKE_NOALLOC_MAX_BYTES);
+    if (nothing) return SHM_OK;
+    return launch_bake_sh_noalloc(coeffs, L, N, n_obj, out_dtype, lut_out, stream);
 }
 
 int shm_margin_dirs(int32_t N, float* dirs, hipStream_t stream)

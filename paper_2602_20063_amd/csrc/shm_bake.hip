@@ -29,6 +29,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "shm_device.hpp"
 #include "shm_internal.hpp"
 
@@ -610,6 +612,45 @@ int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dty
         SHM_LAUNCH_CHECK();
     }
     return SHM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The bake without a caller workspace, for callers that cannot allocate: the
+// basis table goes to a file-scope device array of SHM_BAKE_NOALLOC_MAX_BYTES
+// (each device the library runs on holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address is looked up once per device, with that device current, and kept.
+// Every call on a device uses the same array; the table is rewritten in full
+// by each call (nothing in it needs clearing), so calls that overlap on one
+// device race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SHM_BAKE_NOALLOC_MAX_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];  // device address of `scratch` per device
+
+static int scratch_address(void** out)
+{
+    int dev = 0;
+    SHM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(SHM_ERR_UNSUPPORTED, "bake_noalloc: device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        SHM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SHM_ERR_HIP, "bake_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SHM_OK;
+}
+
+int launch_bake_sh_noalloc(const float* coeffs, int L, int N, int64_t n_obj, int out_dtype, void* lut,
+                           hipStream_t stream)
+{
+    void* ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    return launch_bake_sh(coeffs, L, N, n_obj, out_dtype, lut, ws, stream);
 }
 
 // ---------------------------------------------------------------------------

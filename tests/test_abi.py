@@ -310,3 +310,17 @@ def test_probe_argument_validation():
     assert call("shm_probe_gather", p, 4096, 0, 256, 64, 1, None, None, None) == shm.SHM_OK  # empty
     assert call("shm_probe_stream_read", p, 100, p, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_probe_stream_read", p, 0, None, None) == shm.SHM_OK
+
+
+def test_bake_noalloc_argument_validation():
+    """The no-allocation bake validates like the workspace bake and refuses a
+    basis table larger than its scratch before touching a device."""
+    p = ctypes.c_void_p(256)
+    assert call("shm_bake_sh_lut_noalloc", p, 16, 64, 1, 0, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert "scratch" in shm.shm_last_error()
+    assert shm.shm_bake_sh_lut_workspace(16, 64) > shm.SHM_BAKE_NOALLOC_MAX_BYTES >= shm.shm_bake_sh_lut_workspace(16, 32)
+    assert call("shm_bake_sh_lut_noalloc", p, 17, 8, 1, 0, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_bake_sh_lut_noalloc", p, 4, 0, 1, 0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_bake_sh_lut_noalloc", None, 4, 8, 1, 0, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_bake_sh_lut_noalloc", p, 4, 8, 1, 7, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_bake_sh_lut_noalloc", None, 4, 8, 0, 0, None, None) == shm.SHM_OK
