@@ -86,7 +86,9 @@ def test_cell_keys_match_fp64_except_ties():
         assert r["ok"], (N, r)
         assert r["mismatches"] <= r["ties_in_band"]
         # the band is a few FP32 ulps of f wide, ~N ulp(1) at the face edges
-        assert r["ties_in_band"] <= 1e-6 * N * r["queries"] + 10, (N, r)
+        # (plus the hand-made edge directions, several of them exactly on
+        # cell edges)
+        assert r["ties_in_band"] <= 1e-6 * N * r["queries"] + len(edge_dirs()) + 10, (N, r)
         total += r["mismatches"]
     # workload 1 at full size
     dirs1 = workloads.uniform_dirs(65536, workloads.rng_for(1))
