@@ -563,6 +563,7 @@ def run_backward_fit():
     gd = torch.empty((Q, 3), device=DEV)
     bwd = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, gd, bctx.ws, True)
     bwd_lut = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, None, bctx.ws, True)
+    bwd_dirs = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, None, gd, bctx.ws, True)
     fwd(); bwd()
     # error sample: a random LUT's gradients; the LUT gradient through the
     # adjoint identity (exact here: the outputs are linear in the LUT), the
@@ -583,8 +584,10 @@ def run_backward_fit():
     ms_f = t_gpu(fwd, 20)
     ms_b = t_gpu(bwd, 20)
     ms_bl = t_gpu(bwd_lut, 20)
+    ms_bd = t_gpu(bwd_dirs, 20)
     lut_bytes = lut.numel() * 4
-    res = {"N": N, "queries": Q, "sort_first_call_ms": sort_ms, "sort_ms": ms_sort, "fwd_ms": ms_f, "bwd_ms": ms_b, "bwd_lut_only_ms": ms_bl,
+    res = {"N": N, "queries": Q, "sort_first_call_ms": sort_ms, "sort_ms": ms_sort, "fwd_ms": ms_f, "bwd_ms": ms_b,
+           "bwd_lut_only_ms": ms_bl, "bwd_dirs_only_ms": ms_bd,
            "bwd_over_fwd": ms_b / ms_f,
            "fwd_hbm_frac": (Q * 28 + lut_bytes) / ms_f / 1e6 / PEAK_HBM_GBS,
            "bwd_hbm_frac": (Q * 40 + 2 * lut_bytes) / ms_b / 1e6 / PEAK_HBM_GBS}

@@ -7,10 +7,11 @@
 //              (key, query index) -> permutation, cell segment starts
 //   2. tiles:  one workgroup per 15 x 15 texel tile of a face; one lane per
 //              cell of the tile (halo included) sums the 16 weights (4 corners
-//              x 4 channels) of its sorted query segment in order and, for the
-//              cells the tile owns, writes the direction gradient (second
-//              chart derivatives + derivative of the chart map); each texel
+//              x 4 channels) of its sorted query segment in order; each texel
 //              then adds its <= 4 cells' corner sums in a fixed order
+//   3. dirs:   the direction gradient of each query (second chart derivatives
+//              + derivative of the chart map), one lane per query in the
+//              queries' own order: it involves no other query
 // The sort depends only on the directions and is reused while they stay
 // fixed.  Integer atomics appear only in the per-block digit histograms.
 #include "shm_device.hpp"
@@ -274,10 +275,8 @@ int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
 // contiguous range of queries, so the tile's queries are BC ranges, read as
 // one concatenated list in rounds of BWD_THREADS:
 //   * every lane takes the next query of the list (balanced, coalesced when
-//     the directions are sorted), computes its 16 weights (4 corners x 4
-//     channels) into an LDS slot and, if the tile owns the query's cell
-//     (i0 >= p0, j0 >= q0: every cell has one owner), its direction
-//     gradient;
+//     the directions are sorted) and computes its 16 weights (4 corners x 4
+//     channels) into an LDS slot;
 //   * every cell lane (one per cell) adds the slots of its segment, in
 //     sorted order.
 // Then each texel adds the corner sums of its <= 4 cells in a fixed order.
@@ -300,10 +299,15 @@ struct FitArgs {
     AdamConsts k;
 };
 
-constexpr int BT = 15;                 // texels per tile side: BC * BC = 256 cells, one per lane
+// texels per tile side (a compile-time tuning knob): BC * BC cells, one per
+// lane of the tile's workgroup (256 lanes for 15, 1024 for 31)
+#ifndef SHM_BWD_BT
+#define SHM_BWD_BT 15
+#endif
+constexpr int BT = SHM_BWD_BT;
 constexpr int BC = BT + 1;             // cells per tile side
-constexpr int BWD_THREADS = 256;
-static_assert(BC * BC == BWD_THREADS, "one lane per cell of a tile");
+constexpr int BWD_THREADS = BC * BC;
+constexpr int DIRS_THREADS = 256;      // lanes per workgroup of the direction gradient
 
 // dL/d(16 footprint scalars) of one query, as 4 corners x (r, r_u h, r_v h, r_uv h^2).
 // Each weight is gR Fs Ft + nlu Fs' Ft + nlv Fs Ft' for one s-basis function
@@ -333,11 +337,9 @@ __device__ __forceinline__ void query_weights(float gR, float nlu, float nlv, co
 }
 
 // dL/d dirs of one query: second chart derivatives of the patch plus the
-// derivative of the chart map (a = sc/ma, b = tc/ma) at d.  Not inlined, so
-// that every kernel variant runs the same instructions and gets the same
-// bits whichever other gradients it computes.  Its reciprocals and square
-// root are the hardware's (~1 ulp): no decision depends on them.
-__device__ __noinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int N, Loc L, float4 gq, float3 M,
+// derivative of the chart map (a = sc/ma, b = tc/ma) at d.  Its reciprocals
+// and square root are the hardware's (~1 ulp): no decision depends on them.
+__device__ __forceinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int N, Loc L, float4 gq, float3 M,
                                          float3 S, float3 T, float x, float y, float z)
 {
     const float Nf = (float)N;
@@ -372,23 +374,23 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <bool LUT, bool DIRS, bool FIT>
-__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
-                                                           int64_t Q, const float* __restrict__ dirs,
-                                                           const float* __restrict__ gout,
-                                                           const uint32_t* __restrict__ perm,
-                                                           const uint32_t* __restrict__ cs, int tiles_per_face,
-                                                           float* __restrict__ grad_lut, float* __restrict__ grad_dirs,
-                                                           FitArgs fa)
+// One texel tile (workgroup-wide: every lane of the workgroup calls it with
+// the same tile index).
+template <bool FIT>
+__device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut, int N, int64_t lut_elems, int64_t Q,
+                                         const float* __restrict__ dirs, const float* __restrict__ gout,
+                                         const uint32_t* __restrict__ perm, const uint32_t* __restrict__ cs,
+                                         int tiles_per_face, float* __restrict__ grad_lut, const FitArgs& fa)
 {
-    static_assert(!FIT || (LUT && !DIRS), "the fitting step sums LUT gradients only");
-    __shared__ float4 slot[BWD_THREADS][4];  // one query's weights per lane; later the cell sums
+    // one query's weights per lane, later the cell sums: corner-major, so that
+    // the 16-byte accesses of consecutive lanes fall on consecutive banks
+    __shared__ float4 slot[4][BWD_THREADS];
     __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
     __shared__ int64_t row_len[BC];          // queries in each cell row's range
     __shared__ int64_t row_off[BC + 1];      // offsets of the rows in the concatenated list
     const int C = N + 1, P = N + 2;
     const int tpf = tiles_per_face;
-    int b = blockIdx.x;
+    int b = tile;
     const int per_face = tpf * tpf;
     const int64_t fo = b / per_face;  // object * 6 + face
     b -= (int)(fo * per_face);
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     const int ci = tid % BC, cj = tid / BC;
     const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
     // with no queries the sort wrote no segment starts: every list is empty
-    const bool cell_ok = LUT && Q > 0 && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
+    const bool cell_ok = Q > 0 && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
     int64_t cs_lo = 0, cs_hi = 0;
     if (cell_ok) {
         const int64_t c = cbase + (int64_t)j0c * C + i0c;
@@ -495,7 +497,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
                 // to its output
                 gq = loss_grad_one(fit_forward(lut_obj, N, L), x, y, z, gq.x, gq.y, gq.z, gq.w, fa.w_value, fa.inv_q);
             }
-            if constexpr (LUT) {
+            {
                 const float A = L.a, B = L.b;
                 const float gS = gq.y * (S.x - A * M.x) + gq.z * (S.y - A * M.y) + gq.w * (S.z - A * M.z);
                 const float gT = gq.y * (T.x - B * M.x) + gq.z * (T.y - B * M.y) + gq.w * (T.z - B * M.z);
@@ -503,13 +505,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
                 float4 w[4];
                 query_weights(gq.x, Nf * kk2 * gS, Nf * kk2 * gT, basis1(L.s), basis1(L.t), w);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) slot[tid][k] = w[k];
-            }
-            if (DIRS && L.i0 >= p0 && r_cur >= 1) {  // the tile owns the cell
-                const float3 gd = dirs_grad(lut_obj, N, L, gq, M, S, T, x, y, z);
-                grad_dirs[3 * q_cur] = gd.x;
-                grad_dirs[3 * q_cur + 1] = gd.y;
-                grad_dirs[3 * q_cur + 2] = gd.z;
+                for (int k = 0; k < 4; ++k) slot[k][tid] = w[k];
             }
         }
         // unconditional: q_next is a valid index even past the list's end
@@ -520,13 +516,13 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         q_cur = q_next;
         r_cur = r_next;
         v_cur = v_next;
-        if constexpr (LUT) {
+        {
             lds_barrier();
             const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
             for (int k2 = lo; k2 < hi; ++k2) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const float4 v = slot[k2][k];
+                    const float4 v = slot[k][k2];
                     acc[k].x += v.x;
                     acc[k].y += v.y;
                     acc[k].z += v.z;
@@ -536,7 +532,6 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
             lds_barrier();
         }
     }
-    if constexpr (!LUT) return;
     // the fitting step's parameters and moments of this lane's texel load
     // while the cell sums are exchanged
     const int t_x = tid % BT, t_y = tid / BT, t_p = p0 + t_x, t_q = q0 + t_y;
@@ -549,7 +544,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         vv = fa.v[t_i];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) slot[tid][k] = acc[k];
+    for (int k = 0; k < 4; ++k) slot[k][tid] = acc[k];
     lds_barrier();
     // texel (p0 + tx, q0 + ty) is corner (1,1) of cell (tx, ty), (0,1) of
     // (tx+1, ty), (1,0) of (tx, ty+1) and (0,0) of (tx+1, ty+1) in tile cells
@@ -561,7 +556,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
         for (int dj = 1; dj >= 0; --dj)
 #pragma unroll
             for (int di = 1; di >= 0; --di) {
-                const float4 v = slot[(ty + 1 - dj) * BC + (tx + 1 - di)][dj * 2 + di];
+                const float4 v = slot[dj * 2 + di][(ty + 1 - dj) * BC + (tx + 1 - di)];
                 a.x += v.x;
                 a.y += v.y;
                 a.z += v.z;
@@ -578,24 +573,55 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
     }
 }
 
+template <bool FIT>
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
+                                                           int64_t Q, const float* __restrict__ dirs,
+                                                           const float* __restrict__ gout,
+                                                           const uint32_t* __restrict__ perm,
+                                                           const uint32_t* __restrict__ cs, int tiles_per_face,
+                                                           float* __restrict__ grad_lut, FitArgs fa)
+{
+    bwd_tile<FIT>((int)blockIdx.x, lut, N, lut_elems, Q, dirs, gout, perm, cs, tiles_per_face, grad_lut, fa);
+}
+
+// Direction gradients of DIRS_THREADS consecutive queries (block blk), in the
+// queries' own order: a direction's gradient involves no other query, so it
+// needs neither the sort nor LDS.  NaN for an invalid direction.
+__device__ __forceinline__ void bwd_dirs_block(int64_t blk, const float* __restrict__ lut, int N, int64_t lut_elems,
+                                               int64_t Q, int64_t q_per_obj, const float* __restrict__ dirs,
+                                               const float* __restrict__ gout, float* __restrict__ grad_dirs)
+{
+    const int64_t q = blk * DIRS_THREADS + threadIdx.x;
+    if (q >= Q) return;
+    const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+    const Loc L = locate(x, y, z, N);
+    float3 gd;
+    if (L.face < 0) {
+        const float nan = __builtin_nanf("");
+        gd = make_float3(nan, nan, nan);
+    } else {
+        const float4 gq = reinterpret_cast<const float4*>(gout)[q];
+        float3 M, S, T;
+        frame_of(L.face, M, S, T);
+        gd = dirs_grad(lut + (q / q_per_obj) * lut_elems, N, L, gq, M, S, T, x, y, z);
+    }
+    grad_dirs[3 * q] = gd.x;
+    grad_dirs[3 * q + 1] = gd.y;
+    grad_dirs[3 * q + 2] = gd.z;
+}
+
+__global__ __launch_bounds__(DIRS_THREADS) void k_bwd_dirs(const float* __restrict__ lut, int N, int64_t lut_elems,
+                                                          int64_t Q, int64_t q_per_obj, const float* __restrict__ dirs,
+                                                          const float* __restrict__ gout,
+                                                          float* __restrict__ grad_dirs)
+{
+    bwd_dirs_block(blockIdx.x, lut, N, lut_elems, Q, q_per_obj, dirs, gout, grad_dirs);
+}
+
 __global__ void k_zero_f4(float4* __restrict__ a, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
-// invalid directions sort after every cell: NaN direction gradient
-__global__ void k_bwd_invalid(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ cs, int64_t n_cells,
-                              int64_t Q, float* __restrict__ grad_dirs)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= Q || k < (int64_t)cs[n_cells]) return;
-    const int64_t q = perm[k];
-    if (q >= Q) return;
-    const float nan = __builtin_nanf("");
-    grad_dirs[3 * q] = nan;
-    grad_dirs[3 * q + 1] = nan;
-    grad_dirs[3 * q + 2] = nan;
 }
 
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
@@ -618,18 +644,21 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     }
     const int tpf = (N + 2 + BT - 1) / BT;
     const int64_t tiles = n_obj * 6ll * tpf * tpf;
-    if (tiles > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "backward: too many tiles for one launch");
-#define SHM_B(A, B)                                                                                                  \
-    hipLaunchKernelGGL((k_bwd_fused<A, B, false>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,      \
-                       texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, grad_lut, grad_dirs, FitArgs{})
-    if (grad_lut && grad_dirs) SHM_B(true, true);
-    else if (grad_lut) SHM_B(true, false);
-    else SHM_B(false, true);
-#undef SHM_B
-    SHM_LAUNCH_CHECK();
+    const int64_t dblocks = (W.Q + DIRS_THREADS - 1) / DIRS_THREADS;
+    if (tiles + dblocks > 0x7fffffff) return fail(SHM_ERR_UNSUPPORTED, "backward: too many workgroups for one launch");
+    // the LUT gradient (sorted tiles) and the direction gradients (query
+    // order) are separate launches: computing the direction gradient inside
+    // the tiles, interleaving both kinds of workgroup in one launch, or
+    // running the two on concurrent streams all measured the same or slower
+    // (the two compete for the same units: the total work sets the time)
+    if (grad_lut) {
+        hipLaunchKernelGGL((k_bwd_fused<false>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,
+                           texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, grad_lut, FitArgs{});
+        SHM_LAUNCH_CHECK();
+    }
     if (grad_dirs) {
-        hipLaunchKernelGGL(k_bwd_invalid, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, perm, cs, W.n_cells,
-                           W.Q, grad_dirs);
+        hipLaunchKernelGGL(k_bwd_dirs, dim3((unsigned)dblocks), dim3(DIRS_THREADS), 0, stream, lut, N, texel_elems(N),
+                           W.Q, q_per_obj, dirs, gout, grad_dirs);
         SHM_LAUNCH_CHECK();
     }
     return SHM_OK;
@@ -654,9 +683,8 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
     fa.m = reinterpret_cast<float4*>(m);
     fa.v = reinterpret_cast<float4*>(v);
     fa.k = adam_consts(step, lr_value, lr_deriv, b1, b2, eps);
-    hipLaunchKernelGGL((k_bwd_fused<true, false, true>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut_in,
-                       N, texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf, (float*)nullptr,
-                       (float*)nullptr, fa);
+    hipLaunchKernelGGL((k_bwd_fused<true>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut_in, N,
+                       texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf, (float*)nullptr, fa);
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }

@@ -10,22 +10,34 @@
 #include "shm_device.hpp"
 #include "shm_internal.hpp"
 
-// queries per lane in the uniform kernel (a compile-time tuning knob)
+// Compile-time tuning knobs of the uniform kernel (every setting gives the
+// same bits; the measured sweep is recorded with the design notes):
+//   SHM_QPT     queries per lane
+//   SHM_QBLOCK  lanes per workgroup (one tile = SHM_QBLOCK * SHM_QPT queries)
+//   SHM_DIR_NT  non-temporal direction loads
+//   SHM_OUT_NT  non-temporal result stores
+// Both streams are touched once; non-temporal accesses keep them from
+// displacing the LUT lines in L2/MALL (non-temporal LUT loads are slower).
 #ifndef SHM_QPT
 #define SHM_QPT 1
 #endif
-// non-temporal direction loads and result stores: both are streamed once,
-// and keeping them out of the caches' retention leaves L2/MALL to the LUT
-// (measured 4% faster on the glyph field; non-temporal LUT loads are slower)
-#ifndef SHM_IO_NT
-#define SHM_IO_NT 1
+#ifndef SHM_QBLOCK
+#define SHM_QBLOCK 256
+#endif
+#ifndef SHM_DIR_NT
+#define SHM_DIR_NT 1
+#endif
+#ifndef SHM_OUT_NT
+#define SHM_OUT_NT 1
 #endif
 
 namespace shm {
 
+constexpr int QB = SHM_QBLOCK;
+
 __device__ __forceinline__ float ld_dir(const float* p)
 {
-#if SHM_IO_NT
+#if SHM_DIR_NT
     return __builtin_nontemporal_load(p);
 #else
     return *p;
@@ -34,7 +46,7 @@ __device__ __forceinline__ float ld_dir(const float* p)
 
 __device__ __forceinline__ void st_out(float* out, int64_t q, float4 r)
 {
-#if SHM_IO_NT
+#if SHM_OUT_NT
     __builtin_nontemporal_store(f32x4{r.x, r.y, r.z, r.w}, reinterpret_cast<f32x4*>(out) + q);
 #else
     reinterpret_cast<float4*>(out)[q] = r;
@@ -43,7 +55,7 @@ __device__ __forceinline__ void st_out(float* out, int64_t q, float4 r)
 
 
 template <bool FP16, bool CELL, bool NRM>
-__global__ __launch_bounds__(256) void k_query_uniform(const void* __restrict__ lut, int N, int64_t lut_elems,
+__global__ __launch_bounds__(QB) void k_query_uniform(const void* __restrict__ lut, int N, int64_t lut_elems,
                                                        int64_t q_per_obj, int tiles_per_obj,
                                                        const float* __restrict__ dirs, float* __restrict__ out,
                                                        float* __restrict__ nrm)
@@ -57,7 +69,7 @@ __global__ __launch_bounds__(256) void k_query_uniform(const void* __restrict__ 
     bool act[SHM_QPT];
 #pragma unroll
     for (int j = 0; j < SHM_QPT; ++j) {
-        const int64_t ql = (int64_t)tile * (256 * SHM_QPT) + j * 256 + threadIdx.x;
+        const int64_t ql = (int64_t)tile * (QB * SHM_QPT) + j * QB + threadIdx.x;
         act[j] = ql < q_per_obj;
         qq[j] = (int64_t)obj * q_per_obj + ql;
         if (act[j]) {
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(256) void k_query_uniform(const void* __restrict__ 
 // written as 4 float4 (corners (i0,j0), (i0+1,j0), (i0,j0+1), (i0+1,j0+1),
 // each (r, r_u h, r_v h, r_uv h^2)); NaN for an invalid direction.
 template <bool FP16, bool CELL>
-__global__ __launch_bounds__(256) void k_gather_foot(const void* __restrict__ lut, int N, int64_t lut_elems,
+__global__ __launch_bounds__(QB) void k_gather_foot(const void* __restrict__ lut, int N, int64_t lut_elems,
                                                      int64_t q_per_obj, int tiles_per_obj,
                                                      const float* __restrict__ dirs, float4* __restrict__ foot)
 {
@@ -98,7 +110,7 @@ __global__ __launch_bounds__(256) void k_gather_foot(const void* __restrict__ lu
     bool act[SHM_QPT];
 #pragma unroll
     for (int j = 0; j < SHM_QPT; ++j) {
-        const int64_t ql = (int64_t)tile * (256 * SHM_QPT) + j * 256 + threadIdx.x;
+        const int64_t ql = (int64_t)tile * (QB * SHM_QPT) + j * QB + threadIdx.x;
         act[j] = ql < q_per_obj;
         qq[j] = (int64_t)obj * q_per_obj + ql;
         if (act[j]) {
@@ -128,7 +140,7 @@ int launch_gather_footprints(const void* lut, int dtype, int layout, int N, int6
                              int64_t q_per_obj, float* foot, hipStream_t stream)
 {
     if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
-    const int64_t tiles = (q_per_obj + 256 * SHM_QPT - 1) / (256 * SHM_QPT);
+    const int64_t tiles = (q_per_obj + QB * SHM_QPT - 1) / (QB * SHM_QPT);
     if (tiles > 0x7fffffff || tiles * n_obj > 0x7fffffff)
         return fail(SHM_ERR_UNSUPPORTED, "gather_footprints: %lld objects x %lld tiles exceeds one launch",
                     (long long)n_obj, (long long)tiles);
@@ -137,11 +149,11 @@ int launch_gather_footprints(const void* lut, int dtype, int layout, int N, int6
     float4* f4 = reinterpret_cast<float4*>(foot);
     const int tpo = (int)tiles;
     if (dtype == SHM_F16) {
-        if (layout == SHM_LAYOUT_CELL) hipLaunchKernelGGL((k_gather_foot<true, true>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
-        else hipLaunchKernelGGL((k_gather_foot<true, false>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+        if (layout == SHM_LAYOUT_CELL) hipLaunchKernelGGL((k_gather_foot<true, true>), grid, dim3(QB), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+        else hipLaunchKernelGGL((k_gather_foot<true, false>), grid, dim3(QB), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
     } else {
-        if (layout == SHM_LAYOUT_CELL) hipLaunchKernelGGL((k_gather_foot<false, true>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
-        else hipLaunchKernelGGL((k_gather_foot<false, false>), grid, dim3(256), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+        if (layout == SHM_LAYOUT_CELL) hipLaunchKernelGGL((k_gather_foot<false, true>), grid, dim3(QB), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
+        else hipLaunchKernelGGL((k_gather_foot<false, false>), grid, dim3(QB), 0, stream, lut, N, le, q_per_obj, tpo, dirs, f4);
     }
     SHM_LAUNCH_CHECK();
     return SHM_OK;
@@ -151,7 +163,7 @@ template <bool FP16, bool CELL, bool NRM>
 static void launch_uniform_t(dim3 grid, hipStream_t st, const void* lut, int N, int64_t le, int64_t qpo, int tpo,
                              const float* dirs, float* out, float* nrm)
 {
-    hipLaunchKernelGGL((k_query_uniform<FP16, CELL, NRM>), grid, dim3(256), 0, st, lut, N, le, qpo, tpo, dirs, out,
+    hipLaunchKernelGGL((k_query_uniform<FP16, CELL, NRM>), grid, dim3(QB), 0, st, lut, N, le, qpo, tpo, dirs, out,
                        nrm);
 }
 
@@ -159,7 +171,7 @@ int launch_query_uniform(const void* lut, int dtype, int layout, int N, int64_t 
                          int64_t q_per_obj, float* out, float* normal, hipStream_t stream)
 {
     if (n_obj == 0 || q_per_obj == 0) return SHM_OK;
-    const int64_t tiles = (q_per_obj + 256 * SHM_QPT - 1) / (256 * SHM_QPT);
+    const int64_t tiles = (q_per_obj + QB * SHM_QPT - 1) / (QB * SHM_QPT);
     if (tiles > 0x7fffffff || tiles * n_obj > 0x7fffffff)
         return fail(SHM_ERR_UNSUPPORTED, "query: %lld objects x %lld tiles exceeds one launch", (long long)n_obj,
                     (long long)tiles);
