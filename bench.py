@@ -155,8 +155,9 @@ def run_probes(lut_cell, dirs_t, out, ms_query):
         query's regions and launch mapping), and 64 B reads anywhere in the
         13.7 GB;
       * the query's full memory pattern: one random 64 B cell per query
-        plus the streamed 12 B direction and 16 B result, no arithmetic.
-    The last is the ceiling the query's rate is set against."""
+        plus the streamed 12 B direction and 16 B result, no arithmetic,
+        and its parts (each stream alone, gathers with one stream).
+    The full pattern is the ceiling the query's rate is set against."""
     n, N, qp = W2["n_glyph"], W2["N"], W2["q_per"]
     Q = n * qp
     region = shm.shm_lut_elems(N, shm.SHM_LAYOUT_CELL) * 4
@@ -168,21 +169,28 @@ def run_probes(lut_cell, dirs_t, out, ms_query):
     ms = t_gpu(f, 5)
     res["stream_read_gbs"] = nbytes / ms / 1e6
     for req in (16, 32, 64, 128):
-        f = lambda: shm.shm_probe_gather(lut_cell, region, n, qp, req, 20063, None, sink)
+        f = lambda: shm.shm_probe_gather(lut_cell, region, n, qp, req, 20063, 0, None, sink)
         f()
         ms = t_gpu(f, 10)
         res[f"gather_{req}B_regions_per_s"] = Q / ms * 1e3
         res[f"gather_{req}B_regions_us"] = ms * 1e3
-    f = lambda: shm.shm_probe_gather(lut_cell, nbytes, 1, Q, 64, 20063, None, sink)
+    f = lambda: shm.shm_probe_gather(lut_cell, nbytes, 1, Q, 64, 20063, 0, None, sink)
     f()
     ms = t_gpu(f, 10)
     res["gather_64B_anywhere_per_s"] = Q / ms * 1e3
-    f = lambda: shm.shm_probe_gather(lut_cell, region, n, qp, 64, 20063, dirs_t, out)
-    f()
-    ms = t_gpu(f, 20)
-    res["query_pattern_us"] = ms * 1e3
-    res["query_pattern_per_s"] = Q / ms * 1e3
-    res["query_over_pattern_time"] = ms_query / ms
+    # the query's pattern and its parts (64 B cells, 12 B directions, 16 B results)
+    parts = {"dirs_only": (0, shm.SHM_PROBE_DIRS), "results_only": (0, shm.SHM_PROBE_OUT),
+             "dirs_and_results": (0, shm.SHM_PROBE_DIRS | shm.SHM_PROBE_OUT),
+             "cells_and_dirs": (64, shm.SHM_PROBE_DIRS), "cells_and_results": (64, shm.SHM_PROBE_OUT),
+             "query_pattern": (64, shm.SHM_PROBE_DIRS | shm.SHM_PROBE_OUT)}
+    res["pattern_parts_us"] = {"cells_only": res["gather_64B_regions_us"]}
+    for name, (req, fl) in parts.items():
+        f = lambda: shm.shm_probe_gather(lut_cell, region, n, qp, req, 20063, fl, dirs_t, out)
+        f()
+        res["pattern_parts_us"][name] = t_gpu(f, 20) * 1e3
+    res["query_pattern_us"] = res["pattern_parts_us"]["query_pattern"]
+    res["query_pattern_per_s"] = Q / res["query_pattern_us"] * 1e6
+    res["query_over_pattern_time"] = ms_query * 1e3 / res["query_pattern_us"]
     log("probes", res)
     return res
 
@@ -256,9 +264,10 @@ def main():
         # pattern, gathers of 64 and 128 B in glyph regions, a stream read
         region = shm.shm_lut_elems(N, shm.SHM_LAYOUT_CELL) * 4
         sink = torch.zeros(4, device=DEV)
-        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 64, 20063, dirs_t, out)
-        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 64, 20063, None, sink)
-        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 128, 20063, None, sink)
+        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 64, 20063, shm.SHM_PROBE_DIRS | shm.SHM_PROBE_OUT,
+                             dirs_t, out)
+        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 64, 20063, 0, None, sink)
+        shm.shm_probe_gather(lut_cell, region, n_glyph, q_per, 128, 20063, 0, None, sink)
         shm.shm_probe_stream_read(lut_cell, lut_cell.numel() * 4, sink)
         torch.cuda.synchronize()
         shm.bake_sh(c_t, N)

@@ -23,21 +23,26 @@ extern "C" {
 
 /* Random gathers inside regions.  Request r (0 <= r < n_regions *
  * per_region) belongs to region r / per_region and reads req_bytes (16, 32,
- * 64 or 128) at the aligned offset req_bytes * floor(h(r) * S / 2^32) of
- * its region, S = floor(region_bytes / req_bytes), h a 32-bit integer hash
- * of (seed, r); one lane per request, 256 requests of one region per
- * workgroup (the query's launch mapping).
- *   base          n_regions * region_bytes readable bytes, 16-byte aligned;
- *                 region_bytes a multiple of 16 and >= req_bytes
- *   dirs          NULL: gathers only, and out is a 16-byte sink that is not
- *                 written for finite data;  non-NULL: [n_regions *
- *                 per_region][3] FP32 streamed as the query streams its
- *                 directions, and out [n_regions * per_region][4] FP32 (16-byte
- *                 aligned) receives one 16 B result per request, as the
- *                 query writes its results
- * Errors: SHM_ERR_INVALID_ARG for a bad size, alignment or null pointer. */
+ * 64 or 128; 0 reads nothing) at the aligned offset req_bytes * floor(h(r) *
+ * S / 2^32) of its region, S = floor(region_bytes / req_bytes), h a 32-bit
+ * integer hash of (seed, r); one lane per request, 256 requests of one
+ * region per workgroup (the query's launch mapping).  flags:
+ *   SHM_PROBE_DIRS  also read the request's direction dirs[r][0..2] (FP32)
+ *                   as the query streams its directions
+ *   SHM_PROBE_OUT   also write one 16 B result per request to out[r][0..3]
+ *                   (FP32), as the query writes its results
+ *   base    n_regions * region_bytes readable bytes, 16-byte aligned (unused
+ *           when req_bytes is 0); region_bytes a multiple of 16, >= req_bytes
+ *   dirs    [n_regions * per_region][3] with SHM_PROBE_DIRS, else unused
+ *   out     [n_regions * per_region][4], 16-byte aligned, with SHM_PROBE_OUT;
+ *           else a 16-byte sink that is not written for finite data
+ * Errors: SHM_ERR_INVALID_ARG for a bad size, flag, alignment or null
+ * pointer. */
+#define SHM_PROBE_DIRS 1
+#define SHM_PROBE_OUT 2
 SHM_API int shm_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region,
-                             int32_t req_bytes, uint32_t seed, const float* dirs, float* out, hipStream_t stream);
+                             int32_t req_bytes, uint32_t seed, int32_t flags, const float* dirs, float* out,
+                             hipStream_t stream);
 
 /* Streaming read of `bytes` bytes (a multiple of 16) at base (16-byte
  * aligned); sink is a 16-byte buffer that is not written for finite data. */

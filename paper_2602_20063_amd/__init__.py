@@ -29,6 +29,7 @@ SHM_MAX_N, SHM_MAX_L, SHM_MAX_BOUND_BLOCKS = 1024, 16, 64
 SHM_RECON_NEAREST, SHM_RECON_BILINEAR_FD, SHM_RECON_BICUBIC, SHM_RECON_FAST_BICUBIC_FD = 0, 1, 2, 3
 SHM_SIGNED = 1
 SHM_CELL_LUT = 2
+SHM_PROBE_DIRS, SHM_PROBE_OUT = 1, 2
 SHM_BAKE_NOALLOC_MAX_BYTES = 32 << 20  # scratch of shm_bake_sh_lut_noalloc
 
 
@@ -113,7 +114,7 @@ SIGNATURES = {
                                     _VP, ctypes.c_size_t, _I32, _VP]),
     "shm_bake_sh_lut_noalloc": (ctypes.c_int, [_VP, _I32, _I32, _I64, _I32, _VP, _VP]),
     # memory-system probes (include/shm_probe.h)
-    "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _VP, _VP, _VP]),
+    "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _I32, _VP, _VP, _VP]),
     "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
 }
 
@@ -222,11 +223,12 @@ def shm_query_value_grad(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, nor
                                              _ptr(normal), _stream(stream)))
 
 
-def shm_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, dirs, out, stream=None):
-    """Random gathers of req_bytes inside regions of base (see shm_probe.h);
-    with dirs, also the query's streamed directions and 16 B results."""
+def shm_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, flags, dirs, out, stream=None):
+    """Random gathers of req_bytes inside regions of base (see shm_probe.h),
+    with the query's streamed directions (SHM_PROBE_DIRS) and/or 16 B results
+    (SHM_PROBE_OUT)."""
     return _check(lib().shm_probe_gather(_ptr(base), region_bytes, n_regions, per_region, req_bytes, seed & 0xFFFFFFFF,
-                                         _ptr(dirs), _ptr(out), _stream(stream)))
+                                         flags, _ptr(dirs), _ptr(out), _stream(stream)))
 
 
 def shm_probe_stream_read(base, nbytes, sink, stream=None):

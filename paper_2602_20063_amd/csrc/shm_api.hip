@@ -86,7 +86,7 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
                     float b2, float eps, void* ws, hipStream_t stream);
 
 int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int req_bytes,
-                        uint32_t seed, const float* dirs, float* out, hipStream_t stream);
+                        uint32_t seed, int flags, const float* dirs, float* out, hipStream_t stream);
 int launch_probe_stream(const void* base, int64_t bytes, float* sink, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
@@ -933,24 +933,28 @@ int shm_sh_eval(const float* coeffs, int32_t L, int64_t n_obj, const float* dirs
 // memory-system probes
 // ---------------------------------------------------------------------------
 int shm_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int32_t req_bytes,
-                     uint32_t seed, const float* dirs, float* out, hipStream_t stream)
+                     uint32_t seed, int32_t flags, const float* dirs, float* out, hipStream_t stream)
 {
     clear_error();
-    if (!(req_bytes == 16 || req_bytes == 32 || req_bytes == 64 || req_bytes == 128))
-        return fail(SHM_ERR_INVALID_ARG, "probe_gather: req_bytes must be 16, 32, 64 or 128 (got %d)", req_bytes);
+    if (!(req_bytes == 0 || req_bytes == 16 || req_bytes == 32 || req_bytes == 64 || req_bytes == 128))
+        return fail(SHM_ERR_INVALID_ARG, "probe_gather: req_bytes must be 0, 16, 32, 64 or 128 (got %d)", req_bytes);
+    if (flags & ~(SHM_PROBE_DIRS | SHM_PROBE_OUT)) return fail(SHM_ERR_INVALID_ARG, "probe_gather: unknown flags %d", flags);
     if (n_regions < 0 || per_region < 0) return fail(SHM_ERR_INVALID_ARG, "probe_gather: negative size");
-    if (region_bytes < req_bytes || region_bytes % 16)
+    if (region_bytes < req_bytes || region_bytes < 16 || region_bytes % 16)
         return fail(SHM_ERR_INVALID_ARG, "probe_gather: region_bytes must be a multiple of 16 and >= req_bytes");
-    if (region_bytes / req_bytes > 0xffffffffll) return fail(SHM_ERR_UNSUPPORTED, "probe_gather: region too large");
+    if (req_bytes && region_bytes / req_bytes > 0xffffffffll)
+        return fail(SHM_ERR_UNSUPPORTED, "probe_gather: region too large");
     if (product_exceeds(n_regions, region_bytes, INT64_MAX / 2) || product_exceeds(n_regions, per_region, INT64_MAX / 16))
         return fail(SHM_ERR_UNSUPPORTED, "probe_gather: sizes overflow");
     const int64_t tiles = (per_region + 255) / 256;
     if (product_exceeds(n_regions, tiles, 0x7fffffff)) return fail(SHM_ERR_UNSUPPORTED, "probe_gather: grid too large");
     if (n_regions == 0 || per_region == 0) return SHM_OK;
-    if (!base || !out) return fail(SHM_ERR_INVALID_ARG, "probe_gather: null pointer");
-    if (!aligned(base, 16) || !aligned(out, 16) || (dirs && !aligned(dirs, 4)))
+    if ((req_bytes && !base) || !out || ((flags & SHM_PROBE_DIRS) && !dirs))
+        return fail(SHM_ERR_INVALID_ARG, "probe_gather: null pointer");
+    if ((req_bytes && !aligned(base, 16)) || !aligned(out, 16) || (dirs && !aligned(dirs, 4)))
         return fail(SHM_ERR_INVALID_ARG, "probe_gather: misaligned buffer");
-    return launch_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, dirs, out, stream);
+    return launch_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, flags,
+                               (flags & SHM_PROBE_DIRS) ? dirs : nullptr, out, stream);
 }
 
 int shm_probe_stream_read(const void* base, int64_t bytes, float* sink, hipStream_t stream)

@@ -300,14 +300,16 @@ def test_hip_error_is_reported_without_a_gpu():
 
 def test_probe_argument_validation():
     p = ctypes.c_void_p(256)
-    assert call("shm_probe_gather", p, 4096, 4, 256, 48, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG  # req size
+    assert call("shm_probe_gather", p, 4096, 4, 256, 48, 1, 0, None, p, None) == shm.SHM_ERR_INVALID_ARG  # req size
     assert "req_bytes" in shm.shm_last_error()
-    assert call("shm_probe_gather", p, 4100, 4, 256, 64, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG  # region % 16
-    assert call("shm_probe_gather", p, 32, 4, 256, 64, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG    # region < req
-    assert call("shm_probe_gather", ctypes.c_void_p(8), 4096, 4, 256, 64, 1, None, p, None) == shm.SHM_ERR_INVALID_ARG
-    assert call("shm_probe_gather", p, 4096, 4, 256, 64, 1, None, None, None) == shm.SHM_ERR_INVALID_ARG
-    assert call("shm_probe_gather", p, 4096, 1 << 40, 1 << 40, 64, 1, None, p, None) == shm.SHM_ERR_UNSUPPORTED
-    assert call("shm_probe_gather", p, 4096, 0, 256, 64, 1, None, None, None) == shm.SHM_OK  # empty
+    assert call("shm_probe_gather", p, 4096, 4, 256, 64, 1, 4, None, p, None) == shm.SHM_ERR_INVALID_ARG   # flags
+    assert call("shm_probe_gather", p, 4100, 4, 256, 64, 1, 0, None, p, None) == shm.SHM_ERR_INVALID_ARG  # region % 16
+    assert call("shm_probe_gather", p, 32, 4, 256, 64, 1, 0, None, p, None) == shm.SHM_ERR_INVALID_ARG    # region < req
+    assert call("shm_probe_gather", ctypes.c_void_p(8), 4096, 4, 256, 64, 1, 0, None, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_probe_gather", p, 4096, 4, 256, 64, 1, 0, None, None, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_probe_gather", p, 4096, 4, 256, 64, 1, shm.SHM_PROBE_DIRS, None, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert call("shm_probe_gather", p, 4096, 1 << 40, 1 << 40, 64, 1, 0, None, p, None) == shm.SHM_ERR_UNSUPPORTED
+    assert call("shm_probe_gather", p, 4096, 0, 256, 64, 1, 0, None, None, None) == shm.SHM_OK  # empty
     assert call("shm_probe_stream_read", p, 100, p, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_probe_stream_read", p, 0, None, None) == shm.SHM_OK
 
