@@ -122,7 +122,7 @@ SHM_API int shm_bake_sh_lut(const float* coeffs, int32_t L, int32_t N, int64_t n
  * scratch array of SHM_BAKE_NOALLOC_MAX_BYTES inside the library (one per
  * device, held until the process ends).  Bits identical to shm_bake_sh_lut.
  * Returns SHM_ERR_UNSUPPORTED when shm_bake_sh_lut_workspace(L, N) exceeds
- * that size (L <= 16 fits up to N = 32, L <= 8 up to N = 58).  Every call on
+ * that size (L <= 16 fits up to N = 32, L <= 8 up to N = 62).  Every call on
  * a device shares its array: calls that overlap on one device (different
  * streams, no ordering between them) race and must not be issued. */
 #define SHM_BAKE_NOALLOC_MAX_BYTES (32u << 20)

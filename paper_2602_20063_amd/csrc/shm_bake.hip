@@ -15,9 +15,11 @@
 // The table is built in FP64 and stored in FP32; the contraction runs on the
 // matrix cores (v_mfma_f32_16x16x4f32, FP32 operands and accumulation).
 //
-// The l = 0 term is left out of the contraction and added once, in the
-// epilogue: Y_00 is a constant with zero derivatives, so it only shifts the
-// value channel, by c_00 Y_00 (rounded once from FP64).  Its value is the
+// The l = 0 term is left out of the table and the contraction and added
+// once, in the epilogue: Y_00 is a constant with zero derivatives, so it only
+// shifts the value channel, by c_00 Y_00 (rounded once from FP64).  The table
+// row kt holds basis function k = kt + 1, and the contraction runs over
+// K - 1 terms.  Its value is the
 // bulk of R (about 1 for a glyph), and summing it first would make every
 // later FP32 addition round at the scale of R rather than at the scale of
 // the varying part; the derivatives of the reconstruction difference
@@ -62,8 +64,9 @@ __device__ __forceinline__ int64_t basis_index(int k, int64_t col, int Kp, int64
 }
 
 // ---------------------------------------------------------------------------
-// Basis table.  One lane per padded texel; writes Bt[k][row], row = texel*4+ch
-// (k-major so the MFMA B operand loads are coalesced), ld = rows_pad.
+// Basis table.  One lane per padded texel; writes Bt[k-1][row] for
+// k = 1 .. K-1, row = texel*4+ch (k-major so the MFMA B operand loads are
+// coalesced), ld = rows_pad.
 // ---------------------------------------------------------------------------
 // Layouts of the table: k-major Bt[k][col] (ld = rows_pad), or, for the
 // register-resident contraction, MFMA fragment order: the B fragment value
@@ -112,7 +115,8 @@ __global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, int frag, flo
         const Real Hv2 = H[2] * wv[0] + H[4] * wv[1] + H[5] * wv[2];
         const Real Yuv = wu[0] * Hv0 + wu[1] * Hv1 + wu[2] * Hv2 + g[0] * wuv[0] + g[1] * wuv[1] + g[2] * wuv[2];
         const float v4[4] = {(float)val, (float)(Yu * sN), (float)(Yv * sN), (float)(Yuv * sN2)};
-        for (int ch = 0; ch < 4; ++ch) Bt[basis_index(k, row + ch, Kp, rows_pad, frag)] = v4[ch];
+        if (k == 0) return;  // the constant l = 0 term is added by the contraction's epilogue
+        for (int ch = 0; ch < 4; ++ch) Bt[basis_index(k - 1, row + ch, Kp, rows_pad, frag)] = v4[ch];
     };
     const Real SQ2 = sqrt(Real(2));
     // complex powers (x + i y)^m = A_m + i B_m, sliding window m-2..m
@@ -176,8 +180,8 @@ __global__ void k_sh_basis(int L, int N, int Kp, int64_t rows_pad, int frag, flo
             }
         }
     }
-    // zero padding rows of K (k = K .. Kp-1)
-    for (int k = (L + 1) * (L + 1); k < Kp; ++k)
+    // zero padding rows (table rows K-1 .. Kp-1)
+    for (int k = (L + 1) * (L + 1) - 1; k < Kp; ++k)
         for (int ch = 0; ch < 4; ++ch) Bt[basis_index(k, row + ch, Kp, rows_pad, frag)] = 0.0f;
 }
 
@@ -192,7 +196,7 @@ __global__ void k_zero_cols(float* __restrict__ Bt, int Kp, int64_t rows, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Contraction on the matrix cores.  D[o][row] = sum_k C[o][k] Bt[k][row].
+// Contraction on the matrix cores.  D[o][row] = sum_{k>=1} C[o][k] Bt[k-1][row].
 // Block: 256 lanes (4 waves, 2 x 2), tile 64 objects x 128 rows; each wave
 // 32 x 64 = 2 x 4 MFMA 16x16 tiles.  K is staged through LDS in chunks.
 // v_mfma_f32_16x16x4f32 operand layout (lane l): A[m = l%16][k = l/16],
@@ -225,12 +229,12 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
         for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < Kp; kc += GB_KC) {
         const int kn = (Kp - kc) < GB_KC ? (Kp - kc) : GB_KC;  // multiple of 4
-        // stage A: As[k][m] = C[o0+m][kc+k] (zero outside)
+        // stage A: As[k][m] = C[o0+m][kc+k+1] (table row kc+k is term kc+k+1; zero outside)
         for (int i = tid; i < GB_M * kn; i += 256) {
             const int m = i / kn, k = i - m * kn;
             const int64_t o = o0 + m;
-            const int kk = kc + k;
-            As[k * GB_LDA + m] = (o < n_obj && kk < K && kk > 0) ? C[o * K + kk] : 0.0f;
+            const int kk = kc + k + 1;
+            As[k * GB_LDA + m] = (o < n_obj && kk < K) ? C[o * K + kk] : 0.0f;
         }
         // stage B: Bs[k][n] = Bt[kc+k][r0+n]  (rows_pad covers the tile)
         for (int i = tid; i < GB_N * kn; i += 256) {
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
 // asynchronously), so the matrix pipe does not wait for them.  No workgroup
 // barriers.
 // ---------------------------------------------------------------------------
-constexpr int G2_KS = 21;  // K steps of 4 held in registers (K <= 84)
+constexpr int G2_KS = 20;  // K steps of 4 held in registers (K - 1 <= 80)
 
 // One wave's output tile goes through LDS so that it leaves as whole rows:
 // the MFMA D layout gives each lane 16 values in 4 rows of 16-column
@@ -476,12 +480,13 @@ __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__
             const int64_t oc = o < n_obj ? o : n_obj - 1;
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
-                const int k = 4 * s + lk;
+                // table row 4 s + lk holds term k = 4 s + lk + 1 (the l = 0
+                // term is added in the epilogue)
+                const int k = 4 * s + lk + 1;
                 const float v = C[oc * K + (k < K ? k : K - 1)];
                 // zero outside the table by a bit mask: a select would let the
                 // compiler sink the load into a branch of its own
-                // (k = 0, the l = 0 term, is added in the epilogue instead)
-                const unsigned int keep = (o < n_obj && k < K && k > 0) ? 0xffffffffu : 0u;
+                const unsigned int keep = (o < n_obj && k < K) ? 0xffffffffu : 0u;
                 a[i][s] = __uint_as_float(__float_as_uint(v) & keep);
             }
         }
@@ -525,7 +530,12 @@ __global__ __launch_bounds__(256, 2) void k_bake_gemm2(const float* __restrict__
     }
 }
 
-static inline int bake_kp(int L) { return (((L + 1) * (L + 1)) + 3) / 4 * 4; }
+// table rows: the K - 1 terms l >= 1, rounded up to a multiple of 4 (at least 4)
+static inline int bake_kp(int L)
+{
+    const int kt = (L + 1) * (L + 1) - 1;
+    return kt < 4 ? 4 : (kt + 3) / 4 * 4;
+}
 static inline int64_t bake_rows(int N) { return texel_elems(N); }
 static inline int64_t bake_rows_pad(int N) { return (bake_rows(N) + GB_N - 1) / GB_N * GB_N; }
 
@@ -578,15 +588,15 @@ int launch_bake_sh(const float* coeffs, int L, int N, int64_t n_obj, int out_dty
             hipLaunchKernelGGL((k_bake_gemm2<false, KSV>), grid, dim3(256), 0, stream, coeffs, K, n_obj, Bt, rows,    \
                                rows_pad, lut, waves_per_xcd, (int)n_sub);                                            \
         break;
-        switch (Kp / 4) {  // L = 0..8: (L + 1)^2 rounded up to a multiple of 4, in steps of 4
+        switch (Kp / 4) {  // L = 0..8: (L + 1)^2 - 1 rounded up to a multiple of 4, in steps of 4
             SHM_G2(1)
-            SHM_G2(3)
+            SHM_G2(2)
             SHM_G2(4)
-            SHM_G2(7)
+            SHM_G2(6)
             SHM_G2(9)
-            SHM_G2(13)
+            SHM_G2(12)
             SHM_G2(16)
-            SHM_G2(21)
+            SHM_G2(20)
             default:
                 return fail(SHM_ERR_UNSUPPORTED, "bake: no contraction kernel for %d K steps", Kp / 4);
         }

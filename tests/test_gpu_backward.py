@@ -10,6 +10,12 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+# FP32 against FP64, relative to the reference's scale: dL/dLUT within 1e-5
+# (measured <= 1.2e-6 on these inputs), dL/d dirs within 2e-5 per query of
+# max(|ref|, RMS |ref|) on random LUTs (measured <= 1e-6); the smooth glyph of
+# the first test, whose gradients pass near zero, within 1e-4 (measured 1.3e-5)
+LUT_TOL = 1e-5
+DIRS_TOL = 2e-5
 
 
 def rng(k):
@@ -39,12 +45,14 @@ def test_backward_matches_oracle():
     gl, gd = run_bwd(lut, dirs, g)
     rl, rd = oracle.backward(lut, dirs, g)
     scale = np.sqrt(np.mean(rl ** 2, axis=(0, 1, 2)))
-    assert (np.abs(gl - rl).max(axis=(0, 1, 2)) / scale).max() < 1e-4
+    print('grad_lut error %.3e' % (np.abs(gl - rl).max(axis=(0, 1, 2)) / scale).max())
+    assert (np.abs(gl - rl).max(axis=(0, 1, 2)) / scale).max() < LUT_TOL
     gn = np.linalg.norm(rd, axis=1)
     floor = np.sqrt(np.mean(gn ** 2))
     err = np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)
-    assert err.max() < 1e-3, err.max()
-    assert np.sqrt(np.mean(err ** 2)) < 1e-4
+    print('grad_dirs error max %.3e rms %.3e' % (err.max(), np.sqrt(np.mean(err ** 2))))
+    assert err.max() < 1e-4, err.max()
+    assert np.sqrt(np.mean(err ** 2)) < 5e-6
 
 
 def test_backward_multi_object_and_invalid():
@@ -61,12 +69,15 @@ def test_backward_multi_object_and_invalid():
         sl = slice(o * qpo, (o + 1) * qpo)
         rl, rd = oracle.backward(lut[o], dirs[sl], g[sl])
         scale = np.sqrt(np.mean(rl ** 2))
-        assert np.abs(gl[o] - rl).max() / scale < 1e-4
+        print('grad_lut error %.3e' % (np.abs(gl[o] - rl).max() / scale))
+        assert np.abs(gl[o] - rl).max() / scale < LUT_TOL
         ok = np.isfinite(rd[:, 0])
         assert np.array_equal(np.isfinite(gd[sl, 0]), ok)
         gn = np.linalg.norm(rd[ok], axis=1)
         floor = np.sqrt(np.mean(gn ** 2))
-        assert (np.linalg.norm(gd[sl][ok] - rd[ok], axis=1) / np.maximum(gn, floor)).max() < 1e-3
+        _e = np.linalg.norm(gd[sl][ok] - rd[ok], axis=1) / np.maximum(gn, floor)
+        print('grad_dirs error max %.3e rms %.3e' % (_e.max(), np.sqrt(np.mean(_e ** 2))))
+        assert _e.max() < DIRS_TOL
 
 
 def test_backward_bitwise_repeatable():
@@ -92,7 +103,8 @@ def test_backward_all_queries_in_one_cell():
     gl, _ = run_bwd(lut, dirs, g)
     rl, _ = oracle.backward(lut, dirs, g, want_dirs=False)
     scale = np.abs(rl).max()
-    assert np.abs(gl - rl).max() / scale < 1e-4
+    print('grad_lut error %.3e' % (np.abs(gl - rl).max() / scale))
+    assert np.abs(gl - rl).max() / scale < LUT_TOL
 
 
 def test_autograd_function_and_fd():
@@ -133,10 +145,13 @@ def test_backward_three_radix_passes(N):
     gl, gd = run_bwd(lut, dirs, g)
     rl, rd = oracle.backward(lut, dirs, g)
     scale = np.abs(rl).max()
-    assert np.abs(gl - rl).max() / scale < 1e-4
+    print('grad_lut error %.3e' % (np.abs(gl - rl).max() / scale))
+    assert np.abs(gl - rl).max() / scale < LUT_TOL
     gn = np.linalg.norm(rd, axis=1)
     floor = np.sqrt(np.mean(gn ** 2))
-    assert (np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3
+    _e = np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)
+    print('grad_dirs error max %.3e rms %.3e' % (_e.max(), np.sqrt(np.mean(_e ** 2))))
+    assert _e.max() < DIRS_TOL
 
 
 def test_backward_empty_and_partial_requests():

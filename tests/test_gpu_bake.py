@@ -37,7 +37,10 @@ def check_lut(g, ref, what, val_rtol=1e-5, der_rtol=1e-4):
         assert e <= der_rtol, f"{what}: channel {ch} error {e:.3e} of RMS"
 
 
-@pytest.mark.parametrize("L,N,n", [(4, 10, 1), (8, 32, 70), (2, 5, 3), (0, 3, 2), (12, 16, 5), (16, 8, 4)])
+# every register-resident contraction width (L = 0 .. 8: 1, 1, 2, 4, 6, 9, 12,
+# 16, 20 K steps of 4) and the LDS-staged kernel above it (L >= 9)
+@pytest.mark.parametrize("L,N,n", [(4, 10, 1), (8, 32, 70), (2, 5, 3), (0, 3, 2), (12, 16, 5), (16, 8, 4), (1, 7, 2),
+                                   (3, 9, 3), (5, 11, 2), (6, 12, 2), (7, 13, 2), (9, 8, 2)])
 def test_bake_sh_matches_oracle(L, N, n):
     c = workloads.sh_glyph_coeffs(L, n, rng(L * 100 + N))
     c32 = c.astype(np.float32)

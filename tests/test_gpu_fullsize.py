@@ -95,7 +95,9 @@ def test_backward_full_size():
     gk = gd.cpu().numpy()[k]
     gn = np.linalg.norm(rd, axis=1)
     floor = np.sqrt(np.mean(gn ** 2))
-    assert (np.linalg.norm(gk - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3
+    _e = np.linalg.norm(gk - rd, axis=1) / np.maximum(gn, floor)
+    print('grad_dirs error max %.3e rms %.3e' % (_e.max(), np.sqrt(np.mean(_e ** 2))))
+    assert _e.max() < 2e-5  # FP32 vs FP64 (measured <= 1e-6)
 
 
 def test_backward_full_size_texels_elementwise_and_fd():
@@ -164,7 +166,7 @@ def test_backward_full_size_texels_elementwise_and_fd():
     e_fd = np.abs(fd - ref) / np.maximum(np.abs(ref), scale)
     e_gfd = np.abs(got - fd) / np.maximum(np.abs(fd), scale)
     print(f"grad_lut vs oracle: max rel {e_ref.max():.2e}; vs FD {e_gfd.max():.2e}; oracle vs FD {e_fd.max():.2e}")
-    assert e_ref.max() < 1e-4 and e_gfd.max() < 1e-4
+    assert e_ref.max() < 1e-5 and e_gfd.max() < 1e-5  # FP32 sums vs FP64 (measured 4.4e-7)
     assert e_fd.max() < 1e-7
 
 

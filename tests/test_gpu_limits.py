@@ -64,7 +64,9 @@ def test_backward_largest_face():
     gk = gd.cpu().numpy()[k]
     gn = np.linalg.norm(rd, axis=1)
     floor = np.sqrt(np.mean(gn ** 2))
-    assert (np.linalg.norm(gk - rd, axis=1) / np.maximum(gn, floor)).max() < 1e-3
+    _e = np.linalg.norm(gk - rd, axis=1) / np.maximum(gn, floor)
+    print('grad_dirs error max %.3e rms %.3e' % (_e.max(), np.sqrt(np.mean(_e ** 2))))
+    assert _e.max() < 2e-5  # FP32 vs FP64 (measured <= 1e-6)
 
 
 def test_trace_face_size_one():
