@@ -298,6 +298,7 @@ def main():
         plan = shm.Plan(B["objs"], shm.SHM_F16, shm.SHM_LAYOUT_CELL)
         plan.set_shape(256, 2, 512, 4)
         plan.launch(lut16, B["dirs"], outb)
+        plan.probe(lut16, B["dirs"], outb)
         torch.cuda.synchronize()
         plan.close()
         print(json.dumps({"counters_run": True, "query_launches": 3, "copy_bytes": 1 << 30}))
@@ -727,6 +728,12 @@ def run_batched():
     plan.capture_graph(lut16, dirs, out16)
     ms_graph = t_gpu(lambda: plan.graph_launch(), 10)
     ms_plan = t_gpu(lambda: plan.launch(lut16, dirs, out16), 10)
+    # the same walk, shape and traffic without the arithmetic (shm_plan_probe):
+    # the rate the memory system gives this batch's access pattern
+    outp = torch.empty_like(out16)
+    plan.probe(lut16, dirs, outp)
+    ms_probe = t_gpu(lambda: plan.probe(lut16, dirs, outp), 10)
+    del outp
 
     def per_object():
         for (o_off, Nn, q0, q) in objs:
@@ -753,7 +760,8 @@ def run_batched():
            "graph_ms": ms_graph, "plan_launch_ms": ms_plan, "per_object_f32_ms": ms_per,
            "per_object_f32_graph_ms": ms_per_graph, "queries_per_s": Qtot / ms_graph * 1e3,
            "speedup_vs_per_object_f32": ms_per / ms_graph, "speedup_vs_per_object_f32_graph": ms_per_graph / ms_graph,
-           "alg_bytes": b16, "hbm_frac": b16 / ms_graph / 1e6 / PEAK_HBM_GBS, "shape": shape, "autotune_s": tune_s,
+           "alg_bytes": b16, "hbm_frac": b16 / ms_graph / 1e6 / PEAK_HBM_GBS,
+           "pattern_probe_ms": ms_probe, "frac_of_pattern": ms_probe / ms_graph, "shape": shape, "autotune_s": tune_s,
            "work_items": plan.work_items}
     # sample for the error check: the first 16 objects
     smp = {"coeffs": coeffs[:16], "N": [int(x) for x in spec["N"][:16]], "q": [int(x) for x in Qs[:16]],

@@ -48,6 +48,24 @@ SHM_API int shm_probe_gather(const void* base, int64_t region_bytes, int64_t n_r
  * aligned); sink is a 16-byte buffer that is not written for finite data. */
 SHM_API int shm_probe_stream_read(const void* base, int64_t bytes, float* sink, hipStream_t stream);
 
+/* The batched form's memory traffic without its arithmetic: the walk of
+ * shm_plan_launch over the plan's work list, in the plan's current launch
+ * shape, where each query q reads its direction dirs[q][0..2], the
+ * footprint of one pseudo-random cell of its object's LUT (cell index
+ * floor(h(q) * 6 (N+1)^2 / 2^32), h a 32-bit integer hash of (seed, q);
+ * loaded as the query loads it in the plan's dtype and layout: one 64 B
+ * (FP32) or 32 B (FP16) block in the CELL layout, two rows of two texels in
+ * the TEXEL layout), and writes out[q] = (dirs[q][0..2], w) with w the
+ * 32-bit pattern of the wrapping sum of the footprint's 32-bit words.
+ * Arguments as for shm_plan_launch (lut, dirs, out of the plan's objects;
+ * out 16-byte aligned, lut 16-byte aligned, 8 for FP16 texels).  The launch
+ * counts as a launch of the plan (shm_plan_set_shape and
+ * shm_plan_destroy wait for it).
+ * Errors: SHM_ERR_INVALID_ARG for a null plan or pointer or a misaligned
+ * buffer. */
+SHM_API int shm_plan_probe(shm_plan* plan, const void* lut, const float* dirs, float* out, uint32_t seed,
+                           hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

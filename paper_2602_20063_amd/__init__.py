@@ -116,6 +116,7 @@ SIGNATURES = {
     # memory-system probes (include/shm_probe.h)
     "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _I32, _VP, _VP, _VP]),
     "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    "shm_plan_probe": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_uint32, _VP]),
 }
 
 _lib = None
@@ -476,6 +477,11 @@ class Plan:
 
     def graph_launch(self, stream=None):
         _check(lib().shm_plan_graph_launch(self.handle, _stream(stream)))
+
+    def probe(self, lut, dirs, out, seed=20063, stream=None):
+        """shm_plan_probe: the launch's memory traffic without its arithmetic
+        (see shm_probe.h); out[q] = (dirs[q], bits of the footprint's word sum)."""
+        _check(lib().shm_plan_probe(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), seed & 0xFFFFFFFF, _stream(stream)))
 
     @property
     def work_items(self):

@@ -88,6 +88,9 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
 int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int req_bytes,
                         uint32_t seed, int flags, const float* dirs, float* out, hipStream_t stream);
 int launch_probe_stream(const void* base, int64_t bytes, float* sink, hipStream_t stream);
+int launch_probe_plan(const void* lut, int dtype, int layout, const shm_object* objs_dev, const WorkItem* items_dev,
+                      int64_t n_items, const XcdSplit& split, const shm_launch_shape& shape, int n_cu,
+                      const float* dirs, float* out, uint32_t seed, hipStream_t stream);
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
@@ -965,6 +968,19 @@ int shm_probe_stream_read(const void* base, int64_t bytes, float* sink, hipStrea
     if (!base || !sink) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: null pointer");
     if (!aligned(base, 16) || !aligned(sink, 16)) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: misaligned buffer");
     return launch_probe_stream(base, bytes, sink, stream);
+}
+
+int shm_plan_probe(shm_plan* plan, const void* lut, const float* dirs, float* out, uint32_t seed, hipStream_t stream)
+{
+    clear_error();
+    if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_probe: null plan");
+    if (plan->n_items == 0) return SHM_OK;
+    if (!lut || !dirs || !out) return fail(SHM_ERR_INVALID_ARG, "plan_probe: null pointer");
+    const size_t al = (plan->dtype == SHM_F16 && plan->layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(out, 16)) return fail(SHM_ERR_INVALID_ARG, "plan_probe: misaligned buffer");
+    int rc = launch_probe_plan(lut, plan->dtype, plan->layout, plan->d_objs, plan->d_items, plan->n_items, plan->split,
+                               plan->shape, plan->n_cu, dirs, out, seed, stream);
+    return rc ? rc : plan_mark_launch(plan, stream);
 }
 
 }  // extern "C"

@@ -14,6 +14,12 @@
 //                    the query's; the parts alone show what each costs.
 //   k_probe_stream   streaming reads of a whole buffer (float4 per lane,
 //                    grid-stride), the bandwidth ceiling of plain reads.
+//   k_probe_plan     the batched form's traffic: the persistent kernel's walk
+//                    over a plan's work list in the plan's launch shape; per
+//                    query the 12 B direction, the footprint of a
+//                    pseudo-random cell of its object's LUT (loaded as the
+//                    query loads it: one block in the CELL layout, two texel
+//                    rows in the TEXEL layout) and the 16 B result.
 // Offsets come from Wellons' "lowbias32" integer hash of (seed, request).
 #include "shm_device.hpp"
 #include "shm_internal.hpp"
@@ -83,6 +89,122 @@ __global__ __launch_bounds__(256) void k_probe_stream(const float4* __restrict__
         acc.w += v.w;
     }
     if (__float_as_uint(acc.x + acc.y + acc.z + acc.w) == 0x7fc00001u) sink[0] = acc.x;
+}
+
+// pseudo-random index in [0, n) of request q (n < 2^32)
+__device__ __forceinline__ uint32_t probe_pick(int64_t q, uint32_t seed, uint32_t n)
+{
+    const uint32_t h = lowbias32((uint32_t)q * 0x9e3779b1u ^ seed ^ (uint32_t)(q >> 32));
+    return (uint32_t)(((uint64_t)h * n) >> 32);
+}
+
+// The footprint loads of one query at cell (face, j0, i0) of a LUT of face
+// size N, as the query issues them, folded into a 32-bit word sum.
+template <bool FP16, bool CELL>
+__device__ __forceinline__ uint32_t probe_footprint(const char* __restrict__ base, int N, uint32_t cell)
+{
+    uint32_t acc = 0;
+    if constexpr (CELL) {
+        const uint4* p = reinterpret_cast<const uint4*>(base) + (int64_t)cell * (FP16 ? 2 : 4);
+#pragma unroll
+        for (int k = 0; k < (FP16 ? 2 : 4); ++k) {
+            const uint4 v = p[k];
+            acc += v.x + v.y + v.z + v.w;
+        }
+    } else {
+        const int C = N + 1, P = N + 2;
+        const int face = (int)(cell / (uint32_t)(C * C));
+        const int rem = (int)(cell - (uint32_t)face * (uint32_t)(C * C));
+        const int j0 = rem / C, i0 = rem - j0 * C;
+        const int64_t t0 = (int64_t)(face * P + j0) * P + i0;  // texel (i0, j0); the row above is t0 + P
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int64_t t = t0 + r * P;
+            if constexpr (FP16) {
+                const uint2* p = reinterpret_cast<const uint2*>(base) + t;
+                const uint2 a = p[0], b = p[1];
+                acc += a.x + a.y + b.x + b.y;
+            } else {
+                const uint4* p = reinterpret_cast<const uint4*>(base) + t;
+                const uint4 a = p[0], b = p[1];
+                acc += a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w;
+            }
+        }
+    }
+    return acc;
+}
+
+template <bool FP16, bool CELL, int QPT>
+__global__ void k_probe_plan(const void* __restrict__ lut, const shm_object* __restrict__ objs,
+                             const WorkItem* __restrict__ items, XcdSplit split, const float* __restrict__ dirs,
+                             float* __restrict__ out, uint32_t seed)
+{
+    // the walk of k_query_persistent: nx groups of blocks, group x walks
+    // slices x, x + nx, ... of the work list
+    const int G = (int)gridDim.x;
+    const int nx = G < 8 ? G : 8;
+    const int x = (int)blockIdx.x % nx, local = (int)blockIdx.x / nx;
+    const int per = (G - x + nx - 1) / nx;
+    const int B = (int)blockDim.x;
+    for (int s = x; s < 8; s += nx)
+    for (int64_t w = split.b[s] + local; w < split.b[s + 1]; w += per) {
+        const WorkItem it = items[w];
+        const shm_object o = objs[it.obj];
+        const int N = o.N;
+        const uint32_t n_cells = 6u * (uint32_t)(N + 1) * (uint32_t)(N + 1);
+        const char* base = reinterpret_cast<const char*>(lut) + (size_t)o.lut_offset * (FP16 ? 2 : 4);
+        for (int k0 = 0; k0 < it.n; k0 += B * QPT) {
+            float dx[QPT], dy[QPT], dz[QPT];
+            int64_t qq[QPT];
+            bool act[QPT];
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                const int k = k0 + j * B + (int)threadIdx.x;
+                act[j] = k < it.n;
+                qq[j] = it.q0 + k;
+                if (act[j]) {
+                    dx[j] = __builtin_nontemporal_load(dirs + 3 * qq[j]);
+                    dy[j] = __builtin_nontemporal_load(dirs + 3 * qq[j] + 1);
+                    dz[j] = __builtin_nontemporal_load(dirs + 3 * qq[j] + 2);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                if (!act[j]) continue;
+                const uint32_t acc = probe_footprint<FP16, CELL>(base, N, probe_pick(qq[j], seed, n_cells));
+                __builtin_nontemporal_store(f32x4{dx[j], dy[j], dz[j], __uint_as_float(acc)},
+                                            reinterpret_cast<f32x4*>(out) + qq[j]);
+            }
+        }
+    }
+}
+
+int launch_probe_plan(const void* lut, int dtype, int layout, const shm_object* objs_dev, const WorkItem* items_dev,
+                      int64_t n_items, const XcdSplit& split, const shm_launch_shape& shape, int n_cu,
+                      const float* dirs, float* out, uint32_t seed, hipStream_t stream)
+{
+    if (n_items == 0) return SHM_OK;
+    int64_t G = (int64_t)shape.grid_per_cu * n_cu;
+    if (G > n_items) G = n_items;
+    const dim3 grid((unsigned)G), block((unsigned)shape.block);
+    const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL;
+#define SHM_PP(F, C, Q) hipLaunchKernelGGL((k_probe_plan<F, C, Q>), grid, block, 0, stream, lut, objs_dev, items_dev, \
+                                           split, dirs, out, seed)
+#define SHM_PPQ(F, C)                                    \
+    switch (shape.qpt) {                                 \
+        case 1: SHM_PP(F, C, 1); break;                  \
+        case 2: SHM_PP(F, C, 2); break;                  \
+        default: SHM_PP(F, C, 4); break;                 \
+    }
+    if (f16) {
+        if (cell) { SHM_PPQ(true, true) } else { SHM_PPQ(true, false) }
+    } else {
+        if (cell) { SHM_PPQ(false, true) } else { SHM_PPQ(false, false) }
+    }
+#undef SHM_PPQ
+#undef SHM_PP
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
 }
 
 int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int req_bytes,

@@ -312,6 +312,8 @@ def test_probe_argument_validation():
     assert call("shm_probe_gather", p, 4096, 0, 256, 64, 1, 0, None, None, None) == shm.SHM_OK  # empty
     assert call("shm_probe_stream_read", p, 100, p, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_probe_stream_read", p, 0, None, None) == shm.SHM_OK
+    assert call("shm_plan_probe", None, p, p, p, 1, None) == shm.SHM_ERR_INVALID_ARG  # no plan, no device call
+    assert "null plan" in shm.shm_last_error()
 
 
 def test_bake_noalloc_argument_validation():

@@ -40,3 +40,40 @@ def test_probe_sinks_are_not_written():
     shm.shm_probe_stream_read(base, base.numel() * 4, sink)
     torch.cuda.synchronize()
     assert torch.equal(sink, torch.full_like(sink, 123.0))
+
+
+@pytest.mark.parametrize("dtype,layout", [(shm.SHM_F32, shm.SHM_LAYOUT_CELL), (shm.SHM_F16, shm.SHM_LAYOUT_CELL),
+                                          (shm.SHM_F32, shm.SHM_LAYOUT_TEXEL), (shm.SHM_F16, shm.SHM_LAYOUT_TEXEL)])
+def test_plan_probe_walks_every_query_of_its_object(dtype, layout):
+    """The plan probe answers every query of the plan once, from its own
+    object's LUT: each object's LUT holds one distinct 32-bit word, so the
+    footprint's word sum names the object, in every launch shape."""
+    Ns, Qs = [5, 8, 3, 1], [700, 131, 2000, 64]
+    cell = layout == shm.SHM_LAYOUT_CELL
+    elems = [6 * (N + 1) ** 2 * 16 if cell else 6 * (N + 2) ** 2 * 4 for N in Ns]
+    offs = np.concatenate([[0], np.cumsum(elems)[:-1]])
+    qb = np.concatenate([[0], np.cumsum(Qs)[:-1]])
+    Q = int(sum(Qs))
+    f16 = dtype == shm.SHM_F16
+    vals = [1.5, -2.25, 3.0, 0.125]
+    lut = torch.empty(int(sum(elems)), dtype=torch.float16 if f16 else torch.float32, device=DEV)
+    words = []
+    for o, v in enumerate(vals):
+        lut[int(offs[o]):int(offs[o]) + elems[o]] = v
+        b = int(np.array([v], np.float16 if f16 else np.float32).view(np.uint16 if f16 else np.uint32)[0])
+        words.append(b | (b << 16) if f16 else b)
+    n_words = 8 if f16 else 16  # 32 B (FP16) or 64 B (FP32) per footprint, both layouts
+    expect_w = np.concatenate([np.full(q, (n_words * w) & 0xFFFFFFFF, np.uint32) for q, w in zip(Qs, words)])
+    dirs = torch.as_tensor(np.random.default_rng(9).standard_normal((Q, 3)).astype(np.float32)).to(DEV)
+    plan = shm.Plan([(int(offs[o]), Ns[o], int(qb[o]), Qs[o]) for o in range(4)], dtype, layout)
+    try:
+        for shape in [(256, 2, 512, 4), (64, 1, 64, 2), (128, 4, 1024, 1)]:
+            plan.set_shape(*shape)
+            out = torch.full((Q, 4), float("nan"), device=DEV)
+            plan.probe(lut, dirs, out, seed=11)
+            torch.cuda.synchronize()
+            assert torch.equal(out[:, :3], dirs), shape
+            got_w = out[:, 3].contiguous().view(torch.int32).cpu().numpy().view(np.uint32)
+            assert np.array_equal(got_w, expect_w), shape
+    finally:
+        plan.close()
