@@ -287,6 +287,23 @@ __global__ __launch_bounds__(256) void k_bake_gemm(const float* __restrict__ C, 
 // ---------------------------------------------------------------------------
 constexpr int G2_KS = 20;  // K steps of 4 held in registers (K - 1 <= 80)
 
+// Compile-time scheduling knobs of the register-resident contraction (every
+// setting gives the same bits):
+//   SHM_G2_MODE       0: scheduling barriers between the MFMA groups and the
+//                     epilogue parts threaded through them; 1: no barriers
+//                     (the compiler's order); 2: as 0, and the wave raises
+//                     its priority while it issues an MFMA group
+#ifndef SHM_G2_MODE
+#define SHM_G2_MODE 0
+#endif
+
+__device__ __forceinline__ void g2_sep()
+{
+#if SHM_G2_MODE != 1
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // One wave's output tile goes through LDS so that it leaves as whole rows:
 // the MFMA D layout gives each lane 16 values in 4 rows of 16-column
 // segments; stored directly that is 64 B pieces of four rows per
@@ -307,6 +324,9 @@ __device__ __forceinline__ void wave_lds_sync()
 template <int KS, int S0, int S1>
 __device__ __forceinline__ void g2_mma(const float (&a)[2][KS], const float (&b)[2][KS], floatx4 (&acc)[2][2])
 {
+#if SHM_G2_MODE == 2
+    __builtin_amdgcn_s_setprio(1);
+#endif
 #pragma unroll
     for (int s = S0; s < S1; ++s)
 #pragma unroll
@@ -314,6 +334,9 @@ __device__ __forceinline__ void g2_mma(const float (&a)[2][KS], const float (&b)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+#if SHM_G2_MODE == 2
+    __builtin_amdgcn_s_setprio(0);
+#endif
 }
 
 // Epilogue, part 1: D[m][n] with m = 16 i + 4 lk + e (object), n = 16 j + lm
@@ -394,18 +417,18 @@ __device__ __forceinline__ void g2_tile_overlap(const float (&a)[2][KS], const f
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     g2_mma<KS, 0, S1>(a, b, acc);
-    __builtin_amdgcn_sched_barrier(0);
+    g2_sep();
     g2_stage(prev, stage, lane);
-    __builtin_amdgcn_sched_barrier(0);
+    g2_sep();
     g2_mma<KS, S1, S2>(a, b, acc);
-    __builtin_amdgcn_sched_barrier(0);
+    g2_sep();
     float4 v[4];
     g2_unstage(stage, lane, v);
-    __builtin_amdgcn_sched_barrier(0);
+    g2_sep();
     g2_mma<KS, S2, S3>(a, b, acc);
-    __builtin_amdgcn_sched_barrier(0);
+    g2_sep();
     g2_store<F16OUT>(v, cst, o0, n_obj, col_prev, rows, lane, lut);
-    __builtin_amdgcn_sched_barrier(0);
+    g2_sep();
     g2_mma<KS, S3, KS>(a, b, acc);
 }
 
