@@ -172,6 +172,22 @@ def _need(t, dtype, name):
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
 
 
+def _fits(t, nbytes, name):
+    """The C ABI takes bare pointers: refuse a tensor smaller than the bytes
+    the call will read or write there, before anything is launched."""
+    if t is not None and nbytes > 0 and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes; the call accesses {nbytes}")
+
+
+def _dbytes(dtype_code):
+    return 2 if dtype_code == SHM_F16 else 4
+
+
+def _lut_bytes(N, layout, dtype_code, n_obj=1):
+    per = 6 * (N + 2) ** 2 * 4 if layout == SHM_LAYOUT_TEXEL else 6 * (N + 1) ** 2 * 16
+    return max(n_obj, 0) * per * _dbytes(dtype_code)
+
+
 # ---------------------------------------------------------------------------
 # one-to-one mirrors of the C ABI
 # ---------------------------------------------------------------------------
@@ -193,6 +209,8 @@ def shm_bake_sh_lut_workspace(L, N):
 
 def shm_bake_sh_lut(coeffs, L, N, n_obj, out_dtype, lut_out, ws, stream=None):
     _need(coeffs, torch.float32, "coeffs")
+    _fits(coeffs, max(n_obj, 0) * (L + 1) ** 2 * 4, "coeffs")
+    _fits(lut_out, _lut_bytes(N, SHM_LAYOUT_TEXEL, out_dtype, n_obj), "lut_out")
     return _check(lib().shm_bake_sh_lut(_ptr(coeffs), L, N, n_obj, out_dtype, _ptr(lut_out), _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream(stream)))
 
@@ -200,26 +218,39 @@ def shm_bake_sh_lut(coeffs, L, N, n_obj, out_dtype, lut_out, ws, stream=None):
 def shm_bake_sh_lut_noalloc(coeffs, L, N, n_obj, out_dtype, lut_out, stream=None):
     """The SH bake without a workspace (the library's scratch array)."""
     _need(coeffs, torch.float32, "coeffs")
+    _fits(coeffs, max(n_obj, 0) * (L + 1) ** 2 * 4, "coeffs")
+    _fits(lut_out, _lut_bytes(N, SHM_LAYOUT_TEXEL, out_dtype, n_obj), "lut_out")
     return _check(lib().shm_bake_sh_lut_noalloc(_ptr(coeffs), L, N, n_obj, out_dtype, _ptr(lut_out), _stream(stream)))
 
 
 def shm_margin_dirs(N, dirs, stream=None):
     _need(dirs, torch.float32, "dirs")
+    _fits(dirs, 6 * (N + 4) ** 2 * 12, "dirs")
     return _check(lib().shm_margin_dirs(N, _ptr(dirs), _stream(stream)))
 
 
 def shm_bake_fd(samples, N, n_obj, out_dtype, lut_out, stream=None):
     _need(samples, torch.float32, "samples")
+    _fits(samples, max(n_obj, 0) * 6 * (N + 4) ** 2 * 4, "samples")
+    _fits(lut_out, _lut_bytes(N, SHM_LAYOUT_TEXEL, out_dtype, n_obj), "lut_out")
     return _check(lib().shm_bake_fd(_ptr(samples), N, n_obj, out_dtype, _ptr(lut_out), _stream(stream)))
 
 
 def shm_lut_to_cells(lut_texel, dtype, N, n_obj, lut_cell, stream=None):
+    _fits(lut_texel, _lut_bytes(N, SHM_LAYOUT_TEXEL, dtype, n_obj), "lut_texel")
+    _fits(lut_cell, _lut_bytes(N, SHM_LAYOUT_CELL, dtype, n_obj), "lut_cell")
     return _check(lib().shm_lut_to_cells(_ptr(lut_texel), dtype, N, n_obj, _ptr(lut_cell), _stream(stream)))
 
 
 def shm_query_value_grad(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, normal=None, stream=None):
     _need(dirs, torch.float32, "dirs")
     _need(out, torch.float32, "out")
+    Q = max(n_obj, 0) * max(q_per_obj, 0)
+    if Q:
+        _fits(lut, _lut_bytes(N, layout, dtype, n_obj), "lut")
+    _fits(dirs, Q * 12, "dirs")
+    _fits(out, Q * 16, "out")
+    _fits(normal, Q * 12, "normal")
     return _check(lib().shm_query_value_grad(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, _ptr(out),
                                              _ptr(normal), _stream(stream)))
 
@@ -228,11 +259,18 @@ def shm_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed,
     """Random gathers of req_bytes inside regions of base (see shm_probe.h),
     with the query's streamed directions (SHM_PROBE_DIRS) and/or 16 B results
     (SHM_PROBE_OUT)."""
+    n = max(n_regions, 0) * max(per_region, 0)
+    if n and req_bytes:
+        _fits(base, n_regions * region_bytes, "base")
+    _fits(dirs, n * 12 if flags & SHM_PROBE_DIRS else 0, "dirs")
+    _fits(out, n * 16 if flags & SHM_PROBE_OUT else (16 if n else 0), "out")
     return _check(lib().shm_probe_gather(_ptr(base), region_bytes, n_regions, per_region, req_bytes, seed & 0xFFFFFFFF,
                                          flags, _ptr(dirs), _ptr(out), _stream(stream)))
 
 
 def shm_probe_stream_read(base, nbytes, sink, stream=None):
+    _fits(base, nbytes, "base")
+    _fits(sink, 16 if nbytes > 0 else 0, "sink")
     return _check(lib().shm_probe_stream_read(_ptr(base), nbytes, _ptr(sink), _stream(stream)))
 
 
@@ -242,22 +280,41 @@ def shm_backward_workspace(N, n_obj, q_per_obj):
 
 def shm_cell_keys(N, n_obj, dirs, q_per_obj, keys, stream=None):
     _need(keys, torch.int32, "keys (uint32 bits stored as int32)")
+    _fits(dirs, max(n_obj, 0) * max(q_per_obj, 0) * 12, "dirs")
+    _fits(keys, max(n_obj, 0) * max(q_per_obj, 0) * 4, "keys")
     return _check(lib().shm_cell_keys(N, n_obj, _ptr(dirs), q_per_obj, _ptr(keys), _stream(stream)))
 
 
 def shm_backward_sort(N, n_obj, dirs, q_per_obj, ws, stream=None):
+    _fits(dirs, max(n_obj, 0) * max(q_per_obj, 0) * 12, "dirs")
     return _check(lib().shm_backward_sort(N, n_obj, _ptr(dirs), q_per_obj, _ptr(ws), ws.numel() * ws.element_size(),
                                           _stream(stream)))
 
 
 def shm_query_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_dirs, ws, sort_ready, stream=None):
+    Q = max(n_obj, 0) * max(q_per_obj, 0)
+    lb = _lut_bytes(N, SHM_LAYOUT_TEXEL, SHM_F32, n_obj)
+    _fits(lut, lb, "lut")
+    _fits(dirs, Q * 12, "dirs")
+    _fits(grad_out, Q * 16, "grad_out")
+    _fits(grad_lut, lb, "grad_lut")
+    _fits(grad_dirs, Q * 12, "grad_dirs")
     return _check(lib().shm_query_backward(_ptr(lut), N, n_obj, _ptr(dirs), q_per_obj, _ptr(grad_out), _ptr(grad_lut),
                                            _ptr(grad_dirs), _ptr(ws), ws.numel() * ws.element_size(),
                                            1 if sort_ready else 0, _stream(stream)))
 
 
+def _fits_rays(P, ray_o, ray_d, t_out, out, normal, sign=None, evals=None):
+    P = max(P, 0)
+    for t, b, name in ((ray_o, 12, "ray_o"), (ray_d, 12, "ray_d"), (t_out, 4, "t_out"), (out, 16, "out"),
+                       (normal, 12, "normal"), (sign, 1, "sign"), (evals, 1, "evals")):
+        _fits(t, P * b, name)
+
+
 def shm_trace_radial(lut, dtype, N, center, rmax, ray_o, ray_d, P, n_march, n_bisect, n_newton, t_out, out,
                      normal=None, stream=None):
+    _fits(lut, _lut_bytes(N, SHM_LAYOUT_TEXEL, dtype) if P > 0 else 0, "lut")
+    _fits_rays(P, ray_o, ray_d, t_out, out, normal)
     c = (ctypes.c_float * 3)(*[float(x) for x in center])
     return _check(lib().shm_trace_radial(_ptr(lut), dtype, N, c, float(rmax), _ptr(ray_o), _ptr(ray_d), P, n_march,
                                          n_bisect, n_newton, _ptr(t_out), _ptr(out), _ptr(normal), _stream(stream)))
@@ -265,6 +322,9 @@ def shm_trace_radial(lut, dtype, N, center, rmax, ray_o, ray_d, P, n_march, n_bi
 
 def shm_trace_radial_ex(lut, dtype, N, center, rmax, params, ray_o, ray_d, P, t_out, out, normal=None, sign=None,
                         evals=None, stream=None):
+    layout = SHM_LAYOUT_CELL if params.flags & SHM_CELL_LUT else SHM_LAYOUT_TEXEL
+    _fits(lut, _lut_bytes(N, layout, dtype) if P > 0 else 0, "lut")
+    _fits_rays(P, ray_o, ray_d, t_out, out, normal, sign, evals)
     c = (ctypes.c_float * 3)(*[float(x) for x in center])
     return _check(lib().shm_trace_radial_ex(_ptr(lut), dtype, N, c, float(rmax), ctypes.byref(params), _ptr(ray_o),
                                             _ptr(ray_d), P, _ptr(t_out), _ptr(out), _ptr(normal), _ptr(sign),
@@ -277,6 +337,13 @@ def shm_lut_rmax(lut, dtype, N, flags, rmax_out, stream=None):
 
 def shm_query_scaled(lut, dtype, layout, N, n_obj, dirs, q_per_obj, scale, flags, out, normal=None, sign=None,
                      stream=None):
+    Q = max(n_obj, 0) * max(q_per_obj, 0)
+    if Q:
+        _fits(lut, _lut_bytes(N, layout, dtype, n_obj), "lut")
+    _fits(dirs, Q * 12, "dirs")
+    _fits(out, Q * 16, "out")
+    _fits(normal, Q * 12, "normal")
+    _fits(sign, Q, "sign")
     return _check(lib().shm_query_scaled(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, float(scale),
                                          flags, _ptr(out), _ptr(normal), _ptr(sign), _stream(stream)))
 
@@ -287,17 +354,32 @@ def shm_mesh_radial_depth(verts, n_verts, tris, n_tris, center, dirs, P, depth, 
                                               _ptr(depth), _stream(stream)))
 
 
+def _fits_fit(Q, dirs, target_r, target_n):
+    Q = max(Q, 0)
+    _fits(dirs, Q * 12, "dirs")
+    _fits(target_r, Q * 4, "target_r")
+    _fits(target_n, Q * 12, "target_n")
+
+
 def shm_fit_loss_grad(out, dirs, target_r, target_n, Q, w_value, grad, stream=None):
+    _fits_fit(Q, dirs, target_r, target_n)
+    _fits(out, max(Q, 0) * 16, "out")
+    _fits(grad, max(Q, 0) * 16, "grad")
     return _check(lib().shm_fit_loss_grad(_ptr(out), _ptr(dirs), _ptr(target_r), _ptr(target_n), Q, float(w_value),
                                           _ptr(grad), _stream(stream)))
 
 
 def shm_fit_forward_loss_grad(lut, N, dirs, target_r, target_n, Q, w_value, grad, stream=None):
+    _fits(lut, _lut_bytes(N, SHM_LAYOUT_TEXEL, SHM_F32) if Q > 0 else 0, "lut")
+    _fits_fit(Q, dirs, target_r, target_n)
+    _fits(grad, max(Q, 0) * 16, "grad")
     return _check(lib().shm_fit_forward_loss_grad(_ptr(lut), N, _ptr(dirs), _ptr(target_r), _ptr(target_n), Q,
                                                   float(w_value), _ptr(grad), _stream(stream)))
 
 
 def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for t, name in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
+        _fits(t, max(n4, 0) * 16, name)
     return _check(lib().shm_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), n4, step, float(lr_value),
                                       float(lr_deriv), float(beta1), float(beta2), float(eps), _stream(stream)))
 
@@ -305,12 +387,19 @@ def shm_adam_step(param, grad, m, v, n4, step, lr_value, lr_deriv, beta1=0.9, be
 def shm_gather_footprints(lut, dtype, layout, N, n_obj, dirs, q_per_obj, foot, stream=None):
     _need(dirs, torch.float32, "dirs")
     _need(foot, torch.float32, "foot")
+    Q = max(n_obj, 0) * max(q_per_obj, 0)
+    if Q:
+        _fits(lut, _lut_bytes(N, layout, dtype, n_obj), "lut")
+    _fits(dirs, Q * 12, "dirs")
+    _fits(foot, Q * 64, "foot")
     return _check(lib().shm_gather_footprints(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, _ptr(foot),
                                               _stream(stream)))
 
 
 def shm_count_invalid(dirs, Q, count, stream=None):
     _need(count, torch.int64, "count")
+    _fits(dirs, max(Q, 0) * 12, "dirs")
+    _fits(count, 8, "count")
     return _check(lib().shm_count_invalid(_ptr(dirs), Q, _ptr(count), _stream(stream)))
 
 
@@ -326,6 +415,8 @@ def shm_fit_step(lut_in, lut_out, m, v, N, dirs, target_r, target_n, Q, w_value,
                  beta1, beta2, eps, ws, sort_ready, stream=None):
     for t, name in ((lut_in, "lut_in"), (lut_out, "lut_out"), (m, "m"), (v, "v")):
         _need(t, torch.float32, name)
+        _fits(t, _lut_bytes(N, SHM_LAYOUT_TEXEL, SHM_F32), name)
+    _fits_fit(Q, dirs, target_r, target_n)
     return _check(lib().shm_fit_step(_ptr(lut_in), _ptr(lut_out), _ptr(m), _ptr(v), N, _ptr(dirs), _ptr(target_r),
                                      _ptr(target_n), Q, float(w_value), step, float(lr_value), float(lr_deriv),
                                      float(beta1), float(beta2), float(eps), _ptr(ws), ws.numel() * ws.element_size(),
@@ -425,18 +516,30 @@ def shm_mip_level_workspace(N):
 
 def shm_mip_level(lut, N, mode, ws, out, stream=None):
     _need(lut, torch.float32, "lut")
+    _fits(lut, _lut_bytes(N, SHM_LAYOUT_TEXEL, SHM_F32), "lut")
+    _fits(out, _lut_bytes(N // 2, SHM_LAYOUT_TEXEL, SHM_F32), "out")
     return _check(lib().shm_mip_level(_ptr(lut), N, mode, _ptr(ws), ws.numel() * ws.element_size(), _ptr(out),
                                       _stream(stream)))
 
 
 def shm_query_baseline(vlut, N, n_obj, dirs, q_per_obj, method, out, stream=None):
     _need(vlut, torch.float32, "vlut")
+    Q = max(n_obj, 0) * max(q_per_obj, 0)
+    if Q:
+        _fits(vlut, n_obj * 6 * (N + 4) ** 2 * 4, "vlut")
+    _fits(dirs, Q * 12, "dirs")
+    _fits(out, Q * 16, "out")
     return _check(lib().shm_query_baseline(_ptr(vlut), N, n_obj, _ptr(dirs), q_per_obj, method, _ptr(out),
                                            _stream(stream)))
 
 
 def shm_sh_eval(coeffs, L, n_obj, dirs, q_per_obj, out, stream=None):
     _need(coeffs, torch.float32, "coeffs")
+    Q = max(n_obj, 0) * max(q_per_obj, 0)
+    if Q:
+        _fits(coeffs, n_obj * (L + 1) ** 2 * 4, "coeffs")
+    _fits(dirs, Q * 12, "dirs")
+    _fits(out, Q * 16, "out")
     return _check(lib().shm_sh_eval(_ptr(coeffs), L, n_obj, _ptr(dirs), q_per_obj, _ptr(out), _stream(stream)))
 
 
@@ -454,12 +557,17 @@ class Plan:
             arr[i].lut_offset, arr[i].N, arr[i].reserved, arr[i].q_begin, arr[i].q_count = int(off), int(N), 0, int(qb), int(qc)
         self._arr = arr
         self.dtype, self.layout = dtype, layout
+        # extents the launches access: rows of dirs/out and bytes of the LUT
+        self._rows = max((int(qb) + int(qc) for (_, _, qb, qc) in objs if int(qc) > 0), default=0)
+        self._lut_bytes = max((int(off) * _dbytes(dtype) + _lut_bytes(int(N), layout, dtype)
+                               for (off, N, _, qc) in objs if int(qc) > 0), default=0)
         h = ctypes.c_void_p()
         _check(lib().shm_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(objs), dtype, layout, _stream(stream),
                                      ctypes.byref(h)))
         self.handle = h
 
     def autotune(self, lut, dirs, out, cache_path=None, stream=None):
+        self._fits(lut, dirs, out)
         s = shm_launch_shape()
         _check(lib().shm_plan_autotune(self.handle, _ptr(lut), _ptr(dirs), _ptr(out),
                                        cache_path.encode() if cache_path else None, _stream(stream), ctypes.byref(s)))
@@ -469,10 +577,18 @@ class Plan:
         s = shm_launch_shape(block, qpt, tile, grid_per_cu)
         _check(lib().shm_plan_set_shape(self.handle, ctypes.byref(s)))
 
+    def _fits(self, lut, dirs, out, normal=None):
+        _fits(lut, self._lut_bytes, "lut")
+        _fits(dirs, self._rows * 12, "dirs")
+        _fits(out, self._rows * 16, "out")
+        _fits(normal, self._rows * 12, "normal")
+
     def launch(self, lut, dirs, out, normal=None, stream=None):
+        self._fits(lut, dirs, out, normal)
         _check(lib().shm_plan_launch(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), _ptr(normal), _stream(stream)))
 
     def capture_graph(self, lut, dirs, out, normal=None, stream=None):
+        self._fits(lut, dirs, out, normal)
         _check(lib().shm_plan_capture_graph(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), _ptr(normal), _stream(stream)))
 
     def graph_launch(self, stream=None):
@@ -481,6 +597,7 @@ class Plan:
     def probe(self, lut, dirs, out, seed=20063, stream=None):
         """shm_plan_probe: the launch's memory traffic without its arithmetic
         (see shm_probe.h); out[q] = (dirs[q], bits of the footprint's word sum)."""
+        self._fits(lut, dirs, out)
         _check(lib().shm_plan_probe(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), seed & 0xFFFFFFFF, _stream(stream)))
 
     @property
