@@ -413,6 +413,15 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
         forms[name] = {"queries_per_s": Q / ms * 1e3, "ms": ms, "hbm_frac": B16 / ms / 1e6 / PEAK_HBM_GBS,
                        "speedup_vs_f32_cell": ms_cell / ms}
         sample[name] = out[: CPU_GLYPHS * q_per].cpu().numpy()
+    # the FP16 cell query's own memory pattern: one random 32 B cell per query
+    # inside its glyph's FP16 cell LUT, the directions and the results
+    region16 = shm.shm_lut_elems(N, shm.SHM_LAYOUT_CELL) * 2
+    pat = lambda: shm.shm_probe_gather(l16c, region16, n_glyph, q_per, 32, 20063,
+                                       shm.SHM_PROBE_DIRS | shm.SHM_PROBE_OUT, dirs_t, out)
+    pat()
+    ms_pat = t_gpu(pat, 20)
+    forms["query_f16_cell"]["pattern_ms"] = ms_pat
+    forms["query_f16_cell"]["frac_of_pattern"] = ms_pat / forms["query_f16_cell"]["ms"]
     del l16t, l16c
 
     # bake: SH basis + MFMA contraction (workload 2)
