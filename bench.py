@@ -747,7 +747,16 @@ def run_batched():
     outp = torch.empty_like(out16)
     plan.probe(lut16, dirs, outp)
     ms_probe = t_gpu(lambda: plan.probe(lut16, dirs, outp), 10)
-    del outp
+    # the plan-free object query on the same batch (descriptors in device
+    # memory, fixed launch shape): same bits as the plan
+    od = shm.objects_tensor(objs, DEV)
+    wso = torch.empty(shm.shm_query_objects_workspace(n_obj), dtype=torch.uint8, device=DEV)
+    qobj = lambda: shm.shm_query_objects(lut16, shm.SHM_F16, shm.SHM_LAYOUT_CELL, od, n_obj, dirs, outp, None, wso)
+    qobj()
+    ms_objects = t_gpu(qobj, 10)
+    torch.cuda.synchronize()
+    objects_same_bits = bool(torch.equal(outp.view(torch.int32), out16.view(torch.int32)))
+    del outp, od, wso
 
     def per_object():
         for (o_off, Nn, q0, q) in objs:
@@ -775,7 +784,9 @@ def run_batched():
            "per_object_f32_graph_ms": ms_per_graph, "queries_per_s": Qtot / ms_graph * 1e3,
            "speedup_vs_per_object_f32": ms_per / ms_graph, "speedup_vs_per_object_f32_graph": ms_per_graph / ms_graph,
            "alg_bytes": b16, "hbm_frac": b16 / ms_graph / 1e6 / PEAK_HBM_GBS,
-           "pattern_probe_ms": ms_probe, "frac_of_pattern": ms_probe / ms_graph, "shape": shape, "autotune_s": tune_s,
+           "pattern_probe_ms": ms_probe, "frac_of_pattern": ms_probe / ms_graph,
+           "objects_no_plan_ms": ms_objects, "objects_no_plan_same_bits": objects_same_bits,
+           "shape": shape, "autotune_s": tune_s,
            "work_items": plan.work_items}
     # sample for the error check: the first 16 objects
     smp = {"coeffs": coeffs[:16], "N": [int(x) for x in spec["N"][:16]], "q": [int(x) for x in Qs[:16]],

@@ -228,6 +228,30 @@ typedef struct shm_object {
 
 typedef struct shm_plan shm_plan;
 
+/* Query of objects described in DEVICE memory, without a plan (the object
+ * form of the value + gradient query, Sec. 3.2-3.4): objs [n_obj]
+ * shm_object on the device (8-byte aligned); object o answers the queries
+ * dirs[q_begin .. q_begin + q_count) from its LUT at lut + lut_offset
+ * elements (face size N) in the given dtype and layout, writing out (and
+ * normal, if not NULL) at the same rows, bit for bit as shm_query_value_grad
+ * answers them.  The ranges may come in any order and must not overlap.
+ * The descriptors are read on the device only: an object with N outside
+ * 1..SHM_MAX_N, a negative or misaligned lut_offset (a multiple of 8
+ * elements for FP16 cells, else 4), a negative q_begin or q_count <= 0 is
+ * skipped (its rows are not written); the caller guarantees that every
+ * answered object's LUT and rows lie inside the buffers.  Two launches on
+ * `stream` (a one-workgroup scan of the objects' tile counts into ws, then a
+ * persistent grid over all tiles, a contiguous slice per XCD); no host
+ * synchronisation, no allocation, capturable in a graph.
+ *   ws  shm_query_objects_workspace(n_obj) bytes, 8-byte aligned (n_obj + 1
+ *       int64 tile offsets), overwritten.
+ * Errors: SHM_ERR_INVALID_ARG (bad dtype/layout, negative n_obj, null or
+ * misaligned pointer), SHM_ERR_WORKSPACE (ws too small). */
+SHM_API size_t shm_query_objects_workspace(int64_t n_obj);
+SHM_API int shm_query_objects(const void* lut, int32_t dtype, int32_t layout, const shm_object* objs, int64_t n_obj,
+                              const float* dirs, float* out, float* normal, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
 /* Launch shape of the persistent kernel. */
 typedef struct shm_launch_shape {
     int32_t block;       /* threads per workgroup: 64, 128, 256 or 512        */

@@ -116,6 +116,8 @@ SIGNATURES = {
     # memory-system probes (include/shm_probe.h)
     "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _I32, _VP, _VP, _VP]),
     "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    "shm_query_objects_workspace": (_SZ, [_I64]),
+    "shm_query_objects": (ctypes.c_int, [_VP, _I32, _I32, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "shm_plan_probe": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_uint32, _VP]),
 }
 
@@ -253,6 +255,48 @@ def shm_query_value_grad(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, nor
     _fits(normal, Q * 12, "normal")
     return _check(lib().shm_query_value_grad(_ptr(lut), dtype, layout, N, n_obj, _ptr(dirs), q_per_obj, _ptr(out),
                                              _ptr(normal), _stream(stream)))
+
+
+def shm_query_objects_workspace(n_obj):
+    return lib().shm_query_objects_workspace(n_obj)
+
+
+def shm_query_objects(lut, dtype, layout, objs, n_obj, dirs, out, normal, ws, stream=None):
+    """objs: device tensor holding n_obj shm_object records (objects_tensor)."""
+    _need(dirs, torch.float32, "dirs")
+    _need(out, torch.float32, "out")
+    _fits(objs, max(n_obj, 0) * ctypes.sizeof(shm_object), "objs")
+    _fits(ws, shm_query_objects_workspace(n_obj) if n_obj > 0 else 0, "ws")
+    return _check(lib().shm_query_objects(_ptr(lut), dtype, layout, _ptr(objs), n_obj, _ptr(dirs), _ptr(out),
+                                          _ptr(normal), _ptr(ws), ws.numel() * ws.element_size() if ws is not None
+                                          else 0, _stream(stream)))
+
+
+def objects_tensor(objs, device="cuda"):
+    """shm_object records [(lut_offset, N, q_begin, q_count), ...] as a
+    device tensor (int64 [n, 4]; N in the low half of the second word)."""
+    rows = [[int(off), int(N) & 0xFFFFFFFF, int(qb), int(qc)] for (off, N, qb, qc) in objs]
+    return torch.tensor(rows, dtype=torch.int64).reshape(-1, 4).to(device)
+
+
+def query_objects(lut, dirs, objs, dtype=None, layout=SHM_LAYOUT_TEXEL, normals=False, out=None, stream=None):
+    """Value + gradient of uneven objects without a plan: objs as for Plan
+    ((lut_offset, N, q_begin, q_count) per object, ranges disjoint); rows of
+    out outside every range are left as they were."""
+    dtype = _dtype_code(lut) if dtype is None else dtype
+    rows = max((int(qb) + int(qc) for (_, _, qb, qc) in objs if int(qc) > 0), default=0)
+    need = max((int(off) * _dbytes(dtype) + _lut_bytes(int(N), layout, dtype) for (off, N, _, qc) in objs
+                if int(qc) > 0), default=0)
+    _fits(lut, need, "lut")
+    _fits(dirs, rows * 12, "dirs")
+    if out is None:
+        out = torch.empty((dirs.shape[0], 4), dtype=torch.float32, device=dirs.device)
+    _fits(out, rows * 16, "out")
+    nrm = torch.empty((dirs.shape[0], 3), dtype=torch.float32, device=dirs.device) if normals else None
+    od = objects_tensor(objs, dirs.device)
+    ws = torch.empty(max(shm_query_objects_workspace(len(objs)), 8), dtype=torch.uint8, device=dirs.device)
+    shm_query_objects(lut, dtype, layout, od, len(objs), dirs, out, nrm, ws, stream)
+    return (out, nrm) if normals else out
 
 
 def shm_probe_gather(base, region_bytes, n_regions, per_region, req_bytes, seed, flags, dirs, out, stream=None):

@@ -337,6 +337,28 @@ int shm_query_value_grad(const void* lut, int32_t dtype, int32_t layout, int32_t
     return launch_query_uniform(lut, dtype, layout, N, n_obj, dirs, q_per_obj, out, normal, stream);
 }
 
+size_t shm_query_objects_workspace(int64_t n_obj) { return n_obj < 0 ? 0 : query_objects_workspace(n_obj); }
+
+int shm_query_objects(const void* lut, int32_t dtype, int32_t layout, const shm_object* objs, int64_t n_obj,
+                      const float* dirs, float* out, float* normal, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    if (!valid_dtype(dtype)) return fail(SHM_ERR_INVALID_ARG, "query_objects: bad dtype %d", dtype);
+    if (!valid_layout(layout)) return fail(SHM_ERR_INVALID_ARG, "query_objects: bad layout %d", layout);
+    if (n_obj < 0) return fail(SHM_ERR_INVALID_ARG, "query_objects: negative object count");
+    if (n_obj > INT64_MAX / 64) return fail(SHM_ERR_UNSUPPORTED, "query_objects: too many objects");
+    if (n_obj == 0) return SHM_OK;
+    if (!lut || !objs || !dirs || !out || !ws) return fail(SHM_ERR_INVALID_ARG, "query_objects: null pointer");
+    if (ws_bytes < query_objects_workspace(n_obj))
+        return fail(SHM_ERR_WORKSPACE, "query_objects: workspace of %zu bytes needed (got %zu)",
+                    query_objects_workspace(n_obj), ws_bytes);
+    const size_t al = (dtype == SHM_F16 && layout == SHM_LAYOUT_TEXEL) ? 8 : 16;
+    if (!aligned(lut, al) || !aligned(out, 16) || !aligned(dirs, 4) || (normal && !aligned(normal, 4)) ||
+        !aligned(objs, 8) || !aligned(ws, 8))
+        return fail(SHM_ERR_INVALID_ARG, "query_objects: misaligned buffer (lut %zu B, out 16 B, objs and ws 8 B)", al);
+    return launch_query_objects(lut, dtype, layout, objs, n_obj, dirs, out, normal, ws, stream);
+}
+
 int shm_cells_to_f16(const float* cells, int64_t n_cells, void* cells_f16, hipStream_t stream)
 {
     clear_error();

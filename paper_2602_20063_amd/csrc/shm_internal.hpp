@@ -59,6 +59,9 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
                             const WorkItem* items_dev, int64_t n_items, const XcdSplit& split,
                             const shm_launch_shape& shape, int n_cu,
                             const float* dirs, float* out, float* normal, hipStream_t stream);
+size_t query_objects_workspace(int64_t n_obj);
+int launch_query_objects(const void* lut, int dtype, int layout, const shm_object* objs, int64_t n_obj,
+                         const float* dirs, float* out, float* normal, void* ws, hipStream_t stream);
 int launch_lut_to_cells(const void* lut, int dtype, int N, int64_t n_obj, void* cells, hipStream_t stream);
 int launch_query_baseline(const float* vlut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, int method,
                           float* out, hipStream_t stream);

@@ -250,6 +250,155 @@ __global__ void k_query_persistent(const void* __restrict__ lut, const shm_objec
     }
 }
 
+// ---------------------------------------------------------------------------
+// Plan-free query of objects described on the device.  k_obj_tiles counts
+// each object's tiles of OBJ_TILE queries (0 for an object the kernel would
+// skip) and scans the counts in one workgroup into tile_start[0..n_obj];
+// k_query_objects then walks tiles 0 .. tile_start[n_obj) - 1 with a
+// persistent grid, the tiles cut into 8 contiguous slices, one per XCD
+// (group of blocks blockIdx % 8), so an object's tiles share one L2.  A
+// workgroup finds the object of its tile by binary search over tile_start
+// (uniform across the workgroup).  Deterministic: every query is answered
+// by query_one exactly as the uniform and plan kernels answer it.
+// ---------------------------------------------------------------------------
+// launch shape of the plan-free kernel (compile-time knobs, same bits at any
+// setting): queries per lane, workgroups per compute unit
+#ifndef SHM_OBJ_QPT
+#define SHM_OBJ_QPT 4
+#endif
+#ifndef SHM_OBJ_WG_PER_CU
+#define SHM_OBJ_WG_PER_CU 4
+#endif
+constexpr int OBJ_LANES = 256;
+constexpr int OBJ_TILE = OBJ_LANES * SHM_OBJ_QPT;  // queries per tile
+constexpr int OBJ_SCAN = 1024;                     // lanes of the scan workgroup
+
+// an object the kernel answers: N in range, the LUT offset aligned for the
+// loads of the dtype/layout, a nonnegative range
+template <bool FP16, bool CELL>
+__device__ __forceinline__ bool obj_ok(const shm_object& o)
+{
+    const int64_t al = (FP16 && CELL) ? 8 : 4;
+    return o.N >= 1 && o.N <= SHM_MAX_N && o.lut_offset >= 0 && o.lut_offset % al == 0 && o.q_begin >= 0 &&
+           o.q_count > 0;
+}
+
+template <bool FP16, bool CELL>
+__global__ __launch_bounds__(OBJ_SCAN) void k_obj_tiles(const shm_object* __restrict__ objs, int64_t n_obj,
+                                                        int64_t* __restrict__ tile_start)
+{
+    __shared__ int64_t part[OBJ_SCAN];
+    const int tid = threadIdx.x;
+    const int64_t per = (n_obj + OBJ_SCAN - 1) / OBJ_SCAN;
+    const int64_t b = tid * per, e = min(b + per, n_obj);
+    int64_t sum = 0;
+    for (int64_t o = b; o < e; ++o) {
+        const shm_object ob = objs[o];
+        sum += obj_ok<FP16, CELL>(ob) ? (ob.q_count + OBJ_TILE - 1) / OBJ_TILE : 0;
+    }
+    part[tid] = sum;
+    __syncthreads();
+    // inclusive scan of the lane sums (Hillis-Steele; exact integers)
+    for (int d = 1; d < OBJ_SCAN; d <<= 1) {
+        const int64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = tid > 0 ? part[tid - 1] : 0;
+    for (int64_t o = b; o < e; ++o) {
+        tile_start[o] = run;
+        const shm_object ob = objs[o];
+        run += obj_ok<FP16, CELL>(ob) ? (ob.q_count + OBJ_TILE - 1) / OBJ_TILE : 0;
+    }
+    if (tid == OBJ_SCAN - 1) tile_start[n_obj] = part[OBJ_SCAN - 1];
+}
+
+template <bool FP16, bool CELL, bool NRM>
+__global__ __launch_bounds__(OBJ_LANES) void k_query_objects(const void* __restrict__ lut,
+                                                            const shm_object* __restrict__ objs, int64_t n_obj,
+                                                            const int64_t* __restrict__ tile_start,
+                                                            const float* __restrict__ dirs, float* __restrict__ out,
+                                                            float* __restrict__ nrm)
+{
+    const int64_t total = tile_start[n_obj];
+    const int G = (int)gridDim.x;
+    const int nx = G < 8 ? G : 8;
+    const int x = (int)blockIdx.x % nx, local = (int)blockIdx.x / nx;
+    const int per = (G - x + nx - 1) / nx;
+    // slice x of the tiles: [total x / nx, total (x + 1) / nx)
+    const int64_t t_end = total * (x + 1) / nx;
+    for (int64_t t = total * x / nx + local; t < t_end; t += per) {
+        // the object of tile t: the last o with tile_start[o] <= t (objects
+        // without tiles share their successor's start)
+        int64_t lo = 0, hi = n_obj - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (tile_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const shm_object o = objs[lo];
+        const char* base = reinterpret_cast<const char*>(lut) + (size_t)o.lut_offset * (FP16 ? 2 : 4);
+        const int64_t k0 = (t - tile_start[lo]) * OBJ_TILE + threadIdx.x;
+        float x0[SHM_OBJ_QPT], y0[SHM_OBJ_QPT], z0[SHM_OBJ_QPT];
+#pragma unroll
+        for (int j = 0; j < SHM_OBJ_QPT; ++j) {
+            const int64_t k = k0 + j * OBJ_LANES;
+            if (k < o.q_count) {
+                const int64_t q = o.q_begin + k;
+                x0[j] = ld_dir(dirs + 3 * q);
+                y0[j] = ld_dir(dirs + 3 * q + 1);
+                z0[j] = ld_dir(dirs + 3 * q + 2);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < SHM_OBJ_QPT; ++j) {
+            const int64_t k = k0 + j * OBJ_LANES;
+            if (k >= o.q_count) continue;
+            const int64_t q = o.q_begin + k;
+            const float4 r = query_one<FP16, CELL>(base, o.N, x0[j], y0[j], z0[j]);
+            st_out(out, q, r);
+            if constexpr (NRM) {
+                const float3 n = normal_of(r.x, x0[j], y0[j], z0[j], make_float3(r.y, r.z, r.w));
+                nrm[3 * q] = n.x;
+                nrm[3 * q + 1] = n.y;
+                nrm[3 * q + 2] = n.z;
+            }
+        }
+    }
+}
+
+template <bool FP16, bool CELL, bool NRM>
+static void launch_objects_t(int n_cu, hipStream_t st, const void* lut, const shm_object* objs, int64_t n_obj,
+                             int64_t* tile_start, const float* dirs, float* out, float* nrm)
+{
+    hipLaunchKernelGGL((k_obj_tiles<FP16, CELL>), dim3(1), dim3(OBJ_SCAN), 0, st, objs, n_obj, tile_start);
+    hipLaunchKernelGGL((k_query_objects<FP16, CELL, NRM>), dim3((unsigned)(n_cu * SHM_OBJ_WG_PER_CU)), dim3(OBJ_LANES), 0,
+                       st, lut, objs, n_obj, tile_start, dirs, out, nrm);
+}
+
+size_t query_objects_workspace(int64_t n_obj) { return (size_t)(n_obj + 1) * sizeof(int64_t); }
+
+int launch_query_objects(const void* lut, int dtype, int layout, const shm_object* objs, int64_t n_obj,
+                         const float* dirs, float* out, float* normal, void* ws, hipStream_t stream)
+{
+    if (n_obj == 0) return SHM_OK;
+    int64_t* ts = reinterpret_cast<int64_t*>(ws);
+    const int n_cu = device_cu_count();
+    const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL, nrm = normal != nullptr;
+#define SHM_O(a, b, c) launch_objects_t<a, b, c>(n_cu, stream, lut, objs, n_obj, ts, dirs, out, normal)
+    if (f16) {
+        if (cell) { if (nrm) SHM_O(true, true, true); else SHM_O(true, true, false); }
+        else { if (nrm) SHM_O(true, false, true); else SHM_O(true, false, false); }
+    } else {
+        if (cell) { if (nrm) SHM_O(false, true, true); else SHM_O(false, true, false); }
+        else { if (nrm) SHM_O(false, false, true); else SHM_O(false, false, false); }
+    }
+#undef SHM_O
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
 template <bool FP16, bool CELL, bool NRM>
 static void launch_persistent_t(int qpt, dim3 grid, dim3 block, hipStream_t st, const void* lut,
                                 const shm_object* objs, const WorkItem* items, const XcdSplit& split, const float* dirs,

@@ -316,6 +316,24 @@ def test_probe_argument_validation():
     assert "null plan" in shm.shm_last_error()
 
 
+def test_query_objects_argument_validation():
+    """The plan-free object query validates on the host before any launch."""
+    p = ctypes.c_void_p(256)
+    ws_need = shm.shm_query_objects_workspace(10)
+    assert ws_need == 88  # n_obj + 1 int64 tile offsets
+    f = "shm_query_objects"
+    assert call(f, p, 5, 0, p, 10, p, p, None, p, ws_need, None) == shm.SHM_ERR_INVALID_ARG  # dtype
+    assert call(f, p, 0, 7, p, 10, p, p, None, p, ws_need, None) == shm.SHM_ERR_INVALID_ARG  # layout
+    assert call(f, p, 0, 0, p, -1, p, p, None, p, ws_need, None) == shm.SHM_ERR_INVALID_ARG
+    assert call(f, p, 0, 0, None, 10, p, p, None, p, ws_need, None) == shm.SHM_ERR_INVALID_ARG
+    assert call(f, p, 0, 0, p, 10, p, p, None, None, ws_need, None) == shm.SHM_ERR_INVALID_ARG
+    assert call(f, p, 0, 0, p, 10, p, p, None, p, ws_need - 1, None) == shm.SHM_ERR_WORKSPACE
+    assert "workspace" in shm.shm_last_error()
+    assert call(f, p, 0, 0, ctypes.c_void_p(260), 10, p, p, None, p, ws_need, None) == shm.SHM_ERR_INVALID_ARG
+    assert call(f, ctypes.c_void_p(264), 0, 1, p, 10, p, p, None, p, ws_need, None) == shm.SHM_ERR_INVALID_ARG
+    assert call(f, None, 0, 0, None, 0, None, None, None, None, 0, None) == shm.SHM_OK  # no objects
+
+
 def test_bake_noalloc_argument_validation():
     """The no-allocation bake validates like the workspace bake and refuses a
     basis table larger than its scratch before touching a device."""

@@ -137,3 +137,91 @@ def test_set_shape_waits_for_earlier_launches():
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     plan.close()
+
+
+def to_cells_batch(lut_t, objs):
+    parts, cobjs, off = [], [], 0
+    for (o_off, N, qb, q) in objs:
+        n = 6 * (N + 2) * (N + 2) * 4
+        cl = shm.to_cells(lut_t[o_off:o_off + n].reshape(1, 6, N + 2, N + 2, 4)).reshape(-1)
+        parts.append(cl)
+        cobjs.append((off, N, qb, q))
+        off += cl.numel()
+    return torch.cat(parts), cobjs
+
+
+@pytest.mark.parametrize("dt,layout", [(torch.float32, 0), (torch.float16, 0), (torch.float16, 1), (torch.float32, 1)])
+def test_objects_without_plan_equal_per_object(dt, layout):
+    """shm_query_objects (descriptors in device memory, no plan): every
+    answered row has the bits of a per-object launch, in any descriptor
+    order; objects the kernel must skip (N out of range, a misaligned or
+    negative LUT offset, a negative q_begin, no queries) leave their rows
+    untouched; tiles of 1, 256 and 257 queries and N = 1 included."""
+    flat, objs, dirs = build_batch(40, 7)
+    r = np.random.default_rng(8)
+    code = shm.SHM_F16 if dt == torch.float16 else shm.SHM_F32
+    lut_t = torch.as_tensor(flat).to(DEV, dt)
+    # tile-boundary counts and N = 1 on top of the lognormal batch
+    extra_lut = [workloads.random_lut(1, r), workloads.random_lut(9, r), workloads.random_lut(4, r)]
+    off, qb = lut_t.numel(), dirs.shape[0]
+    for lut_x, q in zip(extra_lut, (1, 256, 257)):
+        objs.append((off, lut_x.shape[-2] - 2, qb, q))
+        off += lut_x.size
+        qb += q
+    lut_t = torch.cat([lut_t] + [torch.as_tensor(x.reshape(-1)).to(DEV, dt) for x in extra_lut])
+    dirs = np.concatenate([dirs, workloads.uniform_dirs(qb - dirs.shape[0], r)])
+    if layout == shm.SHM_LAYOUT_CELL:
+        lut_t, objs = to_cells_batch(lut_t, objs)
+    Q = qb
+    # objects to skip, each with rows of its own past the answered ones
+    al = 8 if (code == shm.SHM_F16 and layout == shm.SHM_LAYOUT_CELL) else 4
+    skip = [(0, 0, Q, 5), (0, shm.SHM_MAX_N + 1, Q + 5, 5), (objs[0][0] + al // 2, objs[0][1], Q + 10, 5),
+            (-al, objs[0][1], Q + 15, 5), (0, 4, Q + 20, 0)]
+    dirs = np.concatenate([dirs, workloads.uniform_dirs(25, r)])
+    d_t = torch.as_tensor(dirs).to(DEV)
+    order = list(r.permutation(len(objs)))
+    descs = [objs[i] for i in order] + skip
+    descs.insert(3, (0, objs[0][1], -5, 5))  # negative q_begin: skipped, writes nothing
+    sentinel = -7.0
+    out = torch.full((Q + 25, 4), sentinel, device=DEV)
+    nrm = torch.full((Q + 25, 3), sentinel, device=DEV)
+    ws = torch.empty(shm.shm_query_objects_workspace(len(descs)), dtype=torch.uint8, device=DEV)
+    shm.shm_query_objects(lut_t, code, layout, shm.objects_tensor(descs, DEV), len(descs), d_t, out, nrm, ws)
+    ref = torch.full_like(out, sentinel)
+    rn = torch.full_like(nrm, sentinel)
+    for (o_off, N, q0, q) in objs:
+        n = shm.shm_lut_elems(N, layout)
+        shm.shm_query_value_grad(lut_t[o_off:o_off + n], code, layout, N, 1, d_t[q0:q0 + q], q, ref[q0:q0 + q],
+                                 rn[q0:q0 + q])
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int32), ref.view(torch.int32))
+    assert torch.equal(nrm.view(torch.int32), rn.view(torch.int32))
+    # the same call again, reusing the workspace: same bits
+    out2 = torch.full_like(out, sentinel)
+    shm.shm_query_objects(lut_t, code, layout, shm.objects_tensor(descs, DEV), len(descs), d_t, out2, None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(out2.view(torch.int32), ref.view(torch.int32))
+
+
+def test_objects_without_plan_many_small_objects():
+    """More objects than the scan has lanes (several per lane), tiny query
+    counts and face sizes: the tile offsets and the object search."""
+    r = np.random.default_rng(9)
+    n_obj = 2500
+    Ns = r.integers(1, 7, n_obj)
+    qs = r.integers(0, 40, n_obj)
+    luts = [workloads.random_lut(int(N), r).reshape(-1) for N in Ns]
+    offs = np.concatenate([[0], np.cumsum([x.size for x in luts])[:-1]])
+    qb = np.concatenate([[0], np.cumsum(qs)[:-1]])
+    objs = [(int(offs[o]), int(Ns[o]), int(qb[o]), int(qs[o])) for o in range(n_obj)]
+    lut_t = torch.as_tensor(np.concatenate(luts)).to(DEV)
+    Q = int(qs.sum())
+    d_t = torch.as_tensor(workloads.uniform_dirs(Q, r)).to(DEV)
+    out = shm.query_objects(lut_t, d_t, objs)
+    ref = torch.empty_like(out)
+    for (o_off, N, q0, q) in objs:
+        if q:
+            n = shm.shm_lut_elems(N)
+            shm.shm_query_value_grad(lut_t[o_off:o_off + n], shm.SHM_F32, 0, N, 1, d_t[q0:q0 + q], q, ref[q0:q0 + q])
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int32), ref.view(torch.int32))

@@ -199,6 +199,11 @@ def test_uneven_batch_full_size_sampled(tmp_path):
         assert torch.equal(out[q0:q0 + q].view(torch.int32), ref.view(torch.int32)), o
     q_all = out[:, 0]
     assert torch.isfinite(q_all).all()
+    # the plan-free object query (device descriptors) gives the plan's bits
+    out2 = torch.full((Qtot, 4), float("nan"), device=DEV)
+    shm.query_objects(lut16, B["dirs"], objs, layout=shm.SHM_LAYOUT_CELL, out=out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out2.view(torch.int32), out.view(torch.int32))
 
 
 def test_trace_full_size_bound_map_same_bits():
