@@ -779,7 +779,29 @@ def run_batched():
     for (o_off, Nn, q0, q) in objs:
         lut_b = 6 * (Nn + 2) ** 2 * 4 * 2
         b16 += 28 * q + min(32 * q, lut_b)
+    # the batch's backward (FP32 TEXEL LUTs, the form a fit updates): sort
+    # once per direction set, then both gradients, against the forward of
+    # the same plan
+    objs_t = [(int(B["texel_off"][o]), Nn, q0, q) for o, (_, Nn, q0, q) in enumerate(objs)]
+    plan_t = shm.Plan(objs_t, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL)
+    lut_t = B["lut_tex"]
+    plan_t.autotune(lut_t, dirs, out32)
+    plan_t.launch(lut_t, dirs, out32)
+    ms_fwd_t = t_gpu(lambda: plan_t.launch(lut_t, dirs, out32), 10)
+    plan_t.backward_sort(dirs)
+    torch.cuda.synchronize()
+    ms_sort_t = t_gpu(lambda: plan_t.backward_sort(dirs), 2)
+    g_b = torch.randn((Qtot, 4), device=DEV, generator=torch.Generator(device=DEV).manual_seed(5))
+    gl_b = torch.empty_like(lut_t)
+    gd_b = torch.empty((Qtot, 3), device=DEV)
+    plan_t.backward(lut_t, dirs, g_b, gl_b, gd_b)
+    ms_bwd_t = t_gpu(lambda: plan_t.backward(lut_t, dirs, g_b, gl_b, gd_b), 5)
+    plan_t.close()
+    del g_b, gl_b, gd_b
+    backward_plan = {"sort_ms": ms_sort_t, "forward_f32_texel_ms": ms_fwd_t, "backward_ms": ms_bwd_t,
+                     "bwd_over_fwd": ms_bwd_t / ms_fwd_t}
     res = {"objects": n_obj, "queries": Qtot, "lut_f16_cell_bytes": lut16.numel() * 2,
+           "backward_f32_texel": backward_plan,
            "graph_ms": ms_graph, "plan_launch_ms": ms_plan, "per_object_f32_ms": ms_per,
            "per_object_f32_graph_ms": ms_per_graph, "queries_per_s": Qtot / ms_graph * 1e3,
            "speedup_vs_per_object_f32": ms_per / ms_graph, "speedup_vs_per_object_f32_graph": ms_per_graph / ms_graph,

@@ -15,12 +15,14 @@
  *  - All array arguments are DEVICE pointers unless the comment says "host".
  *    The caller allocates and owns every buffer, including workspaces; the
  *    library never frees caller memory.  It allocates device memory only in
- *    shm_plan_create (released by shm_plan_destroy).
+ *    shm_plan_create and in a plan's first shm_plan_backward_sort (both
+ *    released by shm_plan_destroy).
  *  - Every call is asynchronous on the given HIP stream (0 = the null
  *    stream); arguments are validated on the host before anything is
  *    enqueued.  The exceptions are the plan calls that say they wait
  *    (shm_plan_create, shm_plan_set_shape, shm_plan_autotune,
- *    shm_plan_capture_graph, shm_plan_destroy): each blocks the host until
+ *    shm_plan_capture_graph, shm_plan_backward_sort, shm_plan_destroy):
+ *    each blocks the host until
  *    its own copies, or the plan's earlier launches, have completed; none
  *    waits for the whole device.  Calls return SHM_OK or an error code and
  *    never throw; shm_last_error() gives a thread-local message for the last
@@ -266,7 +268,8 @@ typedef struct shm_launch_shape {
  * allocates the plan's device memory (the descriptors and a work list sized
  * for the smallest tile a shape may have, 64 queries: sum over objects of
  * ceil(q_count / 64) items of 16 B) and builds the work list with the
- * default shape {256, 2, 2048, 8}.  This is the plan's only allocation.
+ * default shape {256, 2, 2048, 8}.  Apart from the backward's sort buffers
+ * (shm_plan_backward_sort) this is the plan's only allocation.
  * The plan must not outlive the device it was created on. */
 SHM_API int shm_plan_create(const shm_object* objs_host, int64_t n_obj, int32_t dtype, int32_t layout, hipStream_t stream,
                     shm_plan** plan_out);
@@ -294,6 +297,35 @@ SHM_API int shm_plan_capture_graph(shm_plan* plan, const void* lut, const float*
 SHM_API int shm_plan_graph_launch(shm_plan* plan, hipStream_t stream);
 SHM_API int64_t shm_plan_work_items(const shm_plan* plan);
 SHM_API int shm_plan_destroy(shm_plan* plan);
+
+/* Backward of a plan's objects (the differentiation form of the batched
+ * query; TEXEL plans, FP32 or FP16 LUT): the gradients of Eqs. 4-9 with
+ * respect to each object's LUT and to the directions, as shm_query_backward
+ * computes them for one object, for objects of their own face sizes, LUT
+ * offsets and query ranges.  Each object's LUT gradient has the bits of a
+ * one-object shm_query_backward over that object's queries.
+ * shm_plan_backward_sort sorts the plan's queries by (object, face, cell)
+ * and keeps the sort in the plan; it stays valid while dirs are unchanged.
+ * The first call checks that no two objects' LUTs and no two non-empty
+ * query ranges overlap (SHM_ERR_INVALID_ARG otherwise), builds the objects'
+ * prefix arrays and allocates the sort buffers (44 B per query row up to the
+ * last object's range, 4 B per cell of all objects); every call first waits
+ * (host) for the plan's earlier launches, which may read the sort.
+ * shm_plan_backward then, on `stream`:
+ *   lut        the objects' LUT (read for the direction gradient only)
+ *   grad_out   [rows][4] upstream gradient dL/d(R, g), FP32
+ *   grad_lut   dL/dLUT in FP32, the LUT's shape and element offsets (an
+ *              FP16 LUT's gradient is FP32 at the same element indices);
+ *              every object's texels are overwritten, elements outside all
+ *              objects are not touched (or NULL)
+ *   grad_dirs  [rows][3] dL/d dirs of every object's rows, NaN for an
+ *              invalid direction (or NULL)
+ * Deterministic (no floating-point atomics).  Errors: SHM_ERR_UNSUPPORTED
+ * for a CELL plan or more than 2^32 - 1 cells or query rows;
+ * SHM_ERR_INVALID_ARG for a missing sort, null or misaligned pointers. */
+SHM_API int shm_plan_backward_sort(shm_plan* plan, const float* dirs, hipStream_t stream);
+SHM_API int shm_plan_backward(shm_plan* plan, const void* lut, const float* dirs, const float* grad_out,
+                              float* grad_lut, float* grad_dirs, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Backward (differentiation form) for FP32 TEXEL LUTs with uniform objects

@@ -117,6 +117,8 @@ SIGNATURES = {
     "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _I32, _VP, _VP, _VP]),
     "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
     "shm_query_objects_workspace": (_SZ, [_I64]),
+    "shm_plan_backward_sort": (ctypes.c_int, [_VP, _VP, _VP]),
+    "shm_plan_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "shm_query_objects": (ctypes.c_int, [_VP, _I32, _I32, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "shm_plan_probe": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_uint32, _VP]),
 }
@@ -605,6 +607,9 @@ class Plan:
         self._rows = max((int(qb) + int(qc) for (_, _, qb, qc) in objs if int(qc) > 0), default=0)
         self._lut_bytes = max((int(off) * _dbytes(dtype) + _lut_bytes(int(N), layout, dtype)
                                for (off, N, _, qc) in objs if int(qc) > 0), default=0)
+        # elements of every object's LUT (the backward writes them all)
+        self._lut_elems_all = max((int(off) + _lut_bytes(int(N), layout, dtype) // _dbytes(dtype)
+                                   for (off, N, _, _) in objs), default=0)
         h = ctypes.c_void_p()
         _check(lib().shm_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(objs), dtype, layout, _stream(stream),
                                      ctypes.byref(h)))
@@ -643,6 +648,26 @@ class Plan:
         (see shm_probe.h); out[q] = (dirs[q], bits of the footprint's word sum)."""
         self._fits(lut, dirs, out)
         _check(lib().shm_plan_probe(self.handle, _ptr(lut), _ptr(dirs), _ptr(out), seed & 0xFFFFFFFF, _stream(stream)))
+
+    def backward_sort(self, dirs, stream=None):
+        """shm_plan_backward_sort: sort the plan's queries by cell (kept in
+        the plan while dirs are unchanged)."""
+        _fits(dirs, self._rows * 12, "dirs")
+        _check(lib().shm_plan_backward_sort(self.handle, _ptr(dirs), _stream(stream)))
+
+    def backward(self, lut, dirs, grad_out, grad_lut=None, grad_dirs=None, stream=None):
+        """shm_plan_backward: dL/dLUT (FP32, the LUT's element layout) and
+        dL/d dirs of every object's rows."""
+        _fits(lut, self._lut_bytes, "lut")
+        _fits(dirs, self._rows * 12, "dirs")
+        _fits(grad_out, self._rows * 16, "grad_out")
+        _fits(grad_lut, self._lut_elems_all * 4, "grad_lut")
+        _fits(grad_dirs, self._rows * 12, "grad_dirs")
+        for t, name in ((grad_out, "grad_out"), (grad_lut, "grad_lut"), (grad_dirs, "grad_dirs")):
+            if t is not None:
+                _need(t, torch.float32, name)
+        _check(lib().shm_plan_backward(self.handle, _ptr(lut), _ptr(dirs), _ptr(grad_out), _ptr(grad_lut),
+                                       _ptr(grad_dirs), _stream(stream)))
 
     @property
     def work_items(self):

@@ -127,6 +127,14 @@ struct shm_plan {
     // completed
     std::vector<std::pair<hipStream_t, hipEvent_t>> launched;
     hipEvent_t t0 = nullptr, t1 = nullptr;  // autotuner timing
+    // backward of the objects (shm_plan_backward_sort): host prefix arrays
+    // (cell, tile, query-tile bases; kept alive for their device copy), the
+    // device copy, the sort workspace and whether a sort has been issued
+    std::vector<int64_t> bwd_prefix;
+    int64_t* d_bwd_prefix = nullptr;
+    void* bwd_ws = nullptr;
+    BwdObjectsHost bwd{};
+    bool bwd_ready = false, bwd_sorted = false;
 };
 
 // Smallest work-item tile a shape may have (block 64 x 1 query per thread):
@@ -636,8 +644,130 @@ int shm_plan_destroy(shm_plan* plan)
     }
     if (plan->d_items) (void)hipFree(plan->d_items);
     if (plan->d_objs) (void)hipFree(plan->d_objs);
+    if (plan->d_bwd_prefix) (void)hipFree(plan->d_bwd_prefix);
+    if (plan->bwd_ws) (void)hipFree(plan->bwd_ws);
     delete plan;
     return SHM_OK;
+}
+
+// Host side of a plan's backward: checks that the objects' LUTs and query
+// ranges do not overlap, builds the prefix arrays and allocates the device
+// copy and the sort workspace (once per plan).
+static int plan_backward_prepare(shm_plan* P, hipStream_t stream)
+{
+    if (P->bwd_ready) return SHM_OK;
+    if (P->layout != SHM_LAYOUT_TEXEL)
+        return fail(SHM_ERR_UNSUPPORTED, "plan_backward: the backward takes TEXEL LUTs (the gradient is per texel)");
+    const int64_t n = (int64_t)P->objs.size();
+    // LUT extents [off, off + texel_elems) and query ranges must not overlap
+    std::vector<std::pair<int64_t, int64_t>> lut_r, q_r;
+    for (const shm_object& o : P->objs) {
+        lut_r.emplace_back(o.lut_offset, o.lut_offset + texel_elems(o.N));
+        if (o.q_count > 0) q_r.emplace_back(o.q_begin, o.q_begin + o.q_count);
+    }
+    std::sort(lut_r.begin(), lut_r.end());
+    std::sort(q_r.begin(), q_r.end());
+    for (size_t i = 1; i < lut_r.size(); ++i)
+        if (lut_r[i].first < lut_r[i - 1].second)
+            return fail(SHM_ERR_INVALID_ARG, "plan_backward: two objects' LUTs overlap (each texel has one gradient)");
+    for (size_t i = 1; i < q_r.size(); ++i)
+        if (q_r[i].first < q_r[i - 1].second)
+            return fail(SHM_ERR_INVALID_ARG, "plan_backward: two objects' query ranges overlap");
+    const int64_t BT = backward_tile_texels(), QT = backward_query_tile();
+    std::vector<int64_t> pre(3 * (size_t)(n + 1));
+    int64_t* cb = pre.data();
+    int64_t* tb = cb + (n + 1);
+    int64_t* qb = tb + (n + 1);
+    int64_t Q = 0;
+    for (int64_t o = 0; o < n; ++o) {
+        const shm_object& ob = P->objs[o];
+        const int64_t C = ob.N + 1, tpf = (ob.N + 2 + BT - 1) / BT;
+        cb[o + 1] = cb[o] + 6 * C * C;
+        tb[o + 1] = tb[o] + 6 * tpf * tpf;
+        qb[o + 1] = qb[o] + (ob.q_count + QT - 1) / QT;
+        if (ob.q_count > 0) Q = std::max(Q, ob.q_begin + ob.q_count);
+    }
+    // 32-bit sort keys (the key n_cells marks an invalid direction) and
+    // query indices; one-dimensional grids
+    if (cb[n] >= 0xffffffffll || Q >= 0xffffffffll || tb[n] > 0x7fffffff || qb[n] > 0x7fffffff)
+        return fail(SHM_ERR_UNSUPPORTED, "plan_backward: %lld cells, %lld queries exceed the 32-bit sort",
+                    (long long)cb[n], (long long)Q);
+    BwdObjectsHost H;
+    H.n_obj = n;
+    H.Q = Q;
+    H.n_cells = cb[n];
+    H.n_tiles = tb[n];
+    H.n_qtiles = qb[n];
+    // the object of every tile and query tile (int32), after the prefixes
+    const size_t n64 = pre.size();
+    pre.resize(n64 + (size_t)((tb[n] + qb[n] + 1) / 2));
+    cb = pre.data();
+    tb = cb + (n + 1);
+    qb = tb + (n + 1);
+    int32_t* t_obj = reinterpret_cast<int32_t*>(pre.data() + n64);
+    int32_t* q_obj = t_obj + tb[n];
+    for (int64_t o = 0; o < n; ++o) {
+        for (int64_t t = tb[o]; t < tb[o + 1]; ++t) t_obj[t] = (int32_t)o;
+        for (int64_t t = qb[o]; t < qb[o + 1]; ++t) q_obj[t] = (int32_t)o;
+    }
+    const size_t ws_bytes = backward_objects_workspace_bytes(Q, H.n_cells, H.n_tiles);
+    if (hipMalloc(&P->d_bwd_prefix, pre.size() * sizeof(int64_t)) != hipSuccess) {
+        P->d_bwd_prefix = nullptr;
+        return fail(SHM_ERR_HIP, "plan_backward: hipMalloc of the object prefixes failed");
+    }
+    if (hipMalloc(&P->bwd_ws, std::max<size_t>(ws_bytes, 256)) != hipSuccess) {
+        P->bwd_ws = nullptr;
+        (void)hipFree(P->d_bwd_prefix);
+        P->d_bwd_prefix = nullptr;
+        return fail(SHM_ERR_HIP, "plan_backward: hipMalloc of %zu bytes of sort workspace failed", ws_bytes);
+    }
+    P->bwd_prefix = std::move(pre);
+    SHM_HIP_CHECK(hipMemcpyAsync(P->d_bwd_prefix, P->bwd_prefix.data(), P->bwd_prefix.size() * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, stream));
+    H.objs = P->d_objs;
+    H.cell_base = P->d_bwd_prefix;
+    H.tile_base = P->d_bwd_prefix + (n + 1);
+    H.qtile_base = P->d_bwd_prefix + 2 * (n + 1);
+    H.tile_obj = reinterpret_cast<const int32_t*>(P->d_bwd_prefix + n64);
+    H.qtile_obj = H.tile_obj + H.n_tiles;
+    P->bwd = H;
+    P->bwd_ready = true;
+    return SHM_OK;
+}
+
+int shm_plan_backward_sort(shm_plan* plan, const float* dirs, hipStream_t stream)
+{
+    clear_error();
+    if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_backward_sort: null plan");
+    int rc = plan_backward_prepare(plan, stream);
+    if (rc) return rc;
+    if (plan->bwd.Q > 0 && (!dirs || !aligned(dirs, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "plan_backward_sort: null or misaligned dirs");
+    // an earlier backward may still read the sort this call rewrites: the
+    // stream orders it if it ran on the same stream; else wait for it
+    if ((rc = plan_wait_launches(plan)) != SHM_OK) return rc;
+    rc = launch_backward_sort_objects(plan->bwd, dirs, plan->bwd_ws, stream);
+    if (rc) return rc;
+    plan->bwd_sorted = true;
+    return plan_mark_launch(plan, stream);
+}
+
+int shm_plan_backward(shm_plan* plan, const void* lut, const float* dirs, const float* grad_out, float* grad_lut,
+                      float* grad_dirs, hipStream_t stream)
+{
+    clear_error();
+    if (!plan) return fail(SHM_ERR_INVALID_ARG, "plan_backward: null plan");
+    if (!plan->bwd_sorted) return fail(SHM_ERR_INVALID_ARG, "plan_backward: call shm_plan_backward_sort first");
+    if (!grad_lut && !grad_dirs) return SHM_OK;
+    const BwdObjectsHost& H = plan->bwd;
+    if (H.Q > 0 && (!dirs || !grad_out)) return fail(SHM_ERR_INVALID_ARG, "plan_backward: null dirs or grad_out");
+    if (grad_dirs && H.Q > 0 && !lut) return fail(SHM_ERR_INVALID_ARG, "plan_backward: null lut");
+    const size_t al = plan->dtype == SHM_F16 ? 8 : 16;
+    if ((lut && !aligned(lut, al)) || (grad_out && !aligned(grad_out, 16)) || (grad_lut && !aligned(grad_lut, 16)) ||
+        (dirs && !aligned(dirs, 4)) || (grad_dirs && !aligned(grad_dirs, 4)))
+        return fail(SHM_ERR_INVALID_ARG, "plan_backward: misaligned buffer");
+    int rc = launch_backward_objects(H, plan->dtype, lut, dirs, grad_out, grad_lut, grad_dirs, plan->bwd_ws, stream);
+    return rc ? rc : plan_mark_launch(plan, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,12 @@
 #include "shm_fit.hpp"
 #include "shm_internal.hpp"
 
+// texels per LUT-gradient tile side (a compile-time tuning knob): BC * BC
+// cells, one per lane of the tile's workgroup (256 lanes for 15, 1024 for 31)
+#ifndef SHM_BWD_BT
+#define SHM_BWD_BT 15
+#endif
+
 namespace shm {
 
 constexpr int RS_THREADS = 256;
@@ -28,9 +34,23 @@ constexpr int SC_THREADS = 256, SC_ITEMS = 16, SC_TILE = SC_THREADS * SC_ITEMS; 
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// dense-tile record of a sort: a uint32 count, the list of dense tiles
+// (uint32 each, in no particular order) and one flag byte per tile
+static inline size_t dense_bytes(int64_t n_tiles) { return 16 + (size_t)n_tiles * 5; }
+struct DenseTiles {
+    uint32_t* count;
+    uint32_t* list;
+    uint8_t* flag;
+};
+static inline DenseTiles dense_tiles(char* at, int64_t n_tiles)
+{
+    return DenseTiles{reinterpret_cast<uint32_t*>(at), reinterpret_cast<uint32_t*>(at + 16),
+                      reinterpret_cast<uint8_t*>(at + 16 + (size_t)n_tiles * 4)};
+}
+
 struct BwdLayout {
-    size_t keys0, vals0, keys1, vals1, cstart, hist, tsum, total;
-    int64_t Q, n_cells, nb;
+    size_t keys0, vals0, keys1, vals1, cstart, hist, tsum, sdirs = 0, sgout = 0, dense = 0, total;
+    int64_t Q, n_cells, nb, n_tiles = 0;
     int passes;
 };
 
@@ -52,6 +72,9 @@ static BwdLayout bwd_layout(int N, int64_t n_obj, int64_t q_per_obj)
     W.cstart = take((W.n_cells + 1) * 4);
     W.hist = take((size_t)256 * W.nb * 4);
     W.tsum = take(((size_t)256 * W.nb + SC_TILE - 1) / SC_TILE * 4);
+    const int64_t tpf = (N + 2 + SHM_BWD_BT - 1) / SHM_BWD_BT;
+    W.n_tiles = n_obj * 6 * tpf * tpf;
+    W.dense = take(dense_bytes(W.n_tiles));  // dense-tile count, list and flags
     W.total = o;
     return W;
 }
@@ -222,52 +245,6 @@ __global__ void k_cell_start(const uint32_t* __restrict__ sk, int64_t Q, int64_t
     cs[c] = (uint32_t)lo;
 }
 
-int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream)
-{
-    const BwdLayout W = bwd_layout(N, n_obj, q_per_obj);
-    if (W.Q == 0) return SHM_OK;
-    char* base = reinterpret_cast<char*>(ws);
-    uint32_t* k0 = reinterpret_cast<uint32_t*>(base + W.keys0);
-    uint32_t* v0 = reinterpret_cast<uint32_t*>(base + W.vals0);
-    uint32_t* k1 = reinterpret_cast<uint32_t*>(base + W.keys1);
-    uint32_t* v1 = reinterpret_cast<uint32_t*>(base + W.vals1);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(base + W.hist);
-    uint32_t* tsum = reinterpret_cast<uint32_t*>(base + W.tsum);
-    const int64_t n_hist = (int64_t)256 * W.nb;
-    const int64_t n_tiles = (n_hist + SC_TILE - 1) / SC_TILE;
-    const unsigned gq = (unsigned)((W.Q + 255) / 256);
-    hipLaunchKernelGGL(k_cell_keys, dim3(gq), dim3(256), 0, stream, N, W.Q, q_per_obj, dirs, (uint32_t)W.n_cells, k0, v0);
-    SHM_LAUNCH_CHECK();
-    for (int p = 0; p < W.passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, W.Q, shift, W.nb, hist);
-        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SC_THREADS), 0, stream, tsum, n_tiles);
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, v0, W.Q, shift, W.nb,
-                           hist, k1, v1);
-        SHM_LAUNCH_CHECK();
-        uint32_t* t = k0; k0 = k1; k1 = t;
-        t = v0; v0 = v1; v1 = t;
-    }
-    // sorted keys in k0, permutation in v0 (buffer 0 or 1 depending on parity)
-    uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
-    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.n_cells + 1 + 255) / 256)), dim3(256), 0, stream, k0, W.Q,
-                       W.n_cells, cs);
-    SHM_LAUNCH_CHECK();
-    return SHM_OK;
-}
-
-int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream)
-{
-    const int64_t Q = n_obj * q_per_obj;
-    if (Q == 0) return SHM_OK;
-    hipLaunchKernelGGL(k_cell_keys, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, stream, N, Q, q_per_obj, dirs,
-                       KEY_INVALID, keys, (uint32_t*)nullptr);
-    SHM_LAUNCH_CHECK();
-    return SHM_OK;
-}
-
 // ---------------------------------------------------------------------------
 // Fused gradient pass.  One workgroup per tile of BT x BT texels of one face;
 // its texels touch the BC x BC cells i0 in [p0-1, p0+BT-1], j0 in
@@ -299,13 +276,11 @@ struct FitArgs {
     AdamConsts k;
 };
 
-// texels per tile side (a compile-time tuning knob): BC * BC cells, one per
-// lane of the tile's workgroup (256 lanes for 15, 1024 for 31)
-#ifndef SHM_BWD_BT
-#define SHM_BWD_BT 15
-#endif
 constexpr int BT = SHM_BWD_BT;
 constexpr int BC = BT + 1;             // cells per tile side
+// a tile with a cell of more than BWD_DENSE queries sums each round in runs
+// of at most 16 slots (the serial per-cell loop would take one step per query)
+constexpr int BWD_DENSE = 32;
 constexpr int BWD_THREADS = BC * BC;
 constexpr int DIRS_THREADS = 256;      // lanes per workgroup of the direction gradient
 
@@ -339,7 +314,8 @@ __device__ __forceinline__ void query_weights(float gR, float nlu, float nlv, co
 // dL/d dirs of one query: second chart derivatives of the patch plus the
 // derivative of the chart map (a = sc/ma, b = tc/ma) at d.  Its reciprocals
 // and square root are the hardware's (~1 ulp): no decision depends on them.
-__device__ __forceinline__ float3 dirs_grad(const float* __restrict__ lut_obj, int N, Loc L, float4 gq, float3 M,
+template <bool FP16 = false>
+__device__ __forceinline__ float3 dirs_grad(const void* __restrict__ lut_obj, int N, Loc L, float4 gq, float3 M,
                                          float3 S, float3 T, float x, float y, float z)
 {
     const float Nf = (float)N;
@@ -351,7 +327,7 @@ __device__ __forceinline__ float3 dirs_grad(const float* __restrict__ lut_obj, i
     const float rho = __builtin_amdgcn_sqrtf(1.0f + A * A + B * B);
     const float kk2 = 0.5f * rho;
     const float gR = gq.x;
-    const Foot F = load_texel_f32(lut_obj, N, L);
+    const Foot F = load_foot<FP16, false>(lut_obj, N, L);
     const Patch2 Pp = hermite2(F, L.s, L.t);
     const float gM = gq.y * M.x + gq.z * M.y + gq.w * M.z;
     const float ru = Nf * Pp.rs, rv = Nf * Pp.rt;
@@ -374,30 +350,60 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Where a texel tile sits: face size, face, first texel (p0, q0), the global
+// index of the face's cell (0, 0) in the sorted keys, the global texel index
+// of the face's texel (0, 0) in the LUT-shaped arrays, and the object's LUT.
+struct TileGeo {
+    int N, face, p0, q0;
+    int64_t cbase, tex_base;
+    const float* lut_obj;
+};
+
+// tile `tile` of n_obj uniform objects of face size N stored back to back
+__device__ __forceinline__ TileGeo uniform_tile(int tile, int N, int tpf, const float* lut, int64_t lut_elems)
+{
+    const int C = N + 1, P = N + 2;
+    const int per_face = tpf * tpf;
+    const int64_t fo = tile / per_face;  // object * 6 + face
+    const int b = tile - (int)(fo * per_face);
+    TileGeo G;
+    G.N = N;
+    G.p0 = (b % tpf) * BT;
+    G.q0 = (b / tpf) * BT;
+    const int64_t obj = fo / 6;
+    G.face = (int)(fo - obj * 6);
+    G.cbase = fo * (int64_t)C * C;
+    G.tex_base = fo * (int64_t)P * P;
+    G.lut_obj = lut + obj * lut_elems;
+    return G;
+}
+
 // One texel tile (workgroup-wide: every lane of the workgroup calls it with
-// the same tile index).
-template <bool FIT>
-__device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut, int N, int64_t lut_elems, int64_t Q,
+// the same tile).  SORTED: dirs and gout hold the queries' directions and
+// upstream gradients already in sorted order (read at the sorted position,
+// coalesced); otherwise they are in query order and read through perm.
+template <bool FIT, bool SORTED = false, bool DENSE = false>
+__device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restrict__ lut, int64_t Q,
                                          const float* __restrict__ dirs, const float* __restrict__ gout,
                                          const uint32_t* __restrict__ perm, const uint32_t* __restrict__ cs,
-                                         int tiles_per_face, float* __restrict__ grad_lut, const FitArgs& fa)
+                                         float* __restrict__ grad_lut, const FitArgs& fa,
+                                         const uint8_t* __restrict__ skip_flag = nullptr)
 {
+    // a tile another kernel handles (the dense ones) is left after the first
+    // barrier: its flag loads beside the segment bounds, off the critical path
+    const uint8_t skip = skip_flag != nullptr ? *skip_flag : 0;
     // one query's weights per lane, later the cell sums: corner-major, so that
     // the 16-byte accesses of consecutive lanes fall on consecutive banks
     __shared__ float4 slot[4][BWD_THREADS];
     __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
     __shared__ int64_t row_len[BC];          // queries in each cell row's range
     __shared__ int64_t row_off[BC + 1];      // offsets of the rows in the concatenated list
+    __shared__ int slot_cell[DENSE ? BWD_THREADS : 1];  // dense tiles: the tile cell of each slot's query
+    const int N = G.N;
     const int C = N + 1, P = N + 2;
-    const int tpf = tiles_per_face;
-    int b = tile;
-    const int per_face = tpf * tpf;
-    const int64_t fo = b / per_face;  // object * 6 + face
-    b -= (int)(fo * per_face);
-    const int p0 = (b % tpf) * BT, q0 = (b / tpf) * BT;
-    const int64_t obj = fo / 6;
-    const int face = (int)(fo - obj * 6);
-    const int64_t cbase = fo * (int64_t)C * C;
+    const int p0 = G.p0, q0 = G.q0;
+    const int face = G.face;
+    const int64_t cbase = G.cbase;
     const int i_lo = max(p0 - 1, 0), i_hi = min(p0 + BT - 1, N);  // the tile's cell columns (p0 <= N + 1)
     const int tid = threadIdx.x;
     // this lane's cell: its segment bounds load beside the row setup
@@ -423,6 +429,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
         row_len[tid] = e - a;
     }
     lds_barrier();
+    if (skip) return;  // uniform over the workgroup
     if (tid <= BC) {  // exclusive prefix: independent reads, no serial chain
         int64_t o = 0;
         for (int k = 0; k < tid; ++k) o += row_len[k];
@@ -459,7 +466,8 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
             if (row_off[r + step] <= gc) r += step;
         int64_t pos = row_start[r] + (gc - row_off[r]);
         pos = pos < 0 ? 0 : (pos >= Q ? Q - 1 : pos);
-        return (int64_t)perm[pos];
+        if constexpr (SORTED) return pos;
+        else return (int64_t)perm[pos];
     };
     // the upstream gradient of query q, or for the fitting step its targets
     // (R*, n*), from which the lane computes the upstream gradient
@@ -467,7 +475,8 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
         if constexpr (FIT) return make_float4(fa.tr[q], fa.tn[3 * q], fa.tn[3 * q + 1], fa.tn[3 * q + 2]);
         else return reinterpret_cast<const float4*>(gout)[q];
     };
-    const float* lut_obj = lut + obj * lut_elems;
+    static_assert(!(FIT && SORTED), "the fitting step reads its inputs in query order");
+    const float* lut_obj = G.lut_obj;
     // software pipeline: round k + 1's index, direction and upstream
     // gradient loads are in flight while round k computes and reduces
     // (an empty list, as with no queries at all, loads nothing: its clamped
@@ -507,6 +516,9 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
 #pragma unroll
                 for (int k = 0; k < 4; ++k) slot[k][tid] = w[k];
             }
+            if constexpr (DENSE) slot_cell[tid] = r_cur * BC + (L.i0 - (p0 - 1));
+        } else if constexpr (DENSE) {
+            slot_cell[tid] = -1;
         }
         // unconditional: q_next is a valid index even past the list's end
         x = dirs[3 * q_next];
@@ -519,14 +531,49 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
         {
             lds_barrier();
             const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
-            for (int k2 = lo; k2 < hi; ++k2) {
+            if constexpr (!DENSE) {
+                for (int k2 = lo; k2 < hi; ++k2) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float4 v = slot[k][k2];
-                    acc[k].x += v.x;
-                    acc[k].y += v.y;
-                    acc[k].z += v.z;
-                    acc[k].w += v.w;
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 v = slot[k][k2];
+                        acc[k].x += v.x;
+                        acc[k].y += v.y;
+                        acc[k].z += v.z;
+                        acc[k].w += v.w;
+                    }
+                }
+            } else {
+                // a cell's segment may fill whole rounds: first each run of
+                // one cell inside a chunk of 16 slots is summed in order, one
+                // lane per (chunk, scalar), into the run's last slot; then
+                // each cell lane adds its runs' sums in order (at most one
+                // per chunk instead of one per query)
+                {
+                    const int chunk = tid >> 4, ch = tid & 15;
+                    float* col = reinterpret_cast<float*>(&slot[ch >> 2][0]) + (ch & 3);
+                    float run = 0.0f;
+#pragma unroll 1
+                    for (int i = 0; i < 16; ++i) {
+                        const int sp = chunk * 16 + i;
+                        run += col[4 * sp];
+                        if (i == 15 || slot_cell[sp + 1] != slot_cell[sp]) {
+                            col[4 * sp] = run;
+                            run = 0.0f;
+                        }
+                    }
+                }
+                lds_barrier();
+                for (int p = lo; p < hi;) {
+                    const int pe = min(hi, (p | 15) + 1) - 1;  // the end of the run holding p
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 v = slot[k][pe];
+                        acc[k].x += v.x;
+                        acc[k].y += v.y;
+                        acc[k].z += v.z;
+                        acc[k].w += v.w;
+                    }
+                    p = pe + 1;
                 }
             }
             lds_barrier();
@@ -536,7 +583,7 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
     // while the cell sums are exchanged
     const int t_x = tid % BT, t_y = tid / BT, t_p = p0 + t_x, t_q = q0 + t_y;
     const bool t_ok = tid < BT * BT && t_p <= N + 1 && t_q <= N + 1;
-    const int64_t t_i = (fo * P + t_q) * (int64_t)P + t_p;
+    const int64_t t_i = G.tex_base + (int64_t)t_q * P + t_p;
     float4 pp, mm, vv;
     if (FIT && t_ok) {
         pp = reinterpret_cast<const float4*>(lut)[t_i];
@@ -573,15 +620,129 @@ __device__ __forceinline__ void bwd_tile(int tile, const float* __restrict__ lut
     }
 }
 
+// Whether a tile is dense (some cell of its 16 x 16 cells holds more than
+// BWD_DENSE queries): decided once per sort, so that each backward runs the
+// sparse and the dense tiles in two kernels of their own (the dense sums need
+// registers the sparse kernel should not pay for).
+__device__ __forceinline__ void tile_dense_flag(const TileGeo& G, const uint32_t* __restrict__ cs, DenseTiles D,
+                                                uint32_t t)
+{
+    __shared__ int any;
+    const int tid = threadIdx.x;
+    if (tid == 0) any = 0;
+    __syncthreads();
+    const int C = G.N + 1;
+    const int i0c = G.p0 - 1 + tid % BC, j0c = G.q0 - 1 + tid / BC;
+    if (i0c >= 0 && i0c <= G.N && j0c >= 0 && j0c <= G.N) {
+        const int64_t c = G.cbase + (int64_t)j0c * C + i0c;
+        if ((int64_t)cs[c + 1] - cs[c] > BWD_DENSE) any = 1;  // every writer stores the same value
+    }
+    __syncthreads();
+    if (tid == 0) {
+        D.flag[t] = any ? 1 : 0;
+        if (any) D.list[atomicAdd(D.count, 1u)] = t;  // integer atomic: the list's order is free
+    }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// workgroups of a dense-tile kernel: eight per compute unit, at most one per tile
+static inline int64_t dense_grid(int64_t n_tiles)
+{
+    return std::max<int64_t>(1, std::min<int64_t>(n_tiles, 8ll * device_cu_count()));
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_tile_dense(int N, int tiles_per_face, const uint32_t* __restrict__ cs,
+                                                            DenseTiles D)
+{
+    tile_dense_flag(uniform_tile((int)blockIdx.x, N, tiles_per_face, nullptr, 0), cs, D, blockIdx.x);
+}
+
+int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream)
+{
+    const BwdLayout W = bwd_layout(N, n_obj, q_per_obj);
+    if (W.Q == 0) return SHM_OK;
+    char* base = reinterpret_cast<char*>(ws);
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(base + W.keys0);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(base + W.vals0);
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(base + W.keys1);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(base + W.vals1);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(base + W.hist);
+    uint32_t* tsum = reinterpret_cast<uint32_t*>(base + W.tsum);
+    const int64_t n_hist = (int64_t)256 * W.nb;
+    const int64_t n_tiles = (n_hist + SC_TILE - 1) / SC_TILE;
+    const unsigned gq = (unsigned)((W.Q + 255) / 256);
+    hipLaunchKernelGGL(k_cell_keys, dim3(gq), dim3(256), 0, stream, N, W.Q, q_per_obj, dirs, (uint32_t)W.n_cells, k0, v0);
+    SHM_LAUNCH_CHECK();
+    for (int p = 0; p < W.passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, W.Q, shift, W.nb, hist);
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SC_THREADS), 0, stream, tsum, n_tiles);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, v0, W.Q, shift, W.nb,
+                           hist, k1, v1);
+        SHM_LAUNCH_CHECK();
+        uint32_t* t = k0; k0 = k1; k1 = t;
+        t = v0; v0 = v1; v1 = t;
+    }
+    // sorted keys in k0, permutation in v0 (buffer 0 or 1 depending on parity)
+    uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.n_cells + 1 + 255) / 256)), dim3(256), 0, stream, k0, W.Q,
+                       W.n_cells, cs);
+    if (W.n_tiles > 0) {
+        const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, D.count, 0u);
+        hipLaunchKernelGGL(k_tile_dense, dim3((unsigned)W.n_tiles), dim3(BWD_THREADS), 0, stream, N,
+                           (N + 2 + BT - 1) / BT, (const uint32_t*)cs, D);
+    }
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream)
+{
+    const int64_t Q = n_obj * q_per_obj;
+    if (Q == 0) return SHM_OK;
+    hipLaunchKernelGGL(k_cell_keys, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, stream, N, Q, q_per_obj, dirs,
+                       KEY_INVALID, keys, (uint32_t*)nullptr);
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+// the sparse tiles, one workgroup per tile (a dense tile's workgroup exits)
 template <bool FIT>
 __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restrict__ lut, int N, int64_t lut_elems,
                                                            int64_t Q, const float* __restrict__ dirs,
                                                            const float* __restrict__ gout,
                                                            const uint32_t* __restrict__ perm,
                                                            const uint32_t* __restrict__ cs, int tiles_per_face,
+                                                           const uint8_t* __restrict__ dense_flag,
                                                            float* __restrict__ grad_lut, FitArgs fa)
 {
-    bwd_tile<FIT>((int)blockIdx.x, lut, N, lut_elems, Q, dirs, gout, perm, cs, tiles_per_face, grad_lut, fa);
+    bwd_tile<FIT>(uniform_tile((int)blockIdx.x, N, tiles_per_face, lut, lut_elems), lut, Q, dirs, gout, perm, cs,
+                  grad_lut, fa, dense_flag != nullptr ? dense_flag + blockIdx.x : nullptr);
+}
+
+// the dense tiles, from the sort's list: a small persistent grid, so that a
+// backward without dense tiles pays little for this launch
+template <bool FIT>
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_dense(const float* __restrict__ lut, int N,
+                                                                 int64_t lut_elems, int64_t Q,
+                                                                 const float* __restrict__ dirs,
+                                                                 const float* __restrict__ gout,
+                                                                 const uint32_t* __restrict__ perm,
+                                                                 const uint32_t* __restrict__ cs, int tiles_per_face,
+                                                                 const uint32_t* __restrict__ count,
+                                                                 const uint32_t* __restrict__ list,
+                                                                 float* __restrict__ grad_lut, FitArgs fa)
+{
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        bwd_tile<FIT, false, true>(uniform_tile((int)list[i], N, tiles_per_face, lut, lut_elems), lut, Q, dirs, gout,
+                                   perm, cs, grad_lut, fa);
+        lds_barrier();  // the next tile reuses the workgroup's LDS
+    }
 }
 
 // Direction gradients of DIRS_THREADS consecutive queries (block blk), in the
@@ -624,6 +785,294 @@ __global__ void k_zero_f4(float4* __restrict__ a, int64_t n)
     if (i < n) a[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// ---------------------------------------------------------------------------
+// Backward of a plan's objects: face sizes, LUT offsets and query ranges of
+// their own.  The host builds three prefix arrays over the objects (n_obj + 1
+// entries each): the first global cell key of each object (cells of the
+// objects before it), its first LUT-gradient tile (6 tpf^2 per object) and
+// its first query tile (OBJ_QT queries).  A workgroup finds its object by
+// binary search over the prefix of its kind; everything else is the uniform
+// path's arithmetic, so a plan's backward gives each object the bits of a
+// one-object backward of that object's queries.
+// ---------------------------------------------------------------------------
+constexpr int OBJ_QT = 256;  // queries per query tile
+
+struct BwdObjects {
+    const shm_object* objs;
+    const int64_t* cell_base;
+    const int64_t* tile_base;
+    const int64_t* qtile_base;
+    const int32_t* tile_obj;   // object of each LUT-gradient tile
+    const int32_t* qtile_obj;  // object of each query tile
+    int64_t n_obj;
+};
+
+__global__ void k_keys_init(int64_t Q, uint32_t invalid_key, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q) return;
+    keys[q] = invalid_key;
+    vals[q] = (uint32_t)q;
+}
+
+__global__ __launch_bounds__(OBJ_QT) void k_cell_keys_objects(BwdObjects B, const float* __restrict__ dirs,
+                                                              uint32_t invalid_key, uint32_t* __restrict__ keys)
+{
+    const int64_t t = blockIdx.x;
+    const int64_t o = B.qtile_obj[t];
+    const shm_object ob = B.objs[o];
+    const int64_t k = (t - B.qtile_base[o]) * OBJ_QT + threadIdx.x;
+    if (k >= ob.q_count) return;
+    const int64_t q = ob.q_begin + k;
+    const Loc L = locate(dirs[3 * q], dirs[3 * q + 1], dirs[3 * q + 2], ob.N);
+    const int64_t C = ob.N + 1;
+    keys[q] = L.face < 0 ? invalid_key : (uint32_t)(B.cell_base[o] + ((int64_t)L.face * C + L.j0) * C + L.i0);
+}
+
+// row i of dst = row perm[i] of src (rows of W floats): the queries' inputs
+// in sorted order, read at random once so that the tiles read them coalesced
+template <int W>
+__global__ void k_gather_rows(const uint32_t* __restrict__ perm, const float* __restrict__ src, int64_t Q,
+                              float* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q) return;
+    const int64_t q = perm[i];
+    if constexpr (W == 4) {
+        reinterpret_cast<float4*>(dst)[i] = reinterpret_cast<const float4*>(src)[q];
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) dst[W * i + k] = src[W * q + k];
+    }
+}
+
+// tile t of a plan's objects
+__device__ __forceinline__ TileGeo object_tile(const BwdObjects& B, int64_t t)
+{
+    const int64_t o = B.tile_obj[t];
+    const shm_object ob = B.objs[o];
+    const int N = ob.N, C = N + 1, P = N + 2;
+    const int tpf = (P + BT - 1) / BT, per_face = tpf * tpf;
+    const int local = (int)(t - B.tile_base[o]);
+    TileGeo G;
+    G.N = N;
+    G.face = local / per_face;
+    const int b = local - G.face * per_face;
+    G.p0 = (b % tpf) * BT;
+    G.q0 = (b / tpf) * BT;
+    G.cbase = B.cell_base[o] + (int64_t)G.face * C * C;
+    G.tex_base = ob.lut_offset / 4 + (int64_t)G.face * P * P;  // texels of 4 elements
+    G.lut_obj = nullptr;                                       // read only by the fitting step
+    return G;
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_tile_dense_objects(BwdObjects B, const uint32_t* __restrict__ cs,
+                                                                    DenseTiles D)
+{
+    tile_dense_flag(object_tile(B, blockIdx.x), cs, D, blockIdx.x);
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects(BwdObjects B, int64_t Q,
+                                                                   const float* __restrict__ sdirs,
+                                                                   const float* __restrict__ sgout,
+                                                                   const uint32_t* __restrict__ perm,
+                                                                   const uint32_t* __restrict__ cs,
+                                                                   const uint8_t* __restrict__ dense_flag,
+                                                                   float* __restrict__ grad_lut)
+{
+    const int64_t t = blockIdx.x;
+    const uint8_t dense = dense_flag != nullptr ? dense_flag[t] : 0;  // a dense tile: k_bwd_fused_objects_dense
+    const TileGeo G = object_tile(B, t);
+    const int N = G.N, C = N + 1, P = N + 2;
+    // a tile whose cell rows hold no query has a zero gradient: write it
+    // without the row setup and its barriers (most tiles of a large face
+    // with few queries)
+    const int j_lo = max(G.q0 - 1, 0), j_hi = min(G.q0 + BT - 1, N);
+    const int64_t in_rows = Q > 0 ? (int64_t)cs[G.cbase + (int64_t)(j_hi + 1) * C] - cs[G.cbase + (int64_t)j_lo * C] : 0;
+    if (dense) return;
+    if (in_rows == 0) {
+        const int tid = threadIdx.x, t_x = tid % BT, t_y = tid / BT;
+        if (tid < BT * BT && G.p0 + t_x <= N + 1 && G.q0 + t_y <= N + 1)
+            reinterpret_cast<float4*>(grad_lut)[G.tex_base + (int64_t)(G.q0 + t_y) * P + G.p0 + t_x] =
+                make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    bwd_tile<false, true>(G, nullptr, Q, sdirs, sgout, perm, cs, grad_lut, FitArgs{});
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects_dense(BwdObjects B, int64_t Q,
+                                                                         const float* __restrict__ sdirs,
+                                                                         const float* __restrict__ sgout,
+                                                                         const uint32_t* __restrict__ perm,
+                                                                         const uint32_t* __restrict__ cs,
+                                                                         const uint32_t* __restrict__ count,
+                                                                         const uint32_t* __restrict__ list,
+                                                                         float* __restrict__ grad_lut)
+{
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        bwd_tile<false, true, true>(object_tile(B, list[i]), nullptr, Q, sdirs, sgout, perm, cs, grad_lut, FitArgs{});
+        lds_barrier();  // the next tile reuses the workgroup's LDS
+    }
+}
+
+template <bool FP16>
+__global__ __launch_bounds__(OBJ_QT) void k_bwd_dirs_objects(BwdObjects B, const void* __restrict__ lut,
+                                                             const float* __restrict__ dirs,
+                                                             const float* __restrict__ gout,
+                                                             float* __restrict__ grad_dirs)
+{
+    const int64_t t = blockIdx.x;
+    const int64_t o = B.qtile_obj[t];
+    const shm_object ob = B.objs[o];
+    const int64_t k = (t - B.qtile_base[o]) * OBJ_QT + threadIdx.x;
+    if (k >= ob.q_count) return;
+    const int64_t q = ob.q_begin + k;
+    const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
+    const Loc L = locate(x, y, z, ob.N);
+    float3 gd;
+    if (L.face < 0) {
+        const float nan = __builtin_nanf("");
+        gd = make_float3(nan, nan, nan);
+    } else {
+        const float4 gq = reinterpret_cast<const float4*>(gout)[q];
+        float3 M, S, T;
+        frame_of(L.face, M, S, T);
+        const char* base = reinterpret_cast<const char*>(lut) + (size_t)ob.lut_offset * (FP16 ? 2 : 4);
+        gd = dirs_grad<FP16>(base, ob.N, L, gq, M, S, T, x, y, z);
+    }
+    grad_dirs[3 * q] = gd.x;
+    grad_dirs[3 * q + 1] = gd.y;
+    grad_dirs[3 * q + 2] = gd.z;
+}
+
+// Sort of a plan's queries: Q rows (rows outside every object keep the
+// invalid key and sort last), n_cells keys.  The workspace layout is the
+// uniform one for (Q, n_cells).
+static BwdLayout bwd_layout_cells(int64_t Q, int64_t n_cells, int64_t n_tiles)
+{
+    BwdLayout W;
+    W.n_tiles = n_tiles;
+    W.Q = Q;
+    W.n_cells = n_cells;
+    W.nb = (W.Q + RS_TILE - 1) / RS_TILE;
+    int bits = 1;
+    while (((int64_t)1 << bits) <= W.n_cells) ++bits;
+    W.passes = (bits + 7) / 8;
+    size_t at = 0;
+    auto take = [&](size_t bytes) { size_t a = at; at += align256(bytes); return a; };
+    W.keys0 = take(W.Q * 4);
+    W.vals0 = take(W.Q * 4);
+    W.keys1 = take(W.Q * 4);
+    W.vals1 = take(W.Q * 4);
+    W.cstart = take((W.n_cells + 1) * 4);
+    W.hist = take((size_t)256 * W.nb * 4);
+    W.tsum = take(((size_t)256 * W.nb + SC_TILE - 1) / SC_TILE * 4);
+    W.sdirs = take(W.Q * 12);  // directions in sorted order (with the sort)
+    W.sgout = take(W.Q * 16);  // upstream gradients in sorted order (per backward)
+    W.dense = take(dense_bytes(n_tiles));
+    W.total = at;
+    return W;
+}
+
+size_t backward_objects_workspace_bytes(int64_t Q, int64_t n_cells, int64_t n_tiles)
+{
+    return bwd_layout_cells(Q, n_cells, n_tiles).total;
+}
+int backward_tile_texels() { return BT; }
+int backward_query_tile() { return OBJ_QT; }
+
+static void radix_sort_pass_all(const BwdLayout& W, char* base, hipStream_t stream, uint32_t*& k0, uint32_t*& v0)
+{
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(base + W.keys1);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(base + W.vals1);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(base + W.hist);
+    uint32_t* tsum = reinterpret_cast<uint32_t*>(base + W.tsum);
+    const int64_t n_hist = (int64_t)256 * W.nb;
+    const int64_t n_tiles = (n_hist + SC_TILE - 1) / SC_TILE;
+    for (int p = 0; p < W.passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, W.Q, shift, W.nb, hist);
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SC_THREADS), 0, stream, tsum, n_tiles);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(SC_THREADS), 0, stream, hist, n_hist, tsum);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)W.nb), dim3(RS_THREADS), 0, stream, k0, v0, W.Q, shift, W.nb,
+                           hist, k1, v1);
+        uint32_t* t = k0; k0 = k1; k1 = t;
+        t = v0; v0 = v1; v1 = t;
+    }
+}
+
+int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, void* ws, hipStream_t stream)
+{
+    const BwdLayout W = bwd_layout_cells(H.Q, H.n_cells, H.n_tiles);
+    if (W.Q == 0) return SHM_OK;
+    char* base = reinterpret_cast<char*>(ws);
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(base + W.keys0);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(base + W.vals0);
+    const BwdObjects B{H.objs, H.cell_base, H.tile_base, H.qtile_base, H.tile_obj, H.qtile_obj, H.n_obj};
+    hipLaunchKernelGGL(k_keys_init, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, W.Q,
+                       (uint32_t)W.n_cells, k0, v0);
+    if (H.n_qtiles > 0)
+        hipLaunchKernelGGL(k_cell_keys_objects, dim3((unsigned)H.n_qtiles), dim3(OBJ_QT), 0, stream, B, dirs,
+                           (uint32_t)W.n_cells, k0);
+    SHM_LAUNCH_CHECK();
+    radix_sort_pass_all(W, base, stream, k0, v0);
+    SHM_LAUNCH_CHECK();
+    uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.n_cells + 1 + 255) / 256)), dim3(256), 0, stream, k0, W.Q,
+                       W.n_cells, cs);
+    hipLaunchKernelGGL(k_gather_rows<3>, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, v0, dirs, W.Q,
+                       reinterpret_cast<float*>(base + W.sdirs));
+    if (H.n_tiles > 0) {
+        const DenseTiles D = dense_tiles(base + W.dense, H.n_tiles);
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, D.count, 0u);
+        hipLaunchKernelGGL(k_tile_dense_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B,
+                           (const uint32_t*)cs, D);
+    }
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut, const float* dirs, const float* gout,
+                            float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream)
+{
+    const BwdLayout W = bwd_layout_cells(H.Q, H.n_cells, H.n_tiles);
+    char* base = reinterpret_cast<char*>(ws);
+    const uint32_t* cs = reinterpret_cast<const uint32_t*>(base + W.cstart);
+    const uint32_t* perm = reinterpret_cast<const uint32_t*>(base + ((W.passes & 1) ? W.vals1 : W.vals0));
+    const float* sdirs = reinterpret_cast<const float*>(base + W.sdirs);
+    float* sgout = reinterpret_cast<float*>(base + W.sgout);
+    const BwdObjects B{H.objs, H.cell_base, H.tile_base, H.qtile_base, H.tile_obj, H.qtile_obj, H.n_obj};
+    if (grad_lut && H.n_tiles > 0) {
+        if (W.Q == 0) {  // no queries: the sort wrote nothing; every object's gradient is zero
+            hipLaunchKernelGGL(k_bwd_fused_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B,
+                               (int64_t)0, (const float*)nullptr, (const float*)nullptr, (const uint32_t*)nullptr,
+                               (const uint32_t*)nullptr, (const uint8_t*)nullptr, grad_lut);
+        } else {
+            const DenseTiles D = dense_tiles(base + W.dense, H.n_tiles);
+            hipLaunchKernelGGL(k_gather_rows<4>, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, perm, gout,
+                               W.Q, sgout);
+            hipLaunchKernelGGL(k_bwd_fused_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B, W.Q,
+                               sdirs, (const float*)sgout, perm, cs, (const uint8_t*)D.flag, grad_lut);
+            hipLaunchKernelGGL(k_bwd_fused_objects_dense, dim3((unsigned)dense_grid(H.n_tiles)), dim3(BWD_THREADS), 0,
+                               stream, B, W.Q, sdirs, (const float*)sgout, perm, cs, (const uint32_t*)D.count,
+                               (const uint32_t*)D.list, grad_lut);
+        }
+        SHM_LAUNCH_CHECK();
+    }
+    if (grad_dirs && H.n_qtiles > 0) {
+        if (dtype == SHM_F16)
+            hipLaunchKernelGGL((k_bwd_dirs_objects<true>), dim3((unsigned)H.n_qtiles), dim3(OBJ_QT), 0, stream, B, lut,
+                               dirs, gout, grad_dirs);
+        else
+            hipLaunchKernelGGL((k_bwd_dirs_objects<false>), dim3((unsigned)H.n_qtiles), dim3(OBJ_QT), 0, stream, B, lut,
+                               dirs, gout, grad_dirs);
+        SHM_LAUNCH_CHECK();
+    }
+    return SHM_OK;
+}
+
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
                     float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream)
 {
@@ -652,8 +1101,12 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     // running the two on concurrent streams all measured the same or slower
     // (the two compete for the same units: the total work sets the time)
     if (grad_lut) {
+        const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
         hipLaunchKernelGGL((k_bwd_fused<false>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,
-                           texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, grad_lut, FitArgs{});
+                           texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, (const uint8_t*)D.flag, grad_lut, FitArgs{});
+        hipLaunchKernelGGL((k_bwd_fused_dense<false>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0, stream,
+                           lut, N, texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, (const uint32_t*)D.count,
+                           (const uint32_t*)D.list, grad_lut, FitArgs{});
         SHM_LAUNCH_CHECK();
     }
     if (grad_dirs) {
@@ -683,8 +1136,15 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
     fa.m = reinterpret_cast<float4*>(m);
     fa.v = reinterpret_cast<float4*>(v);
     fa.k = adam_consts(step, lr_value, lr_deriv, b1, b2, eps);
+    // with no queries the sort wrote nothing: every tile is sparse
+    const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
     hipLaunchKernelGGL((k_bwd_fused<true>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut_in, N,
-                       texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf, (float*)nullptr, fa);
+                       texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf,
+                       Q > 0 ? (const uint8_t*)D.flag : nullptr, (float*)nullptr, fa);
+    if (Q > 0)
+        hipLaunchKernelGGL((k_bwd_fused_dense<true>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0, stream,
+                           lut_in, N, texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf,
+                           (const uint32_t*)D.count, (const uint32_t*)D.list, (float*)nullptr, fa);
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }

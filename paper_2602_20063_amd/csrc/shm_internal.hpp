@@ -59,6 +59,23 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
                             const WorkItem* items_dev, int64_t n_items, const XcdSplit& split,
                             const shm_launch_shape& shape, int n_cu,
                             const float* dirs, float* out, float* normal, hipStream_t stream);
+// backward of a plan's objects: device prefix arrays (n_obj + 1 entries each)
+// and the totals the host derived from the descriptors
+struct BwdObjectsHost {
+    const shm_object* objs = nullptr;
+    const int64_t* cell_base = nullptr;
+    const int64_t* tile_base = nullptr;
+    const int64_t* qtile_base = nullptr;
+    const int32_t* tile_obj = nullptr;   // object of each LUT-gradient tile
+    const int32_t* qtile_obj = nullptr;  // object of each query tile
+    int64_t n_obj = 0, Q = 0, n_cells = 0, n_tiles = 0, n_qtiles = 0;
+};
+int backward_tile_texels();   // texels per side of a LUT-gradient tile
+int backward_query_tile();    // queries per query tile of the object kernels
+size_t backward_objects_workspace_bytes(int64_t Q, int64_t n_cells, int64_t n_tiles);
+int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, void* ws, hipStream_t stream);
+int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut, const float* dirs, const float* gout,
+                            float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
 size_t query_objects_workspace(int64_t n_obj);
 int launch_query_objects(const void* lut, int dtype, int layout, const shm_object* objs, int64_t n_obj,
                          const float* dirs, float* out, float* normal, void* ws, hipStream_t stream);

@@ -334,6 +334,13 @@ def test_query_objects_argument_validation():
     assert call(f, None, 0, 0, None, 0, None, None, None, None, 0, None) == shm.SHM_OK  # no objects
 
 
+def test_plan_backward_argument_validation():
+    p = ctypes.c_void_p(256)
+    assert call("shm_plan_backward_sort", None, p, None) == shm.SHM_ERR_INVALID_ARG
+    assert "null plan" in shm.shm_last_error()
+    assert call("shm_plan_backward", None, p, p, p, p, p, None) == shm.SHM_ERR_INVALID_ARG
+
+
 def test_bake_noalloc_argument_validation():
     """The no-allocation bake validates like the workspace bake and refuses a
     basis table larger than its scratch before touching a device."""

@@ -133,6 +133,26 @@ def test_autograd_function_and_fd():
     assert d_t.grad is not None and torch.isfinite(d_t.grad).all()
 
 
+@pytest.mark.parametrize("N,Q", [(2, 20000), (5, 60000)])
+def test_backward_dense_cells(N, Q):
+    """Hundreds of queries per cell: the tiles sum each round in runs of at
+    most 16 slots; against the oracle and bitwise repeatable."""
+    r = rng(30 + N)
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(Q, r)
+    g = r.standard_normal((Q, 4)).astype(np.float32)
+    gl, gd = run_bwd(lut, dirs, g)
+    gl2, gd2 = run_bwd(lut, dirs, g)
+    assert np.array_equal(gl, gl2) and np.array_equal(gd, gd2)
+    rl, rd = oracle.backward(lut, dirs, g)
+    scale = np.abs(rl).max()
+    print('grad_lut error %.3e' % (np.abs(gl - rl).max() / scale))
+    assert np.abs(gl - rl).max() / scale < LUT_TOL
+    gn = np.linalg.norm(rd, axis=1)
+    floor = np.sqrt(np.mean(gn ** 2))
+    assert (np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)).max() < DIRS_TOL
+
+
 @pytest.mark.parametrize("N", [100, 512])
 def test_backward_three_radix_passes(N):
     """Cell keys above 2^16 take three 8-bit radix passes (N >= 105 for one
@@ -196,3 +216,104 @@ def test_hermite_query_checks_its_context():
     d.mul_(2.0)  # same storage, new values: the sort is stale
     with pytest.raises(ValueError):
         shm.HermiteQuery.apply(lut_t, d, bc)
+
+
+def plan_batch(r, dt):
+    """Uneven objects for the plan backward: face sizes 1..40, query counts
+    0..3000 (one object without queries), a 4-element gap between LUTs and a
+    5-row gap between query ranges, a few invalid directions."""
+    Ns = [1, 7, 40, 12, 3, 25, 9, 1]
+    qs = [200, 3000, 2500, 0, 1, 777, 1300, 3000]  # the last: ~125 queries per cell (dense tiles)
+    luts, objs, off, qb = [], [], 0, 0
+    for N, q in zip(Ns, qs):
+        lut = workloads.random_lut(N, r)
+        luts.append(np.concatenate([lut.reshape(-1), np.zeros(4, np.float32)]))
+        objs.append((off, N, qb, q))
+        off += lut.size + 4
+        qb += q + 5
+    flat = np.concatenate(luts)
+    dirs = workloads.uniform_dirs(qb, r)
+    dirs[[3, 250, 4000]] = 0.0
+    dirs[100, 1] = np.nan
+    return torch.as_tensor(flat).to(DEV, dt), objs, torch.as_tensor(dirs).to(DEV)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float16])
+def test_plan_backward_equals_per_object(dt):
+    """shm_plan_backward over objects of their own face sizes, LUT offsets
+    and query ranges: each object's dL/dLUT and its rows' dL/d dirs have the
+    bits of a one-object backward of that object's queries (FP16 LUTs: of
+    the decoded values); LUT gaps and rows outside every object untouched;
+    repeatable."""
+    r = rng(20)
+    lut, objs, d_t = plan_batch(r, dt)
+    rows = d_t.shape[0]
+    code = shm.SHM_F16 if dt == torch.float16 else shm.SHM_F32
+    g = torch.randn((rows, 4), device=DEV, generator=torch.Generator(device=DEV).manual_seed(20))
+    plan = shm.Plan(objs, code, shm.SHM_LAYOUT_TEXEL)
+    try:
+        plan.backward_sort(d_t)
+        sentinel = -3.0
+        gl = torch.full((lut.numel(),), sentinel, device=DEV)
+        gd = torch.full((rows, 3), sentinel, device=DEV)
+        plan.backward(lut, d_t, g, gl, gd)
+        gl2 = torch.full_like(gl, sentinel)
+        gd2 = torch.full_like(gd, sentinel)
+        plan.backward(lut, d_t, g, gl2, gd2)
+        torch.cuda.synchronize()
+        assert torch.equal(gl.view(torch.int32), gl2.view(torch.int32))
+        assert torch.equal(gd.view(torch.int32), gd2.view(torch.int32))
+        ref_l = torch.full_like(gl, sentinel)
+        ref_d = torch.full_like(gd, sentinel)
+        for (off, N, q0, q) in objs:
+            n = 6 * (N + 2) ** 2 * 4
+            lo = lut[off:off + n].float().reshape(1, 6, N + 2, N + 2, 4).contiguous()
+            if q == 0:
+                ref_l[off:off + n] = 0.0
+                continue
+            bc = shm.BackwardContext(N, 1, d_t[q0:q0 + q].contiguous(), q)
+            a, b = bc.backward(lo, g[q0:q0 + q].contiguous())
+            ref_l[off:off + n] = a.reshape(-1)
+            ref_d[q0:q0 + q] = b
+        torch.cuda.synchronize()
+        assert torch.equal(gl.view(torch.int32), ref_l.view(torch.int32))
+        assert torch.equal(gd.view(torch.int32), ref_d.view(torch.int32))
+        # only the direction gradient, then only the LUT gradient: same bits
+        gd3 = torch.full_like(gd, sentinel)
+        plan.backward(lut, d_t, g, None, gd3)
+        gl3 = torch.full_like(gl, sentinel)
+        plan.backward(lut, d_t, g, gl3, None)
+        torch.cuda.synchronize()
+        assert torch.equal(gd3.view(torch.int32), ref_d.view(torch.int32))
+        assert torch.equal(gl3.view(torch.int32), ref_l.view(torch.int32))
+    finally:
+        plan.close()
+
+
+def test_plan_backward_refusals():
+    """A CELL plan has no backward; overlapping LUTs or query ranges are
+    refused before anything is allocated or launched; a backward before its
+    sort is refused."""
+    r = rng(21)
+    lut, objs, d_t = plan_batch(r, torch.float32)
+    g = torch.zeros((d_t.shape[0], 4), device=DEV)
+    plan = shm.Plan(objs, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL)
+    with pytest.raises(shm.ShmError) as e:
+        plan.backward(lut, d_t, g, torch.empty_like(lut))
+    assert "backward_sort" in str(e.value)
+    plan.close()
+    cells = shm.Plan([(0, 4, 0, 10)], shm.SHM_F32, shm.SHM_LAYOUT_CELL)
+    with pytest.raises(shm.ShmError) as e:
+        cells.backward_sort(d_t)
+    assert e.value.code == shm.SHM_ERR_UNSUPPORTED
+    cells.close()
+    over_lut = shm.Plan([(0, 4, 0, 10), (100, 4, 10, 10)], shm.SHM_F32, shm.SHM_LAYOUT_TEXEL)
+    with pytest.raises(shm.ShmError) as e:
+        over_lut.backward_sort(d_t)
+    assert "overlap" in str(e.value)
+    over_lut.close()
+    over_q = shm.Plan([(0, 4, 0, 10), (6 * 36 * 4, 4, 5, 10)], shm.SHM_F32, shm.SHM_LAYOUT_TEXEL)
+    with pytest.raises(shm.ShmError) as e:
+        over_q.backward_sort(d_t)
+    assert "overlap" in str(e.value)
+    over_q.close()
