@@ -310,7 +310,9 @@ SHM_API int shm_plan_destroy(shm_plan* plan);
  * query ranges overlap (SHM_ERR_INVALID_ARG otherwise), builds the objects'
  * prefix arrays and allocates the sort buffers (44 B per query row up to the
  * last object's range, 4 B per cell of all objects); every call first waits
- * (host) for the plan's earlier launches, which may read the sort.
+ * (host) for the plan's earlier launches, which may read the sort, and
+ * finally for the sort itself (it reads back how many tiles hold a cell of
+ * more than 32 queries, which the backward sums by a kernel of their own).
  * shm_plan_backward then, on `stream`:
  *   lut        the objects' LUT (read for the direction gradient only)
  *   grad_out   [rows][4] upstream gradient dL/d(R, g), FP32

@@ -748,6 +748,16 @@ int shm_plan_backward_sort(shm_plan* plan, const float* dirs, hipStream_t stream
     if ((rc = plan_wait_launches(plan)) != SHM_OK) return rc;
     rc = launch_backward_sort_objects(plan->bwd, dirs, plan->bwd_ws, stream);
     if (rc) return rc;
+    // how many dense tiles the sort listed: the backward launches their
+    // kernel only when there are some, with a grid to match
+    plan->bwd.n_dense = 0;
+    if (plan->bwd.Q > 0 && plan->bwd.n_tiles > 0) {
+        uint32_t n_dense = 0;
+        SHM_HIP_CHECK(hipMemcpyAsync(&n_dense, backward_objects_dense_count(plan->bwd, plan->bwd_ws), sizeof n_dense,
+                                     hipMemcpyDeviceToHost, stream));
+        SHM_HIP_CHECK(hipStreamSynchronize(stream));
+        plan->bwd.n_dense = n_dense;
+    }
     plan->bwd_sorted = true;
     return plan_mark_launch(plan, stream);
 }

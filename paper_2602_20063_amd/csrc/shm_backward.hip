@@ -646,10 +646,12 @@ __device__ __forceinline__ void tile_dense_flag(const TileGeo& G, const uint32_t
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
-// workgroups of a dense-tile kernel: eight per compute unit, at most one per tile
+// workgroups of a dense-tile kernel whose tile count the host does not know:
+// one per compute unit (a launch that finds no dense tile stays cheap), at
+// most one per tile
 static inline int64_t dense_grid(int64_t n_tiles)
 {
-    return std::max<int64_t>(1, std::min<int64_t>(n_tiles, 8ll * device_cu_count()));
+    return std::max<int64_t>(1, std::min<int64_t>(n_tiles, (int64_t)device_cu_count()));
 }
 
 __global__ __launch_bounds__(BWD_THREADS) void k_tile_dense(int N, int tiles_per_face, const uint32_t* __restrict__ cs,
@@ -1003,6 +1005,12 @@ static void radix_sort_pass_all(const BwdLayout& W, char* base, hipStream_t stre
     }
 }
 
+const uint32_t* backward_objects_dense_count(const BwdObjectsHost& H, const void* ws)
+{
+    const BwdLayout W = bwd_layout_cells(H.Q, H.n_cells, H.n_tiles);
+    return reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(ws) + W.dense);
+}
+
 int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, void* ws, hipStream_t stream)
 {
     const BwdLayout W = bwd_layout_cells(H.Q, H.n_cells, H.n_tiles);
@@ -1055,9 +1063,12 @@ int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut,
                                W.Q, sgout);
             hipLaunchKernelGGL(k_bwd_fused_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B, W.Q,
                                sdirs, (const float*)sgout, perm, cs, (const uint8_t*)D.flag, grad_lut);
-            hipLaunchKernelGGL(k_bwd_fused_objects_dense, dim3((unsigned)dense_grid(H.n_tiles)), dim3(BWD_THREADS), 0,
-                               stream, B, W.Q, sdirs, (const float*)sgout, perm, cs, (const uint32_t*)D.count,
-                               (const uint32_t*)D.list, grad_lut);
+            // the plan read the dense-tile count back after its sort
+            if (H.n_dense > 0)
+                hipLaunchKernelGGL(k_bwd_fused_objects_dense,
+                                   dim3((unsigned)std::min<int64_t>(H.n_dense, 8ll * device_cu_count())),
+                                   dim3(BWD_THREADS), 0, stream, B, W.Q, sdirs, (const float*)sgout, perm, cs,
+                                   (const uint32_t*)D.count, (const uint32_t*)D.list, grad_lut);
         }
         SHM_LAUNCH_CHECK();
     }

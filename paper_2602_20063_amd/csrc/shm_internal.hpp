@@ -69,10 +69,12 @@ struct BwdObjectsHost {
     const int32_t* tile_obj = nullptr;   // object of each LUT-gradient tile
     const int32_t* qtile_obj = nullptr;  // object of each query tile
     int64_t n_obj = 0, Q = 0, n_cells = 0, n_tiles = 0, n_qtiles = 0;
+    int64_t n_dense = 0;  // dense tiles found by the last sort (read back by the plan)
 };
 int backward_tile_texels();   // texels per side of a LUT-gradient tile
 int backward_query_tile();    // queries per query tile of the object kernels
 size_t backward_objects_workspace_bytes(int64_t Q, int64_t n_cells, int64_t n_tiles);
+const uint32_t* backward_objects_dense_count(const BwdObjectsHost& H, const void* ws);  // device address
 int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, void* ws, hipStream_t stream);
 int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut, const float* dirs, const float* gout,
                             float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
