@@ -317,3 +317,22 @@ def test_plan_backward_refusals():
         over_q.backward_sort(d_t)
     assert "overlap" in str(e.value)
     over_q.close()
+
+
+def test_plan_backward_without_queries():
+    """Objects without queries: the sort has nothing to order, every object's
+    LUT gradient is zero and no direction row is written."""
+    objs = [(0, 4, 0, 0), (6 * 36 * 4 + 8, 2, 0, 0)]
+    n = objs[1][0] + 6 * 16 * 4
+    lut = torch.ones(n, device=DEV)
+    d_t = torch.zeros((1, 3), device=DEV)
+    plan = shm.Plan(objs, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL)
+    try:
+        plan.backward_sort(d_t)
+        gl = torch.full((n,), 5.0, device=DEV)
+        plan.backward(lut, d_t, torch.zeros((1, 4), device=DEV), gl, None)
+        torch.cuda.synchronize()
+        assert torch.all(gl[:6 * 36 * 4] == 0) and torch.all(gl[objs[1][0]:] == 0)
+        assert torch.all(gl[6 * 36 * 4:objs[1][0]] == 5.0)  # the gap between the LUTs
+    finally:
+        plan.close()

@@ -156,7 +156,7 @@ def fit_problem(N, Q, seed, zero=()):
     return lut, dirs, tv.float().contiguous(), tn.contiguous()
 
 
-@pytest.mark.parametrize("N,Q", [(16, 20011), (37, 50000)])
+@pytest.mark.parametrize("N,Q", [(16, 20011), (37, 50000), (3, 30011)])  # (3, 30011): ~300 queries per cell, dense tiles
 def test_fused_step_matches_three_kernel_step(N, Q):
     """The one-kernel fitting step against the three-kernel step (forward +
     loss gradient, LUT-only backward, Adam) from the same LUT, over 4 steps:
