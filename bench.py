@@ -577,17 +577,19 @@ def run_backward_fit():
     lut = torch.zeros((1, 6, N + 2, N + 2, 4), device=DEV)
     lut[..., 0] = 1.0
     t0 = time.time()
-    bctx = shm.BackwardContext(N, 1, dirs, Q)
+    bctx = shm.BackwardContext(N, 1, dirs, Q, check_dense=True)
     torch.cuda.synchronize()
     sort_ms = (time.time() - t0) * 1e3
+    dense_tiles = shm.shm_backward_dense_tiles(N, 1, Q, bctx.ws)
+    sr = bctx.sort_ready  # no dense tiles on this workload: no dense-tile launch
     out = torch.empty((Q, 4), device=DEV)
     g = torch.randn((Q, 4), device=DEV)
     fwd = lambda: shm.shm_query_value_grad(lut, shm.SHM_F32, 0, N, 1, dirs, Q, out)
     gl = torch.empty_like(lut)
     gd = torch.empty((Q, 3), device=DEV)
-    bwd = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, gd, bctx.ws, True)
-    bwd_lut = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, None, bctx.ws, True)
-    bwd_dirs = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, None, gd, bctx.ws, True)
+    bwd = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, gd, bctx.ws, sr)
+    bwd_lut = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, gl, None, bctx.ws, sr)
+    bwd_dirs = lambda: shm.shm_query_backward(lut, N, 1, dirs, Q, g, None, gd, bctx.ws, sr)
     fwd(); bwd()
     # error sample: a random LUT's gradients; the LUT gradient through the
     # adjoint identity (exact here: the outputs are linear in the LUT), the
@@ -610,7 +612,8 @@ def run_backward_fit():
     ms_bl = t_gpu(bwd_lut, 20)
     ms_bd = t_gpu(bwd_dirs, 20)
     lut_bytes = lut.numel() * 4
-    res = {"N": N, "queries": Q, "sort_first_call_ms": sort_ms, "sort_ms": ms_sort, "fwd_ms": ms_f, "bwd_ms": ms_b,
+    res = {"N": N, "queries": Q, "dense_tiles": dense_tiles, "sort_first_call_ms": sort_ms, "sort_ms": ms_sort,
+           "fwd_ms": ms_f, "bwd_ms": ms_b,
            "bwd_lut_only_ms": ms_bl, "bwd_dirs_only_ms": ms_bd,
            "bwd_over_fwd": ms_b / ms_f,
            "fwd_hbm_frac": (Q * 28 + lut_bytes) / ms_f / 1e6 / PEAK_HBM_GBS,

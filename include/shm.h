@@ -341,8 +341,21 @@ SHM_API int shm_plan_backward(shm_plan* plan, const void* lut, const float* dirs
  * that order and every texel adds the sums of its <= 4 adjacent cells in a
  * fixed order; no floating-point atomics.  shm_backward_sort builds the sort in the workspace; it stays
  * valid while dirs (and N, n_obj, q_per_obj) are unchanged, so a fitting
- * loop sorts once and passes sort_ready = 1 afterwards.
+ * loop sorts once and passes sort_ready = SHM_SORT_READY afterwards.
+ * A tile with a cell of more than 32 queries (dense) is summed by a kernel
+ * of its own; the sort lists such tiles.  sort_ready:
+ *   0                      sort dirs into the workspace first
+ *   SHM_SORT_READY         reuse the sort
+ *   SHM_SORT_READY_SPARSE  reuse the sort and launch no dense-tile kernel:
+ *                          the tile kernel sums every tile itself.  The
+ *                          result is correct either way (equal up to the
+ *                          order of the sums), but dense cells are summed
+ *                          slowly: pass it when shm_backward_dense_tiles
+ *                          returned 0 for this sort.
+ * Other values are rejected (SHM_ERR_INVALID_ARG).
  * ---------------------------------------------------------------------- */
+#define SHM_SORT_READY 1
+#define SHM_SORT_READY_SPARSE 2
 SHM_API size_t shm_backward_workspace(int32_t N, int64_t n_obj, int64_t q_per_obj);
 /* Cell key of every query: ((obj*6 + face)*(N+1) + j0)*(N+1) + i0, or
  * 0xFFFFFFFF for an invalid direction.  keys [n_obj*q_per_obj] uint32.
@@ -355,6 +368,11 @@ SHM_API int shm_backward_sort(int32_t N, int64_t n_obj, const float* dirs, int64
 SHM_API int shm_query_backward(const float* lut, int32_t N, int64_t n_obj, const float* dirs, int64_t q_per_obj,
                        const float* grad_out, float* grad_lut, float* grad_dirs, void* ws, size_t ws_bytes,
                        int32_t sort_ready, hipStream_t stream);
+/* The number of dense tiles the sort in ws listed (>= 0), or -1 with an
+ * error for bad arguments.  Waits (host) for `stream`, on which the sort was
+ * issued: call it once after shm_backward_sort, not per step. */
+SHM_API int64_t shm_backward_dense_tiles(int32_t N, int64_t n_obj, int64_t q_per_obj, const void* ws,
+                                         size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Ray casting against x(w) = c + R(w) w (Sec. 3.1, Eq. 1), one object.
@@ -550,8 +568,9 @@ SHM_API int shm_adam_step(float* param, const float* grad, float* m, float* v, i
  *   dirs, target_r, target_n, Q, w_value  as in shm_fit_loss_grad
  *   step, lr_value, lr_deriv, beta1, beta2, eps  as in shm_adam_step
  *   ws, ws_bytes  shm_backward_workspace(N, 1, Q) bytes, 256-byte aligned;
- *            sort_ready = 0 sorts dirs into it first, 1 reuses the sort a
- *            previous call (or shm_backward_sort(N, 1, dirs, Q)) left there
+ *            sort_ready = 0 sorts dirs into it first, SHM_SORT_READY reuses
+ *            the sort a previous call (or shm_backward_sort(N, 1, dirs, Q))
+ *            left there, SHM_SORT_READY_SPARSE as for shm_query_backward
  * Q = 0 is allowed: the gradient is zero and Adam still moves the moments. */
 SHM_API int shm_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int32_t N, const float* dirs,
                          const float* target_r, const float* target_n, int64_t Q, float w_value, int64_t step,

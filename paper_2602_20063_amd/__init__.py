@@ -31,6 +31,7 @@ SHM_SIGNED = 1
 SHM_CELL_LUT = 2
 SHM_PROBE_DIRS, SHM_PROBE_OUT = 1, 2
 SHM_BAKE_NOALLOC_MAX_BYTES = 32 << 20  # scratch of shm_bake_sh_lut_noalloc
+SHM_SORT_READY, SHM_SORT_READY_SPARSE = 1, 2
 
 
 class ShmError(RuntimeError):
@@ -87,6 +88,7 @@ SIGNATURES = {
     "shm_cell_keys": (ctypes.c_int, [_I32, _I64, _VP, _I64, _VP, _VP]),
     "shm_backward_sort": (ctypes.c_int, [_I32, _I64, _VP, _I64, _VP, _SZ, _VP]),
     "shm_query_backward": (ctypes.c_int, [_VP, _I32, _I64, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _I32, _VP]),
+    "shm_backward_dense_tiles": (_I64, [_I32, _I64, _I64, _VP, _SZ, _VP]),
     "shm_trace_radial": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float, _VP, _VP,
                                         _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP]),
     "shm_trace_radial_ex": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_float), ctypes.c_float,
@@ -337,6 +339,19 @@ def shm_backward_sort(N, n_obj, dirs, q_per_obj, ws, stream=None):
                                           _stream(stream)))
 
 
+def _sort_ready(x):
+    """sort_ready as the library takes it: False/True -> 0/SHM_SORT_READY,
+    integers unchanged (0, SHM_SORT_READY or SHM_SORT_READY_SPARSE)."""
+    return int(bool(x)) if isinstance(x, bool) else int(x)
+
+
+def shm_backward_dense_tiles(N, n_obj, q_per_obj, ws, stream=None):
+    n = lib().shm_backward_dense_tiles(N, n_obj, q_per_obj, _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    if n < 0:
+        raise ShmError(SHM_ERR_INVALID_ARG, lib().shm_last_error().decode())
+    return int(n)
+
+
 def shm_query_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_dirs, ws, sort_ready, stream=None):
     Q = max(n_obj, 0) * max(q_per_obj, 0)
     lb = _lut_bytes(N, SHM_LAYOUT_TEXEL, SHM_F32, n_obj)
@@ -347,7 +362,7 @@ def shm_query_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_
     _fits(grad_dirs, Q * 12, "grad_dirs")
     return _check(lib().shm_query_backward(_ptr(lut), N, n_obj, _ptr(dirs), q_per_obj, _ptr(grad_out), _ptr(grad_lut),
                                            _ptr(grad_dirs), _ptr(ws), ws.numel() * ws.element_size(),
-                                           1 if sort_ready else 0, _stream(stream)))
+                                           _sort_ready(sort_ready), _stream(stream)))
 
 
 def _fits_rays(P, ray_o, ray_d, t_out, out, normal, sign=None, evals=None):
@@ -466,7 +481,7 @@ def shm_fit_step(lut_in, lut_out, m, v, N, dirs, target_r, target_n, Q, w_value,
     return _check(lib().shm_fit_step(_ptr(lut_in), _ptr(lut_out), _ptr(m), _ptr(v), N, _ptr(dirs), _ptr(target_r),
                                      _ptr(target_n), Q, float(w_value), step, float(lr_value), float(lr_deriv),
                                      float(beta1), float(beta2), float(eps), _ptr(ws), ws.numel() * ws.element_size(),
-                                     int(bool(sort_ready)), _stream(stream)))
+                                     _sort_ready(sort_ready), _stream(stream)))
 
 
 class LutFit:
@@ -489,7 +504,7 @@ class LutFit:
         self.w_value, self.lr_value, self.lr_deriv = w_value, lr_value, lr_deriv
         self.betas, self.eps = betas, eps
         self.fused = fused
-        self.bctx = BackwardContext(self.N, 1, dirs, self.Q, stream)
+        self.bctx = BackwardContext(self.N, 1, dirs, self.Q, stream, check_dense=True)
         dev = lut.device
         self.bufs = [lut, torch.empty_like(lut)] if fused else [lut]
         self.cur = 0
@@ -526,13 +541,14 @@ class LutFit:
         if self.fused:
             nxt = 1 - self.cur
             shm_fit_step(self.bufs[self.cur], self.bufs[nxt], self.m, self.v, N, self.dirs, self.tr, self.tn, Q,
-                         self.w_value, self.t, self.lr_value, self.lr_deriv, b1, b2, self.eps, self.bctx.ws, True,
-                         stream)
+                         self.w_value, self.t, self.lr_value, self.lr_deriv, b1, b2, self.eps, self.bctx.ws,
+                         self.bctx.sort_ready, stream)
             self.cur = nxt
             return
         lut = self.lut
         shm_fit_forward_loss_grad(lut, N, self.dirs, self.tr, self.tn, Q, self.w_value, self.g, stream)
-        shm_query_backward(lut, N, 1, self.dirs, Q, self.g, self.grad, None, self.bctx.ws, True, stream)
+        shm_query_backward(lut, N, 1, self.dirs, Q, self.g, self.grad, None, self.bctx.ws, self.bctx.sort_ready,
+                           stream)
         shm_adam_step(lut, self.grad, self.m, self.v, lut.numel() // 4, self.t, self.lr_value, self.lr_deriv, b1, b2,
                       self.eps, stream)
 
@@ -894,9 +910,14 @@ def query_scaled(lut, dirs, scale=1.0, signed=False, layout=None, normals=True, 
 
 class BackwardContext:
     """Workspace + cached sort for repeated backward passes over fixed
-    directions (a fitting loop)."""
+    directions (a fitting loop).
 
-    def __init__(self, N, n_obj, dirs, q_per_obj, stream=None):
+    check_dense=True reads back (one wait) whether the sort listed dense
+    tiles (cells of more than 32 queries); if it listed none, the backward
+    calls launch no dense-tile kernel.  Worth it when the context serves many
+    calls."""
+
+    def __init__(self, N, n_obj, dirs, q_per_obj, stream=None, check_dense=False):
         self.N, self.n_obj, self.q_per_obj = N, n_obj, q_per_obj
         self.dirs = dirs
         # the sort is valid for exactly these direction values
@@ -904,12 +925,15 @@ class BackwardContext:
         nbytes = shm_backward_workspace(N, n_obj, q_per_obj)
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dirs.device)
         shm_backward_sort(N, n_obj, dirs, q_per_obj, self.ws, stream)
+        self.sort_ready = SHM_SORT_READY
+        if check_dense and shm_backward_dense_tiles(N, n_obj, q_per_obj, self.ws, stream) == 0:
+            self.sort_ready = SHM_SORT_READY_SPARSE
 
     def backward(self, lut, grad_out, want_lut=True, want_dirs=True, stream=None):
         gl = torch.empty_like(lut) if want_lut else None
         gd = torch.empty((self.dirs.shape[0], 3), dtype=torch.float32, device=lut.device) if want_dirs else None
         shm_query_backward(lut, self.N, self.n_obj, self.dirs, self.q_per_obj, grad_out.contiguous(), gl, gd, self.ws,
-                           True, stream)
+                           self.sort_ready, stream)
         return gl, gd
 
 

@@ -58,7 +58,8 @@ size_t backward_workspace_bytes(int N, int64_t n_obj, int64_t q_per_obj);
 int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream);
 int launch_cell_keys(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, uint32_t* keys, hipStream_t stream);
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
-                    float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream);
+                    float* grad_lut, float* grad_dirs, void* ws, bool skip_dense, hipStream_t stream);
+const uint32_t* backward_dense_count(int N, int64_t n_obj, int64_t q_per_obj, const void* ws);
 int launch_trace(const void* lut, int dtype, int N, const float* center, float rmax, float scale, int flags,
                  float px_focal, float eps_px, const float* ray_o, const float* ray_d, int64_t P, int image_width,
                  const float* bound_map, int bound_blocks, int n_march, int n_bisect, int n_newton, float* t_out,
@@ -83,7 +84,7 @@ int launch_gather_footprints(const void* lut, int dtype, int layout, int N, int6
                              int64_t q_per_obj, float* foot, hipStream_t stream);
 int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
                     const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
-                    float b2, float eps, void* ws, hipStream_t stream);
+                    float b2, float eps, void* ws, bool skip_dense, hipStream_t stream);
 
 int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int req_bytes,
                         uint32_t seed, int flags, const float* dirs, float* out, hipStream_t stream);
@@ -838,8 +839,28 @@ int shm_query_backward(const float* lut, int32_t N, int64_t n_obj, const float* 
     if (Q > 0 && (!dirs || !grad_out)) return fail(SHM_ERR_INVALID_ARG, "backward: null dirs or grad_out");
     if (!aligned(lut, 16) || (grad_lut && !aligned(grad_lut, 16)) || (grad_out && !aligned(grad_out, 16)))
         return fail(SHM_ERR_INVALID_ARG, "backward: lut, grad_lut and grad_out must be 16-byte aligned");
+    if (sort_ready < 0 || sort_ready > SHM_SORT_READY_SPARSE)
+        return fail(SHM_ERR_INVALID_ARG, "backward: sort_ready must be 0, SHM_SORT_READY or SHM_SORT_READY_SPARSE");
     if (!sort_ready && (rc = launch_backward_sort(N, n_obj, dirs, q_per_obj, ws, stream)) != SHM_OK) return rc;
-    return launch_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_dirs, ws, stream);
+    return launch_backward(lut, N, n_obj, dirs, q_per_obj, grad_out, grad_lut, grad_dirs, ws,
+                           sort_ready == SHM_SORT_READY_SPARSE, stream);
+}
+
+int64_t shm_backward_dense_tiles(int32_t N, int64_t n_obj, int64_t q_per_obj, const void* ws, size_t ws_bytes,
+                                 hipStream_t stream)
+{
+    clear_error();
+    if (check_bwd(N, n_obj, q_per_obj, ws, ws_bytes) != SHM_OK) return -1;
+    if (n_obj * q_per_obj == 0) return 0;  // the sort lists nothing without queries
+    uint32_t count = 0;
+    hipError_t e = hipMemcpyAsync(&count, backward_dense_count(N, n_obj, q_per_obj, ws), sizeof(count),
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        fail(SHM_ERR_HIP, "backward_dense_tiles: %s", hipGetErrorString(e));
+        return -1;
+    }
+    return (int64_t)count;
 }
 
 // ---------------------------------------------------------------------------
@@ -1040,9 +1061,11 @@ int shm_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int32_
         for (int j = i + 1; j < 4; ++j)
             if (ranges_overlap(bufs[i], bufs[j], bytes))
                 return fail(SHM_ERR_INVALID_ARG, "fit_step: lut_in, lut_out, m and v must not overlap");
+    if (sort_ready < 0 || sort_ready > SHM_SORT_READY_SPARSE)
+        return fail(SHM_ERR_INVALID_ARG, "fit_step: sort_ready must be 0, SHM_SORT_READY or SHM_SORT_READY_SPARSE");
     if (!sort_ready && Q > 0 && (rc = launch_backward_sort(N, 1, dirs, Q, ws, stream)) != SHM_OK) return rc;
     return launch_fit_step(lut_in, lut_out, m, v, N, dirs, target_r, target_n, Q, w_value, step, lr_value, lr_deriv,
-                           beta1, beta2, eps, ws, stream);
+                           beta1, beta2, eps, ws, sort_ready == SHM_SORT_READY_SPARSE, stream);
 }
 
 // ---------------------------------------------------------------------------

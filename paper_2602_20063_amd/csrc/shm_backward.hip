@@ -1084,8 +1084,13 @@ int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut,
     return SHM_OK;
 }
 
+const uint32_t* backward_dense_count(int N, int64_t n_obj, int64_t q_per_obj, const void* ws)
+{
+    return reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(ws) + bwd_layout(N, n_obj, q_per_obj).dense);
+}
+
 int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, const float* gout,
-                    float* grad_lut, float* grad_dirs, void* ws, hipStream_t stream)
+                    float* grad_lut, float* grad_dirs, void* ws, bool skip_dense, hipStream_t stream)
 {
     const BwdLayout W = bwd_layout(N, n_obj, q_per_obj);
     char* base = reinterpret_cast<char*>(ws);
@@ -1113,11 +1118,15 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     // (the two compete for the same units: the total work sets the time)
     if (grad_lut) {
         const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
+        // skip_dense: the sparse kernel sums every tile itself (any number of
+        // queries per cell is correct there, only slower)
         hipLaunchKernelGGL((k_bwd_fused<false>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut, N,
-                           texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, (const uint8_t*)D.flag, grad_lut, FitArgs{});
-        hipLaunchKernelGGL((k_bwd_fused_dense<false>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0, stream,
-                           lut, N, texel_elems(N), W.Q, dirs, gout, perm, cs, tpf, (const uint32_t*)D.count,
-                           (const uint32_t*)D.list, grad_lut, FitArgs{});
+                           texel_elems(N), W.Q, dirs, gout, perm, cs, tpf,
+                           skip_dense ? nullptr : (const uint8_t*)D.flag, grad_lut, FitArgs{});
+        if (!skip_dense)
+            hipLaunchKernelGGL((k_bwd_fused_dense<false>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0,
+                               stream, lut, N, texel_elems(N), W.Q, dirs, gout, perm, cs, tpf,
+                               (const uint32_t*)D.count, (const uint32_t*)D.list, grad_lut, FitArgs{});
         SHM_LAUNCH_CHECK();
     }
     if (grad_dirs) {
@@ -1130,7 +1139,7 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
 
 int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int N, const float* dirs, const float* tr,
                     const float* tn, int64_t Q, float w_value, int64_t step, float lr_value, float lr_deriv, float b1,
-                    float b2, float eps, void* ws, hipStream_t stream)
+                    float b2, float eps, void* ws, bool skip_dense, hipStream_t stream)
 {
     const BwdLayout W = bwd_layout(N, 1, Q);
     char* base = reinterpret_cast<char*>(ws);
@@ -1151,8 +1160,8 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
     const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
     hipLaunchKernelGGL((k_bwd_fused<true>), dim3((unsigned)tiles), dim3(BWD_THREADS), 0, stream, lut_in, N,
                        texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf,
-                       Q > 0 ? (const uint8_t*)D.flag : nullptr, (float*)nullptr, fa);
-    if (Q > 0)
+                       Q > 0 && !skip_dense ? (const uint8_t*)D.flag : nullptr, (float*)nullptr, fa);
+    if (Q > 0 && !skip_dense)
         hipLaunchKernelGGL((k_bwd_fused_dense<true>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0, stream,
                            lut_in, N, texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf,
                            (const uint32_t*)D.count, (const uint32_t*)D.list, (float*)nullptr, fa);

@@ -93,6 +93,19 @@ def test_backward_and_trace_validation():
     assert call("shm_backward_sort", 8, 1, p, 100, p, 10, None) == shm.SHM_ERR_WORKSPACE
     assert call("shm_backward_sort", 0, 1, p, 100, p, 1 << 30, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_backward_sort", 8, 1, p, 100, ctypes.c_void_p(300), 1 << 30, None) == shm.SHM_ERR_INVALID_ARG
+    # sort_ready takes 0, SHM_SORT_READY or SHM_SORT_READY_SPARSE only
+    qb = lambda sr: call("shm_query_backward", p, 8, 1, p, 100, p, p, p, p, 1 << 30, sr, None)
+    for sr in (-1, 3):
+        assert qb(sr) == shm.SHM_ERR_INVALID_ARG
+        assert "sort_ready" in shm.lib().shm_last_error().decode()
+    # the dense-tile count: nothing to read without queries, -1 for bad arguments
+    dt = lambda *a: shm.lib().shm_backward_dense_tiles(*a)
+    assert dt(8, 1, 0, p, 1 << 30, None) == 0
+    assert dt(8, 0, 100, p, 1 << 30, None) == 0
+    assert dt(0, 1, 100, p, 1 << 30, None) == -1
+    assert dt(8, 1, 100, p, 10, None) == -1
+    assert dt(8, 1, 100, ctypes.c_void_p(300), 1 << 30, None) == -1
+    assert "workspace" in shm.lib().shm_last_error().decode()
     c = (ctypes.c_float * 3)(0, 0, 0)
     assert call("shm_trace_radial", p, 0, 8, c, ctypes.c_float(-1.0), p, p, 10, 20, 8, 3, p, p, None, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_trace_radial", p, 0, 8, c, ctypes.c_float(1.0), p, p, 10, 40, 20, 10, p, p, None, None) == shm.SHM_ERR_INVALID_ARG
@@ -220,8 +233,10 @@ def test_fit_step_validation():
     ws = ctypes.c_void_p(16 << 20)
     d = ctypes.c_void_p(32 << 20)
     ok = (1e-3, 1e-3, 0.9, 0.999, 1e-8)
-    fs = lambda lin, lout, mm, vv, n=N, q=Q, wv=1.0, step=1, hp=ok, w=ws, wb=ws_bytes, dd=d: call(
-        "shm_fit_step", lin, lout, mm, vv, n, dd, dd, dd, q, wv, step, *hp, w, wb, 1, None)
+    fs = lambda lin, lout, mm, vv, n=N, q=Q, wv=1.0, step=1, hp=ok, w=ws, wb=ws_bytes, dd=d, sr=1: call(
+        "shm_fit_step", lin, lout, mm, vv, n, dd, dd, dd, q, wv, step, *hp, w, wb, sr, None)
+    assert fs(a, b, m, v, sr=3) == shm.SHM_ERR_INVALID_ARG
+    assert fs(a, b, m, v, sr=-1) == shm.SHM_ERR_INVALID_ARG
     assert fs(a, a, m, v) == shm.SHM_ERR_INVALID_ARG                                   # in place
     assert fs(a, ctypes.c_void_p((1 << 20) + lut_bytes - 16), m, v) == shm.SHM_ERR_INVALID_ARG  # overlap
     assert fs(a, b, m, m) == shm.SHM_ERR_INVALID_ARG

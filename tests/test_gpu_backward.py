@@ -153,6 +153,40 @@ def test_backward_dense_cells(N, Q):
     assert (np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, floor)).max() < DIRS_TOL
 
 
+@pytest.mark.parametrize("N,Q", [(5, 60000), (64, 30000)])
+def test_backward_sort_ready_sparse(N, Q):
+    """SHM_SORT_READY_SPARSE launches no dense-tile kernel: the tile kernel
+    sums every tile.  With dense tiles listed (N = 5, thousands of queries per
+    cell) the result still matches the oracle; with none listed (N = 64, about
+    one query per cell) it is the same bits as SHM_SORT_READY."""
+    r = rng(50 + N)
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(Q, r)
+    g = r.standard_normal((Q, 4)).astype(np.float32)
+    lut_t, d_t, g_t = gpu(lut), gpu(dirs), gpu(g)
+    bc = shm.BackwardContext(N, 1, d_t, Q, check_dense=True)
+    n_dense = shm.shm_backward_dense_tiles(N, 1, Q, bc.ws)
+    print('N %d Q %d dense tiles %d' % (N, Q, n_dense), flush=True)
+    assert (n_dense > 0) == (N == 5)
+    assert bc.sort_ready == (shm.SHM_SORT_READY if n_dense else shm.SHM_SORT_READY_SPARSE)
+    outs = {}
+    for sr in (shm.SHM_SORT_READY, shm.SHM_SORT_READY_SPARSE):
+        gl = torch.empty_like(lut_t)
+        gd = torch.empty((Q, 3), device=DEV)
+        shm.shm_query_backward(lut_t, N, 1, d_t, Q, g_t, gl, gd, bc.ws, sr)
+        torch.cuda.synchronize()
+        outs[sr] = (gl.cpu().numpy(), gd.cpu().numpy())
+    a, b = outs[shm.SHM_SORT_READY], outs[shm.SHM_SORT_READY_SPARSE]
+    assert np.array_equal(a[1], b[1])  # the direction gradient does not use the tiles
+    if n_dense == 0:
+        assert np.array_equal(a[0], b[0])
+    rl, _ = oracle.backward(lut, dirs, g)
+    scale = np.abs(rl).max()
+    for gl, _ in (a, b):
+        print('grad_lut error %.3e' % (np.abs(gl - rl).max() / scale))
+        assert np.abs(gl - rl).max() / scale < LUT_TOL
+
+
 @pytest.mark.parametrize("N", [100, 512])
 def test_backward_three_radix_passes(N):
     """Cell keys above 2^16 take three 8-bit radix passes (N >= 105 for one
