@@ -301,6 +301,17 @@ def main():
         plan.probe(lut16, B["dirs"], outb)
         torch.cuda.synchronize()
         plan.close()
+        del lut16, outb
+        # one backward of the batch's objects (FP32 TEXEL LUTs): sort, then
+        # both gradients
+        objs_t = [(int(B["texel_off"][o]), Nn, q0, q) for o, (_, Nn, q0, q) in enumerate(B["objs"])]
+        plan_t = shm.Plan(objs_t, shm.SHM_F32, shm.SHM_LAYOUT_TEXEL)
+        plan_t.backward_sort(B["dirs"])
+        g_b = torch.randn((B["Qtot"], 4), device=DEV, generator=torch.Generator(device=DEV).manual_seed(5))
+        plan_t.backward(B["lut_tex"], B["dirs"], g_b, torch.empty_like(B["lut_tex"]),
+                        torch.empty((B["Qtot"], 3), device=DEV))
+        torch.cuda.synchronize()
+        plan_t.close()
         print(json.dumps({"counters_run": True, "query_launches": 3, "copy_bytes": 1 << 30}))
         return
 

@@ -394,11 +394,15 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     const uint8_t skip = skip_flag != nullptr ? *skip_flag : 0;
     // one query's weights per lane, later the cell sums: corner-major, so that
     // the 16-byte accesses of consecutive lanes fall on consecutive banks
-    __shared__ float4 slot[4][BWD_THREADS];
+    // dense tiles pad each corner's row by one float4 every 16 slots (and
+    // the rows by 4): the run sums below then read 64 distinct banks per wave
+    constexpr int SROW = DENSE ? BWD_THREADS + BWD_THREADS / 16 + 4 : BWD_THREADS;
+    __shared__ float4 slot_m[4 * SROW];
+    auto slot = [&](int k, int s) -> float4& { return slot_m[k * SROW + (DENSE ? s + (s >> 4) : s)]; };
     __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
     __shared__ int64_t row_len[BC];          // queries in each cell row's range
     __shared__ int64_t row_off[BC + 1];      // offsets of the rows in the concatenated list
-    __shared__ int slot_cell[DENSE ? BWD_THREADS : 1];  // dense tiles: the tile cell of each slot's query
+    __shared__ uint64_t run_end[DENSE ? BWD_THREADS / 64 : 1];  // dense tiles: per wave, the slots that end a run
     const int N = G.N;
     const int C = N + 1, P = N + 2;
     const int p0 = G.p0, q0 = G.q0;
@@ -499,6 +503,7 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
         const int64_t q_next = query_at(base + BWD_THREADS + tid, r_next, v_next);
         // list positions base + tid < total hold a query and fill their
         // slot; the reduction below reads no other slot
+        int my_cell = -1;  // dense tiles: the tile cell of this lane's query, -1 for none
         if (v_cur) {
             const Loc L = locate(x, y, z, N);  // the cell of row r_cur (keys come from the same decision)
             if constexpr (FIT) {
@@ -514,11 +519,16 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
                 float4 w[4];
                 query_weights(gq.x, Nf * kk2 * gS, Nf * kk2 * gT, basis1(L.s), basis1(L.t), w);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) slot[k][tid] = w[k];
+                for (int k = 0; k < 4; ++k) slot(k, tid) = w[k];
             }
-            if constexpr (DENSE) slot_cell[tid] = r_cur * BC + (L.i0 - (p0 - 1));
-        } else if constexpr (DENSE) {
-            slot_cell[tid] = -1;
+            if constexpr (DENSE) my_cell = r_cur * BC + (L.i0 - (p0 - 1));
+        }
+        if constexpr (DENSE) {
+            // slot tid ends a run when the next slot holds another cell (or
+            // none) or a chunk of 16 slots ends; chunks do not cross waves
+            const int nb = __shfl_down(my_cell, 1);
+            const uint64_t m = __ballot((tid & 15) == 15 || nb != my_cell);
+            if ((tid & 63) == 0) run_end[tid >> 6] = m;
         }
         // unconditional: q_next is a valid index even past the list's end
         x = dirs[3 * q_next];
@@ -535,7 +545,7 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
                 for (int k2 = lo; k2 < hi; ++k2) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const float4 v = slot[k][k2];
+                        const float4 v = slot(k, k2);
                         acc[k].x += v.x;
                         acc[k].y += v.y;
                         acc[k].z += v.z;
@@ -550,16 +560,19 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
                 // per chunk instead of one per query)
                 {
                     const int chunk = tid >> 4, ch = tid & 15;
-                    float* col = reinterpret_cast<float*>(&slot[ch >> 2][0]) + (ch & 3);
+                    float* col = reinterpret_cast<float*>(&slot(ch >> 2, chunk * 16)) + (ch & 3);
+                    const uint32_t ends = (uint32_t)(run_end[chunk >> 2] >> ((chunk & 3) * 16));
+                    float v[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) v[i] = col[4 * i];
+                    // the running sum is stored at every slot; only the run
+                    // ends are read
                     float run = 0.0f;
-#pragma unroll 1
+#pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        const int sp = chunk * 16 + i;
-                        run += col[4 * sp];
-                        if (i == 15 || slot_cell[sp + 1] != slot_cell[sp]) {
-                            col[4 * sp] = run;
-                            run = 0.0f;
-                        }
+                        run += v[i];
+                        col[4 * i] = run;
+                        run = ((ends >> i) & 1u) ? 0.0f : run;
                     }
                 }
                 lds_barrier();
@@ -567,7 +580,7 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
                     const int pe = min(hi, (p | 15) + 1) - 1;  // the end of the run holding p
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const float4 v = slot[k][pe];
+                        const float4 v = slot(k, pe);
                         acc[k].x += v.x;
                         acc[k].y += v.y;
                         acc[k].z += v.z;
@@ -591,7 +604,7 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
         vv = fa.v[t_i];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) slot[k][tid] = acc[k];
+    for (int k = 0; k < 4; ++k) slot(k, tid) = acc[k];
     lds_barrier();
     // texel (p0 + tx, q0 + ty) is corner (1,1) of cell (tx, ty), (0,1) of
     // (tx+1, ty), (1,0) of (tx, ty+1) and (0,0) of (tx+1, ty+1) in tile cells
@@ -603,7 +616,7 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
         for (int dj = 1; dj >= 0; --dj)
 #pragma unroll
             for (int di = 1; di >= 0; --di) {
-                const float4 v = slot[dj * 2 + di][(ty + 1 - dj) * BC + (tx + 1 - di)];
+                const float4 v = slot(dj * 2 + di, (ty + 1 - dj) * BC + (tx + 1 - di));
                 a.x += v.x;
                 a.y += v.y;
                 a.z += v.z;
