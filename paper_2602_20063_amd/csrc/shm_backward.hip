@@ -399,9 +399,10 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     constexpr int SROW = DENSE ? BWD_THREADS + BWD_THREADS / 16 + 4 : BWD_THREADS;
     __shared__ float4 slot_m[4 * SROW];
     auto slot = [&](int k, int s) -> float4& { return slot_m[k * SROW + (DENSE ? s + (s >> 4) : s)]; };
-    __shared__ int64_t row_start[BC];        // first sorted position of each cell row's range
-    __shared__ int64_t row_len[BC];          // queries in each cell row's range
-    __shared__ int64_t row_off[BC + 1];      // offsets of the rows in the concatenated list
+    // sorted positions and list offsets are below Q < 2^32 - 1: 32 bits
+    __shared__ uint32_t row_start[BC];       // first sorted position of each cell row's range
+    __shared__ uint32_t row_len[BC];         // queries in each cell row's range
+    __shared__ uint32_t row_off[BC + 1];     // offsets of the rows in the concatenated list
     __shared__ uint64_t run_end[DENSE ? BWD_THREADS / 64 : 1];  // dense tiles: per wave, the slots that end a run
     const int N = G.N;
     const int C = N + 1, P = N + 2;
@@ -415,7 +416,8 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
     // with no queries the sort wrote no segment starts: every list is empty
     const bool cell_ok = Q > 0 && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
-    int64_t cs_lo = 0, cs_hi = 0;
+    const uint32_t Qu = (uint32_t)Q;
+    uint32_t cs_lo = 0, cs_hi = 0;
     if (cell_ok) {
         const int64_t c = cbase + (int64_t)j0c * C + i0c;
         cs_lo = cs[c];
@@ -423,11 +425,11 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     }
     if (tid < BC) {
         const int j0 = q0 - 1 + tid;
-        int64_t a = 0, e = 0;
+        uint32_t a = 0, e = 0;
         if (Q > 0 && j0 >= 0 && j0 <= N) {
             const int64_t c0 = cbase + (int64_t)j0 * C;
-            a = min((int64_t)cs[c0 + i_lo], Q);
-            e = min(max((int64_t)cs[c0 + i_hi + 1], a), Q);
+            a = min(cs[c0 + i_lo], Qu);
+            e = min(max(cs[c0 + i_hi + 1], a), Qu);
         }
         row_start[tid] = a;
         row_len[tid] = e - a;
@@ -435,20 +437,20 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     lds_barrier();
     if (skip) return;  // uniform over the workgroup
     if (tid <= BC) {  // exclusive prefix: independent reads, no serial chain
-        int64_t o = 0;
+        uint32_t o = 0;
         for (int k = 0; k < tid; ++k) o += row_len[k];
         row_off[tid] = o;
     }
     lds_barrier();
-    int64_t seg_lo = 0, seg_hi = 0;
+    uint32_t seg_lo = 0, seg_hi = 0;
     if (cell_ok) {
-        const int64_t rs = row_start[cj], len = row_off[cj + 1] - row_off[cj];
-        const int64_t a = min(max(cs_lo - rs, (int64_t)0), len);
-        const int64_t e = min(max(cs_hi - rs, a), len);
+        const uint32_t rs = row_start[cj], len = row_off[cj + 1] - row_off[cj];
+        const uint32_t a = min(cs_lo > rs ? cs_lo - rs : 0u, len);
+        const uint32_t e = min(max(cs_hi > rs ? cs_hi - rs : 0u, a), len);
         seg_lo = row_off[cj] + a;
         seg_hi = row_off[cj] + e;
     }
-    const int64_t total = row_off[BC];
+    const uint32_t total = row_off[BC];
     const float Nf = (float)N;
     float3 M, S, T;
     frame_of(face, M, S, T);
@@ -461,17 +463,16 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     // a position clamped into the list and the entry past the end is marked
     // by the flag alone: no branch, so the loaded index is not waited for
     // until its first use, a round's weights later.
-    auto query_at = [&](int64_t g, int& r, bool& valid) -> int64_t {
-        valid = g < total;
-        const int64_t gc = valid ? g : total - 1;
+    auto query_at = [&](int64_t g, int& r, bool& valid) -> uint32_t {
+        valid = g < (int64_t)total;
+        const uint32_t gc = valid ? (uint32_t)g : total - 1;
         r = 0;
 #pragma unroll
         for (int step = BC / 2; step >= 1; step >>= 1)
             if (row_off[r + step] <= gc) r += step;
-        int64_t pos = row_start[r] + (gc - row_off[r]);
-        pos = pos < 0 ? 0 : (pos >= Q ? Q - 1 : pos);
+        const uint32_t pos = min(row_start[r] + (gc - row_off[r]), Qu - 1);
         if constexpr (SORTED) return pos;
-        else return (int64_t)perm[pos];
+        else return perm[pos];
     };
     // the upstream gradient of query q, or for the fitting step its targets
     // (R*, n*), from which the lane computes the upstream gradient
@@ -487,20 +488,20 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     // position would not name a query)
     int r_cur = 0;
     bool v_cur = false;
-    int64_t q_cur = 0;
+    uint32_t q_cur = 0;
     float x = 0.0f, y = 0.0f, z = 0.0f;
     float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
     if (total > 0) {
         q_cur = query_at(tid, r_cur, v_cur);
-        x = dirs[3 * q_cur];
-        y = dirs[3 * q_cur + 1];
-        z = dirs[3 * q_cur + 2];
+        x = dirs[3 * (size_t)q_cur];
+        y = dirs[3 * (size_t)q_cur + 1];
+        z = dirs[3 * (size_t)q_cur + 2];
         gq = upstream_in(q_cur);
     }
     for (int64_t base = 0; base < total; base += BWD_THREADS) {
         int r_next;
         bool v_next;
-        const int64_t q_next = query_at(base + BWD_THREADS + tid, r_next, v_next);
+        const uint32_t q_next = query_at(base + BWD_THREADS + tid, r_next, v_next);
         // list positions base + tid < total hold a query and fill their
         // slot; the reduction below reads no other slot
         int my_cell = -1;  // dense tiles: the tile cell of this lane's query, -1 for none
@@ -531,16 +532,19 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
             if ((tid & 63) == 0) run_end[tid >> 6] = m;
         }
         // unconditional: q_next is a valid index even past the list's end
-        x = dirs[3 * q_next];
-        y = dirs[3 * q_next + 1];
-        z = dirs[3 * q_next + 2];
+        x = dirs[3 * (size_t)q_next];
+        y = dirs[3 * (size_t)q_next + 1];
+        z = dirs[3 * (size_t)q_next + 2];
         gq = upstream_in(q_next);
         q_cur = q_next;
         r_cur = r_next;
         v_cur = v_next;
         {
             lds_barrier();
-            const int lo = (int)(max(seg_lo, base) - base), hi = (int)(min(seg_hi, base + BWD_THREADS) - base);
+            // the segment's slots in this round (base < total < 2^32)
+            const uint32_t b = (uint32_t)base;
+            const int lo = (int)min(seg_lo > b ? seg_lo - b : 0u, (uint32_t)BWD_THREADS);
+            const int hi = (int)min(seg_hi > b ? seg_hi - b : 0u, (uint32_t)BWD_THREADS);
             if constexpr (!DENSE) {
                 for (int k2 = lo; k2 < hi; ++k2) {
 #pragma unroll
@@ -763,12 +767,20 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_dense(const float* __
 // Direction gradients of DIRS_THREADS consecutive queries (block blk), in the
 // queries' own order: a direction's gradient involves no other query, so it
 // needs neither the sort nor LDS.  NaN for an invalid direction.
+//
+// The object of query q is floor(q / q_per_obj), taken without a division:
+// for q < 2^32 and 2 <= d < 2^32, m = floor((2^64 - 1) / d) + 1 exceeds
+// 2^64 / d by at most 1 (d a power of two: by 0), so q m / 2^64 exceeds q / d
+// by less than q / 2^64 < 1 / d, too little to reach the next integer; its
+// integer part (the high word of the product) is floor(q / d).  d = 1 is
+// passed as m = 0.
 __device__ __forceinline__ void bwd_dirs_block(int64_t blk, const float* __restrict__ lut, int N, int64_t lut_elems,
-                                               int64_t Q, int64_t q_per_obj, const float* __restrict__ dirs,
+                                               int64_t Q, uint64_t obj_magic, const float* __restrict__ dirs,
                                                const float* __restrict__ gout, float* __restrict__ grad_dirs)
 {
     const int64_t q = blk * DIRS_THREADS + threadIdx.x;
     if (q >= Q) return;
+    const uint64_t obj = obj_magic == 0 ? (uint64_t)q : __umul64hi((uint64_t)q, obj_magic);
     const float x = dirs[3 * q], y = dirs[3 * q + 1], z = dirs[3 * q + 2];
     const Loc L = locate(x, y, z, N);
     float3 gd;
@@ -779,7 +791,7 @@ __device__ __forceinline__ void bwd_dirs_block(int64_t blk, const float* __restr
         const float4 gq = reinterpret_cast<const float4*>(gout)[q];
         float3 M, S, T;
         frame_of(L.face, M, S, T);
-        gd = dirs_grad(lut + (q / q_per_obj) * lut_elems, N, L, gq, M, S, T, x, y, z);
+        gd = dirs_grad(lut + (int64_t)obj * lut_elems, N, L, gq, M, S, T, x, y, z);
     }
     grad_dirs[3 * q] = gd.x;
     grad_dirs[3 * q + 1] = gd.y;
@@ -787,11 +799,17 @@ __device__ __forceinline__ void bwd_dirs_block(int64_t blk, const float* __restr
 }
 
 __global__ __launch_bounds__(DIRS_THREADS) void k_bwd_dirs(const float* __restrict__ lut, int N, int64_t lut_elems,
-                                                          int64_t Q, int64_t q_per_obj, const float* __restrict__ dirs,
+                                                          int64_t Q, uint64_t obj_magic, const float* __restrict__ dirs,
                                                           const float* __restrict__ gout,
                                                           float* __restrict__ grad_dirs)
 {
-    bwd_dirs_block(blockIdx.x, lut, N, lut_elems, Q, q_per_obj, dirs, gout, grad_dirs);
+    bwd_dirs_block(blockIdx.x, lut, N, lut_elems, Q, obj_magic, dirs, gout, grad_dirs);
+}
+
+// the multiplier of bwd_dirs_block for d queries per object (1 <= d < 2^32)
+static uint64_t obj_magic(int64_t d)
+{
+    return d <= 1 ? 0 : UINT64_MAX / (uint64_t)d + 1;
 }
 
 __global__ void k_zero_f4(float4* __restrict__ a, int64_t n)
@@ -845,12 +863,14 @@ __global__ __launch_bounds__(OBJ_QT) void k_cell_keys_objects(BwdObjects B, cons
 }
 
 // row i of dst = row perm[i] of src (rows of W floats): the queries' inputs
-// in sorted order, read at random once so that the tiles read them coalesced
+// in sorted order, read at random once so that the tiles read them coalesced.
+// Each XCD takes a contiguous eighth of the rows: an object's rows, and so
+// the random reads of its source rows, stay on one XCD and its L2.
 template <int W>
 __global__ void k_gather_rows(const uint32_t* __restrict__ perm, const float* __restrict__ src, int64_t Q,
                               float* __restrict__ dst)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_remap((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= Q) return;
     const int64_t q = perm[i];
     if constexpr (W == 4) {
@@ -937,7 +957,8 @@ __global__ __launch_bounds__(OBJ_QT) void k_bwd_dirs_objects(BwdObjects B, const
                                                              const float* __restrict__ gout,
                                                              float* __restrict__ grad_dirs)
 {
-    const int64_t t = blockIdx.x;
+    // an object's query tiles are contiguous: on one XCD, its LUT stays in that L2
+    const int64_t t = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int64_t o = B.qtile_obj[t];
     const shm_object ob = B.objs[o];
     const int64_t k = (t - B.qtile_base[o]) * OBJ_QT + threadIdx.x;
@@ -1144,7 +1165,7 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
     }
     if (grad_dirs) {
         hipLaunchKernelGGL(k_bwd_dirs, dim3((unsigned)dblocks), dim3(DIRS_THREADS), 0, stream, lut, N, texel_elems(N),
-                           W.Q, q_per_obj, dirs, gout, grad_dirs);
+                           W.Q, obj_magic(q_per_obj), dirs, gout, grad_dirs);
         SHM_LAUNCH_CHECK();
     }
     return SHM_OK;

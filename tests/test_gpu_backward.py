@@ -80,6 +80,25 @@ def test_backward_multi_object_and_invalid():
         assert _e.max() < DIRS_TOL
 
 
+@pytest.mark.parametrize("n,qpo", [(7, 1), (3, 256), (4, 1000), (2, 4097)])
+def test_backward_dirs_use_each_querys_object(n, qpo):
+    """The direction gradient reads the LUT of the query's own object (the
+    object index is taken by a multiply, not a division): one query per
+    object, a power of two, and counts that do not divide a block."""
+    r = rng(60 + qpo)
+    N = 6
+    lut = workloads.random_lut(N, r, n_obj=n)
+    dirs = workloads.uniform_dirs(n * qpo, r)
+    g = r.standard_normal((n * qpo, 4)).astype(np.float32)
+    _, gd = run_bwd(lut, dirs, g, n_obj=n)
+    for o in range(n):
+        sl = slice(o * qpo, (o + 1) * qpo)
+        _, rd = oracle.backward(lut[o], dirs[sl], g[sl], want_lut=False)
+        gn = np.linalg.norm(rd, axis=1)
+        floor = np.sqrt(np.mean(gn ** 2))
+        assert (np.linalg.norm(gd[sl] - rd, axis=1) / np.maximum(gn, floor)).max() < DIRS_TOL, o
+
+
 def test_backward_bitwise_repeatable():
     r = rng(3)
     N = 64
