@@ -184,65 +184,161 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_add(uint32_t* __restrict__ 
         if (base + i < n) a[base + i] += add;
 }
 
+// Stable scatter of one digit pass.  Each wave ranks a contiguous quarter of
+// the tile on its own (per-wave digit counters in LDS, no workgroup barrier
+// per element round); the waves' counts then give every pair its position in
+// the tile in (digit, input order) order, the pairs are placed in LDS and
+// written out in that order: the keys of one digit leave as one run of
+// consecutive positions (coalesced stores), not one scattered store per key.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin, int64_t Q, int shift,
                                                               int64_t nb, const uint32_t* __restrict__ offs,
                                                               uint32_t* __restrict__ kout, uint32_t* __restrict__ vout)
 {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t cnt[4][256];
+    static_assert(RS_THREADS == SC_THREADS, "one lane per digit in the tile's digit scan");
+    constexpr int WAVES = RS_THREADS / 64, PER_WAVE = RS_TILE / WAVES, WITEMS = PER_WAVE / 64;
+    __shared__ uint32_t wcnt[WAVES][256];  // per wave: digit counts, then the digit's first tile position
+    __shared__ uint32_t gdelta[256];       // global position minus tile position, per digit
+    __shared__ uint32_t scan_sh[SC_THREADS];
+    __shared__ uint32_t tk[RS_TILE], tv[RS_TILE];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    run[tid] = offs[(int64_t)tid * nb + blockIdx.x];
-    const int64_t t0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t blk = blockIdx.x;
+    const int64_t t0 = blk * RS_TILE;
+    const int n_here = (int)min((int64_t)RS_TILE, Q - t0);
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
-    for (int c = 0; c < RS_ITEMS; ++c) {
-        for (int k = 0; k < 4; ++k) cnt[k][tid] = 0;
-        __syncthreads();
-        const int64_t e = t0 + (int64_t)c * RS_THREADS + tid;
+    const int64_t wbase = t0 + (int64_t)w * PER_WAVE;
+    uint32_t key[WITEMS], val[WITEMS], rank[WITEMS];
+#pragma unroll
+    for (int c = 0; c < WITEMS; ++c) {
+        const int64_t e = wbase + c * 64 + lane;
         const bool valid = e < Q;
-        const uint32_t key = valid ? kin[e] : 0u;
-        const uint32_t val = valid ? vin[e] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        key[c] = valid ? kin[e] : 0u;
+        val[c] = valid ? vin[e] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < WITEMS; ++c) {
+        const bool valid = wbase + c * 64 + lane < Q;
+        const uint32_t d = (key[c] >> shift) & 255u;
         // lanes of this wave holding the same digit (valid lanes only)
         unsigned long long same = __ballot(valid);
+#pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
             const unsigned long long bb = __ballot((d >> bit) & 1u);
             same &= ((d >> bit) & 1u) ? bb : ~bb;
         }
-        const uint32_t r_in_wave = (uint32_t)__popcll(same & lt);
-        if (valid && r_in_wave == 0) cnt[w][d] = (uint32_t)__popcll(same);
-        __syncthreads();
-        // prefix over waves for digit tid
-        const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid], c3 = cnt[3][tid];
-        __syncthreads();
-        cnt[0][tid] = 0;
-        cnt[1][tid] = c0;
-        cnt[2][tid] = c0 + c1;
-        cnt[3][tid] = c0 + c1 + c2;
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = run[d] + cnt[w][d] + r_in_wave;
-            kout[pos] = key;
-            vout[pos] = val;
+        const uint32_t r = (uint32_t)__popcll(same & lt);
+        // a wave's LDS accesses run in program order: every lane reads the
+        // count before the digit's first lane adds the round's lanes to it
+        const uint32_t before = wcnt[w][d];
+        rank[c] = before + r;
+        if (valid && r == 0) wcnt[w][d] = before + (uint32_t)__popcll(same);
+    }
+    __syncthreads();
+    // digit tid: its tile total, its first tile position, each wave's part
+    uint32_t cw[WAVES], tot = 0;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) {
+        cw[k] = wcnt[k][tid];
+        tot += cw[k];
+    }
+    uint32_t tile_total;
+    uint32_t at = block_excl_scan(tot, scan_sh, &tile_total);
+    gdelta[tid] = offs[(int64_t)tid * nb + blk] - at;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) {
+        wcnt[k][tid] = at;
+        at += cw[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < WITEMS; ++c) {
+        if (wbase + c * 64 + lane < Q) {
+            const uint32_t pos = wcnt[w][(key[c] >> shift) & 255u] + rank[c];
+            tk[pos] = key[c];
+            tv[pos] = val[c];
         }
-        __syncthreads();
-        run[tid] += c0 + c1 + c2 + c3;
-        __syncthreads();
+    }
+    __syncthreads();
+    // tile positions 0..n_here-1 hold the tile's pairs in (digit, input
+    // order) order; position p of digit d goes to gdelta[d] + p
+    for (int p = tid; p < n_here; p += RS_THREADS) {
+        const uint32_t k2 = tk[p];
+        const uint32_t gpos = gdelta[(k2 >> shift) & 255u] + (uint32_t)p;
+        kout[gpos] = k2;
+        vout[gpos] = tv[p];
     }
 }
 
-// cell_start[c] = first sorted position with key >= c, c = 0..n_cells
-__global__ void k_cell_start(const uint32_t* __restrict__ sk, int64_t Q, int64_t n_cells, uint32_t* __restrict__ cs)
+// Cell starts: cs[c] = first sorted position whose key is >= c, for
+// c = 0..n_cells (keys clamped to n_cells, the bucket of invalid directions).
+// Sorted position i (0..Q) owns the cells c with key[i-1] < c <= key[i]
+// (key[-1] = -1, key[Q] = n_cells): each cell has exactly one owner, so each
+// entry is written once, without a search.  A wave writes the runs of its 64
+// positions together, 64 consecutive cells per store; a run longer than
+// CS_LONG cells, and the run of position Q (the cells after the last key),
+// are listed and written by a workgroup each.  The list's order is free: the
+// result is the same.
+constexpr uint32_t CS_LONG = 65536;
+
+// the cells [lo, hi] owned by sorted position i (lo > hi: none)
+__device__ __forceinline__ void cs_owned(const uint32_t* __restrict__ sk, int64_t i, int64_t Q, uint32_t n_cells,
+                                         uint32_t& lo, uint32_t& hi)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > n_cells) return;
-    int64_t lo = 0, hi = Q;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)sk[mid] < c) lo = mid + 1;
-        else hi = mid;
+    lo = i > 0 ? min(sk[i - 1], n_cells) + 1u : 0u;
+    hi = i < Q ? min(sk[i], n_cells) : n_cells;
+}
+
+__global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ sk, int64_t Q, uint32_t n_cells,
+                                                    uint32_t* __restrict__ cs, uint32_t* __restrict__ n_long,
+                                                    uint32_t* __restrict__ long_list)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    // both keys load at once (clamped indices, no branch)
+    const uint32_t k_prev = sk[i > 0 ? min(i, Q) - 1 : 0], k_cur = sk[min(i, Q - 1)];
+    uint32_t lo = i > 0 ? min(k_prev, n_cells) + 1u : 0u, hi = min(k_cur, n_cells);
+    if (i >= Q) lo = 1, hi = 0;
+    uint32_t count = hi >= lo ? hi - lo + 1u : 0u;
+    if (count > CS_LONG) {
+        long_list[atomicAdd(n_long, 1u)] = (uint32_t)i;
+        count = 0;
     }
-    cs[c] = (uint32_t)lo;
+    // inclusive prefix of the counts over the wave
+    uint32_t incl = count;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    const uint32_t excl = incl - count;
+    const uint32_t total = __shfl(incl, 63);  // at most 64 CS_LONG < 2^32
+    const int64_t i_wave = i - lane;
+    for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+        const uint32_t t = t0 + lane;
+        // the owner: the last lane whose run starts at or before entry t
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+            if (__shfl(excl, j + step) <= t) j += step;
+        const uint32_t e_j = __shfl(excl, j), lo_j = __shfl(lo, j);
+        if (t < total) cs[lo_j + (t - e_j)] = (uint32_t)(i_wave + j);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_start_long(const uint32_t* __restrict__ sk, int64_t Q, uint32_t n_cells,
+                                                         uint32_t* __restrict__ cs, const uint32_t* __restrict__ n_long,
+                                                         const uint32_t* __restrict__ long_list)
+{
+    const uint32_t n = *n_long;
+    for (int64_t e = blockIdx.x; e <= (int64_t)n; e += gridDim.x) {
+        const int64_t i = e < (int64_t)n ? (int64_t)long_list[e] : Q;
+        uint32_t lo, hi;
+        cs_owned(sk, i, Q, n_cells, lo, hi);
+        for (int64_t c = (int64_t)lo + threadIdx.x; c <= (int64_t)hi; c += blockDim.x) cs[c] = (uint32_t)i;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -677,6 +773,23 @@ __global__ __launch_bounds__(BWD_THREADS) void k_tile_dense(int N, int tiles_per
     tile_dense_flag(uniform_tile((int)blockIdx.x, N, tiles_per_face, nullptr, 0), cs, D, blockIdx.x);
 }
 
+// cell starts from the sorted keys sk (Q > 0); the radix histogram's first
+// word counts the long runs and the key buffer not holding sk lists them
+// (the list holds at most Q positions)
+static void launch_cell_start(const BwdLayout& W, char* base, const uint32_t* sk, hipStream_t stream)
+{
+    uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
+    uint32_t* n_long = reinterpret_cast<uint32_t*>(base + W.hist);
+    uint32_t* k_free = reinterpret_cast<uint32_t*>(base + (sk == reinterpret_cast<const uint32_t*>(base + W.keys0)
+                                                                 ? W.keys1
+                                                                 : W.keys0));
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, n_long, 0u);
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, sk, W.Q,
+                       (uint32_t)W.n_cells, cs, n_long, k_free);
+    hipLaunchKernelGGL(k_cell_start_long, dim3((unsigned)(4 * device_cu_count())), dim3(256), 0, stream, sk, W.Q,
+                       (uint32_t)W.n_cells, cs, (const uint32_t*)n_long, (const uint32_t*)k_free);
+}
+
 int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_obj, void* ws, hipStream_t stream)
 {
     const BwdLayout W = bwd_layout(N, n_obj, q_per_obj);
@@ -706,9 +819,8 @@ int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_
         t = v0; v0 = v1; v1 = t;
     }
     // sorted keys in k0, permutation in v0 (buffer 0 or 1 depending on parity)
-    uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
-    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.n_cells + 1 + 255) / 256)), dim3(256), 0, stream, k0, W.Q,
-                       W.n_cells, cs);
+    launch_cell_start(W, base, k0, stream);
+    const uint32_t* cs = reinterpret_cast<const uint32_t*>(base + W.cstart);
     if (W.n_tiles > 0) {
         const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
         hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, D.count, 0u);
@@ -1061,9 +1173,8 @@ int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, voi
     SHM_LAUNCH_CHECK();
     radix_sort_pass_all(W, base, stream, k0, v0);
     SHM_LAUNCH_CHECK();
-    uint32_t* cs = reinterpret_cast<uint32_t*>(base + W.cstart);
-    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((W.n_cells + 1 + 255) / 256)), dim3(256), 0, stream, k0, W.Q,
-                       W.n_cells, cs);
+    launch_cell_start(W, base, k0, stream);
+    const uint32_t* cs = reinterpret_cast<const uint32_t*>(base + W.cstart);
     hipLaunchKernelGGL(k_gather_rows<3>, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, v0, dirs, W.Q,
                        reinterpret_cast<float*>(base + W.sdirs));
     if (H.n_tiles > 0) {

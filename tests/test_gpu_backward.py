@@ -99,6 +99,31 @@ def test_backward_dirs_use_each_querys_object(n, qpo):
         assert (np.linalg.norm(gd[sl] - rd, axis=1) / np.maximum(gn, floor)).max() < DIRS_TOL, o
 
 
+def test_backward_few_queries_long_empty_runs():
+    """Cell starts where long runs of cells hold no query: a few directions
+    on faces +Y and -Z of two N = 200 objects (40,401 cells per face), so the
+    runs before the first query, between the faces and after the last query
+    exceed 65,536 cells and are written by the long-run kernel."""
+    r = rng(70)
+    N, n, qpo = 200, 2, 6
+    lut = workloads.random_lut(N, r, n_obj=n)
+    d = r.standard_normal((n * qpo, 3)).astype(np.float32) * 0.2
+    d[:, 1] += np.where(np.arange(n * qpo) % 2 == 0, 1.0, 0.0).astype(np.float32)   # +Y (face 2)
+    d[:, 2] -= np.where(np.arange(n * qpo) % 2 == 1, 1.0, 0.0).astype(np.float32)   # -Z (face 5)
+    g = r.standard_normal((n * qpo, 4)).astype(np.float32)
+    keys = oracle.locate(d, N)[0]
+    assert set(keys.tolist()) == {2, 5}
+    gl, gd = run_bwd(lut, d, g, n_obj=n)
+    for o in range(n):
+        sl = slice(o * qpo, (o + 1) * qpo)
+        rl, rd = oracle.backward(lut[o], d[sl], g[sl])
+        scale = np.abs(rl).max()
+        assert np.abs(gl[o] - rl).max() / scale < LUT_TOL
+        assert np.count_nonzero(gl[o]) <= 16 * qpo  # 4 texels x 4 channels per query
+        gn = np.linalg.norm(rd, axis=1)
+        assert (np.linalg.norm(gd[sl] - rd, axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))).max() < DIRS_TOL
+
+
 def test_backward_bitwise_repeatable():
     r = rng(3)
     N = 64
