@@ -102,19 +102,61 @@ __global__ void k_cell_keys(int N, int64_t Q, int64_t q_per_obj, const float* __
 // ---------------------------------------------------------------------------
 // stable LSD radix sort, one 8-bit digit per pass
 // ---------------------------------------------------------------------------
+// the valid lanes of this wave whose digit equals this lane's digit d
+__device__ __forceinline__ unsigned long long same_digit_lanes(uint32_t d, bool valid)
+{
+    unsigned long long same = __ballot(valid);
+    // a round whose valid lanes share one digit (common where keys are
+    // nearly in order) needs no per-bit ballots
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    if (__ballot(valid && d == d0) == same) return same;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const unsigned long long bb = __ballot((d >> bit) & 1u);
+        same &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    return same;
+}
+
+// Digit counts of one tile, each wave into counters of its own.  A round of
+// 64 keys that share one digit (the high digits of keys that are nearly in
+// order, as a batch's or a presorted fit's are) is counted by one add;
+// other rounds by one LDS atomic per key.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t Q, int shift,
                                                            int64_t nb, uint32_t* __restrict__ hist)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr int WAVES = RS_THREADS / 64, PER_WAVE = RS_TILE / WAVES, WITEMS = PER_WAVE / 64;
+    __shared__ uint32_t wcnt[WAVES][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) wcnt[k][tid] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * RS_TILE;
-    for (int i = threadIdx.x; i < RS_TILE; i += RS_THREADS) {
-        const int64_t e = t0 + i;
-        if (e < Q) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * PER_WAVE;
+    uint32_t key[WITEMS];
+#pragma unroll
+    for (int c = 0; c < WITEMS; ++c) {
+        const int64_t e = wbase + c * 64 + lane;
+        key[c] = e < Q ? keys[e] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < WITEMS; ++c) {
+        const bool valid = wbase + c * 64 + lane < Q;
+        const uint32_t d = (key[c] >> shift) & 255u;
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const unsigned long long vm = __ballot(valid);
+        if (__ballot(valid && d == d0) == vm) {
+            // lane 0 is valid whenever any lane is (the invalid keys end the
+            // last tile); LDS accesses of one wave run in program order
+            if (lane == 0 && vm) wcnt[w][d0] += (uint32_t)__popcll(vm);
+        } else if (valid) {
+            atomicAdd(&wcnt[w][d], 1u);
+        }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) sum += wcnt[k][tid];
+    hist[(int64_t)tid * nb + blockIdx.x] = sum;
 }
 
 // exclusive scan of n uint32: per-block scans of 4096 elements (256 lanes x
@@ -222,13 +264,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint32_t* __
     for (int c = 0; c < WITEMS; ++c) {
         const bool valid = wbase + c * 64 + lane < Q;
         const uint32_t d = (key[c] >> shift) & 255u;
-        // lanes of this wave holding the same digit (valid lanes only)
-        unsigned long long same = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const unsigned long long bb = __ballot((d >> bit) & 1u);
-            same &= ((d >> bit) & 1u) ? bb : ~bb;
-        }
+        const unsigned long long same = same_digit_lanes(d, valid);  // this wave's lanes of digit d
         const uint32_t r = (uint32_t)__popcll(same & lt);
         // a wave's LDS accesses run in program order: every lane reads the
         // count before the digit's first lane adds the round's lanes to it
