@@ -271,6 +271,7 @@ def main():
         shm.shm_probe_stream_read(lut_cell, lut_cell.numel() * 4, sink)
         torch.cuda.synchronize()
         shm.bake_sh(c_t, N)
+        shm.shm_probe_mfma_f32(2, 4, 10000, torch.zeros(4, device=DEV))
         Nb, Qb = 512, 1 << 22
         d4 = to_dev(workloads.uniform_dirs(Qb, workloads.rng_for(4)))
         d4 = d4[torch.argsort(shm.cell_keys(Nb, d4).to(torch.int64) & 0xFFFFFFFF, stable=True)].contiguous()
@@ -450,6 +451,17 @@ def run_forms(c_t, dirs_t, lut_tex, lut_cell, out_cell, ms_cell):
     forms["bake_sh"] = {"ms": ms, "tflops": flops / ms / 1e9, "mfma_frac": flops / ms / 1e9 / PEAK_FP32_MFMA_TFLOPS,
                         "write_gbs": lut_b.numel() * 4 / ms / 1e6, "flops": flops, "first_call_ms": ms_first}
     del lut_b, ws
+    # the matrix cores with register operands only, right after the bakes
+    # (the same clock regime): the contraction's shape (2 waves per SIMD, 4
+    # accumulator chains) and a deeper one, each ~1.4 ms per launch
+    sink = torch.zeros(4, device=DEV)
+    probe = {}
+    for wps, ch, it in ((2, 4, 10000), (4, 8, 2500)):
+        fl = shm.shm_probe_mfma_f32(wps, ch, it, sink)
+        ms_p = t_gpu(lambda: shm.shm_probe_mfma_f32(wps, ch, it, sink), 5)
+        probe[f"waves{wps}_chains{ch}"] = {"ms": ms_p, "tflops": fl / ms_p / 1e9}
+    forms["bake_sh"]["mfma_probe"] = probe
+    forms["bake_sh"]["frac_of_mfma_probe"] = forms["bake_sh"]["tflops"] / probe["waves2_chains4"]["tflops"]
     log("bake", forms["bake_sh"])
 
     forms["cfg1_glyph"], sample["cfg1"] = run_cfg1()

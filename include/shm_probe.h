@@ -1,6 +1,6 @@
 /*
- * shm_probe.h -- memory-system probes of libshm (measurement, not part of
- * the method).
+ * shm_probe.h -- memory-system and matrix-core probes of libshm
+ * (measurement, not part of the method).
  *
  * The value + gradient query of Spherical Hermite Maps reads, per query, the
  * 2x2 texel footprint of its cell (16 scalars, Sec. 3.3 Eq. 4 and Table
@@ -47,6 +47,18 @@ SHM_API int shm_probe_gather(const void* base, int64_t region_bytes, int64_t n_r
 /* Streaming read of `bytes` bytes (a multiple of 16) at base (16-byte
  * aligned); sink is a 16-byte buffer that is not written for finite data. */
 SHM_API int shm_probe_stream_read(const void* base, int64_t bytes, float* sink, hipStream_t stream);
+
+/* The FP32 matrix cores without memory traffic: waves_per_simd (1..8)
+ * workgroups of 4 waves per compute unit, each wave running `iters` (>= 1)
+ * rounds of `chains` (1, 2, 4 or 8) independent v_mfma_f32_16x16x4f32 on
+ * register operands, 2,048 flops each; the bake's contraction (Sec. 3.3,
+ * the basis x coefficient product) uses the same instruction.  *flops
+ * (host pointer) receives the launch's flop count before the launch; sink
+ * is a 16-byte aligned device buffer that is not written for finite data.
+ * Errors: SHM_ERR_INVALID_ARG for an argument out of range or a null or
+ * misaligned pointer. */
+SHM_API int shm_probe_mfma_f32(int32_t waves_per_simd, int32_t chains, int64_t iters, double* flops, float* sink,
+                               hipStream_t stream);
 
 /* The batched form's memory traffic without its arithmetic: the walk of
  * shm_plan_launch over the plan's work list, in the plan's current launch

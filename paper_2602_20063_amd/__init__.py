@@ -118,6 +118,7 @@ SIGNATURES = {
     # memory-system probes (include/shm_probe.h)
     "shm_probe_gather": (ctypes.c_int, [_VP, _I64, _I64, _I64, _I32, ctypes.c_uint32, _I32, _VP, _VP, _VP]),
     "shm_probe_stream_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    "shm_probe_mfma_f32": (ctypes.c_int, [_I32, _I32, _I64, ctypes.POINTER(ctypes.c_double), _VP, _VP]),
     "shm_query_objects_workspace": (_SZ, [_I64]),
     "shm_plan_backward_sort": (ctypes.c_int, [_VP, _VP, _VP]),
     "shm_plan_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -320,6 +321,14 @@ def shm_probe_stream_read(base, nbytes, sink, stream=None):
     _fits(base, nbytes, "base")
     _fits(sink, 16 if nbytes > 0 else 0, "sink")
     return _check(lib().shm_probe_stream_read(_ptr(base), nbytes, _ptr(sink), _stream(stream)))
+
+
+def shm_probe_mfma_f32(waves_per_simd, chains, iters, sink, stream=None):
+    """Launch the FP32 matrix-core probe; returns the launch's flop count."""
+    _fits(sink, 16, "sink")
+    fl = ctypes.c_double(0.0)
+    _check(lib().shm_probe_mfma_f32(waves_per_simd, chains, iters, ctypes.byref(fl), _ptr(sink), _stream(stream)))
+    return fl.value
 
 
 def shm_backward_workspace(N, n_obj, q_per_obj):

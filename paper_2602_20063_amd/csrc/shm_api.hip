@@ -89,6 +89,7 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
 int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_regions, int64_t per_region, int req_bytes,
                         uint32_t seed, int flags, const float* dirs, float* out, hipStream_t stream);
 int launch_probe_stream(const void* base, int64_t bytes, float* sink, hipStream_t stream);
+int launch_probe_mfma(int waves_per_simd, int chains, int64_t iters, double* flops, float* sink, hipStream_t stream);
 int launch_probe_plan(const void* lut, int dtype, int layout, const shm_object* objs_dev, const WorkItem* items_dev,
                       int64_t n_items, const XcdSplit& split, const shm_launch_shape& shape, int n_cu,
                       const float* dirs, float* out, uint32_t seed, hipStream_t stream);
@@ -1153,6 +1154,19 @@ int shm_probe_stream_read(const void* base, int64_t bytes, float* sink, hipStrea
     if (!base || !sink) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: null pointer");
     if (!aligned(base, 16) || !aligned(sink, 16)) return fail(SHM_ERR_INVALID_ARG, "probe_stream_read: misaligned buffer");
     return launch_probe_stream(base, bytes, sink, stream);
+}
+
+int shm_probe_mfma_f32(int32_t waves_per_simd, int32_t chains, int64_t iters, double* flops, float* sink,
+                       hipStream_t stream)
+{
+    clear_error();
+    if (waves_per_simd < 1 || waves_per_simd > 8) return fail(SHM_ERR_INVALID_ARG, "probe_mfma: waves_per_simd must be 1..8");
+    if (chains != 1 && chains != 2 && chains != 4 && chains != 8)
+        return fail(SHM_ERR_INVALID_ARG, "probe_mfma: chains must be 1, 2, 4 or 8");
+    if (iters < 1) return fail(SHM_ERR_INVALID_ARG, "probe_mfma: iters must be >= 1");
+    if (!flops || !sink) return fail(SHM_ERR_INVALID_ARG, "probe_mfma: null pointer");
+    if (!aligned(sink, 16)) return fail(SHM_ERR_INVALID_ARG, "probe_mfma: misaligned sink");
+    return launch_probe_mfma(waves_per_simd, chains, iters, flops, sink, stream);
 }
 
 int shm_plan_probe(shm_plan* plan, const void* lut, const float* dirs, float* out, uint32_t seed, hipStream_t stream)

@@ -14,6 +14,8 @@
 //                    the query's; the parts alone show what each costs.
 //   k_probe_stream   streaming reads of a whole buffer (float4 per lane,
 //                    grid-stride), the bandwidth ceiling of plain reads.
+//   k_probe_mfma     FP32 matrix-core rounds with register operands only: the
+//                    rate the bake's contraction is measured against.
 //   k_probe_plan     the batched form's traffic: the persistent kernel's walk
 //                    over a plan's work list in the plan's launch shape; per
 //                    query the 12 B direction, the footprint of a
@@ -235,6 +237,44 @@ int launch_probe_gather(const void* base, int64_t region_bytes, int64_t n_region
     }
 #undef SHM_PG
 #undef SHM_PG3
+    SHM_LAUNCH_CHECK();
+    return SHM_OK;
+}
+
+// The FP32 matrix cores with register operands only: CH independent
+// accumulator chains per wave, `iters` rounds; nothing but the MFMAs and the
+// loop runs, so the launch measures the rate the matrix pipes sustain at the
+// clock they hold under this load.
+template <int CH>
+__global__ __launch_bounds__(256) void k_probe_mfma(int64_t iters, float* __restrict__ sink)
+{
+    const int lane = threadIdx.x & 63;
+    const float a = 1.0f + 1e-3f * (float)lane, b = 1.0f - 1e-3f * (float)lane;
+    f32x4 acc[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+    }
+    float t = 0.0f;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) t += acc[c].x + acc[c].y + acc[c].z + acc[c].w;
+    if (__float_as_uint(t) == 0x7fc00001u) sink[0] = t;  // never for finite data
+}
+
+int launch_probe_mfma(int waves_per_simd, int chains, int64_t iters, double* flops, float* sink, hipStream_t stream)
+{
+    // one workgroup of 4 waves (one per SIMD) per compute unit and wave slot
+    const int64_t groups = (int64_t)device_cu_count() * waves_per_simd;
+    *flops = (double)groups * 4 * iters * chains * 2.0 * 16 * 16 * 4;
+    const dim3 grid((unsigned)groups), block(256);
+    switch (chains) {
+        case 1: hipLaunchKernelGGL(k_probe_mfma<1>, grid, block, 0, stream, iters, sink); break;
+        case 2: hipLaunchKernelGGL(k_probe_mfma<2>, grid, block, 0, stream, iters, sink); break;
+        case 4: hipLaunchKernelGGL(k_probe_mfma<4>, grid, block, 0, stream, iters, sink); break;
+        default: hipLaunchKernelGGL(k_probe_mfma<8>, grid, block, 0, stream, iters, sink); break;
+    }
     SHM_LAUNCH_CHECK();
     return SHM_OK;
 }

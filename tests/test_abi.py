@@ -327,6 +327,14 @@ def test_probe_argument_validation():
     assert call("shm_probe_gather", p, 4096, 0, 256, 64, 1, 0, None, None, None) == shm.SHM_OK  # empty
     assert call("shm_probe_stream_read", p, 100, p, None) == shm.SHM_ERR_INVALID_ARG
     assert call("shm_probe_stream_read", p, 0, None, None) == shm.SHM_OK
+    fl = ctypes.c_double(-1.0)
+    mf = lambda w, c, it, f=ctypes.byref(fl), sk=p: call("shm_probe_mfma_f32", w, c, it, f, sk, None)
+    for args in ((0, 4, 10), (9, 4, 10), (2, 3, 10), (2, 16, 10), (2, 4, 0)):
+        assert mf(*args) == shm.SHM_ERR_INVALID_ARG, args
+    assert mf(2, 4, 10, f=None) == shm.SHM_ERR_INVALID_ARG
+    assert mf(2, 4, 10, sk=None) == shm.SHM_ERR_INVALID_ARG
+    assert mf(2, 4, 10, sk=ctypes.c_void_p(260)) == shm.SHM_ERR_INVALID_ARG
+    assert fl.value == -1.0  # nothing written on refusal
     assert call("shm_plan_probe", None, p, p, p, 1, None) == shm.SHM_ERR_INVALID_ARG  # no plan, no device call
     assert "null plan" in shm.shm_last_error()
 

@@ -42,6 +42,28 @@ def test_probe_sinks_are_not_written():
     assert torch.equal(sink, torch.full_like(sink, 123.0))
 
 
+@pytest.mark.parametrize("wps,chains", [(1, 1), (2, 4), (4, 8)])
+def test_mfma_probe_counts_its_flops(wps, chains):
+    """The matrix-core probe reports 2,048 flops per MFMA for 4 waves per
+    workgroup, wps workgroups per compute unit, `iters` rounds of `chains`
+    MFMAs, leaves its sink alone, and runs at a plausible rate (between 1
+    and 200 TFLOP/s: FP32 matrix peak 157.3)."""
+    sink = torch.full((4,), 7.0, device=DEV)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    iters = 2000
+    shm.shm_probe_mfma_f32(wps, chains, iters, sink)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    flops = shm.shm_probe_mfma_f32(wps, chains, iters, sink)
+    e1.record()
+    e1.synchronize()
+    assert flops == n_cu * wps * 4 * iters * chains * 2048
+    assert torch.equal(sink, torch.full_like(sink, 7.0))
+    tf = flops / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    print(f"wps {wps} chains {chains}: {tf:.1f} TFLOP/s")
+    assert 1.0 < tf < 200.0
+
+
 @pytest.mark.parametrize("dtype,layout", [(shm.SHM_F32, shm.SHM_LAYOUT_CELL), (shm.SHM_F16, shm.SHM_LAYOUT_CELL),
                                           (shm.SHM_F32, shm.SHM_LAYOUT_TEXEL), (shm.SHM_F16, shm.SHM_LAYOUT_TEXEL)])
 def test_plan_probe_walks_every_query_of_its_object(dtype, layout):
