@@ -776,18 +776,22 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
 __device__ __forceinline__ void tile_dense_flag(const TileGeo& G, const uint32_t* __restrict__ cs, DenseTiles D,
                                                 uint32_t t)
 {
-    __shared__ int any;
-    const int tid = threadIdx.x;
-    if (tid == 0) any = 0;
-    __syncthreads();
+    // one wave per tile, BC * BC / 64 of its cells per lane
+    static_assert(BC * BC % 64 == 0, "whole cells per lane");
+    const int lane = threadIdx.x & 63;
     const int C = G.N + 1;
-    const int i0c = G.p0 - 1 + tid % BC, j0c = G.q0 - 1 + tid / BC;
-    if (i0c >= 0 && i0c <= G.N && j0c >= 0 && j0c <= G.N) {
-        const int64_t c = G.cbase + (int64_t)j0c * C + i0c;
-        if ((int64_t)cs[c + 1] - cs[c] > BWD_DENSE) any = 1;  // every writer stores the same value
+    bool dense = false;
+#pragma unroll
+    for (int k = 0; k < BC * BC / 64; ++k) {
+        const int cell = lane + 64 * k;
+        const int i0c = G.p0 - 1 + cell % BC, j0c = G.q0 - 1 + cell / BC;
+        if (i0c >= 0 && i0c <= G.N && j0c >= 0 && j0c <= G.N) {
+            const int64_t c = G.cbase + (int64_t)j0c * C + i0c;
+            dense |= (int64_t)cs[c + 1] - cs[c] > BWD_DENSE;
+        }
     }
-    __syncthreads();
-    if (tid == 0) {
+    const bool any = __ballot(dense) != 0;
+    if (lane == 0) {
         D.flag[t] = any ? 1 : 0;
         if (any) D.list[atomicAdd(D.count, 1u)] = t;  // integer atomic: the list's order is free
     }
@@ -803,10 +807,13 @@ static inline int64_t dense_grid(int64_t n_tiles)
     return std::max<int64_t>(1, std::min<int64_t>(n_tiles, (int64_t)device_cu_count()));
 }
 
-__global__ __launch_bounds__(BWD_THREADS) void k_tile_dense(int N, int tiles_per_face, const uint32_t* __restrict__ cs,
-                                                            DenseTiles D)
+// tile flags: one wave per tile, 4 tiles per workgroup of 256
+__global__ __launch_bounds__(256) void k_tile_dense(int N, int tiles_per_face, int64_t n_tiles,
+                                                    const uint32_t* __restrict__ cs, DenseTiles D)
 {
-    tile_dense_flag(uniform_tile((int)blockIdx.x, N, tiles_per_face, nullptr, 0), cs, D, blockIdx.x);
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    tile_dense_flag(uniform_tile((int)t, N, tiles_per_face, nullptr, 0), cs, D, (uint32_t)t);
 }
 
 // cell starts from the sorted keys sk (Q > 0); the radix histogram's first
@@ -860,8 +867,8 @@ int launch_backward_sort(int N, int64_t n_obj, const float* dirs, int64_t q_per_
     if (W.n_tiles > 0) {
         const DenseTiles D = dense_tiles(base + W.dense, W.n_tiles);
         hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, D.count, 0u);
-        hipLaunchKernelGGL(k_tile_dense, dim3((unsigned)W.n_tiles), dim3(BWD_THREADS), 0, stream, N,
-                           (N + 2 + BT - 1) / BT, (const uint32_t*)cs, D);
+        hipLaunchKernelGGL(k_tile_dense, dim3((unsigned)((W.n_tiles + 3) / 4)), dim3(256), 0, stream, N,
+                           (N + 2 + BT - 1) / BT, W.n_tiles, (const uint32_t*)cs, D);
     }
     SHM_LAUNCH_CHECK();
     return SHM_OK;
@@ -1049,10 +1056,12 @@ __device__ __forceinline__ TileGeo object_tile(const BwdObjects& B, int64_t t)
     return G;
 }
 
-__global__ __launch_bounds__(BWD_THREADS) void k_tile_dense_objects(BwdObjects B, const uint32_t* __restrict__ cs,
-                                                                    DenseTiles D)
+__global__ __launch_bounds__(256) void k_tile_dense_objects(BwdObjects B, int64_t n_tiles,
+                                                            const uint32_t* __restrict__ cs, DenseTiles D)
 {
-    tile_dense_flag(object_tile(B, blockIdx.x), cs, D, blockIdx.x);
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    tile_dense_flag(object_tile(B, t), cs, D, (uint32_t)t);
 }
 
 __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects(BwdObjects B, int64_t Q,
@@ -1216,8 +1225,8 @@ int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, voi
     if (H.n_tiles > 0) {
         const DenseTiles D = dense_tiles(base + W.dense, H.n_tiles);
         hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, D.count, 0u);
-        hipLaunchKernelGGL(k_tile_dense_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B,
-                           (const uint32_t*)cs, D);
+        hipLaunchKernelGGL(k_tile_dense_objects, dim3((unsigned)((H.n_tiles + 3) / 4)), dim3(256), 0, stream, B,
+                           H.n_tiles, (const uint32_t*)cs, D);
     }
     SHM_LAUNCH_CHECK();
     return SHM_OK;
