@@ -49,7 +49,7 @@ static inline DenseTiles dense_tiles(char* at, int64_t n_tiles)
 }
 
 struct BwdLayout {
-    size_t keys0, vals0, keys1, vals1, cstart, hist, tsum, sdirs = 0, sgout = 0, dense = 0, total;
+    size_t keys0, vals0, keys1, vals1, cstart, hist, tsum, sdirs = 0, sgout = 0, dense = 0, geo = 0, total;
     int64_t Q, n_cells, nb, n_tiles = 0;
     int passes;
 };
@@ -1056,35 +1056,89 @@ __device__ __forceinline__ TileGeo object_tile(const BwdObjects& B, int64_t t)
     return G;
 }
 
+// A plan tile's geometry and kind, written once per sort so that the tile
+// kernels start from one (scalar) load instead of the chain tile -> object
+// -> object record -> divisions.  kind: 0 no query in the tile's cells (a
+// zero gradient), 1 sparse, 2 dense (some cell with more than BWD_DENSE).
+struct TileRec {
+    int32_t N, face_kind, p0, q0;  // face_kind = face | kind << 8
+    int64_t cbase, tex_base;
+};
+static_assert(sizeof(TileRec) == 32, "one 32-byte record per tile");
+
+__device__ __forceinline__ TileGeo tile_of_rec(const TileRec& r)
+{
+    TileGeo G;
+    G.N = r.N;
+    G.face = r.face_kind & 255;
+    G.p0 = r.p0;
+    G.q0 = r.q0;
+    G.cbase = r.cbase;
+    G.tex_base = r.tex_base;
+    G.lut_obj = nullptr;
+    return G;
+}
+
 __global__ __launch_bounds__(256) void k_tile_dense_objects(BwdObjects B, int64_t n_tiles,
-                                                            const uint32_t* __restrict__ cs, DenseTiles D)
+                                                            const uint32_t* __restrict__ cs, DenseTiles D,
+                                                            TileRec* __restrict__ recs)
 {
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
-    tile_dense_flag(object_tile(B, t), cs, D, (uint32_t)t);
+    const TileGeo G = object_tile(B, t);
+    const int lane = threadIdx.x & 63;
+    const int C = G.N + 1;
+    bool dense = false, any = false;
+#pragma unroll
+    for (int k = 0; k < BC * BC / 64; ++k) {
+        const int cell = lane + 64 * k;
+        const int i0c = G.p0 - 1 + cell % BC, j0c = G.q0 - 1 + cell / BC;
+        if (i0c >= 0 && i0c <= G.N && j0c >= 0 && j0c <= G.N) {
+            const int64_t c = G.cbase + (int64_t)j0c * C + i0c;
+            const int64_t n = (int64_t)cs[c + 1] - cs[c];
+            dense |= n > BWD_DENSE;
+            any |= n > 0;
+        }
+    }
+    const bool d = __ballot(dense) != 0, a = __ballot(any) != 0;
+    if (lane == 0) {
+        D.flag[t] = d ? 1 : 0;
+        if (d) D.list[atomicAdd(D.count, 1u)] = (uint32_t)t;  // integer atomic: the list's order is free
+        TileRec r;
+        r.N = G.N;
+        r.face_kind = G.face | ((d ? 2 : (a ? 1 : 0)) << 8);
+        r.p0 = G.p0;
+        r.q0 = G.q0;
+        r.cbase = G.cbase;
+        r.tex_base = G.tex_base;
+        recs[t] = r;
+    }
 }
 
-__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects(BwdObjects B, int64_t Q,
-                                                                   const float* __restrict__ sdirs,
+// recs: the tile records of the sort; null when there are no queries (every
+// tile then has a zero gradient, its geometry taken from the objects)
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects(BwdObjects B, const TileRec* __restrict__ recs,
+                                                                   int64_t Q, const float* __restrict__ sdirs,
                                                                    const float* __restrict__ sgout,
                                                                    const uint32_t* __restrict__ perm,
                                                                    const uint32_t* __restrict__ cs,
-                                                                   const uint8_t* __restrict__ dense_flag,
                                                                    float* __restrict__ grad_lut)
 {
     const int64_t t = blockIdx.x;
-    const uint8_t dense = dense_flag != nullptr ? dense_flag[t] : 0;  // a dense tile: k_bwd_fused_objects_dense
-    const TileGeo G = object_tile(B, t);
-    const int N = G.N, C = N + 1, P = N + 2;
-    // a tile whose cell rows hold no query has a zero gradient: write it
-    // without the row setup and its barriers (most tiles of a large face
-    // with few queries)
-    const int j_lo = max(G.q0 - 1, 0), j_hi = min(G.q0 + BT - 1, N);
-    const int64_t in_rows = Q > 0 ? (int64_t)cs[G.cbase + (int64_t)(j_hi + 1) * C] - cs[G.cbase + (int64_t)j_lo * C] : 0;
-    if (dense) return;
-    if (in_rows == 0) {
+    TileGeo G;
+    int kind = 0;
+    if (recs != nullptr) {
+        const TileRec r = recs[t];
+        G = tile_of_rec(r);
+        kind = r.face_kind >> 8;
+    } else {
+        G = object_tile(B, t);
+    }
+    if (kind == 2) return;  // a dense tile: k_bwd_fused_objects_dense
+    if (kind == 0) {        // no query in the tile's cells: a zero gradient, without the row setup
+        const int P = G.N + 2;
         const int tid = threadIdx.x, t_x = tid % BT, t_y = tid / BT;
-        if (tid < BT * BT && G.p0 + t_x <= N + 1 && G.q0 + t_y <= N + 1)
+        if (tid < BT * BT && G.p0 + t_x <= G.N + 1 && G.q0 + t_y <= G.N + 1)
             reinterpret_cast<float4*>(grad_lut)[G.tex_base + (int64_t)(G.q0 + t_y) * P + G.p0 + t_x] =
                 make_float4(0.f, 0.f, 0.f, 0.f);
         return;
@@ -1092,7 +1146,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects(BwdObjects B,
     bwd_tile<false, true>(G, nullptr, Q, sdirs, sgout, perm, cs, grad_lut, FitArgs{});
 }
 
-__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects_dense(BwdObjects B, int64_t Q,
+__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects_dense(const TileRec* __restrict__ recs, int64_t Q,
                                                                          const float* __restrict__ sdirs,
                                                                          const float* __restrict__ sgout,
                                                                          const uint32_t* __restrict__ perm,
@@ -1103,7 +1157,8 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects_dense(BwdObje
 {
     const uint32_t n = *count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        bwd_tile<false, true, true>(object_tile(B, list[i]), nullptr, Q, sdirs, sgout, perm, cs, grad_lut, FitArgs{});
+        bwd_tile<false, true, true>(tile_of_rec(recs[list[i]]), nullptr, Q, sdirs, sgout, perm, cs, grad_lut,
+                                    FitArgs{});
         lds_barrier();  // the next tile reuses the workgroup's LDS
     }
 }
@@ -1164,6 +1219,7 @@ static BwdLayout bwd_layout_cells(int64_t Q, int64_t n_cells, int64_t n_tiles)
     W.sdirs = take(W.Q * 12);  // directions in sorted order (with the sort)
     W.sgout = take(W.Q * 16);  // upstream gradients in sorted order (per backward)
     W.dense = take(dense_bytes(n_tiles));
+    W.geo = take((size_t)n_tiles * 32);  // each tile's geometry and kind (TileRec), with the sort
     W.total = at;
     return W;
 }
@@ -1226,7 +1282,7 @@ int launch_backward_sort_objects(const BwdObjectsHost& H, const float* dirs, voi
         const DenseTiles D = dense_tiles(base + W.dense, H.n_tiles);
         hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, stream, D.count, 0u);
         hipLaunchKernelGGL(k_tile_dense_objects, dim3((unsigned)((H.n_tiles + 3) / 4)), dim3(256), 0, stream, B,
-                           H.n_tiles, (const uint32_t*)cs, D);
+                           H.n_tiles, (const uint32_t*)cs, D, reinterpret_cast<TileRec*>(base + W.geo));
     }
     SHM_LAUNCH_CHECK();
     return SHM_OK;
@@ -1245,19 +1301,20 @@ int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut,
     if (grad_lut && H.n_tiles > 0) {
         if (W.Q == 0) {  // no queries: the sort wrote nothing; every object's gradient is zero
             hipLaunchKernelGGL(k_bwd_fused_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B,
-                               (int64_t)0, (const float*)nullptr, (const float*)nullptr, (const uint32_t*)nullptr,
-                               (const uint32_t*)nullptr, (const uint8_t*)nullptr, grad_lut);
+                               (const TileRec*)nullptr, (int64_t)0, (const float*)nullptr, (const float*)nullptr,
+                               (const uint32_t*)nullptr, (const uint32_t*)nullptr, grad_lut);
         } else {
             const DenseTiles D = dense_tiles(base + W.dense, H.n_tiles);
             hipLaunchKernelGGL(k_gather_rows<4>, dim3((unsigned)((W.Q + 255) / 256)), dim3(256), 0, stream, perm, gout,
                                W.Q, sgout);
-            hipLaunchKernelGGL(k_bwd_fused_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B, W.Q,
-                               sdirs, (const float*)sgout, perm, cs, (const uint8_t*)D.flag, grad_lut);
+            const TileRec* recs = reinterpret_cast<const TileRec*>(base + W.geo);
+            hipLaunchKernelGGL(k_bwd_fused_objects, dim3((unsigned)H.n_tiles), dim3(BWD_THREADS), 0, stream, B, recs,
+                               W.Q, sdirs, (const float*)sgout, perm, cs, grad_lut);
             // the plan read the dense-tile count back after its sort
             if (H.n_dense > 0)
                 hipLaunchKernelGGL(k_bwd_fused_objects_dense,
                                    dim3((unsigned)std::min<int64_t>(H.n_dense, 8ll * device_cu_count())),
-                                   dim3(BWD_THREADS), 0, stream, B, W.Q, sdirs, (const float*)sgout, perm, cs,
+                                   dim3(BWD_THREADS), 0, stream, recs, W.Q, sdirs, (const float*)sgout, perm, cs,
                                    (const uint32_t*)D.count, (const uint32_t*)D.list, grad_lut);
         }
         SHM_LAUNCH_CHECK();
