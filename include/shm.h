@@ -309,7 +309,8 @@ SHM_API int shm_plan_destroy(shm_plan* plan);
  * The first call checks that no two objects' LUTs and no two non-empty
  * query ranges overlap (SHM_ERR_INVALID_ARG otherwise), builds the objects'
  * prefix arrays and allocates the sort buffers (44 B per query row up to the
- * last object's range, 4 B per cell of all objects); every call first waits
+ * last object's range, 4 B per cell and 37 B per gradient tile of 15 x 15
+ * texels of all objects); every call first waits
  * (host) for the plan's earlier launches, which may read the sort, and
  * finally for the sort itself (it reads back how many tiles hold a cell of
  * more than 32 queries, which the backward sums by a kernel of their own).
