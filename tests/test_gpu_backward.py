@@ -231,10 +231,11 @@ def test_backward_sort_ready_sparse(N, Q):
         assert np.abs(gl - rl).max() / scale < LUT_TOL
 
 
-@pytest.mark.parametrize("N", [100, 512])
+@pytest.mark.parametrize("N", [100, 150, 512])
 def test_backward_three_radix_passes(N):
     """Cell keys above 2^16 take three 8-bit radix passes (N >= 105 for one
-    object); N = 100 takes two."""
+    object: N = 150 with 18-bit keys, N = 512 with 21-bit keys); N = 100
+    takes two."""
     r = rng(10 + N)
     lut = workloads.random_lut(N, r)
     Q = 30000
