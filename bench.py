@@ -392,7 +392,10 @@ def main():
         cpu, errs, oracle_forms, extra = cpu_baseline_leg(c_np, dirs_np, out, sample_out, keys2)
         result["cpu_baseline"] = cpu
         for k, v in errs.items():
-            forms.setdefault(k, {})["err_vs_fp64"] = v
+            if k == "batched_backward" and "backward_f32_texel" in forms.get("batched", {}):
+                forms["batched"]["backward_f32_texel"]["err_vs_fp64"] = v
+            else:
+                forms.setdefault(k, {})["err_vs_fp64"] = v
         for k, v in oracle_forms.items():
             forms.setdefault(k, {})["cpu_oracle"] = v
         result.update(extra)
@@ -823,6 +826,26 @@ def run_batched():
     plan_t.backward(lut_t, dirs, g_b, gl_b, gd_b)
     ms_bwd_t = t_gpu(lambda: plan_t.backward(lut_t, dirs, g_b, gl_b, gd_b), 5)
     plan_t.close()
+    # error sample of the batch's backward: per face size, the first object
+    # with at most 20,000 queries, and the object with the most queries per
+    # cell among those with at most 200,000 (dense tiles)
+    Ns_all, Qs_all = np.asarray(spec["N"]), np.asarray(Qs)
+    pick = []
+    for Nn in sorted(set(int(x) for x in Ns_all)):
+        cand = np.nonzero((Ns_all == Nn) & (Qs_all <= 20000))[0]
+        if cand.size:
+            pick.append(int(cand[0]))
+    dens = Qs_all / (6.0 * (Ns_all + 1) ** 2)
+    dens[Qs_all > 200000] = -1
+    pick.append(int(np.argmax(dens)))
+    bwd_smp = []
+    for o in pick:
+        off, Nn, q0, q = objs_t[o]
+        ne = 6 * (Nn + 2) ** 2 * 4
+        bwd_smp.append({"o": o, "N": Nn, "lut": lut_t[off:off + ne].reshape(6, Nn + 2, Nn + 2, 4).cpu().numpy(),
+                        "dirs": dirs[q0:q0 + q].cpu().numpy(), "g": g_b[q0:q0 + q].cpu().numpy(),
+                        "gl": gl_b[off:off + ne].reshape(6, Nn + 2, Nn + 2, 4).cpu().numpy(),
+                        "gd": gd_b[q0:q0 + q].cpu().numpy()})
     del g_b, gl_b, gd_b
     backward_plan = {"sort_ms": ms_sort_t, "forward_f32_texel_ms": ms_fwd_t, "backward_ms": ms_bwd_t,
                      "bwd_over_fwd": ms_bwd_t / ms_fwd_t}
@@ -842,7 +865,7 @@ def run_batched():
            # every object's FP32 texel LUT (the data the FP16 cells encode), for the oracle's timing
            "lut_tex": B["lut_tex"].cpu().numpy(), "texel_off": np.asarray(B["texel_off"], np.int64),
            "N_all": np.asarray(spec["N"], np.int32), "qb_all": np.asarray(qb, np.int64),
-           "q_all": np.asarray(Qs, np.int64), "dirs_all": B["dirs_np"]}
+           "q_all": np.asarray(Qs, np.int64), "dirs_all": B["dirs_np"], "backward": bwd_smp}
     plan.close()
     return res, smp
 
@@ -1051,6 +1074,22 @@ def cpu_baseline_leg(c_np, dirs_np, out_cell, sample, keys2):
             d_all.append(s["dirs"][q0:q0 + q])
             q0 += q
         errs["batched"] = stats(np.concatenate(o_all), np.concatenate(r_all), np.concatenate(d_all))
+        # the batch's backward (plan of FP32 TEXEL LUTs) on sampled objects
+        # against the oracle's FP64 backward of each object alone
+        if s.get("backward"):
+            lmax, dmax, nq = 0.0, 0.0, 0
+            for b in s["backward"]:
+                rl, rd = oracle.backward(b["lut"], b["dirs"], b["g"])
+                lmax = max(lmax, float(np.abs(b["gl"] - rl).max() / max(np.abs(rl).max(), 1e-30)))
+                ok = np.isfinite(rd[:, 0])
+                gn = np.linalg.norm(rd[ok], axis=1)
+                if gn.size:
+                    e = np.linalg.norm(b["gd"][ok] - rd[ok], axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))
+                    dmax = max(dmax, float(e.max()))
+                nq += int(b["dirs"].shape[0])
+            errs["batched_backward"] = {"objects": [int(b["o"]) for b in s["backward"]],
+                                        "face_sizes": [int(b["N"]) for b in s["backward"]], "queries": nq,
+                                        "lut_grad_max_rel_to_max": lmax, "dirs_grad_max_rel": dmax}
         # the oracle's batched query over all 4,096 objects (FP64 copies of the
         # GPU-baked FP32 texel LUTs, the data the FP16 cells encode)
         if "lut_tex" in s:
