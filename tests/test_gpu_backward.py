@@ -99,6 +99,21 @@ def test_backward_dirs_use_each_querys_object(n, qpo):
         assert (np.linalg.norm(gd[sl] - rd, axis=1) / np.maximum(gn, floor)).max() < DIRS_TOL, o
 
 
+@pytest.mark.parametrize("N,Q", [(1, 1), (1, 2), (3, 5), (2, 4097)])
+def test_backward_tiny_inputs(N, Q):
+    """The smallest sorts: one query, two, a face of one cell, and a query
+    count one past a radix tile (4,096 keys); against the oracle."""
+    r = rng(80 + Q)
+    lut = workloads.random_lut(N, r)
+    dirs = workloads.uniform_dirs(Q, r)
+    g = r.standard_normal((Q, 4)).astype(np.float32)
+    gl, gd = run_bwd(lut, dirs, g)
+    rl, rd = oracle.backward(lut, dirs, g)
+    assert np.abs(gl - rl).max() <= LUT_TOL * max(np.abs(rl).max(), 1e-30)
+    gn = np.linalg.norm(rd, axis=1)
+    assert (np.linalg.norm(gd - rd, axis=1) / np.maximum(gn, np.sqrt(np.mean(gn ** 2)))).max() < DIRS_TOL
+
+
 def test_backward_few_queries_long_empty_runs():
     """Cell starts where long runs of cells hold no query: a few directions
     on faces +Y and -Z of two N = 200 objects (40,401 cells per face), so the
