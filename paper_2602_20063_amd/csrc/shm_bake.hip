@@ -369,34 +369,47 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // ... and part 3: stored as whole 128 B rows; rows is a multiple of 4, so a
 // group of four columns is wholly inside or outside the table
 // cst[q] is the l = 0 term of object row q, added to the value channel (the
-// first of each group of four columns: a texel's channels)
+// first of each group of four columns: a texel's channels).  The stores are
+// buffer stores over the wave's own object rows: a store outside the table
+// (an object row past n_obj, columns past rows) gets an offset past the
+// buffer's end, which the hardware drops.  No branch guards a store, so the
+// compiler's count of memory operations in flight stays exact and the loop
+// does not wait for its stores to finish.
 template <bool F16OUT>
 __device__ __forceinline__ void g2_store(float4 (&v)[4], const float (&cst)[4], int64_t o0, int64_t n_obj,
                                          int64_t col0, int64_t rows, int lane, void* __restrict__ lut)
 {
+    constexpr int ES = F16OUT ? 2 : 4;  // bytes per output element
     const int64_t col = col0 + 4 * (lane & 7);
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q].x += cst[q];
     // an empty statement that takes every value: the LDS reads stay where
-    // they were issued instead of sinking into the guarded stores below
+    // they were issued instead of sinking into the stores below
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : : "v"(v[q].x), "v"(v[q].y), "v"(v[q].z), "v"(v[q].w));
+    // the wave's window: object rows o0 .. o0 + 31 (32 x rows x 4 B < 2^32
+    // for rows <= 6 (SHM_MAX_N + 2)^2 4)
+    const int64_t n_here = (n_obj - o0) < 32 ? (n_obj - o0) : 32;
+    char* wbase = reinterpret_cast<char*>(lut) + o0 * rows * ES;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(wbase, (short)0, (int)(uint32_t)(n_here * rows * ES), 0x00020000);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int64_t o = o0 + (lane >> 3) + 8 * q;
-        if (o < n_obj && col < rows) {
-            // non-temporal: the output lines are written once and need not
-            // displace the basis fragments the XCD's waves share in L2
-            if constexpr (F16OUT) {
-                const __half2 h0 = __floats2half2_rn(v[q].x, v[q].y), h1 = __floats2half2_rn(v[q].z, v[q].w);
-                u32x2 w;
-                w.x = *reinterpret_cast<const unsigned int*>(&h0);
-                w.y = *reinterpret_cast<const unsigned int*>(&h1);
-                __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(reinterpret_cast<__half*>(lut) + o * rows + col));
-            } else {
-                const floatx4 w = {v[q].x, v[q].y, v[q].z, v[q].w};
-                __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(reinterpret_cast<float*>(lut) + o * rows + col));
-            }
+        const int64_t ol = (lane >> 3) + 8 * q;  // object row in the window
+        const bool ok = ol < n_here && col < rows;
+        const uint32_t off = ok ? (uint32_t)((ol * rows + col) * ES) : 0xFFFFFFF0u;
+        // non-temporal: the output lines are written once and need not
+        // displace the basis fragments the XCD's waves share in L2
+        if constexpr (F16OUT) {
+            const __half2 h0 = __floats2half2_rn(v[q].x, v[q].y), h1 = __floats2half2_rn(v[q].z, v[q].w);
+            u32x2 w;
+            w.x = *reinterpret_cast<const unsigned int*>(&h0);
+            w.y = *reinterpret_cast<const unsigned int*>(&h1);
+            __builtin_amdgcn_raw_buffer_store_b64(w, rs, off, 0, 2);
+        } else {
+            const u32x4 w = {__float_as_uint(v[q].x), __float_as_uint(v[q].y), __float_as_uint(v[q].z),
+                             __float_as_uint(v[q].w)};
+            __builtin_amdgcn_raw_buffer_store_b128(w, rs, off, 0, 2);
         }
     }
 }
