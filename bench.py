@@ -297,7 +297,7 @@ def main():
         lut16 = shm.cells_to_f16(B["lut32"])
         outb = torch.empty((B["Qtot"], 4), device=DEV)
         plan = shm.Plan(B["objs"], shm.SHM_F16, shm.SHM_LAYOUT_CELL)
-        plan.set_shape(256, 2, 512, 4)
+        plan.set_shape(512, 2, 1024, 0)
         plan.launch(lut16, B["dirs"], outb)
         plan.probe(lut16, B["dirs"], outb)
         torch.cuda.synchronize()

@@ -259,7 +259,8 @@ typedef struct shm_launch_shape {
     int32_t block;       /* threads per workgroup: 64, 128, 256 or 512        */
     int32_t qpt;         /* queries per thread per pass: 1, 2 or 4            */
     int32_t tile;        /* queries per work item, a multiple of block * qpt  */
-    int32_t grid_per_cu; /* persistent workgroups per compute unit, 1..32     */
+    int32_t grid_per_cu; /* persistent workgroups per compute unit, 1..32;    */
+                         /* 0: one workgroup per work item (no persistence)  */
 } shm_launch_shape;
 
 /* Validates the descriptors (N in range, lut_offset >= 0 and aligned for

@@ -225,7 +225,7 @@ static int check_shape(const shm_launch_shape& s)
     if (!(s.qpt == 1 || s.qpt == 2 || s.qpt == 4)) return fail(SHM_ERR_INVALID_ARG, "shape.qpt must be 1, 2 or 4");
     if (s.tile <= 0 || s.tile % (s.block * s.qpt) != 0 || s.tile > (1 << 24))
         return fail(SHM_ERR_INVALID_ARG, "shape.tile must be a positive multiple of block*qpt (<= 2^24)");
-    if (s.grid_per_cu < 1 || s.grid_per_cu > 32) return fail(SHM_ERR_INVALID_ARG, "shape.grid_per_cu must be 1..32");
+    if (s.grid_per_cu < 0 || s.grid_per_cu > 32) return fail(SHM_ERR_INVALID_ARG, "shape.grid_per_cu must be 0..32");
     return SHM_OK;
 }
 
@@ -565,7 +565,8 @@ int shm_plan_autotune(shm_plan* plan, const void* lut, const float* dirs, float*
     for (int block : {256, 512})
         for (int qpt : {1, 2, 4})
             for (int mult : {1, 4, 16})
-                for (int gpc : {4, 8, 16}) cands.push_back(shm_launch_shape{block, qpt, block * qpt * mult, gpc});
+                for (int gpc : {0, 4, 8, 16})  // 0: one workgroup per work item
+                    if (gpc > 0 || mult < 16) cands.push_back(shm_launch_shape{block, qpt, block * qpt * mult, gpc});
     hipEvent_t e0 = plan->t0, e1 = plan->t1;
     float best_ms = 1e30f;
     shm_launch_shape best = plan->shape;

@@ -417,8 +417,11 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
                             hipStream_t stream)
 {
     if (n_items == 0) return SHM_OK;
-    int64_t G = (int64_t)shape.grid_per_cu * n_cu;
+    // grid_per_cu 0: one workgroup per work item (each runs its item and
+    // exits: no store of one item waits behind the loads of the next)
+    int64_t G = shape.grid_per_cu == 0 ? n_items : (int64_t)shape.grid_per_cu * n_cu;
     if (G > n_items) G = n_items;
+    if (G > 0x7fffffff) G = 0x7fffffff;
     const dim3 grid((unsigned)G), block((unsigned)shape.block);
     const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL, nrm = normal != nullptr;
 #define SHM_P(a, b, c) launch_persistent_t<a, b, c>(shape.qpt, grid, block, stream, lut, objs_dev, items_dev, split, dirs, out, normal)

@@ -71,12 +71,30 @@ def test_plan_matches_oracle_and_shapes():
                                [o[0] // 4 for o in objs], [o[1] for o in objs], [o[2] for o in objs],
                                [o[3] for o in objs], dirs)
     plan = shm.Plan(objs, shm.SHM_F32)
-    for shape in [(64, 1, 64, 1), (256, 2, 512, 8), (512, 4, 2048, 16), (128, 1, 128 * 7, 3)]:
+    # grid_per_cu 0: one workgroup per work item
+    for shape in [(64, 1, 64, 1), (256, 2, 512, 8), (512, 4, 2048, 16), (128, 1, 128 * 7, 3), (256, 1, 256, 0),
+                  (64, 4, 512, 0)]:
         plan.set_shape(*shape)
         out = torch.full((dirs.shape[0], 4), float("nan"), device=DEV)
         plan.launch(lut_t, d_t, out)
         torch.cuda.synchronize()
         check_value_grad(out.cpu().numpy(), ref, f"shape {shape}")
+    plan.close()
+
+
+def test_set_shape_refuses_bad_shapes():
+    """A shape is checked before the work list is rebuilt: block, queries per
+    lane, a tile that is no multiple of block * qpt, workgroups per CU
+    outside 0..32; the plan keeps its shape and still answers."""
+    flat, objs, dirs = build_batch(4, 3)
+    plan = shm.Plan(objs, shm.SHM_F32)
+    for bad in [(100, 1, 100, 4), (256, 3, 768, 4), (256, 2, 500, 4), (256, 1, 256, -1), (256, 1, 256, 33)]:
+        with pytest.raises(shm.ShmError):
+            plan.set_shape(*bad)
+    out = torch.full((dirs.shape[0], 4), float("nan"), device=DEV)
+    plan.launch(torch.as_tensor(flat).to(DEV), torch.as_tensor(dirs).to(DEV), out)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).any()
     plan.close()
 
 
