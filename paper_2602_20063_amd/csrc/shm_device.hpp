@@ -26,6 +26,7 @@ namespace shm {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 
 __device__ __forceinline__ float4 ld_f4(const float4* p)
 {
@@ -90,6 +91,7 @@ __device__ __forceinline__ float dir_prescale(float ma)
 // The unit vector d/|d| of a nonzero finite d of any magnitude.
 __device__ __forceinline__ float3 unit_dir(float x, float y, float z)
 {
+#pragma clang fp contract(on)
     const float k = dir_prescale(fmaxf(fabsf(x), fmaxf(fabsf(y), fabsf(z))));
     x *= k;
     y *= k;
@@ -106,27 +108,12 @@ __device__ __forceinline__ Loc locate_t(float x, float y, float z, int N)
     const float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
     const bool isx = (ax >= ay) && (ax >= az);
     const bool isy = !isx && (ay >= az);
-    float sc, tc, ma;
-    int face;
-    if (isx) {
-        const bool pos = x >= 0.0f;
-        face = pos ? 0 : 1;
-        ma = ax;
-        sc = pos ? -z : z;
-        tc = -y;
-    } else if (isy) {
-        const bool pos = y >= 0.0f;
-        face = pos ? 2 : 3;
-        ma = ay;
-        sc = x;
-        tc = pos ? z : -z;
-    } else {
-        const bool pos = z >= 0.0f;
-        face = pos ? 4 : 5;
-        ma = az;
-        sc = pos ? x : -x;
-        tc = -y;
-    }
+    // selects, not branches: a branch would wait for every load in flight
+    const bool pos = (isx ? x : (isy ? y : z)) >= 0.0f;
+    int face = (isx ? 0 : (isy ? 2 : 4)) + (pos ? 0 : 1);
+    float ma = isx ? ax : (isy ? ay : az);
+    float sc = isx ? (pos ? -z : z) : (isy ? x : (pos ? x : -x));
+    float tc = isy ? (pos ? z : -z) : -y;
     const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && (ma > 0.0f);
     if (!FAST) {
         // a major axis below 2^-64 (subnormal ones included) is scaled by
@@ -187,84 +174,153 @@ __device__ __forceinline__ float4 h4_to_f4(uint2 h)
     return make_float4(a.x, a.y, b.x, b.y);
 }
 
-// TEXEL layout, FP32: two rows of two texels (2 x 32 B).
-__device__ __forceinline__ Foot load_texel_f32(const float* __restrict__ lut, int N, const Loc& L)
+// A footprint as loaded, before any conversion: FP32 layouts load the four
+// corners as they are; FP16 cells load two 16 B halves, FP16 texels four 8 B
+// corners.  decode() turns it into the 16 FP32 scalars.
+template <bool FP16, bool CELL>
+struct FootRaw {
+    float4 c[4];
+};
+template <>
+struct FootRaw<true, true> {
+    uint4 q[2];
+};
+template <>
+struct FootRaw<true, false> {
+    uint2 h[4];
+};
+
+// TEXEL layout: two rows of two texels (2 x 32 B in FP32, 2 x 16 B in FP16).
+__device__ __forceinline__ FootRaw<false, false> load_raw_texel_f32(const float* __restrict__ lut, int N, const Loc& L)
 {
     const int P = N + 2;
     const int64_t row0 = ((int64_t)(L.face * P + L.j0) * P + L.i0) * 4;
     const float4* p0 = reinterpret_cast<const float4*>(lut + row0);
     const float4* p1 = reinterpret_cast<const float4*>(lut + row0 + (int64_t)P * 4);
-    Foot F;
-    F.c[0] = *(p0);
-    F.c[1] = *(p0 + 1);
-    F.c[2] = *(p1);
-    F.c[3] = *(p1 + 1);
-    return F;
+    FootRaw<false, false> R;
+    R.c[0] = *(p0);
+    R.c[1] = *(p0 + 1);
+    R.c[2] = *(p1);
+    R.c[3] = *(p1 + 1);
+    return R;
 }
 
-__device__ __forceinline__ Foot load_texel_f16(const __half* __restrict__ lut, int N, const Loc& L)
+__device__ __forceinline__ FootRaw<true, false> load_raw_texel_f16(const __half* __restrict__ lut, int N, const Loc& L)
 {
     const int P = N + 2;
     const int64_t row0 = ((int64_t)(L.face * P + L.j0) * P + L.i0) * 4;
     const uint2* p0 = reinterpret_cast<const uint2*>(lut + row0);
     const uint2* p1 = reinterpret_cast<const uint2*>(lut + row0 + (int64_t)P * 4);
-    Foot F;
-    F.c[0] = h4_to_f4(*(p0));
-    F.c[1] = h4_to_f4(*(p0 + 1));
-    F.c[2] = h4_to_f4(*(p1));
-    F.c[3] = h4_to_f4(*(p1 + 1));
-    return F;
+    FootRaw<true, false> R;
+    R.h[0] = *(p0);
+    R.h[1] = *(p0 + 1);
+    R.h[2] = *(p1);
+    R.h[3] = *(p1 + 1);
+    return R;
 }
 
 // CELL layout: one contiguous, aligned block per cell.
-__device__ __forceinline__ Foot load_cell_f32(const float* __restrict__ lut, int N, const Loc& L)
+__device__ __forceinline__ FootRaw<false, true> load_raw_cell_f32(const float* __restrict__ lut, int N, const Loc& L)
 {
     const int C = N + 1;
     const int64_t cell = (int64_t)(L.face * C + L.j0) * C + L.i0;
     const float4* p = reinterpret_cast<const float4*>(lut + cell * 16);
-    Foot F;
-    F.c[0] = ld_f4(p);
-    F.c[1] = ld_f4(p + 1);
-    F.c[2] = ld_f4(p + 2);
-    F.c[3] = ld_f4(p + 3);
-    return F;
+    FootRaw<false, true> R;
+    R.c[0] = ld_f4(p);
+    R.c[1] = ld_f4(p + 1);
+    R.c[2] = ld_f4(p + 2);
+    R.c[3] = ld_f4(p + 3);
+    return R;
 }
 
-// FP16 cell encoding: corner 0 stores (r, r_u h, r_v h, r_uv h^2); corners
-// 1..3 store the value r as its difference from corner 0's r.  Derivatives of
-// the patch weigh the corner values by basis functions that sum to zero, so
-// the rounding of corner 0's r cancels from them exactly and only the
-// (small) differences are rounded: the gradient keeps FP16's relative
-// precision instead of losing a factor ~N to the value's rounding.
-__device__ __forceinline__ Foot load_cell_f16(const __half* __restrict__ lut, int N, const Loc& L)
+__device__ __forceinline__ FootRaw<true, true> load_raw_cell_f16(const __half* __restrict__ lut, int N, const Loc& L)
 {
     const int C = N + 1;
     const int64_t cell = (int64_t)(L.face * C + L.j0) * C + L.i0;
     const uint4* p = reinterpret_cast<const uint4*>(lut + cell * 16);
-    const uint4 q0 = ld_u4(p);
-    const uint4 q1 = ld_u4(p + 1);
+    FootRaw<true, true> R;
+    R.q[0] = ld_u4(p);
+    R.q[1] = ld_u4(p + 1);
+    return R;
+}
+
+template <bool FP16, bool CELL>
+__device__ __forceinline__ FootRaw<FP16, CELL> load_raw(const void* __restrict__ lut, int N, const Loc& L)
+{
+    if constexpr (CELL) {
+        if constexpr (FP16) return load_raw_cell_f16(reinterpret_cast<const __half*>(lut), N, L);
+        else return load_raw_cell_f32(reinterpret_cast<const float*>(lut), N, L);
+    } else {
+        if constexpr (FP16) return load_raw_texel_f16(reinterpret_cast<const __half*>(lut), N, L);
+        else return load_raw_texel_f32(reinterpret_cast<const float*>(lut), N, L);
+    }
+}
+
+template <bool FP16, bool CELL>
+__device__ __forceinline__ Foot decode(const FootRaw<FP16, CELL>& R)
+{
+#pragma clang fp contract(on)
     Foot F;
-    F.c[0] = h4_to_f4(make_uint2(q0.x, q0.y));
-    F.c[1] = h4_to_f4(make_uint2(q0.z, q0.w));
-    F.c[2] = h4_to_f4(make_uint2(q1.x, q1.y));
-    F.c[3] = h4_to_f4(make_uint2(q1.z, q1.w));
-    F.c[1].x += F.c[0].x;
-    F.c[2].x += F.c[0].x;
-    F.c[3].x += F.c[0].x;
+    if constexpr (!FP16) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F.c[c] = R.c[c];
+    } else if constexpr (!CELL) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F.c[c] = h4_to_f4(R.h[c]);
+    } else {
+        // FP16 cell encoding: corner 0 stores (r, r_u h, r_v h, r_uv h^2);
+        // corners 1..3 store the value r as its difference from corner 0's
+        // r.  Derivatives of the patch weigh the corner values by basis
+        // functions that sum to zero, so the rounding of corner 0's r cancels
+        // from them exactly and only the (small) differences are rounded:
+        // the gradient keeps FP16's relative precision instead of losing a
+        // factor ~N to the value's rounding.
+        F.c[0] = h4_to_f4(make_uint2(R.q[0].x, R.q[0].y));
+        F.c[1] = h4_to_f4(make_uint2(R.q[0].z, R.q[0].w));
+        F.c[2] = h4_to_f4(make_uint2(R.q[1].x, R.q[1].y));
+        F.c[3] = h4_to_f4(make_uint2(R.q[1].z, R.q[1].w));
+        F.c[1].x += F.c[0].x;
+        F.c[2].x += F.c[0].x;
+        F.c[3].x += F.c[0].x;
+    }
     return F;
+}
+
+// An empty statement that takes (and may change) a loaded footprint's
+// registers: code after it cannot start before the load is issued.
+__device__ __forceinline__ void pin(FootRaw<true, true>& R)
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i) asm volatile("" : "+v"(R.q[i].x), "+v"(R.q[i].y), "+v"(R.q[i].z), "+v"(R.q[i].w));
+}
+__device__ __forceinline__ void pin(FootRaw<true, false>& R)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(R.h[i].x), "+v"(R.h[i].y));
+}
+template <bool CELL>
+__device__ __forceinline__ void pin(FootRaw<false, CELL>& R)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(R.c[i].x), "+v"(R.c[i].y), "+v"(R.c[i].z), "+v"(R.c[i].w));
+}
+__device__ __forceinline__ void pin(Foot& F)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(F.c[i].x), "+v"(F.c[i].y), "+v"(F.c[i].z), "+v"(F.c[i].w));
 }
 
 template <bool FP16, bool CELL>
 __device__ __forceinline__ Foot load_foot(const void* __restrict__ lut, int N, const Loc& L)
 {
-    if constexpr (CELL) {
-        if constexpr (FP16) return load_cell_f16(reinterpret_cast<const __half*>(lut), N, L);
-        else return load_cell_f32(reinterpret_cast<const float*>(lut), N, L);
-    } else {
-        if constexpr (FP16) return load_texel_f16(reinterpret_cast<const __half*>(lut), N, L);
-        else return load_texel_f32(reinterpret_cast<const float*>(lut), N, L);
-    }
+    return decode<FP16, CELL>(load_raw<FP16, CELL>(lut, N, L));
 }
+
+// The arithmetic from a loaded footprint to a result fuses a multiply into an
+// add only where one source expression holds both (fp contract(on) in each
+// function below), never across statements as the code generator would
+// choose it: every kernel that calls these functions then gives the same
+// bits for the same inputs, whatever code surrounds the call.
 
 // Cubic Hermite basis on [0,1], Eq. (3): only H1, H0d, H1d are needed
 // (H0 = 1 - H1) plus first derivatives (H0' = -H1').
@@ -275,6 +331,7 @@ struct Basis1 {
 
 __device__ __forceinline__ Basis1 basis1(float s)
 {
+#pragma clang fp contract(on)
     Basis1 B;
     const float s2 = s * s;
     B.h1 = s2 * (3.0f - 2.0f * s);          // -2s^3 + 3s^2
@@ -295,6 +352,7 @@ struct Patch {
 // weighted, so chart derivatives keep full relative accuracy at large N.
 __device__ __forceinline__ Patch hermite(const Foot& F, float s, float t)
 {
+#pragma clang fp contract(on)
     const Basis1 S = basis1(s), T = basis1(t);
     const float4 c00 = F.c[0], c10 = F.c[1], c01 = F.c[2], c11 = F.c[3];
     // differences along s (rows j = 0, 1) and along t (columns i = 0, 1)
@@ -327,6 +385,7 @@ struct Patch2 {
 // backward.  H1'' = 6 - 12s, (H0^d)'' = 6s - 4, (H1^d)'' = 6s - 2.
 __device__ __forceinline__ Patch2 hermite2(const Foot& F, float s, float t)
 {
+#pragma clang fp contract(on)
     const Basis1 S = basis1(s), T = basis1(t);
     const float e1s = 6.0f - 12.0f * s, e0ds = 6.0f * s - 4.0f, e1ds = 6.0f * s - 2.0f;
     const float e1t = 6.0f - 12.0f * t, e0dt = 6.0f * t - 4.0f, e1dt = 6.0f * t - 2.0f;
@@ -375,6 +434,7 @@ __device__ __forceinline__ void frame_of(int face, float3& M, float3& S, float3&
 template <bool FAST>
 __device__ __forceinline__ float3 transport_t(int face, float a, float b, float ru, float rv)
 {
+#pragma clang fp contract(on)
     const float rho2 = 1.0f + a * a + b * b;
     const float rho = FAST ? __builtin_amdgcn_sqrtf(rho2) : sqrtf(rho2);
     const float k = 0.5f * rho;
@@ -399,10 +459,23 @@ __device__ __forceinline__ float3 transport(int face, float a, float b, float ru
 // Eq. (10)
 __device__ __forceinline__ float3 normal_of(float R, float x, float y, float z, float3 g)
 {
+#pragma clang fp contract(on)
     const float3 w = unit_dir(x, y, z);
     const float mx = R * w.x - g.x, my = R * w.y - g.y, mz = R * w.z - g.z;
     const float in = rsqrtf(mx * mx + my * my + mz * mz);
     return make_float3(mx * in, my * in, mz * in);
+}
+
+// The query's arithmetic after its loads: (r, grad r) from the footprint of
+// a valid location.
+template <bool FAST = false>
+__device__ __forceinline__ float4 query_eval(const Foot& F, const Loc& L, int N)
+{
+#pragma clang fp contract(on)
+    const Patch P = hermite(F, L.s, L.t);
+    const float Nf = (float)N;
+    const float3 g = transport_t<FAST>(L.face, L.a, L.b, Nf * P.rs, Nf * P.rt);
+    return make_float4(P.r, g.x, g.y, g.z);
 }
 
 // Full query: returns (R, gx, gy, gz); NaN for an invalid direction.
@@ -412,10 +485,27 @@ __device__ __forceinline__ float4 query_one(const void* __restrict__ lut, int N,
     const Loc L = locate_t<FAST>(x, y, z, N);
     if (L.face < 0) return make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
     const Foot F = load_foot<FP16, CELL>(lut, N, L);
-    const Patch P = hermite(F, L.s, L.t);
-    const float Nf = (float)N;
-    const float3 g = transport_t<FAST>(L.face, L.a, L.b, Nf * P.rs, Nf * P.rt);
-    return make_float4(P.r, g.x, g.y, g.z);
+    return query_eval<FAST>(F, L, N);
+}
+
+// The same query in two halves with no branch between them, for kernels that
+// issue the loads of several queries before any of their arithmetic:
+// query_load reads the footprint of L's cell (of face 0 for an invalid
+// direction: i0, j0 are always clamped to [0, N], so the address stays in the
+// LUT), query_finish on its decoded form gives query_one's result bit for bit.
+template <bool FP16, bool CELL>
+__device__ __forceinline__ FootRaw<FP16, CELL> query_load(const void* __restrict__ lut, int N, const Loc& L)
+{
+    Loc Ls = L;
+    Ls.face = L.face < 0 ? 0 : L.face;
+    return load_raw<FP16, CELL>(lut, N, Ls);
+}
+
+__device__ __forceinline__ float4 query_finish(const Foot& F, const Loc& L, int N)
+{
+    const float4 r = query_eval(F, L, N);
+    const float nan = __builtin_nanf("");
+    return L.face < 0 ? make_float4(nan, nan, nan, nan) : r;
 }
 
 // Rendered radius (Sec. 3.1) from (r, grad r): R = s r, or for a signed
@@ -423,6 +513,7 @@ __device__ __forceinline__ float4 query_one(const void* __restrict__ lut, int N,
 // sign(0) = 0).  *sgn gets sign(r); NaN input stays NaN.
 __device__ __forceinline__ float4 rendered(float4 q, float scale, bool is_signed, int* sgn)
 {
+#pragma clang fp contract(on)
     const float r = q.x;
     const int sg = r > 0.0f ? 1 : (r < 0.0f ? -1 : 0);
     *sgn = sg;

@@ -49,6 +49,25 @@ struct XcdSplit {
     int64_t b[9];
 };
 
+// Grid of a plan launch.  grid_per_cu > 0: a persistent grid of that many
+// workgroups per CU (at most one per item).  grid_per_cu 0: one workgroup
+// per work item; the slices hold (nearly) equal query counts, not item
+// counts, so each XCD gets as many workgroups as the largest slice has items
+// and none walks a second item (those of smaller slices exit at once).
+inline int64_t plan_grid(const shm_launch_shape& shape, int n_cu, int64_t n_items, const XcdSplit& split)
+{
+    int64_t G;
+    if (shape.grid_per_cu == 0 && n_items >= 8) {
+        int64_t most = 0;
+        for (int s = 0; s < 8; ++s) most = split.b[s + 1] - split.b[s] > most ? split.b[s + 1] - split.b[s] : most;
+        G = 8 * most;
+    } else {
+        G = shape.grid_per_cu == 0 ? n_items : (int64_t)shape.grid_per_cu * n_cu;
+        if (G > n_items) G = n_items;
+    }
+    return G > 0x7fffffff ? 0x7fffffff : G;
+}
+
 // device copy of a host shm_object (same layout)
 static_assert(sizeof(shm_object) == 32, "shm_object layout");
 

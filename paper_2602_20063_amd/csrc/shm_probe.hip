@@ -100,40 +100,40 @@ __device__ __forceinline__ uint32_t probe_pick(int64_t q, uint32_t seed, uint32_
     return (uint32_t)(((uint64_t)h * n) >> 32);
 }
 
-// The footprint loads of one query at cell (face, j0, i0) of a LUT of face
-// size N, as the query issues them, folded into a 32-bit word sum.
-template <bool FP16, bool CELL>
-__device__ __forceinline__ uint32_t probe_footprint(const char* __restrict__ base, int N, uint32_t cell)
+// The cell (face, j0, i0) of index `cell` of a LUT of face size N, as the
+// location the query's footprint loads take.
+__device__ __forceinline__ Loc probe_loc(int N, uint32_t cell)
 {
-    uint32_t acc = 0;
-    if constexpr (CELL) {
-        const uint4* p = reinterpret_cast<const uint4*>(base) + (int64_t)cell * (FP16 ? 2 : 4);
+    const uint32_t C = (uint32_t)N + 1;
+    Loc L{};
+    L.face = (int)(cell / (C * C));
+    const uint32_t rem = cell - (uint32_t)L.face * C * C;
+    L.j0 = (int)(rem / C);
+    L.i0 = (int)(rem - (uint32_t)L.j0 * C);
+    return L;
+}
+
+// A loaded footprint folded into a 32-bit word sum.
+__device__ __forceinline__ uint32_t raw_sum(const FootRaw<true, true>& R)
+{
+    return R.q[0].x + R.q[0].y + R.q[0].z + R.q[0].w + R.q[1].x + R.q[1].y + R.q[1].z + R.q[1].w;
+}
+__device__ __forceinline__ uint32_t raw_sum(const FootRaw<true, false>& R)
+{
+    uint32_t a = 0;
 #pragma unroll
-        for (int k = 0; k < (FP16 ? 2 : 4); ++k) {
-            const uint4 v = p[k];
-            acc += v.x + v.y + v.z + v.w;
-        }
-    } else {
-        const int C = N + 1, P = N + 2;
-        const int face = (int)(cell / (uint32_t)(C * C));
-        const int rem = (int)(cell - (uint32_t)face * (uint32_t)(C * C));
-        const int j0 = rem / C, i0 = rem - j0 * C;
-        const int64_t t0 = (int64_t)(face * P + j0) * P + i0;  // texel (i0, j0); the row above is t0 + P
+    for (int i = 0; i < 4; ++i) a += R.h[i].x + R.h[i].y;
+    return a;
+}
+template <bool CELL>
+__device__ __forceinline__ uint32_t raw_sum(const FootRaw<false, CELL>& R)
+{
+    uint32_t a = 0;
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int64_t t = t0 + r * P;
-            if constexpr (FP16) {
-                const uint2* p = reinterpret_cast<const uint2*>(base) + t;
-                const uint2 a = p[0], b = p[1];
-                acc += a.x + a.y + b.x + b.y;
-            } else {
-                const uint4* p = reinterpret_cast<const uint4*>(base) + t;
-                const uint4 a = p[0], b = p[1];
-                acc += a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w;
-            }
-        }
-    }
-    return acc;
+    for (int i = 0; i < 4; ++i)
+        a += __float_as_uint(R.c[i].x) + __float_as_uint(R.c[i].y) + __float_as_uint(R.c[i].z) +
+             __float_as_uint(R.c[i].w);
+    return a;
 }
 
 template <bool FP16, bool CELL, int QPT>
@@ -155,27 +155,53 @@ __global__ void k_probe_plan(const void* __restrict__ lut, const shm_object* __r
         const int N = o.N;
         const uint32_t n_cells = 6u * (uint32_t)(N + 1) * (uint32_t)(N + 1);
         const char* base = reinterpret_cast<const char*>(lut) + (size_t)o.lut_offset * (FP16 ? 2 : 4);
+        // the structure of k_query_persistent, its loads in the same order:
+        // the directions, then (after them, as the query needs the direction
+        // to find its cell) the footprints
+        if constexpr (QPT == 1) {
+            for (int k0 = 0; k0 < it.n; k0 += B) {
+                const int k = k0 + (int)threadIdx.x;
+                if (k >= it.n) continue;
+                const int64_t q = it.q0 + k;
+                float dx = __builtin_nontemporal_load(dirs + 3 * q);
+                float dy = __builtin_nontemporal_load(dirs + 3 * q + 1);
+                float dz = __builtin_nontemporal_load(dirs + 3 * q + 2);
+                asm volatile("" : "+v"(dx), "+v"(dy), "+v"(dz));
+                const FootRaw<FP16, CELL> F = load_raw<FP16, CELL>(base, N, probe_loc(N, probe_pick(q, seed, n_cells)));
+                __builtin_nontemporal_store(f32x4{dx, dy, dz, __uint_as_float(raw_sum(F))},
+                                            reinterpret_cast<f32x4*>(out) + q);
+            }
+            continue;
+        }
+        // QPT > 1: every load of the lane's QPT queries issued before any
+        // use, no branch, results stored through a buffer range of the
+        // item's it.n rows (idle lanes' stores dropped)
+        const __amdgpu_buffer_rsrc_t ro =
+            __builtin_amdgcn_make_buffer_rsrc(out + 4 * it.q0, (short)0, it.n * 16, 0x00020000);
         for (int k0 = 0; k0 < it.n; k0 += B * QPT) {
             float dx[QPT], dy[QPT], dz[QPT];
-            int64_t qq[QPT];
-            bool act[QPT];
+            FootRaw<FP16, CELL> F[QPT];
 #pragma unroll
             for (int j = 0; j < QPT; ++j) {
                 const int k = k0 + j * B + (int)threadIdx.x;
-                act[j] = k < it.n;
-                qq[j] = it.q0 + k;
-                if (act[j]) {
-                    dx[j] = __builtin_nontemporal_load(dirs + 3 * qq[j]);
-                    dy[j] = __builtin_nontemporal_load(dirs + 3 * qq[j] + 1);
-                    dz[j] = __builtin_nontemporal_load(dirs + 3 * qq[j] + 2);
-                }
+                const int64_t q = it.q0 + (k < it.n ? k : 0);
+                dx[j] = __builtin_nontemporal_load(dirs + 3 * q);
+                dy[j] = __builtin_nontemporal_load(dirs + 3 * q + 1);
+                dz[j] = __builtin_nontemporal_load(dirs + 3 * q + 2);
             }
 #pragma unroll
+            for (int j = 0; j < QPT; ++j) asm volatile("" : "+v"(dx[j]), "+v"(dy[j]), "+v"(dz[j]));
+#pragma unroll
+            for (int j = 0; j < QPT; ++j)
+                F[j] = load_raw<FP16, CELL>(base, N, probe_loc(N, probe_pick(it.q0 + k0 + j * B + (int)threadIdx.x,
+                                                                             seed, n_cells)));
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) pin(F[j]);
+#pragma unroll
             for (int j = 0; j < QPT; ++j) {
-                if (!act[j]) continue;
-                const uint32_t acc = probe_footprint<FP16, CELL>(base, N, probe_pick(qq[j], seed, n_cells));
-                __builtin_nontemporal_store(f32x4{dx[j], dy[j], dz[j], __uint_as_float(acc)},
-                                            reinterpret_cast<f32x4*>(out) + qq[j]);
+                const uint32_t k = (uint32_t)(k0 + j * B + (int)threadIdx.x);
+                const u32x4 w = {__float_as_uint(dx[j]), __float_as_uint(dy[j]), __float_as_uint(dz[j]), raw_sum(F[j])};
+                __builtin_amdgcn_raw_buffer_store_b128(w, ro, k * 16u, 0, 2);
             }
         }
     }
@@ -188,9 +214,7 @@ int launch_probe_plan(const void* lut, int dtype, int layout, const shm_object* 
     if (n_items == 0) return SHM_OK;
     // grid_per_cu 0: one workgroup per work item (each runs its item and
     // exits: no store of one item waits behind the loads of the next)
-    int64_t G = shape.grid_per_cu == 0 ? n_items : (int64_t)shape.grid_per_cu * n_cu;
-    if (G > n_items) G = n_items;
-    if (G > 0x7fffffff) G = 0x7fffffff;
+    const int64_t G = plan_grid(shape, n_cu, n_items, split);
     const dim3 grid((unsigned)G), block((unsigned)shape.block);
     const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL;
 #define SHM_PP(F, C, Q) hipLaunchKernelGGL((k_probe_plan<F, C, Q>), grid, block, 0, stream, lut, objs_dev, items_dev, \

@@ -219,31 +219,71 @@ __global__ void k_query_persistent(const void* __restrict__ lut, const shm_objec
         const shm_object o = objs[it.obj];
         const int N = o.N;
         const char* base = reinterpret_cast<const char*>(lut) + (size_t)o.lut_offset * (FP16 ? 2 : 4);
+        if constexpr (QPT == 1) {
+            // one query per lane: each lane's loads are serial anyway (the
+            // direction decides the cell), and the plain form measures fastest
+            for (int k0 = 0; k0 < it.n; k0 += B) {
+                const int k = k0 + (int)threadIdx.x;
+                if (k >= it.n) continue;
+                const int64_t q = it.q0 + k;
+                const float x = ld_dir(dirs + 3 * q), y = ld_dir(dirs + 3 * q + 1), z = ld_dir(dirs + 3 * q + 2);
+                const float4 r = query_one<FP16, CELL>(base, N, x, y, z);
+                st_out(out, q, r);
+                if constexpr (NRM) {
+                    const float3 n = normal_of(r.x, x, y, z, make_float3(r.y, r.z, r.w));
+                    nrm[3 * q] = n.x;
+                    nrm[3 * q + 1] = n.y;
+                    nrm[3 * q + 2] = n.z;
+                }
+            }
+            continue;
+        }
+        // QPT queries per lane: all their loads go out before any query's
+        // arithmetic, with no branch between them (a branch ends in a wait
+        // for every load in flight), so a lane has QPT footprints in flight.
+        // The item's results are written through buffer ranges of it.n rows:
+        // the stores of idle lanes (k >= it.n) fall outside them and are
+        // dropped, so no branch guards a store (aux 2: non-temporal).
+        const __amdgpu_buffer_rsrc_t ro =
+            __builtin_amdgcn_make_buffer_rsrc(out + 4 * it.q0, (short)0, it.n * 16, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rn =
+            __builtin_amdgcn_make_buffer_rsrc(NRM ? nrm + 3 * it.q0 : out, (short)0, NRM ? it.n * 12 : 0, 0x00020000);
         for (int k0 = 0; k0 < it.n; k0 += B * QPT) {
+            // an idle lane reads the item's first direction
             float x[QPT], y[QPT], z[QPT];
-            int64_t qq[QPT];
-            bool act[QPT];
 #pragma unroll
             for (int j = 0; j < QPT; ++j) {
                 const int k = k0 + j * B + (int)threadIdx.x;
-                act[j] = k < it.n;
-                qq[j] = it.q0 + k;
-                if (act[j]) {
-                    x[j] = ld_dir(dirs + 3 * qq[j]);
-                    y[j] = ld_dir(dirs + 3 * qq[j] + 1);
-                    z[j] = ld_dir(dirs + 3 * qq[j] + 2);
-                }
+                const int64_t q = it.q0 + (k < it.n ? k : 0);
+                x[j] = ld_dir(dirs + 3 * q);
+                y[j] = ld_dir(dirs + 3 * q + 1);
+                z[j] = ld_dir(dirs + 3 * q + 2);
             }
+            // an empty statement that takes (and may change) every loaded
+            // value: no query's arithmetic can start before all the loads
+            // above are issued
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) asm volatile("" : "+v"(x[j]), "+v"(y[j]), "+v"(z[j]));
+            Loc L[QPT];
+            Foot F[QPT];
 #pragma unroll
             for (int j = 0; j < QPT; ++j) {
-                if (!act[j]) continue;
-                const float4 r = query_one<FP16, CELL>(base, N, x[j], y[j], z[j]);
-                st_out(out, qq[j], r);
+                L[j] = locate(x[j], y[j], z[j], N);
+                F[j] = decode<FP16, CELL>(query_load<FP16, CELL>(base, N, L[j]));
+            }
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) pin(F[j]);
+#pragma unroll
+            for (int j = 0; j < QPT; ++j) {
+                const uint32_t k = (uint32_t)(k0 + j * B + (int)threadIdx.x);
+                const float4 r = query_finish(F[j], L[j], N);
+                const u32x4 w = {__float_as_uint(r.x), __float_as_uint(r.y), __float_as_uint(r.z),
+                                 __float_as_uint(r.w)};
+                __builtin_amdgcn_raw_buffer_store_b128(w, ro, k * 16u, 0, 2);
                 if constexpr (NRM) {
                     const float3 n = normal_of(r.x, x[j], y[j], z[j], make_float3(r.y, r.z, r.w));
-                    nrm[3 * qq[j]] = n.x;
-                    nrm[3 * qq[j] + 1] = n.y;
-                    nrm[3 * qq[j] + 2] = n.z;
+                    const u32x3 wn = {__float_as_uint(n.x), __float_as_uint(n.y), __float_as_uint(n.z)};
+                    __builtin_amdgcn_raw_buffer_store_b96(wn, rn, k * 12u, 0, 2);
                 }
             }
         }
@@ -419,9 +459,7 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
     if (n_items == 0) return SHM_OK;
     // grid_per_cu 0: one workgroup per work item (each runs its item and
     // exits: no store of one item waits behind the loads of the next)
-    int64_t G = shape.grid_per_cu == 0 ? n_items : (int64_t)shape.grid_per_cu * n_cu;
-    if (G > n_items) G = n_items;
-    if (G > 0x7fffffff) G = 0x7fffffff;
+    const int64_t G = plan_grid(shape, n_cu, n_items, split);
     const dim3 grid((unsigned)G), block((unsigned)shape.block);
     const bool f16 = dtype == SHM_F16, cell = layout == SHM_LAYOUT_CELL, nrm = normal != nullptr;
 #define SHM_P(a, b, c) launch_persistent_t<a, b, c>(shape.qpt, grid, block, stream, lut, objs_dev, items_dev, split, dirs, out, normal)
@@ -441,7 +479,7 @@ int launch_query_persistent(const void* lut, int dtype, int layout, const shm_ob
 // TEXEL -> CELL relayout: one lane per (cell, corner), 16 B (FP32) or 8 B
 // (FP16) written contiguously.  FP16 cells hold the value channel of corners
 // 1..3 as differences from corner 0's value (FP16 cell encoding, see
-// load_cell_f16); from FP16 texels the difference is formed in FP32 (exact)
+// decode()); from FP16 texels the difference is formed in FP32 (exact)
 // and rounded once.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint2 f4_to_h4(float4 v)
