@@ -306,8 +306,14 @@ __device__ __forceinline__ void pin(FootRaw<false, CELL>& R)
 }
 __device__ __forceinline__ void pin(Foot& F)
 {
+    // one 4-register operand per corner: the corner stays the register
+    // quadruple its load wrote (no copies that would wait for the load)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(F.c[i].x), "+v"(F.c[i].y), "+v"(F.c[i].z), "+v"(F.c[i].w));
+    for (int i = 0; i < 4; ++i) {
+        f32x4 v = {F.c[i].x, F.c[i].y, F.c[i].z, F.c[i].w};
+        asm volatile("" : "+v"(v));
+        F.c[i] = make_float4(v.x, v.y, v.z, v.w);
+    }
 }
 
 template <bool FP16, bool CELL>

@@ -12,7 +12,7 @@
 
 // Compile-time tuning knobs of the uniform kernel (every setting gives the
 // same bits; the measured sweep is recorded with the design notes):
-//   SHM_QPT     queries per lane
+//   SHM_QPT     queries per lane (2 or more: the batched form, query_batch)
 //   SHM_QBLOCK  lanes per workgroup (one tile = SHM_QBLOCK * SHM_QPT queries)
 //   SHM_DIR_NT  non-temporal direction loads
 //   SHM_OUT_NT  non-temporal result stores
@@ -54,6 +54,55 @@ __device__ __forceinline__ void st_out(float* out, int64_t q, float4 r)
 }
 
 
+// QPT queries per lane: rows q0 + k0 + j B + lane (j < QPT) of a range of
+// n rows.  All their loads go out before any query's arithmetic, with no
+// branch between them (a branch ends in a wait for every load in flight),
+// so a lane has QPT footprints in flight; an idle lane (row >= n) reads the
+// range's first direction.  Results (and normals) are written through
+// buffer descriptors ro (rn) whose ranges end at the range's last row: the
+// stores of idle lanes fall outside them and are dropped, so no branch
+// guards a store (aux 2: non-temporal).  The same bits as query_one.
+template <bool FP16, bool CELL, bool NRM, int QPT>
+__device__ __forceinline__ void query_batch(const char* __restrict__ base, int N, const float* __restrict__ dirs,
+                                            int64_t q0, int n, int k0, int B, __amdgpu_buffer_rsrc_t ro,
+                                            __amdgpu_buffer_rsrc_t rn)
+{
+    float x[QPT], y[QPT], z[QPT];
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int k = k0 + j * B + (int)threadIdx.x;
+        const int64_t q = q0 + (k < n ? k : 0);
+        x[j] = ld_dir(dirs + 3 * q);
+        y[j] = ld_dir(dirs + 3 * q + 1);
+        z[j] = ld_dir(dirs + 3 * q + 2);
+    }
+    // an empty statement that takes (and may change) every loaded value: no
+    // query's arithmetic can start before all the loads above are issued
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) asm volatile("" : "+v"(x[j]), "+v"(y[j]), "+v"(z[j]));
+    Loc L[QPT];
+    Foot F[QPT];
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        L[j] = locate(x[j], y[j], z[j], N);
+        F[j] = decode<FP16, CELL>(query_load<FP16, CELL>(base, N, L[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) pin(F[j]);
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const uint32_t k = (uint32_t)(k0 + j * B + (int)threadIdx.x);
+        const float4 r = query_finish(F[j], L[j], N);
+        const u32x4 w = {__float_as_uint(r.x), __float_as_uint(r.y), __float_as_uint(r.z), __float_as_uint(r.w)};
+        __builtin_amdgcn_raw_buffer_store_b128(w, ro, k * 16u, 0, 2);
+        if constexpr (NRM) {
+            const float3 nv = normal_of(r.x, x[j], y[j], z[j], make_float3(r.y, r.z, r.w));
+            const u32x3 wn = {__float_as_uint(nv.x), __float_as_uint(nv.y), __float_as_uint(nv.z)};
+            __builtin_amdgcn_raw_buffer_store_b96(wn, rn, k * 12u, 0, 2);
+        }
+    }
+}
+
 template <bool FP16, bool CELL, bool NRM>
 __global__ __launch_bounds__(QB) void k_query_uniform(const void* __restrict__ lut, int N, int64_t lut_elems,
                                                        int64_t q_per_obj, int tiles_per_obj,
@@ -64,6 +113,16 @@ __global__ __launch_bounds__(QB) void k_query_uniform(const void* __restrict__ l
     const int obj = b / tiles_per_obj;
     const int tile = b - obj * tiles_per_obj;
     const char* base = reinterpret_cast<const char*>(lut) + (size_t)obj * (size_t)lut_elems * (FP16 ? 2 : 4);
+    if constexpr (SHM_QPT > 1) {
+        const int64_t ql0 = (int64_t)tile * (QB * SHM_QPT);
+        const int64_t q0 = (int64_t)obj * q_per_obj + ql0;
+        const int n = (int)((q_per_obj - ql0) < QB * SHM_QPT ? (q_per_obj - ql0) : QB * SHM_QPT);
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(out + 4 * q0, (short)0, n * 16, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rn =
+            __builtin_amdgcn_make_buffer_rsrc(NRM ? nrm + 3 * q0 : out, (short)0, NRM ? n * 12 : 0, 0x00020000);
+        query_batch<FP16, CELL, NRM, SHM_QPT>(base, N, dirs, q0, n, 0, QB, ro, rn);
+        return;
+    }
     float x[SHM_QPT], y[SHM_QPT], z[SHM_QPT];
     int64_t qq[SHM_QPT];
     bool act[SHM_QPT];
@@ -238,55 +297,13 @@ __global__ void k_query_persistent(const void* __restrict__ lut, const shm_objec
             }
             continue;
         }
-        // QPT queries per lane: all their loads go out before any query's
-        // arithmetic, with no branch between them (a branch ends in a wait
-        // for every load in flight), so a lane has QPT footprints in flight.
-        // The item's results are written through buffer ranges of it.n rows:
-        // the stores of idle lanes (k >= it.n) fall outside them and are
-        // dropped, so no branch guards a store (aux 2: non-temporal).
+        // QPT queries per lane, all loads before any arithmetic (query_batch)
         const __amdgpu_buffer_rsrc_t ro =
             __builtin_amdgcn_make_buffer_rsrc(out + 4 * it.q0, (short)0, it.n * 16, 0x00020000);
         const __amdgpu_buffer_rsrc_t rn =
             __builtin_amdgcn_make_buffer_rsrc(NRM ? nrm + 3 * it.q0 : out, (short)0, NRM ? it.n * 12 : 0, 0x00020000);
-        for (int k0 = 0; k0 < it.n; k0 += B * QPT) {
-            // an idle lane reads the item's first direction
-            float x[QPT], y[QPT], z[QPT];
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) {
-                const int k = k0 + j * B + (int)threadIdx.x;
-                const int64_t q = it.q0 + (k < it.n ? k : 0);
-                x[j] = ld_dir(dirs + 3 * q);
-                y[j] = ld_dir(dirs + 3 * q + 1);
-                z[j] = ld_dir(dirs + 3 * q + 2);
-            }
-            // an empty statement that takes (and may change) every loaded
-            // value: no query's arithmetic can start before all the loads
-            // above are issued
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) asm volatile("" : "+v"(x[j]), "+v"(y[j]), "+v"(z[j]));
-            Loc L[QPT];
-            Foot F[QPT];
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) {
-                L[j] = locate(x[j], y[j], z[j], N);
-                F[j] = decode<FP16, CELL>(query_load<FP16, CELL>(base, N, L[j]));
-            }
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) pin(F[j]);
-#pragma unroll
-            for (int j = 0; j < QPT; ++j) {
-                const uint32_t k = (uint32_t)(k0 + j * B + (int)threadIdx.x);
-                const float4 r = query_finish(F[j], L[j], N);
-                const u32x4 w = {__float_as_uint(r.x), __float_as_uint(r.y), __float_as_uint(r.z),
-                                 __float_as_uint(r.w)};
-                __builtin_amdgcn_raw_buffer_store_b128(w, ro, k * 16u, 0, 2);
-                if constexpr (NRM) {
-                    const float3 n = normal_of(r.x, x[j], y[j], z[j], make_float3(r.y, r.z, r.w));
-                    const u32x3 wn = {__float_as_uint(n.x), __float_as_uint(n.y), __float_as_uint(n.z)};
-                    __builtin_amdgcn_raw_buffer_store_b96(wn, rn, k * 12u, 0, 2);
-                }
-            }
-        }
+        for (int k0 = 0; k0 < it.n; k0 += B * QPT)
+            query_batch<FP16, CELL, NRM, QPT>(base, N, dirs, it.q0, it.n, k0, B, ro, rn);
     }
 }
 
