@@ -82,6 +82,55 @@ def test_plan_matches_oracle_and_shapes():
     plan.close()
 
 
+@pytest.mark.parametrize("dt,layout", [(torch.float32, 0), (torch.float16, 1)])
+def test_plan_normals_and_row_gaps_every_shape(dt, layout):
+    """A plan with normal output, objects whose row ranges leave gaps (and
+    one with no queries): at every launch form (one and several queries per
+    lane, persistent and one workgroup per item, tiles that split objects
+    unevenly) every answered row and normal has the bits of a per-object
+    launch, and the gap rows keep their sentinel (the stores of idle lanes
+    are dropped, not written past an item's last row)."""
+    flat, objs0, dirs0 = build_batch(30, 11)
+    code = shm.SHM_F16 if dt == torch.float16 else shm.SHM_F32
+    lut_t = torch.as_tensor(flat).to(DEV, dt)
+    if layout == shm.SHM_LAYOUT_CELL:
+        lut_t, objs0 = to_cells_batch(lut_t, objs0)
+    r = np.random.default_rng(12)
+    # spread the objects' rows apart: a gap of 0..9 rows before each object
+    objs, rows, src = [], 0, []
+    for (o_off, N, q0, q) in objs0:
+        rows += int(r.integers(0, 10))
+        objs.append((o_off, N, rows, q))
+        src.append((q0, q))
+        rows += q
+    objs.insert(5, (objs0[0][0], objs0[0][1], rows, 0))  # no queries
+    Q = rows + 7
+    dirs = np.zeros((Q, 3), np.float32)
+    for (o_off, N, q0, q), (s0, sq) in zip([o for o in objs if o[3] > 0], src):
+        dirs[q0:q0 + q] = dirs0[s0:s0 + sq]
+    d_t = torch.as_tensor(dirs).to(DEV)
+    sentinel = -7.0
+    ref = torch.full((Q, 4), sentinel, device=DEV)
+    rn = torch.full((Q, 3), sentinel, device=DEV)
+    for (o_off, N, q0, q) in objs:
+        if q == 0:
+            continue
+        n = shm.shm_lut_elems(N, layout)
+        shm.shm_query_value_grad(lut_t[o_off:o_off + n], code, layout, N, 1, d_t[q0:q0 + q], q, ref[q0:q0 + q],
+                                 rn[q0:q0 + q])
+    plan = shm.Plan(objs, code, layout)
+    for shape in [(64, 1, 64, 1), (256, 1, 256, 0), (64, 2, 128, 0), (256, 2, 512, 4), (128, 4, 512, 0),
+                  (64, 4, 64 * 4 * 3, 2), (512, 2, 1024, 0)]:
+        plan.set_shape(*shape)
+        out = torch.full((Q, 4), sentinel, device=DEV)
+        nrm = torch.full((Q, 3), sentinel, device=DEV)
+        plan.launch(lut_t, d_t, out, nrm)
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.int32), ref.view(torch.int32)), shape
+        assert torch.equal(nrm.view(torch.int32), rn.view(torch.int32)), shape
+    plan.close()
+
+
 def test_set_shape_refuses_bad_shapes():
     """A shape is checked before the work list is rebuilt: block, queries per
     lane, a tile that is no multiple of block * qpt, workgroups per CU

@@ -89,7 +89,8 @@ def test_plan_probe_walks_every_query_of_its_object(dtype, layout):
     dirs = torch.as_tensor(np.random.default_rng(9).standard_normal((Q, 3)).astype(np.float32)).to(DEV)
     plan = shm.Plan([(int(offs[o]), Ns[o], int(qb[o]), Qs[o]) for o in range(4)], dtype, layout)
     try:
-        for shape in [(256, 2, 512, 4), (64, 1, 64, 2), (128, 4, 1024, 1), (256, 1, 256, 0)]:
+        for shape in [(256, 2, 512, 4), (64, 1, 64, 2), (128, 4, 1024, 1), (256, 1, 256, 0), (64, 2, 128, 0),
+                      (128, 4, 512, 0)]:
             plan.set_shape(*shape)
             out = torch.full((Q, 4), float("nan"), device=DEV)
             plan.probe(lut, dirs, out, seed=11)
