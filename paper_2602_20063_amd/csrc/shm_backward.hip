@@ -414,6 +414,12 @@ constexpr int BC = BT + 1;             // cells per tile side
 // of at most 16 slots (the serial per-cell loop would take one step per query)
 constexpr int BWD_DENSE = 32;
 constexpr int BWD_THREADS = BC * BC;
+// dense tiles run in workgroups of BWD_GROUPS groups of BWD_THREADS lanes:
+// group g takes rounds g, g + BWD_GROUPS, ... of the tile's list, and the
+// groups' cell sums are added in group order at the end (a tile's list may
+// hold a million queries: one group alone would make it the launch's tail)
+constexpr int BWD_GROUPS = 4;
+constexpr int BWD_DENSE_THREADS = BWD_THREADS * BWD_GROUPS;
 constexpr int DIRS_THREADS = 256;      // lanes per workgroup of the direction gradient
 
 // dL/d(16 footprint scalars) of one query, as 4 corners x (r, r_u h, r_v h, r_uv h^2).
@@ -529,22 +535,28 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     // dense tiles pad each corner's row by one float4 every 16 slots (and
     // the rows by 4): the run sums below then read 64 distinct banks per wave
     constexpr int SROW = DENSE ? BWD_THREADS + BWD_THREADS / 16 + 4 : BWD_THREADS;
-    __shared__ float4 slot_m[4 * SROW];
-    auto slot = [&](int k, int s) -> float4& { return slot_m[k * SROW + (DENSE ? s + (s >> 4) : s)]; };
+    constexpr int GS = DENSE ? BWD_GROUPS : 1;  // lane groups of BWD_THREADS
+    __shared__ float4 slot_m[GS * 4 * SROW];
+    const int tid = threadIdx.x;
+    const int grp = DENSE ? tid / BWD_THREADS : 0, lt = DENSE ? tid % BWD_THREADS : tid;
+    auto slot_of = [&](int gg, int k, int s) -> float4& {
+        return slot_m[(gg * 4 + k) * SROW + (DENSE ? s + (s >> 4) : s)];
+    };
+    auto slot = [&](int k, int s) -> float4& { return slot_of(grp, k, s); };
     // sorted positions and list offsets are below Q < 2^32 - 1: 32 bits
     __shared__ uint32_t row_start[BC];       // first sorted position of each cell row's range
     __shared__ uint32_t row_len[BC];         // queries in each cell row's range
     __shared__ uint32_t row_off[BC + 1];     // offsets of the rows in the concatenated list
-    __shared__ uint64_t run_end[DENSE ? BWD_THREADS / 64 : 1];  // dense tiles: per wave, the slots that end a run
+    __shared__ uint64_t run_end[DENSE ? GS * BWD_THREADS / 64 : 1];  // dense tiles: per wave, the slots that end a run
     const int N = G.N;
     const int C = N + 1, P = N + 2;
     const int p0 = G.p0, q0 = G.q0;
     const int face = G.face;
     const int64_t cbase = G.cbase;
     const int i_lo = max(p0 - 1, 0), i_hi = min(p0 + BT - 1, N);  // the tile's cell columns (p0 <= N + 1)
-    const int tid = threadIdx.x;
-    // this lane's cell: its segment bounds load beside the row setup
-    const int ci = tid % BC, cj = tid / BC;
+    // this lane's cell: its segment bounds load beside the row setup (every
+    // group of a dense tile accumulates its own rounds' sums per cell)
+    const int ci = lt % BC, cj = lt / BC;
     const int i0c = p0 - 1 + ci, j0c = q0 - 1 + cj;
     // with no queries the sort wrote no segment starts: every list is empty
     const bool cell_ok = Q > 0 && i0c >= 0 && i0c <= N && j0c >= 0 && j0c <= N;
@@ -623,18 +635,23 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
     uint32_t q_cur = 0;
     float x = 0.0f, y = 0.0f, z = 0.0f;
     float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
+    // this group's rounds start at list position grp * BWD_THREADS and step
+    // by GS * BWD_THREADS; every group runs every round's barriers
+    constexpr int STEP = GS * BWD_THREADS;
+    const int64_t gofs = (int64_t)grp * BWD_THREADS;
     if (total > 0) {
-        q_cur = query_at(tid, r_cur, v_cur);
+        q_cur = query_at(gofs + lt, r_cur, v_cur);
         x = dirs[3 * (size_t)q_cur];
         y = dirs[3 * (size_t)q_cur + 1];
         z = dirs[3 * (size_t)q_cur + 2];
         gq = upstream_in(q_cur);
     }
-    for (int64_t base = 0; base < total; base += BWD_THREADS) {
+    for (int64_t base0 = 0; base0 < total; base0 += STEP) {
+        const int64_t base = base0 + gofs;  // this group's round
         int r_next;
         bool v_next;
-        const uint32_t q_next = query_at(base + BWD_THREADS + tid, r_next, v_next);
-        // list positions base + tid < total hold a query and fill their
+        const uint32_t q_next = query_at(base + STEP + lt, r_next, v_next);
+        // list positions base + lt < total hold a query and fill their
         // slot; the reduction below reads no other slot
         int my_cell = -1;  // dense tiles: the tile cell of this lane's query, -1 for none
         if (v_cur) {
@@ -652,16 +669,16 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
                 float4 w[4];
                 query_weights(gq.x, Nf * kk2 * gS, Nf * kk2 * gT, basis1(L.s), basis1(L.t), w);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) slot(k, tid) = w[k];
+                for (int k = 0; k < 4; ++k) slot(k, lt) = w[k];
             }
             if constexpr (DENSE) my_cell = r_cur * BC + (L.i0 - (p0 - 1));
         }
         if constexpr (DENSE) {
-            // slot tid ends a run when the next slot holds another cell (or
+            // slot lt ends a run when the next slot holds another cell (or
             // none) or a chunk of 16 slots ends; chunks do not cross waves
             const int nb = __shfl_down(my_cell, 1);
-            const uint64_t m = __ballot((tid & 15) == 15 || nb != my_cell);
-            if ((tid & 63) == 0) run_end[tid >> 6] = m;
+            const uint64_t m = __ballot((lt & 15) == 15 || nb != my_cell);
+            if ((lt & 63) == 0) run_end[grp * (BWD_THREADS / 64) + (lt >> 6)] = m;
         }
         // unconditional: q_next is a valid index even past the list's end
         x = dirs[3 * (size_t)q_next];
@@ -673,8 +690,9 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
         v_cur = v_next;
         {
             lds_barrier();
-            // the segment's slots in this round (base < total < 2^32)
-            const uint32_t b = (uint32_t)base;
+            // the segment's slots in this group's round (base may pass the
+            // list's end, then the range is empty; base < 2^32 + STEP)
+            const uint32_t b = base < (int64_t)total ? (uint32_t)base : total;
             const int lo = (int)min(seg_lo > b ? seg_lo - b : 0u, (uint32_t)BWD_THREADS);
             const int hi = (int)min(seg_hi > b ? seg_hi - b : 0u, (uint32_t)BWD_THREADS);
             if constexpr (!DENSE) {
@@ -695,9 +713,10 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
                 // each cell lane adds its runs' sums in order (at most one
                 // per chunk instead of one per query)
                 {
-                    const int chunk = tid >> 4, ch = tid & 15;
+                    const int chunk = lt >> 4, ch = lt & 15;
                     float* col = reinterpret_cast<float*>(&slot(ch >> 2, chunk * 16)) + (ch & 3);
-                    const uint32_t ends = (uint32_t)(run_end[chunk >> 2] >> ((chunk & 3) * 16));
+                    const uint32_t ends =
+                        (uint32_t)(run_end[grp * (BWD_THREADS / 64) + (chunk >> 2)] >> ((chunk & 3) * 16));
                     float v[16];
 #pragma unroll
                     for (int i = 0; i < 16; ++i) v[i] = col[4 * i];
@@ -740,8 +759,26 @@ __device__ __forceinline__ void bwd_tile(const TileGeo& G, const float* __restri
         vv = fa.v[t_i];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) slot(k, tid) = acc[k];
+    for (int k = 0; k < 4; ++k) slot(k, lt) = acc[k];
     lds_barrier();
+    if constexpr (DENSE) {
+        // the groups' cell sums, added in group order into group 0's slots
+        if (grp == 0) {
+#pragma unroll
+            for (int gg = 1; gg < GS; ++gg)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = slot_of(gg, k, lt);
+                    acc[k].x += v.x;
+                    acc[k].y += v.y;
+                    acc[k].z += v.z;
+                    acc[k].w += v.w;
+                }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) slot(k, lt) = acc[k];
+        }
+        lds_barrier();
+    }
     // texel (p0 + tx, q0 + ty) is corner (1,1) of cell (tx, ty), (0,1) of
     // (tx+1, ty), (1,0) of (tx, ty+1) and (0,0) of (tx+1, ty+1) in tile cells
     static_assert(BT * BT <= BWD_THREADS, "one texel per lane");
@@ -901,7 +938,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused(const float* __restri
 // the dense tiles, from the sort's list: a small persistent grid, so that a
 // backward without dense tiles pays little for this launch
 template <bool FIT>
-__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_dense(const float* __restrict__ lut, int N,
+__global__ __launch_bounds__(BWD_DENSE_THREADS) void k_bwd_fused_dense(const float* __restrict__ lut, int N,
                                                                  int64_t lut_elems, int64_t Q,
                                                                  const float* __restrict__ dirs,
                                                                  const float* __restrict__ gout,
@@ -1146,7 +1183,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects(BwdObjects B,
     bwd_tile<false, true>(G, nullptr, Q, sdirs, sgout, perm, cs, grad_lut, FitArgs{});
 }
 
-__global__ __launch_bounds__(BWD_THREADS) void k_bwd_fused_objects_dense(const TileRec* __restrict__ recs, int64_t Q,
+__global__ __launch_bounds__(BWD_DENSE_THREADS) void k_bwd_fused_objects_dense(const TileRec* __restrict__ recs, int64_t Q,
                                                                          const float* __restrict__ sdirs,
                                                                          const float* __restrict__ sgout,
                                                                          const uint32_t* __restrict__ perm,
@@ -1314,7 +1351,7 @@ int launch_backward_objects(const BwdObjectsHost& H, int dtype, const void* lut,
             if (H.n_dense > 0)
                 hipLaunchKernelGGL(k_bwd_fused_objects_dense,
                                    dim3((unsigned)std::min<int64_t>(H.n_dense, 8ll * device_cu_count())),
-                                   dim3(BWD_THREADS), 0, stream, recs, W.Q, sdirs, (const float*)sgout, perm, cs,
+                                   dim3(BWD_DENSE_THREADS), 0, stream, recs, W.Q, sdirs, (const float*)sgout, perm, cs,
                                    (const uint32_t*)D.count, (const uint32_t*)D.list, grad_lut);
         }
         SHM_LAUNCH_CHECK();
@@ -1371,7 +1408,7 @@ int launch_backward(const float* lut, int N, int64_t n_obj, const float* dirs, i
                            texel_elems(N), W.Q, dirs, gout, perm, cs, tpf,
                            skip_dense ? nullptr : (const uint8_t*)D.flag, grad_lut, FitArgs{});
         if (!skip_dense)
-            hipLaunchKernelGGL((k_bwd_fused_dense<false>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0,
+            hipLaunchKernelGGL((k_bwd_fused_dense<false>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_DENSE_THREADS), 0,
                                stream, lut, N, texel_elems(N), W.Q, dirs, gout, perm, cs, tpf,
                                (const uint32_t*)D.count, (const uint32_t*)D.list, grad_lut, FitArgs{});
         SHM_LAUNCH_CHECK();
@@ -1409,7 +1446,7 @@ int launch_fit_step(const float* lut_in, float* lut_out, float* m, float* v, int
                        texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf,
                        Q > 0 && !skip_dense ? (const uint8_t*)D.flag : nullptr, (float*)nullptr, fa);
     if (Q > 0 && !skip_dense)
-        hipLaunchKernelGGL((k_bwd_fused_dense<true>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_THREADS), 0, stream,
+        hipLaunchKernelGGL((k_bwd_fused_dense<true>), dim3((unsigned)dense_grid(tiles)), dim3(BWD_DENSE_THREADS), 0, stream,
                            lut_in, N, texel_elems(N), Q, dirs, (const float*)nullptr, perm, cs, tpf,
                            (const uint32_t*)D.count, (const uint32_t*)D.list, (float*)nullptr, fa);
     SHM_LAUNCH_CHECK();
