@@ -192,10 +192,12 @@ def test_autograd_function_and_fd():
     assert d_t.grad is not None and torch.isfinite(d_t.grad).all()
 
 
-@pytest.mark.parametrize("N,Q", [(2, 20000), (5, 60000)])
+@pytest.mark.parametrize("N,Q", [(2, 20000), (5, 60000), (1, 1500), (3, 5000)])
 def test_backward_dense_cells(N, Q):
     """Hundreds of queries per cell: the tiles sum each round in runs of at
-    most 16 slots; against the oracle and bitwise repeatable."""
+    most 16 slots, four lane groups taking alternate rounds (13 and 40
+    rounds per tile; one round, so three groups idle; four rounds, one per
+    group); against the oracle and bitwise repeatable."""
     r = rng(30 + N)
     lut = workloads.random_lut(N, r)
     dirs = workloads.uniform_dirs(Q, r)
