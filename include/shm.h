@@ -254,7 +254,10 @@ SHM_API int shm_query_objects(const void* lut, int32_t dtype, int32_t layout, co
                               const float* dirs, float* out, float* normal, void* ws, size_t ws_bytes,
                               hipStream_t stream);
 
-/* Launch shape of the persistent kernel. */
+/* Launch shape of the plan's kernel.  With qpt 2 or 4 a thread issues the
+ * loads of all its queries before their arithmetic (same results as qpt 1).
+ * grid_per_cu 0 launches 8 x (items of the largest of the 8 per-XCD
+ * slices of the work list) workgroups, so that none takes a second item. */
 typedef struct shm_launch_shape {
     int32_t block;       /* threads per workgroup: 64, 128, 256 or 512        */
     int32_t qpt;         /* queries per thread per pass: 1, 2 or 4            */
